@@ -1,0 +1,788 @@
+/*
+ * zfo.c -- the oracle (test infrastructure only; see zfo.h).
+ *
+ * Plain C99, single-threaded, no SIMD, no cleverness.  Every stream is built
+ * and read one field at a time with byte-wise little-endian helpers and a
+ * bit-at-a-time packer, so each function can be checked against its
+ * definition by eye.
+ *
+ * ---------------------------------------------------------------- container
+ * Column blob, all integers little-endian:
+ *   [0,64)   header: "ZFC1", u16 version=1, u8 dtype, u8 codec (0 if the
+ *            chunks mix codecs), u64 n_elems, u64 plain_bytes, u32 n_chunks,
+ *            u32 dict_count, u64 dict_off, u64 total_bytes, u32 table_crc,
+ *            u32 0, u32 0, u32 header_crc (CRC-32 of bytes [0,60)).
+ *   [64, 64+32*n_chunks)  chunk table, one 32-byte entry per chunk:
+ *            u64 plain_off, u64 comp_off, u32 plain_len, u32 comp_len,
+ *            u32 n_elems, u8 codec, 3 zero bytes.
+ *   dictionary (when dict_count > 0) at dict_off = align16(end of table):
+ *            dict_count entries of elem_size bytes, sorted ascending and
+ *            unique (integers by signed value, FIXED16 by memcmp).
+ *   chunk streams, each at a 16-aligned comp_off, in chunk order; the gap
+ *            bytes are zero; total_bytes = align16(end of the last stream).
+ *   table_crc = CRC-32 over the chunk table followed by the dictionary.
+ *
+ * The codec streams are described above their encoders below.
+ */
+#include "zfo.h"
+
+#include <stdlib.h>
+#include <string.h>
+
+#define FOR_BLOCK 2048u /* values per FOR / bit-packing block */
+#define RLE_GROUP 64u   /* runs per RLE group record */
+#define LZ_MAX_CHUNK 65536u
+#define LZ_HASH_BITS 16
+#define LZ_CHAIN 16
+
+/* ------------------------------------------------------------ byte helpers */
+static void put8(uint8_t *p, uint32_t v) { p[0] = (uint8_t)v; }
+static void put16(uint8_t *p, uint32_t v) { p[0] = (uint8_t)v; p[1] = (uint8_t)(v >> 8); }
+static void put32(uint8_t *p, uint32_t v) {
+    for (int i = 0; i < 4; i++) p[i] = (uint8_t)(v >> (8 * i));
+}
+static void put64(uint8_t *p, uint64_t v) {
+    for (int i = 0; i < 8; i++) p[i] = (uint8_t)(v >> (8 * i));
+}
+static uint32_t get16(const uint8_t *p) { return (uint32_t)p[0] | ((uint32_t)p[1] << 8); }
+static uint32_t get32(const uint8_t *p) {
+    uint32_t v = 0;
+    for (int i = 0; i < 4; i++) v |= (uint32_t)p[i] << (8 * i);
+    return v;
+}
+static uint64_t get64(const uint8_t *p) {
+    uint64_t v = 0;
+    for (int i = 0; i < 8; i++) v |= (uint64_t)p[i] << (8 * i);
+    return v;
+}
+static uint64_t align16(uint64_t x) { return (x + 15u) & ~(uint64_t)15u; }
+
+/* ---------------------------------------------------------------- CRC-32 */
+/* IEEE 802.3 CRC-32 (reflected polynomial 0xEDB88320, initial value and final
+ * xor 0xFFFFFFFF), computed one bit at a time from its definition. */
+uint32_t zfo_crc32(const uint8_t *p, uint64_t n) {
+    uint32_t c = 0xFFFFFFFFu;
+    for (uint64_t i = 0; i < n; i++) {
+        c ^= p[i];
+        for (int k = 0; k < 8; k++) c = (c & 1u) ? (c >> 1) ^ 0xEDB88320u : (c >> 1);
+    }
+    return c ^ 0xFFFFFFFFu;
+}
+
+uint32_t zfo_elem_size(uint32_t dtype) {
+    switch (dtype) {
+    case ZFO_I32: return 4;
+    case ZFO_I64: return 8;
+    case ZFO_BYTES: return 1;
+    case ZFO_FIXED16: return 16;
+    default: return 0;
+    }
+}
+
+/* number of bits needed to write v; bitlen(0) = 0 */
+static uint32_t bitlen64(uint64_t v) {
+    uint32_t n = 0;
+    while (v) { n++; v >>= 1; }
+    return n;
+}
+
+/* width of the integer type in bits (32 for I32, 64 for I64) */
+static uint32_t int_bits(uint32_t dtype) { return dtype == ZFO_I32 ? 32u : 64u; }
+static uint64_t mask_bits(uint32_t w) { return w >= 64 ? ~(uint64_t)0 : (((uint64_t)1 << w) - 1); }
+
+/* read element j of an integer column as a two's complement value held in
+ * 64 bits (I32 is sign-extended) */
+static int64_t load_int(const uint8_t *p, uint32_t dtype, uint64_t j) {
+    if (dtype == ZFO_I32) return (int64_t)(int32_t)get32(p + 4 * j);
+    return (int64_t)get64(p + 8 * j);
+}
+static void store_int(uint8_t *p, uint32_t dtype, uint64_t j, uint64_t v) {
+    if (dtype == ZFO_I32) put32(p + 4 * j, (uint32_t)v);
+    else put64(p + 8 * j, v);
+}
+
+/* ------------------------------------------------------------ growing buffer */
+typedef struct { uint8_t *p; uint64_t n, cap; int bad; } buf_t;
+static void buf_reserve(buf_t *b, uint64_t need) {
+    if (b->bad || need <= b->cap) return;
+    uint64_t cap = b->cap ? b->cap : 256;
+    while (cap < need) cap *= 2;
+    uint8_t *q = (uint8_t *)realloc(b->p, cap);
+    if (!q) { b->bad = 1; return; }
+    memset(q + b->cap, 0, cap - b->cap);
+    b->p = q;
+    b->cap = cap;
+}
+/* grow to length n (new bytes are zero) */
+static void buf_resize(buf_t *b, uint64_t n) {
+    buf_reserve(b, n);
+    if (!b->bad && n > b->n) b->n = n;
+}
+
+/* ------------------------------------------------------------- bit packing */
+/* The packed stream is a sequence of little-endian u32 words; stream bit k is
+ * bit (k mod 32) of word floor(k/32).  Field j of width w occupies stream bits
+ * [j*w, j*w + w), least significant bit first (Sec. 2.1, bit-packing).
+ * Both directions go one bit at a time. */
+static void pack_bits(uint8_t *words, uint64_t j, uint32_t w, uint64_t v) {
+    for (uint32_t k = 0; k < w; k++) {
+        uint64_t bit = (uint64_t)j * w + k;
+        if ((v >> k) & 1u) words[4 * (bit / 32) + (bit % 32) / 8] |= (uint8_t)(1u << (bit % 8));
+    }
+}
+static uint64_t unpack_bits(const uint8_t *words, uint64_t j, uint32_t w) {
+    uint64_t v = 0;
+    for (uint32_t k = 0; k < w; k++) {
+        uint64_t bit = (uint64_t)j * w + k;
+        uint64_t b = (words[4 * (bit / 32) + (bit % 32) / 8] >> (bit % 8)) & 1u;
+        v |= b << k;
+    }
+    return v;
+}
+static uint64_t packed_words(uint64_t nfields, uint32_t w) { return (nfields * w + 31) / 32; }
+
+/* ============================================================== FOR + BP
+ * Frame of reference plus bit-packing (Sec. 2.1: the reference is the block
+ * minimum and the width follows from the minimum and maximum).
+ * Stream for a chunk of n values, B = 2048, nb = ceil(n/B) blocks:
+ *   block directory, 16 bytes per block at offset 16*b:
+ *       i64 ref (the block minimum; I32 sign-extended), u32 w, u32 poff
+ *   payload of block b at byte offset poff (16-aligned): the fields
+ *       d_j = x_j - ref (mod 2^bits), packed at width w = bitlen(max d).
+ *   poff_0 = align16(16*nb), poff_{b+1} = align16(poff_b + 4*words_b);
+ *   comp_len = poff_last + 4*words_last.
+ * Decode: x_j = ref + field_j (mod 2^bits). */
+static void enc_for_bp(buf_t *s, const uint8_t *x, uint32_t dtype, uint32_t n) {
+    uint32_t nb = (n + FOR_BLOCK - 1) / FOR_BLOCK;
+    uint64_t mask = mask_bits(int_bits(dtype));
+    uint64_t pos = align16((uint64_t)16 * nb);
+    buf_resize(s, pos);
+    uint64_t end = pos;
+    for (uint32_t b = 0; b < nb && !s->bad; b++) {
+        uint32_t j0 = b * FOR_BLOCK, nv = n - j0 < FOR_BLOCK ? n - j0 : FOR_BLOCK;
+        int64_t ref = load_int(x, dtype, j0);
+        for (uint32_t j = 1; j < nv; j++) {
+            int64_t v = load_int(x, dtype, j0 + j);
+            if (v < ref) ref = v;
+        }
+        uint64_t dmax = 0;
+        for (uint32_t j = 0; j < nv; j++) {
+            uint64_t d = ((uint64_t)load_int(x, dtype, j0 + j) - (uint64_t)ref) & mask;
+            if (d > dmax) dmax = d;
+        }
+        uint32_t w = bitlen64(dmax);
+        uint64_t nw = packed_words(nv, w);
+        buf_resize(s, pos + 4 * nw);
+        if (s->bad) return;
+        put64(s->p + 16 * (uint64_t)b, (uint64_t)ref);
+        put32(s->p + 16 * (uint64_t)b + 8, w);
+        put32(s->p + 16 * (uint64_t)b + 12, (uint32_t)pos);
+        for (uint32_t j = 0; j < nv; j++) {
+            uint64_t d = ((uint64_t)load_int(x, dtype, j0 + j) - (uint64_t)ref) & mask;
+            pack_bits(s->p + pos, j, w, d);
+        }
+        end = pos + 4 * nw;
+        pos = align16(end);
+    }
+    s->n = end;
+}
+
+/* Decode FOR+BP into 64-bit unsigned values (the caller narrows). */
+static int dec_for_bp_u64(const uint8_t *s, uint64_t comp_len, uint32_t n, uint32_t bits,
+                          uint64_t *out) {
+    uint32_t nb = (n + FOR_BLOCK - 1) / FOR_BLOCK;
+    if ((uint64_t)16 * nb > comp_len) return ZFO_ECORRUPT;
+    uint64_t mask = mask_bits(bits);
+    for (uint32_t b = 0; b < nb; b++) {
+        uint32_t j0 = b * FOR_BLOCK, nv = n - j0 < FOR_BLOCK ? n - j0 : FOR_BLOCK;
+        uint64_t ref = get64(s + 16 * (uint64_t)b);
+        uint32_t w = get32(s + 16 * (uint64_t)b + 8);
+        uint64_t poff = get32(s + 16 * (uint64_t)b + 12);
+        if (w > bits || poff % 16 != 0 || poff < (uint64_t)16 * nb) return ZFO_ECORRUPT;
+        if (poff + 4 * packed_words(nv, w) > comp_len) return ZFO_ECORRUPT;
+        for (uint32_t j = 0; j < nv; j++)
+            out[j0 + j] = (ref + unpack_bits(s + poff, j, w)) & mask;
+    }
+    return ZFO_OK;
+}
+
+/* ============================================================ dictionary
+ * Dictionary encoding (Sec. 2.1; the FP example of Sec. 3.1 decodes with the
+ * dictionary as a lookup table held in metadata).  The column dictionary is
+ * the sorted set of distinct values; the code of a value is its index in it.
+ * A DICT_BP chunk stream is exactly the FOR_BP stream of its u32 code
+ * sequence (read as I32): dictionary encoding nested with bit-packing.
+ * Decode: x_j = dict[code_j]; a code >= dict_count is corrupt. */
+static uint32_t g_sort_es; /* element size for the qsort comparator */
+static uint32_t g_sort_dtype;
+static int cmp_entry(const void *a, const void *b) {
+    if (g_sort_dtype == ZFO_FIXED16) return memcmp(a, b, 16);
+    int64_t x = load_int((const uint8_t *)a, g_sort_dtype, 0);
+    int64_t y = load_int((const uint8_t *)b, g_sort_dtype, 0);
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+/* sorted unique values of x[0..n) -> *dict (malloc'd), *count */
+static int build_dict(const uint8_t *x, uint64_t n, uint32_t dtype, uint8_t **dict,
+                      uint32_t *count) {
+    uint32_t es = zfo_elem_size(dtype);
+    uint8_t *tmp = (uint8_t *)malloc(n ? n * es : 1);
+    if (!tmp) return ZFO_ENOMEM;
+    memcpy(tmp, x, n * es);
+    g_sort_es = es;
+    g_sort_dtype = dtype;
+    qsort(tmp, n, es, cmp_entry);
+    uint64_t m = 0;
+    for (uint64_t i = 0; i < n; i++)
+        if (m == 0 || cmp_entry(tmp + (m - 1) * es, tmp + i * es) != 0) {
+            memmove(tmp + m * es, tmp + i * es, es);
+            m++;
+        }
+    if (m > 0xFFFFFFFFu) { free(tmp); return ZFO_EUNSUP; }
+    *dict = tmp;
+    *count = (uint32_t)m;
+    return ZFO_OK;
+}
+
+/* index of value v in the sorted dictionary (binary search; v is present) */
+static uint32_t dict_code(const uint8_t *dict, uint32_t count, uint32_t dtype, const uint8_t *v) {
+    uint32_t es = zfo_elem_size(dtype), lo = 0, hi = count;
+    while (hi - lo > 1) {
+        uint32_t mid = lo + (hi - lo) / 2;
+        if (cmp_entry(dict + (uint64_t)mid * es, v) <= 0) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+/* ============================================================ RLE + delta
+ * Run-length encoding (Sec. 2.1: a value and a count per run), with the run
+ * values delta-encoded (Sec. 2.1: differences to the previous value over a
+ * stored base) and the deltas bit-packed with a frame of reference.  The runs
+ * of a chunk are maximal.  Every RLE_GROUP consecutive runs form a group whose
+ * record carries its own output offset and value base, so groups decode
+ * independently; the output offset of a run is the exclusive prefix sum of
+ * the counts (the `presum` of Sec. 3.2).
+ * Stream:
+ *   header 16 bytes: u32 n_runs, u32 n_groups = ceil(n_runs/64),
+ *                    u32 runs_off, u32 0
+ *   group records, 32 bytes each at offset 16 + 32*g:
+ *       u32 out_off (element index of the group's first run in the chunk),
+ *       u32 w, u32 doff (byte offset of the packed deltas, 4-aligned), u32 0,
+ *       i64 base (value of the first run), i64 dmin
+ *   packed deltas of group g at doff: nr_g - 1 fields of width w, field j-1
+ *       = delta_j - dmin (mod 2^bits) for j = 1 .. nr_g-1, where
+ *       delta_j = v_j - v_{j-1} (mod 2^bits) and dmin is the smallest delta
+ *       read as a signed integer; w = bitlen(max field); groups of one run
+ *       store w = 0 and dmin = 0.  Groups follow each other at 4-byte steps
+ *       starting at 16 + 32*n_groups.
+ *   run lengths: u32[n_runs] at runs_off = align16(end of deltas).
+ *   comp_len = runs_off + 4*n_runs.
+ * DELTA_BP is the same stream for runs that are all of length one (every
+ * value is its own run, equal neighbours included): n_runs = n, runs_off = 0,
+ * no run array, comp_len = end of the deltas. */
+static void enc_rle_delta(buf_t *s, const uint8_t *x, uint32_t dtype, uint32_t n, int unit_runs) {
+    uint32_t bits = int_bits(dtype);
+    uint64_t mask = mask_bits(bits);
+    /* runs */
+    uint64_t *val = (uint64_t *)malloc(sizeof(uint64_t) * (n ? n : 1));
+    uint32_t *len = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+    if (!val || !len) { free(val); free(len); s->bad = 1; return; }
+    uint32_t nr = 0;
+    for (uint32_t j = 0; j < n; j++) {
+        uint64_t v = (uint64_t)load_int(x, dtype, j) & mask;
+        if (!unit_runs && nr > 0 && val[nr - 1] == v) len[nr - 1]++;
+        else { val[nr] = v; len[nr] = 1; nr++; }
+    }
+    uint32_t ng = (nr + RLE_GROUP - 1) / RLE_GROUP;
+    uint64_t pos = 16 + (uint64_t)32 * ng;
+    buf_resize(s, pos);
+    uint32_t out_off = 0;
+    for (uint32_t g = 0; g < ng && !s->bad; g++) {
+        uint32_t r0 = g * RLE_GROUP, cnt = nr - r0 < RLE_GROUP ? nr - r0 : RLE_GROUP;
+        /* signed minimum delta, then the field width */
+        int64_t dmin = 0;
+        for (uint32_t j = 1; j < cnt; j++) {
+            uint64_t d = (val[r0 + j] - val[r0 + j - 1]) & mask;
+            int64_t sd = bits == 32 ? (int64_t)(int32_t)(uint32_t)d : (int64_t)d;
+            if (j == 1 || sd < dmin) dmin = sd;
+        }
+        uint64_t fmax = 0;
+        for (uint32_t j = 1; j < cnt; j++) {
+            uint64_t d = (val[r0 + j] - val[r0 + j - 1]) & mask;
+            uint64_t f = (d - (uint64_t)dmin) & mask;
+            if (f > fmax) fmax = f;
+        }
+        uint32_t w = bitlen64(fmax);
+        uint64_t nw = packed_words(cnt - 1, w);
+        buf_resize(s, pos + 4 * nw);
+        if (s->bad) break;
+        uint8_t *rec = s->p + 16 + (uint64_t)32 * g;
+        put32(rec + 0, out_off);
+        put32(rec + 4, w);
+        put32(rec + 8, (uint32_t)pos);
+        put32(rec + 12, 0);
+        /* base is the first run value as a signed integer (I32 sign-extended) */
+        int64_t base = bits == 32 ? (int64_t)(int32_t)(uint32_t)val[r0] : (int64_t)val[r0];
+        put64(rec + 16, (uint64_t)base);
+        put64(rec + 24, (uint64_t)dmin);
+        for (uint32_t j = 1; j < cnt; j++) {
+            uint64_t d = (val[r0 + j] - val[r0 + j - 1]) & mask;
+            pack_bits(s->p + pos, j - 1, w, (d - (uint64_t)dmin) & mask);
+        }
+        pos += 4 * nw;
+        for (uint32_t j = 0; j < cnt; j++) out_off += len[r0 + j];
+    }
+    if (!s->bad) {
+        put32(s->p + 0, nr);
+        put32(s->p + 4, ng);
+        put32(s->p + 12, 0);
+        if (unit_runs) {
+            put32(s->p + 8, 0);
+            s->n = pos;
+        } else {
+            uint64_t roff = align16(pos);
+            buf_resize(s, roff + 4 * (uint64_t)nr);
+            if (!s->bad) {
+                put32(s->p + 8, (uint32_t)roff);
+                for (uint32_t j = 0; j < nr; j++) put32(s->p + roff + 4 * (uint64_t)j, len[j]);
+                s->n = roff + 4 * (uint64_t)nr;
+            }
+        }
+    }
+    free(val);
+    free(len);
+}
+
+static int dec_rle_delta(const uint8_t *s, uint64_t comp_len, uint32_t dtype, uint32_t n,
+                         int unit_runs, uint8_t *dst) {
+    uint32_t bits = int_bits(dtype);
+    uint64_t mask = mask_bits(bits);
+    if (comp_len < 16) return ZFO_ECORRUPT;
+    uint32_t nr = get32(s), ng = get32(s + 4), roff = get32(s + 8);
+    if (ng != (nr + RLE_GROUP - 1) / RLE_GROUP) return ZFO_ECORRUPT;
+    if (16 + (uint64_t)32 * ng > comp_len) return ZFO_ECORRUPT;
+    if (unit_runs) {
+        if (nr != n || roff != 0) return ZFO_ECORRUPT;
+    } else {
+        if (roff % 4 != 0 || roff < 16 + (uint64_t)32 * ng) return ZFO_ECORRUPT;
+        if ((uint64_t)roff + 4 * (uint64_t)nr > comp_len) return ZFO_ECORRUPT;
+    }
+    uint64_t produced = 0;
+    for (uint32_t g = 0; g < ng; g++) {
+        const uint8_t *rec = s + 16 + (uint64_t)32 * g;
+        uint32_t out_off = get32(rec), w = get32(rec + 4), doff = get32(rec + 8);
+        uint64_t base = get64(rec + 16), dmin = get64(rec + 24);
+        uint32_t r0 = g * RLE_GROUP, cnt = nr - r0 < RLE_GROUP ? nr - r0 : RLE_GROUP;
+        if (w > bits || doff % 4 != 0) return ZFO_ECORRUPT;
+        if ((uint64_t)doff + 4 * packed_words(cnt - 1, w) > comp_len) return ZFO_ECORRUPT;
+        /* the record's offset must equal the sum of all earlier runs */
+        if (out_off != produced) return ZFO_ECORRUPT;
+        uint64_t v = base & mask;
+        for (uint32_t j = 0; j < cnt; j++) {
+            if (j > 0) v = (v + dmin + unpack_bits(s + doff, j - 1, w)) & mask;
+            uint32_t r = unit_runs ? 1u : get32(s + roff + 4 * (uint64_t)(r0 + j));
+            if (r == 0 || produced + r > n) return ZFO_ECORRUPT;
+            for (uint32_t k = 0; k < r; k++) store_int(dst, dtype, produced + k, v);
+            produced += r;
+        }
+    }
+    if (produced != n) return ZFO_ECORRUPT;
+    return ZFO_OK;
+}
+
+/* ================================================================= LZ77
+ * LZ77 family (Sec. 2.1): repeated byte sequences become pointers to earlier
+ * output.  A chunk holds at most 65536 plain bytes and decodes on its own
+ * (Sec. 3.1: independent file chunks are what the Non-Parallel pattern
+ * parallelises over).  The chunk is a list of sequences; sequence i is
+ * ll_i literal bytes followed by a match of ml_i bytes (ml_i = 0: none)
+ * copied from off_i bytes back.
+ * Stream:
+ *   header 16 bytes: u32 n_seq, u32 n_lit, u32 n_ext, u32 plain_len
+ *   offs:  u16[n_seq] at 16                (0 when the sequence has no match)
+ *   ext:   u16[n_ext] at 16 + 2*n_seq      (extended lengths, in order)
+ *   tags:  u8[n_seq]  at 16 + 2*n_seq + 2*n_ext
+ *   lits:  u8[n_lit]  right after the tags
+ *   comp_len = 16 + 3*n_seq + 2*n_ext + n_lit.
+ * tag bits 0..2 = lc: ll = lc for lc < 7; lc = 7 takes the next ext e, ll = 7 + e.
+ * tag bits 3..7 = mc: mc = 0 no match; 1..30: ml = mc + 3; 31 takes the next
+ * ext e (after the literal one, if any), ml = 34 + e.
+ * Decode in order: copy ll literals, then for j = 0 .. ml-1 ascending
+ * out[p + j] = out[p - off + j] (so an overlapping match repeats its period);
+ * 1 <= off <= p.  Corrupt: off out of range, off != 0 without a match, any
+ * write past plain_len, and at the end p != plain_len, or the literal or ext
+ * cursors short of n_lit or n_ext.
+ * Encoder: greedy, hash of the 4 bytes at a position, chains of the most
+ * recent earlier positions (depth 16), longest match, ties to the nearest. */
+static uint32_t lz_hash(const uint8_t *p) {
+    uint32_t v = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) |
+                 ((uint32_t)p[3] << 24);
+    return (v * 2654435761u) >> (32 - LZ_HASH_BITS);
+}
+
+typedef struct { uint32_t ll, ml, off; } lz_seq;
+
+static void enc_lz77(buf_t *s, const uint8_t *x, uint32_t n) {
+    int32_t *head = (int32_t *)malloc(sizeof(int32_t) << LZ_HASH_BITS);
+    int32_t *prev = (int32_t *)malloc(sizeof(int32_t) * (n ? n : 1));
+    lz_seq *seq = (lz_seq *)malloc(sizeof(lz_seq) * (n + 1));
+    if (!head || !prev || !seq) { free(head); free(prev); free(seq); s->bad = 1; return; }
+    for (uint32_t i = 0; i < (1u << LZ_HASH_BITS); i++) head[i] = -1;
+    uint32_t nseq = 0, i = 0, lit_start = 0;
+    while (i < n) {
+        uint32_t best = 0, best_off = 0;
+        if (i + 4 <= n) {
+            int32_t c = head[lz_hash(x + i)];
+            for (int d = 0; d < LZ_CHAIN && c >= 0; d++) {
+                uint32_t l = 0;
+                while (i + l < n && x[(uint32_t)c + l] == x[i + l]) l++;
+                if (l > best) { best = l; best_off = i - (uint32_t)c; }
+                c = prev[c];
+            }
+        }
+        if (best >= 4) {
+            seq[nseq].ll = i - lit_start;
+            seq[nseq].ml = best;
+            seq[nseq].off = best_off;
+            nseq++;
+            for (uint32_t k = i; k < i + best; k++)
+                if (k + 4 <= n) { uint32_t h = lz_hash(x + k); prev[k] = head[h]; head[h] = (int32_t)k; }
+            i += best;
+            lit_start = i;
+        } else {
+            if (i + 4 <= n) { uint32_t h = lz_hash(x + i); prev[i] = head[h]; head[h] = (int32_t)i; }
+            i++;
+        }
+    }
+    if (lit_start < n || nseq == 0) {
+        seq[nseq].ll = n - lit_start;
+        seq[nseq].ml = 0;
+        seq[nseq].off = 0;
+        nseq++;
+    }
+    if (n == 0) nseq = 0;
+    uint32_t next = 0, nlit = 0;
+    for (uint32_t k = 0; k < nseq; k++) {
+        next += (seq[k].ll >= 7) + (seq[k].ml >= 34);
+        nlit += seq[k].ll;
+    }
+    uint64_t total = 16 + 3 * (uint64_t)nseq + 2 * (uint64_t)next + nlit;
+    buf_resize(s, total);
+    if (!s->bad) {
+        put32(s->p + 0, nseq);
+        put32(s->p + 4, nlit);
+        put32(s->p + 8, next);
+        put32(s->p + 12, n);
+        uint8_t *offs = s->p + 16, *ext = offs + 2 * (uint64_t)nseq,
+                *tags = ext + 2 * (uint64_t)next, *lits = tags + nseq;
+        uint32_t e = 0, lp = 0, pos = 0;
+        for (uint32_t k = 0; k < nseq; k++) {
+            uint32_t lc, mc;
+            if (seq[k].ll < 7) lc = seq[k].ll;
+            else { lc = 7; put16(ext + 2 * (uint64_t)e++, seq[k].ll - 7); }
+            if (seq[k].ml == 0) mc = 0;
+            else if (seq[k].ml <= 33) mc = seq[k].ml - 3;
+            else { mc = 31; put16(ext + 2 * (uint64_t)e++, seq[k].ml - 34); }
+            put8(tags + k, lc | (mc << 3));
+            put16(offs + 2 * (uint64_t)k, seq[k].off);
+            memcpy(lits + lp, x + pos, seq[k].ll);
+            lp += seq[k].ll;
+            pos += seq[k].ll + seq[k].ml;
+        }
+        s->n = total;
+    }
+    free(head);
+    free(prev);
+    free(seq);
+}
+
+static int dec_lz77(const uint8_t *s, uint64_t comp_len, uint32_t plain_len, uint8_t *out) {
+    if (comp_len < 16) return ZFO_ECORRUPT;
+    uint32_t nseq = get32(s), nlit = get32(s + 4), next = get32(s + 8), plen = get32(s + 12);
+    if (plen != plain_len || plain_len > LZ_MAX_CHUNK) return ZFO_ECORRUPT;
+    if (16 + 3 * (uint64_t)nseq + 2 * (uint64_t)next + nlit != comp_len) return ZFO_ECORRUPT;
+    const uint8_t *offs = s + 16, *ext = offs + 2 * (uint64_t)nseq,
+                  *tags = ext + 2 * (uint64_t)next, *lits = tags + nseq;
+    uint64_t p = 0, lp = 0, e = 0;
+    for (uint32_t k = 0; k < nseq; k++) {
+        uint32_t tag = tags[k], lc = tag & 7u, mc = tag >> 3, off = get16(offs + 2 * (uint64_t)k);
+        uint64_t ll = lc, ml = 0;
+        if (lc == 7) { if (e >= next) return ZFO_ECORRUPT; ll = 7 + get16(ext + 2 * e++); }
+        if (mc == 31) { if (e >= next) return ZFO_ECORRUPT; ml = 34 + get16(ext + 2 * e++); }
+        else if (mc > 0) ml = mc + 3;
+        if (lp + ll > nlit || p + ll > plain_len) return ZFO_ECORRUPT;
+        for (uint64_t j = 0; j < ll; j++) out[p + j] = lits[lp + j];
+        p += ll;
+        lp += ll;
+        if (ml == 0) {
+            if (off != 0) return ZFO_ECORRUPT;
+            continue;
+        }
+        if (off == 0 || off > p || p + ml > plain_len) return ZFO_ECORRUPT;
+        for (uint64_t j = 0; j < ml; j++) out[p + j] = out[p - off + j];
+        p += ml;
+    }
+    if (p != plain_len || lp != nlit || e != next) return ZFO_ECORRUPT;
+    return ZFO_OK;
+}
+
+/* ============================================================ per stream */
+static int codec_allows(uint32_t codec, uint32_t dtype) {
+    switch (codec) {
+    case ZFO_PLAIN: return zfo_elem_size(dtype) != 0;
+    case ZFO_FOR_BP:
+    case ZFO_DELTA_BP:
+    case ZFO_RLE_DELTA_BP: return dtype == ZFO_I32 || dtype == ZFO_I64;
+    case ZFO_DICT_BP: return dtype == ZFO_I32 || dtype == ZFO_I64 || dtype == ZFO_FIXED16;
+    case ZFO_LZ77: return zfo_elem_size(dtype) != 0;
+    default: return 0;
+    }
+}
+
+int zfo_decode_stream(uint32_t codec, uint32_t dtype, const uint8_t *s, uint64_t comp_len,
+                      uint32_t n, const uint8_t *dict, uint32_t dict_count, void *dstv) {
+    uint8_t *dst = (uint8_t *)dstv;
+    uint32_t es = zfo_elem_size(dtype);
+    if (!codec_allows(codec, dtype) || n == 0) return ZFO_ECORRUPT;
+    uint64_t plain = (uint64_t)n * es;
+    switch (codec) {
+    case ZFO_PLAIN:
+        if (comp_len != plain) return ZFO_ECORRUPT;
+        memcpy(dst, s, plain);
+        return ZFO_OK;
+    case ZFO_LZ77:
+        if (plain > LZ_MAX_CHUNK) return ZFO_ECORRUPT;
+        return dec_lz77(s, comp_len, (uint32_t)plain, dst);
+    case ZFO_DELTA_BP:
+    case ZFO_RLE_DELTA_BP:
+        return dec_rle_delta(s, comp_len, dtype, n, codec == ZFO_DELTA_BP, dst);
+    case ZFO_FOR_BP:
+    case ZFO_DICT_BP: {
+        uint64_t *tmp = (uint64_t *)malloc(sizeof(uint64_t) * n);
+        if (!tmp) return ZFO_ENOMEM;
+        uint32_t bits = codec == ZFO_DICT_BP ? 32u : int_bits(dtype);
+        int rc = dec_for_bp_u64(s, comp_len, n, bits, tmp);
+        for (uint32_t j = 0; rc == ZFO_OK && j < n; j++) {
+            if (codec == ZFO_FOR_BP) store_int(dst, dtype, j, tmp[j]);
+            else if (tmp[j] >= dict_count || !dict) rc = ZFO_ECORRUPT;
+            else memcpy(dst + (uint64_t)j * es, dict + tmp[j] * es, es);
+        }
+        free(tmp);
+        return rc;
+    }
+    }
+    return ZFO_ECORRUPT;
+}
+
+/* ============================================================= container */
+void zfo_free(void *p) { free(p); }
+
+int zfo_encode(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t codec,
+               const uint32_t *chunk_elems, uint32_t n_chunks, const uint32_t *codecs,
+               uint8_t **out, uint64_t *out_len) {
+    const uint8_t *src = (const uint8_t *)srcv;
+    uint32_t es = zfo_elem_size(dtype);
+    if (!es || !out || !out_len) return ZFO_EINVAL;
+    uint64_t sum = 0;
+    int any_dict = 0;
+    for (uint32_t i = 0; i < n_chunks; i++) {
+        uint32_t c = codecs ? codecs[i] : codec;
+        if (chunk_elems[i] == 0 || !codec_allows(c, dtype)) return ZFO_EINVAL;
+        if (c == ZFO_LZ77 && (uint64_t)chunk_elems[i] * es > LZ_MAX_CHUNK) return ZFO_EINVAL;
+        if ((uint64_t)chunk_elems[i] * es > 0xFFFFFFFFu) return ZFO_EINVAL;
+        any_dict |= c == ZFO_DICT_BP;
+        sum += chunk_elems[i];
+    }
+    if (sum != n_elems) return ZFO_EINVAL;
+    int mixed = 0;
+    for (uint32_t i = 1; i < n_chunks; i++)
+        if ((codecs ? codecs[i] : codec) != (codecs ? codecs[0] : codec)) mixed = 1;
+
+    uint8_t *dict = NULL;
+    uint32_t dict_count = 0;
+    if (any_dict) {
+        int rc = build_dict(src, n_elems, dtype, &dict, &dict_count);
+        if (rc) return rc;
+    }
+    uint64_t table_end = 64 + (uint64_t)32 * n_chunks;
+    uint64_t dict_off = dict_count ? align16(table_end) : 0;
+    uint64_t pos = align16(dict_count ? dict_off + (uint64_t)dict_count * es : table_end);
+
+    buf_t b = {0};
+    buf_resize(&b, pos);
+    uint64_t plain_off = 0;
+    uint32_t *codes = NULL;
+    for (uint32_t i = 0; i < n_chunks && !b.bad; i++) {
+        uint32_t c = codecs ? codecs[i] : codec, n = chunk_elems[i];
+        const uint8_t *x = src + plain_off;
+        buf_t s = {0};
+        switch (c) {
+        case ZFO_PLAIN:
+            buf_resize(&s, (uint64_t)n * es);
+            if (!s.bad) memcpy(s.p, x, (uint64_t)n * es);
+            break;
+        case ZFO_FOR_BP: enc_for_bp(&s, x, dtype, n); break;
+        case ZFO_DICT_BP:
+            codes = (uint32_t *)realloc(codes, sizeof(uint32_t) * n);
+            if (!codes) { s.bad = 1; break; }
+            for (uint32_t j = 0; j < n; j++)
+                codes[j] = dict_code(dict, dict_count, dtype, x + (uint64_t)j * es);
+            {
+                /* the code sequence as an I32 column */
+                uint8_t *cb = (uint8_t *)malloc((uint64_t)4 * n);
+                if (!cb) { s.bad = 1; break; }
+                for (uint32_t j = 0; j < n; j++) put32(cb + 4 * (uint64_t)j, codes[j]);
+                enc_for_bp(&s, cb, ZFO_I32, n);
+                free(cb);
+            }
+            break;
+        case ZFO_DELTA_BP: enc_rle_delta(&s, x, dtype, n, 1); break;
+        case ZFO_RLE_DELTA_BP: enc_rle_delta(&s, x, dtype, n, 0); break;
+        case ZFO_LZ77: enc_lz77(&s, x, n * es); break;
+        }
+        if (s.bad || s.n > 0xFFFFFFFFu) { free(s.p); b.bad = 1; break; }
+        buf_resize(&b, pos + s.n);
+        if (!b.bad) {
+            memcpy(b.p + pos, s.p, s.n);
+            uint8_t *e = b.p + 64 + (uint64_t)32 * i;
+            put64(e + 0, plain_off);
+            put64(e + 8, pos);
+            put32(e + 16, n * es);
+            put32(e + 20, (uint32_t)s.n);
+            put32(e + 24, n);
+            put8(e + 28, c);
+        }
+        free(s.p);
+        pos = align16(pos + s.n);
+        plain_off += (uint64_t)n * es;
+    }
+    free(codes);
+    buf_resize(&b, pos);
+    if (b.bad) { free(b.p); free(dict); return ZFO_ENOMEM; }
+    if (dict_count) memcpy(b.p + dict_off, dict, (uint64_t)dict_count * es);
+    free(dict);
+
+    uint8_t *h = b.p;
+    memcpy(h, "ZFC1", 4);
+    put16(h + 4, 1);
+    put8(h + 6, dtype);
+    /* the column codec byte is 0 when the chunks mix codecs */
+    uint32_t col_codec = n_chunks == 0 ? codec : (codecs ? codecs[0] : codec);
+    put8(h + 7, mixed ? 0 : col_codec);
+    put64(h + 8, n_elems);
+    put64(h + 16, n_elems * es);
+    put32(h + 24, n_chunks);
+    put32(h + 28, dict_count);
+    put64(h + 32, dict_off);
+    put64(h + 40, pos);
+    /* table CRC covers the chunk table followed by the dictionary */
+    uint64_t tl = (uint64_t)32 * n_chunks, dl = (uint64_t)dict_count * es;
+    uint8_t *tmp = (uint8_t *)malloc(tl + dl + 1);
+    if (!tmp) { free(b.p); return ZFO_ENOMEM; }
+    memcpy(tmp, h + 64, tl);
+    if (dl) memcpy(tmp + tl, h + dict_off, dl);
+    put32(h + 48, zfo_crc32(tmp, tl + dl));
+    free(tmp);
+    put32(h + 52, 0);
+    put32(h + 56, 0);
+    put32(h + 60, zfo_crc32(h, 60));
+    *out = b.p;
+    *out_len = pos;
+    return ZFO_OK;
+}
+
+int zfo_inspect(const uint8_t *blob, uint64_t len, zfo_info *info) {
+    if (!blob || len < 64) return ZFO_ECORRUPT;
+    if (memcmp(blob, "ZFC1", 4) != 0 || get16(blob + 4) != 1) return ZFO_ECORRUPT;
+    if (get32(blob + 60) != zfo_crc32(blob, 60)) return ZFO_ECORRUPT;
+    zfo_info in;
+    in.dtype = blob[6];
+    in.codec = blob[7];
+    in.n_elems = get64(blob + 8);
+    in.plain_bytes = get64(blob + 16);
+    in.n_chunks = get32(blob + 24);
+    in.dict_count = get32(blob + 28);
+    in.dict_off = get64(blob + 32);
+    in.total_bytes = get64(blob + 40);
+    uint32_t es = zfo_elem_size(in.dtype);
+    if (!es || in.plain_bytes != in.n_elems * es || in.total_bytes != len) return ZFO_ECORRUPT;
+    uint64_t tl = (uint64_t)32 * in.n_chunks;
+    if (64 + tl > len) return ZFO_ECORRUPT;
+    uint64_t dl = (uint64_t)in.dict_count * es;
+    if (in.dict_count) {
+        if (in.dict_off % 16 != 0 || in.dict_off < 64 + tl || in.dict_off + dl > len)
+            return ZFO_ECORRUPT;
+    } else if (in.dict_off != 0) return ZFO_ECORRUPT;
+    uint8_t *tmp = (uint8_t *)malloc(tl + dl + 1);
+    if (!tmp) return ZFO_ENOMEM;
+    memcpy(tmp, blob + 64, tl);
+    if (dl) memcpy(tmp + tl, blob + in.dict_off, dl);
+    uint32_t crc = zfo_crc32(tmp, tl + dl);
+    free(tmp);
+    if (crc != get32(blob + 48)) return ZFO_ECORRUPT;
+    /* chunks tile the plain bytes in order and sit inside the blob */
+    uint64_t plain_off = 0, elems = 0;
+    for (uint32_t i = 0; i < in.n_chunks; i++) {
+        zfo_chunk c;
+        zfo_get_chunk(blob, len, i, &c);
+        if (c.plain_off != plain_off || c.n_elems == 0 || (uint64_t)c.n_elems * es != c.plain_len)
+            return ZFO_ECORRUPT;
+        if (c.comp_off % 16 != 0 || c.comp_off < 64 + tl || c.comp_off + c.comp_len > len)
+            return ZFO_ECORRUPT;
+        if (!codec_allows(c.codec, in.dtype)) return ZFO_ECORRUPT;
+        if (c.codec == ZFO_DICT_BP && in.dict_count == 0) return ZFO_ECORRUPT;
+        plain_off += c.plain_len;
+        elems += c.n_elems;
+    }
+    if (plain_off != in.plain_bytes || elems != in.n_elems) return ZFO_ECORRUPT;
+    if (info) *info = in;
+    return ZFO_OK;
+}
+
+int zfo_get_chunk(const uint8_t *blob, uint64_t len, uint32_t i, zfo_chunk *c) {
+    if (len < 64 || i >= get32(blob + 24) || 64 + (uint64_t)32 * (i + 1) > len) return ZFO_EINVAL;
+    const uint8_t *e = blob + 64 + (uint64_t)32 * i;
+    c->plain_off = get64(e);
+    c->comp_off = get64(e + 8);
+    c->plain_len = get32(e + 16);
+    c->comp_len = get32(e + 20);
+    c->n_elems = get32(e + 24);
+    c->codec = e[28];
+    return ZFO_OK;
+}
+
+int zfo_decode_chunks(const uint8_t *blob, uint64_t len, uint32_t first, uint32_t count,
+                      void *dstv, uint64_t dst_len) {
+    zfo_info in;
+    int rc = zfo_inspect(blob, len, &in);
+    if (rc) return rc;
+    if ((uint64_t)first + count > in.n_chunks) return ZFO_EINVAL;
+    uint8_t *dst = (uint8_t *)dstv;
+    uint64_t need = 0;
+    for (uint32_t i = first; i < first + count; i++) {
+        zfo_chunk c;
+        zfo_get_chunk(blob, len, i, &c);
+        need += c.plain_len;
+    }
+    if (need != dst_len) return ZFO_EINVAL;
+    uint64_t at = 0;
+    const uint8_t *dict = in.dict_count ? blob + in.dict_off : NULL;
+    for (uint32_t i = first; i < first + count; i++) {
+        zfo_chunk c;
+        zfo_get_chunk(blob, len, i, &c);
+        rc = zfo_decode_stream(c.codec, in.dtype, blob + c.comp_off, c.comp_len, c.n_elems, dict,
+                               in.dict_count, dst + at);
+        if (rc) return rc;
+        at += c.plain_len;
+    }
+    return ZFO_OK;
+}
+
+int zfo_decode(const uint8_t *blob, uint64_t len, void *dst, uint64_t dst_len) {
+    zfo_info in;
+    int rc = zfo_inspect(blob, len, &in);
+    if (rc) return rc;
+    if (dst_len != in.plain_bytes) return ZFO_EINVAL;
+    return zfo_decode_chunks(blob, len, 0, in.n_chunks, dst, dst_len);
+}

@@ -1,0 +1,76 @@
+"""Build the native libraries in-tree.
+
+* ``libzf.so``     -- the zf library: host C++ (encoders, planner, pipeline,
+  C ABI) and the HIP kernels, compiled for gfx950 with hipcc.
+* ``libzfgen.so``  -- the input generator's text helper (plain C).
+"""
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
+OBJ = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libzf.so")
+GENLIB = os.path.join(HERE, "libzfgen.so")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+
+HOST_SRC = ["abi.cpp", "format.cpp", "encode.cpp", "plan.cpp", "run.cpp"]
+HIP_SRC = ["kernels.hip"]
+
+COMMON = ["-O3", "-fPIC", "-std=c++17", "-I", INCLUDE, "-I", CSRC, "-Wall",
+          "-Wno-unused-function", "-Wno-unused-parameter"]
+# Packed FP32 instructions are kept out of every device build.
+DEVICE = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
+          "-packed-fp32-ops", "-munsafe-fp-atomics"]
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(" ".join(cmd) + "\n" + r.stdout + r.stderr)
+        raise RuntimeError(f"compile failed: {cmd[-1]}")
+    return r.stderr
+
+
+def build_gen():
+    tmp = GENLIB + ".tmp"
+    _run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp,
+          os.path.join(HERE, "datagen_text.c")])
+    os.replace(tmp, GENLIB)
+    return GENLIB
+
+
+def build_zf(jobs=8):
+    os.makedirs(OBJ, exist_ok=True)
+    cmds = []
+    objs = []
+    for s in HOST_SRC:
+        o = os.path.join(OBJ, s + ".o")
+        cmds.append([HIPCC] + COMMON + ["-D__HIP_PLATFORM_AMD__", "-c", "-o", o,
+                                        os.path.join(CSRC, s)])
+        objs.append(o)
+    for s in HIP_SRC:
+        o = os.path.join(OBJ, s + ".o")
+        cmds.append([HIPCC] + COMMON + DEVICE + ["-c", "-o", o, os.path.join(CSRC, s)])
+        objs.append(o)
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        list(ex.map(_run, cmds))
+    tmp = LIB + ".tmp"
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs +
+         ["-lpthread"])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def build():
+    build_gen()
+    build_zf()
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build())
