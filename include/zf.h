@@ -1,0 +1,218 @@
+/*
+ * zf.h -- C ABI of the zf library: compressed column chunks move from pinned
+ * host memory to an MI355X over PCIe and are decoded there by HIP kernels.
+ *
+ * The calls follow the problem statement of the ZipFlow paper (Sec. 3,
+ * "Design"): columns are compressed on the CPU and kept in CPU memory;
+ * online, the compressed bytes cross PCIe and a device-specific decoder
+ * expands them in GPU memory, with copies and decodes of successive blocks
+ * overlapped (Sec. 3.3) and kernels instantiated per device (Sec. 4).
+ *
+ * Conventions for every call:
+ *   - plain C types only; pointers are host pointers unless named d_*;
+ *     a zf_stream_t is a hipStream_t (NULL = the legacy default stream).
+ *   - every call returns a zf_status; on failure the out-parameters are left
+ *     untouched and zf_last_error() holds a message for the calling thread.
+ *   - no C++ exception crosses this boundary.
+ *
+ * Column byte format (little-endian), shared by every codec:
+ *   64-byte header: "ZFC1", u16 version = 1, u8 dtype, u8 codec (0 when the
+ *     chunks mix codecs), u64 n_elems, u64 plain_bytes, u32 n_chunks,
+ *     u32 dict_count, u64 dict_off, u64 total_bytes, u32 table_crc,
+ *     u32 0, u32 0, u32 header_crc (CRC-32 of header bytes [0,60)).
+ *   chunk table at 64: per chunk 32 bytes {u64 plain_off, u64 comp_off,
+ *     u32 plain_len, u32 comp_len, u32 n_elems, u8 codec, 3 zero bytes}.
+ *   dictionary (dict_count > 0) at dict_off: sorted unique values.
+ *   chunk streams at 16-aligned comp_off.  table_crc = CRC-32 of the chunk
+ *   table followed by the dictionary.  The per-codec streams are described
+ *   at zf_codec below.
+ */
+#ifndef ZF_H
+#define ZF_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ZF_OK = 0,
+    ZF_E_INVALID = 1,     /* bad argument (null pointer, size mismatch, bad enum) */
+    ZF_E_UNSUPPORTED = 2, /* valid request this build does not handle          */
+    ZF_E_CORRUPT = 3,     /* stream failed validation on the host or the device */
+    ZF_E_NOMEM = 4,       /* host or device allocation failed                   */
+    ZF_E_HIP = 5,         /* a HIP runtime call failed                          */
+    ZF_E_TOO_SMALL = 6,   /* a caller buffer is smaller than required           */
+    ZF_E_STATE = 7        /* call out of order (e.g. plan already failed)       */
+} zf_status;
+
+typedef enum {
+    ZF_I32 = 1,     /* int32 values                        */
+    ZF_I64 = 2,     /* int64 values                        */
+    ZF_BYTES = 3,   /* byte column (e.g. text)             */
+    ZF_FIXED16 = 4  /* 16-byte fixed-width strings, CHAR(16) */
+} zf_dtype;
+
+/*
+ * Codecs (Sec. 2.1 defines the algorithms; Sec. 3.1 classifies them as
+ * Fully-Parallel, Group-Parallel or Non-Parallel):
+ *  ZF_PLAIN         raw bytes.
+ *  ZF_FOR_BP        [FP] frame of reference + bit-packing, blocks of 2048:
+ *                   16-byte directory {i64 ref = block minimum, u32 w, u32 poff}
+ *                   per block, payload of w-bit fields, LSB-first in LE u32
+ *                   words; value = ref + field (mod 2^bits).  I32, I64.
+ *  ZF_DICT_BP       [FP] dictionary + bit-packing: the column dictionary is
+ *                   the sorted distinct values; a chunk is the FOR_BP stream
+ *                   of the dictionary indices; value = dict[code].
+ *                   I32, I64, FIXED16.
+ *  ZF_DELTA_BP      [GP] delta + bit-packing: ZF_RLE_DELTA_BP with every run
+ *                   of length one and no run array.  I32, I64.
+ *  ZF_RLE_DELTA_BP  [GP] RLE; run values delta-coded and bit-packed; groups
+ *                   of 64 runs, each with a 32-byte record {u32 out_off,
+ *                   u32 w, u32 doff, u32 0, i64 base, i64 dmin}; header
+ *                   {u32 n_runs, u32 n_groups, u32 runs_off, u32 0}; u32 run
+ *                   lengths at runs_off.  I32, I64.
+ *  ZF_LZ77          [NP] LZ77 sequences in chunks of <= 65536 bytes; header
+ *                   {u32 n_seq, u32 n_lit, u32 n_ext, u32 plain_len}, u16
+ *                   offsets[n_seq], u16 ext[n_ext], u8 tags[n_seq], literals.
+ *                   Tag bits 0-2: literal count (7 = 7 + next ext), bits 3-7:
+ *                   match code (0 none, 1..30 -> length code+3, 31 -> 34 +
+ *                   next ext).  Any dtype (decoded as bytes).
+ */
+typedef enum {
+    ZF_AUTO = 0,
+    ZF_PLAIN = 1,
+    ZF_FOR_BP = 2,
+    ZF_DICT_BP = 3,
+    ZF_DELTA_BP = 4,
+    ZF_RLE_DELTA_BP = 5,
+    ZF_LZ77 = 6
+} zf_codec;
+
+typedef void *zf_stream_t;              /* a hipStream_t */
+typedef struct zf_column zf_column_t;   /* compressed column, host memory */
+typedef struct zf_plan zf_plan_t;       /* schedule + device workspace     */
+
+typedef struct {
+    uint32_t chunk_bytes_min;     /* uneven chunks: log-uniform plain size in  */
+    uint32_t chunk_bytes_max;     /*  [min, max]; min == max gives fixed size  */
+    uint64_t seed;                /* seed of the chunk-size draw               */
+    int32_t n_threads;            /* encoder threads; 0 = all host cores       */
+    int32_t pinned;               /* 1: hipHostMalloc (default); 0: malloc     */
+    const uint32_t *chunk_elems;  /* explicit chunking (overrides the above)   */
+    uint32_t n_chunk_elems;
+    const uint32_t *chunk_codecs; /* per-chunk codec for explicit chunking     */
+} zf_encode_opts;
+
+/* Defaults: chunks of 1 MiB plain (LZ77: 64 KiB), all cores, pinned. */
+void zf_encode_opts_default(zf_encode_opts *opts);
+
+/*
+ * Compress n_elems values of `dtype` at src (host memory, read only, not
+ * retained) into a new column (Sec. 3: compression runs on the CPU and the
+ * result stays in CPU memory).  Chunks are encoded in parallel.  With codec
+ * ZF_AUTO each chunk takes the codec the cost model predicts cheapest.
+ * n_elems == 0 makes an empty column.  The column owns its memory (pinned by
+ * default) until zf_column_free.  Errors: ZF_E_INVALID (dtype/codec mix,
+ * null pointers, chunking that does not sum to n_elems, LZ77 chunks above
+ * 65536 bytes), ZF_E_NOMEM.
+ */
+zf_status zf_compress_host(const void *src, uint64_t n_elems, zf_dtype dtype, zf_codec codec,
+                           const zf_encode_opts *opts /* nullable */, zf_column_t **out);
+
+/* Adopt a serialised column (copied; `pinned` as in zf_encode_opts).  The
+ * header, CRCs, chunk table and every stream's directory are validated;
+ * ZF_E_CORRUPT on failure. */
+zf_status zf_column_from_bytes(const void *buf, uint64_t len, int32_t pinned, zf_column_t **out);
+/* Serialised bytes of a column (owned by the column). */
+const void *zf_column_bytes(const zf_column_t *col, uint64_t *len);
+uint64_t zf_column_plain_bytes(const zf_column_t *col);
+uint64_t zf_column_n_elems(const zf_column_t *col);
+uint32_t zf_column_n_chunks(const zf_column_t *col);
+int32_t zf_column_dtype(const zf_column_t *col);
+void zf_column_free(zf_column_t *col);
+
+/* Tile shapes (the paper's <L,S,C> per pattern, Sec. 4); 0 = tune cache. */
+typedef struct {
+    uint32_t fp_blocks;       /* FP: 2048-value blocks per wave unit            */
+    uint32_t gp_elems;        /* GP: output elements per wave unit              */
+    uint32_t waves_per_block; /* waves per workgroup (per-kind launches)        */
+    uint32_t waves_per_cu;    /* persistent kernel: waves in flight per CU      */
+} zf_tiles;
+
+typedef struct {
+    uint64_t slot_bytes;     /* staging slot size for transfers (default 256 MiB) */
+    int32_t n_slots;         /* staging slots, >= 1 (default 2: double buffering)   */
+    int32_t use_graphs;      /* 1: one hipGraph per batch (default); 0: plain launches */
+    int32_t persistent;      /* 1: one persistent multi-codec kernel per batch (default);
+                                0: one launch per pattern class                      */
+    int32_t order;           /* 0: Johnson order (default); 1: column order          */
+    double pcie_gbps;        /* transfer-time estimate for ordering (0: 55)          */
+    zf_tiles tiles;          /* explicit tile shapes; zero fields use the defaults */
+} zf_plan_opts;
+
+void zf_plan_opts_default(zf_plan_opts *opts);
+
+/*
+ * Build a plan for decoding `cols` on HIP device `device`: per-chunk tiles
+ * from the tune cache (Sec. 4, device geometry scheduling), batches of chunks
+ * no larger than one staging slot, the batch order by Johnson's rule on
+ * (transfer, decode) estimates (Sec. 3.3), and the device workspace (tables,
+ * staging slots, error word, graphs).  The columns must outlive the plan and
+ * must not change.  Errors: ZF_E_INVALID, ZF_E_CORRUPT (host validation of
+ * every stream header), ZF_E_NOMEM, ZF_E_HIP.
+ */
+zf_status zf_plan(const zf_column_t *const *cols, uint32_t n_cols, int32_t device,
+                  const zf_plan_opts *opts /* nullable */, zf_plan_t **out);
+void zf_plan_free(zf_plan_t *plan);
+
+/* Device image for zf_decompress_async: column c's serialised bytes go at
+ * byte offset zf_plan_image_offset(plan, c) of a device buffer of
+ * zf_plan_image_bytes(plan) bytes (offsets are 256-aligned). */
+uint64_t zf_plan_image_bytes(const zf_plan_t *plan);
+uint64_t zf_plan_image_offset(const zf_plan_t *plan, uint32_t col);
+
+/*
+ * Decode every column of the plan from a device image already in HBM
+ * (d_comp, laid out as above) into d_out[c] (device buffers of exactly
+ * zf_column_plain_bytes(cols[c]) bytes, 16-aligned), enqueued on `stream`.
+ * The image must hold the same bytes the plan was built from; kernels
+ * re-check every offset they use against the plan's sizes, never read or
+ * write out of bounds, and latch corruption into the plan's error word
+ * (reported by zf_sync).  Returns after enqueueing.  A plan serves one
+ * stream at a time.
+ */
+zf_status zf_decompress_async(zf_plan_t *plan, const void *d_comp, uint64_t comp_bytes,
+                              void *const *d_out, zf_stream_t stream);
+
+typedef struct {
+    double h2d_ms;       /* sum of copy durations                       */
+    double decode_ms;    /* sum of decode durations                     */
+    double wall_ms;      /* first copy start to last decode end         */
+    uint64_t plain_bytes, comp_bytes;
+} zf_timing;
+
+/*
+ * Transfer and decode (Sec. 3.3): for each batch in plan order, the copy
+ * stream waits for its staging slot to be free, copies the batch's
+ * compressed chunks from the columns' pinned memory over PCIe, and signals;
+ * `stream` waits for that signal and runs the batch's decode graph.  With two
+ * slots the copy of batch k+1 overlaps the decode of batch k.  Outputs as in
+ * zf_decompress_async.  `timing` (nullable) is filled by zf_sync.
+ */
+zf_status zf_transfer_and_decompress(zf_plan_t *plan, void *const *d_out, zf_stream_t stream,
+                                     zf_timing *timing);
+
+/* Wait for the plan's work on `stream`; read the device error word:
+ * ZF_E_CORRUPT if any kernel found a corrupt stream (sticky until
+ * zf_plan_clear_error). */
+zf_status zf_sync(zf_plan_t *plan, zf_stream_t stream);
+void zf_plan_clear_error(zf_plan_t *plan);
+
+const char *zf_status_str(zf_status s);
+const char *zf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -21,7 +21,7 @@ ARCH = "gfx950"
 HOST_SRC = ["abi.cpp", "format.cpp", "encode.cpp", "plan.cpp", "run.cpp"]
 HIP_SRC = ["kernels.hip"]
 
-COMMON = ["-O3", "-fPIC", "-std=c++17", "-I", INCLUDE, "-I", CSRC, "-Wall",
+COMMON = ["-O3", "-fPIC", "-std=c++17", "-I", INCLUDE, "-I", CSRC, "-I", "/opt/rocm/include", "-Wall",
           "-Wno-unused-function", "-Wno-unused-parameter"]
 # Packed FP32 instructions are kept out of every device build.
 DEVICE = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
@@ -50,7 +50,7 @@ def build_zf(jobs=8):
     objs = []
     for s in HOST_SRC:
         o = os.path.join(OBJ, s + ".o")
-        cmds.append([HIPCC] + COMMON + ["-D__HIP_PLATFORM_AMD__", "-c", "-o", o,
+        cmds.append([HIPCC] + COMMON + ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-c", "-o", o,
                                         os.path.join(CSRC, s)])
         objs.append(o)
     for s in HIP_SRC:

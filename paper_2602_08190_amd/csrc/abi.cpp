@@ -1,0 +1,141 @@
+// extern "C" entry points declared in zf.h.  Each one validates its
+// arguments, runs inside zf::guard (no exception crosses the boundary) and
+// leaves its out-parameters untouched on failure.
+#include <memory>
+
+#include "plan.hpp"
+
+namespace zf {
+const std::string &last_error();
+void compress_host(const void *src, uint64_t n_elems, uint32_t dtype, uint32_t codec,
+                   const zf_encode_opts &o, zf_column_t *col);
+void build_plan(zf_plan_t *P, const zf_column *const *cols, uint32_t n_cols, int device,
+                const zf_plan_opts &o);
+void decompress_async(zf_plan_t *P, const void *d_comp, uint64_t comp_bytes, void *const *d_out,
+                      hipStream_t st);
+void transfer_and_decompress(zf_plan_t *P, void *const *d_out, hipStream_t st, zf_timing *timing);
+void sync_plan(zf_plan_t *P, hipStream_t st);
+void clear_error(zf_plan_t *P);
+}  // namespace zf
+
+using namespace zf;
+
+extern "C" {
+
+void zf_encode_opts_default(zf_encode_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->pinned = 1;
+}
+
+void zf_plan_opts_default(zf_plan_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->slot_bytes = 256ull << 20;
+    o->n_slots = 2;
+    o->use_graphs = 1;
+    o->persistent = 1;
+    o->order = 0;
+    o->pcie_gbps = 0;
+}
+
+zf_status zf_compress_host(const void *src, uint64_t n_elems, zf_dtype dtype, zf_codec codec,
+                           const zf_encode_opts *opts, zf_column_t **out) {
+    return guard([&] {
+        ZF_REQUIRE(out, ZF_E_INVALID, "null output pointer");
+        zf_encode_opts o;
+        zf_encode_opts_default(&o);
+        if (opts) o = *opts;
+        auto col = std::make_unique<zf_column>();
+        compress_host(src, n_elems, uint32_t(dtype), uint32_t(codec), o, col.get());
+        *out = col.release();
+    });
+}
+
+zf_status zf_column_from_bytes(const void *buf, uint64_t len, int32_t pinned, zf_column_t **out) {
+    return guard([&] {
+        ZF_REQUIRE(buf && out, ZF_E_INVALID, "null pointer");
+        ColumnView v = parse_column(static_cast<const uint8_t *>(buf), len);
+        auto col = std::make_unique<zf_column>();
+        col->buf.alloc(len, pinned != 0);
+        std::memcpy(col->buf.p, buf, len);
+        col->view = std::move(v);
+        *out = col.release();
+    });
+}
+
+const void *zf_column_bytes(const zf_column_t *col, uint64_t *len) {
+    if (!col) return nullptr;
+    if (len) *len = col->buf.n;
+    return col->buf.p;
+}
+uint64_t zf_column_plain_bytes(const zf_column_t *col) { return col ? col->view.plain_bytes : 0; }
+uint64_t zf_column_n_elems(const zf_column_t *col) { return col ? col->view.n_elems : 0; }
+uint32_t zf_column_n_chunks(const zf_column_t *col) { return col ? col->view.n_chunks : 0; }
+int32_t zf_column_dtype(const zf_column_t *col) { return col ? int32_t(col->view.dtype) : 0; }
+void zf_column_free(zf_column_t *col) { delete col; }
+
+zf_status zf_plan(const zf_column_t *const *cols, uint32_t n_cols, int32_t device,
+                  const zf_plan_opts *opts, zf_plan_t **out) {
+    return guard([&] {
+        ZF_REQUIRE(out, ZF_E_INVALID, "null output pointer");
+        zf_plan_opts o;
+        zf_plan_opts_default(&o);
+        if (opts) o = *opts;
+        auto P = std::make_unique<zf_plan_t>();
+        build_plan(P.get(), cols, n_cols, device, o);
+        *out = P.release();
+    });
+}
+
+void zf_plan_free(zf_plan_t *plan) { delete plan; }
+
+uint64_t zf_plan_image_bytes(const zf_plan_t *plan) { return plan ? plan->image_bytes : 0; }
+uint64_t zf_plan_image_offset(const zf_plan_t *plan, uint32_t col) {
+    return (plan && col < plan->image_off.size()) ? plan->image_off[col] : 0;
+}
+
+zf_status zf_decompress_async(zf_plan_t *plan, const void *d_comp, uint64_t comp_bytes,
+                              void *const *d_out, zf_stream_t stream) {
+    return guard([&] {
+        ZF_REQUIRE(plan, ZF_E_INVALID, "null plan");
+        decompress_async(plan, d_comp, comp_bytes, d_out, static_cast<hipStream_t>(stream));
+    });
+}
+
+zf_status zf_transfer_and_decompress(zf_plan_t *plan, void *const *d_out, zf_stream_t stream,
+                                     zf_timing *timing) {
+    return guard([&] {
+        ZF_REQUIRE(plan, ZF_E_INVALID, "null plan");
+        transfer_and_decompress(plan, d_out, static_cast<hipStream_t>(stream), timing);
+    });
+}
+
+zf_status zf_sync(zf_plan_t *plan, zf_stream_t stream) {
+    return guard([&] {
+        ZF_REQUIRE(plan, ZF_E_INVALID, "null plan");
+        sync_plan(plan, static_cast<hipStream_t>(stream));
+    });
+}
+
+void zf_plan_clear_error(zf_plan_t *plan) {
+    if (plan) clear_error(plan);
+}
+
+const char *zf_status_str(zf_status s) {
+    switch (s) {
+    case ZF_OK: return "ok";
+    case ZF_E_INVALID: return "invalid argument";
+    case ZF_E_UNSUPPORTED: return "unsupported";
+    case ZF_E_CORRUPT: return "corrupt stream";
+    case ZF_E_NOMEM: return "out of memory";
+    case ZF_E_HIP: return "HIP runtime error";
+    case ZF_E_TOO_SMALL: return "buffer too small";
+    case ZF_E_STATE: return "bad state";
+    }
+    return "unknown status";
+}
+
+const char *zf_last_error(void) { return last_error().c_str(); }
+
+}  // extern "C"

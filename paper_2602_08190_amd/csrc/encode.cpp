@@ -1,0 +1,542 @@
+// Host encoders (Sec. 3: compression happens on the CPU and the compressed
+// column stays in CPU memory).  Chunks are independent, so they are encoded in
+// parallel across host threads.  FOR_BP, DICT_BP, DELTA_BP and RLE_DELTA_BP
+// produce the canonical streams of the zf format byte for byte; the LZ77
+// encoder additionally keeps every 64-sequence batch "flat" (see enc_lz77) so
+// that the GPU can decode a batch with one sequence per lane.
+#include <algorithm>
+#include <atomic>
+#include <functional>
+#include <mutex>
+#include <cmath>
+#include <thread>
+#include <type_traits>
+
+#include "zf_internal.hpp"
+
+namespace zf {
+
+// ---------------------------------------------------------------- helpers
+static inline uint32_t bit_width64(uint64_t v) { return v ? 64u - uint32_t(__builtin_clzll(v)) : 0u; }
+
+static void parallel_for(uint64_t n, int threads, const std::function<void(uint64_t)> &fn);
+
+// Append LSB-first w-bit fields into little-endian u32 words at `dst`.
+struct BitPacker {
+    uint8_t *dst;
+    unsigned __int128 acc = 0;
+    uint32_t nbits = 0;
+    uint64_t words = 0;
+    explicit BitPacker(uint8_t *d) : dst(d) {}
+    inline void put(uint64_t v, uint32_t w) {
+        if (w == 0) return;
+        acc |= (unsigned __int128)v << nbits;
+        nbits += w;
+        while (nbits >= 32) {
+            wr32(dst + 4 * words++, uint32_t(acc));
+            acc >>= 32;
+            nbits -= 32;
+        }
+    }
+    inline void flush() {
+        if (nbits) wr32(dst + 4 * words++, uint32_t(acc));
+        acc = 0;
+        nbits = 0;
+    }
+};
+
+// ------------------------------------------------------------- FOR + BP
+// Blocks of 2048 values; the reference is the block minimum and the width
+// covers max - min (Sec. 2.1).
+template <class T>
+static void enc_for(std::vector<uint8_t> &s, const T *x, uint32_t n) {
+    using U = std::make_unsigned_t<T>;
+    const uint64_t nb = (n + kForBlock - 1) / kForBlock;
+    std::vector<T> ref(nb);
+    std::vector<uint32_t> w(nb), poff(nb);
+    uint64_t pos = align_up(16 * nb, 16), end = pos;
+    for (uint64_t b = 0; b < nb; b++) {
+        const T *v = x + b * kForBlock;
+        const uint32_t nv = uint32_t(std::min<uint64_t>(kForBlock, n - b * kForBlock));
+        T lo = v[0], hi = v[0];
+        for (uint32_t j = 1; j < nv; j++) {
+            lo = std::min(lo, v[j]);
+            hi = std::max(hi, v[j]);
+        }
+        ref[b] = lo;
+        w[b] = bit_width64(uint64_t(U(U(hi) - U(lo))));
+        poff[b] = uint32_t(pos);
+        end = pos + 4 * ((uint64_t(nv) * w[b] + 31) / 32);
+        pos = align_up(end, 16);
+    }
+    s.assign(end, 0);
+    for (uint64_t b = 0; b < nb; b++) {
+        wr64(s.data() + 16 * b, uint64_t(int64_t(ref[b])));
+        wr32(s.data() + 16 * b + 8, w[b]);
+        wr32(s.data() + 16 * b + 12, poff[b]);
+        const T *v = x + b * kForBlock;
+        const uint32_t nv = uint32_t(std::min<uint64_t>(kForBlock, n - b * kForBlock));
+        BitPacker bp(s.data() + poff[b]);
+        const U r = U(ref[b]);
+        for (uint32_t j = 0; j < nv; j++) bp.put(uint64_t(U(U(v[j]) - r)), w[b]);
+        bp.flush();
+    }
+}
+
+// ------------------------------------------------------------ dictionary
+// Open-addressing set/map over keys of up to 16 bytes.
+struct KeyTable {
+    std::vector<uint64_t> k0, k1;
+    std::vector<uint32_t> val;
+    std::vector<uint8_t> used;
+    uint64_t mask = 0, count = 0;
+    static inline uint64_t mix(uint64_t a, uint64_t b) {
+        uint64_t z = a * 0x9E3779B97F4A7C15ull ^ (b + 0x7F4A7C159E3779B9ull + (a << 6) + (a >> 2));
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+    void init(uint64_t cap) {
+        uint64_t c = 16;
+        while (c < 2 * cap) c <<= 1;
+        k0.assign(c, 0);
+        k1.assign(c, 0);
+        val.assign(c, 0);
+        used.assign(c, 0);
+        mask = c - 1;
+        count = 0;
+    }
+    // returns slot; inserts when absent
+    uint64_t insert(uint64_t a, uint64_t b) {
+        if (2 * (count + 1) > mask + 1) grow();
+        uint64_t h = mix(a, b) & mask;
+        while (used[h]) {
+            if (k0[h] == a && k1[h] == b) return h;
+            h = (h + 1) & mask;
+        }
+        used[h] = 1;
+        k0[h] = a;
+        k1[h] = b;
+        count++;
+        return h;
+    }
+    int64_t find(uint64_t a, uint64_t b) const {
+        uint64_t h = mix(a, b) & mask;
+        while (used[h]) {
+            if (k0[h] == a && k1[h] == b) return int64_t(h);
+            h = (h + 1) & mask;
+        }
+        return -1;
+    }
+    void grow() {
+        KeyTable t;
+        t.init(2 * (mask + 1));
+        for (uint64_t i = 0; i <= mask; i++)
+            if (used[i]) t.insert(k0[i], k1[i]);
+        *this = std::move(t);
+    }
+};
+
+static inline void key_of(const uint8_t *v, uint32_t es, uint64_t &a, uint64_t &b) {
+    a = b = 0;
+    if (es == 4) a = uint64_t(int64_t(int32_t(rd32(v))));
+    else if (es == 8) a = rd64(v);
+    else { a = rd64(v); b = rd64(v + 8); }
+}
+
+struct Dictionary {
+    std::vector<uint8_t> bytes;  // sorted unique entries
+    uint32_t count = 0;
+    uint32_t es = 0;
+    KeyTable index;              // key -> code
+};
+
+// Sorted distinct values (integers by signed value, FIXED16 by memcmp).
+// Returns false when there are more than max_count distinct values.
+static bool build_dictionary(Dictionary &d, const uint8_t *x, uint64_t n, uint32_t dtype,
+                             uint64_t max_count, int threads) {
+    const uint32_t es = elem_size(dtype);
+    d.es = es;
+    const uint64_t parts = std::max<uint64_t>(1, std::min<uint64_t>(threads, (n + 65535) / 65536));
+    std::vector<KeyTable> local(parts);
+    std::atomic<bool> over{false};
+    parallel_for(parts, threads, [&](uint64_t p) {
+        uint64_t lo = n * p / parts, hi = n * (p + 1) / parts;
+        local[p].init(1024);
+        for (uint64_t i = lo; i < hi && !over.load(std::memory_order_relaxed); i++) {
+            uint64_t a, b;
+            key_of(x + i * es, es, a, b);
+            local[p].insert(a, b);
+            if (local[p].count > max_count) over = true;
+        }
+    });
+    if (over) return false;
+    KeyTable all;
+    all.init(1024);
+    for (auto &t : local)
+        for (uint64_t i = 0; i <= t.mask; i++)
+            if (t.used[i]) all.insert(t.k0[i], t.k1[i]);
+    if (all.count > max_count) return false;
+    std::vector<std::pair<uint64_t, uint64_t>> keys;
+    keys.reserve(all.count);
+    for (uint64_t i = 0; i <= all.mask; i++)
+        if (all.used[i]) keys.emplace_back(all.k0[i], all.k1[i]);
+    if (es == 16) {
+        std::sort(keys.begin(), keys.end(), [](auto &p, auto &q) {
+            uint8_t a[16], b[16];
+            wr64(a, p.first); wr64(a + 8, p.second);
+            wr64(b, q.first); wr64(b + 8, q.second);
+            return std::memcmp(a, b, 16) < 0;
+        });
+    } else {
+        std::sort(keys.begin(), keys.end(),
+                  [](auto &p, auto &q) { return int64_t(p.first) < int64_t(q.first); });
+    }
+    d.count = uint32_t(keys.size());
+    d.bytes.assign(uint64_t(d.count) * es, 0);
+    d.index = std::move(all);
+    for (uint32_t c = 0; c < d.count; c++) {
+        uint8_t *e = d.bytes.data() + uint64_t(c) * es;
+        if (es == 4) wr32(e, uint32_t(keys[c].first));
+        else if (es == 8) wr64(e, keys[c].first);
+        else { wr64(e, keys[c].first); wr64(e + 8, keys[c].second); }
+        d.index.val[d.index.find(keys[c].first, keys[c].second)] = c;
+    }
+    return true;
+}
+
+static void enc_dict(std::vector<uint8_t> &s, const uint8_t *x, uint32_t n, const Dictionary &d) {
+    std::vector<int32_t> codes(n);
+    for (uint32_t j = 0; j < n; j++) {
+        uint64_t a, b;
+        key_of(x + uint64_t(j) * d.es, d.es, a, b);
+        int64_t h = d.index.find(a, b);
+        if (h < 0) fail(ZF_E_INVALID, "value missing from the dictionary");
+        codes[j] = int32_t(d.index.val[h]);
+    }
+    enc_for<int32_t>(s, codes.data(), n);
+}
+
+// ------------------------------------------------------- RLE / delta + BP
+// Maximal runs (or unit runs for DELTA_BP); groups of 64 runs with their
+// own output offset and value base; deltas of run values FOR-bit-packed.
+template <class T>
+static void enc_rle(std::vector<uint8_t> &s, const T *x, uint32_t n, bool unit_runs) {
+    using U = std::make_unsigned_t<T>;
+    std::vector<T> val;
+    std::vector<uint32_t> len;
+    val.reserve(unit_runs ? n : n / 4 + 16);
+    len.reserve(unit_runs ? 0 : n / 4 + 16);
+    for (uint32_t j = 0; j < n; j++) {
+        if (!unit_runs && !val.empty() && val.back() == x[j]) len.back()++;
+        else {
+            val.push_back(x[j]);
+            if (!unit_runs) len.push_back(1);
+        }
+    }
+    const uint32_t nr = uint32_t(val.size());
+    const uint32_t ng = (nr + kRleGroup - 1) / kRleGroup;
+    // widths and offsets first
+    std::vector<uint32_t> w(ng), doff(ng), out_off(ng);
+    std::vector<T> dmin(ng);
+    uint64_t pos = 16 + 32ull * ng;
+    uint32_t produced = 0;
+    for (uint32_t g = 0; g < ng; g++) {
+        const uint32_t r0 = g * kRleGroup, cnt = std::min(kRleGroup, nr - r0);
+        T mn = 0;
+        U fmax = 0;
+        for (uint32_t j = 1; j < cnt; j++) {
+            T d = T(U(U(val[r0 + j]) - U(val[r0 + j - 1])));
+            if (j == 1 || d < mn) mn = d;
+        }
+        for (uint32_t j = 1; j < cnt; j++) {
+            U f = U(U(U(val[r0 + j]) - U(val[r0 + j - 1])) - U(mn));
+            fmax = std::max(fmax, f);
+        }
+        dmin[g] = mn;
+        w[g] = bit_width64(uint64_t(fmax));
+        doff[g] = uint32_t(pos);
+        out_off[g] = produced;
+        pos += 4 * ((uint64_t(cnt - 1) * w[g] + 31) / 32);
+        if (unit_runs) produced += cnt;
+        else
+            for (uint32_t j = 0; j < cnt; j++) produced += len[r0 + j];
+    }
+    const uint64_t roff = unit_runs ? 0 : align_up(pos, 16);
+    s.assign(unit_runs ? pos : roff + 4ull * nr, 0);
+    uint8_t *p = s.data();
+    wr32(p, nr);
+    wr32(p + 4, ng);
+    wr32(p + 8, uint32_t(roff));
+    for (uint32_t g = 0; g < ng; g++) {
+        const uint32_t r0 = g * kRleGroup, cnt = std::min(kRleGroup, nr - r0);
+        uint8_t *rec = p + 16 + 32ull * g;
+        wr32(rec, out_off[g]);
+        wr32(rec + 4, w[g]);
+        wr32(rec + 8, doff[g]);
+        wr64(rec + 16, uint64_t(int64_t(val[r0])));
+        wr64(rec + 24, uint64_t(int64_t(dmin[g])));
+        BitPacker bp(p + doff[g]);
+        for (uint32_t j = 1; j < cnt; j++)
+            bp.put(uint64_t(U(U(U(val[r0 + j]) - U(val[r0 + j - 1])) - U(dmin[g]))), w[g]);
+        bp.flush();
+    }
+    if (!unit_runs)
+        for (uint32_t j = 0; j < nr; j++) wr32(p + roff + 4ull * j, len[j]);
+}
+
+// ------------------------------------------------------------------ LZ77
+// Greedy LZ77 over a chunk of <= 64 KiB: hash chains of 4-byte prefixes
+// (depth 16), longest match, nearest source on ties.
+//
+// Flat batches: sequences are grouped 64 at a time (one per lane of a
+// wavefront).  Within a batch, every match may read only bytes written before
+// the batch began, or bytes of its own sequence's literals.  Then all literal
+// copies of a batch are independent, and so are all match copies once the
+// literals are in place; the decoder needs no ordering inside the batch.  A
+// candidate that would read another sequence of the same batch is shortened
+// to end before the batch (or dropped).  Streams without this property are
+// still valid and still decode (the GPU falls back to in-order copies).
+struct LzScratch {
+    std::vector<int32_t> head, prev;
+    LzScratch() : head(1u << 16), prev(kLzMaxChunk) {}
+};
+
+static inline uint32_t lz_hash4(const uint8_t *p) {
+    uint32_t v;
+    std::memcpy(&v, p, 4);
+    return (v * 2654435761u) >> 16;
+}
+
+static void enc_lz77(std::vector<uint8_t> &s, const uint8_t *x, uint32_t n, LzScratch &sc) {
+    struct Seq { uint32_t ll, ml, off; };
+    std::vector<Seq> seq;
+    seq.reserve(n / 8 + 4);
+    std::fill(sc.head.begin(), sc.head.end(), -1);
+    int32_t *head = sc.head.data(), *prev = sc.prev.data();
+    auto insert = [&](uint32_t k) {
+        if (k + 4 <= n) {
+            uint32_t h = lz_hash4(x + k);
+            prev[k] = head[h];
+            head[h] = int32_t(k);
+        }
+    };
+    uint32_t i = 0, lit_start = 0, batch_start = 0;
+    while (i < n) {
+        uint32_t best = 0, best_off = 0;
+        if (i + 4 <= n) {
+            int32_t c = head[lz_hash4(x + i)];
+            const uint32_t lim = n - i;
+            for (int d = 0; d < 16 && c >= 0; d++, c = prev[c]) {
+                const uint32_t cu = uint32_t(c);
+                if (best > 0 && (best >= lim || x[cu + best] != x[i + best])) continue;
+                uint32_t l = 0;
+                while (l < lim && x[cu + l] == x[i + l]) l++;
+                const uint32_t off = i - cu;
+                if (cu < lit_start && cu + std::min(l, off) > batch_start)
+                    l = batch_start > cu ? batch_start - cu : 0;
+                if (l > best) {
+                    best = l;
+                    best_off = off;
+                }
+            }
+        }
+        if (best >= 4) {
+            seq.push_back({i - lit_start, best, best_off});
+            for (uint32_t k = i; k < i + best; k++) insert(k);
+            i += best;
+            lit_start = i;
+            if (seq.size() % 64 == 0) batch_start = i;
+        } else {
+            insert(i);
+            i++;
+        }
+    }
+    if (lit_start < n) seq.push_back({n - lit_start, 0, 0});
+
+    uint64_t next = 0, nlit = 0;
+    for (auto &q : seq) {
+        next += (q.ll >= 7) + (q.ml >= 34);
+        nlit += q.ll;
+    }
+    const uint64_t ns = seq.size();
+    s.assign(16 + 3 * ns + 2 * next + nlit, 0);
+    uint8_t *p = s.data();
+    wr32(p, uint32_t(ns));
+    wr32(p + 4, uint32_t(nlit));
+    wr32(p + 8, uint32_t(next));
+    wr32(p + 12, n);
+    uint8_t *offs = p + 16, *ext = offs + 2 * ns, *tags = ext + 2 * next, *lits = tags + ns;
+    uint64_t e = 0, lp = 0, pos = 0;
+    for (uint64_t k = 0; k < ns; k++) {
+        const Seq &q = seq[k];
+        uint32_t lc = q.ll, mc;
+        if (q.ll >= 7) { lc = 7; wr16(ext + 2 * e++, uint16_t(q.ll - 7)); }
+        if (q.ml == 0) mc = 0;
+        else if (q.ml <= 33) mc = q.ml - 3;
+        else { mc = 31; wr16(ext + 2 * e++, uint16_t(q.ml - 34)); }
+        tags[k] = uint8_t(lc | (mc << 3));
+        wr16(offs + 2 * k, uint16_t(q.off));
+        std::memcpy(lits + lp, x + pos, q.ll);
+        lp += q.ll;
+        pos += q.ll + q.ml;
+    }
+}
+
+// --------------------------------------------------------------- driver
+static void parallel_for(uint64_t n, int threads, const std::function<void(uint64_t)> &fn) {
+    if (n == 0) return;
+    const int t = int(std::max<uint64_t>(1, std::min<uint64_t>(uint64_t(threads), n)));
+    std::atomic<uint64_t> next{0};
+    std::vector<Error> errs;
+    std::mutex mu;
+    auto work = [&] {
+        try {
+            for (uint64_t i; (i = next.fetch_add(1)) < n;) fn(i);
+        } catch (const Error &e) {
+            std::lock_guard<std::mutex> g(mu);
+            errs.push_back(e);
+            next = n;
+        }
+    };
+    if (t == 1) work();
+    else {
+        std::vector<std::thread> ts;
+        for (int k = 0; k < t; k++) ts.emplace_back(work);
+        for (auto &th : ts) th.join();
+    }
+    if (!errs.empty()) throw errs[0];
+}
+
+static uint64_t splitmix(uint64_t &s) {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+static void encode_chunk(std::vector<uint8_t> &out, uint32_t codec, uint32_t dtype, const uint8_t *x,
+                         uint32_t n, const Dictionary *dict, LzScratch &sc) {
+    const uint32_t es = elem_size(dtype);
+    switch (codec) {
+    case C_PLAIN: out.assign(x, x + uint64_t(n) * es); return;
+    case C_FOR_BP:
+        if (dtype == D_I32) enc_for<int32_t>(out, reinterpret_cast<const int32_t *>(x), n);
+        else enc_for<int64_t>(out, reinterpret_cast<const int64_t *>(x), n);
+        return;
+    case C_DICT_BP: enc_dict(out, x, n, *dict); return;
+    case C_DELTA_BP:
+    case C_RLE_DELTA_BP:
+        if (dtype == D_I32) enc_rle<int32_t>(out, reinterpret_cast<const int32_t *>(x), n, codec == C_DELTA_BP);
+        else enc_rle<int64_t>(out, reinterpret_cast<const int64_t *>(x), n, codec == C_DELTA_BP);
+        return;
+    case C_LZ77: enc_lz77(out, x, n * es, sc); return;
+    }
+    fail(ZF_E_INVALID, "unknown codec %u", codec);
+}
+
+void compress_host(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t codec,
+                   const zf_encode_opts &o, zf_column_t *col) {
+    const uint8_t *src = static_cast<const uint8_t *>(srcv);
+    const uint32_t es = elem_size(dtype);
+    ZF_REQUIRE(es, ZF_E_INVALID, "unknown dtype %u", dtype);
+    ZF_REQUIRE(src || n_elems == 0, ZF_E_INVALID, "null source");
+    ZF_REQUIRE(codec == 0 || codec_allows(codec, dtype), ZF_E_INVALID, "codec %u cannot encode dtype %u",
+               codec, dtype);
+    const int threads = o.n_threads > 0 ? o.n_threads : int(std::max(1u, std::thread::hardware_concurrency()));
+
+    // chunking
+    std::vector<uint32_t> ce;
+    std::vector<uint8_t> cc;
+    if (o.chunk_elems && o.n_chunk_elems) {
+        uint64_t sum = 0;
+        for (uint32_t i = 0; i < o.n_chunk_elems; i++) {
+            ZF_REQUIRE(o.chunk_elems[i] > 0, ZF_E_INVALID, "empty chunk %u", i);
+            ce.push_back(o.chunk_elems[i]);
+            sum += o.chunk_elems[i];
+            uint32_t c = o.chunk_codecs ? o.chunk_codecs[i] : codec;
+            ZF_REQUIRE(c == 0 || codec_allows(c, dtype), ZF_E_INVALID, "chunk %u: codec %u", i, c);
+            cc.push_back(uint8_t(c));
+        }
+        ZF_REQUIRE(sum == n_elems, ZF_E_INVALID, "chunk sizes sum to %llu, not %llu",
+                   (unsigned long long)sum, (unsigned long long)n_elems);
+    } else {
+        const bool lz = codec == C_LZ77;
+        uint64_t lo = o.chunk_bytes_min ? o.chunk_bytes_min : (lz ? kLzMaxChunk : (1u << 20));
+        uint64_t hi = std::max<uint64_t>(lo, o.chunk_bytes_max ? o.chunk_bytes_max : lo);
+        uint64_t rs = o.seed ^ 0x5A17C0DEull;
+        for (uint64_t at = 0; at < n_elems;) {
+            uint64_t bytes = lo;
+            if (hi > lo) {
+                double u = double(splitmix(rs) >> 11) * (1.0 / 9007199254740992.0);
+                bytes = uint64_t(std::exp(std::log(double(lo)) + u * (std::log(double(hi)) - std::log(double(lo)))));
+            }
+            uint64_t e = lz ? std::min<uint64_t>(bytes, kLzMaxChunk) / es
+                            : std::max<uint64_t>(kForBlock, bytes / es / kForBlock * kForBlock);
+            e = std::max<uint64_t>(1, std::min<uint64_t>(e, n_elems - at));
+            e = std::min<uint64_t>(e, 0xFFFFFFFFull / es);
+            ce.push_back(uint32_t(e));
+            cc.push_back(uint8_t(codec));
+            at += e;
+        }
+    }
+    for (size_t i = 0; i < ce.size(); i++)
+        if (cc[i] == C_LZ77)
+            ZF_REQUIRE(uint64_t(ce[i]) * es <= kLzMaxChunk, ZF_E_INVALID,
+                       "LZ77 chunk %zu holds %llu bytes (limit 65536)", i,
+                       (unsigned long long)(uint64_t(ce[i]) * es));
+
+    // dictionary, when any chunk may use it
+    bool want_dict = false, any_auto = false;
+    for (auto c : cc) {
+        want_dict |= c == C_DICT_BP;
+        any_auto |= c == 0;
+    }
+    Dictionary dict;
+    bool have_dict = false;
+    if (want_dict || (any_auto && dtype != D_BYTES)) {
+        const uint64_t limit = want_dict ? (1ull << 31) : (1ull << 16);
+        have_dict = build_dictionary(dict, src, n_elems, dtype, limit, threads);
+        ZF_REQUIRE(have_dict || !want_dict, ZF_E_UNSUPPORTED, "too many distinct values for DICT_BP");
+    }
+
+    // encode
+    std::vector<uint64_t> first(ce.size() + 1, 0);
+    for (size_t i = 0; i < ce.size(); i++) first[i + 1] = first[i] + ce[i];
+    std::vector<EncodedChunk> chunks(ce.size());
+    parallel_for(ce.size(), threads, [&](uint64_t i) {
+        static thread_local LzScratch sc_tl;
+        LzScratch *sc = &sc_tl;
+        const uint8_t *x = src + first[i] * es;
+        EncodedChunk &out = chunks[i];
+        out.n_elems = ce[i];
+        if (cc[i] != 0) {
+            out.codec = cc[i];
+            encode_chunk(out.bytes, cc[i], dtype, x, ce[i], &dict, *sc);
+        } else {
+            // smallest stream among the applicable codecs
+            const uint32_t cands[] = {C_FOR_BP, C_DICT_BP, C_DELTA_BP, C_RLE_DELTA_BP, C_LZ77};
+            encode_chunk(out.bytes, C_PLAIN, dtype, x, ce[i], nullptr, *sc);
+            out.codec = C_PLAIN;
+            std::vector<uint8_t> tmp;
+            for (uint32_t c : cands) {
+                if (!codec_allows(c, dtype)) continue;
+                if (c == C_DICT_BP && !have_dict) continue;
+                if (c == C_LZ77 && uint64_t(ce[i]) * es > kLzMaxChunk) continue;
+                encode_chunk(tmp, c, dtype, x, ce[i], &dict, *sc);
+                if (tmp.size() < out.bytes.size()) {
+                    out.bytes.swap(tmp);
+                    out.codec = uint8_t(c);
+                }
+            }
+        }
+        ZF_REQUIRE(out.bytes.size() <= 0xFFFFFFFFull, ZF_E_UNSUPPORTED, "chunk stream above 4 GiB");
+    });
+    bool uses_dict = false;
+    for (auto &c : chunks) uses_dict |= c.codec == C_DICT_BP;
+    assemble_column(col->buf, o.pinned != 0, dtype, n_elems, chunks,
+                    uses_dict ? dict.bytes.data() : nullptr, uses_dict ? dict.count : 0);
+    col->view = parse_column(col->buf.p, col->buf.n);
+}
+
+}  // namespace zf

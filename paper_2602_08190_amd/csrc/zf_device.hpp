@@ -1,0 +1,73 @@
+// Device-side work tables: written by the host planner, read by the kernels.
+// Plain structs only; the same definitions compile on both sides.
+#pragma once
+#include <stdint.h>
+
+namespace zf {
+
+constexpr uint32_t kForBlock = 2048;   // values per FOR / bit-packing block
+constexpr uint32_t kRleGroup = 64;     // runs per RLE group record (one wave)
+constexpr uint32_t kLzMaxChunk = 65536;
+constexpr uint32_t kMaxCols = 256;     // columns per plan (output table size)
+
+// Codec / dtype codes, as in zf.h.
+enum : uint8_t { C_PLAIN = 1, C_FOR_BP = 2, C_DICT_BP = 3, C_DELTA_BP = 4, C_RLE_DELTA_BP = 5, C_LZ77 = 6 };
+enum : uint8_t { D_I32 = 1, D_I64 = 2, D_BYTES = 3, D_FIXED16 = 4 };
+
+// Kernel kinds: one device routine per (codec class, value width).  The
+// order is the order of the persistent queue: slow units first, so that the
+// long serial LZ77 chunks start early and the short streaming units fill in.
+enum Kind : uint32_t {
+    K_LZ = 0,
+    K_RLE64,   // RLE_DELTA_BP and DELTA_BP, int64
+    K_RLE32,   // RLE_DELTA_BP and DELTA_BP, int32
+    K_DICT128,
+    K_DICT64,
+    K_DICT32,
+    K_FOR64,
+    K_FOR32,
+    K_PLAIN,
+    K_COUNT
+};
+
+// One chunk of one column, as seen from the device.
+struct ChunkDesc {
+    uint64_t comp_off;    // stream offset from the launch's comp base
+    uint64_t out_off;     // byte offset of the chunk in its column's output
+    uint64_t dict_off;    // dictionary offset from the launch's dict base
+    uint32_t comp_len;    // stream bytes
+    uint32_t n_elems;     // values in the chunk
+    uint32_t dict_count;  // dictionary entries (DICT_BP)
+    uint16_t col;         // column index (output table slot)
+    uint8_t codec;
+    uint8_t dtype;
+};
+static_assert(sizeof(ChunkDesc) == 40, "ChunkDesc layout");
+
+// One unit of work for one wavefront.
+//   FOR / DICT: a = first block, b = number of blocks
+//   RLE / DELTA: a = first group, b = first element, c = end element
+//   LZ77: the whole chunk
+//   PLAIN: a = first byte, b = end byte
+struct Tile {
+    uint32_t chunk;
+    uint32_t a, b, c;
+};
+static_assert(sizeof(Tile) == 16, "Tile layout");
+
+// Device error word bits.
+enum : uint32_t { ERR_CORRUPT = 1u, ERR_BOUNDS = 2u };
+
+// Arguments of one decode launch (a batch or the whole image).
+struct LaunchArgs {
+    const uint8_t *comp;          // base of the compressed streams
+    const uint8_t *dict;          // base of the dictionaries
+    uint8_t *const *out_tab;      // device table: column -> output pointer
+    const ChunkDesc *chunks;
+    const Tile *tiles;            // tiles grouped by kind
+    uint32_t *err;                // device error word
+    uint32_t *counter;            // persistent-kernel queue head (zeroed per launch)
+    uint32_t kind_begin[K_COUNT + 1];
+};
+
+}  // namespace zf

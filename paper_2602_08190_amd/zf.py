@@ -1,0 +1,314 @@
+"""Python binding of libzf (``include/zf.h``): argument marshalling only.
+
+Every step of the hot path runs in the native library and its HIP kernels;
+PyTorch tensors are used only as device buffers (their data pointers) and
+streams (their HIP stream handles).  If ``libzf.so`` cannot be loaded the
+binding raises instead of falling back to anything else.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libzf.so")
+
+# dtypes and codecs (zf.h)
+I32, I64, BYTES, FIXED16 = 1, 2, 3, 4
+AUTO, PLAIN, FOR_BP, DICT_BP, DELTA_BP, RLE_DELTA_BP, LZ77 = 0, 1, 2, 3, 4, 5, 6
+CODEC_NAMES = {PLAIN: "PLAIN", FOR_BP: "FOR_BP", DICT_BP: "DICT_BP", DELTA_BP: "DELTA_BP",
+               RLE_DELTA_BP: "RLE_DELTA_BP", LZ77: "LZ77"}
+ELEM_SIZE = {I32: 4, I64: 8, BYTES: 1, FIXED16: 16}
+OK, E_INVALID, E_UNSUPPORTED, E_CORRUPT, E_NOMEM, E_HIP, E_TOO_SMALL, E_STATE = range(8)
+
+
+class ZfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"zf status {status}: {msg}")
+        self.status = status
+
+
+class EncodeOpts(ctypes.Structure):
+    _fields_ = [("chunk_bytes_min", ctypes.c_uint32), ("chunk_bytes_max", ctypes.c_uint32),
+                ("seed", ctypes.c_uint64), ("n_threads", ctypes.c_int32),
+                ("pinned", ctypes.c_int32), ("chunk_elems", ctypes.c_void_p),
+                ("n_chunk_elems", ctypes.c_uint32), ("chunk_codecs", ctypes.c_void_p)]
+
+
+class Tiles(ctypes.Structure):
+    _fields_ = [("fp_blocks", ctypes.c_uint32), ("gp_elems", ctypes.c_uint32),
+                ("waves_per_block", ctypes.c_uint32), ("waves_per_cu", ctypes.c_uint32)]
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("slot_bytes", ctypes.c_uint64), ("n_slots", ctypes.c_int32),
+                ("use_graphs", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("pcie_gbps", ctypes.c_double), ("tiles", Tiles)]
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("h2d_ms", ctypes.c_double), ("decode_ms", ctypes.c_double),
+                ("wall_ms", ctypes.c_double), ("plain_bytes", ctypes.c_uint64),
+                ("comp_bytes", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# every symbol zf.h declares, with (restype, argtypes)
+_vp, _u32, _u64, _i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
+SIGNATURES = {
+    "zf_encode_opts_default": (None, [ctypes.POINTER(EncodeOpts)]),
+    "zf_compress_host": (_i32, [_vp, _u64, _i32, _i32, ctypes.POINTER(EncodeOpts),
+                                ctypes.POINTER(_vp)]),
+    "zf_column_from_bytes": (_i32, [_vp, _u64, _i32, ctypes.POINTER(_vp)]),
+    "zf_column_bytes": (_vp, [_vp, ctypes.POINTER(_u64)]),
+    "zf_column_plain_bytes": (_u64, [_vp]),
+    "zf_column_n_elems": (_u64, [_vp]),
+    "zf_column_n_chunks": (_u32, [_vp]),
+    "zf_column_dtype": (_i32, [_vp]),
+    "zf_column_free": (None, [_vp]),
+    "zf_plan_opts_default": (None, [ctypes.POINTER(PlanOpts)]),
+    "zf_plan": (_i32, [ctypes.POINTER(_vp), _u32, _i32, ctypes.POINTER(PlanOpts),
+                       ctypes.POINTER(_vp)]),
+    "zf_plan_free": (None, [_vp]),
+    "zf_plan_image_bytes": (_u64, [_vp]),
+    "zf_plan_image_offset": (_u64, [_vp, _u32]),
+    "zf_decompress_async": (_i32, [_vp, _vp, _u64, ctypes.POINTER(_vp), _vp]),
+    "zf_transfer_and_decompress": (_i32, [_vp, ctypes.POINTER(_vp), _vp,
+                                          ctypes.POINTER(Timing)]),
+    "zf_sync": (_i32, [_vp, _vp]),
+    "zf_plan_clear_error": (None, [_vp]),
+    "zf_status_str": (ctypes.c_char_p, [_i32]),
+    "zf_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libzf.so (building it first only when no build exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != OK:
+        msg = lib().zf_last_error().decode(errors="replace")
+        raise ZfError(rc, msg)
+
+
+def dtype_of(x):
+    if x.dtype == np.int32:
+        return I32
+    if x.dtype == np.int64:
+        return I64
+    if x.dtype == np.uint8 and x.ndim == 1:
+        return BYTES
+    if x.dtype == np.uint8 and x.ndim == 2 and x.shape[1] == 16:
+        return FIXED16
+    raise TypeError(f"unsupported column {x.dtype} {x.shape}")
+
+
+class Column:
+    """A compressed column in host memory (pinned unless asked otherwise)."""
+
+    def __init__(self, handle):
+        self._h = ctypes.c_void_p(handle)
+
+    @classmethod
+    def compress(cls, x, codec, chunk_elems=None, chunk_codecs=None, chunk_bytes=None, seed=0,
+                 threads=0, pinned=True):
+        x = np.ascontiguousarray(x)
+        o = EncodeOpts()
+        lib().zf_encode_opts_default(ctypes.byref(o))
+        o.pinned = 1 if pinned else 0
+        o.n_threads = threads
+        o.seed = seed
+        keep = []
+        if chunk_bytes is not None:
+            o.chunk_bytes_min, o.chunk_bytes_max = chunk_bytes
+        if chunk_elems is not None:
+            ce = np.ascontiguousarray(chunk_elems, dtype=np.uint32)
+            keep.append(ce)
+            o.chunk_elems = ce.ctypes.data
+            o.n_chunk_elems = ce.size
+            if chunk_codecs is not None:
+                cc = np.ascontiguousarray(chunk_codecs, dtype=np.uint32)
+                keep.append(cc)
+                o.chunk_codecs = cc.ctypes.data
+        h = ctypes.c_void_p()
+        _check(lib().zf_compress_host(x.ctypes.data, x.shape[0], dtype_of(x), codec,
+                                      ctypes.byref(o), ctypes.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def from_bytes(cls, buf, pinned=True):
+        a = np.ascontiguousarray(np.frombuffer(bytes(buf), np.uint8) if not isinstance(buf, np.ndarray) else buf)
+        h = ctypes.c_void_p()
+        _check(lib().zf_column_from_bytes(a.ctypes.data, a.size, 1 if pinned else 0, ctypes.byref(h)))
+        return cls(h.value)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def bytes(self):
+        n = ctypes.c_uint64()
+        p = lib().zf_column_bytes(self._h, ctypes.byref(n))
+        return np.ctypeslib.as_array((ctypes.c_uint8 * n.value).from_address(p)).copy() if n.value else np.zeros(0, np.uint8)
+
+    def host_pointer(self):
+        n = ctypes.c_uint64()
+        p = lib().zf_column_bytes(self._h, ctypes.byref(n))
+        return p, n.value
+
+    @property
+    def plain_bytes(self):
+        return lib().zf_column_plain_bytes(self._h)
+
+    @property
+    def n_elems(self):
+        return lib().zf_column_n_elems(self._h)
+
+    @property
+    def n_chunks(self):
+        return lib().zf_column_n_chunks(self._h)
+
+    @property
+    def dtype(self):
+        return lib().zf_column_dtype(self._h)
+
+    def free(self):
+        if self._h and self._h.value:
+            lib().zf_column_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _ptr(x):
+    """Device pointer of a torch tensor, or an int."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(s):
+    if s is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+class Plan:
+    """Work tables, batches and device workspace for decoding `cols`."""
+
+    def __init__(self, cols, device=0, slot_bytes=256 << 20, n_slots=2, use_graphs=True,
+                 persistent=True, order=0, pcie_gbps=0.0, tiles=None):
+        self.cols = list(cols)
+        o = PlanOpts()
+        lib().zf_plan_opts_default(ctypes.byref(o))
+        o.slot_bytes = slot_bytes
+        o.n_slots = n_slots
+        o.use_graphs = 1 if use_graphs else 0
+        o.persistent = 1 if persistent else 0
+        o.order = order
+        o.pcie_gbps = pcie_gbps
+        if tiles:
+            for k, v in tiles.items():
+                setattr(o.tiles, k, v)
+        arr = (ctypes.c_void_p * len(self.cols))(*[c.handle.value for c in self.cols])
+        h = ctypes.c_void_p()
+        _check(lib().zf_plan(arr, len(self.cols), device, ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._timing = Timing()
+
+    @property
+    def image_bytes(self):
+        return lib().zf_plan_image_bytes(self._h)
+
+    def image_offset(self, c):
+        return lib().zf_plan_image_offset(self._h, c)
+
+    def _outs(self, outs):
+        return (ctypes.c_void_p * len(outs))(*[_ptr(t) for t in outs])
+
+    def decompress_async(self, d_comp, comp_bytes, outs, stream=None):
+        _check(lib().zf_decompress_async(self._h, _ptr(d_comp), comp_bytes, self._outs(outs),
+                                         _stream(stream)))
+
+    def transfer_and_decompress(self, outs, stream=None, timing=True):
+        t = ctypes.byref(self._timing) if timing else None
+        _check(lib().zf_transfer_and_decompress(self._h, self._outs(outs), _stream(stream), t))
+
+    def sync(self, stream=None):
+        _check(lib().zf_sync(self._h, _stream(stream)))
+        return self._timing.as_dict()
+
+    def clear_error(self):
+        lib().zf_plan_clear_error(self._h)
+
+    def free(self):
+        if self._h and self._h.value:
+            lib().zf_plan_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------- torch helpers
+def torch_dtype_shape(col):
+    """(torch dtype, shape) of a decoded column."""
+    import torch
+    n = col.n_elems
+    dt = col.dtype
+    if dt == I32:
+        return torch.int32, (n,)
+    if dt == I64:
+        return torch.int64, (n,)
+    if dt == FIXED16:
+        return torch.uint8, (n, 16)
+    return torch.uint8, (n,)
+
+
+def empty_outputs(cols, device="cuda"):
+    import torch
+    outs = []
+    for c in cols:
+        dt, shape = torch_dtype_shape(c)
+        outs.append(torch.empty(shape, dtype=dt, device=device))
+    return outs
+
+
+def upload_image(plan, cols, device="cuda"):
+    """Copy the columns' bytes into a device image laid out for `plan`."""
+    import torch
+    img = torch.empty(max(1, plan.image_bytes), dtype=torch.uint8, device=device)
+    for i, c in enumerate(cols):
+        b = torch.from_numpy(c.bytes())
+        off = plan.image_offset(i)
+        img[off:off + b.numel()].copy_(b)
+    return img
