@@ -1,0 +1,275 @@
+"""Benchmark of the zf hot path on one MI355X.
+
+Default workload: the batched 16-column fact table (45.45M rows, ~8.0 GiB
+plain): six int32 key columns (FOR_BP), three int64 cents columns (FOR_BP),
+three date-like columns with runs (RLE_DELTA_BP), three CHAR(16) flag columns
+(DICT_BP) and one comment-text column (LZ77), in uneven chunks of
+16 KiB - 4 MiB.  Synthetic, seeded data.
+
+One step decodes the whole table from its compressed image already in HBM
+(zf_decompress_async: one persistent kernel over every chunk).  `value` is the
+plain bytes produced per second.  Reported beside it: the PCIe end-to-end rate
+of zf_transfer_and_decompress from pinned host memory, the raw uncompressed
+PCIe copy rate, the kernel's HBM roofline, and the oracle decoding a sample on
+the host CPU.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload fact|for|rle|lz|copy]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "end-to-end effective GB/s (H2D+decode) vs raw PCIe copy; decode HBM GB/s"
+HBM_PEAK_GBPS = 8000.0
+PCIE_PEAK_GBPS = 63.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2602_08190_amd", "csrc", "kernels.hip")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+# ------------------------------------------------------------- workloads
+def fact_table(rows):
+    from paper_2602_08190_amd import datagen as g
+    from paper_2602_08190_amd import zf
+    codec_of = {"u32": zf.FOR_BP, "cents": zf.FOR_BP, "date": zf.RLE_DELTA_BP,
+                "char16": zf.DICT_BP, "text": zf.LZ77}
+    cols, xs, names = [], [], []
+    for i, (name, kind, _) in enumerate(g.FACT_COLUMNS):
+        t = time.time()
+        x = g.fact_column(i, rows)
+        t1 = time.time()
+        c = zf.Column.compress(x, codec_of[kind], chunk_bytes=(16 << 10, 4 << 20), seed=3000 + i)
+        log(f"column {i:2d} {name:9s} {x.nbytes / 2**20:8.1f} MiB -> {c.host_pointer()[1] / 2**20:8.1f} MiB"
+            f"  ({c.n_chunks} chunks, gen {t1 - t:.1f}s, encode {time.time() - t1:.1f}s)")
+        cols.append(c)
+        xs.append(x)
+        names.append(name)
+    desc = (f"batched 16-column fact table, {rows} rows: 6 int32 keys (FOR_BP), 3 int64 cents "
+            f"(FOR_BP), 3 run-sorted dates (RLE_DELTA_BP), 3 CHAR(16) flags (DICT_BP), 1 Zipf "
+            f"comment text (LZ77); uneven chunks 16 KiB-4 MiB")
+    return cols, xs, names, desc
+
+
+def single(kind, n):
+    from paper_2602_08190_amd import datagen as g
+    from paper_2602_08190_amd import zf
+    if kind == "for":
+        x = g.for_bp_column(n, 0)
+        c = zf.Column.compress(x, zf.FOR_BP, chunk_bytes=(4 << 20, 4 << 20))
+        desc = f"FOR_BP int32, {n} values uniform in [10^6, 10^6+4096), w=12, 4 MiB chunks"
+    elif kind == "rle":
+        x = g.sorted_runs_column(n, 8, 1)
+        c = zf.Column.compress(x, zf.RLE_DELTA_BP, chunk_elems=[16384] * (n // 16384) +
+                               ([n % 16384] if n % 16384 else []))
+        desc = f"RLE_DELTA_BP int32, {n} values, geometric(8) runs, 64 KiB chunks"
+    elif kind == "lz":
+        x = g.text_column(n, 2)
+        c = zf.Column.compress(x, zf.LZ77)
+        desc = f"LZ77 text, {n} bytes, Zipf(1.1) over 10,000 words, 64 KiB chunks"
+    elif kind == "copy":
+        x = np.frombuffer(np.random.default_rng(0).bytes(n), np.uint8)
+        c = zf.Column.compress(x, zf.PLAIN, chunk_bytes=(4 << 20, 4 << 20))
+        desc = f"PLAIN copy probe, {n} bytes"
+    else:
+        raise ValueError(kind)
+    return [c], [x], [kind], desc
+
+
+# ------------------------------------------------------------- CPU oracle
+def cpu_baseline(cols, budget_s=15.0):
+    """The oracle (single-threaded C) decoding runs of consecutive chunks from
+    every column for about budget_s seconds in total."""
+    import oracle.zfo as zo
+    per_col = budget_s / len(cols)
+    total_bytes, total_s, nchunks = 0, 0.0, 0
+    for c in cols:
+        b = c.bytes()
+        cs = zo.chunks(b)
+        first, k, spent = len(cs) // 3, 1, 0.0
+        while spent < per_col:
+            k = min(k, len(cs) - first)
+            t = time.perf_counter()
+            zo.decode_chunks(b, first, k)
+            dt = time.perf_counter() - t
+            spent += dt
+            total_s += dt
+            total_bytes += sum(x["plain_len"] for x in cs[first:first + k])
+            nchunks += k
+            first = (first + k) % len(cs)
+            k *= 2
+    return {"value": round(total_bytes / total_s / 1e9, 4), "unit": "GB/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{nchunks} chunks in runs of consecutive chunks, about {per_col:.1f} s of "
+                      f"decoding per column over all {len(cols)} columns, {total_bytes / 2**20:.0f} "
+                      f"MiB plain decoded from host memory in {total_s:.1f} s; rate = plain bytes "
+                      f"/ time"}
+
+
+def read_traffic(workload):
+    """HBM traffic per launch from committed rocprofv3 counter summaries, if
+    they were taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
+    if not os.path.exists(p):
+        return None
+    kv = {}
+    for line in open(p):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_sha") != kernel_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+# ------------------------------------------------------------------ main
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="fact", choices=["fact", "for", "rle", "lz", "copy"])
+    ap.add_argument("--rows", type=int, default=None)
+    ap.add_argument("--no-e2e", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--persistent", type=int, default=1)
+    ap.add_argument("--e2e-reps", type=int, default=3)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the decode path needs no exchange between GPUs, and "
+              "multi-GPU runs are not part of this build (each GPU would decode its own chunks "
+              "over its own PCIe link).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2602_08190_amd import datagen as g
+    from paper_2602_08190_amd import zf
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    zf.lib()
+    t0 = time.time()
+    if args.workload == "fact":
+        cols, xs, names, desc = fact_table(args.rows or g.FACT_ROWS)
+    else:
+        n = args.rows or {"for": 1 << 28, "rle": 1 << 26, "lz": 1 << 30, "copy": 1 << 30}[args.workload]
+        cols, xs, names, desc = single(args.workload, n)
+    plain = sum(c.plain_bytes for c in cols)
+    comp = sum(c.host_pointer()[1] for c in cols)
+    log(f"data ready in {time.time() - t0:.1f}s: plain {plain / 2**30:.2f} GiB, compressed "
+        f"{comp / 2**30:.2f} GiB (ratio {plain / comp:.2f}x)")
+
+    plan = zf.Plan(cols, device=0, persistent=bool(args.persistent))
+    img = zf.upload_image(plan, cols)
+    outs = zf.empty_outputs(cols)
+    stream = torch.cuda.current_stream()
+
+    # one decode, checked against the input on a sample of rows
+    plan.decompress_async(img, img.numel(), outs)
+    plan.sync()
+    r = np.random.default_rng(0)
+    for x, o in zip(xs, outs):
+        idx = r.integers(0, len(x), size=4096)
+        got = o[torch.from_numpy(idx).to(o.device)].cpu().numpy()
+        assert np.array_equal(got, x[idx]), "decode mismatch"
+    log("sampled check against the input: ok")
+
+    # timed steps: decode of the whole table from HBM
+    for _ in range(args.warmup):
+        plan.decompress_async(img, img.numel(), outs)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        plan.decompress_async(img, img.numel(), outs)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    plan.sync()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    value = plain / (ms * 1e-3) / 1e9
+    alg_bytes = comp + plain  # every compressed byte read once, every plain byte written once
+    hbm_gbps = alg_bytes / (ms * 1e-3) / 1e9
+    log(f"decode from HBM: {ms:.3f} ms/step, {value:.1f} GB/s plain, {hbm_gbps:.1f} GB/s HBM")
+
+    result = {
+        "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": desc, "plain_bytes": plain, "comp_bytes": comp,
+                   "ratio": round(plain / comp, 3),
+                   "chunks": sum(c.n_chunks for c in cols),
+                   "launch": "persistent" if args.persistent else "per-kind"},
+        "decode_hbm_GBps": round(hbm_gbps, 1),
+        "roofline": {"bound": "hbm", "achieved": round(hbm_gbps, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(hbm_gbps / HBM_PEAK_GBPS, 4),
+                     "traffic": None, "kernel": "k_decode_persistent" if args.persistent else "k_decode_kind",
+                     "algorithmic_bytes_per_launch": alg_bytes},
+    }
+    traffic = read_traffic(args.workload)
+    if traffic is not None:
+        result["roofline"]["traffic"] = traffic
+
+    if not args.no_e2e:
+        # PCIe end to end: pinned host -> staging slots -> decode, pipelined
+        walls = []
+        for rep in range(args.e2e_reps):
+            plan.transfer_and_decompress(outs, timing=True)
+            t = plan.sync()
+            walls.append(t)
+        walls.sort(key=lambda t: t["wall_ms"])
+        tm = walls[len(walls) // 2]
+        eff = plain / (tm["wall_ms"] * 1e-3) / 1e9
+        # raw copy of the plain bytes from pinned memory, 256 MiB pieces
+        hosts = [torch.from_numpy(np.ascontiguousarray(x).view(np.uint8).reshape(-1)).pin_memory()
+                 for x in xs]
+        flat = [o.view(torch.uint8).reshape(-1) for o in outs]
+        raws = []
+        for rep in range(args.e2e_reps):
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for h, d in zip(hosts, flat):
+                for s in range(0, h.numel(), 256 << 20):
+                    d[s:s + (256 << 20)].copy_(h[s:s + (256 << 20)], non_blocking=True)
+            b.record(stream)
+            torch.cuda.synchronize()
+            raws.append(a.elapsed_time(b))
+        raw_ms = sorted(raws)[len(raws) // 2]
+        raw = plain / (raw_ms * 1e-3) / 1e9
+        del hosts
+        result["e2e"] = {
+            "effective_GBps": round(eff, 2), "raw_copy_GBps": round(raw, 2),
+            "vs_raw_copy": round(eff / raw, 3), "wall_ms": round(tm["wall_ms"], 2),
+            "h2d_ms": round(tm["h2d_ms"], 2), "decode_ms": round(tm["decode_ms"], 2),
+            "pcie_GBps_compressed": round(comp / (tm["h2d_ms"] * 1e-3) / 1e9, 2),
+            "pcie_frac_of_63": round(comp / (tm["h2d_ms"] * 1e-3) / 1e9 / PCIE_PEAK_GBPS, 3)}
+        log(f"end to end: {eff:.1f} GB/s effective vs raw copy {raw:.1f} GB/s "
+            f"(x{eff / raw:.2f}); wall {tm['wall_ms']:.1f} ms, h2d {tm['h2d_ms']:.1f} ms, "
+            f"decode {tm['decode_ms']:.1f} ms")
+
+    if not args.no_cpu:
+        log("CPU oracle baseline ...")
+        result["cpu_baseline"] = cpu_baseline(cols)
+        log(f"oracle: {result['cpu_baseline']['value']} GB/s")
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()
