@@ -149,7 +149,7 @@ def main():
     ap.add_argument("--rows", type=int, default=None)
     ap.add_argument("--no-e2e", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--persistent", type=int, default=1)
+    ap.add_argument("--persistent", type=int, default=0)
     ap.add_argument("--e2e-reps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:

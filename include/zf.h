@@ -144,8 +144,8 @@ typedef struct {
     uint64_t slot_bytes;     /* staging slot size for transfers (default 256 MiB) */
     int32_t n_slots;         /* staging slots, >= 1 (default 2: double buffering)   */
     int32_t use_graphs;      /* 1: one hipGraph per batch (default); 0: plain launches */
-    int32_t persistent;      /* 1: one persistent multi-codec kernel per batch (default);
-                                0: one launch per pattern class                      */
+    int32_t persistent;      /* 1: one persistent multi-codec kernel per batch;
+                                0: one launch per kernel kind (default)             */
     int32_t order;           /* 0: Johnson order (default); 1: column order          */
     double pcie_gbps;        /* transfer-time estimate for ordering (0: 55)          */
     zf_tiles tiles;          /* explicit tile shapes; zero fields use the defaults */

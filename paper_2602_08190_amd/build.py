@@ -19,7 +19,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 HOST_SRC = ["abi.cpp", "format.cpp", "encode.cpp", "plan.cpp", "run.cpp"]
-HIP_SRC = ["kernels.hip"]
+HIP_SRC = ["k_persistent.hip", "k_for32.hip", "k_dict32.hip", "k_for64.hip", "k_dict64.hip",
+           "k_fp128.hip", "k_gp.hip", "k_np.hip"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-I", INCLUDE, "-I", CSRC, "-I", "/opt/rocm/include", "-Wall",
           "-Wno-unused-function", "-Wno-unused-parameter"]
@@ -44,7 +45,8 @@ def build_gen():
     return GENLIB
 
 
-def build_zf(jobs=8):
+def build_zf(jobs=None):
+    jobs = jobs or max(1, min(16, os.cpu_count() or 1))
     os.makedirs(OBJ, exist_ok=True)
     cmds = []
     objs = []

@@ -34,7 +34,7 @@ void zf_plan_opts_default(zf_plan_opts *o) {
     o->slot_bytes = 256ull << 20;
     o->n_slots = 2;
     o->use_graphs = 1;
-    o->persistent = 1;
+    o->persistent = 0;
     o->order = 0;
     o->pcie_gbps = 0;
 }

@@ -1,0 +1,66 @@
+// The persistent multi-codec kernel, the small helper kernels and the host
+// entry that enqueues a launch's decode.
+#include "kernels.hpp"
+
+namespace zf {
+
+// Persistent: every wave pulls units from one queue until it is empty.
+// Units are ordered by kind, the costliest kinds first.
+__global__ __launch_bounds__(256) void k_decode_persistent(LaunchArgs A) {
+    __shared__ LzSeq tab[4];
+    LzSeq *mine = &tab[threadIdx.x / 64];
+    const uint32_t n = A.kind_begin[K_COUNT];
+    for (;;) {
+        uint32_t u = 0;
+        if (lane_id() == 0) u = atomicAdd(A.counter, 1u);
+        u = first32(u);
+        if (u >= n) return;
+        uint32_t kind = 0;
+        while (kind + 1 < K_COUNT && u >= A.kind_begin[kind + 1]) kind++;
+        run_unit<0>(A, kind, u, mine);
+    }
+}
+
+__global__ void k_zero_counter(uint32_t *c) { *c = 0; }
+
+struct OutTable {
+    uint8_t *p[kMaxCols];
+};
+__global__ void k_set_out_tab(uint8_t **tab, OutTable t, uint32_t n) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) tab[i] = t.p[i];
+}
+
+// ============================================================ host side
+hipError_t launch_set_out_tab(uint8_t **d_tab, uint8_t *const *ptrs, uint32_t n, hipStream_t st) {
+    OutTable t{};
+    for (uint32_t i = 0; i < n && i < kMaxCols; i++) t.p[i] = ptrs[i];
+    hipLaunchKernelGGL(k_set_out_tab, dim3(1), dim3(kMaxCols), 0, st, d_tab, t, n);
+    return hipGetLastError();
+}
+
+// Enqueue the decode of one launch's units.  persistent_waves > 0 selects
+// the persistent kernel with that many waves in flight.
+hipError_t launch_decode(const LaunchArgs &A, uint32_t persistent_waves, uint32_t waves_per_block,
+                         hipStream_t st) {
+    if (A.kind_begin[K_COUNT] == 0) return hipSuccess;
+    if (persistent_waves) {
+        hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, st, A.counter);
+        const uint32_t blocks = (persistent_waves + 3) / 4;
+        hipLaunchKernelGGL(k_decode_persistent, dim3(blocks), dim3(256), 0, st, A);
+        return hipGetLastError();
+    }
+    const uint32_t wpb = waves_per_block ? waves_per_block : 4;
+    launch_lz(A, wpb, st);
+    launch_rle32(A, wpb, st);
+    launch_rle64(A, wpb, st);
+    launch_dict128(A, wpb, st);
+    launch_dict64(A, wpb, st);
+    launch_dict32(A, wpb, st);
+    launch_for64(A, wpb, st);
+    launch_for32(A, wpb, st);
+    launch_plain(A, wpb, st);
+    return hipGetLastError();
+}
+
+}  // namespace zf

@@ -1,0 +1,821 @@
+// Decode routines for gfx950 (wave64), shared by the kernel translation units.  Every unit of work is owned by one
+// wavefront; waves never wait for each other, so a workgroup is just a
+// bundle of independent waves and there is no barrier anywhere.
+//
+//  Fully-Parallel (Sec. 3.1, Sec. 4 "Scheduling Fully-Parallel"):
+//    FOR+BP and Dict+BP.  A lane owns 16 contiguous output bytes per step
+//    (4 x int32, 2 x int64 or 1 x CHAR(16)): the paper's C, sized for one
+//    16-byte store.  The packed words a lane needs (at most 5) are read
+//    straight from HBM; neighbouring lanes share words, which the L1 absorbs,
+//    so HBM sees each payload byte once.  Dictionary lookup is fused into the
+//    unpack (Sec. 3.2, Eq. 2): no intermediate code array.
+//  Group-Parallel (Sec. 4 "Scheduling Group-Parallel for load balance"):
+//    RLE + delta + BP.  A wave takes one group of 64 runs: lane l loads run
+//    l, an exclusive wave scan of the counts gives each run's output offset
+//    (the paper's presum, fused), an inclusive wave scan of the unpacked
+//    deltas gives the run values.  Output is written in 64-wide windows; the
+//    runs that start inside a window are walked with uniform readlanes, so the
+//    work per window is proportional to its run count and long runs cost no
+//    more than short ones.  Units are balanced by output count on the host.
+//  Non-Parallel (Sec. 4 "Scheduling Non-Parallel towards SIMT"): LZ77, one
+//    chunk per wavefront.  Lane i holds sequence i of a batch of 64; wave
+//    scans give every sequence's output and literal positions at once.  When
+//    the batch is flat (no match reads another sequence of the same batch)
+//    all literals, then all matches, are copied in lockstep; otherwise the
+//    batch is replayed in order, one sequence at a time.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "zf_device.hpp"
+
+namespace zf {
+
+#define ZF_DEV __device__ __forceinline__
+
+// ------------------------------------------------------------ wave helpers
+ZF_DEV uint32_t lane_id() { return __lane_id(); }
+
+ZF_DEV uint32_t rl32(uint32_t v, uint32_t lane) {
+    return uint32_t(__builtin_amdgcn_readlane(int(v), int(lane)));
+}
+ZF_DEV uint64_t rl64(uint64_t v, uint32_t lane) {
+    return uint64_t(rl32(uint32_t(v), lane)) | (uint64_t(rl32(uint32_t(v >> 32), lane)) << 32);
+}
+template <class T>
+ZF_DEV T rlT(T v, uint32_t lane) {
+    if constexpr (sizeof(T) == 8) return T(rl64(uint64_t(v), lane));
+    else return T(rl32(uint32_t(v), lane));
+}
+ZF_DEV uint32_t first32(uint32_t v) { return uint32_t(__builtin_amdgcn_readfirstlane(int(v))); }
+
+// Inclusive prefix sums across the 64 lanes (wrapping), with DPP lane moves:
+// row_shr 1, 2, 4, 8 inside each row of 16 lanes, then row_bcast 15 and 31
+// carry the row totals into the rows above (GCN / CDNA DPP controls).
+template <int CTRL, int ROWS>
+ZF_DEV uint32_t dpp(uint32_t x) {
+    return uint32_t(__builtin_amdgcn_update_dpp(0, int(x), CTRL, ROWS, 0xF, true));
+}
+ZF_DEV uint32_t scan_add32(uint32_t x) {
+    x += dpp<0x111, 0xF>(x);   // row_shr:1
+    x += dpp<0x112, 0xF>(x);   // row_shr:2
+    x += dpp<0x114, 0xF>(x);   // row_shr:4
+    x += dpp<0x118, 0xF>(x);   // row_shr:8
+    x += dpp<0x142, 0xA>(x);   // row_bcast:15 into rows 1 and 3
+    x += dpp<0x143, 0xC>(x);   // row_bcast:31 into rows 2 and 3
+    return x;
+}
+// 64-bit version: the same moves on both halves, with the carry of each add.
+template <int CTRL, int ROWS>
+ZF_DEV void add64_dpp(uint32_t &lo, uint32_t &hi) {
+    const uint32_t ylo = dpp<CTRL, ROWS>(lo), yhi = dpp<CTRL, ROWS>(hi);
+    const uint32_t nlo = lo + ylo;
+    hi = hi + yhi + (nlo < lo ? 1u : 0u);
+    lo = nlo;
+}
+ZF_DEV uint64_t scan_add64(uint64_t x) {
+    uint32_t lo = uint32_t(x), hi = uint32_t(x >> 32);
+    add64_dpp<0x111, 0xF>(lo, hi);
+    add64_dpp<0x112, 0xF>(lo, hi);
+    add64_dpp<0x114, 0xF>(lo, hi);
+    add64_dpp<0x118, 0xF>(lo, hi);
+    add64_dpp<0x142, 0xA>(lo, hi);
+    add64_dpp<0x143, 0xC>(lo, hi);
+    return uint64_t(lo) | (uint64_t(hi) << 32);
+}
+template <class T>
+ZF_DEV T scan_addT(T x) {
+    if constexpr (sizeof(T) == 8) return T(scan_add64(uint64_t(x)));
+    else return T(scan_add32(uint32_t(x)));
+}
+ZF_DEV uint32_t wave_max32(uint32_t x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x = max(x, uint32_t(__shfl_xor(x, d, 64)));
+    return x;
+}
+ZF_DEV bool any(bool p) { return __ballot(p) != 0; }
+
+// Orders this wave's global memory accesses for the compiler.  Lanes of one
+// wavefront share one in-order path to the L1, so a load issued after a
+// store of the same wave observes it; the fence only stops reordering.
+ZF_DEV void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
+
+ZF_DEV void flag(uint32_t *err, uint32_t bits) {
+    if (lane_id() == 0) atomicOr(err, bits);
+}
+
+ZF_DEV uint32_t ld32u(const uint8_t *p) { return *reinterpret_cast<const uint32_t *>(p); }
+ZF_DEV uint64_t ld64u(const uint8_t *p) {
+    return uint64_t(ld32u(p)) | (uint64_t(ld32u(p + 4)) << 32);
+}
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
+#define ZF_GLOBAL __attribute__((address_space(1)))
+// Every buffer the kernels touch is device global memory; saying so lets the
+// compiler use global (not flat) loads and stores.
+template <class T>
+ZF_DEV ZF_GLOBAL T *gp(T *p) {
+    return (ZF_GLOBAL T *)(p);
+}
+template <class T>
+ZF_DEV const ZF_GLOBAL T *gp(const T *p) {
+    return (const ZF_GLOBAL T *)(p);
+}
+// 16-byte store of streaming output (not read again by this kernel).
+ZF_DEV void st16_nt(uint8_t *p, uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+    u32x4 v = {a, b, c, d};
+    __builtin_nontemporal_store(v, gp(reinterpret_cast<u32x4 *>(p)));
+}
+ZF_DEV void st4(uint8_t *p, uint32_t v) { *gp(reinterpret_cast<uint32_t *>(p)) = v; }
+
+ZF_DEV uint32_t mask32(uint32_t w) { return w >= 32 ? 0xFFFFFFFFu : ((1u << w) - 1u); }
+ZF_DEV uint64_t mask64(uint32_t w) { return w >= 64 ? ~0ull : ((1ull << w) - 1ull); }
+
+// A lane's window of five packed words, kept in named registers (an array
+// indexed by a per-lane value would be demoted to LDS or scratch).
+struct Win {
+    uint32_t w0, w1, w2, w3, w4;
+};
+
+// Word d (0..6) of the window; words past the fifth read as zero.
+ZF_DEV uint32_t pick(const Win &v, uint32_t d) {
+    uint32_t r = 0;
+    r = d == 0 ? v.w0 : r;
+    r = d == 1 ? v.w1 : r;
+    r = d == 2 ? v.w2 : r;
+    r = d == 3 ? v.w3 : r;
+    r = d == 4 ? v.w4 : r;
+    return r;
+}
+
+// Load the 5 packed words starting at word k0 (zero past nwords).
+ZF_DEV Win load_window(const uint32_t *words, uint64_t k0, uint64_t nwords) {
+    Win v;
+    if (k0 + 5 <= nwords) {
+        uint4 q;
+        __builtin_memcpy(&q, words + k0, 16);  // dword aligned: one dwordx4 load
+        v.w0 = q.x;
+        v.w1 = q.y;
+        v.w2 = q.z;
+        v.w3 = q.w;
+        v.w4 = words[k0 + 4];
+    } else {
+        v.w0 = k0 < nwords ? words[k0] : 0u;
+        v.w1 = k0 + 1 < nwords ? words[k0 + 1] : 0u;
+        v.w2 = k0 + 2 < nwords ? words[k0 + 2] : 0u;
+        v.w3 = k0 + 3 < nwords ? words[k0 + 3] : 0u;
+        v.w4 = k0 + 4 < nwords ? words[k0 + 4] : 0u;
+    }
+    return v;
+}
+
+// Field at bit `pos` (0 <= pos < 128) of the window, width w <= 32.
+ZF_DEV uint32_t field32(const Win &wv, uint32_t pos, uint32_t w) {
+    const uint32_t d = pos >> 5, s = pos & 31u;
+    const uint64_t pair = uint64_t(pick(wv, d)) | (uint64_t(pick(wv, d + 1)) << 32);
+    return uint32_t(pair >> s) & mask32(w);
+}
+// Field at bit `pos` (0 <= pos < 96) of the window, width w <= 64.
+ZF_DEV uint64_t field64(const Win &wv, uint32_t pos, uint32_t w) {
+    const uint32_t d = pos >> 5, s = pos & 31u;
+    const uint64_t lo = uint64_t(pick(wv, d)) | (uint64_t(pick(wv, d + 1)) << 32);
+    const uint64_t hi = pick(wv, d + 2);
+    const uint64_t v = s ? ((lo >> s) | (hi << (64 - s))) : lo;
+    return v & mask64(w);
+}
+
+// ====================================================== Fully-Parallel
+ZF_DEV uint32_t alignbit(uint32_t hi, uint32_t lo, uint32_t s) {
+    return __builtin_amdgcn_alignbit(hi, lo, s);
+}
+
+// The NW packed words starting at word k0 (NW <= 5, known per width);
+// zero past nwords.
+template <uint32_t NW>
+ZF_DEV Win load_words(const uint32_t *words, uint64_t k0, uint64_t nwords) {
+    Win v{0, 0, 0, 0, 0};
+    const ZF_GLOBAL uint32_t *g = gp(words) + k0;
+    if (k0 + NW <= nwords) {
+        if constexpr (NW >= 4) {
+            u32x4 q;
+            __builtin_memcpy(&q, (const uint32_t *)g, 16);
+            v.w0 = q.x; v.w1 = q.y; v.w2 = q.z; v.w3 = q.w;
+            if constexpr (NW == 5) v.w4 = g[4];
+        } else if constexpr (NW == 3) {
+            u32x3 q;
+            __builtin_memcpy(&q, (const uint32_t *)g, 12);
+            v.w0 = q.x; v.w1 = q.y; v.w2 = q.z;
+        } else if constexpr (NW == 2) {
+            u32x2 q;
+            __builtin_memcpy(&q, (const uint32_t *)g, 8);
+            v.w0 = q.x; v.w1 = q.y;
+        } else if constexpr (NW == 1) {
+            v.w0 = g[0];
+        }
+    } else {
+        if constexpr (NW >= 1) v.w0 = k0 < nwords ? g[0] : 0u;
+        if constexpr (NW >= 2) v.w1 = k0 + 1 < nwords ? g[1] : 0u;
+        if constexpr (NW >= 3) v.w2 = k0 + 2 < nwords ? g[2] : 0u;
+        if constexpr (NW >= 4) v.w3 = k0 + 3 < nwords ? g[3] : 0u;
+        if constexpr (NW >= 5) v.w4 = k0 + 4 < nwords ? g[4] : 0u;
+    }
+    return v;
+}
+
+// Word K (compile time) of the 128-bit value Y = window >> sh.
+template <uint32_t K>
+ZF_DEV uint32_t yword(const Win &v, uint32_t sh) {
+    if constexpr (K == 0) return alignbit(v.w1, v.w0, sh);
+    else if constexpr (K == 1) return alignbit(v.w2, v.w1, sh);
+    else if constexpr (K == 2) return alignbit(v.w3, v.w2, sh);
+    else if constexpr (K == 3) return alignbit(v.w4, v.w3, sh);
+    else return 0u;
+}
+// Field I of width W (W <= 32) of Y: bits [I*W, I*W + W).
+template <uint32_t W, uint32_t I>
+ZF_DEV uint32_t yfield32(const Win &v, uint32_t sh) {
+    if constexpr (W == 0) {
+        return 0u;
+    } else {
+        constexpr uint32_t pos = I * W, k = pos >> 5, s = pos & 31;
+        constexpr uint32_t m = W == 32 ? 0xFFFFFFFFu : ((1u << W) - 1u);
+        if constexpr (s + W <= 32) return (yword<k>(v, sh) >> s) & m;
+        else return alignbit(yword<k + 1>(v, sh), yword<k>(v, sh), s) & m;
+    }
+}
+// Field I of width W (W <= 64) of Y, as 64 bits.
+template <uint32_t W, uint32_t I>
+ZF_DEV uint64_t yfield64(const Win &v, uint32_t sh) {
+    if constexpr (W == 0) {
+        return 0ull;
+    } else {
+        constexpr uint32_t pos = I * W, k = pos >> 5, s = pos & 31;
+        constexpr uint64_t m = W == 64 ? ~0ull : ((1ull << W) - 1ull);
+        const uint32_t lo = s ? alignbit(yword<k + 1>(v, sh), yword<k>(v, sh), s) : yword<k>(v, sh);
+        const uint32_t hi = s ? alignbit(yword<k + 2>(v, sh), yword<k + 1>(v, sh), s) : yword<k + 1>(v, sh);
+        return (uint64_t(lo) | (uint64_t(hi) << 32)) & m;
+    }
+}
+
+// Decode one block of nv values, width W known at compile time.  A lane owns
+// 16 output bytes per step; the packed words of UNR steps are loaded before
+// any is used, so each wave keeps UNR x 1 KiB of output's loads in flight.
+template <int ES, bool DICT, uint32_t UNR, uint32_t W>
+ZF_DEV void fp_block(const uint32_t *words, uint64_t nwords, uint64_t ref, uint32_t nv,
+                     uint8_t *ob, bool vec, const uint8_t *dict, uint32_t dict_count, bool &bad) {
+    constexpr uint32_t VPL = 16 / ES;
+    constexpr uint32_t NW = (31 + VPL * W + 31) / 32;  // words a lane may need
+    const uint32_t lane = lane_id();
+    const uint32_t steps = (nv + 64 * VPL - 1) / (64 * VPL);
+    const ZF_GLOBAL uint8_t *gd = gp(dict);
+    for (uint32_t g = 0; g < steps; g += UNR) {
+        Win wv[UNR];
+#pragma unroll
+        for (uint32_t u = 0; u < UNR; u++) {
+            const uint32_t v0 = ((g + u) * 64 + lane) * VPL;
+            if (v0 < nv) wv[u] = load_words<NW>(words, (uint64_t(v0) * W) >> 5, nwords);
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < UNR; u++) {
+            const uint32_t v0 = ((g + u) * 64 + lane) * VPL;
+            if (v0 >= nv) continue;
+            const uint32_t sh = uint32_t((uint64_t(v0) * W) & 31u);
+            if constexpr (ES == 4) {
+                uint32_t f[4] = {yfield32<W, 0>(wv[u], sh), yfield32<W, 1>(wv[u], sh),
+                                 yfield32<W, 2>(wv[u], sh), yfield32<W, 3>(wv[u], sh)};
+                uint32_t v[4];
+#pragma unroll
+                for (uint32_t i = 0; i < 4; i++) {
+                    if constexpr (DICT) {
+                        const uint32_t code = uint32_t(ref) + f[i];
+                        const bool in = v0 + i < nv, ok = code < dict_count;
+                        bad |= in && !ok;
+                        v[i] = (in && ok) ? *reinterpret_cast<const ZF_GLOBAL uint32_t *>(gd + 4ull * code) : 0u;
+                    } else {
+                        v[i] = uint32_t(ref) + f[i];
+                    }
+                }
+                if (vec && v0 + 4 <= nv) {
+                    st16_nt(ob + 4ull * v0, v[0], v[1], v[2], v[3]);
+                } else {
+#pragma unroll
+                    for (uint32_t i = 0; i < 4; i++)
+                        if (v0 + i < nv) st4(ob + 4ull * (v0 + i), v[i]);
+                }
+            } else if constexpr (ES == 8) {
+                uint64_t v[2];
+                if constexpr (DICT) {
+                    const uint32_t f[2] = {yfield32<W, 0>(wv[u], sh), yfield32<W, 1>(wv[u], sh)};
+#pragma unroll
+                    for (uint32_t i = 0; i < 2; i++) {
+                        const uint32_t code = uint32_t(ref) + f[i];
+                        const bool in = v0 + i < nv, ok = code < dict_count;
+                        bad |= in && !ok;
+                        v[i] = (in && ok) ? *reinterpret_cast<const ZF_GLOBAL uint64_t *>(gd + 8ull * code) : 0ull;
+                    }
+                } else {
+                    v[0] = ref + yfield64<W, 0>(wv[u], sh);
+                    v[1] = ref + yfield64<W, 1>(wv[u], sh);
+                }
+                if (vec && v0 + 2 <= nv) {
+                    st16_nt(ob + 8ull * v0, uint32_t(v[0]), uint32_t(v[0] >> 32), uint32_t(v[1]),
+                            uint32_t(v[1] >> 32));
+                } else {
+#pragma unroll
+                    for (uint32_t i = 0; i < 2; i++)
+                        if (v0 + i < nv) {
+                            st4(ob + 8ull * (v0 + i), uint32_t(v[i]));
+                            st4(ob + 8ull * (v0 + i) + 4, uint32_t(v[i] >> 32));
+                        }
+                }
+            } else {  // ES == 16: dictionary of CHAR(16)
+                const uint32_t code = uint32_t(ref) + yfield32<W, 0>(wv[u], sh);
+                const bool ok = code < dict_count;
+                bad |= !ok;
+                u32x4 e = {0, 0, 0, 0};
+                if (ok) e = *reinterpret_cast<const ZF_GLOBAL u32x4 *>(gd + 16ull * code);
+                if (vec) {
+                    st16_nt(ob + 16ull * v0, e.x, e.y, e.z, e.w);
+                } else {
+                    st4(ob + 16ull * v0, e.x);
+                    st4(ob + 16ull * v0 + 4, e.y);
+                    st4(ob + 16ull * v0 + 8, e.z);
+                    st4(ob + 16ull * v0 + 12, e.w);
+                }
+            }
+        }
+    }
+}
+
+
+// ---- runtime-width variant (persistent kernel): the same steps with the
+// field positions computed at run time (uniform across the wave).
+ZF_DEV uint32_t ysel(uint32_t y0, uint32_t y1, uint32_t y2, uint32_t y3, uint32_t k) {
+    return k == 0 ? y0 : k == 1 ? y1 : k == 2 ? y2 : k == 3 ? y3 : 0u;
+}
+ZF_DEV uint64_t yfield_rt(uint32_t y0, uint32_t y1, uint32_t y2, uint32_t y3, uint32_t pos, uint32_t w) {
+    const uint32_t k = pos >> 5, s = pos & 31;
+    const uint32_t a = ysel(y0, y1, y2, y3, k), b = ysel(y0, y1, y2, y3, k + 1),
+                   c = ysel(y0, y1, y2, y3, k + 2);
+    const uint32_t lo = alignbit(b, a, s), hi = alignbit(c, b, s);
+    const uint64_t v = uint64_t(lo) | (uint64_t(hi) << 32);
+    return w >= 64 ? v : (v & ((1ull << w) - 1ull));
+}
+
+template <int ES, bool DICT>
+ZF_DEV void fp_block_rt(uint32_t w, const uint32_t *words, uint64_t nwords, uint64_t ref, uint32_t nv,
+                        uint8_t *ob, bool vec, const uint8_t *dict, uint32_t dict_count, bool &bad) {
+    constexpr uint32_t VPL = 16 / ES;
+    const uint32_t lane = lane_id();
+    const ZF_GLOBAL uint8_t *gd = gp(dict);
+    for (uint32_t v0 = lane * VPL; v0 < nv; v0 += 64 * VPL) {
+        const Win wv = load_words<5>(words, (uint64_t(v0) * w) >> 5, nwords);
+        const uint32_t sh = uint32_t((uint64_t(v0) * w) & 31u);
+        const uint32_t y0 = yword<0>(wv, sh), y1 = yword<1>(wv, sh), y2 = yword<2>(wv, sh),
+                       y3 = yword<3>(wv, sh);
+        uint64_t v[VPL];
+#pragma unroll
+        for (uint32_t i = 0; i < VPL; i++) {
+            const uint64_t f = yfield_rt(y0, y1, y2, y3, i * w, w);
+            if constexpr (DICT) {
+                const uint32_t code = uint32_t(ref) + uint32_t(f);
+                const bool in = v0 + i < nv, ok = code < dict_count;
+                bad |= in && !ok;
+                v[i] = 0;
+                if (in && ok) {
+                    if constexpr (ES == 4) v[i] = *reinterpret_cast<const ZF_GLOBAL uint32_t *>(gd + 4ull * code);
+                    if constexpr (ES == 8) v[i] = *reinterpret_cast<const ZF_GLOBAL uint64_t *>(gd + 8ull * code);
+                }
+                if constexpr (ES == 16) {
+                    u32x4 e = {0, 0, 0, 0};
+                    if (ok) e = *reinterpret_cast<const ZF_GLOBAL u32x4 *>(gd + 16ull * code);
+                    if (vec) st16_nt(ob + 16ull * v0, e.x, e.y, e.z, e.w);
+                    else {
+                        st4(ob + 16ull * v0, e.x);
+                        st4(ob + 16ull * v0 + 4, e.y);
+                        st4(ob + 16ull * v0 + 8, e.z);
+                        st4(ob + 16ull * v0 + 12, e.w);
+                    }
+                }
+            } else {
+                v[i] = ref + f;
+            }
+        }
+        if constexpr (ES == 4) {
+            if (vec && v0 + 4 <= nv) st16_nt(ob + 4ull * v0, uint32_t(v[0]), uint32_t(v[1]), uint32_t(v[2]), uint32_t(v[3]));
+            else
+                for (uint32_t i = 0; i < 4; i++)
+                    if (v0 + i < nv) st4(ob + 4ull * (v0 + i), uint32_t(v[i]));
+        } else if constexpr (ES == 8) {
+            if (vec && v0 + 2 <= nv)
+                st16_nt(ob + 8ull * v0, uint32_t(v[0]), uint32_t(v[0] >> 32), uint32_t(v[1]), uint32_t(v[1] >> 32));
+            else
+                for (uint32_t i = 0; i < 2; i++)
+                    if (v0 + i < nv) {
+                        st4(ob + 8ull * (v0 + i), uint32_t(v[i]));
+                        st4(ob + 8ull * (v0 + i) + 4, uint32_t(v[i] >> 32));
+                    }
+        }
+    }
+}
+
+// Uniform dispatch on the block's width to its specialised decoder.
+template <int ES, bool DICT, uint32_t UNR, uint32_t W, uint32_t WMAX>
+ZF_DEV void fp_dispatch(uint32_t w, const uint32_t *words, uint64_t nwords, uint64_t ref, uint32_t nv,
+                        uint8_t *ob, bool vec, const uint8_t *dict, uint32_t dict_count, bool &bad) {
+    if constexpr (W <= WMAX) {
+        if (w == W) fp_block<ES, DICT, UNR, W>(words, nwords, ref, nv, ob, vec, dict, dict_count, bad);
+        else fp_dispatch<ES, DICT, UNR, W + 1, WMAX>(w, words, nwords, ref, nv, ob, vec, dict, dict_count, bad);
+    }
+}
+
+// One wave decodes blocks [t.a, t.a + t.b) of a FOR_BP or DICT_BP chunk.
+// ES = output bytes per value; DICT = dictionary lookup fused after unpack.
+// MAXUNR = 0 selects the runtime-width variant.
+template <int ES, bool DICT, uint32_t MAXUNR>
+ZF_DEV void unit_fp(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck) {
+    constexpr uint32_t VPL = 16 / ES;                     // values per lane per step
+    constexpr uint32_t STEPS = kForBlock / (64 * VPL);    // lane-steps per block
+    constexpr uint32_t UNR = STEPS < MAXUNR ? STEPS : (MAXUNR ? MAXUNR : 1);
+    constexpr uint32_t BITS = (ES == 8 && !DICT) ? 64 : 32;
+    const uint8_t *s = A.comp + ck.comp_off;
+    const uint32_t n = ck.n_elems, clen = ck.comp_len;
+    const uint32_t nb = (n + kForBlock - 1) / kForBlock;
+    uint8_t *out = A.out_tab[ck.col] + ck.out_off;
+    const uint8_t *dict = A.dict + ck.dict_off;
+    if (16ull * nb > clen || t.a + t.b > nb) {
+        flag(A.err, ERR_CORRUPT);
+        return;
+    }
+    bool bad = false;
+    for (uint32_t b = t.a; b < t.a + t.b; b++) {
+        const uint8_t *d = s + 16ull * b;
+        const uint64_t ref = ld64u(d);
+        const uint32_t w = ld32u(d + 8), poff = ld32u(d + 12);
+        const uint32_t j0 = b * kForBlock;
+        const uint32_t nv = min(kForBlock, n - j0);
+        const uint64_t nwords = (uint64_t(nv) * w + 31) / 32;
+        if (w > BITS || (poff & 15u) || poff < 16ull * nb || poff + 4 * nwords > clen) {
+            flag(A.err, ERR_CORRUPT);
+            return;
+        }
+        const uint32_t *words = reinterpret_cast<const uint32_t *>(s + poff);
+        uint8_t *ob = out + uint64_t(j0) * ES;
+        const bool vec = (reinterpret_cast<uintptr_t>(ob) & 15u) == 0;
+        if constexpr (MAXUNR == 0)
+            fp_block_rt<ES, DICT>(first32(w), words, nwords, ref, nv, ob, vec, dict, ck.dict_count, bad);
+        else
+            fp_dispatch<ES, DICT, UNR, 0, BITS>(first32(w), words, nwords, ref, nv, ob, vec, dict,
+                                                ck.dict_count, bad);
+    }
+    if (any(bad)) flag(A.err, ERR_CORRUPT);
+}
+
+// ===================================================== Group-Parallel
+// One wave writes elements [t.b, t.c) of an RLE_DELTA_BP / DELTA_BP chunk,
+// starting at group t.a.
+template <class T>
+ZF_DEV void unit_rle(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck) {
+    using U = T;  // unsigned value type: uint32_t or uint64_t
+    constexpr uint32_t BITS = sizeof(T) * 8;
+    const uint8_t *s = A.comp + ck.comp_off;
+    const uint32_t n = ck.n_elems, clen = ck.comp_len, lane = lane_id();
+    const bool unit_runs = ck.codec == C_DELTA_BP;
+    U *out = reinterpret_cast<U *>(A.out_tab[ck.col] + ck.out_off);
+    if (clen < 16) {
+        flag(A.err, ERR_CORRUPT);
+        return;
+    }
+    const uint32_t nr = ld32u(s), ng = ld32u(s + 4), roff = ld32u(s + 8);
+    bool hdr_ok = ng == (uint64_t(nr) + kRleGroup - 1) / kRleGroup && 16ull + 32ull * ng <= clen;
+    if (unit_runs) hdr_ok = hdr_ok && nr == n && roff == 0;
+    else hdr_ok = hdr_ok && (roff & 3u) == 0 && roff >= 16ull + 32ull * ng && roff + 4ull * nr <= clen;
+    const uint32_t e0 = t.b, e1 = t.c;
+    if (!hdr_ok || e1 > n || e0 >= e1) {
+        flag(A.err, ERR_CORRUPT);
+        return;
+    }
+    const uint32_t *runs = reinterpret_cast<const uint32_t *>(s + roff);
+    for (uint32_t g = t.a;; g++) {
+        if (g >= ng) {
+            flag(A.err, ERR_CORRUPT);
+            return;
+        }
+        const uint8_t *rec = s + 16 + 32ull * g;
+        const uint32_t goff = ld32u(rec), w = ld32u(rec + 4), doff = ld32u(rec + 8);
+        const U base = U(ld64u(rec + 16)), dmin = U(ld64u(rec + 24));
+        const uint32_t cnt = min(kRleGroup, nr - g * kRleGroup);
+        const uint64_t nwords = (uint64_t(cnt - 1) * w + 31) / 32;
+        const uint32_t next_off = (g + 1 < ng) ? ld32u(rec + 32) : n;
+        if (w > BITS || (doff & 3u) || doff + 4 * nwords > clen || (g == t.a && goff > e0) ||
+            next_off > n) {
+            flag(A.err, ERR_CORRUPT);
+            return;
+        }
+        // run lengths -> output offsets (exclusive scan = presum)
+        const bool act = lane < cnt;
+        const uint32_t r = act ? (unit_runs ? 1u : runs[uint64_t(g) * kRleGroup + lane]) : 0u;
+        const uint64_t incl = scan_add64(r);
+        const uint64_t total = rl64(incl, cnt - 1);
+        if (any(act && r == 0) || uint64_t(goff) + total != next_off) {
+            flag(A.err, ERR_CORRUPT);
+            return;
+        }
+        const uint32_t end_abs = goff + uint32_t(incl);  // end of run `lane`
+        // run values: base, then base + prefix sums of (dmin + field)
+        U delta = base;
+        if (lane >= 1 && act) {
+            const uint64_t bit = uint64_t(lane - 1) * w;
+            const uint32_t *words = reinterpret_cast<const uint32_t *>(s + doff);
+            const uint64_t k = bit >> 5;
+            const uint32_t sh = uint32_t(bit & 31u);
+            const uint32_t w0 = k < nwords ? words[k] : 0u;
+            const uint32_t w1 = k + 1 < nwords ? words[k + 1] : 0u;
+            U f;
+            if constexpr (BITS == 32) {
+                f = uint32_t((uint64_t(w0) | (uint64_t(w1) << 32)) >> sh) & mask32(w);
+            } else {
+                const uint32_t w2 = k + 2 < nwords ? words[k + 2] : 0u;
+                const uint64_t lo = uint64_t(w0) | (uint64_t(w1) << 32);
+                f = (sh ? ((lo >> sh) | (uint64_t(w2) << (64 - sh))) : lo) & mask64(w);
+            }
+            delta = U(dmin + f);
+        }
+        const U v = scan_addT<U>(act ? delta : U(0));
+        // expand the part of this group inside [e0, e1)
+        const uint32_t a = max(e0, goff), bnd = min(e1, next_off);
+        if (a < bnd) {
+            uint32_t j = uint32_t(__popcll(__ballot(act && end_abs <= a)));  // run holding a
+            for (uint32_t W0 = a; W0 < bnd; W0 += 64) {
+                const uint32_t wend = W0 + 64, p = W0 + lane;
+                U val = rlT<U>(v, j);
+                uint32_t k = j;
+                while (k + 1 < cnt) {
+                    const uint32_t st = rl32(end_abs, k);  // start of run k+1
+                    if (st >= wend) break;
+                    k++;
+                    if (p >= st) val = rlT<U>(v, k);
+                }
+                if (p < bnd) out[p] = val;
+                j = (rl32(end_abs, k) <= wend) ? k + 1 : k;
+            }
+        }
+        if (next_off >= e1) return;
+    }
+}
+
+// ======================================================== Non-Parallel
+// Per-wave table of the current batch's sequences (LDS): output start P,
+// literal end D, sequence end E, literal start LP, and the match offset.
+struct LzSeq {
+    uint4 pdel[64];   // {P, D, E, LP}
+    uint32_t off[64];
+};
+
+// One wave decodes one whole LZ77 chunk.
+ZF_DEV void unit_lz(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, LzSeq &tab) {
+    const uint8_t *s = A.comp + ck.comp_off;
+    const uint32_t clen = ck.comp_len, lane = lane_id();
+    const uint32_t es = ck.dtype == D_I32 ? 4 : ck.dtype == D_I64 ? 8 : ck.dtype == D_FIXED16 ? 16 : 1;
+    const uint32_t plain = ck.n_elems * es;
+    uint8_t *out = A.out_tab[ck.col] + ck.out_off;
+    if (clen < 16) {
+        flag(A.err, ERR_CORRUPT);
+        return;
+    }
+    const uint32_t nseq = ld32u(s), nlit = ld32u(s + 4), next = ld32u(s + 8), plen = ld32u(s + 12);
+    if (plen != plain || plain > kLzMaxChunk ||
+        16ull + 3ull * nseq + 2ull * next + nlit != uint64_t(clen)) {
+        flag(A.err, ERR_CORRUPT);
+        return;
+    }
+    const uint16_t *offs = reinterpret_cast<const uint16_t *>(s + 16);
+    const uint16_t *ext = offs + nseq;
+    const uint8_t *tags = reinterpret_cast<const uint8_t *>(ext + next);
+    const uint8_t *lits = tags + nseq;
+    // misalignment of the chunk's output, for 16-byte aligned stores
+    const uint32_t mis = uint32_t(reinterpret_cast<uintptr_t>(out) & 15u);
+    uint32_t pos = 0, lp = 0, ep = 0;
+    uint32_t tag = lane < nseq ? tags[lane] : 0u;
+    uint32_t off = lane < nseq ? offs[lane] : 0u;
+    for (uint32_t base = 0; base < nseq; base += 64) {
+        const uint32_t i = base + lane;
+        const bool act = i < nseq;
+        // prefetch the next batch's headers
+        const uint32_t ni = i + 64;
+        const uint32_t ntag = ni < nseq ? tags[ni] : 0u;
+        const uint32_t noff = ni < nseq ? offs[ni] : 0u;
+
+        const uint32_t lc = tag & 7u, mc = tag >> 3;
+        const uint32_t ne = (lc == 7u) + (mc == 31u);
+        const uint32_t eincl = scan_add32(ne);
+        const uint32_t eex = ep + eincl - ne, etot = rl32(eincl, 63);
+        if (uint64_t(ep) + etot > next) {
+            flag(A.err, ERR_CORRUPT);
+            return;
+        }
+        uint32_t ll = lc, ml = 0;
+        if (lc == 7u) ll = 7u + ext[eex];
+        if (mc == 31u) ml = 34u + ext[eex + (lc == 7u)];
+        else if (mc) ml = mc + 3u;
+        const uint32_t len = ll + ml;
+        const uint32_t pincl = scan_add32(len), lincl = scan_add32(ll);
+        const uint32_t P = pos + pincl - len, LP = lp + lincl - ll;
+        const uint32_t total = rl32(pincl, 63), ltot = rl32(lincl, 63);
+        const uint32_t D = P + ll;
+        const bool bad = act && (uint64_t(P) + len > plain || uint64_t(LP) + ll > nlit ||
+                                 (ml == 0 ? off != 0 : (off == 0 || off > D)));
+        if (any(bad)) {
+            flag(A.err, ERR_CORRUPT);
+            return;
+        }
+        const uint32_t q0 = D - off;  // first source byte of the match
+        const bool flat = ml == 0 || q0 + min(ml, off) <= pos || q0 >= P;
+        const uint32_t cnt = min(64u, nseq - base);
+        const uint32_t end = pos + total;
+        if (!any(!flat)) {
+            // Flat batch: every byte's source is final before the batch starts
+            // (earlier output) or is a literal of the same sequence.  Each lane
+            // owns one 16-byte aligned block of the batch's output at a time.
+            tab.pdel[lane] = make_uint4(P, D, P + len, LP);
+            tab.off[lane] = off;
+            wave_fence();
+            for (int32_t B = int32_t(pos) - int32_t((mis + pos) & 15u) + int32_t(16 * lane);
+                 B < int32_t(end); B += 1024) {
+                const uint32_t p0 = uint32_t(max(B, int32_t(pos)));
+                const uint32_t pe = min(uint32_t(B + 16), end);
+                // sequence holding p0: the last one with P <= p0
+                uint32_t lo = 0, hi = cnt;
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (tab.pdel[mid].x <= p0) lo = mid;
+                    else hi = mid;
+                }
+                uint4 r = tab.pdel[lo];
+                uint32_t so = tab.off[lo], sidx = lo;
+                // phase 1: where each byte comes from (bit 31 set: a literal)
+                uint32_t src[16];
+#pragma unroll
+                for (uint32_t k = 0; k < 16; k++) {
+                    const uint32_t p = uint32_t(B) + k;
+                    src[k] = 0;
+                    if (p >= p0 && p < pe) {
+                        while (p >= r.z) {  // next sequence (zero-length ones skipped)
+                            sidx++;
+                            r = tab.pdel[sidx];
+                            so = tab.off[sidx];
+                        }
+                        if (p < r.y) {
+                            src[k] = 0x80000000u | (r.w + (p - r.x));
+                        } else {
+                            const uint32_t j = p - r.y;
+                            const uint32_t q = (r.y - so) + (j < so ? j : j % so);
+                            src[k] = q >= pos ? 0x80000000u | (r.w + (q - r.x)) : q;
+                        }
+                    }
+                }
+                // phase 2: all 16 loads in flight together
+                uint32_t byte[16];
+#pragma unroll
+                for (uint32_t k = 0; k < 16; k++) {
+                    const uint32_t p = uint32_t(B) + k;
+                    byte[k] = 0;
+                    if (p >= p0 && p < pe)
+                        byte[k] = (src[k] & 0x80000000u) ? lits[src[k] & 0x7FFFFFFFu] : out[src[k]];
+                }
+                const uint32_t w0 = byte[0] | (byte[1] << 8) | (byte[2] << 16) | (byte[3] << 24);
+                const uint32_t w1 = byte[4] | (byte[5] << 8) | (byte[6] << 16) | (byte[7] << 24);
+                const uint32_t w2 = byte[8] | (byte[9] << 8) | (byte[10] << 16) | (byte[11] << 24);
+                const uint32_t w3 = byte[12] | (byte[13] << 8) | (byte[14] << 16) | (byte[15] << 24);
+                if (p0 == uint32_t(B) && pe == uint32_t(B) + 16) {
+                    *reinterpret_cast<uint4 *>(out + B) = make_uint4(w0, w1, w2, w3);
+                } else {
+                    for (uint32_t p = p0; p < pe; p++) {
+                        const uint32_t k = p - uint32_t(B);
+                        const uint32_t wd = k < 4 ? w0 : k < 8 ? w1 : k < 12 ? w2 : w3;
+                        out[p] = uint8_t(wd >> (8 * (k & 3)));
+                    }
+                }
+            }
+            wave_fence();
+        } else {
+            // in-order replay of this batch
+            for (uint32_t k = 0; k < cnt; k++) {
+                const uint32_t Pk = rl32(P, k), llk = rl32(ll, k), LPk = rl32(LP, k);
+                const uint32_t mlk = rl32(ml, k), offk = rl32(off, k), Dk = Pk + llk;
+                for (uint32_t x = lane; x < llk; x += 64) out[Pk + x] = lits[LPk + x];
+                wave_fence();
+                const uint32_t step = min(offk, 64u);
+                for (uint32_t j0 = 0; j0 < mlk; j0 += step) {
+                    const uint32_t j = j0 + lane;
+                    if (lane < step && j < mlk) out[Dk + j] = out[Dk - offk + j];
+                    wave_fence();
+                }
+            }
+        }
+        pos = end;
+        lp += ltot;
+        ep += etot;
+        tag = ntag;
+        off = noff;
+    }
+    if (pos != plain || lp != nlit || ep != next) flag(A.err, ERR_CORRUPT);
+}
+
+// ================================================================ PLAIN
+ZF_DEV void unit_plain(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck) {
+    const uint8_t *src = A.comp + ck.comp_off;
+    uint8_t *dst = A.out_tab[ck.col] + ck.out_off;
+    const uint32_t a = t.a, b = min(t.b, ck.comp_len), lane = lane_id();
+    if (((reinterpret_cast<uintptr_t>(src + a) | reinterpret_cast<uintptr_t>(dst + a)) & 15u) == 0) {
+        const uint32_t nvec = (b - a) / 16;
+        const uint4 *s4 = reinterpret_cast<const uint4 *>(src + a);
+        uint8_t *d8 = dst + a;
+        uint32_t i = lane;
+        for (; i + 7 * 64 < nvec; i += 8 * 64) {
+            uint4 v[8];
+#pragma unroll
+            for (uint32_t u = 0; u < 8; u++) v[u] = s4[i + u * 64];
+#pragma unroll
+            for (uint32_t u = 0; u < 8; u++)
+                st16_nt(d8 + 16ull * (i + u * 64), v[u].x, v[u].y, v[u].z, v[u].w);
+        }
+        for (; i < nvec; i += 64) {
+            const uint4 v = s4[i];
+            st16_nt(d8 + 16ull * i, v.x, v.y, v.z, v.w);
+        }
+        for (uint32_t k = a + nvec * 16 + lane; k < b; k += 64) dst[k] = src[k];
+    } else {
+        for (uint32_t k = a + lane; k < b; k += 64) dst[k] = src[k];
+    }
+}
+
+
+// ============================================================== dispatch
+// UNR: FP lane-steps of loads kept in flight; 0 = runtime-width FP path.
+template <uint32_t UNR>
+ZF_DEV void run_unit(const LaunchArgs &A, uint32_t kind, uint32_t u, LzSeq *tab) {
+    const Tile t = A.tiles[u];
+    const ChunkDesc ck = A.chunks[t.chunk];
+    switch (kind) {
+    case K_PLAIN: unit_plain(A, t, ck); break;
+    case K_FOR32: unit_fp<4, false, UNR>(A, t, ck); break;
+    case K_FOR64: unit_fp<8, false, UNR>(A, t, ck); break;
+    case K_DICT32: unit_fp<4, true, UNR>(A, t, ck); break;
+    case K_DICT64: unit_fp<8, true, UNR>(A, t, ck); break;
+    case K_DICT128: unit_fp<16, true, UNR>(A, t, ck); break;
+    case K_RLE32: unit_rle<uint32_t>(A, t, ck); break;
+    case K_RLE64: unit_rle<uint64_t>(A, t, ck); break;
+    case K_LZ: unit_lz(A, t, ck, *tab); break;
+    }
+}
+
+// One launch per kind: wave w of block b takes unit begin + b*waves + w.
+// Only the routine of KIND is instantiated here.
+template <uint32_t KIND>
+__global__ __launch_bounds__(1024) void k_decode_kind(LaunchArgs A) {
+    const uint32_t waves = blockDim.x / 64;
+    const uint32_t u = A.kind_begin[KIND] + blockIdx.x * waves + first32(threadIdx.x / 64);
+    if (u >= A.kind_begin[KIND + 1]) return;
+    const Tile t = A.tiles[u];
+    const ChunkDesc ck = A.chunks[t.chunk];
+    if constexpr (KIND == K_LZ) {
+        __shared__ LzSeq tab[16];
+        unit_lz(A, t, ck, tab[threadIdx.x / 64]);
+    } else if constexpr (KIND == K_PLAIN) {
+        unit_plain(A, t, ck);
+    } else if constexpr (KIND == K_FOR32) {
+        unit_fp<4, false, 8>(A, t, ck);
+    } else if constexpr (KIND == K_FOR64) {
+        unit_fp<8, false, 8>(A, t, ck);
+    } else if constexpr (KIND == K_DICT32) {
+        unit_fp<4, true, 8>(A, t, ck);
+    } else if constexpr (KIND == K_DICT64) {
+        unit_fp<8, true, 8>(A, t, ck);
+    } else if constexpr (KIND == K_DICT128) {
+        unit_fp<16, true, 8>(A, t, ck);
+    } else if constexpr (KIND == K_RLE32) {
+        unit_rle<uint32_t>(A, t, ck);
+    } else if constexpr (KIND == K_RLE64) {
+        unit_rle<uint64_t>(A, t, ck);
+    }
+}
+
+// Host launchers, one per kind, each defined in its kind's translation unit.
+#define ZF_KIND_LAUNCHERS(X)                                                                       \
+    X(K_LZ, launch_lz) X(K_RLE64, launch_rle64) X(K_RLE32, launch_rle32)                           \
+    X(K_DICT128, launch_dict128) X(K_DICT64, launch_dict64) X(K_DICT32, launch_dict32)              \
+    X(K_FOR64, launch_for64) X(K_FOR32, launch_for32) X(K_PLAIN, launch_plain)
+#define ZF_DECLARE_LAUNCHER(KIND, NAME) void NAME(const LaunchArgs &A, uint32_t waves, hipStream_t st);
+ZF_KIND_LAUNCHERS(ZF_DECLARE_LAUNCHER)
+
+#define ZF_DEFINE_LAUNCHER(KIND, NAME)                                                             \
+    void NAME(const LaunchArgs &A, uint32_t waves, hipStream_t st) {                               \
+        const uint32_t n = A.kind_begin[KIND + 1] - A.kind_begin[KIND];                            \
+        if (!n) return;                                                                            \
+        hipLaunchKernelGGL(k_decode_kind<KIND>, dim3((n + waves - 1) / waves), dim3(64 * waves), 0, \
+                           st, A);                                                                 \
+    }
+
+}  // namespace zf

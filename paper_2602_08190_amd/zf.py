@@ -223,7 +223,7 @@ class Plan:
     """Work tables, batches and device workspace for decoding `cols`."""
 
     def __init__(self, cols, device=0, slot_bytes=256 << 20, n_slots=2, use_graphs=True,
-                 persistent=True, order=0, pcie_gbps=0.0, tiles=None):
+                 persistent=False, order=0, pcie_gbps=0.0, tiles=None):
         self.cols = list(cols)
         o = PlanOpts()
         lib().zf_plan_opts_default(ctypes.byref(o))
