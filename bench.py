@@ -16,7 +16,6 @@ the host CPU.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload fact|for|rle|lz|copy]
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -30,7 +29,6 @@ sys.path.insert(0, ROOT)
 METRIC = "end-to-end effective GB/s (H2D+decode) vs raw PCIe copy; decode HBM GB/s"
 HBM_PEAK_GBPS = 8000.0
 PCIE_PEAK_GBPS = 63.0
-KERNEL_SRC = os.path.join(ROOT, "paper_2602_08190_amd", "csrc", "kernels.hip")
 
 
 def log(*a):
@@ -38,8 +36,8 @@ def log(*a):
 
 
 def kernel_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    from paper_2602_08190_amd.profiling import kernel_sha
+    return kernel_sha()
 
 
 # ------------------------------------------------------------- workloads
@@ -120,10 +118,10 @@ def cpu_baseline(cols, budget_s=15.0):
                       f"/ time"}
 
 
-def read_traffic(workload):
-    """HBM traffic per launch from committed rocprofv3 counter summaries, if
-    they were taken on the current kernel source."""
-    p = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
+def read_traffic(key):
+    """HBM bytes per launch of one kernel from the committed counter summary
+    (profiles/traffic.txt), if it was taken on the current kernel sources."""
+    p = os.path.join(ROOT, "profiles", "traffic.txt")
     if not os.path.exists(p):
         return None
     kv = {}
@@ -134,9 +132,29 @@ def read_traffic(workload):
     if kv.get("kernel_sha") != kernel_hash():
         return None
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv[key])
     except (KeyError, ValueError):
         return None
+
+
+def time_decode(zf, torch, cols, outs, steps, warmup, **plan_kw):
+    """Average ms of zf_decompress_async over `steps` on the current stream."""
+    plan = zf.Plan(cols, device=0, **plan_kw)
+    img = zf.upload_image(plan, cols)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        plan.decompress_async(img, img.numel(), outs)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(steps):
+        plan.decompress_async(img, img.numel(), outs)
+    b.record(stream)
+    torch.cuda.synchronize()
+    plan.sync()
+    ms = a.elapsed_time(b) / steps
+    del img
+    return ms
 
 
 # ------------------------------------------------------------------ main
@@ -207,6 +225,24 @@ def main():
     hbm_gbps = alg_bytes / (ms * 1e-3) / 1e9
     log(f"decode from HBM: {ms:.3f} ms/step, {value:.1f} GB/s plain, {hbm_gbps:.1f} GB/s HBM")
 
+    # per-kernel breakdown: each codec's columns decoded alone (one kernel
+    # kind per plan), to find the dominant kernel and its roofline
+    kinds = {}
+    groups = {}
+    for c, o in zip(cols, outs):
+        key = zf.kind_of_column(c)
+        groups.setdefault(key, ([], []))
+        groups[key][0].append(c)
+        groups[key][1].append(o)
+    for key, (gc, go) in groups.items():
+        kms = time_decode(zf, torch, gc, go, max(3, args.steps // 2), 1,
+                          persistent=bool(args.persistent))
+        kb = sum(c.host_pointer()[1] + c.plain_bytes for c in gc)
+        kinds[key] = {"ms": round(kms, 4), "algorithmic_bytes": kb,
+                      "GBps": round(kb / (kms * 1e-3) / 1e9, 1)}
+        log(f"kernel {key:8s}: {kms:.3f} ms, {kb / (kms * 1e-3) / 1e9:.1f} GB/s of algorithmic bytes")
+    dom = max(kinds, key=lambda k: kinds[k]["ms"])
+
     result = {
         "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
@@ -217,14 +253,14 @@ def main():
                    "chunks": sum(c.n_chunks for c in cols),
                    "launch": "persistent" if args.persistent else "per-kind"},
         "decode_hbm_GBps": round(hbm_gbps, 1),
-        "roofline": {"bound": "hbm", "achieved": round(hbm_gbps, 1), "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": round(hbm_gbps / HBM_PEAK_GBPS, 4),
-                     "traffic": None, "kernel": "k_decode_persistent" if args.persistent else "k_decode_kind",
-                     "algorithmic_bytes_per_launch": alg_bytes},
+        "roofline": {"bound": "hbm", "achieved": kinds[dom]["GBps"], "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(kinds[dom]["GBps"] / HBM_PEAK_GBPS, 4),
+                     "traffic": read_traffic(f"{args.workload}/{dom}"),
+                     "kernel": f"k_decode_kind<{dom}>",
+                     "algorithmic_bytes_per_launch": kinds[dom]["algorithmic_bytes"],
+                     "avg_launch_ms": kinds[dom]["ms"]},
+        "kernels": kinds,
     }
-    traffic = read_traffic(args.workload)
-    if traffic is not None:
-        result["roofline"]["traffic"] = traffic
 
     if not args.no_e2e:
         # PCIe end to end: pinned host -> staging slots -> decode, pipelined

@@ -21,7 +21,9 @@
  *     u32 dict_count, u64 dict_off, u64 total_bytes, u32 table_crc,
  *     u32 0, u32 0, u32 header_crc (CRC-32 of header bytes [0,60)).
  *   chunk table at 64: per chunk 32 bytes {u64 plain_off, u64 comp_off,
- *     u32 plain_len, u32 comp_len, u32 n_elems, u8 codec, 3 zero bytes}.
+ *     u32 plain_len, u32 comp_len, u32 n_elems, u8 codec, u8 schedule hint
+ *     (0 = tuned default, 1..4 = tile granularity chosen at encode time;
+ *     decoding does not depend on it), 2 zero bytes}.
  *   dictionary (dict_count > 0) at dict_off: sorted unique values.
  *   chunk streams at 16-aligned comp_off.  table_crc = CRC-32 of the chunk
  *   table followed by the dictionary.  The per-codec streams are described
@@ -102,6 +104,9 @@ typedef struct {
     const uint32_t *chunk_elems;  /* explicit chunking (overrides the above)   */
     uint32_t n_chunk_elems;
     const uint32_t *chunk_codecs; /* per-chunk codec for explicit chunking     */
+    const char *mlp_weights;      /* cost model for ZF_AUTO (NULL: $ZF_MLP_WEIGHTS;
+                                     without one, ZF_AUTO keeps the smallest
+                                     stream of the applicable codecs)         */
 } zf_encode_opts;
 
 /* Defaults: chunks of 1 MiB plain (LZ77: 64 KiB), all cores, pinned. */
@@ -116,9 +121,21 @@ void zf_encode_opts_default(zf_encode_opts *opts);
  * default) until zf_column_free.  Errors: ZF_E_INVALID (dtype/codec mix,
  * null pointers, chunking that does not sum to n_elems, LZ77 chunks above
  * 65536 bytes), ZF_E_NOMEM.
+ * ZF_AUTO with a cost model: each chunk's statistics (zf_chunk_features) go
+ * through the network and the chunk takes the applicable (codec, schedule)
+ * with the lowest predicted transfer + decode time; the schedule is stored in
+ * the chunk table (LZ77 chunks are split at the chosen chunk size).
  */
 zf_status zf_compress_host(const void *src, uint64_t n_elems, zf_dtype dtype, zf_codec codec,
                            const zf_encode_opts *opts /* nullable */, zf_column_t **out);
+
+/* The 32 statistics the cost model reads for a chunk of n_elems values at
+ * src (host memory), computed on its first 65,536 values: sizes, value range
+ * and FOR widths, distinct count and top frequencies, byte and value entropy,
+ * order, runs and deltas, text shape, repeats of 4-byte strings, and
+ * closed-form size estimates per codec.  out receives ZF_FEATURES floats. */
+#define ZF_FEATURES 32
+zf_status zf_chunk_features(const void *src, uint64_t n_elems, zf_dtype dtype, float *out);
 
 /* Adopt a serialised column (copied; `pinned` as in zf_encode_opts).  The
  * header, CRCs, chunk table and every stream's directory are validated;
@@ -132,13 +149,29 @@ uint32_t zf_column_n_chunks(const zf_column_t *col);
 int32_t zf_column_dtype(const zf_column_t *col);
 void zf_column_free(zf_column_t *col);
 
-/* Tile shapes (the paper's <L,S,C> per pattern, Sec. 4); 0 = tune cache. */
+/* Kernel kinds: one decode routine per pattern class and value width. */
+typedef enum {
+    ZF_KIND_LZ77 = 0,
+    ZF_KIND_RLE64,   /* RLE_DELTA_BP and DELTA_BP, int64 */
+    ZF_KIND_RLE32,   /* RLE_DELTA_BP and DELTA_BP, int32 */
+    ZF_KIND_DICT128,
+    ZF_KIND_DICT64,
+    ZF_KIND_DICT32,
+    ZF_KIND_FOR64,
+    ZF_KIND_FOR32,
+    ZF_KIND_PLAIN,
+    ZF_KIND_COUNT
+} zf_kind;
+
+/* Tile shape of one kind, the device geometry of Sec. 4 (<L,S,C>): `unit`
+ * is the work of one wavefront (FP: 2048-value blocks; GP: output elements;
+ * PLAIN: bytes; LZ77: ignored, one chunk per wavefront), `waves_per_block`
+ * the wavefronts per workgroup (S/64).  A lane always owns 16 output bytes
+ * per step (C).  Zero fields take the tune cache's value, else a default. */
 typedef struct {
-    uint32_t fp_blocks;       /* FP: 2048-value blocks per wave unit            */
-    uint32_t gp_elems;        /* GP: output elements per wave unit              */
-    uint32_t waves_per_block; /* waves per workgroup (per-kind launches)        */
-    uint32_t waves_per_cu;    /* persistent kernel: waves in flight per CU      */
-} zf_tiles;
+    uint32_t unit;
+    uint32_t waves_per_block;
+} zf_tile;
 
 typedef struct {
     uint64_t slot_bytes;     /* staging slot size for transfers (default 256 MiB) */
@@ -148,7 +181,10 @@ typedef struct {
                                 0: one launch per kernel kind (default)             */
     int32_t order;           /* 0: Johnson order (default); 1: column order          */
     double pcie_gbps;        /* transfer-time estimate for ordering (0: 55)          */
-    zf_tiles tiles;          /* explicit tile shapes; zero fields use the defaults */
+    zf_tile tiles[ZF_KIND_COUNT];
+    uint32_t waves_per_cu;   /* persistent kernel: waves in flight per CU (0: 16)    */
+    const char *tune_cache;  /* tile cache (JSON); NULL: $ZF_TUNE_CACHE, else the
+                                tune_gfx950.json next to libzf.so, else defaults    */
 } zf_plan_opts;
 
 void zf_plan_opts_default(zf_plan_opts *opts);
@@ -208,6 +244,38 @@ zf_status zf_transfer_and_decompress(zf_plan_t *plan, void *const *d_out, zf_str
  * zf_plan_clear_error). */
 zf_status zf_sync(zf_plan_t *plan, zf_stream_t stream);
 void zf_plan_clear_error(zf_plan_t *plan);
+
+/*
+ * Learned (codec, schedule) choice: a cost-model network of 32 chunk
+ * statistics -> 64 -> 64 -> 24 scores (6 codecs x 4 schedules; each a
+ * predicted log of transfer + decode time), relu hidden layers, FP32.
+ * Parameters are one flat device array of ZF_MLP_PARAMS floats:
+ * W1 (64x32), b1 (64), W2 (64x64), b2 (64), W3 (24x64), b3 (24), row-major.
+ * Inputs x are n x 32 row-major; outputs y are n x 24.  All pointers are
+ * device pointers owned by the caller; calls are enqueued on `stream`.
+ */
+#define ZF_MLP_IN 32
+#define ZF_MLP_HIDDEN 64
+#define ZF_MLP_OUT 24
+#define ZF_MLP_PARAMS 7832
+
+/* y = network(x) for n samples. */
+zf_status zf_mlp_forward(const float *d_params, const float *d_x, uint32_t n, float *d_y,
+                         zf_stream_t stream);
+/* Bytes of device workspace zf_mlp_grad needs for n samples. */
+uint64_t zf_mlp_grad_work_bytes(uint32_t n);
+/* Loss (1/n) sum_i (y_i[k_i] - t_i)^2 into *d_loss and its gradient with
+ * respect to every parameter into d_grad (ZF_MLP_PARAMS floats).  Summation
+ * order is fixed, so results are bit-reproducible.  A k_i outside [0, 24)
+ * makes the loss NaN and contributes no gradient.  ZF_E_TOO_SMALL when
+ * work_bytes < zf_mlp_grad_work_bytes(n). */
+zf_status zf_mlp_grad(const float *d_params, const float *d_x, const int32_t *d_k, const float *d_t,
+                      uint32_t n, float *d_grad, float *d_loss, void *d_work, uint64_t work_bytes,
+                      zf_stream_t stream);
+/* One Adam step (step counts from 1) on the parameters in place; d_m and
+ * d_v are the moment estimates (ZF_MLP_PARAMS floats each, zero at start). */
+zf_status zf_mlp_adam(float *d_params, const float *d_grad, float *d_m, float *d_v, uint32_t step,
+                      float lr, float beta1, float beta2, float eps, zf_stream_t stream);
 
 const char *zf_status_str(zf_status s);
 const char *zf_last_error(void);

@@ -14,7 +14,9 @@
  *            u32 0, u32 0, u32 header_crc (CRC-32 of bytes [0,60)).
  *   [64, 64+32*n_chunks)  chunk table, one 32-byte entry per chunk:
  *            u64 plain_off, u64 comp_off, u32 plain_len, u32 comp_len,
- *            u32 n_elems, u8 codec, 3 zero bytes.
+ *            u32 n_elems, u8 codec, u8 schedule hint (a tile choice for the
+ *            decoder; the decoded bytes do not depend on it; this encoder
+ *            writes 0), 2 zero bytes.
  *   dictionary (when dict_count > 0) at dict_off = align16(end of table):
  *            dict_count entries of elem_size bytes, sorted ascending and
  *            unique (integers by signed value, FIXED16 by memcmp).

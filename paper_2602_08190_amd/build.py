@@ -18,9 +18,9 @@ GENLIB = os.path.join(HERE, "libzfgen.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-HOST_SRC = ["abi.cpp", "format.cpp", "encode.cpp", "plan.cpp", "run.cpp"]
+HOST_SRC = ["abi.cpp", "format.cpp", "encode.cpp", "plan.cpp", "run.cpp", "tune.cpp", "features.cpp"]
 HIP_SRC = ["k_persistent.hip", "k_for32.hip", "k_dict32.hip", "k_for64.hip", "k_dict64.hip",
-           "k_fp128.hip", "k_gp.hip", "k_np.hip"]
+           "k_fp128.hip", "k_gp.hip", "k_np.hip", "k_mlp.hip"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-I", INCLUDE, "-I", CSRC, "-I", "/opt/rocm/include", "-Wall",
           "-Wno-unused-function", "-Wno-unused-parameter"]
@@ -63,7 +63,7 @@ def build_zf(jobs=None):
         list(ex.map(_run, cmds))
     tmp = LIB + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs +
-         ["-lpthread"])
+         ["-lpthread", "-ldl"])
     os.replace(tmp, LIB)
     return LIB
 

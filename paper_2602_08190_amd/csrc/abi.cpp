@@ -3,6 +3,7 @@
 // leaves its out-parameters untouched on failure.
 #include <memory>
 
+#include "features.hpp"
 #include "plan.hpp"
 
 namespace zf {
@@ -49,6 +50,14 @@ zf_status zf_compress_host(const void *src, uint64_t n_elems, zf_dtype dtype, zf
         auto col = std::make_unique<zf_column>();
         compress_host(src, n_elems, uint32_t(dtype), uint32_t(codec), o, col.get());
         *out = col.release();
+    });
+}
+
+zf_status zf_chunk_features(const void *src, uint64_t n_elems, zf_dtype dtype, float *out) {
+    return guard([&] {
+        ZF_REQUIRE(out && (src || n_elems == 0), ZF_E_INVALID, "null pointer");
+        ZF_REQUIRE(elem_size(uint32_t(dtype)) != 0, ZF_E_INVALID, "unknown dtype %d", int(dtype));
+        chunk_features(src, n_elems, uint32_t(dtype), out);
     });
 }
 

@@ -9,9 +9,11 @@
 #include <functional>
 #include <mutex>
 #include <cmath>
+#include <cstdlib>
 #include <thread>
 #include <type_traits>
 
+#include "features.hpp"
 #include "zf_internal.hpp"
 
 namespace zf {
@@ -500,6 +502,60 @@ void compress_host(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t 
         ZF_REQUIRE(have_dict || !want_dict, ZF_E_UNSUPPORTED, "too many distinct values for DICT_BP");
     }
 
+    // ZF_AUTO with a cost model: predicted (codec, schedule) per chunk
+    std::vector<uint8_t> sched(ce.size(), 0);
+    if (any_auto) {
+        CostModel model;
+        std::string wpath = o.mlp_weights ? o.mlp_weights : "";
+        if (wpath.empty())
+            if (const char *e = std::getenv("ZF_MLP_WEIGHTS")) wpath = e;
+        if (!wpath.empty()) {
+            ZF_REQUIRE(model.load(wpath), ZF_E_INVALID, "cannot read cost model %s", wpath.c_str());
+            std::vector<uint64_t> at(ce.size() + 1, 0);
+            for (size_t i = 0; i < ce.size(); i++) at[i + 1] = at[i] + ce[i];
+            std::vector<int> pick(ce.size(), -1);
+            parallel_for(ce.size(), threads, [&](uint64_t i) {
+                if (cc[i] != 0) return;
+                float x[kFeatures], y[kChoices];
+                chunk_features(src + at[i] * es, ce[i], dtype, x);
+                model.predict(x, y);
+                int best = -1;
+                for (int c = 0; c < kChoices; c++)
+                    if (choice_allowed(uint32_t(c), dtype, uint64_t(ce[i]) * es, have_dict) &&
+                        (best < 0 || y[c] < y[best]))
+                        best = c;
+                pick[i] = best;
+            });
+            std::vector<uint32_t> ce2;
+            std::vector<uint8_t> cc2, sc2;
+            for (size_t i = 0; i < ce.size(); i++) {
+                if (pick[i] < 0) {
+                    ce2.push_back(ce[i]);
+                    cc2.push_back(cc[i]);
+                    sc2.push_back(0);
+                    continue;
+                }
+                const uint8_t codec = kChoiceCodec[pick[i] / 4], s = uint8_t(pick[i] % 4 + 1);
+                if (codec == C_LZ77) {
+                    // LZ77 schedules are chunk sizes: 8, 16, 32 or 64 KiB
+                    const uint64_t per = std::max<uint64_t>(1, (8192ull << (s - 1)) / es);
+                    for (uint64_t a = 0; a < ce[i]; a += per) {
+                        ce2.push_back(uint32_t(std::min<uint64_t>(per, ce[i] - a)));
+                        cc2.push_back(codec);
+                        sc2.push_back(s);
+                    }
+                } else {
+                    ce2.push_back(ce[i]);
+                    cc2.push_back(codec);
+                    sc2.push_back(s);
+                }
+            }
+            ce.swap(ce2);
+            cc.swap(cc2);
+            sched.swap(sc2);
+        }
+    }
+
     // encode
     std::vector<uint64_t> first(ce.size() + 1, 0);
     for (size_t i = 0; i < ce.size(); i++) first[i + 1] = first[i] + ce[i];
@@ -510,6 +566,7 @@ void compress_host(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t 
         const uint8_t *x = src + first[i] * es;
         EncodedChunk &out = chunks[i];
         out.n_elems = ce[i];
+        out.sched = sched[i];
         if (cc[i] != 0) {
             out.codec = cc[i];
             encode_chunk(out.bytes, cc[i], dtype, x, ce[i], &dict, *sc);

@@ -136,6 +136,7 @@ void assemble_column(HostBuf &out, bool pinned, uint32_t dtype, uint64_t n_elems
         wr32(e + 20, uint32_t(c.bytes.size()));
         wr32(e + 24, c.n_elems);
         e[28] = c.codec;
+        e[29] = c.sched;
         plain_off += uint64_t(c.n_elems) * es;
         mixed |= c.codec != chunks[0].codec;
     }
@@ -262,6 +263,8 @@ ColumnView parse_column(const uint8_t *p, uint64_t len) {
         c.comp_len = rd32(e + 20);
         c.n_elems = rd32(e + 24);
         c.codec = e[28];
+        c.sched = e[29];
+        ZF_REQUIRE(c.sched <= 4, ZF_E_CORRUPT, "chunk %u: schedule hint %u", i, c.sched);
         ZF_REQUIRE(c.plain_off == plain && c.n_elems > 0 && uint64_t(c.n_elems) * es == c.plain_len,
                    ZF_E_CORRUPT, "chunk %u: plain range", i);
         ZF_REQUIRE(c.comp_off % 16 == 0 && c.comp_off >= 64 + tl && c.comp_off + c.comp_len <= len,

@@ -41,7 +41,7 @@ hipError_t launch_set_out_tab(uint8_t **d_tab, uint8_t *const *ptrs, uint32_t n,
 
 // Enqueue the decode of one launch's units.  persistent_waves > 0 selects
 // the persistent kernel with that many waves in flight.
-hipError_t launch_decode(const LaunchArgs &A, uint32_t persistent_waves, uint32_t waves_per_block,
+hipError_t launch_decode(const LaunchArgs &A, uint32_t persistent_waves, const uint32_t *wpb,
                          hipStream_t st) {
     if (A.kind_begin[K_COUNT] == 0) return hipSuccess;
     if (persistent_waves) {
@@ -50,16 +50,15 @@ hipError_t launch_decode(const LaunchArgs &A, uint32_t persistent_waves, uint32_
         hipLaunchKernelGGL(k_decode_persistent, dim3(blocks), dim3(256), 0, st, A);
         return hipGetLastError();
     }
-    const uint32_t wpb = waves_per_block ? waves_per_block : 4;
-    launch_lz(A, wpb, st);
-    launch_rle32(A, wpb, st);
-    launch_rle64(A, wpb, st);
-    launch_dict128(A, wpb, st);
-    launch_dict64(A, wpb, st);
-    launch_dict32(A, wpb, st);
-    launch_for64(A, wpb, st);
-    launch_for32(A, wpb, st);
-    launch_plain(A, wpb, st);
+    launch_lz(A, wpb[K_LZ], st);
+    launch_rle32(A, wpb[K_RLE32], st);
+    launch_rle64(A, wpb[K_RLE64], st);
+    launch_dict128(A, wpb[K_DICT128], st);
+    launch_dict64(A, wpb[K_DICT64], st);
+    launch_dict32(A, wpb[K_DICT32], st);
+    launch_for64(A, wpb[K_FOR64], st);
+    launch_for32(A, wpb[K_FOR32], st);
+    launch_plain(A, wpb[K_PLAIN], st);
     return hipGetLastError();
 }
 

@@ -6,16 +6,9 @@
 #include <numeric>
 
 #include "plan.hpp"
+#include "tune.hpp"
 
 namespace zf {
-
-struct TileShape {
-    uint32_t fp_blocks = 2;       // 2 x 2048 values per wave unit
-    uint32_t gp_elems = 4096;     // output elements per GP wave unit
-    uint32_t wpb = 4;             // waves per workgroup
-    uint32_t wpcu = 16;           // persistent waves per CU
-    uint32_t plain_bytes = 65536; // bytes per PLAIN copy unit
-};
 
 // Decode-rate estimates (GB/s of plain output) used only to order batches.
 static double rate_gbps(Kind k) {
@@ -44,10 +37,11 @@ static void add_chunk(WorkTables &w, const zf_column &col, uint32_t ci, uint32_t
     w.chunks.push_back(d);
     const Kind k = kind_of(c.codec, col.view.dtype);
     std::vector<Tile> &T = w.tiles[k];
+    const uint32_t unit = scheduled_unit(k, c.sched, ts.unit[k]);
     switch (k) {
     case K_PLAIN:
-        for (uint64_t a = 0; a < c.plain_len; a += ts.plain_bytes)
-            T.push_back({idx, uint32_t(a), uint32_t(std::min<uint64_t>(c.plain_len, a + ts.plain_bytes)), 0});
+        for (uint64_t a = 0; a < c.plain_len; a += unit)
+            T.push_back({idx, uint32_t(a), uint32_t(std::min<uint64_t>(c.plain_len, a + unit)), 0});
         break;
     case K_FOR32:
     case K_FOR64:
@@ -55,7 +49,7 @@ static void add_chunk(WorkTables &w, const zf_column &col, uint32_t ci, uint32_t
     case K_DICT64:
     case K_DICT128: {
         const uint32_t nb = (c.n_elems + kForBlock - 1) / kForBlock;
-        for (uint32_t b = 0; b < nb; b += ts.fp_blocks) T.push_back({idx, b, std::min(ts.fp_blocks, nb - b), 0});
+        for (uint32_t b = 0; b < nb; b += unit) T.push_back({idx, b, std::min(unit, nb - b), 0});
         break;
     }
     case K_RLE32:
@@ -68,14 +62,14 @@ static void add_chunk(WorkTables &w, const zf_column &col, uint32_t ci, uint32_t
         uint32_t e = 0, g = 0;
         while (e < n) {
             while (g + 1 < ng && gof(g + 1) <= e) g++;
-            const uint64_t target = uint64_t(e) + ts.gp_elems;
+            const uint64_t target = uint64_t(e) + unit;
             uint32_t e_end;
             if (target >= n) {
                 e_end = n;
             } else {
                 uint32_t gb = g + 1;
                 while (gb < ng && gof(gb) < target) gb++;
-                e_end = (gb < ng && gof(gb) <= target + ts.gp_elems) ? gof(gb) : uint32_t(target);
+                e_end = (gb < ng && gof(gb) <= target + unit) ? gof(gb) : uint32_t(target);
             }
             T.push_back({idx, g, e, e_end});
             e = e_end;
@@ -147,17 +141,13 @@ void build_plan(zf_plan_t *P, const zf_column *const *cols, uint32_t n_cols, int
     P->opts = o;
     P->cols.assign(cols, cols + n_cols);
 
-    TileShape ts;
-    if (o.tiles.fp_blocks) ts.fp_blocks = o.tiles.fp_blocks;
-    if (o.tiles.gp_elems) ts.gp_elems = std::max(64u, o.tiles.gp_elems);
-    if (o.tiles.waves_per_block) ts.wpb = std::min(16u, o.tiles.waves_per_block);
-    if (o.tiles.waves_per_cu) ts.wpcu = std::min(32u, o.tiles.waves_per_cu);
+    const TileShape ts = resolve_tiles(o);
 
     DeviceGuard dg(device);
     hipDeviceProp_t prop;
     ZF_HIP(hipGetDeviceProperties(&prop, device));
     P->cu_count = uint32_t(prop.multiProcessorCount);
-    P->waves_per_block = ts.wpb;
+    for (uint32_t k = 0; k < K_COUNT; k++) P->waves_per_block[k] = ts.wpb[k];
     P->persistent_waves = o.persistent ? P->cu_count * ts.wpcu : 0;
 
     // ---- image layout and its tables

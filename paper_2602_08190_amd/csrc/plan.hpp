@@ -7,7 +7,7 @@
 struct zf_plan;
 namespace zf {
 
-hipError_t launch_decode(const LaunchArgs &A, uint32_t persistent_waves, uint32_t waves_per_block,
+hipError_t launch_decode(const LaunchArgs &A, uint32_t persistent_waves, const uint32_t *waves_per_block,
                          hipStream_t st);
 hipError_t launch_set_out_tab(uint8_t **d_tab, uint8_t *const *ptrs, uint32_t n, hipStream_t st);
 
@@ -49,7 +49,7 @@ struct zf_plan {
 
     // launch configuration
     uint32_t persistent_waves = 0;  // 0: per-kind launches
-    uint32_t waves_per_block = 4;
+    uint32_t waves_per_block[zf::K_COUNT] = {4, 4, 4, 4, 4, 4, 4, 4, 4};
     uint32_t cu_count = 0;
 
     // device memory

@@ -84,6 +84,7 @@ struct ChunkInfo {
     uint64_t plain_off, comp_off;
     uint32_t plain_len, comp_len, n_elems;
     uint8_t codec;
+    uint8_t sched;  // schedule hint: 0 = tuned default, 1..4 = chosen granularity
 };
 
 struct ColumnView {
@@ -102,6 +103,7 @@ struct EncodedChunk {
     std::vector<uint8_t> bytes;
     uint32_t n_elems;
     uint8_t codec;
+    uint8_t sched = 0;
 };
 void assemble_column(HostBuf &out, bool pinned, uint32_t dtype, uint64_t n_elems,
                      const std::vector<EncodedChunk> &chunks, const uint8_t *dict,

@@ -32,18 +32,26 @@ class EncodeOpts(ctypes.Structure):
     _fields_ = [("chunk_bytes_min", ctypes.c_uint32), ("chunk_bytes_max", ctypes.c_uint32),
                 ("seed", ctypes.c_uint64), ("n_threads", ctypes.c_int32),
                 ("pinned", ctypes.c_int32), ("chunk_elems", ctypes.c_void_p),
-                ("n_chunk_elems", ctypes.c_uint32), ("chunk_codecs", ctypes.c_void_p)]
+                ("n_chunk_elems", ctypes.c_uint32), ("chunk_codecs", ctypes.c_void_p),
+                ("mlp_weights", ctypes.c_char_p)]
 
 
-class Tiles(ctypes.Structure):
-    _fields_ = [("fp_blocks", ctypes.c_uint32), ("gp_elems", ctypes.c_uint32),
-                ("waves_per_block", ctypes.c_uint32), ("waves_per_cu", ctypes.c_uint32)]
+# kernel kinds (zf_kind), in enum order
+KINDS = ["LZ77", "RLE64", "RLE32", "DICT128", "DICT64", "DICT32", "FOR64", "FOR32", "PLAIN"]
+KIND_GROUPS = {"FP": ["FOR32", "FOR64", "DICT32", "DICT64", "DICT128"], "GP": ["RLE32", "RLE64"],
+               "NP": ["LZ77"]}
+
+
+class Tile(ctypes.Structure):
+    _fields_ = [("unit", ctypes.c_uint32), ("waves_per_block", ctypes.c_uint32)]
 
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("slot_bytes", ctypes.c_uint64), ("n_slots", ctypes.c_int32),
                 ("use_graphs", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("order", ctypes.c_int32), ("pcie_gbps", ctypes.c_double), ("tiles", Tiles)]
+                ("order", ctypes.c_int32), ("pcie_gbps", ctypes.c_double),
+                ("tiles", Tile * len(KINDS)), ("waves_per_cu", ctypes.c_uint32),
+                ("tune_cache", ctypes.c_char_p)]
 
 
 class Timing(ctypes.Structure):
@@ -62,6 +70,7 @@ SIGNATURES = {
     "zf_compress_host": (_i32, [_vp, _u64, _i32, _i32, ctypes.POINTER(EncodeOpts),
                                 ctypes.POINTER(_vp)]),
     "zf_column_from_bytes": (_i32, [_vp, _u64, _i32, ctypes.POINTER(_vp)]),
+    "zf_chunk_features": (_i32, [_vp, _u64, _i32, _vp]),
     "zf_column_bytes": (_vp, [_vp, ctypes.POINTER(_u64)]),
     "zf_column_plain_bytes": (_u64, [_vp]),
     "zf_column_n_elems": (_u64, [_vp]),
@@ -79,6 +88,11 @@ SIGNATURES = {
                                           ctypes.POINTER(Timing)]),
     "zf_sync": (_i32, [_vp, _vp]),
     "zf_plan_clear_error": (None, [_vp]),
+    "zf_mlp_forward": (_i32, [_vp, _vp, _u32, _vp, _vp]),
+    "zf_mlp_grad_work_bytes": (_u64, [_u32]),
+    "zf_mlp_grad": (_i32, [_vp, _vp, _vp, _vp, _u32, _vp, _vp, _vp, _u64, _vp]),
+    "zf_mlp_adam": (_i32, [_vp, _vp, _vp, _vp, _u32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                           ctypes.c_float, _vp]),
     "zf_status_str": (ctypes.c_char_p, [_i32]),
     "zf_last_error": (ctypes.c_char_p, []),
 }
@@ -128,7 +142,7 @@ class Column:
 
     @classmethod
     def compress(cls, x, codec, chunk_elems=None, chunk_codecs=None, chunk_bytes=None, seed=0,
-                 threads=0, pinned=True):
+                 threads=0, pinned=True, mlp_weights=None):
         x = np.ascontiguousarray(x)
         o = EncodeOpts()
         lib().zf_encode_opts_default(ctypes.byref(o))
@@ -136,6 +150,9 @@ class Column:
         o.n_threads = threads
         o.seed = seed
         keep = []
+        if mlp_weights is not None:
+            keep.append(mlp_weights.encode())
+            o.mlp_weights = keep[-1]
         if chunk_bytes is not None:
             o.chunk_bytes_min, o.chunk_bytes_max = chunk_bytes
         if chunk_elems is not None:
@@ -201,6 +218,14 @@ class Column:
             pass
 
 
+def chunk_features(x):
+    """The 32 cost-model statistics of a chunk (numpy column)."""
+    x = np.ascontiguousarray(x)
+    out = np.zeros(32, np.float32)
+    _check(lib().zf_chunk_features(x.ctypes.data, x.shape[0], dtype_of(x), out.ctypes.data))
+    return out
+
+
 def _ptr(x):
     """Device pointer of a torch tensor, or an int."""
     if x is None:
@@ -223,7 +248,10 @@ class Plan:
     """Work tables, batches and device workspace for decoding `cols`."""
 
     def __init__(self, cols, device=0, slot_bytes=256 << 20, n_slots=2, use_graphs=True,
-                 persistent=False, order=0, pcie_gbps=0.0, tiles=None):
+                 persistent=False, order=0, pcie_gbps=0.0, tiles=None, waves_per_cu=0,
+                 tune_cache=None):
+        """tiles: {kind or group name: {"unit": u, "waves_per_block": w}}, where a
+        kind is one of KINDS and a group one of KIND_GROUPS."""
         self.cols = list(cols)
         o = PlanOpts()
         lib().zf_plan_opts_default(ctypes.byref(o))
@@ -233,9 +261,14 @@ class Plan:
         o.persistent = 1 if persistent else 0
         o.order = order
         o.pcie_gbps = pcie_gbps
-        if tiles:
-            for k, v in tiles.items():
-                setattr(o.tiles, k, v)
+        for name, shape in (tiles or {}).items():
+            for kind in KIND_GROUPS.get(name, [name]):
+                t = o.tiles[KINDS.index(kind)]
+                t.unit = shape.get("unit", 0)
+                t.waves_per_block = shape.get("waves_per_block", 0)
+        o.waves_per_cu = waves_per_cu
+        self._tune = tune_cache.encode() if tune_cache else None
+        o.tune_cache = self._tune
         arr = (ctypes.c_void_p * len(self.cols))(*[c.handle.value for c in self.cols])
         h = ctypes.c_void_p()
         _check(lib().zf_plan(arr, len(self.cols), device, ctypes.byref(o), ctypes.byref(h)))
@@ -279,6 +312,24 @@ class Plan:
             pass
 
 
+def kind_of_column(col):
+    """Kernel kind of a single-codec column (its first chunk's codec)."""
+    b = col.bytes()[:96]
+    if col.n_chunks == 0:
+        return "PLAIN"
+    codec = b[64 + 28]
+    dt = col.dtype
+    if codec == PLAIN:
+        return "PLAIN"
+    if codec == LZ77:
+        return "LZ77"
+    if codec in (DELTA_BP, RLE_DELTA_BP):
+        return "RLE32" if dt == I32 else "RLE64"
+    if codec == DICT_BP:
+        return {I32: "DICT32", I64: "DICT64", FIXED16: "DICT128"}[dt]
+    return "FOR32" if dt == I32 else "FOR64"
+
+
 # ---------------------------------------------------------- torch helpers
 def torch_dtype_shape(col):
     """(torch dtype, shape) of a decoded column."""
@@ -312,3 +363,26 @@ def upload_image(plan, cols, device="cuda"):
         off = plan.image_offset(i)
         img[off:off + b.numel()].copy_(b)
     return img
+
+
+# ------------------------------------------------------------ cost model
+MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 32, 64, 24, 7832
+
+
+def mlp_forward(params, x, y, stream=None):
+    _check(lib().zf_mlp_forward(_ptr(params), _ptr(x), x.shape[0], _ptr(y), _stream(stream)))
+
+
+def mlp_grad_work_bytes(n):
+    return lib().zf_mlp_grad_work_bytes(n)
+
+
+def mlp_grad(params, x, k, t, grad, loss, work, stream=None):
+    _check(lib().zf_mlp_grad(_ptr(params), _ptr(x), _ptr(k), _ptr(t), x.shape[0], _ptr(grad),
+                             _ptr(loss), _ptr(work), work.numel() * work.element_size(),
+                             _stream(stream)))
+
+
+def mlp_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(lib().zf_mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), step, lr, beta1, beta2, eps,
+                             _stream(stream)))

@@ -93,7 +93,7 @@ def test_for_bp_config1_tiles(fp_blocks):
     log("config1 tiles", fp_blocks)
     x = g.for_bp_column()
     cols = [zf.Column.compress(x, zf.FOR_BP, chunk_elems=[1 << 20])]
-    check(cols, decode_image(cols, tiles=dict(fp_blocks=fp_blocks)), [x])
+    check(cols, decode_image(cols, tiles={"FOR32": dict(unit=fp_blocks)}), [x])
 
 
 def test_for_bp_unaligned_chunks():
@@ -142,8 +142,8 @@ def test_rle_families_and_tiles(gp_elems):
             x = x * np.int64(1 << 40) - (1 << 60)
         xs.append(x)
         cols.append(zf.Column.compress(x, zf.RLE_DELTA_BP, chunk_elems=[16384, 16384, 70000 - 32768]))
-    check(cols, decode_image(cols, tiles=dict(gp_elems=gp_elems)), xs)
-    check(cols, decode_image(cols, persistent=False, tiles=dict(gp_elems=gp_elems)), xs)
+    check(cols, decode_image(cols, tiles={"GP": dict(unit=gp_elems)}), xs)
+    check(cols, decode_image(cols, persistent=True, tiles={"GP": dict(unit=gp_elems, waves_per_block=8)}), xs)
 
 
 def test_rle_and_delta_extremes():
@@ -178,7 +178,7 @@ def test_lz77_text_product_streams():
     tail = g.text_column(65536 * 3 + 777, seed=3)
     cols.append(zf.Column.compress(tail, zf.LZ77))
     check(cols, decode_image(cols), [x, tail])
-    check(cols, decode_image(cols, persistent=False), [x, tail])
+    check(cols, decode_image(cols, persistent=True), [x, tail])
 
 
 def test_lz77_oracle_streams_use_the_ordered_path():
@@ -206,7 +206,7 @@ def test_lz77_random_valid_streams():
     blob = H.container(zf.BYTES, chunks)
     cols = [zf.Column.from_bytes(blob)]
     check(cols, decode_image(cols))
-    check(cols, decode_image(cols, persistent=False))
+    check(cols, decode_image(cols, persistent=True))
 
 
 def test_lz77_int_columns():
@@ -231,7 +231,7 @@ def mixed_columns():
 
 
 @pytest.mark.parametrize("kw", [dict(), dict(n_slots=1), dict(n_slots=3, use_graphs=False),
-                                dict(persistent=False), dict(order=1)])
+                                dict(persistent=True), dict(order=1)])
 def test_transfer_and_decompress(kw):
     log("staged", kw)
     xs, cols = mixed_columns()
