@@ -573,6 +573,19 @@ struct LzSeq {
     uint32_t off[64];
 };
 
+// Extension words e0 + lane and e0 + 64 + lane (0 past the array), packed.
+ZF_DEV uint32_t ext_window(const uint16_t *ext, uint32_t e0, uint32_t next, uint32_t lane) {
+    const uint32_t lo = e0 + lane < next ? ext[e0 + lane] : 0u;
+    const uint32_t hi = e0 + 64 + lane < next ? ext[e0 + 64 + lane] : 0u;
+    return lo | (hi << 16);
+}
+
+// Entry k (0..127) of a window; every lane of the wave must take part.
+ZF_DEV uint32_t ext_pick(uint32_t ew, uint32_t k) {
+    const uint32_t v = uint32_t(__builtin_amdgcn_ds_bpermute(int((k & 63u) * 4u), int(ew)));
+    return (k & 64u) ? v >> 16 : v & 0xFFFFu;
+}
+
 // One wave decodes one whole LZ77 chunk.
 ZF_DEV void unit_lz(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, LzSeq &tab) {
     const uint8_t *s = A.comp + ck.comp_off;
@@ -599,6 +612,11 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, LzS
     uint32_t pos = 0, lp = 0, ep = 0;
     uint32_t tag = lane < nseq ? tags[lane] : 0u;
     uint32_t off = lane < nseq ? offs[lane] : 0u;
+    // A batch uses at most 128 extension words, starting at ep: they are
+    // loaded one batch ahead as a 128-entry window, two u16 per lane
+    // (entry k in lane k % 64, low half for k < 64), and read with cross-lane
+    // permutes, so no load sits on the parse's critical path.
+    uint32_t ew = ext_window(ext, 0, next, lane);
     for (uint32_t base = 0; base < nseq; base += 64) {
         const uint32_t i = base + lane;
         const bool act = i < nseq;
@@ -615,9 +633,12 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, LzS
             flag(A.err, ERR_CORRUPT);
             return;
         }
+        const uint32_t k1 = eex - ep, k2 = k1 + (lc == 7u);
+        const uint32_t x1 = ext_pick(ew, k1), x2 = ext_pick(ew, k2);
+        ew = ext_window(ext, ep + etot, next, lane);  // next batch's window
         uint32_t ll = lc, ml = 0;
-        if (lc == 7u) ll = 7u + ext[eex];
-        if (mc == 31u) ml = 34u + ext[eex + (lc == 7u)];
+        if (lc == 7u) ll = 7u + x1;
+        if (mc == 31u) ml = 34u + x2;
         else if (mc) ml = mc + 3u;
         const uint32_t len = ll + ml;
         const uint32_t pincl = scan_add32(len), lincl = scan_add32(ll);

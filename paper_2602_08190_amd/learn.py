@@ -176,8 +176,9 @@ def collect(cols, out_path, check=True, chunk_bytes=CHUNK_BYTES, chunks_per_col=
             S.append(sizes)
             ids.append((i, j))
         log(f"column {i} ({p['fam']}) done, {time.time() - t0:.0f}s")
-    np.savez(out_path, X=np.array(X, np.float32), T=np.array(T), S=np.array(S),
-             ids=np.array(ids, np.int32), fam=np.array([family_of(i) for i, _ in ids]))
+        # written after every column, so a cut-off run keeps what it measured
+        np.savez(out_path, X=np.array(X, np.float32), T=np.array(T), S=np.array(S),
+                 ids=np.array(ids, np.int32), fam=np.array([family_of(i) for i, _ in ids]))
 
 
 # ----------------------------------------------------------------- train
