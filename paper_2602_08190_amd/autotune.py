@@ -32,11 +32,11 @@ UNITS = {
     "FP": [1, 2, 4, 8, 16],                  # L: 2048-value blocks per wave
     "GP": [512, 1024, 2048, 4096, 8192, 16384],
     "PLAIN": [16384, 65536, 262144, 1048576],
-    "NP": [0],                               # one chunk per wave, no unit knob
+    "NP": [16, 32, 64],                      # lanes per chunk (4, 2, 1 chunks per wave)
 }
 GROUP = {"FOR32": "FP", "FOR64": "FP", "DICT32": "FP", "DICT64": "FP", "DICT128": "FP",
          "RLE32": "GP", "RLE64": "GP", "LZ77": "NP", "PLAIN": "PLAIN"}
-DEFAULT = {"FP": 2, "GP": 4096, "PLAIN": 65536, "NP": 0}
+DEFAULT = {"FP": 2, "GP": 4096, "PLAIN": 65536, "NP": 64}
 
 
 def log(*a):

@@ -42,7 +42,7 @@ hipError_t launch_set_out_tab(uint8_t **d_tab, uint8_t *const *ptrs, uint32_t n,
 // Enqueue the decode of one launch's units.  persistent_waves > 0 selects
 // the persistent kernel with that many waves in flight.
 hipError_t launch_decode(const LaunchArgs &A, uint32_t persistent_waves, const uint32_t *wpb,
-                         hipStream_t st) {
+                         uint32_t lz_lanes, hipStream_t st) {
     if (A.kind_begin[K_COUNT] == 0) return hipSuccess;
     if (persistent_waves) {
         hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, st, A.counter);
@@ -50,7 +50,7 @@ hipError_t launch_decode(const LaunchArgs &A, uint32_t persistent_waves, const u
         hipLaunchKernelGGL(k_decode_persistent, dim3(blocks), dim3(256), 0, st, A);
         return hipGetLastError();
     }
-    launch_lz(A, wpb[K_LZ], st);
+    launch_lz(A, wpb[K_LZ], lz_lanes, st);
     launch_rle32(A, wpb[K_RLE32], st);
     launch_rle64(A, wpb[K_RLE64], st);
     launch_dict128(A, wpb[K_DICT128], st);

@@ -566,41 +566,84 @@ ZF_DEV void unit_rle(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck) {
 }
 
 // ======================================================== Non-Parallel
+// A chunk is decoded by a group of G lanes (G = 16, 32 or 64: a DPP row, two
+// rows, or the whole wave), so one wave has 64/G chunks in flight.  The parse
+// of a batch is a short chain of dependent steps (header scans, then one
+// round of source loads); with several chunks per wave those chains overlap.
+//
+// Group primitives.  Groups are aligned to DPP rows, and every lane of a
+// group follows the same control flow, so lane moves never leave the group.
+template <uint32_t G>
+ZF_DEV uint32_t gscan(uint32_t x) {
+    x += dpp<0x111, 0xF>(x);   // row_shr:1
+    x += dpp<0x112, 0xF>(x);   // row_shr:2
+    x += dpp<0x114, 0xF>(x);   // row_shr:4
+    x += dpp<0x118, 0xF>(x);   // row_shr:8
+    if constexpr (G >= 32) x += dpp<0x142, 0xA>(x);  // row_bcast:15
+    if constexpr (G == 64) x += dpp<0x143, 0xC>(x);  // row_bcast:31
+    return x;
+}
+// Value of x in lane k of this lane's group.
+template <uint32_t G>
+ZF_DEV uint32_t gread(uint32_t x, uint32_t k) {
+    if constexpr (G == 64) return rl32(x, k);
+    else return uint32_t(__builtin_amdgcn_ds_bpermute(int(((lane_id() & ~(G - 1)) + k) * 4), int(x)));
+}
+template <uint32_t G>
+ZF_DEV bool gany(bool p) {
+    const uint64_t b = __ballot(p);
+    if constexpr (G == 64) return b != 0;
+    else return ((b >> (lane_id() & ~(G - 1))) & ((1ull << G) - 1)) != 0;
+}
+
 // Per-wave table of the current batch's sequences (LDS): output start P,
-// literal end D, sequence end E, literal start LP, and the match offset.
+// literal end D, sequence end E, literal start LP, and the match offset.  A
+// group of G lanes owns entries [group base, group base + G).
 struct LzSeq {
     uint4 pdel[64];   // {P, D, E, LP}
     uint32_t off[64];
 };
 
-// Extension words e0 + lane and e0 + 64 + lane (0 past the array), packed.
-ZF_DEV uint32_t ext_window(const uint16_t *ext, uint32_t e0, uint32_t next, uint32_t lane) {
-    const uint32_t lo = e0 + lane < next ? ext[e0 + lane] : 0u;
-    const uint32_t hi = e0 + 64 + lane < next ? ext[e0 + 64 + lane] : 0u;
+// Extension words e0 + g and e0 + G + g (0 past the array), packed.
+template <uint32_t G>
+ZF_DEV uint32_t ext_window(const uint16_t *ext, uint32_t e0, uint32_t next, uint32_t g) {
+    const uint32_t lo = e0 + g < next ? ext[e0 + g] : 0u;
+    const uint32_t hi = e0 + G + g < next ? ext[e0 + G + g] : 0u;
     return lo | (hi << 16);
 }
 
-// Entry k (0..127) of a window; every lane of the wave must take part.
+// Entry k (0 .. 2G-1) of a window; every lane of the group must take part.
+template <uint32_t G>
 ZF_DEV uint32_t ext_pick(uint32_t ew, uint32_t k) {
-    const uint32_t v = uint32_t(__builtin_amdgcn_ds_bpermute(int((k & 63u) * 4u), int(ew)));
-    return (k & 64u) ? v >> 16 : v & 0xFFFFu;
+    const uint32_t v = uint32_t(__builtin_amdgcn_ds_bpermute(
+        int(((lane_id() & ~(G - 1)) + (k & (G - 1))) * 4), int(ew)));
+    return (k & G) ? v >> 16 : v & 0xFFFFu;
 }
 
-// One wave decodes one whole LZ77 chunk.
-ZF_DEV void unit_lz(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, LzSeq &tab) {
+// The G lanes of this lane's group decode one whole LZ77 chunk.  Lane g
+// holds sequence g of a batch of G; group scans give every sequence's output
+// position, literal position and extension index.  A batch uses at most 2G
+// extension words, loaded one batch ahead as a window held two per lane and
+// read with cross-lane permutes, so no load sits on the parse's critical
+// path except the copy sources themselves.
+template <uint32_t G>
+ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, LzSeq &tab) {
     const uint8_t *s = A.comp + ck.comp_off;
-    const uint32_t clen = ck.comp_len, lane = lane_id();
+    const uint32_t clen = ck.comp_len, g = lane_id() & (G - 1), gb = lane_id() & ~(G - 1);
     const uint32_t es = ck.dtype == D_I32 ? 4 : ck.dtype == D_I64 ? 8 : ck.dtype == D_FIXED16 ? 16 : 1;
     const uint32_t plain = ck.n_elems * es;
     uint8_t *out = A.out_tab[ck.col] + ck.out_off;
+    auto corrupt = [&]() {
+        if (g == 0) atomicOr(A.err, ERR_CORRUPT);
+    };
     if (clen < 16) {
-        flag(A.err, ERR_CORRUPT);
+        corrupt();
         return;
     }
     const uint32_t nseq = ld32u(s), nlit = ld32u(s + 4), next = ld32u(s + 8), plen = ld32u(s + 12);
     if (plen != plain || plain > kLzMaxChunk ||
         16ull + 3ull * nseq + 2ull * next + nlit != uint64_t(clen)) {
-        flag(A.err, ERR_CORRUPT);
+        corrupt();
         return;
     }
     const uint16_t *offs = reinterpret_cast<const uint16_t *>(s + 16);
@@ -610,71 +653,68 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, LzS
     // misalignment of the chunk's output, for 16-byte aligned stores
     const uint32_t mis = uint32_t(reinterpret_cast<uintptr_t>(out) & 15u);
     uint32_t pos = 0, lp = 0, ep = 0;
-    uint32_t tag = lane < nseq ? tags[lane] : 0u;
-    uint32_t off = lane < nseq ? offs[lane] : 0u;
-    // A batch uses at most 128 extension words, starting at ep: they are
-    // loaded one batch ahead as a 128-entry window, two u16 per lane
-    // (entry k in lane k % 64, low half for k < 64), and read with cross-lane
-    // permutes, so no load sits on the parse's critical path.
-    uint32_t ew = ext_window(ext, 0, next, lane);
-    for (uint32_t base = 0; base < nseq; base += 64) {
-        const uint32_t i = base + lane;
+    uint32_t tag = g < nseq ? tags[g] : 0u;
+    uint32_t off = g < nseq ? offs[g] : 0u;
+    uint32_t ew = ext_window<G>(ext, 0, next, g);
+    for (uint32_t base = 0; base < nseq; base += G) {
+        const uint32_t i = base + g;
         const bool act = i < nseq;
         // prefetch the next batch's headers
-        const uint32_t ni = i + 64;
+        const uint32_t ni = i + G;
         const uint32_t ntag = ni < nseq ? tags[ni] : 0u;
         const uint32_t noff = ni < nseq ? offs[ni] : 0u;
 
         const uint32_t lc = tag & 7u, mc = tag >> 3;
         const uint32_t ne = (lc == 7u) + (mc == 31u);
-        const uint32_t eincl = scan_add32(ne);
-        const uint32_t eex = ep + eincl - ne, etot = rl32(eincl, 63);
+        const uint32_t eincl = gscan<G>(ne);
+        const uint32_t eex = ep + eincl - ne, etot = gread<G>(eincl, G - 1);
         if (uint64_t(ep) + etot > next) {
-            flag(A.err, ERR_CORRUPT);
+            corrupt();
             return;
         }
         const uint32_t k1 = eex - ep, k2 = k1 + (lc == 7u);
-        const uint32_t x1 = ext_pick(ew, k1), x2 = ext_pick(ew, k2);
-        ew = ext_window(ext, ep + etot, next, lane);  // next batch's window
+        const uint32_t x1 = ext_pick<G>(ew, k1), x2 = ext_pick<G>(ew, k2);
+        ew = ext_window<G>(ext, ep + etot, next, g);  // next batch's window
         uint32_t ll = lc, ml = 0;
         if (lc == 7u) ll = 7u + x1;
         if (mc == 31u) ml = 34u + x2;
         else if (mc) ml = mc + 3u;
         const uint32_t len = ll + ml;
-        const uint32_t pincl = scan_add32(len), lincl = scan_add32(ll);
+        const uint32_t pincl = gscan<G>(len), lincl = gscan<G>(ll);
         const uint32_t P = pos + pincl - len, LP = lp + lincl - ll;
-        const uint32_t total = rl32(pincl, 63), ltot = rl32(lincl, 63);
+        const uint32_t total = gread<G>(pincl, G - 1), ltot = gread<G>(lincl, G - 1);
         const uint32_t D = P + ll;
         const bool bad = act && (uint64_t(P) + len > plain || uint64_t(LP) + ll > nlit ||
                                  (ml == 0 ? off != 0 : (off == 0 || off > D)));
-        if (any(bad)) {
-            flag(A.err, ERR_CORRUPT);
+        if (gany<G>(bad)) {
+            corrupt();
             return;
         }
         const uint32_t q0 = D - off;  // first source byte of the match
         const bool flat = ml == 0 || q0 + min(ml, off) <= pos || q0 >= P;
-        const uint32_t cnt = min(64u, nseq - base);
+        const uint32_t cnt = min(G, nseq - base);
         const uint32_t end = pos + total;
-        if (!any(!flat)) {
+        if (!gany<G>(!flat)) {
             // Flat batch: every byte's source is final before the batch starts
             // (earlier output) or is a literal of the same sequence.  Each lane
             // owns one 16-byte aligned block of the batch's output at a time.
-            tab.pdel[lane] = make_uint4(P, D, P + len, LP);
-            tab.off[lane] = off;
+            tab.pdel[gb + g] = make_uint4(P, D, P + len, LP);
+            tab.off[gb + g] = off;
             wave_fence();
-            for (int32_t B = int32_t(pos) - int32_t((mis + pos) & 15u) + int32_t(16 * lane);
-                 B < int32_t(end); B += 1024) {
+            for (int32_t B = int32_t(pos) - int32_t((mis + pos) & 15u) + int32_t(16 * g);
+                 B < int32_t(end); B += int32_t(16 * G)) {
                 const uint32_t p0 = uint32_t(max(B, int32_t(pos)));
                 const uint32_t pe = min(uint32_t(B + 16), end);
                 // sequence holding p0: the last one with P <= p0
                 uint32_t lo = 0, hi = cnt;
                 while (hi - lo > 1) {
                     const uint32_t mid = (lo + hi) >> 1;
-                    if (tab.pdel[mid].x <= p0) lo = mid;
+                    if (tab.pdel[gb + mid].x <= p0) lo = mid;
                     else hi = mid;
                 }
-                uint4 r = tab.pdel[lo];
-                uint32_t so = tab.off[lo], sidx = lo;
+                uint32_t sidx = gb + lo;
+                uint4 r = tab.pdel[sidx];
+                uint32_t so = tab.off[sidx];
                 // phase 1: where each byte comes from (bit 31 set: a literal)
                 uint32_t src[16];
 #pragma unroll
@@ -723,14 +763,14 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, LzS
         } else {
             // in-order replay of this batch
             for (uint32_t k = 0; k < cnt; k++) {
-                const uint32_t Pk = rl32(P, k), llk = rl32(ll, k), LPk = rl32(LP, k);
-                const uint32_t mlk = rl32(ml, k), offk = rl32(off, k), Dk = Pk + llk;
-                for (uint32_t x = lane; x < llk; x += 64) out[Pk + x] = lits[LPk + x];
+                const uint32_t Pk = gread<G>(P, k), llk = gread<G>(ll, k), LPk = gread<G>(LP, k);
+                const uint32_t mlk = gread<G>(ml, k), offk = gread<G>(off, k), Dk = Pk + llk;
+                for (uint32_t x = g; x < llk; x += G) out[Pk + x] = lits[LPk + x];
                 wave_fence();
-                const uint32_t step = min(offk, 64u);
+                const uint32_t step = min(offk, G);
                 for (uint32_t j0 = 0; j0 < mlk; j0 += step) {
-                    const uint32_t j = j0 + lane;
-                    if (lane < step && j < mlk) out[Dk + j] = out[Dk - offk + j];
+                    const uint32_t j = j0 + g;
+                    if (g < step && j < mlk) out[Dk + j] = out[Dk - offk + j];
                     wave_fence();
                 }
             }
@@ -741,7 +781,7 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, LzS
         tag = ntag;
         off = noff;
     }
-    if (pos != plain || lp != nlit || ep != next) flag(A.err, ERR_CORRUPT);
+    if (pos != plain || lp != nlit || ep != next) corrupt();
 }
 
 // ================================================================ PLAIN
@@ -788,7 +828,7 @@ ZF_DEV void run_unit(const LaunchArgs &A, uint32_t kind, uint32_t u, LzSeq *tab)
     case K_DICT128: unit_fp<16, true, UNR>(A, t, ck); break;
     case K_RLE32: unit_rle<uint32_t>(A, t, ck); break;
     case K_RLE64: unit_rle<uint64_t>(A, t, ck); break;
-    case K_LZ: unit_lz(A, t, ck, *tab); break;
+    case K_LZ: unit_lz<64>(A, ck, *tab); break;
     }
 }
 
@@ -801,10 +841,7 @@ __global__ __launch_bounds__(1024) void k_decode_kind(LaunchArgs A) {
     if (u >= A.kind_begin[KIND + 1]) return;
     const Tile t = A.tiles[u];
     const ChunkDesc ck = A.chunks[t.chunk];
-    if constexpr (KIND == K_LZ) {
-        __shared__ LzSeq tab[16];
-        unit_lz(A, t, ck, tab[threadIdx.x / 64]);
-    } else if constexpr (KIND == K_PLAIN) {
+    if constexpr (KIND == K_PLAIN) {
         unit_plain(A, t, ck);
     } else if constexpr (KIND == K_FOR32) {
         unit_fp<4, false, 8>(A, t, ck);
@@ -823,9 +860,21 @@ __global__ __launch_bounds__(1024) void k_decode_kind(LaunchArgs A) {
     }
 }
 
+// LZ77: each wave takes 64/G consecutive units, one per group of G lanes.
+template <uint32_t G>
+__global__ __launch_bounds__(1024) void k_decode_lz(LaunchArgs A) {
+    const uint32_t waves = blockDim.x / 64;
+    const uint32_t w = blockIdx.x * waves + first32(threadIdx.x / 64);
+    const uint32_t u = A.kind_begin[K_LZ] + w * (64 / G) + (G == 64 ? 0u : lane_id() / G);
+    if (u >= A.kind_begin[K_LZ + 1]) return;
+    __shared__ LzSeq tab[16];
+    unit_lz<G>(A, A.chunks[A.tiles[u].chunk], tab[threadIdx.x / 64]);
+}
+void launch_lz(const LaunchArgs &A, uint32_t waves, uint32_t lanes, hipStream_t st);
+
 // Host launchers, one per kind, each defined in its kind's translation unit.
 #define ZF_KIND_LAUNCHERS(X)                                                                       \
-    X(K_LZ, launch_lz) X(K_RLE64, launch_rle64) X(K_RLE32, launch_rle32)                           \
+    X(K_RLE64, launch_rle64) X(K_RLE32, launch_rle32)                           \
     X(K_DICT128, launch_dict128) X(K_DICT64, launch_dict64) X(K_DICT32, launch_dict32)              \
     X(K_FOR64, launch_for64) X(K_FOR32, launch_for32) X(K_PLAIN, launch_plain)
 #define ZF_DECLARE_LAUNCHER(KIND, NAME) void NAME(const LaunchArgs &A, uint32_t waves, hipStream_t st);

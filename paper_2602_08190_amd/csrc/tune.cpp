@@ -95,7 +95,7 @@ const char *kind_name(uint32_t k) { return k < K_COUNT ? kKindNames[k] : "?"; }
 TileShape default_tiles() {
     TileShape t;
     for (uint32_t k = 0; k < K_COUNT; k++) {
-        t.unit[k] = (k == K_PLAIN) ? 65536u : (k == K_RLE32 || k == K_RLE64) ? 4096u : 2u;
+        t.unit[k] = (k == K_PLAIN) ? 65536u : (k == K_RLE32 || k == K_RLE64) ? 4096u : (k == K_LZ) ? 64u : 2u;
         t.wpb[k] = 4;
     }
     t.wpcu = 16;
@@ -169,6 +169,8 @@ TileShape resolve_tiles(const zf_plan_opts &o) {
     t.unit[K_RLE32] = std::max(64u, t.unit[K_RLE32]);
     t.unit[K_RLE64] = std::max(64u, t.unit[K_RLE64]);
     t.unit[K_PLAIN] = std::max(1024u, t.unit[K_PLAIN]);
+    // LZ77: lanes per chunk, one of 16, 32, 64
+    t.unit[K_LZ] = t.unit[K_LZ] <= 16 ? 16u : t.unit[K_LZ] <= 32 ? 32u : 64u;
     return t;
 }
 

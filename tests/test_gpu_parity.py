@@ -171,32 +171,43 @@ def test_rle_config2_shape():
 
 
 # -------------------------------------------------------------- NP codec
-def test_lz77_text_product_streams():
-    log("lz text")
+# lanes per chunk of the per-kind LZ77 kernel: 4, 2 or 1 chunks per wave
+LZ_LANES = [16, 32, 64]
+
+
+def lz_tiles(lanes):
+    return {"LZ77": dict(unit=lanes)}
+
+
+@pytest.mark.parametrize("lanes", LZ_LANES)
+def test_lz77_text_product_streams(lanes):
+    log("lz text", lanes)
     x = g.text_column(3 << 20, seed=2)
     cols = [zf.Column.compress(x, zf.LZ77)]
     tail = g.text_column(65536 * 3 + 777, seed=3)
     cols.append(zf.Column.compress(tail, zf.LZ77))
-    check(cols, decode_image(cols), [x, tail])
+    check(cols, decode_image(cols, tiles=lz_tiles(lanes)), [x, tail])
     check(cols, decode_image(cols, persistent=True), [x, tail])
 
 
-def test_lz77_oracle_streams_use_the_ordered_path():
+@pytest.mark.parametrize("lanes", LZ_LANES)
+def test_lz77_oracle_streams_use_the_ordered_path(lanes):
     """The oracle's greedy encoder does not keep batches flat, so these
     streams take the in-order replay path."""
-    log("lz oracle streams")
+    log("lz oracle streams", lanes)
     x = g.text_column(1 << 20, seed=4)
     blob = zo.encode(x, zo.LZ77, [65536] * 16)
     y = np.frombuffer(b"ab" * 30000 + b"abcabcabc" * 1000, np.uint8)
     blob2 = zo.encode(y, zo.LZ77, [65536, len(y) - 65536])
     cols = [zf.Column.from_bytes(blob), zf.Column.from_bytes(blob2)]
-    check(cols, decode_image(cols), [x, y])
+    check(cols, decode_image(cols, tiles=lz_tiles(lanes)), [x, y])
 
 
-def test_lz77_random_valid_streams():
+@pytest.mark.parametrize("lanes", LZ_LANES)
+def test_lz77_random_valid_streams(lanes):
     """Random valid streams the encoders never write: self-overlapping
     matches, offsets into the same batch, long escapes, ragged chunk sizes."""
-    log("lz random streams")
+    log("lz random streams", lanes)
     r = np.random.default_rng(11)
     chunks = []
     for i in range(24):
@@ -205,15 +216,50 @@ def test_lz77_random_valid_streams():
         chunks.append((H.lz_stream(seqs, lits, plen), plen, zf.LZ77))
     blob = H.container(zf.BYTES, chunks)
     cols = [zf.Column.from_bytes(blob)]
-    check(cols, decode_image(cols))
+    check(cols, decode_image(cols, tiles=lz_tiles(lanes)))
     check(cols, decode_image(cols, persistent=True))
 
 
-def test_lz77_int_columns():
-    log("lz ints")
+def _chunk_streams(blob):
+    return [(blob[c["comp_off"]:c["comp_off"] + c["comp_len"]].tobytes(), c["n_elems"], zf.LZ77)
+            for c in zo.chunks(blob)]
+
+
+@pytest.mark.parametrize("lanes", LZ_LANES)
+def test_lz77_groups_of_one_wave_diverge(lanes):
+    """Neighbouring chunks (decoded by the groups of one wave) alternate
+    between flat product streams, replayed oracle streams and tiny chunks,
+    and the chunk count leaves the last wave partly empty."""
+    log("lz divergent groups", lanes)
+    x = g.text_column(9 * 65536, seed=8)
+    prod = _chunk_streams(zf.Column.compress(x, zf.LZ77).bytes())
+    orc = _chunk_streams(zo.encode(x, zo.LZ77, [65536] * 9))
+    r = np.random.default_rng(12)
+    chunks, ref = [], []
+    for i in range(9):
+        src = prod if i % 3 != 1 else orc
+        chunks.append(src[i])
+        ref.append(x[i * 65536:(i + 1) * 65536])
+        if i % 4 == 2:  # a tiny chunk between two full ones
+            seqs, lits = H.random_lz(r, 5 + i, small_offsets=True)
+            chunks.append((H.lz_stream(seqs, lits, 5 + i), 5 + i, zf.LZ77))
+            ref.append(None)
+    cols = [zf.Column.from_bytes(H.container(zf.BYTES, chunks))]
+    out = decode_image(cols, tiles=lz_tiles(lanes))
+    check(cols, out)
+    at = 0
+    for (s, n, _), want in zip(chunks, ref):
+        if want is not None:
+            assert np.array_equal(out[0][at:at + n], want)
+        at += n
+
+
+@pytest.mark.parametrize("lanes", LZ_LANES)
+def test_lz77_int_columns(lanes):
+    log("lz ints", lanes)
     x = g.sorted_runs_column(100000, 8, 5)
     cols = [zf.Column.compress(x, zf.LZ77)]
-    check(cols, decode_image(cols), [x])
+    check(cols, decode_image(cols, tiles=lz_tiles(lanes)), [x])
 
 
 # ------------------------------------------------------- mixed + staged
@@ -267,9 +313,9 @@ def test_repeated_decodes_identical():
 
 
 # --------------------------------------------------- device-side corruption
-def _expect_corrupt(cols):
+def _expect_corrupt(cols, **plan_kw):
     T = torch()
-    plan = zf.Plan(cols, device=0)
+    plan = zf.Plan(cols, device=0, **plan_kw)
     img = zf.upload_image(plan, cols)
     outs = zf.empty_outputs(cols)
     plan.decompress_async(img, img.numel(), outs)
@@ -283,12 +329,16 @@ def test_device_detects_corrupt_streams():
     """Corruption the host checks cannot see (it lives in the data) is caught
     by the kernels' own checks and reported by zf_sync."""
     log("corrupt")
-    # LZ77: an offset beyond the bytes produced so far
-    s = H.lz_stream([(3, 9, 5), (1, 0, 0)], b"abcX", 13)
-    _expect_corrupt([zf.Column.from_bytes(H.container(zf.BYTES, [(s, 13, zf.LZ77)]))])
-    # LZ77: a match running past the chunk end
-    s = H.lz_stream([(3, 12, 3), (1, 0, 0)], b"abcX", 13)
-    _expect_corrupt([zf.Column.from_bytes(H.container(zf.BYTES, [(s, 13, zf.LZ77)]))])
+    # LZ77: an offset beyond the bytes produced so far; a match running past
+    # the chunk end (alone, and as the third chunk of a wave's groups)
+    good = H.lz_stream([(3, 9, 3), (1, 0, 0)], b"abcX", 13)
+    for s in (H.lz_stream([(3, 9, 5), (1, 0, 0)], b"abcX", 13),
+              H.lz_stream([(3, 12, 3), (1, 0, 0)], b"abcX", 13)):
+        for lanes in LZ_LANES:
+            _expect_corrupt([zf.Column.from_bytes(H.container(zf.BYTES, [(s, 13, zf.LZ77)]))],
+                            tiles=lz_tiles(lanes))
+            blob = H.container(zf.BYTES, [(good, 13, zf.LZ77)] * 2 + [(s, 13, zf.LZ77), (good, 13, zf.LZ77)])
+            _expect_corrupt([zf.Column.from_bytes(blob)], tiles=lz_tiles(lanes))
     # RLE: run lengths that do not add up to the chunk
     x = g.sorted_runs_column(5000, 8, 1)
     b = zo.encode(x, zo.RLE_DELTA_BP).copy()
