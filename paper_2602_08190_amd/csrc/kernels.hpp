@@ -730,8 +730,11 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, LzSeq &tab) {
                         if (p < r.y) {
                             src[k] = 0x80000000u | (r.w + (p - r.x));
                         } else {
-                            const uint32_t j = p - r.y;
-                            const uint32_t q = (r.y - so) + (j < so ? j : j % so);
+                            // a source inside the match itself repeats with
+                            // period so (rare: the remainder is taken only then)
+                            uint32_t j = p - r.y;
+                            if (__builtin_expect(j >= so, 0)) j %= so;
+                            const uint32_t q = (r.y - so) + j;
                             src[k] = q >= pos ? 0x80000000u | (r.w + (q - r.x)) : q;
                         }
                     }
@@ -743,7 +746,7 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, LzSeq &tab) {
                     const uint32_t p = uint32_t(B) + k;
                     byte[k] = 0;
                     if (p >= p0 && p < pe)
-                        byte[k] = (src[k] & 0x80000000u) ? lits[src[k] & 0x7FFFFFFFu] : out[src[k]];
+                        byte[k] = (src[k] & 0x80000000u) ? gp(lits)[src[k] & 0x7FFFFFFFu] : gp(out)[src[k]];
                 }
                 const uint32_t w0 = byte[0] | (byte[1] << 8) | (byte[2] << 16) | (byte[3] << 24);
                 const uint32_t w1 = byte[4] | (byte[5] << 8) | (byte[6] << 16) | (byte[7] << 24);

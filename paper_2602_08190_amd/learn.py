@@ -36,6 +36,24 @@ LZ_SUB = [8192, 16384, 32768, 65536]
 UNIT = {"FP": [1, 2, 4, 8], "GP": [1024, 2048, 4096, 8192], "PLAIN": [16384, 65536, 262144, 1048576]}
 DEFAULT_SCHED = {zf.PLAIN: 1, zf.FOR_BP: 1, zf.DICT_BP: 1, zf.DELTA_BP: 2, zf.RLE_DELTA_BP: 2,
                  zf.LZ77: 3}
+TUNE_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_gfx950.json")
+
+
+def tuned_sched(path=TUNE_CACHE):
+    """Schedule index of each codec under the autotuner's tile cache (what the
+    library runs when no model picks a schedule); LZ77 keeps 64 KiB chunks."""
+    try:
+        with open(path) as f:
+            kinds = json.load(f)["kinds"]
+    except (OSError, ValueError, KeyError):
+        return dict(DEFAULT_SCHED)
+
+    def near(grp, kind):
+        u = kinds.get(kind, {}).get("unit", UNIT[grp][0])
+        return int(np.argmin([abs(math.log2(max(u, 1)) - math.log2(x)) for x in UNIT[grp]]))
+    return {zf.PLAIN: near("PLAIN", "PLAIN"), zf.FOR_BP: near("FP", "FOR32"),
+            zf.DICT_BP: near("FP", "DICT32"), zf.DELTA_BP: near("GP", "RLE32"),
+            zf.RLE_DELTA_BP: near("GP", "RLE32"), zf.LZ77: 3}
 
 
 def log(*a):
@@ -286,21 +304,32 @@ def evaluate(d, mask, Y, margin=0.05):
         idx = np.array([CODECS.index(c) * 4 + sched_of_codec[c] for c in codec_of_row])
         return T[np.arange(len(T)), idx]
 
-    static = pick_codec([STATIC[f] for f in fams], DEFAULT_SCHED)
-    plain = pick_codec([zf.PLAIN] * len(T), DEFAULT_SCHED)
-    # the library without a model: the smallest stream, default schedule
-    small_idx = []
-    for row in S:
-        cands = [(row[c * 4 + DEFAULT_SCHED[CODECS[c]]], c) for c in range(6)
-                 if np.isfinite(row[c * 4 + DEFAULT_SCHED[CODECS[c]]])]
-        small_idx.append(min(cands)[1] * 4 + DEFAULT_SCHED[CODECS[min(cands)[1]]])
-    smallest = T[np.arange(len(T)), np.array(small_idx)]
+    def smallest_stream(sched):
+        idx = []
+        for row in S:
+            cands = [(row[c * 4 + sched[CODECS[c]]], c) for c in range(6)
+                     if np.isfinite(row[c * 4 + sched[CODECS[c]]])]
+            c = min(cands)[1]
+            idx.append(c * 4 + sched[CODECS[c]])
+        return T[np.arange(len(T)), np.array(idx)]
+
     reg = lambda t: float(np.sum(t) / np.sum(best) - 1.0)  # noqa: E731
+    tuned = tuned_sched()
+    fam_reg = {f: {"mlp": float(np.sum(chosen[fams == f]) / np.sum(best[fams == f]) - 1.0),
+                   "smallest_stream_tuned": float(np.sum(smallest_stream(tuned)[fams == f])
+                                                  / np.sum(best[fams == f]) - 1.0)}
+               for f in np.unique(fams)}
     return {"chunks": int(len(T)), "regret_mlp": reg(chosen), "regret_mlp_fallback": reg(fb),
-            "fallback_rate": float(np.mean(close)), "regret_smallest_stream": reg(smallest),
-            "regret_static_rule": reg(static), "regret_always_plain": reg(plain),
+            "fallback_rate": float(np.mean(close)),
+            # the library without a model: the smallest stream, with the tile
+            # cache's schedule (tuned) or the fixed default schedule
+            "regret_smallest_stream_tuned": reg(smallest_stream(tuned)),
+            "regret_smallest_stream_default": reg(smallest_stream(DEFAULT_SCHED)),
+            "regret_static_rule_tuned": reg(pick_codec([STATIC[f] for f in fams], tuned)),
+            "regret_always_plain_tuned": reg(pick_codec([zf.PLAIN] * len(T), tuned)),
             "exact_best_rate": float(np.mean(pick == np.nanargmin(T, axis=1))),
-            "total_best_ms": float(np.sum(best)), "total_mlp_ms": float(np.sum(chosen))}
+            "total_best_ms": float(np.sum(best)), "total_mlp_ms": float(np.sum(chosen)),
+            "per_family": fam_reg, "tuned_schedule": {str(k): v for k, v in tuned.items()}}
 
 
 def main():
