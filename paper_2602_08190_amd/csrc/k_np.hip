@@ -2,15 +2,18 @@
 #include "kernels.hpp"
 
 namespace zf {
-// lanes: lanes per chunk (16, 32 or 64; other values select 64).
-void launch_lz(const LaunchArgs &A, uint32_t waves, uint32_t lanes, hipStream_t st) {
+// knob: 16, 32 or 64 = lanes per chunk (16 output bytes per lane step);
+// 4 or 8 = output bytes per lane step with 64 lanes per chunk.
+void launch_lz(const LaunchArgs &A, uint32_t waves, uint32_t knob, hipStream_t st) {
     const uint32_t n = A.kind_begin[K_LZ + 1] - A.kind_begin[K_LZ];
     if (!n) return;
-    const uint32_t per = lanes == 16 ? 4 : lanes == 32 ? 2 : 1, units = waves * per;
+    const uint32_t per = knob == 16 ? 4 : knob == 32 ? 2 : 1, units = waves * per;
     const dim3 grid((n + units - 1) / units), block(64 * waves);
-    if (per == 4) hipLaunchKernelGGL(k_decode_lz<16>, grid, block, 0, st, A);
-    else if (per == 2) hipLaunchKernelGGL(k_decode_lz<32>, grid, block, 0, st, A);
-    else hipLaunchKernelGGL(k_decode_lz<64>, grid, block, 0, st, A);
+    if (knob == 16) hipLaunchKernelGGL((k_decode_lz<16, 16>), grid, block, 0, st, A);
+    else if (knob == 32) hipLaunchKernelGGL((k_decode_lz<32, 16>), grid, block, 0, st, A);
+    else if (knob == 4) hipLaunchKernelGGL((k_decode_lz<64, 4>), grid, block, 0, st, A);
+    else if (knob == 8) hipLaunchKernelGGL((k_decode_lz<64, 8>), grid, block, 0, st, A);
+    else hipLaunchKernelGGL((k_decode_lz<64, 16>), grid, block, 0, st, A);
 }
 ZF_DEFINE_LAUNCHER(K_PLAIN, launch_plain)
 }  // namespace zf

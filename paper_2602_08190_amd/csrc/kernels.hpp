@@ -626,7 +626,8 @@ ZF_DEV uint32_t ext_pick(uint32_t ew, uint32_t k) {
 // extension words, loaded one batch ahead as a window held two per lane and
 // read with cross-lane permutes, so no load sits on the parse's critical
 // path except the copy sources themselves.
-template <uint32_t G>
+// BLK: output bytes a lane assembles per step of the flat path (4, 8 or 16).
+template <uint32_t G, uint32_t BLK>
 ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, LzSeq &tab) {
     const uint8_t *s = A.comp + ck.comp_off;
     const uint32_t clen = ck.comp_len, g = lane_id() & (G - 1), gb = lane_id() & ~(G - 1);
@@ -650,8 +651,8 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, LzSeq &tab) {
     const uint16_t *ext = offs + nseq;
     const uint8_t *tags = reinterpret_cast<const uint8_t *>(ext + next);
     const uint8_t *lits = tags + nseq;
-    // misalignment of the chunk's output, for 16-byte aligned stores
-    const uint32_t mis = uint32_t(reinterpret_cast<uintptr_t>(out) & 15u);
+    // misalignment of the chunk's output, for BLK-aligned stores
+    const uint32_t mis = uint32_t(reinterpret_cast<uintptr_t>(out) & (BLK - 1));
     uint32_t pos = 0, lp = 0, ep = 0;
     uint32_t tag = g < nseq ? tags[g] : 0u;
     uint32_t off = g < nseq ? offs[g] : 0u;
@@ -701,10 +702,10 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, LzSeq &tab) {
             tab.pdel[gb + g] = make_uint4(P, D, P + len, LP);
             tab.off[gb + g] = off;
             wave_fence();
-            for (int32_t B = int32_t(pos) - int32_t((mis + pos) & 15u) + int32_t(16 * g);
-                 B < int32_t(end); B += int32_t(16 * G)) {
+            for (int32_t B = int32_t(pos) - int32_t((mis + pos) & (BLK - 1)) + int32_t(BLK * g);
+                 B < int32_t(end); B += int32_t(BLK * G)) {
                 const uint32_t p0 = uint32_t(max(B, int32_t(pos)));
-                const uint32_t pe = min(uint32_t(B + 16), end);
+                const uint32_t pe = min(uint32_t(B) + BLK, end);
                 // sequence holding p0: the last one with P <= p0
                 uint32_t lo = 0, hi = cnt;
                 while (hi - lo > 1) {
@@ -716,9 +717,9 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, LzSeq &tab) {
                 uint4 r = tab.pdel[sidx];
                 uint32_t so = tab.off[sidx];
                 // phase 1: where each byte comes from (bit 31 set: a literal)
-                uint32_t src[16];
+                uint32_t src[BLK];
 #pragma unroll
-                for (uint32_t k = 0; k < 16; k++) {
+                for (uint32_t k = 0; k < BLK; k++) {
                     const uint32_t p = uint32_t(B) + k;
                     src[k] = 0;
                     if (p >= p0 && p < pe) {
@@ -739,26 +740,37 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, LzSeq &tab) {
                         }
                     }
                 }
-                // phase 2: all 16 loads in flight together
-                uint32_t byte[16];
+                // phase 2: all BLK loads in flight together, with no branch
+                // between them (bytes outside [p0, pe) read out[0], a valid
+                // address, and are never stored)
+                uint32_t byte[BLK];
 #pragma unroll
-                for (uint32_t k = 0; k < 16; k++) {
-                    const uint32_t p = uint32_t(B) + k;
-                    byte[k] = 0;
-                    if (p >= p0 && p < pe)
-                        byte[k] = (src[k] & 0x80000000u) ? gp(lits)[src[k] & 0x7FFFFFFFu] : gp(out)[src[k]];
+                for (uint32_t k = 0; k < BLK; k++) {
+                    const uint32_t x = src[k];
+                    const uint8_t *a = (x & 0x80000000u) ? lits + (x & 0x7FFFFFFFu) : out + x;
+                    byte[k] = *gp(a);
                 }
-                const uint32_t w0 = byte[0] | (byte[1] << 8) | (byte[2] << 16) | (byte[3] << 24);
-                const uint32_t w1 = byte[4] | (byte[5] << 8) | (byte[6] << 16) | (byte[7] << 24);
-                const uint32_t w2 = byte[8] | (byte[9] << 8) | (byte[10] << 16) | (byte[11] << 24);
-                const uint32_t w3 = byte[12] | (byte[13] << 8) | (byte[14] << 16) | (byte[15] << 24);
-                if (p0 == uint32_t(B) && pe == uint32_t(B) + 16) {
-                    *reinterpret_cast<uint4 *>(out + B) = make_uint4(w0, w1, w2, w3);
+                uint32_t w[BLK / 4];
+#pragma unroll
+                for (uint32_t d = 0; d < BLK / 4; d++)
+                    w[d] = byte[4 * d] | (byte[4 * d + 1] << 8) | (byte[4 * d + 2] << 16) | (byte[4 * d + 3] << 24);
+                if (p0 == uint32_t(B) && pe == uint32_t(B) + BLK) {
+                    if constexpr (BLK == 16) {
+                        const u32x4 v = {w[0], w[1], w[2], w[3]};
+                        *gp(reinterpret_cast<u32x4 *>(out + B)) = v;
+                    } else if constexpr (BLK == 8) {
+                        const u32x2 v = {w[0], w[1]};
+                        *gp(reinterpret_cast<u32x2 *>(out + B)) = v;
+                    } else {
+                        *gp(reinterpret_cast<uint32_t *>(out + B)) = w[0];
+                    }
                 } else {
                     for (uint32_t p = p0; p < pe; p++) {
                         const uint32_t k = p - uint32_t(B);
-                        const uint32_t wd = k < 4 ? w0 : k < 8 ? w1 : k < 12 ? w2 : w3;
-                        out[p] = uint8_t(wd >> (8 * (k & 3)));
+                        uint32_t wd = w[0];
+#pragma unroll
+                        for (uint32_t d = 1; d < BLK / 4; d++) wd = k >= 4 * d ? w[d] : wd;
+                        gp(out)[p] = uint8_t(wd >> (8 * (k & 3)));
                     }
                 }
             }
@@ -831,7 +843,7 @@ ZF_DEV void run_unit(const LaunchArgs &A, uint32_t kind, uint32_t u, LzSeq *tab)
     case K_DICT128: unit_fp<16, true, UNR>(A, t, ck); break;
     case K_RLE32: unit_rle<uint32_t>(A, t, ck); break;
     case K_RLE64: unit_rle<uint64_t>(A, t, ck); break;
-    case K_LZ: unit_lz<64>(A, ck, *tab); break;
+    case K_LZ: unit_lz<64, 16>(A, ck, *tab); break;
     }
 }
 
@@ -864,14 +876,14 @@ __global__ __launch_bounds__(1024) void k_decode_kind(LaunchArgs A) {
 }
 
 // LZ77: each wave takes 64/G consecutive units, one per group of G lanes.
-template <uint32_t G>
+template <uint32_t G, uint32_t BLK>
 __global__ __launch_bounds__(1024) void k_decode_lz(LaunchArgs A) {
     const uint32_t waves = blockDim.x / 64;
     const uint32_t w = blockIdx.x * waves + first32(threadIdx.x / 64);
     const uint32_t u = A.kind_begin[K_LZ] + w * (64 / G) + (G == 64 ? 0u : lane_id() / G);
     if (u >= A.kind_begin[K_LZ + 1]) return;
     __shared__ LzSeq tab[16];
-    unit_lz<G>(A, A.chunks[A.tiles[u].chunk], tab[threadIdx.x / 64]);
+    unit_lz<G, BLK>(A, A.chunks[A.tiles[u].chunk], tab[threadIdx.x / 64]);
 }
 void launch_lz(const LaunchArgs &A, uint32_t waves, uint32_t lanes, hipStream_t st);
 

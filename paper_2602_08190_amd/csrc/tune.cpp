@@ -169,8 +169,12 @@ TileShape resolve_tiles(const zf_plan_opts &o) {
     t.unit[K_RLE32] = std::max(64u, t.unit[K_RLE32]);
     t.unit[K_RLE64] = std::max(64u, t.unit[K_RLE64]);
     t.unit[K_PLAIN] = std::max(1024u, t.unit[K_PLAIN]);
-    // LZ77: lanes per chunk, one of 16, 32, 64
-    t.unit[K_LZ] = t.unit[K_LZ] <= 16 ? 16u : t.unit[K_LZ] <= 32 ? 32u : 64u;
+    // LZ77 knob: 4 or 8 (bytes per lane step, 64 lanes per chunk) or 16, 32, 64
+    // (lanes per chunk, 16 bytes per lane step)
+    {
+        const uint32_t u = t.unit[K_LZ];
+        t.unit[K_LZ] = u <= 4 ? 4u : u <= 8 ? 8u : u <= 16 ? 16u : u <= 32 ? 32u : 64u;
+    }
     return t;
 }
 

@@ -171,8 +171,9 @@ def test_rle_config2_shape():
 
 
 # -------------------------------------------------------------- NP codec
-# lanes per chunk of the per-kind LZ77 kernel: 4, 2 or 1 chunks per wave
-LZ_LANES = [16, 32, 64]
+# LZ77 kernel knob: 16, 32, 64 lanes per chunk (4, 2, 1 chunks per wave) with
+# 16 output bytes per lane step; 4 and 8 bytes per lane step with 64 lanes
+LZ_LANES = [4, 8, 16, 32, 64]
 
 
 def lz_tiles(lanes):
