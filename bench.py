@@ -256,7 +256,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": kinds[dom]["GBps"], "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(kinds[dom]["GBps"] / HBM_PEAK_GBPS, 4),
                      "traffic": read_traffic(f"{args.workload}/{dom}"),
-                     "kernel": f"k_decode_kind<{dom}>",
+                     "kernel": "k_decode_lz (LZ77)" if dom == "LZ77" else f"k_decode_kind<{dom}>",
                      "algorithmic_bytes_per_launch": kinds[dom]["algorithmic_bytes"],
                      "avg_launch_ms": kinds[dom]["ms"]},
         "kernels": kinds,

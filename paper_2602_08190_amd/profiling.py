@@ -34,6 +34,8 @@ def stats(csv_path, out_path, command):
              f"{'kernel':58s} {'calls':>6s} {'avg_us':>11s} {'total_us':>12s} {'pct':>7s}"]
     for r in rows:
         name = r["Name"]
+        for kid, kind in enumerate(KIND_OF_ID):
+            name = name.replace(f"k_decode_kind<{kid}u>", f"k_decode_kind<{kid}u={kind}>")
         name = name if len(name) <= 58 else name[:55] + "..."
         lines.append(f"{name:58s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:11.1f} "
                      f"{float(r['TotalDurationNs']) / 1e3:12.1f} {float(r['Percentage']):7.2f}")
@@ -41,10 +43,16 @@ def stats(csv_path, out_path, command):
         f.write("\n".join(lines) + "\n")
 
 
+def _kernel_of(kernel_id):
+    """Name fragment of the per-kind decode kernel (LZ77 has its own)."""
+    return "k_decode_lz<" if KIND_OF_ID[kernel_id] == "LZ77" else f"k_decode_kind<{kernel_id}u>"
+
+
 def _per_dispatch(path, kernel_id):
     agg = collections.defaultdict(float)
+    frag = _kernel_of(kernel_id)
     for r in csv.DictReader(open(path)):
-        if f"k_decode_kind<{kernel_id}u>" in r["Kernel_Name"]:
+        if frag in r["Kernel_Name"]:
             agg[r["Dispatch_Id"]] += float(r["Counter_Value"])
     v = sorted(agg.values())
     return v[len(v) // 2] * 1024 if v else None  # KiB -> bytes
