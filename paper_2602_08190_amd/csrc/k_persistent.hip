@@ -7,8 +7,8 @@ namespace zf {
 // Persistent: every wave pulls units from one queue until it is empty.
 // Units are ordered by kind, the costliest kinds first.
 __global__ __launch_bounds__(256) void k_decode_persistent(LaunchArgs A) {
-    __shared__ LzSeq tab[4];
-    LzSeq *mine = &tab[threadIdx.x / 64];
+    __shared__ LzWave<16> tab[4];
+    LzWave<16> *mine = &tab[threadIdx.x / 64];
     const uint32_t n = A.kind_begin[K_COUNT];
     for (;;) {
         uint32_t u = 0;

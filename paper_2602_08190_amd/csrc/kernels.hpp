@@ -604,6 +604,14 @@ struct LzSeq {
     uint32_t off[64];
 };
 
+// A wave's LDS for LZ77: the batch table and, for the flat path, one row of
+// BLK dwords per lane.
+template <uint32_t BLK>
+struct LzWave {
+    LzSeq tab;
+    uint32_t row[64 * BLK];
+};
+
 // Extension words e0 + g and e0 + G + g (0 past the array), packed.
 template <uint32_t G>
 ZF_DEV uint32_t ext_window(const uint16_t *ext, uint32_t e0, uint32_t next, uint32_t g) {
@@ -628,7 +636,7 @@ ZF_DEV uint32_t ext_pick(uint32_t ew, uint32_t k) {
 // path except the copy sources themselves.
 // BLK: output bytes a lane assembles per step of the flat path (4, 8 or 16).
 template <uint32_t G, uint32_t BLK>
-ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, LzSeq &tab) {
+ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, LzSeq &tab, uint32_t *row) {
     const uint8_t *s = A.comp + ck.comp_off;
     const uint32_t clen = ck.comp_len, g = lane_id() & (G - 1), gb = lane_id() & ~(G - 1);
     const uint32_t es = ck.dtype == D_I32 ? 4 : ck.dtype == D_I64 ? 8 : ck.dtype == D_FIXED16 ? 16 : 1;
@@ -716,33 +724,55 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, LzSeq &tab) {
                 uint32_t sidx = gb + lo;
                 uint4 r = tab.pdel[sidx];
                 uint32_t so = tab.off[sidx];
-                // phase 1: where each byte comes from (bit 31 set: a literal)
+                // phase 1: where each byte comes from, as src = p + delta with
+                // delta constant over a segment (a literal run, or one period of
+                // a match); bit 31 of src set = a literal index.  Each lane walks
+                // its segments once and scatters the change of delta at each
+                // segment start into its LDS row (entry k of lane l at
+                // row[64k + l]); a prefix sum over the row then gives every
+                // byte's delta, so the per-byte work has no branch.
+                const uint32_t nb = uint32_t(B), l = lane_id();
+                uint32_t prev = 0;
+#pragma unroll
+                for (uint32_t k = 0; k < BLK; k++) row[64 * k + l] = 0;
+                uint32_t cur = p0;
+                while (cur < pe) {
+                    while (cur >= r.z) {  // next sequence (zero-length ones skipped)
+                        sidx++;
+                        r = tab.pdel[sidx];
+                        so = tab.off[sidx];
+                    }
+                    uint32_t delta, send;
+                    if (cur < r.y) {
+                        delta = 0x80000000u + (r.w - r.x);
+                        send = r.y;
+                    } else {
+                        // a source inside the match itself repeats with period
+                        // so: one segment per period (the remainder is taken
+                        // only when the block starts past the first period)
+                        uint32_t j = cur - r.y;
+                        if (__builtin_expect(j >= so, 0)) j %= so;
+                        const uint32_t q = (r.y - so) + j;
+                        delta = q - cur;
+                        if (q >= pos) delta += 0x80000000u + (r.w - r.x);  // own literal
+                        send = min(r.z, cur + (so - j));
+                    }
+                    row[64 * (cur - nb) + l] = delta - prev;
+                    prev = delta;
+                    cur = min(send, pe);
+                }
+                // bytes outside [p0, pe) read out[0], a valid address, and are
+                // never stored
+                const uint32_t k0 = p0 - nb, kn = pe - p0;
                 uint32_t src[BLK];
+                uint32_t acc = 0;
 #pragma unroll
                 for (uint32_t k = 0; k < BLK; k++) {
-                    const uint32_t p = uint32_t(B) + k;
-                    src[k] = 0;
-                    if (p >= p0 && p < pe) {
-                        while (p >= r.z) {  // next sequence (zero-length ones skipped)
-                            sidx++;
-                            r = tab.pdel[sidx];
-                            so = tab.off[sidx];
-                        }
-                        if (p < r.y) {
-                            src[k] = 0x80000000u | (r.w + (p - r.x));
-                        } else {
-                            // a source inside the match itself repeats with
-                            // period so (rare: the remainder is taken only then)
-                            uint32_t j = p - r.y;
-                            if (__builtin_expect(j >= so, 0)) j %= so;
-                            const uint32_t q = (r.y - so) + j;
-                            src[k] = q >= pos ? 0x80000000u | (r.w + (q - r.x)) : q;
-                        }
-                    }
+                    acc += row[64 * k + l];
+                    src[k] = (k - k0) < kn ? nb + k + acc : 0u;
                 }
                 // phase 2: all BLK loads in flight together, with no branch
-                // between them (bytes outside [p0, pe) read out[0], a valid
-                // address, and are never stored)
+                // between them
                 uint32_t byte[BLK];
 #pragma unroll
                 for (uint32_t k = 0; k < BLK; k++) {
@@ -831,7 +861,7 @@ ZF_DEV void unit_plain(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck) 
 // ============================================================== dispatch
 // UNR: FP lane-steps of loads kept in flight; 0 = runtime-width FP path.
 template <uint32_t UNR>
-ZF_DEV void run_unit(const LaunchArgs &A, uint32_t kind, uint32_t u, LzSeq *tab) {
+ZF_DEV void run_unit(const LaunchArgs &A, uint32_t kind, uint32_t u, LzWave<16> *tab) {
     const Tile t = A.tiles[u];
     const ChunkDesc ck = A.chunks[t.chunk];
     switch (kind) {
@@ -843,7 +873,7 @@ ZF_DEV void run_unit(const LaunchArgs &A, uint32_t kind, uint32_t u, LzSeq *tab)
     case K_DICT128: unit_fp<16, true, UNR>(A, t, ck); break;
     case K_RLE32: unit_rle<uint32_t>(A, t, ck); break;
     case K_RLE64: unit_rle<uint64_t>(A, t, ck); break;
-    case K_LZ: unit_lz<64, 16>(A, ck, *tab); break;
+    case K_LZ: unit_lz<64, 16>(A, ck, tab->tab, tab->row); break;
     }
 }
 
@@ -882,8 +912,9 @@ __global__ __launch_bounds__(1024) void k_decode_lz(LaunchArgs A) {
     const uint32_t w = blockIdx.x * waves + first32(threadIdx.x / 64);
     const uint32_t u = A.kind_begin[K_LZ] + w * (64 / G) + (G == 64 ? 0u : lane_id() / G);
     if (u >= A.kind_begin[K_LZ + 1]) return;
-    __shared__ LzSeq tab[16];
-    unit_lz<G, BLK>(A, A.chunks[A.tiles[u].chunk], tab[threadIdx.x / 64]);
+    extern __shared__ uint4 lz_smem[];  // one LzWave per wave, sized at launch
+    LzWave<BLK> &me = reinterpret_cast<LzWave<BLK> *>(lz_smem)[threadIdx.x / 64];
+    unit_lz<G, BLK>(A, A.chunks[A.tiles[u].chunk], me.tab, me.row);
 }
 void launch_lz(const LaunchArgs &A, uint32_t waves, uint32_t lanes, hipStream_t st);
 
