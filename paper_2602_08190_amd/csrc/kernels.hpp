@@ -649,7 +649,13 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, LzSeq &tab, uint32
         corrupt();
         return;
     }
-    const uint32_t nseq = ld32u(s), nlit = ld32u(s + 4), next = ld32u(s + 8), plen = ld32u(s + 12);
+    uint32_t nseq = ld32u(s), nlit = ld32u(s + 4), next = ld32u(s + 8), plen = ld32u(s + 12);
+    if constexpr (G == 64) {  // one chunk per wave: keep the header in scalar registers
+        nseq = first32(nseq);
+        nlit = first32(nlit);
+        next = first32(next);
+        plen = first32(plen);
+    }
     if (plen != plain || plain > kLzMaxChunk ||
         16ull + 3ull * nseq + 2ull * next + nlit != uint64_t(clen)) {
         corrupt();
@@ -659,6 +665,12 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, LzSeq &tab, uint32
     const uint16_t *ext = offs + nseq;
     const uint8_t *tags = reinterpret_cast<const uint8_t *>(ext + next);
     const uint8_t *lits = tags + nseq;
+    // byte-granular bounds-checked views of the output and the literals
+    // (raw buffers, 32-bit offsets; the descriptor's word 3 as for gfx9)
+    [[maybe_unused]] const __amdgpu_buffer_rsrc_t rs_out =
+        __builtin_amdgcn_make_buffer_rsrc(out, 0, int(plain), 0x00020000);
+    [[maybe_unused]] const __amdgpu_buffer_rsrc_t rs_lit =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(lits), 0, int(nlit), 0x00020000);
     // misalignment of the chunk's output, for BLK-aligned stores
     const uint32_t mis = uint32_t(reinterpret_cast<uintptr_t>(out) & (BLK - 1));
     uint32_t pos = 0, lp = 0, ep = 0;
@@ -761,15 +773,16 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, LzSeq &tab, uint32
                     prev = delta;
                     cur = min(send, pe);
                 }
-                // bytes outside [p0, pe) read out[0], a valid address, and are
-                // never stored
                 const uint32_t k0 = p0 - nb, kn = pe - p0;
                 uint32_t src[BLK];
                 uint32_t acc = 0;
 #pragma unroll
                 for (uint32_t k = 0; k < BLK; k++) {
                     acc += row[64 * k + l];
-                    src[k] = (k - k0) < kn ? nb + k + acc : 0u;
+                    src[k] = nb + k + acc;
+                    // bytes outside [p0, pe) are never stored; with global
+                    // loads they must still read a valid address (out[0])
+                    if constexpr (G != 64) src[k] = (k - k0) < kn ? src[k] : 0u;
                 }
                 // phase 2: all BLK loads in flight together, with no branch
                 // between them
@@ -777,8 +790,17 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, LzSeq &tab, uint32
 #pragma unroll
                 for (uint32_t k = 0; k < BLK; k++) {
                     const uint32_t x = src[k];
-                    const uint8_t *a = (x & 0x80000000u) ? lits + (x & 0x7FFFFFFFu) : out + x;
-                    byte[k] = *gp(a);
+                    if constexpr (G == 64) {
+                        // two bounds-checked byte loads, one of which is out
+                        // of range and reads 0: bit 31 of x puts a literal
+                        // index past the output, and its flip puts an output
+                        // position past the literals
+                        byte[k] = __builtin_amdgcn_raw_buffer_load_b8(rs_out, int(x), 0, 0) |
+                                  __builtin_amdgcn_raw_buffer_load_b8(rs_lit, int(x ^ 0x80000000u), 0, 0);
+                    } else {
+                        const uint8_t *a = (x & 0x80000000u) ? lits + (x & 0x7FFFFFFFu) : out + x;
+                        byte[k] = *gp(a);
+                    }
                 }
                 uint32_t w[BLK / 4];
 #pragma unroll
