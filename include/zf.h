@@ -165,8 +165,8 @@ typedef enum {
 
 /* Tile shape of one kind, the device geometry of Sec. 4 (<L,S,C>): `unit`
  * is the work of one wavefront (FP: 2048-value blocks; GP: output elements;
- * PLAIN: bytes; LZ77: lanes per chunk, 16, 32 or 64, so that a wavefront
- * decodes 4, 2 or 1 chunks at once; the persistent kernel always uses 64),
+ * PLAIN: bytes; LZ77: output bytes per block of the copy step, 4, 8 or 16,
+ * one chunk per wavefront; the persistent kernel always uses 16),
  * `waves_per_block`
  * the wavefronts per workgroup (S/64).  A lane always owns 16 output bytes
  * per step (C).  Zero fields take the tune cache's value, else a default. */

@@ -33,11 +33,11 @@ UNITS = {
     "FP": [1, 2, 4, 8, 16],                  # L: 2048-value blocks per wave
     "GP": [512, 1024, 2048, 4096, 8192, 16384],
     "PLAIN": [16384, 65536, 262144, 1048576],
-    "NP": [4, 8, 16, 32, 64],                # 4, 8: bytes per lane step; 16..64: lanes per chunk
+    "NP": [4, 8, 16],                        # LZ77: output bytes per block
 }
 GROUP = {"FOR32": "FP", "FOR64": "FP", "DICT32": "FP", "DICT64": "FP", "DICT128": "FP",
          "RLE32": "GP", "RLE64": "GP", "LZ77": "NP", "PLAIN": "PLAIN"}
-DEFAULT = {"FP": 2, "GP": 4096, "PLAIN": 65536, "NP": 64}
+DEFAULT = {"FP": 2, "GP": 4096, "PLAIN": 65536, "NP": 16}
 
 
 def log(*a):

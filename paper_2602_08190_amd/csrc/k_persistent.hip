@@ -7,8 +7,8 @@ namespace zf {
 // Persistent: every wave pulls units from one queue until it is empty.
 // Units are ordered by kind, the costliest kinds first.
 __global__ __launch_bounds__(256) void k_decode_persistent(LaunchArgs A) {
-    __shared__ LzWave<16> tab[4];
-    LzWave<16> *mine = &tab[threadIdx.x / 64];
+    __shared__ uint32_t lz_rows[4][64 * 16];
+    uint32_t *mine = lz_rows[threadIdx.x / 64];
     const uint32_t n = A.kind_begin[K_COUNT];
     for (;;) {
         uint32_t u = 0;
@@ -42,7 +42,7 @@ hipError_t launch_set_out_tab(uint8_t **d_tab, uint8_t *const *ptrs, uint32_t n,
 // Enqueue the decode of one launch's units.  persistent_waves > 0 selects
 // the persistent kernel with that many waves in flight.
 hipError_t launch_decode(const LaunchArgs &A, uint32_t persistent_waves, const uint32_t *wpb,
-                         uint32_t lz_lanes, hipStream_t st) {
+                         uint32_t lz_blk, hipStream_t st) {
     if (A.kind_begin[K_COUNT] == 0) return hipSuccess;
     if (persistent_waves) {
         hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, st, A.counter);
@@ -50,7 +50,7 @@ hipError_t launch_decode(const LaunchArgs &A, uint32_t persistent_waves, const u
         hipLaunchKernelGGL(k_decode_persistent, dim3(blocks), dim3(256), 0, st, A);
         return hipGetLastError();
     }
-    launch_lz(A, wpb[K_LZ], lz_lanes, st);
+    launch_lz(A, wpb[K_LZ], lz_blk, st);
     launch_rle32(A, wpb[K_RLE32], st);
     launch_rle64(A, wpb[K_RLE64], st);
     launch_dict128(A, wpb[K_DICT128], st);

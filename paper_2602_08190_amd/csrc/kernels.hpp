@@ -566,99 +566,81 @@ ZF_DEV void unit_rle(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck) {
 }
 
 // ======================================================== Non-Parallel
-// A chunk is decoded by a group of G lanes (G = 16, 32 or 64: a DPP row, two
-// rows, or the whole wave), so one wave has 64/G chunks in flight.  The parse
-// of a batch is a short chain of dependent steps (header scans, then one
-// round of source loads); with several chunks per wave those chains overlap.
-//
-// Group primitives.  Groups are aligned to DPP rows, and every lane of a
-// group follows the same control flow, so lane moves never leave the group.
-template <uint32_t G>
-ZF_DEV uint32_t gscan(uint32_t x) {
-    x += dpp<0x111, 0xF>(x);   // row_shr:1
-    x += dpp<0x112, 0xF>(x);   // row_shr:2
-    x += dpp<0x114, 0xF>(x);   // row_shr:4
-    x += dpp<0x118, 0xF>(x);   // row_shr:8
-    if constexpr (G >= 32) x += dpp<0x142, 0xA>(x);  // row_bcast:15
-    if constexpr (G == 64) x += dpp<0x143, 0xC>(x);  // row_bcast:31
-    return x;
-}
-// Value of x in lane k of this lane's group.
-template <uint32_t G>
-ZF_DEV uint32_t gread(uint32_t x, uint32_t k) {
-    if constexpr (G == 64) return rl32(x, k);
-    else return uint32_t(__builtin_amdgcn_ds_bpermute(int(((lane_id() & ~(G - 1)) + k) * 4), int(x)));
-}
-template <uint32_t G>
-ZF_DEV bool gany(bool p) {
-    const uint64_t b = __ballot(p);
-    if constexpr (G == 64) return b != 0;
-    else return ((b >> (lane_id() & ~(G - 1))) & ((1ull << G) - 1)) != 0;
-}
+// One wave decodes one LZ77 chunk.  Lane i holds sequence i of a batch of 64;
+// wave scans give every sequence's output position, literal position and
+// extension index.  Tags, offsets and a 128-entry window of extension words
+// are loaded one batch ahead, so the only loads on the parse's critical path
+// are the copy sources.
 
-// Per-wave table of the current batch's sequences (LDS): output start P,
-// literal end D, sequence end E, literal start LP, and the match offset.  A
-// group of G lanes owns entries [group base, group base + G).
-struct LzSeq {
-    uint4 pdel[64];   // {P, D, E, LP}
-    uint32_t off[64];
-};
-
-// A wave's LDS for LZ77: the batch table and, for the flat path, one row of
-// BLK dwords per lane.
-template <uint32_t BLK>
-struct LzWave {
-    LzSeq tab;
-    uint32_t row[64 * BLK];
-};
-
-// Extension words e0 + g and e0 + G + g (0 past the array), packed.
-template <uint32_t G>
-ZF_DEV uint32_t ext_window(const uint16_t *ext, uint32_t e0, uint32_t next, uint32_t g) {
-    const uint32_t lo = e0 + g < next ? ext[e0 + g] : 0u;
-    const uint32_t hi = e0 + G + g < next ? ext[e0 + G + g] : 0u;
+// Extension words e0 + lane and e0 + 64 + lane (0 past the array), packed.
+ZF_DEV uint32_t ext_window(const uint16_t *ext, uint32_t e0, uint32_t next, uint32_t lane) {
+    const uint32_t lo = e0 + lane < next ? ext[e0 + lane] : 0u;
+    const uint32_t hi = e0 + 64 + lane < next ? ext[e0 + 64 + lane] : 0u;
     return lo | (hi << 16);
 }
 
-// Entry k (0 .. 2G-1) of a window; every lane of the group must take part.
-template <uint32_t G>
+// Entry k (0..127) of a window (entry k in lane k % 64, low half for k < 64);
+// every lane of the wave must take part.
 ZF_DEV uint32_t ext_pick(uint32_t ew, uint32_t k) {
-    const uint32_t v = uint32_t(__builtin_amdgcn_ds_bpermute(
-        int(((lane_id() & ~(G - 1)) + (k & (G - 1))) * 4), int(ew)));
-    return (k & G) ? v >> 16 : v & 0xFFFFu;
+    const uint32_t v = uint32_t(__builtin_amdgcn_ds_bpermute(int((k & 63u) * 4u), int(ew)));
+    return (k & 64u) ? v >> 16 : v & 0xFFFFu;
 }
 
-// The G lanes of this lane's group decode one whole LZ77 chunk.  Lane g
-// holds sequence g of a batch of G; group scans give every sequence's output
-// position, literal position and extension index.  A batch uses at most 2G
-// extension words, loaded one batch ahead as a window held two per lane and
-// read with cross-lane permutes, so no load sits on the parse's critical
-// path except the copy sources themselves.
-// BLK: output bytes a lane assembles per step of the flat path (4, 8 or 16).
-template <uint32_t G, uint32_t BLK>
-ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, LzSeq &tab, uint32_t *row) {
+// Inclusive scan across the wave keeping the value of the highest lane whose
+// x is nonzero (0 where no lane up to this one has one); the same DPP moves
+// as scan_add32.
+ZF_DEV uint32_t scan_last_nonzero(uint32_t x) {
+    uint32_t t;
+    t = dpp<0x111, 0xF>(x);
+    x = x ? x : t;
+    t = dpp<0x112, 0xF>(x);
+    x = x ? x : t;
+    t = dpp<0x114, 0xF>(x);
+    x = x ? x : t;
+    t = dpp<0x118, 0xF>(x);
+    x = x ? x : t;
+    t = dpp<0x142, 0xA>(x);
+    x = x ? x : t;
+    t = dpp<0x143, 0xC>(x);
+    x = x ? x : t;
+    return x;
+}
+
+// Flat batches (every match reads bytes before the batch or its own
+// literals; the product encoder keeps every batch flat) are copied without
+// any per-lane walk:
+//  * the output of the batch is cut into aligned blocks of BLK bytes, block b
+//    of a step of 64 blocks owned by lane b;
+//  * a byte's source is p + delta, with delta constant over a segment (a
+//    literal run, or one period of a match); bit 31 of the source set means
+//    "literal index".  Each sequence lane writes the delta of each of its
+//    segments at the segment's first byte, in an LDS row of BLK dwords per
+//    block (entry k of block b at row[64k + b]; zero = no segment starts
+//    here; no delta is ever zero);
+//  * each block lane carries the last delta forward over its bytes, taking
+//    the delta in force at its first byte from the blocks before it (a wave
+//    scan) or from the previous step;
+//  * every byte is read through two bounds-checked buffer views (the output
+//    and the literals), one of which is out of range and reads 0, and each
+//    block is written with one aligned store.
+// BLK: bytes per block (4, 8 or 16); row: this wave's 64 * BLK dwords.
+template <uint32_t BLK>
+ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, uint32_t *row) {
     const uint8_t *s = A.comp + ck.comp_off;
-    const uint32_t clen = ck.comp_len, g = lane_id() & (G - 1), gb = lane_id() & ~(G - 1);
+    const uint32_t clen = ck.comp_len, lane = lane_id();
     const uint32_t es = ck.dtype == D_I32 ? 4 : ck.dtype == D_I64 ? 8 : ck.dtype == D_FIXED16 ? 16 : 1;
     const uint32_t plain = ck.n_elems * es;
     uint8_t *out = A.out_tab[ck.col] + ck.out_off;
-    auto corrupt = [&]() {
-        if (g == 0) atomicOr(A.err, ERR_CORRUPT);
-    };
     if (clen < 16) {
-        corrupt();
+        flag(A.err, ERR_CORRUPT);
         return;
     }
-    uint32_t nseq = ld32u(s), nlit = ld32u(s + 4), next = ld32u(s + 8), plen = ld32u(s + 12);
-    if constexpr (G == 64) {  // one chunk per wave: keep the header in scalar registers
-        nseq = first32(nseq);
-        nlit = first32(nlit);
-        next = first32(next);
-        plen = first32(plen);
-    }
+    // the header is the same for every lane: keep it in scalar registers
+    const uint32_t nseq = first32(ld32u(s)), nlit = first32(ld32u(s + 4));
+    const uint32_t next = first32(ld32u(s + 8)), plen = first32(ld32u(s + 12));
     if (plen != plain || plain > kLzMaxChunk ||
         16ull + 3ull * nseq + 2ull * next + nlit != uint64_t(clen)) {
-        corrupt();
+        flag(A.err, ERR_CORRUPT);
         return;
     }
     const uint16_t *offs = reinterpret_cast<const uint16_t *>(s + 16);
@@ -666,178 +648,147 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, LzSeq &tab, uint32
     const uint8_t *tags = reinterpret_cast<const uint8_t *>(ext + next);
     const uint8_t *lits = tags + nseq;
     // byte-granular bounds-checked views of the output and the literals
-    // (raw buffers, 32-bit offsets; the descriptor's word 3 as for gfx9)
-    [[maybe_unused]] const __amdgpu_buffer_rsrc_t rs_out =
-        __builtin_amdgcn_make_buffer_rsrc(out, 0, int(plain), 0x00020000);
-    [[maybe_unused]] const __amdgpu_buffer_rsrc_t rs_lit =
+    // (raw buffers, 32-bit offsets; descriptor word 3 as for gfx9)
+    const __amdgpu_buffer_rsrc_t rs_out = __builtin_amdgcn_make_buffer_rsrc(out, 0, int(plain), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rs_lit =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(lits), 0, int(nlit), 0x00020000);
     // misalignment of the chunk's output, for BLK-aligned stores
     const uint32_t mis = uint32_t(reinterpret_cast<uintptr_t>(out) & (BLK - 1));
     uint32_t pos = 0, lp = 0, ep = 0;
-    uint32_t tag = g < nseq ? tags[g] : 0u;
-    uint32_t off = g < nseq ? offs[g] : 0u;
-    uint32_t ew = ext_window<G>(ext, 0, next, g);
-    for (uint32_t base = 0; base < nseq; base += G) {
-        const uint32_t i = base + g;
+    uint32_t tag = lane < nseq ? tags[lane] : 0u;
+    uint32_t off = lane < nseq ? offs[lane] : 0u;
+    uint32_t ew = ext_window(ext, 0, next, lane);
+    for (uint32_t base = 0; base < nseq; base += 64) {
+        const uint32_t i = base + lane;
         const bool act = i < nseq;
         // prefetch the next batch's headers
-        const uint32_t ni = i + G;
+        const uint32_t ni = i + 64;
         const uint32_t ntag = ni < nseq ? tags[ni] : 0u;
         const uint32_t noff = ni < nseq ? offs[ni] : 0u;
 
         const uint32_t lc = tag & 7u, mc = tag >> 3;
         const uint32_t ne = (lc == 7u) + (mc == 31u);
-        const uint32_t eincl = gscan<G>(ne);
-        const uint32_t eex = ep + eincl - ne, etot = gread<G>(eincl, G - 1);
+        const uint32_t eincl = scan_add32(ne);
+        const uint32_t eex = ep + eincl - ne, etot = rl32(eincl, 63);
         if (uint64_t(ep) + etot > next) {
-            corrupt();
+            flag(A.err, ERR_CORRUPT);
             return;
         }
         const uint32_t k1 = eex - ep, k2 = k1 + (lc == 7u);
-        const uint32_t x1 = ext_pick<G>(ew, k1), x2 = ext_pick<G>(ew, k2);
-        ew = ext_window<G>(ext, ep + etot, next, g);  // next batch's window
+        const uint32_t x1 = ext_pick(ew, k1), x2 = ext_pick(ew, k2);
+        ew = ext_window(ext, ep + etot, next, lane);  // next batch's window
         uint32_t ll = lc, ml = 0;
         if (lc == 7u) ll = 7u + x1;
         if (mc == 31u) ml = 34u + x2;
         else if (mc) ml = mc + 3u;
         const uint32_t len = ll + ml;
-        const uint32_t pincl = gscan<G>(len), lincl = gscan<G>(ll);
+        const uint32_t pincl = scan_add32(len), lincl = scan_add32(ll);
         const uint32_t P = pos + pincl - len, LP = lp + lincl - ll;
-        const uint32_t total = gread<G>(pincl, G - 1), ltot = gread<G>(lincl, G - 1);
+        const uint32_t total = rl32(pincl, 63), ltot = rl32(lincl, 63);
         const uint32_t D = P + ll;
         const bool bad = act && (uint64_t(P) + len > plain || uint64_t(LP) + ll > nlit ||
                                  (ml == 0 ? off != 0 : (off == 0 || off > D)));
-        if (gany<G>(bad)) {
-            corrupt();
+        if (any(bad)) {
+            flag(A.err, ERR_CORRUPT);
             return;
         }
         const uint32_t q0 = D - off;  // first source byte of the match
         const bool flat = ml == 0 || q0 + min(ml, off) <= pos || q0 >= P;
-        const uint32_t cnt = min(G, nseq - base);
+        const uint32_t cnt = min(64u, nseq - base);
         const uint32_t end = pos + total;
-        if (!gany<G>(!flat)) {
-            // Flat batch: every byte's source is final before the batch starts
-            // (earlier output) or is a literal of the same sequence.  Each lane
-            // owns one 16-byte aligned block of the batch's output at a time.
-            tab.pdel[gb + g] = make_uint4(P, D, P + len, LP);
-            tab.off[gb + g] = off;
-            wave_fence();
-            for (int32_t B = int32_t(pos) - int32_t((mis + pos) & (BLK - 1)) + int32_t(BLK * g);
-                 B < int32_t(end); B += int32_t(BLK * G)) {
-                const uint32_t p0 = uint32_t(max(B, int32_t(pos)));
-                const uint32_t pe = min(uint32_t(B) + BLK, end);
-                // sequence holding p0: the last one with P <= p0
-                uint32_t lo = 0, hi = cnt;
-                while (hi - lo > 1) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (tab.pdel[gb + mid].x <= p0) lo = mid;
-                    else hi = mid;
-                }
-                uint32_t sidx = gb + lo;
-                uint4 r = tab.pdel[sidx];
-                uint32_t so = tab.off[sidx];
-                // phase 1: where each byte comes from, as src = p + delta with
-                // delta constant over a segment (a literal run, or one period of
-                // a match); bit 31 of src set = a literal index.  Each lane walks
-                // its segments once and scatters the change of delta at each
-                // segment start into its LDS row (entry k of lane l at
-                // row[64k + l]); a prefix sum over the row then gives every
-                // byte's delta, so the per-byte work has no branch.
-                const uint32_t nb = uint32_t(B), l = lane_id();
-                uint32_t prev = 0;
+        if (!any(!flat)) {
+            // segment deltas of this lane's sequence: src = p + delta
+            const uint32_t dL = 0x80000000u + (LP - P);        // literal run
+            uint32_t dM = q0 - D;                              // match, first period
+            if (q0 >= P) dM += 0x80000000u + (LP - P);         // source in own literals
+            const int32_t B0 = int32_t(pos) - int32_t((mis + pos) & (BLK - 1));
+            uint32_t carry = 0;  // delta in force before the step (0: none yet)
+            for (int32_t W = B0; W < int32_t(end); W += int32_t(64 * BLK)) {
+                const uint32_t w0 = uint32_t(W), span = 64 * BLK;
 #pragma unroll
-                for (uint32_t k = 0; k < BLK; k++) row[64 * k + l] = 0;
-                uint32_t cur = p0;
-                while (cur < pe) {
-                    while (cur >= r.z) {  // next sequence (zero-length ones skipped)
-                        sidx++;
-                        r = tab.pdel[sidx];
-                        so = tab.off[sidx];
-                    }
-                    uint32_t delta, send;
-                    if (cur < r.y) {
-                        delta = 0x80000000u + (r.w - r.x);
-                        send = r.y;
+                for (uint32_t k = 0; k < BLK; k++) row[64 * k + lane] = 0;
+                wave_fence();
+                // scatter this sequence's segment starts that fall in the step
+                auto put = [&](uint32_t a, uint32_t d) {
+                    const uint32_t r = a - w0;
+                    if (r < span) row[64 * (r & (BLK - 1)) + r / BLK] = d;
+                };
+                if (act && ll) put(P, dL);
+                if (act && ml) {
+                    if (off >= ml) {
+                        put(D, dM);
                     } else {
-                        // a source inside the match itself repeats with period
-                        // so: one segment per period (the remainder is taken
-                        // only when the block starts past the first period)
-                        uint32_t j = cur - r.y;
-                        if (__builtin_expect(j >= so, 0)) j %= so;
-                        const uint32_t q = (r.y - so) + j;
-                        delta = q - cur;
-                        if (q >= pos) delta += 0x80000000u + (r.w - r.x);  // own literal
-                        send = min(r.z, cur + (so - j));
+                        // self-overlapping match: one segment per period of
+                        // length off, the delta falling by off each period;
+                        // only the periods that start inside the step
+                        uint32_t m = 0;
+                        if (w0 > D && int32_t(w0) > 0) m = (w0 - D + off - 1) / off;
+                        for (uint32_t a = D + m * off; a < D + ml && a - w0 < span; a += off, m++)
+                            put(a, dM - m * off);
                     }
-                    row[64 * (cur - nb) + l] = delta - prev;
-                    prev = delta;
-                    cur = min(send, pe);
                 }
-                const uint32_t k0 = p0 - nb, kn = pe - p0;
-                uint32_t src[BLK];
-                uint32_t acc = 0;
+                wave_fence();
+                // gather: block lane b owns bytes [w0 + BLK b, w0 + BLK b + BLK)
+                uint32_t v[BLK];
+                uint32_t last = 0;
 #pragma unroll
                 for (uint32_t k = 0; k < BLK; k++) {
-                    acc += row[64 * k + l];
-                    src[k] = nb + k + acc;
-                    // bytes outside [p0, pe) are never stored; with global
-                    // loads they must still read a valid address (out[0])
-                    if constexpr (G != 64) src[k] = (k - k0) < kn ? src[k] : 0u;
+                    v[k] = row[64 * k + lane];
+                    last = v[k] ? v[k] : last;
                 }
-                // phase 2: all BLK loads in flight together, with no branch
-                // between them
+                const uint32_t incl = scan_last_nonzero(last);
+                uint32_t cur = uint32_t(__builtin_amdgcn_ds_bpermute(int((lane - 1) * 4), int(incl)));
+                cur = (lane != 0 && cur) ? cur : carry;
+                const uint32_t tail = rl32(incl, 63);
+                carry = tail ? tail : carry;
+                const uint32_t Bb = w0 + BLK * lane;
                 uint32_t byte[BLK];
 #pragma unroll
                 for (uint32_t k = 0; k < BLK; k++) {
-                    const uint32_t x = src[k];
-                    if constexpr (G == 64) {
-                        // two bounds-checked byte loads, one of which is out
-                        // of range and reads 0: bit 31 of x puts a literal
-                        // index past the output, and its flip puts an output
-                        // position past the literals
-                        byte[k] = __builtin_amdgcn_raw_buffer_load_b8(rs_out, int(x), 0, 0) |
-                                  __builtin_amdgcn_raw_buffer_load_b8(rs_lit, int(x ^ 0x80000000u), 0, 0);
-                    } else {
-                        const uint8_t *a = (x & 0x80000000u) ? lits + (x & 0x7FFFFFFFu) : out + x;
-                        byte[k] = *gp(a);
-                    }
+                    cur = v[k] ? v[k] : cur;
+                    const uint32_t x = Bb + k + cur;
+                    byte[k] = __builtin_amdgcn_raw_buffer_load_b8(rs_out, int(x), 0, 0) |
+                              __builtin_amdgcn_raw_buffer_load_b8(rs_lit, int(x ^ 0x80000000u), 0, 0);
                 }
-                uint32_t w[BLK / 4];
+                uint32_t wv[BLK / 4];
 #pragma unroll
                 for (uint32_t d = 0; d < BLK / 4; d++)
-                    w[d] = byte[4 * d] | (byte[4 * d + 1] << 8) | (byte[4 * d + 2] << 16) | (byte[4 * d + 3] << 24);
-                if (p0 == uint32_t(B) && pe == uint32_t(B) + BLK) {
+                    wv[d] = byte[4 * d] | (byte[4 * d + 1] << 8) | (byte[4 * d + 2] << 16) | (byte[4 * d + 3] << 24);
+                const int32_t Bi = W + int32_t(BLK * lane);
+                if (Bi >= int32_t(pos) && Bi + int32_t(BLK) <= int32_t(end)) {
                     if constexpr (BLK == 16) {
-                        const u32x4 v = {w[0], w[1], w[2], w[3]};
-                        *gp(reinterpret_cast<u32x4 *>(out + B)) = v;
+                        const u32x4 vv = {wv[0], wv[1], wv[2], wv[3]};
+                        *gp(reinterpret_cast<u32x4 *>(out + Bi)) = vv;
                     } else if constexpr (BLK == 8) {
-                        const u32x2 v = {w[0], w[1]};
-                        *gp(reinterpret_cast<u32x2 *>(out + B)) = v;
+                        const u32x2 vv = {wv[0], wv[1]};
+                        *gp(reinterpret_cast<u32x2 *>(out + Bi)) = vv;
                     } else {
-                        *gp(reinterpret_cast<uint32_t *>(out + B)) = w[0];
+                        *gp(reinterpret_cast<uint32_t *>(out + Bi)) = wv[0];
                     }
-                } else {
+                } else if (Bi < int32_t(end) && Bi + int32_t(BLK) > int32_t(pos)) {
+                    const uint32_t p0 = uint32_t(max(Bi, int32_t(pos)));
+                    const uint32_t pe = min(uint32_t(Bi) + BLK, end);
                     for (uint32_t p = p0; p < pe; p++) {
-                        const uint32_t k = p - uint32_t(B);
-                        uint32_t wd = w[0];
+                        const uint32_t k = p - uint32_t(Bi);
+                        uint32_t wd = wv[0];
 #pragma unroll
-                        for (uint32_t d = 1; d < BLK / 4; d++) wd = k >= 4 * d ? w[d] : wd;
+                        for (uint32_t d = 1; d < BLK / 4; d++) wd = k >= 4 * d ? wv[d] : wd;
                         gp(out)[p] = uint8_t(wd >> (8 * (k & 3)));
                     }
                 }
+                wave_fence();
             }
-            wave_fence();
         } else {
             // in-order replay of this batch
             for (uint32_t k = 0; k < cnt; k++) {
-                const uint32_t Pk = gread<G>(P, k), llk = gread<G>(ll, k), LPk = gread<G>(LP, k);
-                const uint32_t mlk = gread<G>(ml, k), offk = gread<G>(off, k), Dk = Pk + llk;
-                for (uint32_t x = g; x < llk; x += G) out[Pk + x] = lits[LPk + x];
+                const uint32_t Pk = rl32(P, k), llk = rl32(ll, k), LPk = rl32(LP, k);
+                const uint32_t mlk = rl32(ml, k), offk = rl32(off, k), Dk = Pk + llk;
+                for (uint32_t x = lane; x < llk; x += 64) out[Pk + x] = lits[LPk + x];
                 wave_fence();
-                const uint32_t step = min(offk, G);
+                const uint32_t step = min(offk, 64u);
                 for (uint32_t j0 = 0; j0 < mlk; j0 += step) {
-                    const uint32_t j = j0 + g;
-                    if (g < step && j < mlk) out[Dk + j] = out[Dk - offk + j];
+                    const uint32_t j = j0 + lane;
+                    if (lane < step && j < mlk) out[Dk + j] = out[Dk - offk + j];
                     wave_fence();
                 }
             }
@@ -848,7 +799,7 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, LzSeq &tab, uint32
         tag = ntag;
         off = noff;
     }
-    if (pos != plain || lp != nlit || ep != next) corrupt();
+    if (pos != plain || lp != nlit || ep != next) flag(A.err, ERR_CORRUPT);
 }
 
 // ================================================================ PLAIN
@@ -883,7 +834,8 @@ ZF_DEV void unit_plain(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck) 
 // ============================================================== dispatch
 // UNR: FP lane-steps of loads kept in flight; 0 = runtime-width FP path.
 template <uint32_t UNR>
-ZF_DEV void run_unit(const LaunchArgs &A, uint32_t kind, uint32_t u, LzWave<16> *tab) {
+// lz_row: this wave's LDS row for LZ77 (64 * 16 dwords).
+ZF_DEV void run_unit(const LaunchArgs &A, uint32_t kind, uint32_t u, uint32_t *lz_row) {
     const Tile t = A.tiles[u];
     const ChunkDesc ck = A.chunks[t.chunk];
     switch (kind) {
@@ -895,7 +847,7 @@ ZF_DEV void run_unit(const LaunchArgs &A, uint32_t kind, uint32_t u, LzWave<16> 
     case K_DICT128: unit_fp<16, true, UNR>(A, t, ck); break;
     case K_RLE32: unit_rle<uint32_t>(A, t, ck); break;
     case K_RLE64: unit_rle<uint64_t>(A, t, ck); break;
-    case K_LZ: unit_lz<64, 16>(A, ck, tab->tab, tab->row); break;
+    case K_LZ: unit_lz<16>(A, ck, lz_row); break;
     }
 }
 
@@ -927,18 +879,17 @@ __global__ __launch_bounds__(1024) void k_decode_kind(LaunchArgs A) {
     }
 }
 
-// LZ77: each wave takes 64/G consecutive units, one per group of G lanes.
-template <uint32_t G, uint32_t BLK>
+// LZ77: one unit (chunk) per wave; each wave's LDS row is dynamic shared
+// memory, 64 * BLK dwords.
+template <uint32_t BLK>
 __global__ __launch_bounds__(1024) void k_decode_lz(LaunchArgs A) {
     const uint32_t waves = blockDim.x / 64;
-    const uint32_t w = blockIdx.x * waves + first32(threadIdx.x / 64);
-    const uint32_t u = A.kind_begin[K_LZ] + w * (64 / G) + (G == 64 ? 0u : lane_id() / G);
+    const uint32_t u = A.kind_begin[K_LZ] + blockIdx.x * waves + first32(threadIdx.x / 64);
     if (u >= A.kind_begin[K_LZ + 1]) return;
-    extern __shared__ uint4 lz_smem[];  // one LzWave per wave, sized at launch
-    LzWave<BLK> &me = reinterpret_cast<LzWave<BLK> *>(lz_smem)[threadIdx.x / 64];
-    unit_lz<G, BLK>(A, A.chunks[A.tiles[u].chunk], me.tab, me.row);
+    extern __shared__ uint32_t lz_smem[];
+    unit_lz<BLK>(A, A.chunks[A.tiles[u].chunk], lz_smem + (threadIdx.x / 64) * 64 * BLK);
 }
-void launch_lz(const LaunchArgs &A, uint32_t waves, uint32_t lanes, hipStream_t st);
+void launch_lz(const LaunchArgs &A, uint32_t waves, uint32_t blk, hipStream_t st);
 
 // Host launchers, one per kind, each defined in its kind's translation unit.
 #define ZF_KIND_LAUNCHERS(X)                                                                       \

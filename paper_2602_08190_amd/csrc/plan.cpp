@@ -148,7 +148,7 @@ void build_plan(zf_plan_t *P, const zf_column *const *cols, uint32_t n_cols, int
     ZF_HIP(hipGetDeviceProperties(&prop, device));
     P->cu_count = uint32_t(prop.multiProcessorCount);
     for (uint32_t k = 0; k < K_COUNT; k++) P->waves_per_block[k] = ts.wpb[k];
-    P->lz_lanes = ts.unit[K_LZ];
+    P->lz_blk = ts.unit[K_LZ];
     P->persistent_waves = o.persistent ? P->cu_count * ts.wpcu : 0;
 
     // ---- image layout and its tables
@@ -299,7 +299,7 @@ void build_plan(zf_plan_t *P, const zf_column *const *cols, uint32_t n_cols, int
         try {
             for (auto &b : P->batches) {
                 ZF_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-                hipError_t le = launch_decode(b.args, P->persistent_waves, P->waves_per_block, P->lz_lanes, cap);
+                hipError_t le = launch_decode(b.args, P->persistent_waves, P->waves_per_block, P->lz_blk, cap);
                 hipError_t ce = hipStreamEndCapture(cap, &b.graph);
                 ZF_HIP(le);
                 ZF_HIP(ce);

@@ -7,9 +7,9 @@
 struct zf_plan;
 namespace zf {
 
-// lz_lanes: lanes per LZ77 chunk in the per-kind launch (16, 32 or 64).
+// lz_blk: output bytes per block of the per-kind LZ77 kernel (4, 8 or 16).
 hipError_t launch_decode(const LaunchArgs &A, uint32_t persistent_waves, const uint32_t *waves_per_block,
-                         uint32_t lz_lanes, hipStream_t st);
+                         uint32_t lz_blk, hipStream_t st);
 hipError_t launch_set_out_tab(uint8_t **d_tab, uint8_t *const *ptrs, uint32_t n, hipStream_t st);
 
 struct CopyOp {
@@ -50,7 +50,7 @@ struct zf_plan {
 
     // launch configuration
     uint32_t persistent_waves = 0;  // 0: per-kind launches
-    uint32_t lz_lanes = 64;         // lanes per LZ77 chunk
+    uint32_t lz_blk = 16;         // LZ77 bytes per block
     uint32_t waves_per_block[zf::K_COUNT] = {4, 4, 4, 4, 4, 4, 4, 4, 4};
     uint32_t cu_count = 0;
 

@@ -25,7 +25,7 @@ void decompress_async(zf_plan_t *P, const void *d_comp, uint64_t comp_bytes, voi
     LaunchArgs A = P->image_args;
     A.comp = static_cast<const uint8_t *>(d_comp);
     A.dict = static_cast<const uint8_t *>(d_comp);
-    ZF_HIP(launch_decode(A, P->persistent_waves, P->waves_per_block, P->lz_lanes, st));
+    ZF_HIP(launch_decode(A, P->persistent_waves, P->waves_per_block, P->lz_blk, st));
     P->timing_valid = false;
 }
 
@@ -53,7 +53,7 @@ void transfer_and_decompress(zf_plan_t *P, void *const *d_out, hipStream_t st, z
         ZF_HIP(hipStreamWaitEvent(st, P->slot_full[s], 0));
         ZF_HIP(hipEventRecord(P->ev_dec0[k], st));
         if (b.exec) ZF_HIP(hipGraphLaunch(b.exec, st));
-        else ZF_HIP(launch_decode(b.args, P->persistent_waves, P->waves_per_block, P->lz_lanes, st));
+        else ZF_HIP(launch_decode(b.args, P->persistent_waves, P->waves_per_block, P->lz_blk, st));
         ZF_HIP(hipEventRecord(P->ev_dec1[k], st));
         ZF_HIP(hipEventRecord(P->slot_free[s], st));
     }

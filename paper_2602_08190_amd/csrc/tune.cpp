@@ -95,7 +95,7 @@ const char *kind_name(uint32_t k) { return k < K_COUNT ? kKindNames[k] : "?"; }
 TileShape default_tiles() {
     TileShape t;
     for (uint32_t k = 0; k < K_COUNT; k++) {
-        t.unit[k] = (k == K_PLAIN) ? 65536u : (k == K_RLE32 || k == K_RLE64) ? 4096u : (k == K_LZ) ? 64u : 2u;
+        t.unit[k] = (k == K_PLAIN) ? 65536u : (k == K_RLE32 || k == K_RLE64) ? 4096u : (k == K_LZ) ? 16u : 2u;
         t.wpb[k] = 4;
     }
     t.wpcu = 16;
@@ -169,12 +169,8 @@ TileShape resolve_tiles(const zf_plan_opts &o) {
     t.unit[K_RLE32] = std::max(64u, t.unit[K_RLE32]);
     t.unit[K_RLE64] = std::max(64u, t.unit[K_RLE64]);
     t.unit[K_PLAIN] = std::max(1024u, t.unit[K_PLAIN]);
-    // LZ77 knob: 4 or 8 (bytes per lane step, 64 lanes per chunk) or 16, 32, 64
-    // (lanes per chunk, 16 bytes per lane step)
-    {
-        const uint32_t u = t.unit[K_LZ];
-        t.unit[K_LZ] = u <= 4 ? 4u : u <= 8 ? 8u : u <= 16 ? 16u : u <= 32 ? 32u : 64u;
-    }
+    // LZ77: output bytes per block, 4, 8 or 16
+    t.unit[K_LZ] = t.unit[K_LZ] <= 4 ? 4u : t.unit[K_LZ] <= 8 ? 8u : 16u;
     return t;
 }
 

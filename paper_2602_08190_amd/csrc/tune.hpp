@@ -7,7 +7,7 @@
 namespace zf {
 
 struct TileShape {
-    uint32_t unit[K_COUNT];  // FP: blocks; GP: elements; PLAIN: bytes; LZ77: lanes per chunk
+    uint32_t unit[K_COUNT];  // FP: blocks; GP: elements; PLAIN: bytes; LZ77: bytes per block
     uint32_t wpb[K_COUNT];   // waves per workgroup
     uint32_t wpcu;           // persistent kernel: waves per CU
 };

@@ -51,6 +51,49 @@ def random_lz(rng, plain_len, max_lit=20, small_offsets=True):
     return seqs, bytes(lits)
 
 
+def flat_lz(rng, plain_len, empty_every=0):
+    """A random valid LZ77 sequence list whose every batch of 64 sequences is
+    flat (each match reads only bytes before its batch or its own literals),
+    rich in what the flat copy path must get right: matches repeating their
+    own literals with a short period, long matches spanning many copy steps,
+    sources far back, zero-length literal runs and (every `empty_every`-th
+    sequence, if nonzero) empty sequences."""
+    seqs, lits, pos, batch_start = [], bytearray(), 0, 0
+    while pos < plain_len:
+        if len(seqs) % 64 == 0:
+            batch_start = pos
+        if empty_every and pos > 0 and len(seqs) % empty_every == empty_every - 1:
+            seqs.append((0, 0, 0))
+            continue
+        room = plain_len - pos
+        kind = rng.random()
+        ll = int(rng.integers(0, 12)) if rng.random() < 0.85 else int(rng.integers(7, 200))
+        if pos == 0 and ll == 0:
+            ll = 1
+        ll = min(ll, room)
+        lits += bytes(rng.integers(0, 256, size=ll, dtype=np.uint8))
+        P, D = pos, pos + ll
+        pos = D
+        room = plain_len - pos
+        ml, off = 0, 0
+        if room >= 4 and kind < 0.35 and ll >= 1:
+            # period over its own literals (off <= ll), often long
+            off = int(rng.integers(1, min(ll, 9) + 1))
+            ml = int(min(room, rng.integers(4, 40) if rng.random() < 0.7 else rng.integers(34, 3000)))
+        elif room >= 4 and kind < 0.95 and batch_start >= 4:
+            # a copy from before the batch, without overlap
+            ml = int(min(room, batch_start, rng.integers(4, 30) if rng.random() < 0.9
+                         else rng.integers(34, 2500)))
+            if ml >= 4:
+                q0 = int(rng.integers(max(0, D - 65535), batch_start - ml + 1))
+                off = D - q0
+            else:
+                ml = 0
+        seqs.append((ll, ml, off))
+        pos += ml
+    return seqs, bytes(lits)
+
+
 def container(dtype, chunks, dictionary=b"", dict_count=0):
     """chunks: list of (stream_bytes, n_elems, codec)."""
     es = ES[dtype]

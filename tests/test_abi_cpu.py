@@ -14,6 +14,8 @@ import oracle.zfo as zo
 from paper_2602_08190_amd import datagen as g
 from paper_2602_08190_amd import zf
 
+import helpers as H
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -168,3 +170,23 @@ def test_empty_column():
     col = compress(np.zeros(0, np.int32), zf.FOR_BP)
     assert col.n_elems == 0 and col.n_chunks == 0
     assert zo.decode(col.bytes()).size == 0
+
+
+def test_flat_stream_generator_is_valid_and_flat():
+    """The GPU tests' flat LZ77 streams decode with the oracle and keep every
+    batch of 64 sequences flat."""
+    r = np.random.default_rng(21)
+    for t in range(12):
+        plen = int(r.integers(1, 65537)) if t % 3 else 65536
+        seqs, lits = H.flat_lz(r, plen, empty_every=7 if t % 4 == 0 else 0)
+        blob = H.container(zf.BYTES, [(H.lz_stream(seqs, lits, plen), plen, zf.LZ77)])
+        assert len(zo.decode(blob)) == plen
+        pos = bs = 0
+        for i, (ll, ml, off) in enumerate(seqs):
+            if i % 64 == 0:
+                bs = pos
+            D = pos + ll
+            if ml:
+                assert D - off + min(ml, off) <= bs or D - off >= pos
+            pos = D + ml
+        assert pos == plen

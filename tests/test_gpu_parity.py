@@ -171,44 +171,43 @@ def test_rle_config2_shape():
 
 
 # -------------------------------------------------------------- NP codec
-# LZ77 kernel knob: 16, 32, 64 lanes per chunk (4, 2, 1 chunks per wave) with
-# 16 output bytes per lane step; 4 and 8 bytes per lane step with 64 lanes
-LZ_LANES = [4, 8, 16, 32, 64]
+# LZ77 kernel knob: output bytes per block of the copy step
+LZ_BLK = [4, 8, 16]
 
 
-def lz_tiles(lanes):
-    return {"LZ77": dict(unit=lanes)}
+def lz_tiles(blk):
+    return {"LZ77": dict(unit=blk)}
 
 
-@pytest.mark.parametrize("lanes", LZ_LANES)
-def test_lz77_text_product_streams(lanes):
-    log("lz text", lanes)
+@pytest.mark.parametrize("blk", LZ_BLK)
+def test_lz77_text_product_streams(blk):
+    log("lz text", blk)
     x = g.text_column(3 << 20, seed=2)
     cols = [zf.Column.compress(x, zf.LZ77)]
     tail = g.text_column(65536 * 3 + 777, seed=3)
     cols.append(zf.Column.compress(tail, zf.LZ77))
-    check(cols, decode_image(cols, tiles=lz_tiles(lanes)), [x, tail])
+    check(cols, decode_image(cols, tiles=lz_tiles(blk)), [x, tail])
     check(cols, decode_image(cols, persistent=True), [x, tail])
 
 
-@pytest.mark.parametrize("lanes", LZ_LANES)
-def test_lz77_oracle_streams_use_the_ordered_path(lanes):
+@pytest.mark.parametrize("blk", LZ_BLK)
+def test_lz77_oracle_streams_use_the_ordered_path(blk):
     """The oracle's greedy encoder does not keep batches flat, so these
     streams take the in-order replay path."""
-    log("lz oracle streams", lanes)
+    log("lz oracle streams", blk)
     x = g.text_column(1 << 20, seed=4)
     blob = zo.encode(x, zo.LZ77, [65536] * 16)
     y = np.frombuffer(b"ab" * 30000 + b"abcabcabc" * 1000, np.uint8)
     blob2 = zo.encode(y, zo.LZ77, [65536, len(y) - 65536])
     cols = [zf.Column.from_bytes(blob), zf.Column.from_bytes(blob2)]
-    check(cols, decode_image(cols, tiles=lz_tiles(lanes)), [x, y])
+    check(cols, decode_image(cols, tiles=lz_tiles(blk)), [x, y])
 
 
-@pytest.mark.parametrize("lanes", LZ_LANES)
-def test_lz77_random_valid_streams(lanes):
+@pytest.mark.parametrize("blk", LZ_BLK)
+def test_lz77_random_valid_streams(blk):
     """Random valid streams the encoders never write: self-overlapping
     matches, offsets into the same batch, long escapes, ragged chunk sizes."""
-    log("lz random streams", lanes)
+    log("lz random streams", blk)
     r = np.random.default_rng(11)
     chunks = []
     for i in range(24):
@@ -217,7 +216,24 @@ def test_lz77_random_valid_streams(lanes):
         chunks.append((H.lz_stream(seqs, lits, plen), plen, zf.LZ77))
     blob = H.container(zf.BYTES, chunks)
     cols = [zf.Column.from_bytes(blob)]
-    check(cols, decode_image(cols, tiles=lz_tiles(lanes)))
+    check(cols, decode_image(cols, tiles=lz_tiles(blk)))
+    check(cols, decode_image(cols, persistent=True))
+
+
+@pytest.mark.parametrize("blk", LZ_BLK)
+def test_lz77_flat_batches_with_periods_long_matches_and_empties(blk):
+    """Flat streams the product encoder rarely writes: matches repeating their
+    own literals with periods 1..9, matches of thousands of bytes spanning
+    many copy steps, far sources, zero-length runs and empty sequences."""
+    log("lz flat streams", blk)
+    r = np.random.default_rng(21)
+    chunks = []
+    for t in range(30):
+        plen = int(r.integers(1, 65537)) if t % 3 else 65536
+        seqs, lits = H.flat_lz(r, plen, empty_every=7 if t % 4 == 0 else 0)
+        chunks.append((H.lz_stream(seqs, lits, plen), plen, zf.LZ77))
+    cols = [zf.Column.from_bytes(H.container(zf.BYTES, chunks))]
+    check(cols, decode_image(cols, tiles=lz_tiles(blk)))
     check(cols, decode_image(cols, persistent=True))
 
 
@@ -226,12 +242,12 @@ def _chunk_streams(blob):
             for c in zo.chunks(blob)]
 
 
-@pytest.mark.parametrize("lanes", LZ_LANES)
-def test_lz77_groups_of_one_wave_diverge(lanes):
-    """Neighbouring chunks (decoded by the groups of one wave) alternate
-    between flat product streams, replayed oracle streams and tiny chunks,
-    and the chunk count leaves the last wave partly empty."""
-    log("lz divergent groups", lanes)
+@pytest.mark.parametrize("blk", LZ_BLK)
+def test_lz77_flat_and_replayed_chunks_interleaved(blk):
+    """Neighbouring chunks alternate between flat product streams, replayed
+    oracle streams and tiny chunks, and the chunk count leaves the last
+    workgroup partly empty."""
+    log("lz divergent groups", blk)
     x = g.text_column(9 * 65536, seed=8)
     prod = _chunk_streams(zf.Column.compress(x, zf.LZ77).bytes())
     orc = _chunk_streams(zo.encode(x, zo.LZ77, [65536] * 9))
@@ -246,7 +262,7 @@ def test_lz77_groups_of_one_wave_diverge(lanes):
             chunks.append((H.lz_stream(seqs, lits, 5 + i), 5 + i, zf.LZ77))
             ref.append(None)
     cols = [zf.Column.from_bytes(H.container(zf.BYTES, chunks))]
-    out = decode_image(cols, tiles=lz_tiles(lanes))
+    out = decode_image(cols, tiles=lz_tiles(blk))
     check(cols, out)
     at = 0
     for (s, n, _), want in zip(chunks, ref):
@@ -255,12 +271,12 @@ def test_lz77_groups_of_one_wave_diverge(lanes):
         at += n
 
 
-@pytest.mark.parametrize("lanes", LZ_LANES)
-def test_lz77_int_columns(lanes):
-    log("lz ints", lanes)
+@pytest.mark.parametrize("blk", LZ_BLK)
+def test_lz77_int_columns(blk):
+    log("lz ints", blk)
     x = g.sorted_runs_column(100000, 8, 5)
     cols = [zf.Column.compress(x, zf.LZ77)]
-    check(cols, decode_image(cols, tiles=lz_tiles(lanes)), [x])
+    check(cols, decode_image(cols, tiles=lz_tiles(blk)), [x])
 
 
 # ------------------------------------------------------- mixed + staged
@@ -331,15 +347,15 @@ def test_device_detects_corrupt_streams():
     by the kernels' own checks and reported by zf_sync."""
     log("corrupt")
     # LZ77: an offset beyond the bytes produced so far; a match running past
-    # the chunk end (alone, and as the third chunk of a wave's groups)
+    # the chunk end (alone, and as the third of four chunks)
     good = H.lz_stream([(3, 9, 3), (1, 0, 0)], b"abcX", 13)
     for s in (H.lz_stream([(3, 9, 5), (1, 0, 0)], b"abcX", 13),
               H.lz_stream([(3, 12, 3), (1, 0, 0)], b"abcX", 13)):
-        for lanes in LZ_LANES:
+        for blk in LZ_BLK:
             _expect_corrupt([zf.Column.from_bytes(H.container(zf.BYTES, [(s, 13, zf.LZ77)]))],
-                            tiles=lz_tiles(lanes))
+                            tiles=lz_tiles(blk))
             blob = H.container(zf.BYTES, [(good, 13, zf.LZ77)] * 2 + [(s, 13, zf.LZ77), (good, 13, zf.LZ77)])
-            _expect_corrupt([zf.Column.from_bytes(blob)], tiles=lz_tiles(lanes))
+            _expect_corrupt([zf.Column.from_bytes(blob)], tiles=lz_tiles(blk))
     # RLE: run lengths that do not add up to the chunk
     x = g.sorted_runs_column(5000, 8, 1)
     b = zo.encode(x, zo.RLE_DELTA_BP).copy()
