@@ -742,6 +742,10 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, uint32_t *row) {
                 const uint32_t tail = rl32(incl, 63);
                 carry = tail ? tail : carry;
                 const uint32_t Bb = w0 + BLK * lane;
+                const int32_t Bi = W + int32_t(BLK * lane);
+                // a block wholly outside [pos, end) has no segment start; its
+                // reads are sent out of range of both views (no memory traffic)
+                if (Bi + int32_t(BLK) <= int32_t(pos) || Bi >= int32_t(end)) cur = 0x7FFFFFF0u - Bb;
                 uint32_t byte[BLK];
 #pragma unroll
                 for (uint32_t k = 0; k < BLK; k++) {
@@ -754,7 +758,6 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, uint32_t *row) {
 #pragma unroll
                 for (uint32_t d = 0; d < BLK / 4; d++)
                     wv[d] = byte[4 * d] | (byte[4 * d + 1] << 8) | (byte[4 * d + 2] << 16) | (byte[4 * d + 3] << 24);
-                const int32_t Bi = W + int32_t(BLK * lane);
                 if (Bi >= int32_t(pos) && Bi + int32_t(BLK) <= int32_t(end)) {
                     if constexpr (BLK == 16) {
                         const u32x4 vv = {wv[0], wv[1], wv[2], wv[3]};
