@@ -87,6 +87,26 @@ ZF_DEV T scan_addT(T x) {
     if constexpr (sizeof(T) == 8) return T(scan_add64(uint64_t(x)));
     else return T(scan_add32(uint32_t(x)));
 }
+// Inclusive scan across the wave keeping the value of the highest lane whose
+// x is nonzero (0 where no lane up to this one has one); the same DPP moves
+// as scan_add32.
+ZF_DEV uint32_t scan_last_nonzero(uint32_t x) {
+    uint32_t t;
+    t = dpp<0x111, 0xF>(x);
+    x = x ? x : t;
+    t = dpp<0x112, 0xF>(x);
+    x = x ? x : t;
+    t = dpp<0x114, 0xF>(x);
+    x = x ? x : t;
+    t = dpp<0x118, 0xF>(x);
+    x = x ? x : t;
+    t = dpp<0x142, 0xA>(x);
+    x = x ? x : t;
+    t = dpp<0x143, 0xC>(x);
+    x = x ? x : t;
+    return x;
+}
+
 ZF_DEV uint32_t wave_max32(uint32_t x) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) x = max(x, uint32_t(__shfl_xor(x, d, 64)));
@@ -474,9 +494,23 @@ ZF_DEV void unit_fp(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck) {
 
 // ===================================================== Group-Parallel
 // One wave writes elements [t.b, t.c) of an RLE_DELTA_BP / DELTA_BP chunk,
-// starting at group t.a.
+// starting at group t.a.  Per group of 64 runs, lane j holds run j: an
+// exclusive scan of the run lengths gives the run starts (the paper's presum,
+// fused), an inclusive scan of dmin + field gives the run values.  The next
+// group's record, run lengths and packed words are loaded while this one is
+// expanded.  Expansion goes by windows of 64 outputs: each run starting in
+// the window writes its index into an LDS slot at its start, a wave scan
+// carries the latest index over the window, and each lane takes its value
+// with a cross-lane permute — no per-run loop.  slot: this wave's 64 dwords.
 template <class T>
-ZF_DEV void unit_rle(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck) {
+struct RleGroup {
+    uint32_t goff, w, doff, next_off, r, w0, w1, w2;
+    T base, dmin;
+    bool ok;
+};
+
+template <class T>
+ZF_DEV void unit_rle(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, uint32_t *slot) {
     using U = T;  // unsigned value type: uint32_t or uint64_t
     constexpr uint32_t BITS = sizeof(T) * 8;
     const uint8_t *s = A.comp + ck.comp_off;
@@ -492,76 +526,105 @@ ZF_DEV void unit_rle(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck) {
     if (unit_runs) hdr_ok = hdr_ok && nr == n && roff == 0;
     else hdr_ok = hdr_ok && (roff & 3u) == 0 && roff >= 16ull + 32ull * ng && roff + 4ull * nr <= clen;
     const uint32_t e0 = t.b, e1 = t.c;
-    if (!hdr_ok || e1 > n || e0 >= e1) {
+    if (!hdr_ok || e1 > n || e0 >= e1 || t.a >= ng) {
         flag(A.err, ERR_CORRUPT);
         return;
     }
     const uint32_t *runs = reinterpret_cast<const uint32_t *>(s + roff);
-    for (uint32_t g = t.a;; g++) {
-        if (g >= ng) {
-            flag(A.err, ERR_CORRUPT);
-            return;
-        }
+    // record, run length and packed words of group g (bounds checked before
+    // any load that depends on the record)
+    auto load = [&](uint32_t g, RleGroup<U> &G) {
         const uint8_t *rec = s + 16 + 32ull * g;
-        const uint32_t goff = ld32u(rec), w = ld32u(rec + 4), doff = ld32u(rec + 8);
-        const U base = U(ld64u(rec + 16)), dmin = U(ld64u(rec + 24));
+        G.goff = ld32u(rec);
+        G.w = ld32u(rec + 4);
+        G.doff = ld32u(rec + 8);
+        G.base = U(ld64u(rec + 16));
+        G.dmin = U(ld64u(rec + 24));
+        G.next_off = (g + 1 < ng) ? ld32u(rec + 32) : n;
         const uint32_t cnt = min(kRleGroup, nr - g * kRleGroup);
-        const uint64_t nwords = (uint64_t(cnt - 1) * w + 31) / 32;
-        const uint32_t next_off = (g + 1 < ng) ? ld32u(rec + 32) : n;
-        if (w > BITS || (doff & 3u) || doff + 4 * nwords > clen || (g == t.a && goff > e0) ||
-            next_off > n) {
+        const uint64_t nwords = (uint64_t(cnt - 1) * min(G.w, 64u) + 31) / 32;
+        G.ok = G.w <= BITS && (G.doff & 3u) == 0 && G.doff + 4 * nwords <= clen && G.next_off <= n;
+        const bool act = lane < cnt;
+        G.r = act ? (unit_runs ? 1u : runs[uint64_t(g) * kRleGroup + lane]) : 0u;
+        G.w0 = G.w1 = G.w2 = 0;
+        if (G.ok && lane >= 1 && act) {
+            const uint64_t bit = uint64_t(lane - 1) * G.w;
+            const uint32_t *words = reinterpret_cast<const uint32_t *>(s + G.doff);
+            const uint64_t k = bit >> 5;
+            G.w0 = k < nwords ? words[k] : 0u;
+            G.w1 = k + 1 < nwords ? words[k + 1] : 0u;
+            if constexpr (BITS == 64) G.w2 = k + 2 < nwords ? words[k + 2] : 0u;
+        }
+    };
+    RleGroup<U> cur, nxt;
+    load(t.a, cur);
+    for (uint32_t g = t.a;; g++) {
+        if (!cur.ok || (g == t.a && cur.goff > e0)) {
             flag(A.err, ERR_CORRUPT);
             return;
         }
+        const bool more = cur.next_off < e1;
+        if (more) {
+            if (g + 1 >= ng) {
+                flag(A.err, ERR_CORRUPT);
+                return;
+            }
+            load(g + 1, nxt);  // in flight while this group is expanded
+        }
+        const uint32_t cnt = min(kRleGroup, nr - g * kRleGroup);
         // run lengths -> output offsets (exclusive scan = presum)
         const bool act = lane < cnt;
-        const uint32_t r = act ? (unit_runs ? 1u : runs[uint64_t(g) * kRleGroup + lane]) : 0u;
+        const uint32_t r = cur.r;
         const uint64_t incl = scan_add64(r);
         const uint64_t total = rl64(incl, cnt - 1);
-        if (any(act && r == 0) || uint64_t(goff) + total != next_off) {
+        if (any(act && r == 0) || uint64_t(cur.goff) + total != cur.next_off) {
             flag(A.err, ERR_CORRUPT);
             return;
         }
-        const uint32_t end_abs = goff + uint32_t(incl);  // end of run `lane`
+        const uint32_t end_abs = cur.goff + uint32_t(incl);  // end of run `lane`
+        const uint32_t start_abs = end_abs - r;
         // run values: base, then base + prefix sums of (dmin + field)
-        U delta = base;
+        U delta = cur.base;
         if (lane >= 1 && act) {
-            const uint64_t bit = uint64_t(lane - 1) * w;
-            const uint32_t *words = reinterpret_cast<const uint32_t *>(s + doff);
-            const uint64_t k = bit >> 5;
-            const uint32_t sh = uint32_t(bit & 31u);
-            const uint32_t w0 = k < nwords ? words[k] : 0u;
-            const uint32_t w1 = k + 1 < nwords ? words[k + 1] : 0u;
+            const uint32_t sh = uint32_t((uint64_t(lane - 1) * cur.w) & 31u);
             U f;
             if constexpr (BITS == 32) {
-                f = uint32_t((uint64_t(w0) | (uint64_t(w1) << 32)) >> sh) & mask32(w);
+                f = uint32_t((uint64_t(cur.w0) | (uint64_t(cur.w1) << 32)) >> sh) & mask32(cur.w);
             } else {
-                const uint32_t w2 = k + 2 < nwords ? words[k + 2] : 0u;
-                const uint64_t lo = uint64_t(w0) | (uint64_t(w1) << 32);
-                f = (sh ? ((lo >> sh) | (uint64_t(w2) << (64 - sh))) : lo) & mask64(w);
+                const uint64_t lo = uint64_t(cur.w0) | (uint64_t(cur.w1) << 32);
+                f = (sh ? ((lo >> sh) | (uint64_t(cur.w2) << (64 - sh))) : lo) & mask64(cur.w);
             }
-            delta = U(dmin + f);
+            delta = U(cur.dmin + f);
         }
         const U v = scan_addT<U>(act ? delta : U(0));
         // expand the part of this group inside [e0, e1)
-        const uint32_t a = max(e0, goff), bnd = min(e1, next_off);
+        const uint32_t a = max(e0, cur.goff), bnd = min(e1, cur.next_off);
         if (a < bnd) {
-            uint32_t j = uint32_t(__popcll(__ballot(act && end_abs <= a)));  // run holding a
+            uint32_t jc = uint32_t(__popcll(__ballot(act && end_abs <= a)));  // run holding a
             for (uint32_t W0 = a; W0 < bnd; W0 += 64) {
-                const uint32_t wend = W0 + 64, p = W0 + lane;
-                U val = rlT<U>(v, j);
-                uint32_t k = j;
-                while (k + 1 < cnt) {
-                    const uint32_t st = rl32(end_abs, k);  // start of run k+1
-                    if (st >= wend) break;
-                    k++;
-                    if (p >= st) val = rlT<U>(v, k);
+                slot[lane] = 0;
+                wave_fence();
+                const uint32_t rel = start_abs - W0;
+                if (act && rel < 64u) slot[rel] = lane + 1;
+                wave_fence();
+                const uint32_t latest = scan_last_nonzero(slot[lane]);
+                const uint32_t idx = latest ? latest - 1 : jc;
+                U val;
+                if constexpr (BITS == 32) {
+                    val = uint32_t(__builtin_amdgcn_ds_bpermute(int(idx * 4), int(v)));
+                } else {
+                    const uint32_t lo = uint32_t(__builtin_amdgcn_ds_bpermute(int(idx * 4), int(uint32_t(v))));
+                    const uint32_t hi = uint32_t(__builtin_amdgcn_ds_bpermute(int(idx * 4), int(uint32_t(v >> 32))));
+                    val = uint64_t(lo) | (uint64_t(hi) << 32);
                 }
-                if (p < bnd) out[p] = val;
-                j = (rl32(end_abs, k) <= wend) ? k + 1 : k;
+                const uint32_t p = W0 + lane;
+                if (p < bnd) __builtin_nontemporal_store(val, gp(out + p));
+                jc = rl32(idx, 63);
+                wave_fence();
             }
         }
-        if (next_off >= e1) return;
+        if (!more) return;
+        cur = nxt;
     }
 }
 
@@ -586,25 +649,6 @@ ZF_DEV uint32_t ext_pick(uint32_t ew, uint32_t k) {
     return (k & 64u) ? v >> 16 : v & 0xFFFFu;
 }
 
-// Inclusive scan across the wave keeping the value of the highest lane whose
-// x is nonzero (0 where no lane up to this one has one); the same DPP moves
-// as scan_add32.
-ZF_DEV uint32_t scan_last_nonzero(uint32_t x) {
-    uint32_t t;
-    t = dpp<0x111, 0xF>(x);
-    x = x ? x : t;
-    t = dpp<0x112, 0xF>(x);
-    x = x ? x : t;
-    t = dpp<0x114, 0xF>(x);
-    x = x ? x : t;
-    t = dpp<0x118, 0xF>(x);
-    x = x ? x : t;
-    t = dpp<0x142, 0xA>(x);
-    x = x ? x : t;
-    t = dpp<0x143, 0xC>(x);
-    x = x ? x : t;
-    return x;
-}
 
 // Flat batches (every match reads bytes before the batch or its own
 // literals; the product encoder keeps every batch flat) are copied without
@@ -837,7 +881,8 @@ ZF_DEV void unit_plain(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck) 
 // ============================================================== dispatch
 // UNR: FP lane-steps of loads kept in flight; 0 = runtime-width FP path.
 template <uint32_t UNR>
-// lz_row: this wave's LDS row for LZ77 (64 * 16 dwords).
+// lz_row: this wave's LDS scratch (64 * 16 dwords): the LZ77 row, or the RLE
+// window slots.
 ZF_DEV void run_unit(const LaunchArgs &A, uint32_t kind, uint32_t u, uint32_t *lz_row) {
     const Tile t = A.tiles[u];
     const ChunkDesc ck = A.chunks[t.chunk];
@@ -848,8 +893,8 @@ ZF_DEV void run_unit(const LaunchArgs &A, uint32_t kind, uint32_t u, uint32_t *l
     case K_DICT32: unit_fp<4, true, UNR>(A, t, ck); break;
     case K_DICT64: unit_fp<8, true, UNR>(A, t, ck); break;
     case K_DICT128: unit_fp<16, true, UNR>(A, t, ck); break;
-    case K_RLE32: unit_rle<uint32_t>(A, t, ck); break;
-    case K_RLE64: unit_rle<uint64_t>(A, t, ck); break;
+    case K_RLE32: unit_rle<uint32_t>(A, t, ck, lz_row); break;
+    case K_RLE64: unit_rle<uint64_t>(A, t, ck, lz_row); break;
     case K_LZ: unit_lz<16>(A, ck, lz_row); break;
     }
 }
@@ -876,9 +921,11 @@ __global__ __launch_bounds__(1024) void k_decode_kind(LaunchArgs A) {
     } else if constexpr (KIND == K_DICT128) {
         unit_fp<16, true, 8>(A, t, ck);
     } else if constexpr (KIND == K_RLE32) {
-        unit_rle<uint32_t>(A, t, ck);
+        __shared__ uint32_t rle_slots[16][64];
+        unit_rle<uint32_t>(A, t, ck, rle_slots[threadIdx.x / 64]);
     } else if constexpr (KIND == K_RLE64) {
-        unit_rle<uint64_t>(A, t, ck);
+        __shared__ uint32_t rle_slots[16][64];
+        unit_rle<uint64_t>(A, t, ck, rle_slots[threadIdx.x / 64]);
     }
 }
 
