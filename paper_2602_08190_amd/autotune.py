@@ -31,7 +31,7 @@ DEFAULT_OUT = os.path.join(HERE, "tune_gfx950.json")
 WPB = [1, 2, 4, 8, 16]                       # S = 64 .. 1024 lanes
 UNITS = {
     "FP": [1, 2, 4, 8, 16],                  # L: 2048-value blocks per wave
-    "GP": [512, 1024, 2048, 4096, 8192, 16384],
+    "GP": [256, 512, 1024, 2048, 4096, 8192],
     "PLAIN": [16384, 65536, 262144, 1048576],
     "NP": [4, 8, 16],                        # LZ77: output bytes per block
 }

@@ -498,10 +498,11 @@ ZF_DEV void unit_fp(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck) {
 // exclusive scan of the run lengths gives the run starts (the paper's presum,
 // fused), an inclusive scan of dmin + field gives the run values.  The next
 // group's record, run lengths and packed words are loaded while this one is
-// expanded.  Expansion goes by windows of 64 outputs: each run starting in
-// the window writes its index into an LDS slot at its start, a wave scan
-// carries the latest index over the window, and each lane takes its value
-// with a cross-lane permute — no per-run loop.  slot: this wave's 64 dwords.
+// expanded.  Expansion goes by windows of 64 lanes x 16 bytes of output:
+// each run starting in the window writes its index into an LDS slot at its
+// start, a wave scan carries the latest index over the window, and each lane
+// takes its values with cross-lane permutes — no per-run loop.  slot: this
+// wave's 256 dwords.
 template <class T>
 struct RleGroup {
     uint32_t goff, w, doff, next_off, r, w0, w1, w2;
@@ -597,29 +598,60 @@ ZF_DEV void unit_rle(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, ui
             delta = U(cur.dmin + f);
         }
         const U v = scan_addT<U>(act ? delta : U(0));
-        // expand the part of this group inside [e0, e1)
+        // expand the part of this group inside [e0, e1), R outputs per lane
+        // per window (16 bytes: one aligned store when whole)
+        constexpr uint32_t R = 16 / sizeof(U), SPAN = 64 * R;
         const uint32_t a = max(e0, cur.goff), bnd = min(e1, cur.next_off);
         if (a < bnd) {
-            uint32_t jc = uint32_t(__popcll(__ballot(act && end_abs <= a)));  // run holding a
-            for (uint32_t W0 = a; W0 < bnd; W0 += 64) {
-                slot[lane] = 0;
+            // window grid aligned so that out + W0 + R * lane is 16-byte aligned
+            // (signed: the first window may start before element 0)
+            const int32_t mis = int32_t((reinterpret_cast<uintptr_t>(out + a) & 15u) / sizeof(U));
+            const int32_t ia = int32_t(a), ib = int32_t(bnd);
+            // 1 + index of the run holding a (a run index, plus one, marks a start)
+            uint32_t carry = 1 + uint32_t(__popcll(__ballot(act && end_abs <= a)));
+            for (int32_t W0 = ia - mis; W0 < ib; W0 += int32_t(SPAN)) {
+#pragma unroll
+                for (uint32_t i = 0; i < R; i++) slot[64 * i + lane] = 0;
                 wave_fence();
-                const uint32_t rel = start_abs - W0;
-                if (act && rel < 64u) slot[rel] = lane + 1;
+                // element W0 + R l + i has slot 64 i + l
+                const uint32_t rel = start_abs - uint32_t(W0);
+                if (act && rel < SPAN && start_abs >= a) slot[64 * (rel % R) + rel / R] = lane + 1;
                 wave_fence();
-                const uint32_t latest = scan_last_nonzero(slot[lane]);
-                const uint32_t idx = latest ? latest - 1 : jc;
-                U val;
-                if constexpr (BITS == 32) {
-                    val = uint32_t(__builtin_amdgcn_ds_bpermute(int(idx * 4), int(v)));
-                } else {
-                    const uint32_t lo = uint32_t(__builtin_amdgcn_ds_bpermute(int(idx * 4), int(uint32_t(v))));
-                    const uint32_t hi = uint32_t(__builtin_amdgcn_ds_bpermute(int(idx * 4), int(uint32_t(v >> 32))));
-                    val = uint64_t(lo) | (uint64_t(hi) << 32);
+                uint32_t m[R], last = 0;
+#pragma unroll
+                for (uint32_t i = 0; i < R; i++) {
+                    m[i] = slot[64 * i + lane];
+                    last = m[i] ? m[i] : last;
                 }
-                const uint32_t p = W0 + lane;
-                if (p < bnd) __builtin_nontemporal_store(val, gp(out + p));
-                jc = rl32(idx, 63);
+                const uint32_t inc = scan_last_nonzero(last);
+                uint32_t cur1 = uint32_t(__builtin_amdgcn_ds_bpermute(int((lane - 1) * 4), int(inc)));
+                cur1 = (lane != 0 && cur1) ? cur1 : carry;
+                const uint32_t tail = rl32(inc, 63);
+                carry = tail ? tail : carry;
+                U val[R];
+#pragma unroll
+                for (uint32_t i = 0; i < R; i++) {
+                    cur1 = m[i] ? m[i] : cur1;
+                    const int src = int((cur1 - 1) * 4);
+                    if constexpr (BITS == 32) {
+                        val[i] = uint32_t(__builtin_amdgcn_ds_bpermute(src, int(v)));
+                    } else {
+                        const uint32_t lo = uint32_t(__builtin_amdgcn_ds_bpermute(src, int(uint32_t(v))));
+                        const uint32_t hi = uint32_t(__builtin_amdgcn_ds_bpermute(src, int(uint32_t(v >> 32))));
+                        val[i] = uint64_t(lo) | (uint64_t(hi) << 32);
+                    }
+                }
+                const int32_t p = W0 + int32_t(R * lane);
+                if (p >= ia && p + int32_t(R) <= ib) {
+                    u32x4 q;
+                    if constexpr (BITS == 32) q = u32x4{val[0], val[1], val[2], val[3]};
+                    else q = u32x4{uint32_t(val[0]), uint32_t(val[0] >> 32), uint32_t(val[1]), uint32_t(val[1] >> 32)};
+                    __builtin_nontemporal_store(q, gp(reinterpret_cast<u32x4 *>(out + p)));
+                } else {
+#pragma unroll
+                    for (int32_t i = 0; i < int32_t(R); i++)
+                        if (p + i >= ia && p + i < ib) out[p + i] = val[i];
+                }
                 wave_fence();
             }
         }
@@ -921,10 +953,10 @@ __global__ __launch_bounds__(1024) void k_decode_kind(LaunchArgs A) {
     } else if constexpr (KIND == K_DICT128) {
         unit_fp<16, true, 8>(A, t, ck);
     } else if constexpr (KIND == K_RLE32) {
-        __shared__ uint32_t rle_slots[16][64];
+        __shared__ uint32_t rle_slots[16][256];
         unit_rle<uint32_t>(A, t, ck, rle_slots[threadIdx.x / 64]);
     } else if constexpr (KIND == K_RLE64) {
-        __shared__ uint32_t rle_slots[16][64];
+        __shared__ uint32_t rle_slots[16][256];
         unit_rle<uint64_t>(A, t, ck, rle_slots[threadIdx.x / 64]);
     }
 }
