@@ -14,7 +14,7 @@ def build(force=True):
     if not force and os.path.exists(LIB):
         return LIB
     tmp = LIB + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-fPIC", "-shared", "-o", tmp] + SRC
+    cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-fPIC", "-shared", "-o", tmp] + SRC + ["-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB

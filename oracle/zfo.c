@@ -28,6 +28,7 @@
  */
 #include "zfo.h"
 
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -77,6 +78,7 @@ uint32_t zfo_elem_size(uint32_t dtype) {
     case ZFO_I64: return 8;
     case ZFO_BYTES: return 1;
     case ZFO_FIXED16: return 16;
+    case ZFO_F64: return 8;
     default: return 0;
     }
 }
@@ -204,6 +206,156 @@ static int dec_for_bp_u64(const uint8_t *s, uint64_t comp_len, uint32_t n, uint3
         if (poff + 4 * packed_words(nv, w) > comp_len) return ZFO_ECORRUPT;
         for (uint32_t j = 0; j < nv; j++)
             out[j0 + j] = (ref + unpack_bits(s + poff, j, w)) & mask;
+    }
+    return ZFO_OK;
+}
+
+/* ============================================================= Float2Int
+ * Decimal floating point to integers (Sec. 2.1 names Float2Int: significant
+ * digits and exponent split into integers; it fixes no layout, so this one is
+ * the zf format's).  In block b a float64 value v is represented by the
+ * integer d with
+ *     bits(v) == bits((double)d / 10^e_b)
+ * (IEEE binary64 division, round to nearest even; 10^e exact for e <= 18;
+ * (double)d the round-to-nearest conversion of the int64 d).  Values with no
+ * such d -- NaN, infinities, -0.0, more digits than e_b allows, magnitudes of
+ * 2^62 * 10^-e_b or more -- are exceptions, stored raw.  The d of a block are
+ * then FOR + bit-packed (Float2Int nested with bit-packing, Table 2).
+ * Stream for a chunk of n values, B = 2048, nb = ceil(n/B) blocks:
+ *   block directory, 32 bytes per block at offset 32*b:
+ *       i64 ref, u32 w, u32 poff, u32 xoff, u16 nx, u8 e, u8 0, 8 zero bytes
+ *   payload at poff (16-aligned): field_j = d_j - ref packed at width w, an
+ *       exception holding field 0;
+ *   exceptions at xoff (16-aligned): nx records of 16 bytes
+ *       {u32 j (index in the block, strictly increasing), u32 0, u64 bits};
+ *   blocks in order, each its payload then its exceptions;
+ *   poff_0 = align16(32*nb); xoff_b = align16(poff_b + 4*words_b);
+ *   poff_{b+1} = align16(xoff_b + 16*nx_b); comp_len = xoff_last + 16*nx_last.
+ * The encoder's choice of e_b: for e = 0..18 every value gets
+ * d = nearbyint(v * 10^e) when |v * 10^e| < 2^62 and the round trip above
+ * holds, else it is an exception; cost(e) = nv*w(e) + 128*nx(e) bits, where
+ * w(e) is the bit length of max(d) - min(d) over the non-exceptions; the
+ * smallest cost wins, ties going to the smaller e; ref = min(d) (0 when every
+ * value is an exception).
+ * Decode: x_j = bits of (double)(int64)(ref + field_j) / 10^e, then every
+ * exception record overwrites its x_j. */
+static const double F2I_P10[19] = {1e0,  1e1,  1e2,  1e3,  1e4,  1e5,  1e6,  1e7,  1e8, 1e9,
+                                   1e10, 1e11, 1e12, 1e13, 1e14, 1e15, 1e16, 1e17, 1e18};
+#define F2I_EMAX 18u
+
+static uint64_t f64_bits(double v) {
+    uint64_t b;
+    memcpy(&b, &v, 8);
+    return b;
+}
+static double f64_from(uint64_t b) {
+    double v;
+    memcpy(&v, &b, 8);
+    return v;
+}
+
+/* the d of value bits b at exponent e, if it round-trips */
+static int f2i_digits(uint64_t b, uint32_t e, int64_t *d) {
+    double m = f64_from(b) * F2I_P10[e];
+    if (!(fabs(m) < 4611686018427387904.0)) return 0; /* 2^62; false for NaN */
+    int64_t k = (int64_t)nearbyint(m);
+    if (f64_bits((double)k / F2I_P10[e]) != b) return 0;
+    *d = k;
+    return 1;
+}
+
+static void enc_f2i_bp(buf_t *s, const uint8_t *x, uint32_t n) {
+    uint32_t nb = (n + FOR_BLOCK - 1) / FOR_BLOCK;
+    uint64_t pos = align16((uint64_t)32 * nb);
+    int64_t *d = (int64_t *)malloc(sizeof(int64_t) * FOR_BLOCK);
+    uint8_t *ok = (uint8_t *)malloc(FOR_BLOCK);
+    if (!d || !ok) { s->bad = 1; free(d); free(ok); return; }
+    buf_resize(s, pos);
+    uint64_t end = pos;
+    for (uint32_t b = 0; b < nb && !s->bad; b++) {
+        uint32_t j0 = b * FOR_BLOCK, nv = n - j0 < FOR_BLOCK ? n - j0 : FOR_BLOCK;
+        /* pick e */
+        uint32_t best_e = 0;
+        uint64_t best_cost = 0;
+        for (uint32_t e = 0; e <= F2I_EMAX; e++) {
+            uint32_t nx = 0, any = 0;
+            int64_t lo = 0, hi = 0;
+            for (uint32_t j = 0; j < nv; j++) {
+                int64_t k;
+                if (!f2i_digits(get64(x + 8 * (uint64_t)(j0 + j)), e, &k)) { nx++; continue; }
+                if (!any || k < lo) lo = k;
+                if (!any || k > hi) hi = k;
+                any = 1;
+            }
+            uint32_t w = any ? bitlen64((uint64_t)hi - (uint64_t)lo) : 0;
+            uint64_t cost = (uint64_t)nv * w + (uint64_t)128 * nx;
+            if (e == 0 || cost < best_cost) { best_cost = cost; best_e = e; }
+        }
+        /* encode with best_e */
+        uint32_t e = best_e, nx = 0, any = 0;
+        int64_t ref = 0, hi = 0;
+        for (uint32_t j = 0; j < nv; j++) {
+            ok[j] = (uint8_t)f2i_digits(get64(x + 8 * (uint64_t)(j0 + j)), e, &d[j]);
+            if (!ok[j]) { nx++; continue; }
+            if (!any || d[j] < ref) ref = d[j];
+            if (!any || d[j] > hi) hi = d[j];
+            any = 1;
+        }
+        uint32_t w = any ? bitlen64((uint64_t)hi - (uint64_t)ref) : 0;
+        uint64_t nw = packed_words(nv, w);
+        uint64_t xoff = align16(pos + 4 * nw);
+        buf_resize(s, xoff + (uint64_t)16 * nx);
+        if (s->bad) break;
+        uint8_t *de = s->p + 32 * (uint64_t)b;
+        put64(de, (uint64_t)ref);
+        put32(de + 8, w);
+        put32(de + 12, (uint32_t)pos);
+        put32(de + 16, (uint32_t)xoff);
+        put16(de + 20, nx);
+        put8(de + 22, e);
+        uint32_t xi = 0;
+        for (uint32_t j = 0; j < nv; j++) {
+            if (ok[j]) {
+                pack_bits(s->p + pos, j, w, (uint64_t)d[j] - (uint64_t)ref);
+            } else {
+                uint8_t *r = s->p + xoff + (uint64_t)16 * xi++;
+                put32(r, j);
+                put64(r + 8, get64(x + 8 * (uint64_t)(j0 + j)));
+            }
+        }
+        end = xoff + (uint64_t)16 * nx;
+        pos = align16(end);
+    }
+    free(d);
+    free(ok);
+    s->n = end;
+}
+
+static int dec_f2i_bp(const uint8_t *s, uint64_t comp_len, uint32_t n, uint8_t *out) {
+    uint32_t nb = (n + FOR_BLOCK - 1) / FOR_BLOCK;
+    if ((uint64_t)32 * nb > comp_len) return ZFO_ECORRUPT;
+    for (uint32_t b = 0; b < nb; b++) {
+        uint32_t j0 = b * FOR_BLOCK, nv = n - j0 < FOR_BLOCK ? n - j0 : FOR_BLOCK;
+        const uint8_t *de = s + 32 * (uint64_t)b;
+        uint64_t ref = get64(de);
+        uint32_t w = get32(de + 8);
+        uint64_t poff = get32(de + 12), xoff = get32(de + 16);
+        uint32_t nx = get16(de + 20), e = de[22];
+        if (w > 64 || e > F2I_EMAX || nx > nv) return ZFO_ECORRUPT;
+        if (poff % 16 || poff < (uint64_t)32 * nb || poff + 4 * packed_words(nv, w) > comp_len)
+            return ZFO_ECORRUPT;
+        if (xoff % 16 || xoff < (uint64_t)32 * nb || xoff + (uint64_t)16 * nx > comp_len)
+            return ZFO_ECORRUPT;
+        for (uint32_t j = 0; j < nv; j++) {
+            int64_t k = (int64_t)(ref + unpack_bits(s + poff, j, w));
+            put64(out + 8 * (uint64_t)(j0 + j), f64_bits((double)k / F2I_P10[e]));
+        }
+        for (uint32_t i = 0; i < nx; i++) {
+            const uint8_t *r = s + xoff + (uint64_t)16 * i;
+            uint32_t j = get32(r);
+            if (j >= nv || (i > 0 && j <= get32(r - 16))) return ZFO_ECORRUPT;
+            put64(out + 8 * (uint64_t)(j0 + j), get64(r + 8));
+        }
     }
     return ZFO_OK;
 }
@@ -538,6 +690,7 @@ static int codec_allows(uint32_t codec, uint32_t dtype) {
     case ZFO_RLE_DELTA_BP: return dtype == ZFO_I32 || dtype == ZFO_I64;
     case ZFO_DICT_BP: return dtype == ZFO_I32 || dtype == ZFO_I64 || dtype == ZFO_FIXED16;
     case ZFO_LZ77: return zfo_elem_size(dtype) != 0;
+    case ZFO_F2I_BP: return dtype == ZFO_F64;
     default: return 0;
     }
 }
@@ -559,6 +712,8 @@ int zfo_decode_stream(uint32_t codec, uint32_t dtype, const uint8_t *s, uint64_t
     case ZFO_DELTA_BP:
     case ZFO_RLE_DELTA_BP:
         return dec_rle_delta(s, comp_len, dtype, n, codec == ZFO_DELTA_BP, dst);
+    case ZFO_F2I_BP:
+        return dec_f2i_bp(s, comp_len, n, dst);
     case ZFO_FOR_BP:
     case ZFO_DICT_BP: {
         uint64_t *tmp = (uint64_t *)malloc(sizeof(uint64_t) * n);
@@ -642,6 +797,7 @@ int zfo_encode(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t code
         case ZFO_DELTA_BP: enc_rle_delta(&s, x, dtype, n, 1); break;
         case ZFO_RLE_DELTA_BP: enc_rle_delta(&s, x, dtype, n, 0); break;
         case ZFO_LZ77: enc_lz77(&s, x, n * es); break;
+        case ZFO_F2I_BP: enc_f2i_bp(&s, x, n); break;
         }
         if (s.bad || s.n > 0xFFFFFFFFu) { free(s.p); b.bad = 1; break; }
         buf_resize(&b, pos + s.n);

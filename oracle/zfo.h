@@ -26,6 +26,7 @@ extern "C" {
 #define ZFO_I64 2
 #define ZFO_BYTES 3
 #define ZFO_FIXED16 4
+#define ZFO_F64 5
 
 /* codecs */
 #define ZFO_PLAIN 1
@@ -34,6 +35,7 @@ extern "C" {
 #define ZFO_DELTA_BP 4
 #define ZFO_RLE_DELTA_BP 5
 #define ZFO_LZ77 6
+#define ZFO_F2I_BP 7
 
 /* status */
 #define ZFO_OK 0

@@ -8,10 +8,10 @@ import numpy as np
 
 from . import build as _build
 
-I32, I64, BYTES, FIXED16 = 1, 2, 3, 4
-PLAIN, FOR_BP, DICT_BP, DELTA_BP, RLE_DELTA_BP, LZ77 = 1, 2, 3, 4, 5, 6
+I32, I64, BYTES, FIXED16, F64 = 1, 2, 3, 4, 5
+PLAIN, FOR_BP, DICT_BP, DELTA_BP, RLE_DELTA_BP, LZ77, F2I_BP = 1, 2, 3, 4, 5, 6, 7
 OK, EINVAL, EUNSUP, ECORRUPT, ENOMEM = 0, 1, 2, 3, 4
-ELEM_SIZE = {I32: 4, I64: 8, BYTES: 1, FIXED16: 16}
+ELEM_SIZE = {I32: 4, I64: 8, BYTES: 1, FIXED16: 16, F64: 8}
 
 
 class OracleError(RuntimeError):
@@ -76,6 +76,8 @@ def dtype_of(x):
         return I32
     if x.dtype == np.int64:
         return I64
+    if x.dtype == np.float64:
+        return F64
     if x.dtype == np.uint8 and x.ndim == 1:
         return BYTES
     if x.dtype == np.uint8 and x.ndim == 2 and x.shape[1] == 16:
@@ -134,6 +136,8 @@ def _shape_out(nbytes, dtype):
         return np.empty(nbytes // 4, dtype=np.int32)
     if dtype == I64:
         return np.empty(nbytes // 8, dtype=np.int64)
+    if dtype == F64:
+        return np.empty(nbytes // 8, dtype=np.float64)
     if dtype == FIXED16:
         return np.empty((nbytes // es, 16), dtype=np.uint8)
     return np.empty(nbytes, dtype=np.uint8)
