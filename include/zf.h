@@ -52,7 +52,8 @@ typedef enum {
     ZF_I32 = 1,     /* int32 values                        */
     ZF_I64 = 2,     /* int64 values                        */
     ZF_BYTES = 3,   /* byte column (e.g. text)             */
-    ZF_FIXED16 = 4  /* 16-byte fixed-width strings, CHAR(16) */
+    ZF_FIXED16 = 4, /* 16-byte fixed-width strings, CHAR(16) */
+    ZF_F64 = 5      /* IEEE binary64 values                 */
 } zf_dtype;
 
 /*
@@ -80,6 +81,14 @@ typedef enum {
  *                   Tag bits 0-2: literal count (7 = 7 + next ext), bits 3-7:
  *                   match code (0 none, 1..30 -> length code+3, 31 -> 34 +
  *                   next ext).  Any dtype (decoded as bytes).
+ *  ZF_F2I_BP        [FP] Float2Int + bit-packing (Sec. 2.1; layout ours):
+ *                   per block of 2048 values an exponent e <= 18 and
+ *                   integers d with bits(v) == bits((double)d / 10^e) (IEEE
+ *                   division), FOR + bit-packed; values with no such d are
+ *                   exceptions stored raw.  32-byte directory {i64 ref, u32 w,
+ *                   u32 poff, u32 xoff, u16 nx, u8 e, u8 0, 8 zero bytes};
+ *                   exception records {u32 index in block (increasing), u32 0,
+ *                   u64 bits} at xoff.  F64.
  */
 typedef enum {
     ZF_AUTO = 0,
@@ -88,7 +97,8 @@ typedef enum {
     ZF_DICT_BP = 3,
     ZF_DELTA_BP = 4,
     ZF_RLE_DELTA_BP = 5,
-    ZF_LZ77 = 6
+    ZF_LZ77 = 6,
+    ZF_F2I_BP = 7
 } zf_codec;
 
 typedef void *zf_stream_t;              /* a hipStream_t */
@@ -159,6 +169,7 @@ typedef enum {
     ZF_KIND_DICT32,
     ZF_KIND_FOR64,
     ZF_KIND_FOR32,
+    ZF_KIND_F2I,     /* Float2Int + bit-packing, float64 */
     ZF_KIND_PLAIN,
     ZF_KIND_COUNT
 } zf_kind;

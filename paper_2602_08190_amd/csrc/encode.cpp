@@ -85,6 +85,115 @@ static void enc_for(std::vector<uint8_t> &s, const T *x, uint32_t n) {
     }
 }
 
+// ----------------------------------------------------------- Float2Int
+// Per block of 2048 float64 values, the decimal exponent e <= 18 whose
+// integers d (bits(v) == bits(double(d) / 10^e)) pack into the fewest bits,
+// counting 128 bits per value with no such d (an exception, stored raw);
+// ties go to the smaller e.  The integers are then FOR + bit-packed.
+static const double kF2iPow10[19] = {1e0,  1e1,  1e2,  1e3,  1e4,  1e5,  1e6,  1e7,  1e8, 1e9,
+                                     1e10, 1e11, 1e12, 1e13, 1e14, 1e15, 1e16, 1e17, 1e18};
+
+static inline bool f2i_fit(uint64_t vb, uint32_t e, int64_t &d) {
+    double v;
+    std::memcpy(&v, &vb, 8);
+    const double m = v * kF2iPow10[e];
+    if (!(std::fabs(m) < 4611686018427387904.0)) return false;  // 2^62; NaN fails too
+    const int64_t k = int64_t(std::nearbyint(m));
+    const double back = double(k) / kF2iPow10[e];
+    uint64_t bb;
+    std::memcpy(&bb, &back, 8);
+    if (bb != vb) return false;
+    d = k;
+    return true;
+}
+
+static void enc_f2i(std::vector<uint8_t> &s, const uint8_t *x, uint32_t n) {
+    const uint64_t nb = (n + kForBlock - 1) / kForBlock;
+    struct Blk {
+        uint32_t e, w, nx;
+        int64_t ref;
+        uint64_t poff, xoff;
+    };
+    std::vector<Blk> blk(nb);
+    std::vector<int64_t> d(n);
+    std::vector<uint8_t> ok(n);
+    uint64_t pos = align_up(32 * nb, 16), end = pos;
+    for (uint64_t b = 0; b < nb; b++) {
+        const uint64_t j0 = b * kForBlock;
+        const uint32_t nv = uint32_t(std::min<uint64_t>(kForBlock, n - j0));
+        uint64_t best_cost = ~0ull;
+        uint32_t best_e = 0;
+        for (uint32_t e = 0; e <= 18; e++) {
+            uint32_t nx = 0;
+            bool any = false;
+            int64_t lo = 0, hi = 0, k = 0;
+            for (uint32_t j = 0; j < nv; j++) {
+                if (!f2i_fit(rd64(x + 8 * (j0 + j)), e, k)) {
+                    nx++;
+                    continue;
+                }
+                lo = any ? std::min(lo, k) : k;
+                hi = any ? std::max(hi, k) : k;
+                any = true;
+            }
+            const uint64_t cost = uint64_t(nv) * (any ? bit_width64(uint64_t(hi) - uint64_t(lo)) : 0) +
+                                  128ull * nx;
+            if (cost < best_cost) {
+                best_cost = cost;
+                best_e = e;
+            }
+        }
+        Blk &B = blk[b];
+        B.e = best_e;
+        B.nx = 0;
+        bool any = false;
+        int64_t hi = 0;
+        B.ref = 0;
+        for (uint32_t j = 0; j < nv; j++) {
+            ok[j0 + j] = f2i_fit(rd64(x + 8 * (j0 + j)), best_e, d[j0 + j]);
+            if (!ok[j0 + j]) {
+                B.nx++;
+                continue;
+            }
+            B.ref = any ? std::min(B.ref, d[j0 + j]) : d[j0 + j];
+            hi = any ? std::max(hi, d[j0 + j]) : d[j0 + j];
+            any = true;
+        }
+        B.w = any ? bit_width64(uint64_t(hi) - uint64_t(B.ref)) : 0;
+        B.poff = pos;
+        B.xoff = align_up(pos + 4 * ((uint64_t(nv) * B.w + 31) / 32), 16);
+        end = B.xoff + 16ull * B.nx;
+        pos = align_up(end, 16);
+    }
+    s.assign(end, 0);
+    for (uint64_t b = 0; b < nb; b++) {
+        const Blk &B = blk[b];
+        uint8_t *de = s.data() + 32 * b;
+        wr64(de, uint64_t(B.ref));
+        wr32(de + 8, B.w);
+        wr32(de + 12, uint32_t(B.poff));
+        wr32(de + 16, uint32_t(B.xoff));
+        de[20] = uint8_t(B.nx);
+        de[21] = uint8_t(B.nx >> 8);
+        de[22] = uint8_t(B.e);
+        const uint64_t j0 = b * kForBlock;
+        const uint32_t nv = uint32_t(std::min<uint64_t>(kForBlock, n - j0));
+        BitPacker bp(s.data() + B.poff);
+        uint8_t *xr = s.data() + B.xoff;
+        for (uint32_t j = 0; j < nv; j++) {
+            if (ok[j0 + j]) {
+                bp.put(uint64_t(d[j0 + j]) - uint64_t(B.ref), B.w);
+            } else {
+                bp.put(0, B.w);
+                wr32(xr, j);
+                wr64(xr + 8, rd64(x + 8 * (j0 + j)));
+                xr += 16;
+            }
+        }
+        bp.flush();
+    }
+}
+
 // ------------------------------------------------------------ dictionary
 // Open-addressing set/map over keys of up to 16 bytes.
 struct KeyTable {
@@ -433,6 +542,7 @@ static void encode_chunk(std::vector<uint8_t> &out, uint32_t codec, uint32_t dty
         else enc_rle<int64_t>(out, reinterpret_cast<const int64_t *>(x), n, codec == C_DELTA_BP);
         return;
     case C_LZ77: enc_lz77(out, x, n * es, sc); return;
+    case C_F2I_BP: enc_f2i(out, x, n); return;
     }
     fail(ZF_E_INVALID, "unknown codec %u", codec);
 }
@@ -496,7 +606,7 @@ void compress_host(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t 
     }
     Dictionary dict;
     bool have_dict = false;
-    if (want_dict || (any_auto && dtype != D_BYTES)) {
+    if (want_dict || (any_auto && dtype != D_BYTES && dtype != D_F64)) {
         const uint64_t limit = want_dict ? (1ull << 31) : (1ull << 16);
         have_dict = build_dictionary(dict, src, n_elems, dtype, limit, threads);
         ZF_REQUIRE(have_dict || !want_dict, ZF_E_UNSUPPORTED, "too many distinct values for DICT_BP");
@@ -509,7 +619,9 @@ void compress_host(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t 
         std::string wpath = o.mlp_weights ? o.mlp_weights : "";
         if (wpath.empty())
             if (const char *e = std::getenv("ZF_MLP_WEIGHTS")) wpath = e;
-        if (!wpath.empty()) {
+        // the network's outputs cover the integer and byte codecs; float64
+        // chunks keep the smallest stream
+        if (!wpath.empty() && dtype != D_F64) {
             ZF_REQUIRE(model.load(wpath), ZF_E_INVALID, "cannot read cost model %s", wpath.c_str());
             std::vector<uint64_t> at(ce.size() + 1, 0);
             for (size_t i = 0; i < ce.size(); i++) at[i + 1] = at[i] + ce[i];
@@ -572,7 +684,7 @@ void compress_host(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t 
             encode_chunk(out.bytes, cc[i], dtype, x, ce[i], &dict, *sc);
         } else {
             // smallest stream among the applicable codecs
-            const uint32_t cands[] = {C_FOR_BP, C_DICT_BP, C_DELTA_BP, C_RLE_DELTA_BP, C_LZ77};
+            const uint32_t cands[] = {C_FOR_BP, C_DICT_BP, C_DELTA_BP, C_RLE_DELTA_BP, C_LZ77, C_F2I_BP};
             encode_chunk(out.bytes, C_PLAIN, dtype, x, ce[i], nullptr, *sc);
             out.codec = C_PLAIN;
             std::vector<uint8_t> tmp;

@@ -27,6 +27,7 @@ uint32_t elem_size(uint32_t dtype) {
     case D_I64: return 8;
     case D_BYTES: return 1;
     case D_FIXED16: return 16;
+    case D_F64: return 8;
     }
     return 0;
 }
@@ -39,7 +40,8 @@ bool codec_allows(uint32_t codec, uint32_t dtype) {
     case C_FOR_BP:
     case C_DELTA_BP:
     case C_RLE_DELTA_BP: return dtype == D_I32 || dtype == D_I64;
-    case C_DICT_BP: return dtype != D_BYTES;
+    case C_DICT_BP: return dtype != D_BYTES && dtype != D_F64;
+    case C_F2I_BP: return dtype == D_F64;
     }
     return false;
 }
@@ -52,6 +54,7 @@ Kind kind_of(uint32_t codec, uint32_t dtype) {
     case C_DELTA_BP:
     case C_RLE_DELTA_BP: return dtype == D_I32 ? K_RLE32 : K_RLE64;
     case C_LZ77: return K_LZ;
+    case C_F2I_BP: return K_F2I;
     }
     fail(ZF_E_CORRUPT, "unknown codec %u", codec);
 }
@@ -211,6 +214,22 @@ void check_stream(const ColumnView &v, const uint8_t *blob, uint32_t i) {
             ZF_REQUIRE(g == 0 ? off == 0 : (off > prev && off < n), ZF_E_CORRUPT,
                        "chunk %u group %u: output offset out of order", i, g);
             prev = off;
+        }
+        return;
+    }
+    case C_F2I_BP: {
+        const uint64_t nb = (n + kForBlock - 1) / kForBlock;
+        ZF_REQUIRE(32 * nb <= L, ZF_E_CORRUPT, "chunk %u: block directory overruns", i);
+        for (uint64_t b = 0; b < nb; b++) {
+            const uint8_t *d = s + 32 * b;
+            const uint32_t w = rd32(d + 8), poff = rd32(d + 12), xoff = rd32(d + 16);
+            const uint32_t nx = rd16(d + 20), e = d[22];
+            const uint64_t nv = std::min<uint64_t>(kForBlock, n - b * kForBlock);
+            ZF_REQUIRE(w <= 64 && e <= 18 && nx <= nv && poff % 16 == 0 && poff >= 32 * nb &&
+                           poff + 4 * words_for(nv, w) <= L && xoff % 16 == 0 && xoff >= 32 * nb &&
+                           xoff + 16ull * nx <= L,
+                       ZF_E_CORRUPT, "chunk %u block %llu: bad directory entry", i,
+                       (unsigned long long)b);
         }
         return;
     }

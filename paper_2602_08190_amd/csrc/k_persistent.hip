@@ -58,6 +58,7 @@ hipError_t launch_decode(const LaunchArgs &A, uint32_t persistent_waves, const u
     launch_dict32(A, wpb[K_DICT32], st);
     launch_for64(A, wpb[K_FOR64], st);
     launch_for32(A, wpb[K_FOR32], st);
+    launch_f2i(A, wpb[K_F2I], st);
     launch_plain(A, wpb[K_PLAIN], st);
     return hipGetLastError();
 }

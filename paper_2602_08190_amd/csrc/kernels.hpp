@@ -210,6 +210,13 @@ ZF_DEV uint32_t alignbit(uint32_t hi, uint32_t lo, uint32_t s) {
     return __builtin_amdgcn_alignbit(hi, lo, s);
 }
 
+// A Float2Int integer (two's complement in 64 bits) as the bits of the
+// float64 (double)d / div: IEEE conversion and division, round to nearest.
+ZF_DEV uint64_t f2i_value(uint64_t d, double div) {
+    const double v = double(int64_t(d)) / div;
+    return uint64_t(__double_as_longlong(v));
+}
+
 // The NW packed words starting at word k0 (NW <= 5, known per width);
 // zero past nwords.
 template <uint32_t NW>
@@ -281,9 +288,12 @@ ZF_DEV uint64_t yfield64(const Win &v, uint32_t sh) {
 // Decode one block of nv values, width W known at compile time.  A lane owns
 // 16 output bytes per step; the packed words of UNR steps are loaded before
 // any is used, so each wave keeps UNR x 1 KiB of output's loads in flight.
-template <int ES, bool DICT, uint32_t UNR, uint32_t W>
+// F2I: the 64-bit values are Float2Int integers, written as the float64
+// (double)int64(value) / div.
+template <int ES, bool DICT, uint32_t UNR, uint32_t W, bool F2I = false>
 ZF_DEV void fp_block(const uint32_t *words, uint64_t nwords, uint64_t ref, uint32_t nv,
-                     uint8_t *ob, bool vec, const uint8_t *dict, uint32_t dict_count, bool &bad) {
+                     uint8_t *ob, bool vec, const uint8_t *dict, uint32_t dict_count, bool &bad,
+                     double div = 1.0) {
     constexpr uint32_t VPL = 16 / ES;
     constexpr uint32_t NW = (31 + VPL * W + 31) / 32;  // words a lane may need
     const uint32_t lane = lane_id();
@@ -337,6 +347,10 @@ ZF_DEV void fp_block(const uint32_t *words, uint64_t nwords, uint64_t ref, uint3
                 } else {
                     v[0] = ref + yfield64<W, 0>(wv[u], sh);
                     v[1] = ref + yfield64<W, 1>(wv[u], sh);
+                    if constexpr (F2I) {
+                        v[0] = f2i_value(v[0], div);
+                        v[1] = f2i_value(v[1], div);
+                    }
                 }
                 if (vec && v0 + 2 <= nv) {
                     st16_nt(ob + 8ull * v0, uint32_t(v[0]), uint32_t(v[0] >> 32), uint32_t(v[1]),
@@ -383,9 +397,10 @@ ZF_DEV uint64_t yfield_rt(uint32_t y0, uint32_t y1, uint32_t y2, uint32_t y3, ui
     return w >= 64 ? v : (v & ((1ull << w) - 1ull));
 }
 
-template <int ES, bool DICT>
+template <int ES, bool DICT, bool F2I = false>
 ZF_DEV void fp_block_rt(uint32_t w, const uint32_t *words, uint64_t nwords, uint64_t ref, uint32_t nv,
-                        uint8_t *ob, bool vec, const uint8_t *dict, uint32_t dict_count, bool &bad) {
+                        uint8_t *ob, bool vec, const uint8_t *dict, uint32_t dict_count, bool &bad,
+                        double div = 1.0) {
     constexpr uint32_t VPL = 16 / ES;
     const uint32_t lane = lane_id();
     const ZF_GLOBAL uint8_t *gd = gp(dict);
@@ -420,6 +435,7 @@ ZF_DEV void fp_block_rt(uint32_t w, const uint32_t *words, uint64_t nwords, uint
                 }
             } else {
                 v[i] = ref + f;
+                if constexpr (F2I) v[i] = f2i_value(v[i], div);
             }
         }
         if constexpr (ES == 4) {
@@ -441,12 +457,16 @@ ZF_DEV void fp_block_rt(uint32_t w, const uint32_t *words, uint64_t nwords, uint
 }
 
 // Uniform dispatch on the block's width to its specialised decoder.
-template <int ES, bool DICT, uint32_t UNR, uint32_t W, uint32_t WMAX>
+template <int ES, bool DICT, uint32_t UNR, uint32_t W, uint32_t WMAX, bool F2I = false>
 ZF_DEV void fp_dispatch(uint32_t w, const uint32_t *words, uint64_t nwords, uint64_t ref, uint32_t nv,
-                        uint8_t *ob, bool vec, const uint8_t *dict, uint32_t dict_count, bool &bad) {
+                        uint8_t *ob, bool vec, const uint8_t *dict, uint32_t dict_count, bool &bad,
+                        double div = 1.0) {
     if constexpr (W <= WMAX) {
-        if (w == W) fp_block<ES, DICT, UNR, W>(words, nwords, ref, nv, ob, vec, dict, dict_count, bad);
-        else fp_dispatch<ES, DICT, UNR, W + 1, WMAX>(w, words, nwords, ref, nv, ob, vec, dict, dict_count, bad);
+        if (w == W)
+            fp_block<ES, DICT, UNR, W, F2I>(words, nwords, ref, nv, ob, vec, dict, dict_count, bad, div);
+        else
+            fp_dispatch<ES, DICT, UNR, W + 1, WMAX, F2I>(w, words, nwords, ref, nv, ob, vec, dict, dict_count,
+                                                       bad, div);
     }
 }
 
@@ -488,6 +508,63 @@ ZF_DEV void unit_fp(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck) {
         else
             fp_dispatch<ES, DICT, UNR, 0, BITS>(first32(w), words, nwords, ref, nv, ob, vec, dict,
                                                 ck.dict_count, bad);
+    }
+    if (any(bad)) flag(A.err, ERR_CORRUPT);
+}
+
+// One wave decodes blocks [t.a, t.a + t.b) of a Float2Int + bit-packing
+// chunk: the FOR + bit-packing unpack of the block's integers, each written
+// as (double)d / 10^e (fused: no intermediate integer array), then the
+// block's exceptions, stored raw over their slots by the same wave.
+template <uint32_t MAXUNR>
+ZF_DEV void unit_f2i(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck) {
+    constexpr uint32_t STEPS = kForBlock / 128;  // lane-steps per block (2 values each)
+    constexpr uint32_t UNR = STEPS < MAXUNR ? STEPS : (MAXUNR ? MAXUNR : 1);
+    constexpr double kPow10[19] = {1e0,  1e1,  1e2,  1e3,  1e4,  1e5,  1e6,  1e7,  1e8, 1e9,
+                                   1e10, 1e11, 1e12, 1e13, 1e14, 1e15, 1e16, 1e17, 1e18};
+    const uint8_t *s = A.comp + ck.comp_off;
+    const uint32_t n = ck.n_elems, clen = ck.comp_len, lane = lane_id();
+    const uint32_t nb = (n + kForBlock - 1) / kForBlock;
+    uint8_t *out = A.out_tab[ck.col] + ck.out_off;
+    if (32ull * nb > clen || t.a + t.b > nb) {
+        flag(A.err, ERR_CORRUPT);
+        return;
+    }
+    bool bad = false;
+    for (uint32_t b = t.a; b < t.a + t.b; b++) {
+        const uint8_t *d = s + 32ull * b;
+        const uint64_t ref = ld64u(d);
+        const uint32_t w = ld32u(d + 8), poff = ld32u(d + 12), xoff = ld32u(d + 16);
+        const uint32_t nx = ld32u(d + 20) & 0xFFFFu, e = (ld32u(d + 20) >> 16) & 0xFFu;
+        const uint32_t j0 = b * kForBlock;
+        const uint32_t nv = min(kForBlock, n - j0);
+        const uint64_t nwords = (uint64_t(nv) * min(w, 64u) + 31) / 32;
+        if (w > 64 || e > 18 || nx > nv || (poff & 15u) || poff < 32ull * nb || poff + 4 * nwords > clen ||
+            (xoff & 15u) || xoff < 32ull * nb || xoff + 16ull * nx > clen) {
+            flag(A.err, ERR_CORRUPT);
+            return;
+        }
+        const uint32_t *words = reinterpret_cast<const uint32_t *>(s + poff);
+        uint8_t *ob = out + uint64_t(j0) * 8;
+        const bool vec = (reinterpret_cast<uintptr_t>(ob) & 15u) == 0;
+        const double div = kPow10[first32(e)];
+        if constexpr (MAXUNR == 0)
+            fp_block_rt<8, false, true>(first32(w), words, nwords, ref, nv, ob, vec, nullptr, 0, bad, div);
+        else
+            fp_dispatch<8, false, UNR, 0, 64, true>(first32(w), words, nwords, ref, nv, ob, vec, nullptr, 0,
+                                                  bad, div);
+        // exceptions (issued after the block's stores by the same wave, so
+        // they land last)
+        for (uint32_t i = lane; i < nx; i += 64) {
+            const uint8_t *r = s + xoff + 16ull * i;
+            const uint32_t j = ld32u(r);
+            const bool ok = j < nv && (i == 0 || j > ld32u(r - 16));
+            bad |= !ok;
+            if (ok) {
+                const u32x2 q = {ld32u(r + 8), ld32u(r + 12)};
+                __builtin_nontemporal_store(q, gp(reinterpret_cast<u32x2 *>(ob + 8ull * j)));
+            }
+        }
     }
     if (any(bad)) flag(A.err, ERR_CORRUPT);
 }
@@ -921,6 +998,7 @@ ZF_DEV void run_unit(const LaunchArgs &A, uint32_t kind, uint32_t u, uint32_t *l
     switch (kind) {
     case K_PLAIN: unit_plain(A, t, ck); break;
     case K_FOR32: unit_fp<4, false, UNR>(A, t, ck); break;
+    case K_F2I: unit_f2i<UNR>(A, t, ck); break;
     case K_FOR64: unit_fp<8, false, UNR>(A, t, ck); break;
     case K_DICT32: unit_fp<4, true, UNR>(A, t, ck); break;
     case K_DICT64: unit_fp<8, true, UNR>(A, t, ck); break;
@@ -946,6 +1024,8 @@ __global__ __launch_bounds__(1024) void k_decode_kind(LaunchArgs A) {
         unit_fp<4, false, 8>(A, t, ck);
     } else if constexpr (KIND == K_FOR64) {
         unit_fp<8, false, 8>(A, t, ck);
+    } else if constexpr (KIND == K_F2I) {
+        unit_f2i<8>(A, t, ck);
     } else if constexpr (KIND == K_DICT32) {
         unit_fp<4, true, 8>(A, t, ck);
     } else if constexpr (KIND == K_DICT64) {
@@ -977,7 +1057,7 @@ void launch_lz(const LaunchArgs &A, uint32_t waves, uint32_t blk, hipStream_t st
 #define ZF_KIND_LAUNCHERS(X)                                                                       \
     X(K_RLE64, launch_rle64) X(K_RLE32, launch_rle32)                           \
     X(K_DICT128, launch_dict128) X(K_DICT64, launch_dict64) X(K_DICT32, launch_dict32)              \
-    X(K_FOR64, launch_for64) X(K_FOR32, launch_for32) X(K_PLAIN, launch_plain)
+    X(K_FOR64, launch_for64) X(K_FOR32, launch_for32) X(K_F2I, launch_f2i) X(K_PLAIN, launch_plain)
 #define ZF_DECLARE_LAUNCHER(KIND, NAME) void NAME(const LaunchArgs &A, uint32_t waves, hipStream_t st);
 ZF_KIND_LAUNCHERS(ZF_DECLARE_LAUNCHER)
 

@@ -47,7 +47,8 @@ static void add_chunk(WorkTables &w, const zf_column &col, uint32_t ci, uint32_t
     case K_FOR64:
     case K_DICT32:
     case K_DICT64:
-    case K_DICT128: {
+    case K_DICT128:
+    case K_F2I: {
         const uint32_t nb = (c.n_elems + kForBlock - 1) / kForBlock;
         for (uint32_t b = 0; b < nb; b += unit) T.push_back({idx, b, std::min(unit, nb - b), 0});
         break;

@@ -77,7 +77,7 @@ struct Json {
 };
 
 const char *kKindNames[K_COUNT] = {"LZ77", "RLE64", "RLE32", "DICT128", "DICT64",
-                                   "DICT32", "FOR64", "FOR32", "PLAIN"};
+                                   "DICT32", "FOR64", "FOR32", "F2I", "PLAIN"};
 
 std::string default_cache_path() {
     Dl_info info;

@@ -11,8 +11,9 @@ constexpr uint32_t kLzMaxChunk = 65536;
 constexpr uint32_t kMaxCols = 256;     // columns per plan (output table size)
 
 // Codec / dtype codes, as in zf.h.
-enum : uint8_t { C_PLAIN = 1, C_FOR_BP = 2, C_DICT_BP = 3, C_DELTA_BP = 4, C_RLE_DELTA_BP = 5, C_LZ77 = 6 };
-enum : uint8_t { D_I32 = 1, D_I64 = 2, D_BYTES = 3, D_FIXED16 = 4 };
+enum : uint8_t { C_PLAIN = 1, C_FOR_BP = 2, C_DICT_BP = 3, C_DELTA_BP = 4, C_RLE_DELTA_BP = 5, C_LZ77 = 6,
+                 C_F2I_BP = 7 };
+enum : uint8_t { D_I32 = 1, D_I64 = 2, D_BYTES = 3, D_FIXED16 = 4, D_F64 = 5 };
 
 // Kernel kinds: one device routine per (codec class, value width).  The
 // order is the order of the persistent queue: slow units first, so that the
@@ -26,6 +27,7 @@ enum Kind : uint32_t {
     K_DICT32,
     K_FOR64,
     K_FOR32,
+    K_F2I,     // Float2Int + bit-packing, float64
     K_PLAIN,
     K_COUNT
 };
@@ -45,7 +47,7 @@ struct ChunkDesc {
 static_assert(sizeof(ChunkDesc) == 40, "ChunkDesc layout");
 
 // One unit of work for one wavefront.
-//   FOR / DICT: a = first block, b = number of blocks
+//   FOR / DICT / F2I: a = first block, b = number of blocks
 //   RLE / DELTA: a = first group, b = first element, c = end element
 //   LZ77: the whole chunk
 //   PLAIN: a = first byte, b = end byte

@@ -244,3 +244,16 @@ def fact_column(i, rows=FACT_ROWS, seed=3):
     if kind == "text":
         return TextSource(s).rows_parallel(rows)
     raise ValueError(kind)
+
+
+def decimal_column(n, seed, lo, hi, scale=100, specials=0):
+    """float64 decimals with log10(scale) places, as read from text: integers
+    uniform in [lo, hi) divided by `scale` (IEEE division gives the nearest
+    double to each decimal).  `specials` values at random positions are
+    replaced by NaN, infinities, -0.0 and full-precision doubles."""
+    r = rng(seed)
+    x = r.integers(lo, hi, size=n).astype(np.float64) / float(scale)
+    if specials:
+        pool = np.array([np.nan, np.inf, -np.inf, -0.0, 1.0 / 3.0, np.pi, 5e-324, 1e300])
+        x[r.integers(0, n, size=specials)] = pool[r.integers(0, len(pool), size=specials)]
+    return x

@@ -14,11 +14,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libzf.so")
 
 # dtypes and codecs (zf.h)
-I32, I64, BYTES, FIXED16 = 1, 2, 3, 4
-AUTO, PLAIN, FOR_BP, DICT_BP, DELTA_BP, RLE_DELTA_BP, LZ77 = 0, 1, 2, 3, 4, 5, 6
+I32, I64, BYTES, FIXED16, F64 = 1, 2, 3, 4, 5
+AUTO, PLAIN, FOR_BP, DICT_BP, DELTA_BP, RLE_DELTA_BP, LZ77, F2I_BP = 0, 1, 2, 3, 4, 5, 6, 7
 CODEC_NAMES = {PLAIN: "PLAIN", FOR_BP: "FOR_BP", DICT_BP: "DICT_BP", DELTA_BP: "DELTA_BP",
-               RLE_DELTA_BP: "RLE_DELTA_BP", LZ77: "LZ77"}
-ELEM_SIZE = {I32: 4, I64: 8, BYTES: 1, FIXED16: 16}
+               RLE_DELTA_BP: "RLE_DELTA_BP", LZ77: "LZ77", F2I_BP: "F2I_BP"}
+ELEM_SIZE = {I32: 4, I64: 8, BYTES: 1, FIXED16: 16, F64: 8}
 OK, E_INVALID, E_UNSUPPORTED, E_CORRUPT, E_NOMEM, E_HIP, E_TOO_SMALL, E_STATE = range(8)
 
 
@@ -37,8 +37,8 @@ class EncodeOpts(ctypes.Structure):
 
 
 # kernel kinds (zf_kind), in enum order
-KINDS = ["LZ77", "RLE64", "RLE32", "DICT128", "DICT64", "DICT32", "FOR64", "FOR32", "PLAIN"]
-KIND_GROUPS = {"FP": ["FOR32", "FOR64", "DICT32", "DICT64", "DICT128"], "GP": ["RLE32", "RLE64"],
+KINDS = ["LZ77", "RLE64", "RLE32", "DICT128", "DICT64", "DICT32", "FOR64", "FOR32", "F2I", "PLAIN"]
+KIND_GROUPS = {"FP": ["FOR32", "FOR64", "DICT32", "DICT64", "DICT128", "F2I"], "GP": ["RLE32", "RLE64"],
                "NP": ["LZ77"]}
 
 
@@ -127,6 +127,8 @@ def dtype_of(x):
         return I32
     if x.dtype == np.int64:
         return I64
+    if x.dtype == np.float64:
+        return F64
     if x.dtype == np.uint8 and x.ndim == 1:
         return BYTES
     if x.dtype == np.uint8 and x.ndim == 2 and x.shape[1] == 16:
@@ -323,6 +325,8 @@ def kind_of_column(col):
         return "PLAIN"
     if codec == LZ77:
         return "LZ77"
+    if codec == F2I_BP:
+        return "F2I"
     if codec in (DELTA_BP, RLE_DELTA_BP):
         return "RLE32" if dt == I32 else "RLE64"
     if codec == DICT_BP:
@@ -340,6 +344,8 @@ def torch_dtype_shape(col):
         return torch.int32, (n,)
     if dt == I64:
         return torch.int64, (n,)
+    if dt == F64:
+        return torch.float64, (n,)
     if dt == FIXED16:
         return torch.uint8, (n, 16)
     return torch.uint8, (n,)

@@ -67,6 +67,22 @@ def test_encoder_byte_identical_extremes():
             assert ours.tobytes() == ref.tobytes(), (dt, codec)
 
 
+def test_encoder_byte_identical_f2i():
+    """Float2Int: prices with 2 places, discounts, specials, full-precision
+    doubles (all exceptions) and any bit patterns."""
+    r = g.rng(23)
+    cols = [g.decimal_column(9000, 1, 90000, 10500000),
+            g.decimal_column(5000, 2, 0, 11, specials=60),
+            g.decimal_column(3000, 3, -10 ** 12, 10 ** 12, scale=10 ** 6),
+            r.random(2500),
+            r.integers(0, 2 ** 64, size=2100, dtype=np.uint64).view(np.float64)]
+    for x in cols:
+        n = len(x)
+        ours, ref = same_streams(x, zf.F2I_BP, [n // 3, n - n // 3])
+        assert ours.tobytes() == ref.tobytes()
+        assert np.array_equal(zo.decode(ours).view(np.uint64), x.view(np.uint64))
+
+
 def test_encoder_byte_identical_fixed16_and_mixed():
     x = g.fixed16_column(30000, 25, 4)
     ours, ref = same_streams(x, zf.DICT_BP, [10000, 20000])

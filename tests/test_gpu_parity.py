@@ -170,6 +170,46 @@ def test_rle_config2_shape():
     check(cols, decode_image(cols), [x])
 
 
+# ------------------------------------------------------- Float2Int (FP)
+def f2i_columns():
+    r = g.rng(31)
+    xs = [g.decimal_column(70001, 1, 90000, 10500000),                  # prices, 2 places
+          g.decimal_column(20000, 2, 0, 11, specials=200),               # discounts + specials
+          g.decimal_column(9000, 3, -10 ** 12, 10 ** 12, scale=10 ** 6),  # 6 places, wide
+          r.random(5000),                                                # all exceptions
+          r.integers(0, 2 ** 64, size=3000, dtype=np.uint64).view(np.float64)]
+    cols = []
+    for x in xs:
+        n = len(x)
+        cols.append(zf.Column.compress(x, zf.F2I_BP, chunk_elems=[n // 3 + 1, n - n // 3 - 1]))
+    return cols, xs
+
+
+def check_bits(cols, outs, xs):
+    """Bit-for-bit comparison (NaN payloads and -0.0 included)."""
+    for i, (c, o, x) in enumerate(zip(cols, outs, xs)):
+        want = zo.decode(c.bytes())
+        assert np.array_equal(o.view(np.uint64), want.view(np.uint64)), f"column {i}: GPU != oracle"
+        assert np.array_equal(want.view(np.uint64), x.view(np.uint64))
+
+
+@pytest.mark.parametrize("fp_blocks", [1, 3])
+def test_f2i_decimals_specials_and_modes(fp_blocks):
+    log("f2i", fp_blocks)
+    cols, xs = f2i_columns()
+    check_bits(cols, decode_image(cols, tiles={"F2I": dict(unit=fp_blocks)}), xs)
+    check_bits(cols, decode_image(cols, persistent=True), xs)
+    outs, _ = decode_staged(cols, slot_bytes=1 << 20)
+    check_bits(cols, outs, xs)
+
+
+def test_f2i_auto_picks_float2int_for_decimals():
+    x = g.decimal_column(50000, 4, 0, 10 ** 7)
+    col = zf.Column.compress(x, zf.AUTO)
+    assert {c["codec"] for c in zo.chunks(col.bytes())} == {zf.F2I_BP}
+    check_bits([col], decode_image([col]), [x])
+
+
 # -------------------------------------------------------------- NP codec
 # LZ77 kernel knob: output bytes per block of the copy step
 LZ_BLK = [4, 8, 16]
@@ -363,6 +403,14 @@ def test_device_detects_corrupt_streams():
     roff = int(np.frombuffer(b[c["comp_off"] + 8:c["comp_off"] + 12].tobytes(), np.uint32)[0])
     at = c["comp_off"] + roff
     b[at:at + 4] = np.frombuffer(np.uint32(1000).tobytes(), np.uint8)
+    _expect_corrupt([zf.Column.from_bytes(b)])
+    # F2I: exception records out of order (the host does not read them)
+    x = np.array([0.5, -0.0, np.nan, 1.5] * 3, dtype=np.float64)
+    b = zo.encode(x, zo.F2I_BP).copy()
+    c = zo.chunks(b)[0]
+    xoff = c["comp_off"] + int(np.frombuffer(b[c["comp_off"] + 16:c["comp_off"] + 20].tobytes(), np.uint32)[0])
+    first, second = b[xoff:xoff + 4].copy(), b[xoff + 16:xoff + 20].copy()
+    b[xoff:xoff + 4], b[xoff + 16:xoff + 20] = second, first
     _expect_corrupt([zf.Column.from_bytes(b)])
     # DICT: a code beyond the dictionary
     y = g.fixed16_column(4096, 4, 1)
