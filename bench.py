@@ -79,6 +79,11 @@ def single(kind, n):
         x = g.text_column(n, 2)
         c = zf.Column.compress(x, zf.LZ77)
         desc = f"LZ77 text, {n} bytes, Zipf(1.1) over 10,000 words, 64 KiB chunks"
+    elif kind == "f2i":
+        x = g.decimal_column(n, 5, 90000, 10500000)
+        c = zf.Column.compress(x, zf.F2I_BP)
+        desc = (f"F2I_BP float64, {n} prices with 2 decimal places uniform in [900, 105000), "
+                f"1 MiB chunks")
     elif kind == "copy":
         x = np.frombuffer(np.random.default_rng(0).bytes(n), np.uint8)
         c = zf.Column.compress(x, zf.PLAIN, chunk_bytes=(4 << 20, 4 << 20))
@@ -163,7 +168,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="fact", choices=["fact", "for", "rle", "lz", "copy"])
+    ap.add_argument("--workload", default="fact", choices=["fact", "for", "rle", "lz", "f2i", "copy"])
     ap.add_argument("--rows", type=int, default=None)
     ap.add_argument("--no-e2e", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -186,7 +191,8 @@ def main():
     if args.workload == "fact":
         cols, xs, names, desc = fact_table(args.rows or g.FACT_ROWS)
     else:
-        n = args.rows or {"for": 1 << 28, "rle": 1 << 26, "lz": 1 << 30, "copy": 1 << 30}[args.workload]
+        n = args.rows or {"for": 1 << 28, "rle": 1 << 26, "lz": 1 << 30, "f2i": 1 << 26,
+                           "copy": 1 << 30}[args.workload]
         cols, xs, names, desc = single(args.workload, n)
     plain = sum(c.plain_bytes for c in cols)
     comp = sum(c.host_pointer()[1] for c in cols)
@@ -205,7 +211,11 @@ def main():
     for x, o in zip(xs, outs):
         idx = r.integers(0, len(x), size=4096)
         got = o[torch.from_numpy(idx).to(o.device)].cpu().numpy()
-        assert np.array_equal(got, x[idx]), "decode mismatch"
+        if x.dtype == np.float64:  # bit for bit
+            got, want = got.view(np.uint64), x[idx].view(np.uint64)
+        else:
+            want = x[idx]
+        assert np.array_equal(got, want), "decode mismatch"
     log("sampled check against the input: ok")
 
     # timed steps: decode of the whole table from HBM
@@ -246,7 +256,7 @@ def main():
     result = {
         "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.workload == "f2i" else "u32",
         "data": "synthetic",
         "config": {"workload": desc, "plain_bytes": plain, "comp_bytes": comp,
                    "ratio": round(plain / comp, 3),

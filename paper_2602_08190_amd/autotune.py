@@ -36,7 +36,7 @@ UNITS = {
     "NP": [4, 8, 16],                        # LZ77: output bytes per block
 }
 GROUP = {"FOR32": "FP", "FOR64": "FP", "DICT32": "FP", "DICT64": "FP", "DICT128": "FP",
-         "RLE32": "GP", "RLE64": "GP", "LZ77": "NP", "PLAIN": "PLAIN"}
+         "RLE32": "GP", "RLE64": "GP", "LZ77": "NP", "PLAIN": "PLAIN", "F2I": "FP"}
 DEFAULT = {"FP": 2, "GP": 4096, "PLAIN": 65536, "NP": 16}
 
 
@@ -59,6 +59,7 @@ def workloads(scale):
         "RLE32": (g.sorted_runs_column(n(1 << 26), 8, 1), zf.RLE_DELTA_BP),
         "RLE64": (g.sorted_runs_column(n(1 << 25), 8, 2, dtype=np.int64), zf.RLE_DELTA_BP),
         "LZ77": (g.text_column(n(1 << 30), 2), zf.LZ77),
+        "F2I": (g.decimal_column(n(1 << 25), 5, 90000, 10500000), zf.F2I_BP),
         "PLAIN": (np.frombuffer(g.rng(5).bytes(n(1 << 28)), np.uint8), zf.PLAIN),
     }
 
