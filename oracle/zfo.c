@@ -210,6 +210,144 @@ static int dec_for_bp_u64(const uint8_t *s, uint64_t comp_len, uint32_t n, uint3
     return ZFO_OK;
 }
 
+/* =================================================================== ANS
+ * Asymmetric numeral systems (Sec. 2.1: entropy coding; Sec. 3.1: a serial
+ * state machine per chunk), here range ANS over the chunk's bytes with a
+ * static order-0 model, the byte sequence dealt round-robin to 64 interleaved
+ * coders (byte i to coder i mod 64), each with its own 32-bit state.
+ * Model: M = 4096 (12 bits).  For byte counts c_s over the chunk's n bytes,
+ *   f_s = 0 if c_s = 0, else max(1, floor(c_s * M / n));
+ *   if sum f < M: the byte with the largest count (ties: the smallest byte)
+ *       gets the difference;
+ *   while sum f > M: the byte with the largest f (ties: the smallest byte)
+ *       loses one;
+ *   cum_s = sum of f_t for t < s.
+ * Coder (state x in [L, L * 2^16), L = 2^16), over its bytes in reverse
+ * order, starting from x = L:
+ *   while x >= 2^20 * f_s: emit the low 16 bits of x; x = x >> 16
+ *   x = floor(x / f_s) * M + (x mod f_s) + cum_s.
+ * Decode, in forward order from the final state: slot = x mod M, s = the byte
+ * with cum_s <= slot < cum_s + f_s, x = f_s * floor(x / M) + slot - cum_s,
+ * then while x < L: x = x * 2^16 + the coder's next 16-bit word.  A valid
+ * coder ends with x = L and every word read.
+ * Stream of a chunk of n bytes:
+ *   u32 n, u32 nw (total 16-bit words), u32 0, u32 0;
+ *   u16 f[256]; u32 state[64] (final states); u32 wofs[64] (coder j reads
+ *   words [wofs[j], wofs[j+1]), wofs[64] = nw); u16 words[nw] at byte 1040,
+ *   each coder's words in the order the decoder reads them (the reverse of
+ *   emission).  comp_len = 1040 + 2*nw. */
+#define ANS_M 4096u
+#define ANS_L 65536u
+#define ANS_LANES 64u
+#define ANS_HDR 1040u
+
+static void ans_model(const uint8_t *x, uint32_t n, uint32_t f[256]) {
+    uint64_t c[256] = {0};
+    for (uint32_t i = 0; i < n; i++) c[x[i]]++;
+    uint32_t sum = 0;
+    for (int s = 0; s < 256; s++) {
+        f[s] = 0;
+        if (c[s]) {
+            uint64_t q = c[s] * ANS_M / n;
+            f[s] = q ? (uint32_t)q : 1u;
+        }
+        sum += f[s];
+    }
+    if (sum < ANS_M) {
+        int best = -1;
+        for (int s = 0; s < 256; s++)
+            if (c[s] && (best < 0 || c[s] > c[best])) best = s;
+        f[best] += ANS_M - sum;
+        sum = ANS_M;
+    }
+    while (sum > ANS_M) {
+        int best = -1;
+        for (int s = 0; s < 256; s++)
+            if (f[s] > 1 && (best < 0 || f[s] > f[best])) best = s;
+        f[best]--;
+        sum--;
+    }
+}
+
+static void enc_ans(buf_t *s, const uint8_t *x, uint32_t n) {
+    uint32_t f[256], cum[256];
+    ans_model(x, n, f);
+    cum[0] = 0;
+    for (int t = 1; t < 256; t++) cum[t] = cum[t - 1] + f[t - 1];
+    /* coder j's emitted words, in emission order, at em[j * stride ...]; a
+     * byte emits at most one word (after one shift x < 2^16 <= 2^20 * f) */
+    uint64_t stride = (uint64_t)n / ANS_LANES + 2;
+    uint16_t *em = (uint16_t *)malloc(sizeof(uint16_t) * stride * ANS_LANES);
+    uint64_t *cnt = (uint64_t *)calloc(ANS_LANES, sizeof(uint64_t));
+    uint32_t state[ANS_LANES];
+    if (!em || !cnt) { s->bad = 1; free(em); free(cnt); return; }
+    for (uint32_t j = 0; j < ANS_LANES; j++) {
+        uint64_t x_st = ANS_L;
+        if (j < n) {
+            uint32_t last = j + ((n - 1 - j) / ANS_LANES) * ANS_LANES;
+            for (int64_t i = last; i >= (int64_t)j; i -= ANS_LANES) {
+                uint32_t sy = x[i];
+                uint64_t xmax = ((uint64_t)(ANS_L >> 12) << 16) * f[sy];
+                while (x_st >= xmax) {
+                    em[j * stride + cnt[j]++] = (uint16_t)(x_st & 0xFFFFu);
+                    x_st >>= 16;
+                }
+                x_st = (x_st / f[sy]) * ANS_M + (x_st % f[sy]) + cum[sy];
+            }
+        }
+        state[j] = (uint32_t)x_st;
+    }
+    uint64_t nw = 0;
+    for (uint32_t j = 0; j < ANS_LANES; j++) nw += cnt[j];
+    buf_resize(s, ANS_HDR + 2 * nw);
+    if (!s->bad) {
+        put32(s->p, n);
+        put32(s->p + 4, (uint32_t)nw);
+        for (int t = 0; t < 256; t++) put16(s->p + 16 + 2 * t, f[t]);
+        uint64_t at = 0;
+        for (uint32_t j = 0; j < ANS_LANES; j++) {
+            put32(s->p + 528 + 4 * j, state[j]);
+            put32(s->p + 784 + 4 * j, (uint32_t)at);
+            for (uint64_t k = 0; k < cnt[j]; k++) /* reverse of emission */
+                put16(s->p + ANS_HDR + 2 * (at + k), em[j * stride + cnt[j] - 1 - k]);
+            at += cnt[j];
+        }
+    }
+    free(em);
+    free(cnt);
+}
+
+static int dec_ans(const uint8_t *s, uint64_t comp_len, uint32_t n, uint8_t *out) {
+    if (comp_len < ANS_HDR) return ZFO_ECORRUPT;
+    uint64_t nw = get32(s + 4);
+    if (get32(s) != n || ANS_HDR + 2 * nw != comp_len) return ZFO_ECORRUPT;
+    uint32_t f[256], cum[256], sum = 0;
+    for (int t = 0; t < 256; t++) {
+        f[t] = get16(s + 16 + 2 * t);
+        cum[t] = sum;
+        sum += f[t];
+    }
+    if (sum != ANS_M) return ZFO_ECORRUPT;
+    for (uint32_t j = 0; j < ANS_LANES; j++) {
+        uint64_t x_st = get32(s + 528 + 4 * j);
+        uint64_t w = get32(s + 784 + 4 * j);
+        uint64_t wend = j + 1 < ANS_LANES ? get32(s + 784 + 4 * (j + 1)) : nw;
+        if (w > wend || wend > nw) return ZFO_ECORRUPT;
+        for (uint64_t i = j; i < n; i += ANS_LANES) {
+            uint32_t slot = (uint32_t)(x_st % ANS_M), sy = 0;
+            while (!(cum[sy] <= slot && slot < cum[sy] + f[sy])) sy++;
+            x_st = f[sy] * (x_st / ANS_M) + slot - cum[sy];
+            while (x_st < ANS_L) {
+                if (w >= wend) return ZFO_ECORRUPT;
+                x_st = (x_st << 16) | get16(s + ANS_HDR + 2 * w++);
+            }
+            out[i] = (uint8_t)sy;
+        }
+        if (x_st != ANS_L || w != wend) return ZFO_ECORRUPT;
+    }
+    return ZFO_OK;
+}
+
 /* ============================================================= Float2Int
  * Decimal floating point to integers (Sec. 2.1 names Float2Int: significant
  * digits and exponent split into integers; it fixes no layout, so this one is
@@ -691,6 +829,7 @@ static int codec_allows(uint32_t codec, uint32_t dtype) {
     case ZFO_DICT_BP: return dtype == ZFO_I32 || dtype == ZFO_I64 || dtype == ZFO_FIXED16;
     case ZFO_LZ77: return zfo_elem_size(dtype) != 0;
     case ZFO_F2I_BP: return dtype == ZFO_F64;
+    case ZFO_ANS: return zfo_elem_size(dtype) != 0;
     default: return 0;
     }
 }
@@ -714,6 +853,8 @@ int zfo_decode_stream(uint32_t codec, uint32_t dtype, const uint8_t *s, uint64_t
         return dec_rle_delta(s, comp_len, dtype, n, codec == ZFO_DELTA_BP, dst);
     case ZFO_F2I_BP:
         return dec_f2i_bp(s, comp_len, n, dst);
+    case ZFO_ANS:
+        return dec_ans(s, comp_len, (uint32_t)plain, dst);
     case ZFO_FOR_BP:
     case ZFO_DICT_BP: {
         uint64_t *tmp = (uint64_t *)malloc(sizeof(uint64_t) * n);
@@ -798,6 +939,7 @@ int zfo_encode(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t code
         case ZFO_RLE_DELTA_BP: enc_rle_delta(&s, x, dtype, n, 0); break;
         case ZFO_LZ77: enc_lz77(&s, x, n * es); break;
         case ZFO_F2I_BP: enc_f2i_bp(&s, x, n); break;
+        case ZFO_ANS: enc_ans(&s, x, n * es); break;
         }
         if (s.bad || s.n > 0xFFFFFFFFu) { free(s.p); b.bad = 1; break; }
         buf_resize(&b, pos + s.n);

@@ -36,6 +36,7 @@ extern "C" {
 #define ZFO_RLE_DELTA_BP 5
 #define ZFO_LZ77 6
 #define ZFO_F2I_BP 7
+#define ZFO_ANS 8
 
 /* status */
 #define ZFO_OK 0
