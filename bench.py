@@ -84,6 +84,11 @@ def single(kind, n):
         c = zf.Column.compress(x, zf.F2I_BP)
         desc = (f"F2I_BP float64, {n} prices with 2 decimal places uniform in [900, 105000), "
                 f"1 MiB chunks")
+    elif kind == "ans":
+        x = g.returnflag_column(n, 0.25, 0.5, 9)
+        c = zf.Column.compress(x, zf.ANS)
+        desc = (f"ANS bytes, {n} flags 'A'/'N'/'R' with probabilities 0.25/0.5/0.25, 64 KiB chunks, "
+                f"64 interleaved coders per chunk")
     elif kind == "copy":
         x = np.frombuffer(np.random.default_rng(0).bytes(n), np.uint8)
         c = zf.Column.compress(x, zf.PLAIN, chunk_bytes=(4 << 20, 4 << 20))
@@ -168,7 +173,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="fact", choices=["fact", "for", "rle", "lz", "f2i", "copy"])
+    ap.add_argument("--workload", default="fact", choices=["fact", "for", "rle", "lz", "f2i", "ans", "copy"])
     ap.add_argument("--rows", type=int, default=None)
     ap.add_argument("--no-e2e", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -192,7 +197,7 @@ def main():
         cols, xs, names, desc = fact_table(args.rows or g.FACT_ROWS)
     else:
         n = args.rows or {"for": 1 << 28, "rle": 1 << 26, "lz": 1 << 30, "f2i": 1 << 26,
-                           "copy": 1 << 30}[args.workload]
+                           "ans": 1 << 30, "copy": 1 << 30}[args.workload]
         cols, xs, names, desc = single(args.workload, n)
     plain = sum(c.plain_bytes for c in cols)
     comp = sum(c.host_pointer()[1] for c in cols)
@@ -266,7 +271,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": kinds[dom]["GBps"], "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(kinds[dom]["GBps"] / HBM_PEAK_GBPS, 4),
                      "traffic": read_traffic(f"{args.workload}/{dom}"),
-                     "kernel": "k_decode_lz (LZ77)" if dom == "LZ77" else f"k_decode_kind<{dom}>",
+                     "kernel": {"LZ77": "k_decode_lz (LZ77)", "ANS": "k_decode_ans"}.get(dom, f"k_decode_kind<{dom}>"),
                      "algorithmic_bytes_per_launch": kinds[dom]["algorithmic_bytes"],
                      "avg_launch_ms": kinds[dom]["ms"]},
         "kernels": kinds,

@@ -89,6 +89,13 @@ typedef enum {
  *                   u32 poff, u32 xoff, u16 nx, u8 e, u8 0, 8 zero bytes};
  *                   exception records {u32 index in block (increasing), u32 0,
  *                   u64 bits} at xoff.  F64.
+ *  ZF_ANS           [NP] range ANS over the chunk's bytes (Sec. 2.1), static
+ *                   order-0 model with M = 4096 (frequencies quantised from
+ *                   the byte counts), byte i coded by coder i mod 64, state
+ *                   in [2^16, 2^32), 16-bit renormalisation.  Header {u32 n,
+ *                   u32 nw, u32 0, u32 0}, u16 f[256], u32 final state[64],
+ *                   u32 word offset[64], then nw u16 words, each coder's in
+ *                   decode order.  Any dtype (decoded as bytes).
  */
 typedef enum {
     ZF_AUTO = 0,
@@ -98,7 +105,8 @@ typedef enum {
     ZF_DELTA_BP = 4,
     ZF_RLE_DELTA_BP = 5,
     ZF_LZ77 = 6,
-    ZF_F2I_BP = 7
+    ZF_F2I_BP = 7,
+    ZF_ANS = 8
 } zf_codec;
 
 typedef void *zf_stream_t;              /* a hipStream_t */
@@ -162,6 +170,7 @@ void zf_column_free(zf_column_t *col);
 /* Kernel kinds: one decode routine per pattern class and value width. */
 typedef enum {
     ZF_KIND_LZ77 = 0,
+    ZF_KIND_ANS,     /* range ANS, one chunk per wavefront */
     ZF_KIND_RLE64,   /* RLE_DELTA_BP and DELTA_BP, int64 */
     ZF_KIND_RLE32,   /* RLE_DELTA_BP and DELTA_BP, int32 */
     ZF_KIND_DICT128,

@@ -20,7 +20,7 @@ ARCH = "gfx950"
 
 HOST_SRC = ["abi.cpp", "format.cpp", "encode.cpp", "plan.cpp", "run.cpp", "tune.cpp", "features.cpp"]
 HIP_SRC = ["k_persistent.hip", "k_for32.hip", "k_dict32.hip", "k_for64.hip", "k_dict64.hip",
-           "k_fp128.hip", "k_f2i.hip", "k_gp.hip", "k_np.hip", "k_mlp.hip"]
+           "k_fp128.hip", "k_f2i.hip", "k_gp.hip", "k_np.hip", "k_ans.hip", "k_mlp.hip"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-I", INCLUDE, "-I", CSRC, "-I", "/opt/rocm/include", "-Wall",
           "-Wno-unused-function", "-Wno-unused-parameter"]

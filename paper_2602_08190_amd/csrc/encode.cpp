@@ -194,6 +194,87 @@ static void enc_f2i(std::vector<uint8_t> &s, const uint8_t *x, uint32_t n) {
     }
 }
 
+// ------------------------------------------------------------------- ANS
+// Range ANS over the chunk's bytes (static order-0 model, M = 4096), byte i
+// coded by coder i mod 64.  Frequencies: floor(count * M / n), at least 1 for
+// a present byte; a shortfall goes to the most frequent byte (ties: the
+// smallest), an excess is taken one at a time from the largest frequency
+// (ties: the smallest byte).  Each coder runs over its bytes backwards from
+// x = 2^16, emitting the low 16 bits while x >= 2^20 * f; its words are
+// stored in the order the decoder reads them (reversed).
+static void ans_frequencies(const uint8_t *x, uint64_t n, uint32_t f[256]) {
+    uint64_t cnt[256] = {0};
+    for (uint64_t i = 0; i < n; i++) cnt[x[i]]++;
+    uint32_t total = 0;
+    for (int b = 0; b < 256; b++) {
+        f[b] = cnt[b] ? std::max<uint32_t>(1, uint32_t(cnt[b] * kAnsM / n)) : 0;
+        total += f[b];
+    }
+    if (total < kAnsM) {
+        int top = 0;
+        for (int b = 1; b < 256; b++)
+            if (cnt[b] > cnt[top]) top = b;
+        f[top] += kAnsM - total;
+        total = kAnsM;
+    }
+    while (total > kAnsM) {
+        int top = -1;
+        for (int b = 0; b < 256; b++)
+            if (f[b] > 1 && (top < 0 || f[b] > f[top])) top = b;
+        f[top]--;
+        total--;
+    }
+}
+
+static void enc_ans(std::vector<uint8_t> &s, const uint8_t *x, uint32_t n) {
+    uint32_t f[256], cum[256];
+    ans_frequencies(x, n, f);
+    for (uint32_t b = 0, c = 0; b < 256; b++) {
+        cum[b] = c;
+        c += f[b];
+    }
+    std::vector<std::vector<uint16_t>> words(kAnsLanes);
+    uint32_t state[kAnsLanes];
+    for (uint32_t j = 0; j < kAnsLanes; j++) {
+        uint64_t st = kAnsL;
+        if (j < n) {
+            const uint32_t cnt = (n - 1 - j) / kAnsLanes + 1;
+            words[j].reserve(cnt);
+            for (uint32_t k = cnt; k-- > 0;) {
+                const uint32_t b = x[j + uint64_t(k) * kAnsLanes];
+                const uint64_t lim = (uint64_t(kAnsL >> 12) << 16) * f[b];
+                while (st >= lim) {
+                    words[j].push_back(uint16_t(st));
+                    st >>= 16;
+                }
+                st = (st / f[b]) * kAnsM + st % f[b] + cum[b];
+            }
+        }
+        state[j] = uint32_t(st);
+    }
+    uint64_t nw = 0;
+    for (auto &w : words) nw += w.size();
+    s.assign(kAnsHdr + 2 * nw, 0);
+    uint8_t *p = s.data();
+    wr32(p, n);
+    wr32(p + 4, uint32_t(nw));
+    for (uint32_t b = 0; b < 256; b++) {
+        p[16 + 2 * b] = uint8_t(f[b]);
+        p[17 + 2 * b] = uint8_t(f[b] >> 8);
+    }
+    uint64_t at = 0;
+    for (uint32_t j = 0; j < kAnsLanes; j++) {
+        wr32(p + 528 + 4 * j, state[j]);
+        wr32(p + 784 + 4 * j, uint32_t(at));
+        for (size_t k = words[j].size(); k-- > 0;) {
+            const uint16_t w = words[j][k];
+            p[kAnsHdr + 2 * at] = uint8_t(w);
+            p[kAnsHdr + 2 * at + 1] = uint8_t(w >> 8);
+            at++;
+        }
+    }
+}
+
 // ------------------------------------------------------------ dictionary
 // Open-addressing set/map over keys of up to 16 bytes.
 struct KeyTable {
@@ -543,6 +624,7 @@ static void encode_chunk(std::vector<uint8_t> &out, uint32_t codec, uint32_t dty
         return;
     case C_LZ77: enc_lz77(out, x, n * es, sc); return;
     case C_F2I_BP: enc_f2i(out, x, n); return;
+    case C_ANS: enc_ans(out, x, n * es); return;
     }
     fail(ZF_E_INVALID, "unknown codec %u", codec);
 }
@@ -573,7 +655,7 @@ void compress_host(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t 
         ZF_REQUIRE(sum == n_elems, ZF_E_INVALID, "chunk sizes sum to %llu, not %llu",
                    (unsigned long long)sum, (unsigned long long)n_elems);
     } else {
-        const bool lz = codec == C_LZ77;
+        const bool lz = codec == C_LZ77 || codec == C_ANS;  // 64 KiB chunks
         uint64_t lo = o.chunk_bytes_min ? o.chunk_bytes_min : (lz ? kLzMaxChunk : (1u << 20));
         uint64_t hi = std::max<uint64_t>(lo, o.chunk_bytes_max ? o.chunk_bytes_max : lo);
         uint64_t rs = o.seed ^ 0x5A17C0DEull;
@@ -684,7 +766,7 @@ void compress_host(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t 
             encode_chunk(out.bytes, cc[i], dtype, x, ce[i], &dict, *sc);
         } else {
             // smallest stream among the applicable codecs
-            const uint32_t cands[] = {C_FOR_BP, C_DICT_BP, C_DELTA_BP, C_RLE_DELTA_BP, C_LZ77, C_F2I_BP};
+            const uint32_t cands[] = {C_FOR_BP, C_DICT_BP, C_DELTA_BP, C_RLE_DELTA_BP, C_LZ77, C_F2I_BP, C_ANS};
             encode_chunk(out.bytes, C_PLAIN, dtype, x, ce[i], nullptr, *sc);
             out.codec = C_PLAIN;
             std::vector<uint8_t> tmp;

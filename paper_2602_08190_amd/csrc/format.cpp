@@ -42,6 +42,7 @@ bool codec_allows(uint32_t codec, uint32_t dtype) {
     case C_RLE_DELTA_BP: return dtype == D_I32 || dtype == D_I64;
     case C_DICT_BP: return dtype != D_BYTES && dtype != D_F64;
     case C_F2I_BP: return dtype == D_F64;
+    case C_ANS: return true;
     }
     return false;
 }
@@ -55,6 +56,7 @@ Kind kind_of(uint32_t codec, uint32_t dtype) {
     case C_RLE_DELTA_BP: return dtype == D_I32 ? K_RLE32 : K_RLE64;
     case C_LZ77: return K_LZ;
     case C_F2I_BP: return K_F2I;
+    case C_ANS: return K_ANS;
     }
     fail(ZF_E_CORRUPT, "unknown codec %u", codec);
 }
@@ -230,6 +232,20 @@ void check_stream(const ColumnView &v, const uint8_t *blob, uint32_t i) {
                            xoff + 16ull * nx <= L,
                        ZF_E_CORRUPT, "chunk %u block %llu: bad directory entry", i,
                        (unsigned long long)b);
+        }
+        return;
+    }
+    case C_ANS: {
+        ZF_REQUIRE(L >= kAnsHdr && rd32(s) == c.plain_len && kAnsHdr + 2ull * rd32(s + 4) == L,
+                   ZF_E_CORRUPT, "chunk %u: ANS header does not match its sizes", i);
+        uint32_t sum = 0;
+        for (uint32_t t = 0; t < 256; t++) sum += rd16(s + 16 + 2 * t);
+        ZF_REQUIRE(sum == kAnsM, ZF_E_CORRUPT, "chunk %u: ANS frequencies sum to %u", i, sum);
+        uint32_t prev = 0;
+        for (uint32_t j = 0; j < kAnsLanes; j++) {
+            const uint32_t w = rd32(s + 784 + 4 * j);
+            ZF_REQUIRE(w >= prev && w <= rd32(s + 4), ZF_E_CORRUPT, "chunk %u: ANS word offsets", i);
+            prev = w;
         }
         return;
     }

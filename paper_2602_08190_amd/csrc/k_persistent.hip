@@ -7,7 +7,7 @@ namespace zf {
 // Persistent: every wave pulls units from one queue until it is empty.
 // Units are ordered by kind, the costliest kinds first.
 __global__ __launch_bounds__(256) void k_decode_persistent(LaunchArgs A) {
-    __shared__ uint32_t lz_rows[4][64 * 16];
+    __shared__ uint32_t lz_rows[4][1280];
     uint32_t *mine = lz_rows[threadIdx.x / 64];
     const uint32_t n = A.kind_begin[K_COUNT];
     for (;;) {
@@ -51,6 +51,7 @@ hipError_t launch_decode(const LaunchArgs &A, uint32_t persistent_waves, const u
         return hipGetLastError();
     }
     launch_lz(A, wpb[K_LZ], lz_blk, st);
+    launch_ans(A, wpb[K_ANS], st);
     launch_rle32(A, wpb[K_RLE32], st);
     launch_rle64(A, wpb[K_RLE64], st);
     launch_dict128(A, wpb[K_DICT128], st);

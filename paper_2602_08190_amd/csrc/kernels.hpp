@@ -958,6 +958,105 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, uint32_t *row) {
     if (pos != plain || lp != nlit || ep != next) flag(A.err, ERR_CORRUPT);
 }
 
+// ===================================================================== ANS
+// One wave decodes one chunk: lane j runs coder j, which holds bytes j,
+// j + 64, j + 128, ... (Sec. 3.1 sees ANS as one serial state chain per chunk;
+// the 64 interleaved chains of a chunk advance in lockstep).  Per wave the LDS
+// holds the model: slot -> byte (4096 bytes) and byte -> {f, cum} (256 dwords).
+// A coder's next four 16-bit words are loaded ahead of their use, so the loop
+// waits on memory only when a coder drains words faster than that.
+// lds: this wave's 1280 dwords.
+ZF_DEV void unit_ans(const LaunchArgs &A, const ChunkDesc &ck, uint32_t *lds) {
+    const uint8_t *s = A.comp + ck.comp_off;
+    const uint32_t lane = lane_id();
+    const uint32_t es = ck.dtype == D_I32 ? 4 : (ck.dtype == D_I64 || ck.dtype == D_F64) ? 8
+                        : ck.dtype == D_FIXED16 ? 16 : 1;
+    const uint32_t n = ck.n_elems * es;
+    uint8_t *out = A.out_tab[ck.col] + ck.out_off;
+    // the host checked: comp_len = 1040 + 2 nw, n matches, frequencies sum to
+    // M, word offsets non-decreasing and within nw
+    const uint32_t nw = first32(ld32u(s + 4));
+    uint8_t *sym = reinterpret_cast<uint8_t *>(lds);
+    uint32_t *fc = lds + kAnsM / 4;
+    // model: lane l owns bytes 4l .. 4l + 3
+    const uint32_t f2 = ld32u(s + 16 + 8 * lane), f3 = ld32u(s + 20 + 8 * lane);
+    const uint32_t f[4] = {f2 & 0xFFFFu, f2 >> 16, f3 & 0xFFFFu, f3 >> 16};
+    const uint32_t tot = f[0] + f[1] + f[2] + f[3];
+    uint32_t c = scan_add32(tot) - tot;  // cum of byte 4l
+#pragma unroll
+    for (uint32_t k = 0; k < 4; k++) {
+        fc[4 * lane + k] = f[k] | (c << 16);
+        c += f[k];
+    }
+    wave_fence();
+    // slot -> byte: lane l fills slots [64 l, 64 l + 64), walking the bytes
+    // from the one holding slot 64 l (a binary search over cum)
+    {
+        const uint32_t s0 = 64 * lane;
+        uint32_t lo = 0, hi = 256;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if ((fc[mid] >> 16) <= s0) lo = mid;
+            else hi = mid;
+        }
+        uint32_t b = lo, e = (fc[b] >> 16) + (fc[b] & 0xFFFFu);
+        for (uint32_t k = 0; k < 64; k += 4) {
+            uint32_t word = 0;
+#pragma unroll
+            for (uint32_t i = 0; i < 4; i++) {
+                while (s0 + k + i >= e) {  // next byte with a nonzero frequency
+                    b++;
+                    e = (fc[b] >> 16) + (fc[b] & 0xFFFFu);
+                }
+                word |= b << (8 * i);
+            }
+            *reinterpret_cast<uint32_t *>(sym + s0 + k) = word;
+        }
+    }
+    wave_fence();
+    // this coder's state and words
+    uint32_t x = ld32u(s + 528 + 4 * lane);
+    uint32_t w = ld32u(s + 784 + 4 * lane);
+    const uint32_t wend = lane + 1 < kAnsLanes ? ld32u(s + 788 + 4 * lane) : nw;
+    // words at, at+1, at+2, at+3 through a bounds-checked view of the chunk's
+    // words (0 past them): no branch, so the loads stay in flight until used.
+    // A coder never consumes past its own range in a valid stream; reading a
+    // neighbour's words ahead is harmless (the end check catches overruns).
+    const __amdgpu_buffer_rsrc_t rw =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(s + kAnsHdr), 0, int(2 * nw), 0x00020000);
+    auto ld16 = [&](uint32_t at) { return uint32_t(__builtin_amdgcn_raw_buffer_load_b16(rw, int(2 * at), 0, 0)); };
+    // the words ahead stay in four registers, combined only when taken into
+    // buf, so nothing waits for them before then
+    uint32_t a0 = ld16(w), a1 = ld16(w + 1), a2 = ld16(w + 2), a3 = ld16(w + 3);
+    uint64_t buf = uint64_t(a0 | (a1 << 16)) | (uint64_t(a2 | (a3 << 16)) << 32);
+    a0 = ld16(w + 4), a1 = ld16(w + 5), a2 = ld16(w + 6), a3 = ld16(w + 7);
+    uint32_t nbuf = 4;   // words left in buf
+    bool bad = false;
+    const uint32_t steps = (n + kAnsLanes - 1) / kAnsLanes;
+    for (uint32_t t = 0; t < steps; t++) {
+        const uint32_t i = t * kAnsLanes + lane;
+        if (i < n) {
+            const uint32_t slot = x & (kAnsM - 1);
+            const uint32_t b = sym[slot];
+            const uint32_t e = fc[b];
+            x = (e & 0xFFFFu) * (x >> 12) + slot - (e >> 16);
+            if (x < kAnsL) {  // one word at most: x >= 1 * 2^4 before the shift
+                x = (x << 16) | uint32_t(buf & 0xFFFFu);
+                buf >>= 16;
+                w++;
+                if (--nbuf == 0) {
+                    buf = uint64_t(a0 | (a1 << 16)) | (uint64_t(a2 | (a3 << 16)) << 32);
+                    nbuf = 4;
+                    a0 = ld16(w + 4), a1 = ld16(w + 5), a2 = ld16(w + 6), a3 = ld16(w + 7);
+                }
+            }
+            gp(out)[i] = uint8_t(b);
+        }
+    }
+    bad = x != kAnsL || w != wend;
+    if (any(bad)) flag(A.err, ERR_CORRUPT);
+}
+
 // ================================================================ PLAIN
 ZF_DEV void unit_plain(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck) {
     const uint8_t *src = A.comp + ck.comp_off;
@@ -990,8 +1089,8 @@ ZF_DEV void unit_plain(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck) 
 // ============================================================== dispatch
 // UNR: FP lane-steps of loads kept in flight; 0 = runtime-width FP path.
 template <uint32_t UNR>
-// lz_row: this wave's LDS scratch (64 * 16 dwords): the LZ77 row, or the RLE
-// window slots.
+// lz_row: this wave's LDS scratch (1280 dwords): the LZ77 row, the ANS model
+// or the RLE window slots.
 ZF_DEV void run_unit(const LaunchArgs &A, uint32_t kind, uint32_t u, uint32_t *lz_row) {
     const Tile t = A.tiles[u];
     const ChunkDesc ck = A.chunks[t.chunk];
@@ -1006,6 +1105,7 @@ ZF_DEV void run_unit(const LaunchArgs &A, uint32_t kind, uint32_t u, uint32_t *l
     case K_RLE32: unit_rle<uint32_t>(A, t, ck, lz_row); break;
     case K_RLE64: unit_rle<uint64_t>(A, t, ck, lz_row); break;
     case K_LZ: unit_lz<16>(A, ck, lz_row); break;
+    case K_ANS: unit_ans(A, ck, lz_row); break;
     }
 }
 
@@ -1052,6 +1152,8 @@ __global__ __launch_bounds__(1024) void k_decode_lz(LaunchArgs A) {
     unit_lz<BLK>(A, A.chunks[A.tiles[u].chunk], lz_smem + (threadIdx.x / 64) * 64 * BLK);
 }
 void launch_lz(const LaunchArgs &A, uint32_t waves, uint32_t blk, hipStream_t st);
+
+void launch_ans(const LaunchArgs &A, uint32_t waves, hipStream_t st);
 
 // Host launchers, one per kind, each defined in its kind's translation unit.
 #define ZF_KIND_LAUNCHERS(X)                                                                       \

@@ -14,6 +14,7 @@ namespace zf {
 static double rate_gbps(Kind k) {
     switch (k) {
     case K_LZ: return 150;
+    case K_ANS: return 500;
     case K_RLE32:
     case K_RLE64: return 2500;
     default: return 4000;
@@ -77,7 +78,8 @@ static void add_chunk(WorkTables &w, const zf_column &col, uint32_t ci, uint32_t
         }
         break;
     }
-    case K_LZ: T.push_back({idx, 0, 0, 0}); break;
+    case K_LZ:
+    case K_ANS: T.push_back({idx, 0, 0, 0}); break;
     default: break;
     }
     w.plain_bytes += c.plain_len;

@@ -76,7 +76,7 @@ struct Json {
     }
 };
 
-const char *kKindNames[K_COUNT] = {"LZ77", "RLE64", "RLE32", "DICT128", "DICT64",
+const char *kKindNames[K_COUNT] = {"LZ77", "ANS", "RLE64", "RLE32", "DICT128", "DICT64",
                                    "DICT32", "FOR64", "FOR32", "F2I", "PLAIN"};
 
 std::string default_cache_path() {

@@ -9,10 +9,13 @@ constexpr uint32_t kForBlock = 2048;   // values per FOR / bit-packing block
 constexpr uint32_t kRleGroup = 64;     // runs per RLE group record (one wave)
 constexpr uint32_t kLzMaxChunk = 65536;
 constexpr uint32_t kMaxCols = 256;     // columns per plan (output table size)
+// ANS: M = 2^12 model, state in [2^16, 2^32), 64 interleaved coders, stream
+// header of 16 + 512 (frequencies) + 256 (states) + 256 (word offsets) bytes.
+constexpr uint32_t kAnsM = 4096, kAnsL = 65536, kAnsLanes = 64, kAnsHdr = 1040;
 
 // Codec / dtype codes, as in zf.h.
 enum : uint8_t { C_PLAIN = 1, C_FOR_BP = 2, C_DICT_BP = 3, C_DELTA_BP = 4, C_RLE_DELTA_BP = 5, C_LZ77 = 6,
-                 C_F2I_BP = 7 };
+                 C_F2I_BP = 7, C_ANS = 8 };
 enum : uint8_t { D_I32 = 1, D_I64 = 2, D_BYTES = 3, D_FIXED16 = 4, D_F64 = 5 };
 
 // Kernel kinds: one device routine per (codec class, value width).  The
@@ -20,6 +23,7 @@ enum : uint8_t { D_I32 = 1, D_I64 = 2, D_BYTES = 3, D_FIXED16 = 4, D_F64 = 5 };
 // long serial LZ77 chunks start early and the short streaming units fill in.
 enum Kind : uint32_t {
     K_LZ = 0,
+    K_ANS,     // range ANS, 64 interleaved coders per chunk
     K_RLE64,   // RLE_DELTA_BP and DELTA_BP, int64
     K_RLE32,   // RLE_DELTA_BP and DELTA_BP, int32
     K_DICT128,
@@ -49,7 +53,7 @@ static_assert(sizeof(ChunkDesc) == 40, "ChunkDesc layout");
 // One unit of work for one wavefront.
 //   FOR / DICT / F2I: a = first block, b = number of blocks
 //   RLE / DELTA: a = first group, b = first element, c = end element
-//   LZ77: the whole chunk
+//   LZ77, ANS: the whole chunk
 //   PLAIN: a = first byte, b = end byte
 struct Tile {
     uint32_t chunk;

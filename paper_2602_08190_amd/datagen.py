@@ -257,3 +257,14 @@ def decimal_column(n, seed, lo, hi, scale=100, specials=0):
         pool = np.array([np.nan, np.inf, -np.inf, -0.0, 1.0 / 3.0, np.pi, 5e-324, 1e300])
         x[r.integers(0, n, size=specials)] = pool[r.integers(0, len(pool), size=specials)]
     return x
+
+
+def returnflag_column(n, p_a, p_n, seed):
+    """Bytes 'A', 'N', 'R' with probabilities p_a, p_n and 1 - p_a - p_n
+    (a flag column with a skewed distribution, the paper's ANS workload)."""
+    r = rng(seed)
+    u = r.random(n)
+    out = np.full(n, ord("R"), np.uint8)
+    out[u < p_a + p_n] = ord("N")
+    out[u < p_a] = ord("A")
+    return out

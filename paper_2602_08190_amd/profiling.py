@@ -15,7 +15,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-KIND_OF_ID = ["LZ77", "RLE64", "RLE32", "DICT128", "DICT64", "DICT32", "FOR64", "FOR32", "F2I", "PLAIN"]
+KIND_OF_ID = ["LZ77", "ANS", "RLE64", "RLE32", "DICT128", "DICT64", "DICT32", "FOR64", "FOR32", "F2I", "PLAIN"]
 
 
 def kernel_sha():
@@ -45,7 +45,8 @@ def stats(csv_path, out_path, command):
 
 def _kernel_of(kernel_id):
     """Name fragment of the per-kind decode kernel (LZ77 has its own)."""
-    return "k_decode_lz<" if KIND_OF_ID[kernel_id] == "LZ77" else f"k_decode_kind<{kernel_id}u>"
+    kind = KIND_OF_ID[kernel_id]
+    return {"LZ77": "k_decode_lz<", "ANS": "k_decode_ans"}.get(kind, f"k_decode_kind<{kernel_id}u>")
 
 
 def _per_dispatch(path, kernel_id):

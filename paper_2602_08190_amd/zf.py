@@ -15,9 +15,9 @@ LIB_PATH = os.path.join(HERE, "libzf.so")
 
 # dtypes and codecs (zf.h)
 I32, I64, BYTES, FIXED16, F64 = 1, 2, 3, 4, 5
-AUTO, PLAIN, FOR_BP, DICT_BP, DELTA_BP, RLE_DELTA_BP, LZ77, F2I_BP = 0, 1, 2, 3, 4, 5, 6, 7
+AUTO, PLAIN, FOR_BP, DICT_BP, DELTA_BP, RLE_DELTA_BP, LZ77, F2I_BP, ANS = 0, 1, 2, 3, 4, 5, 6, 7, 8
 CODEC_NAMES = {PLAIN: "PLAIN", FOR_BP: "FOR_BP", DICT_BP: "DICT_BP", DELTA_BP: "DELTA_BP",
-               RLE_DELTA_BP: "RLE_DELTA_BP", LZ77: "LZ77", F2I_BP: "F2I_BP"}
+               RLE_DELTA_BP: "RLE_DELTA_BP", LZ77: "LZ77", F2I_BP: "F2I_BP", ANS: "ANS"}
 ELEM_SIZE = {I32: 4, I64: 8, BYTES: 1, FIXED16: 16, F64: 8}
 OK, E_INVALID, E_UNSUPPORTED, E_CORRUPT, E_NOMEM, E_HIP, E_TOO_SMALL, E_STATE = range(8)
 
@@ -37,9 +37,9 @@ class EncodeOpts(ctypes.Structure):
 
 
 # kernel kinds (zf_kind), in enum order
-KINDS = ["LZ77", "RLE64", "RLE32", "DICT128", "DICT64", "DICT32", "FOR64", "FOR32", "F2I", "PLAIN"]
+KINDS = ["LZ77", "ANS", "RLE64", "RLE32", "DICT128", "DICT64", "DICT32", "FOR64", "FOR32", "F2I", "PLAIN"]
 KIND_GROUPS = {"FP": ["FOR32", "FOR64", "DICT32", "DICT64", "DICT128", "F2I"], "GP": ["RLE32", "RLE64"],
-               "NP": ["LZ77"]}
+               "NP": ["LZ77", "ANS"]}
 
 
 class Tile(ctypes.Structure):
@@ -327,6 +327,8 @@ def kind_of_column(col):
         return "LZ77"
     if codec == F2I_BP:
         return "F2I"
+    if codec == ANS:
+        return "ANS"
     if codec in (DELTA_BP, RLE_DELTA_BP):
         return "RLE32" if dt == I32 else "RLE64"
     if codec == DICT_BP:

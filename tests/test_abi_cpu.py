@@ -83,6 +83,35 @@ def test_encoder_byte_identical_f2i():
         assert np.array_equal(zo.decode(ours).view(np.uint64), x.view(np.uint64))
 
 
+def test_encoder_byte_identical_ans():
+    """ANS: text, skewed flags, one repeated byte, random bytes, tiny chunks,
+    an int32 column coded as bytes."""
+    cases = [(g.text_column(200000, 3), [65536, 65536, 200000 - 131072]),
+             (g.returnflag_column(70000, 0.05, 0.9, 1), [4096] * 17 + [70000 - 4096 * 17]),
+             (np.full(3000, 9, np.uint8), [1000, 2000]),
+             (np.frombuffer(g.rng(3).bytes(20000), np.uint8), [20000]),
+             (g.returnflag_column(200, 0.3, 0.4, 2), [1, 63, 64, 72]),
+             (g.sorted_runs_column(30000, 8, 1), [10000, 20000])]
+    for x, ce in cases:
+        ours, ref = same_streams(x, zf.ANS, ce)
+        assert ours.tobytes() == ref.tobytes()
+        assert np.array_equal(zo.decode(ours), x)
+
+
+def test_ans_host_validation():
+    x = g.returnflag_column(5000, 0.25, 0.5, 4)
+    b = zo.encode(x, zo.ANS).copy()
+    c = zo.chunks(b)[0]
+    t = b.copy()
+    t[c["comp_off"] + 16 + 2 * ord("A")] ^= 1  # frequencies no longer sum to 4096
+    with pytest.raises(zf.ZfError):
+        zf.Column.from_bytes(t, pinned=False)
+    t = b.copy()
+    t[c["comp_off"] + 784 + 4 * 7 + 3] = 0x7F  # a word offset past the words
+    with pytest.raises(zf.ZfError):
+        zf.Column.from_bytes(t, pinned=False)
+
+
 def test_encoder_byte_identical_fixed16_and_mixed():
     x = g.fixed16_column(30000, 25, 4)
     ours, ref = same_streams(x, zf.DICT_BP, [10000, 20000])

@@ -210,6 +210,35 @@ def test_f2i_auto_picks_float2int_for_decimals():
     check_bits([col], decode_image([col]), [x])
 
 
+# --------------------------------------------------------------- ANS (NP)
+def ans_columns():
+    xs = [g.text_column(300000, 5),
+          g.returnflag_column(500000, 0.25, 0.5, 6),
+          g.returnflag_column(100000, 0.01, 0.98, 7),
+          np.full(70000, 65, np.uint8),                             # one symbol: no words
+          np.frombuffer(g.rng(8).bytes(90000), np.uint8),           # incompressible
+          g.returnflag_column(200, 0.3, 0.4, 9)]
+    ces = [[65536] * 4 + [300000 - 4 * 65536], [4096] * 122 + [500000 - 4096 * 122],
+           [100000], [70000], [90000], [1, 63, 64, 72]]
+    return [zf.Column.compress(x, zf.ANS, chunk_elems=ce) for x, ce in zip(xs, ces)], xs
+
+
+def test_ans_streams_and_modes():
+    log("ans")
+    cols, xs = ans_columns()
+    check(cols, decode_image(cols), xs)
+    check(cols, decode_image(cols, persistent=True), xs)
+    check(cols, decode_image(cols, tiles={"ANS": dict(waves_per_block=16)}), xs)
+    outs, _ = decode_staged(cols, slot_bytes=1 << 20)
+    check(cols, outs, xs)
+
+
+def test_ans_int_column():
+    x = g.sorted_runs_column(100000, 8, 5)
+    cols = [zf.Column.compress(x, zf.ANS, chunk_elems=[50000, 50000])]
+    check(cols, decode_image(cols), [x])
+
+
 # -------------------------------------------------------------- NP codec
 # LZ77 kernel knob: output bytes per block of the copy step
 LZ_BLK = [4, 8, 16]
@@ -411,6 +440,12 @@ def test_device_detects_corrupt_streams():
     xoff = c["comp_off"] + int(np.frombuffer(b[c["comp_off"] + 16:c["comp_off"] + 20].tobytes(), np.uint32)[0])
     first, second = b[xoff:xoff + 4].copy(), b[xoff + 16:xoff + 20].copy()
     b[xoff:xoff + 4], b[xoff + 16:xoff + 20] = second, first
+    _expect_corrupt([zf.Column.from_bytes(b)])
+    # ANS: a flipped word (the coder then ends off its start state)
+    x = g.returnflag_column(20000, 0.25, 0.5, 10)
+    b = zo.encode(x, zo.ANS).copy()
+    c = zo.chunks(b)[0]
+    b[c["comp_off"] + 1040 + 10] ^= 0x5A
     _expect_corrupt([zf.Column.from_bytes(b)])
     # DICT: a code beyond the dictionary
     y = g.fixed16_column(4096, 4, 1)
