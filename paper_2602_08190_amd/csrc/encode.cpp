@@ -655,8 +655,10 @@ void compress_host(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t 
         ZF_REQUIRE(sum == n_elems, ZF_E_INVALID, "chunk sizes sum to %llu, not %llu",
                    (unsigned long long)sum, (unsigned long long)n_elems);
     } else {
-        const bool lz = codec == C_LZ77 || codec == C_ANS;  // 64 KiB chunks
-        uint64_t lo = o.chunk_bytes_min ? o.chunk_bytes_min : (lz ? kLzMaxChunk : (1u << 20));
+        // LZ77 chunks hold at most 64 KiB; ANS defaults to 64 KiB chunks (one
+        // wave each) but takes any size; block codecs round to 2048 values
+        const bool lz = codec == C_LZ77, bytewise = lz || codec == C_ANS;
+        uint64_t lo = o.chunk_bytes_min ? o.chunk_bytes_min : (bytewise ? kLzMaxChunk : (1u << 20));
         uint64_t hi = std::max<uint64_t>(lo, o.chunk_bytes_max ? o.chunk_bytes_max : lo);
         uint64_t rs = o.seed ^ 0x5A17C0DEull;
         for (uint64_t at = 0; at < n_elems;) {
@@ -666,7 +668,8 @@ void compress_host(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t 
                 bytes = uint64_t(std::exp(std::log(double(lo)) + u * (std::log(double(hi)) - std::log(double(lo)))));
             }
             uint64_t e = lz ? std::min<uint64_t>(bytes, kLzMaxChunk) / es
-                            : std::max<uint64_t>(kForBlock, bytes / es / kForBlock * kForBlock);
+                         : bytewise ? bytes / es
+                                    : std::max<uint64_t>(kForBlock, bytes / es / kForBlock * kForBlock);
             e = std::max<uint64_t>(1, std::min<uint64_t>(e, n_elems - at));
             e = std::min<uint64_t>(e, 0xFFFFFFFFull / es);
             ce.push_back(uint32_t(e));
