@@ -87,24 +87,19 @@ ZF_DEV T scan_addT(T x) {
     if constexpr (sizeof(T) == 8) return T(scan_add64(uint64_t(x)));
     else return T(scan_add32(uint32_t(x)));
 }
-// Inclusive scan across the wave keeping the value of the highest lane whose
-// x is nonzero (0 where no lane up to this one has one); the same DPP moves
-// as scan_add32.
-ZF_DEV uint32_t scan_last_nonzero(uint32_t x) {
-    uint32_t t;
-    t = dpp<0x111, 0xF>(x);
-    x = x ? x : t;
-    t = dpp<0x112, 0xF>(x);
-    x = x ? x : t;
-    t = dpp<0x114, 0xF>(x);
-    x = x ? x : t;
-    t = dpp<0x118, 0xF>(x);
-    x = x ? x : t;
-    t = dpp<0x142, 0xA>(x);
-    x = x ? x : t;
-    t = dpp<0x143, 0xC>(x);
-    x = x ? x : t;
-    return x;
+// The x of the highest lane below this one whose x is nonzero, or `carry`
+// where there is none; `carry` then becomes the x of the wave's highest lane
+// with a nonzero x (unchanged if there is none).  A ballot finds the lane,
+// one cross-lane read fetches its x.
+ZF_DEV uint32_t last_nonzero_below(uint32_t x, uint32_t &carry) {
+    const uint64_t m = __ballot(x != 0);
+    const uint64_t b = m & ((uint64_t(1) << __lane_id()) - 1);
+    const uint32_t hi = uint32_t(b >> 32), lo = uint32_t(b);
+    const uint32_t src = hi ? 63u - uint32_t(__clz(int(hi))) : 31u - uint32_t(__clz(int(lo)));
+    const uint32_t got = uint32_t(__builtin_amdgcn_ds_bpermute(int(src * 4), int(x)));
+    const uint32_t r = b ? got : carry;
+    if (m) carry = uint32_t(__builtin_amdgcn_readlane(int(x), 63 - __builtin_clzll(m)));
+    return r;
 }
 
 ZF_DEV uint32_t wave_max32(uint32_t x) {
@@ -700,11 +695,7 @@ ZF_DEV void unit_rle(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, ui
                     m[i] = slot[64 * i + lane];
                     last = m[i] ? m[i] : last;
                 }
-                const uint32_t inc = scan_last_nonzero(last);
-                uint32_t cur1 = uint32_t(__builtin_amdgcn_ds_bpermute(int((lane - 1) * 4), int(inc)));
-                cur1 = (lane != 0 && cur1) ? cur1 : carry;
-                const uint32_t tail = rl32(inc, 63);
-                carry = tail ? tail : carry;
+                uint32_t cur1 = last_nonzero_below(last, carry);
                 U val[R];
 #pragma unroll
                 for (uint32_t i = 0; i < R; i++) {
@@ -807,6 +798,8 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, uint32_t *row) {
         __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(lits), 0, int(nlit), 0x00020000);
     // misalignment of the chunk's output, for BLK-aligned stores
     const uint32_t mis = uint32_t(reinterpret_cast<uintptr_t>(out) & (BLK - 1));
+    // a dword read at offset x stays inside a view when x < view size - 3
+    const uint32_t plain4 = plain >= 4 ? plain - 3 : 0, nlit4 = nlit >= 4 ? nlit - 3 : 0;
     uint32_t pos = 0, lp = 0, ep = 0;
     uint32_t tag = lane < nseq ? tags[lane] : 0u;
     uint32_t off = lane < nseq ? offs[lane] : 0u;
@@ -889,28 +882,69 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, uint32_t *row) {
                     v[k] = row[64 * k + lane];
                     last = v[k] ? v[k] : last;
                 }
-                const uint32_t incl = scan_last_nonzero(last);
-                uint32_t cur = uint32_t(__builtin_amdgcn_ds_bpermute(int((lane - 1) * 4), int(incl)));
-                cur = (lane != 0 && cur) ? cur : carry;
-                const uint32_t tail = rl32(incl, 63);
-                carry = tail ? tail : carry;
+                uint32_t cur = last_nonzero_below(last, carry);
                 const uint32_t Bb = w0 + BLK * lane;
                 const int32_t Bi = W + int32_t(BLK * lane);
                 // a block wholly outside [pos, end) has no segment start; its
                 // reads are sent out of range of both views (no memory traffic)
-                if (Bi + int32_t(BLK) <= int32_t(pos) || Bi >= int32_t(end)) cur = 0x7FFFFFF0u - Bb;
-                uint32_t byte[BLK];
+                const bool live = Bi + int32_t(BLK) > int32_t(pos) && Bi < int32_t(end);
+                if (!live) cur = 0x7FFFFFF0u - Bb;
+                // one unaligned dword read per run of equal delta inside each
+                // 4-byte quarter of the block: at the quarter's first byte and
+                // at every segment start.  Byte t of a run sits t bytes into
+                // the run's dword.  A dword that would reach past the end of
+                // its view is not read; its block takes the byte path below.
+                const uint32_t cur0 = cur;
+                uint32_t ro[BLK], rl[BLK];
+                bool slow = false;
+                // all reads first (every lane issues every read; a lane with no
+                // run start at byte k reads nothing), then the bytes
 #pragma unroll
                 for (uint32_t k = 0; k < BLK; k++) {
                     cur = v[k] ? v[k] : cur;
+                    const bool start = (k & 3u) == 0 || v[k] != 0;
                     const uint32_t x = Bb + k + cur;
-                    byte[k] = __builtin_amdgcn_raw_buffer_load_b8(rs_out, int(x), 0, 0) |
-                              __builtin_amdgcn_raw_buffer_load_b8(rs_lit, int(x ^ 0x80000000u), 0, 0);
+                    const uint32_t xl = x ^ 0x80000000u;
+                    const bool in_out = start && x < plain4, in_lit = start && xl < nlit4;
+                    // (a byte of a partial block outside [pos, end) may send its
+                    // block down the byte path needlessly; that is rare)
+                    slow = slow || (live && start && !in_out && !in_lit);
+                    ro[k] = __builtin_amdgcn_raw_buffer_load_b32(rs_out, int(in_out ? x : 0x7FFFFFF0u), 0, 0);
+                    rl[k] = __builtin_amdgcn_raw_buffer_load_b32(rs_lit, int(in_lit ? xl : 0x7FFFFFF0u), 0, 0);
                 }
                 uint32_t wv[BLK / 4];
 #pragma unroll
-                for (uint32_t d = 0; d < BLK / 4; d++)
-                    wv[d] = byte[4 * d] | (byte[4 * d + 1] << 8) | (byte[4 * d + 2] << 16) | (byte[4 * d + 3] << 24);
+                for (uint32_t d = 0; d < BLK / 4; d++) {
+                    uint32_t word = 0, run = 0;
+#pragma unroll
+                    for (uint32_t t = 0; t < 4; t++) {
+                        const uint32_t k = 4 * d + t;
+                        run = (t == 0 || v[k] != 0) ? (ro[k] | rl[k]) : run >> 8;
+                        word |= (run & 0xFFu) << (8 * t);
+                    }
+                    wv[d] = word;
+                }
+                if (any(slow)) {
+                    // byte by byte through the views (the chunk's last bytes,
+                    // the literal array's last bytes)
+                    if (slow) {
+                        uint32_t c = cur0;
+#pragma unroll
+                        for (uint32_t d = 0; d < BLK / 4; d++) {
+                            uint32_t word = 0;
+#pragma unroll
+                            for (uint32_t t = 0; t < 4; t++) {
+                                const uint32_t k = 4 * d + t;
+                                c = v[k] ? v[k] : c;
+                                const uint32_t x = Bb + k + c;
+                                word |= (__builtin_amdgcn_raw_buffer_load_b8(rs_out, int(x), 0, 0) |
+                                         __builtin_amdgcn_raw_buffer_load_b8(rs_lit, int(x ^ 0x80000000u), 0, 0))
+                                        << (8 * t);
+                            }
+                            wv[d] = word;
+                        }
+                    }
+                }
                 if (Bi >= int32_t(pos) && Bi + int32_t(BLK) <= int32_t(end)) {
                     if constexpr (BLK == 16) {
                         const u32x4 vv = {wv[0], wv[1], wv[2], wv[3]};
@@ -1144,7 +1178,7 @@ __global__ __launch_bounds__(1024) void k_decode_kind(LaunchArgs A) {
 // LZ77: one unit (chunk) per wave; each wave's LDS row is dynamic shared
 // memory, 64 * BLK dwords.
 template <uint32_t BLK>
-__global__ __launch_bounds__(1024) void k_decode_lz(LaunchArgs A) {
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_decode_lz(LaunchArgs A) {
     const uint32_t waves = blockDim.x / 64;
     const uint32_t u = A.kind_begin[K_LZ] + blockIdx.x * waves + first32(threadIdx.x / 64);
     if (u >= A.kind_begin[K_LZ + 1]) return;
