@@ -763,9 +763,11 @@ ZF_DEV uint32_t ext_pick(uint32_t ew, uint32_t k) {
 //    here; no delta is ever zero);
 //  * each block lane carries the last delta forward over its bytes, taking
 //    the delta in force at its first byte from the blocks before it (a wave
-//    scan) or from the previous step;
-//  * every byte is read through two bounds-checked buffer views (the output
-//    and the literals), one of which is out of range and reads 0, and each
+//    ballot over the wave) or from the previous step;
+//  * each run of equal delta inside a 4-byte quarter of a block is read as
+//    one unaligned dword through two bounds-checked buffer views (the output
+//    and the literals), one of which is out of range and reads 0; a dword
+//    that would reach past its view sends the block down a byte path; each
 //    block is written with one aligned store.
 // BLK: bytes per block (4, 8 or 16); row: this wave's 64 * BLK dwords.
 template <uint32_t BLK>
