@@ -683,6 +683,170 @@ static int dec_rle_delta(const uint8_t *s, uint64_t comp_len, uint32_t dtype, ui
     return ZFO_OK;
 }
 
+/* ============================================================ DeltaStride
+ * DeltaStride (Sec. 5, a Group-Parallel RLE variant for increasing integer
+ * keys): the column is cut into runs that are arithmetic progressions, each a
+ * (start, stride, count) triple, and the triples are nested with bit-packing.
+ * Runs are maximal from the left: a run starting at element i takes
+ * stride d = x[i+1] - x[i] (mod 2^bits) and extends while the next difference
+ * equals d; a run that starts on the last element has count 1 and stride 0.
+ * Every RLE_GROUP consecutive runs form a group with its own output offset and
+ * start value, so groups decode independently.  Within a group the start of
+ * run j >= 1 is predicted as the value run j-1 would produce next,
+ * s_{j-1} + d_{j-1} * r_{j-1}; the stored gap is the difference to it
+ * (0 for runs that continue a progression after a lone element, small for
+ * nearly increasing keys).
+ * Stream:
+ *   header 16 bytes: u32 n_runs, u32 n_groups = ceil(n_runs/64),
+ *                    u32 runs_off, u32 0
+ *   group records, 32 bytes each at offset 16 + 32*g:
+ *       u32 out_off (element index of the group's first run in the chunk),
+ *       u32 poff (byte offset of the group's payload, 8-aligned),
+ *       u32 widths (bits 0-7: gap width wg, bits 8-15: stride width wd),
+ *       u32 0, i64 base (start of the group's first run), i64 dmin
+ *   payload of group g at poff: i64 gmin, then cnt-1 gap fields of width wg
+ *       (field j-1 = gap_j - gmin mod 2^bits, j = 1 .. cnt-1), then, from the
+ *       next u32 word, cnt stride fields of width wd (field j = d_j - dmin
+ *       mod 2^bits); gmin, dmin are the smallest gap and stride read as
+ *       signed integers (0 when there is none); a width is the bit length of
+ *       the largest field.
+ *   run lengths: u32[n_runs] at runs_off = align16(end of the payloads).
+ *   comp_len = runs_off + 4*n_runs.
+ * Decode: s_0 = base, s_j = s_{j-1} + d_{j-1} r_{j-1} + gap_j; run j writes
+ * s_j + d_j t for t = 0 .. r_j - 1 (all mod 2^bits). */
+static int64_t as_signed(uint64_t v, uint32_t bits) {
+    return bits == 32 ? (int64_t)(int32_t)(uint32_t)v : (int64_t)v;
+}
+
+static void enc_dstride(buf_t *s, const uint8_t *x, uint32_t dtype, uint32_t n) {
+    uint32_t bits = int_bits(dtype);
+    uint64_t mask = mask_bits(bits);
+    uint64_t *st = (uint64_t *)malloc(sizeof(uint64_t) * (n ? n : 1));
+    uint64_t *sd = (uint64_t *)malloc(sizeof(uint64_t) * (n ? n : 1));
+    uint32_t *len = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+    if (!st || !sd || !len) { free(st); free(sd); free(len); s->bad = 1; return; }
+    /* maximal progressions from the left */
+    uint32_t nr = 0;
+    for (uint32_t i = 0; i < n;) {
+        uint64_t a = (uint64_t)load_int(x, dtype, i) & mask, d = 0;
+        uint32_t r = 1;
+        if (i + 1 < n) {
+            d = (((uint64_t)load_int(x, dtype, i + 1)) - a) & mask;
+            r = 2;
+            while (i + r < n && ((((uint64_t)load_int(x, dtype, i + r)) -
+                                  (uint64_t)load_int(x, dtype, i + r - 1)) & mask) == d)
+                r++;
+        }
+        st[nr] = a;
+        sd[nr] = d;
+        len[nr] = r;
+        nr++;
+        i += r;
+    }
+    uint32_t ng = (nr + RLE_GROUP - 1) / RLE_GROUP;
+    uint64_t pos = 16 + (uint64_t)32 * ng;
+    buf_resize(s, pos);
+    uint32_t out_off = 0;
+    for (uint32_t g = 0; g < ng && !s->bad; g++) {
+        uint32_t r0 = g * RLE_GROUP, cnt = nr - r0 < RLE_GROUP ? nr - r0 : RLE_GROUP;
+        /* gaps of runs 1 .. cnt-1 against the predicted start */
+        uint64_t gap[RLE_GROUP];
+        for (uint32_t j = 1; j < cnt; j++) {
+            uint64_t pred = (st[r0 + j - 1] + sd[r0 + j - 1] * (uint64_t)len[r0 + j - 1]) & mask;
+            gap[j] = (st[r0 + j] - pred) & mask;
+        }
+        int64_t gmin = 0, dmin = 0;
+        for (uint32_t j = 1; j < cnt; j++)
+            if (j == 1 || as_signed(gap[j], bits) < gmin) gmin = as_signed(gap[j], bits);
+        for (uint32_t j = 0; j < cnt; j++)
+            if (j == 0 || as_signed(sd[r0 + j], bits) < dmin) dmin = as_signed(sd[r0 + j], bits);
+        uint64_t gmax = 0, dmax = 0;
+        for (uint32_t j = 1; j < cnt; j++) {
+            uint64_t f = (gap[j] - (uint64_t)gmin) & mask;
+            if (f > gmax) gmax = f;
+        }
+        for (uint32_t j = 0; j < cnt; j++) {
+            uint64_t f = (sd[r0 + j] - (uint64_t)dmin) & mask;
+            if (f > dmax) dmax = f;
+        }
+        uint32_t wg = bitlen64(gmax), wd = bitlen64(dmax);
+        pos = (pos + 7) & ~(uint64_t)7;
+        uint64_t gw = packed_words(cnt - 1, wg), dw = packed_words(cnt, wd);
+        buf_resize(s, pos + 8 + 4 * (gw + dw));
+        if (s->bad) break;
+        uint8_t *rec = s->p + 16 + (uint64_t)32 * g;
+        put32(rec + 0, out_off);
+        put32(rec + 4, (uint32_t)pos);
+        put32(rec + 8, wg | (wd << 8));
+        put32(rec + 12, 0);
+        put64(rec + 16, (uint64_t)as_signed(st[r0], bits));
+        put64(rec + 24, (uint64_t)dmin);
+        put64(s->p + pos, (uint64_t)gmin);
+        for (uint32_t j = 1; j < cnt; j++)
+            pack_bits(s->p + pos + 8, j - 1, wg, (gap[j] - (uint64_t)gmin) & mask);
+        for (uint32_t j = 0; j < cnt; j++)
+            pack_bits(s->p + pos + 8 + 4 * gw, j, wd, (sd[r0 + j] - (uint64_t)dmin) & mask);
+        pos += 8 + 4 * (gw + dw);
+        for (uint32_t j = 0; j < cnt; j++) out_off += len[r0 + j];
+    }
+    if (!s->bad) {
+        uint64_t roff = align16(pos);
+        buf_resize(s, roff + 4 * (uint64_t)nr);
+        if (!s->bad) {
+            put32(s->p + 0, nr);
+            put32(s->p + 4, ng);
+            put32(s->p + 8, (uint32_t)roff);
+            put32(s->p + 12, 0);
+            for (uint32_t j = 0; j < nr; j++) put32(s->p + roff + 4 * (uint64_t)j, len[j]);
+            s->n = roff + 4 * (uint64_t)nr;
+        }
+    }
+    free(st);
+    free(sd);
+    free(len);
+}
+
+static int dec_dstride(const uint8_t *s, uint64_t comp_len, uint32_t dtype, uint32_t n, uint8_t *dst) {
+    uint32_t bits = int_bits(dtype);
+    uint64_t mask = mask_bits(bits);
+    if (comp_len < 16) return ZFO_ECORRUPT;
+    uint32_t nr = get32(s), ng = get32(s + 4), roff = get32(s + 8);
+    if (ng != (nr + RLE_GROUP - 1) / RLE_GROUP) return ZFO_ECORRUPT;
+    if (16 + (uint64_t)32 * ng > comp_len) return ZFO_ECORRUPT;
+    if (roff % 4 != 0 || roff < 16 + (uint64_t)32 * ng) return ZFO_ECORRUPT;
+    if ((uint64_t)roff + 4 * (uint64_t)nr > comp_len) return ZFO_ECORRUPT;
+    uint64_t produced = 0;
+    for (uint32_t g = 0; g < ng; g++) {
+        const uint8_t *rec = s + 16 + (uint64_t)32 * g;
+        uint32_t out_off = get32(rec), poff = get32(rec + 4), widths = get32(rec + 8);
+        uint32_t wg = widths & 0xFFu, wd = (widths >> 8) & 0xFFu;
+        uint64_t base = get64(rec + 16), dmin = get64(rec + 24);
+        uint32_t r0 = g * RLE_GROUP, cnt = nr - r0 < RLE_GROUP ? nr - r0 : RLE_GROUP;
+        if (wg > bits || wd > bits || (widths >> 16) != 0 || poff % 8 != 0) return ZFO_ECORRUPT;
+        uint64_t gw = packed_words(cnt - 1, wg), dw = packed_words(cnt, wd);
+        if ((uint64_t)poff + 8 + 4 * (gw + dw) > comp_len) return ZFO_ECORRUPT;
+        if (out_off != produced) return ZFO_ECORRUPT;
+        uint64_t gmin = get64(s + poff);
+        uint64_t start = base & mask, prev_d = 0;
+        uint32_t prev_r = 0;
+        for (uint32_t j = 0; j < cnt; j++) {
+            uint64_t d = (dmin + unpack_bits(s + poff + 8 + 4 * gw, j, wd)) & mask;
+            if (j > 0)
+                start = (start + prev_d * (uint64_t)prev_r + gmin +
+                         unpack_bits(s + poff + 8, j - 1, wg)) & mask;
+            uint32_t r = get32(s + roff + 4 * (uint64_t)(r0 + j));
+            if (r == 0 || produced + r > n) return ZFO_ECORRUPT;
+            for (uint32_t t = 0; t < r; t++)
+                store_int(dst, dtype, produced + t, (start + d * (uint64_t)t) & mask);
+            produced += r;
+            prev_d = d;
+            prev_r = r;
+        }
+    }
+    if (produced != n) return ZFO_ECORRUPT;
+    return ZFO_OK;
+}
+
 /* ================================================================= LZ77
  * LZ77 family (Sec. 2.1): repeated byte sequences become pointers to earlier
  * output.  A chunk holds at most 65536 plain bytes and decodes on its own
@@ -830,6 +994,7 @@ static int codec_allows(uint32_t codec, uint32_t dtype) {
     case ZFO_LZ77: return zfo_elem_size(dtype) != 0;
     case ZFO_F2I_BP: return dtype == ZFO_F64;
     case ZFO_ANS: return zfo_elem_size(dtype) != 0;
+    case ZFO_DSTRIDE_BP: return dtype == ZFO_I32 || dtype == ZFO_I64;
     default: return 0;
     }
 }
@@ -855,6 +1020,8 @@ int zfo_decode_stream(uint32_t codec, uint32_t dtype, const uint8_t *s, uint64_t
         return dec_f2i_bp(s, comp_len, n, dst);
     case ZFO_ANS:
         return dec_ans(s, comp_len, (uint32_t)plain, dst);
+    case ZFO_DSTRIDE_BP:
+        return dec_dstride(s, comp_len, dtype, n, dst);
     case ZFO_FOR_BP:
     case ZFO_DICT_BP: {
         uint64_t *tmp = (uint64_t *)malloc(sizeof(uint64_t) * n);
@@ -940,6 +1107,7 @@ int zfo_encode(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t code
         case ZFO_LZ77: enc_lz77(&s, x, n * es); break;
         case ZFO_F2I_BP: enc_f2i_bp(&s, x, n); break;
         case ZFO_ANS: enc_ans(&s, x, n * es); break;
+        case ZFO_DSTRIDE_BP: enc_dstride(&s, x, dtype, n); break;
         }
         if (s.bad || s.n > 0xFFFFFFFFu) { free(s.p); b.bad = 1; break; }
         buf_resize(&b, pos + s.n);

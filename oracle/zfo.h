@@ -37,6 +37,7 @@ extern "C" {
 #define ZFO_LZ77 6
 #define ZFO_F2I_BP 7
 #define ZFO_ANS 8
+#define ZFO_DSTRIDE_BP 9
 
 /* status */
 #define ZFO_OK 0
