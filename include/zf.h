@@ -96,6 +96,16 @@ typedef enum {
  *                   u32 nw, u32 0, u32 0}, u16 f[256], u32 final state[64],
  *                   u32 word offset[64], then nw u16 words, each coder's in
  *                   decode order.  Any dtype (decoded as bytes).
+ *  ZF_DSTRIDE_BP    [GP] DeltaStride (Sec. 5): runs that are arithmetic
+ *                   progressions (start, stride, count), maximal from the
+ *                   left; groups of 64 runs, each with a 32-byte record
+ *                   {u32 out_off, u32 poff, u32 widths (gap width bits 0-7,
+ *                   stride width bits 8-15), u32 0, i64 base (first start),
+ *                   i64 dmin}; at poff (8-aligned) an i64 gmin, the cnt-1
+ *                   gap fields, then from the next u32 word the cnt stride
+ *                   fields, FOR-bit-packed.  Start j >= 1 = start j-1 +
+ *                   stride j-1 * count j-1 + gap j.  Header and u32 run
+ *                   lengths as ZF_RLE_DELTA_BP.  I32, I64.
  */
 typedef enum {
     ZF_AUTO = 0,
@@ -106,7 +116,8 @@ typedef enum {
     ZF_RLE_DELTA_BP = 5,
     ZF_LZ77 = 6,
     ZF_F2I_BP = 7,
-    ZF_ANS = 8
+    ZF_ANS = 8,
+    ZF_DSTRIDE_BP = 9
 } zf_codec;
 
 typedef void *zf_stream_t;              /* a hipStream_t */
@@ -171,8 +182,8 @@ void zf_column_free(zf_column_t *col);
 typedef enum {
     ZF_KIND_LZ77 = 0,
     ZF_KIND_ANS,     /* range ANS, one chunk per wavefront */
-    ZF_KIND_RLE64,   /* RLE_DELTA_BP and DELTA_BP, int64 */
-    ZF_KIND_RLE32,   /* RLE_DELTA_BP and DELTA_BP, int32 */
+    ZF_KIND_RLE64,   /* RLE_DELTA_BP, DELTA_BP and DSTRIDE_BP, int64 */
+    ZF_KIND_RLE32,   /* RLE_DELTA_BP, DELTA_BP and DSTRIDE_BP, int32 */
     ZF_KIND_DICT128,
     ZF_KIND_DICT64,
     ZF_KIND_DICT32,

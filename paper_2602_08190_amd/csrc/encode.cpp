@@ -477,6 +477,83 @@ static void enc_rle(std::vector<uint8_t> &s, const T *x, uint32_t n, bool unit_r
         for (uint32_t j = 0; j < nr; j++) wr32(p + roff + 4ull * j, len[j]);
 }
 
+// ------------------------------------------------------------ DeltaStride
+// Runs that are arithmetic progressions, maximal from the left (a run of one
+// element only at the end); groups of 64 runs with their own output offset
+// and first start; each later start is coded as its gap to the value the
+// previous run would produce next; gaps and strides FOR-bit-packed.
+template <class T>
+static void enc_dstride(std::vector<uint8_t> &s, const T *x, uint32_t n) {
+    using U = std::make_unsigned_t<T>;
+    std::vector<U> st, sd;
+    std::vector<uint32_t> len;
+    for (uint32_t i = 0; i < n;) {
+        U d = 0;
+        uint32_t r = 1;
+        if (i + 1 < n) {
+            d = U(U(x[i + 1]) - U(x[i]));
+            r = 2;
+            while (i + r < n && U(U(x[i + r]) - U(x[i + r - 1])) == d) r++;
+        }
+        st.push_back(U(x[i]));
+        sd.push_back(d);
+        len.push_back(r);
+        i += r;
+    }
+    const uint32_t nr = uint32_t(st.size()), ng = (nr + kRleGroup - 1) / kRleGroup;
+    struct Grp { uint32_t out_off, poff, wg, wd; T gmin, dmin; };
+    std::vector<Grp> G(ng);
+    std::vector<U> gap(nr, 0);
+    uint64_t pos = 16 + 32ull * ng;
+    uint32_t produced = 0;
+    for (uint32_t g = 0; g < ng; g++) {
+        const uint32_t r0 = g * kRleGroup, cnt = std::min(kRleGroup, nr - r0);
+        T gmin = 0, dmin = T(sd[r0]);
+        for (uint32_t j = 1; j < cnt; j++) {
+            gap[r0 + j] = U(st[r0 + j] - U(st[r0 + j - 1] + U(sd[r0 + j - 1] * U(len[r0 + j - 1]))));
+            if (j == 1 || T(gap[r0 + j]) < gmin) gmin = T(gap[r0 + j]);
+        }
+        for (uint32_t j = 1; j < cnt; j++) dmin = std::min(dmin, T(sd[r0 + j]));
+        U gmax = 0, dmax = 0;
+        for (uint32_t j = 1; j < cnt; j++) gmax = std::max(gmax, U(gap[r0 + j] - U(gmin)));
+        for (uint32_t j = 0; j < cnt; j++) dmax = std::max(dmax, U(sd[r0 + j] - U(dmin)));
+        Grp &q = G[g];
+        q.wg = bit_width64(uint64_t(gmax));
+        q.wd = bit_width64(uint64_t(dmax));
+        q.gmin = gmin;
+        q.dmin = dmin;
+        pos = align_up(pos, 8);
+        q.poff = uint32_t(pos);
+        q.out_off = produced;
+        pos += 8 + 4 * ((uint64_t(cnt - 1) * q.wg + 31) / 32 + (uint64_t(cnt) * q.wd + 31) / 32);
+        for (uint32_t j = 0; j < cnt; j++) produced += len[r0 + j];
+    }
+    const uint64_t roff = align_up(pos, 16);
+    s.assign(roff + 4ull * nr, 0);
+    uint8_t *p = s.data();
+    wr32(p, nr);
+    wr32(p + 4, ng);
+    wr32(p + 8, uint32_t(roff));
+    for (uint32_t g = 0; g < ng; g++) {
+        const uint32_t r0 = g * kRleGroup, cnt = std::min(kRleGroup, nr - r0);
+        const Grp &q = G[g];
+        uint8_t *rec = p + 16 + 32ull * g;
+        wr32(rec, q.out_off);
+        wr32(rec + 4, q.poff);
+        wr32(rec + 8, q.wg | (q.wd << 8));
+        wr64(rec + 16, uint64_t(int64_t(T(st[r0]))));
+        wr64(rec + 24, uint64_t(int64_t(q.dmin)));
+        wr64(p + q.poff, uint64_t(int64_t(q.gmin)));
+        BitPacker bg(p + q.poff + 8);
+        for (uint32_t j = 1; j < cnt; j++) bg.put(uint64_t(U(gap[r0 + j] - U(q.gmin))), q.wg);
+        bg.flush();
+        BitPacker bd(p + q.poff + 8 + 4 * ((uint64_t(cnt - 1) * q.wg + 31) / 32));
+        for (uint32_t j = 0; j < cnt; j++) bd.put(uint64_t(U(sd[r0 + j] - U(q.dmin))), q.wd);
+        bd.flush();
+    }
+    for (uint32_t j = 0; j < nr; j++) wr32(p + roff + 4ull * j, len[j]);
+}
+
 // ------------------------------------------------------------------ LZ77
 // Greedy LZ77 over a chunk of <= 64 KiB: hash chains of 4-byte prefixes
 // (depth 16), longest match, nearest source on ties.
@@ -625,6 +702,10 @@ static void encode_chunk(std::vector<uint8_t> &out, uint32_t codec, uint32_t dty
     case C_LZ77: enc_lz77(out, x, n * es, sc); return;
     case C_F2I_BP: enc_f2i(out, x, n); return;
     case C_ANS: enc_ans(out, x, n * es); return;
+    case C_DSTRIDE_BP:
+        if (dtype == D_I32) enc_dstride<int32_t>(out, reinterpret_cast<const int32_t *>(x), n);
+        else enc_dstride<int64_t>(out, reinterpret_cast<const int64_t *>(x), n);
+        return;
     }
     fail(ZF_E_INVALID, "unknown codec %u", codec);
 }
@@ -769,7 +850,8 @@ void compress_host(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t 
             encode_chunk(out.bytes, cc[i], dtype, x, ce[i], &dict, *sc);
         } else {
             // smallest stream among the applicable codecs
-            const uint32_t cands[] = {C_FOR_BP, C_DICT_BP, C_DELTA_BP, C_RLE_DELTA_BP, C_LZ77, C_F2I_BP, C_ANS};
+            const uint32_t cands[] = {C_FOR_BP, C_DICT_BP, C_DELTA_BP, C_RLE_DELTA_BP, C_LZ77, C_F2I_BP, C_ANS,
+                                      C_DSTRIDE_BP};
             encode_chunk(out.bytes, C_PLAIN, dtype, x, ce[i], nullptr, *sc);
             out.codec = C_PLAIN;
             std::vector<uint8_t> tmp;

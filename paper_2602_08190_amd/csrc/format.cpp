@@ -39,7 +39,8 @@ bool codec_allows(uint32_t codec, uint32_t dtype) {
     case C_LZ77: return true;
     case C_FOR_BP:
     case C_DELTA_BP:
-    case C_RLE_DELTA_BP: return dtype == D_I32 || dtype == D_I64;
+    case C_RLE_DELTA_BP:
+    case C_DSTRIDE_BP: return dtype == D_I32 || dtype == D_I64;
     case C_DICT_BP: return dtype != D_BYTES && dtype != D_F64;
     case C_F2I_BP: return dtype == D_F64;
     case C_ANS: return true;
@@ -53,7 +54,8 @@ Kind kind_of(uint32_t codec, uint32_t dtype) {
     case C_FOR_BP: return dtype == D_I32 ? K_FOR32 : K_FOR64;
     case C_DICT_BP: return dtype == D_I32 ? K_DICT32 : dtype == D_I64 ? K_DICT64 : K_DICT128;
     case C_DELTA_BP:
-    case C_RLE_DELTA_BP: return dtype == D_I32 ? K_RLE32 : K_RLE64;
+    case C_RLE_DELTA_BP:
+    case C_DSTRIDE_BP: return dtype == D_I32 ? K_RLE32 : K_RLE64;
     case C_LZ77: return K_LZ;
     case C_F2I_BP: return K_F2I;
     case C_ANS: return K_ANS;
@@ -212,6 +214,29 @@ void check_stream(const ColumnView &v, const uint8_t *blob, uint32_t i) {
             uint32_t off = rd32(r), w = rd32(r + 4), doff = rd32(r + 8);
             uint32_t cnt = std::min<uint32_t>(kRleGroup, nr - g * kRleGroup);
             ZF_REQUIRE(w <= bits && doff % 4 == 0 && doff + 4 * words_for(cnt - 1, w) <= L,
+                       ZF_E_CORRUPT, "chunk %u group %u: bad record", i, g);
+            ZF_REQUIRE(g == 0 ? off == 0 : (off > prev && off < n), ZF_E_CORRUPT,
+                       "chunk %u group %u: output offset out of order", i, g);
+            prev = off;
+        }
+        return;
+    }
+    case C_DSTRIDE_BP: {
+        const uint32_t bits = v.dtype == D_I32 ? 32 : 64;
+        ZF_REQUIRE(L >= 16, ZF_E_CORRUPT, "chunk %u: short DeltaStride header", i);
+        uint32_t nr = rd32(s), ng = rd32(s + 4), roff = rd32(s + 8);
+        ZF_REQUIRE(ng == (uint64_t(nr) + kRleGroup - 1) / kRleGroup && 16 + 32ull * ng <= L,
+                   ZF_E_CORRUPT, "chunk %u: bad group count", i);
+        ZF_REQUIRE(nr >= 1 && roff % 4 == 0 && roff >= 16 + 32ull * ng && roff + 4ull * nr <= L,
+                   ZF_E_CORRUPT, "chunk %u: run array out of range", i);
+        uint64_t prev = 0;
+        for (uint32_t g = 0; g < ng; g++) {
+            const uint8_t *r = s + 16 + 32ull * g;
+            const uint32_t off = rd32(r), poff = rd32(r + 4), widths = rd32(r + 8);
+            const uint32_t wg = widths & 0xFFu, wd = (widths >> 8) & 0xFFu;
+            const uint32_t cnt = std::min<uint32_t>(kRleGroup, nr - g * kRleGroup);
+            ZF_REQUIRE(wg <= bits && wd <= bits && (widths >> 16) == 0 && poff % 8 == 0 &&
+                           poff + 8 + 4 * (words_for(cnt - 1, wg) + words_for(cnt, wd)) <= L,
                        ZF_E_CORRUPT, "chunk %u group %u: bad record", i, g);
             ZF_REQUIRE(g == 0 ? off == 0 : (off > prev && off < n), ZF_E_CORRUPT,
                        "chunk %u group %u: output offset out of order", i, g);

@@ -575,14 +575,34 @@ ZF_DEV void unit_f2i(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck) {
 // start, a wave scan carries the latest index over the window, and each lane
 // takes its values with cross-lane permutes — no per-run loop.  slot: this
 // wave's 256 dwords.
+// One group's record and this lane's run length and packed words.  For
+// DeltaStride, w/doff/w0..w2 are the gap field's and wd/dw0..dw2 the stride
+// field's.
 template <class T>
 struct RleGroup {
     uint32_t goff, w, doff, next_off, r, w0, w1, w2;
-    T base, dmin;
+    uint32_t wd, dw0, dw1, dw2;
+    T base, dmin, gmin;
     bool ok;
 };
 
-template <class T>
+// Field of width w at bit `bit` of a packed stream, from the three words
+// starting at word bit / 32.
+template <class U>
+ZF_DEV U field_of(uint32_t w0, uint32_t w1, uint32_t w2, uint64_t bit, uint32_t w) {
+    const uint32_t sh = uint32_t(bit & 31u);
+    if constexpr (sizeof(U) == 4) {
+        return uint32_t((uint64_t(w0) | (uint64_t(w1) << 32)) >> sh) & mask32(w);
+    } else {
+        const uint64_t lo = uint64_t(w0) | (uint64_t(w1) << 32);
+        return (sh ? ((lo >> sh) | (uint64_t(w2) << (64 - sh))) : lo) & mask64(w);
+    }
+}
+
+// Group-Parallel decode of RLE_DELTA_BP / DELTA_BP (DS = false) and
+// DSTRIDE_BP (DS = true) chunks: one wave expands the groups that meet its
+// tile's element range [t.b, t.c), starting with group t.a.
+template <class T, bool DS>
 ZF_DEV void unit_rle(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, uint32_t *slot) {
     using U = T;  // unsigned value type: uint32_t or uint64_t
     constexpr uint32_t BITS = sizeof(T) * 8;
@@ -609,24 +629,46 @@ ZF_DEV void unit_rle(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, ui
     auto load = [&](uint32_t g, RleGroup<U> &G) {
         const uint8_t *rec = s + 16 + 32ull * g;
         G.goff = ld32u(rec);
-        G.w = ld32u(rec + 4);
-        G.doff = ld32u(rec + 8);
         G.base = U(ld64u(rec + 16));
         G.dmin = U(ld64u(rec + 24));
         G.next_off = (g + 1 < ng) ? ld32u(rec + 32) : n;
         const uint32_t cnt = min(kRleGroup, nr - g * kRleGroup);
-        const uint64_t nwords = (uint64_t(cnt - 1) * min(G.w, 64u) + 31) / 32;
-        G.ok = G.w <= BITS && (G.doff & 3u) == 0 && G.doff + 4 * nwords <= clen && G.next_off <= n;
+        uint64_t nwords, dwords = 0;
+        if constexpr (DS) {
+            const uint32_t poff = ld32u(rec + 4), widths = ld32u(rec + 8);
+            G.w = widths & 0xFFu;
+            G.wd = (widths >> 8) & 0xFFu;
+            G.doff = poff + 8;
+            nwords = (uint64_t(cnt - 1) * min(G.w, 64u) + 31) / 32;
+            dwords = (uint64_t(cnt) * min(G.wd, 64u) + 31) / 32;
+            G.ok = G.w <= BITS && G.wd <= BITS && (widths >> 16) == 0 && (poff & 7u) == 0 &&
+                   poff + 8 + 4 * (nwords + dwords) <= clen && G.next_off <= n;
+            G.gmin = G.ok ? U(ld64u(s + poff)) : U(0);
+        } else {
+            G.w = ld32u(rec + 4);
+            G.doff = ld32u(rec + 8);
+            nwords = (uint64_t(cnt - 1) * min(G.w, 64u) + 31) / 32;
+            G.ok = G.w <= BITS && (G.doff & 3u) == 0 && G.doff + 4 * nwords <= clen && G.next_off <= n;
+        }
         const bool act = lane < cnt;
         G.r = act ? (unit_runs ? 1u : runs[uint64_t(g) * kRleGroup + lane]) : 0u;
         G.w0 = G.w1 = G.w2 = 0;
+        const uint32_t *words = reinterpret_cast<const uint32_t *>(s + G.doff);
         if (G.ok && lane >= 1 && act) {
-            const uint64_t bit = uint64_t(lane - 1) * G.w;
-            const uint32_t *words = reinterpret_cast<const uint32_t *>(s + G.doff);
-            const uint64_t k = bit >> 5;
+            const uint64_t k = (uint64_t(lane - 1) * G.w) >> 5;
             G.w0 = k < nwords ? words[k] : 0u;
             G.w1 = k + 1 < nwords ? words[k + 1] : 0u;
             if constexpr (BITS == 64) G.w2 = k + 2 < nwords ? words[k + 2] : 0u;
+        }
+        if constexpr (DS) {
+            G.dw0 = G.dw1 = G.dw2 = 0;
+            if (G.ok && act) {
+                const uint32_t *dw = words + nwords;
+                const uint64_t k = (uint64_t(lane) * G.wd) >> 5;
+                G.dw0 = k < dwords ? dw[k] : 0u;
+                G.dw1 = k + 1 < dwords ? dw[k + 1] : 0u;
+                if constexpr (BITS == 64) G.dw2 = k + 2 < dwords ? dw[k + 2] : 0u;
+            }
         }
     };
     RleGroup<U> cur, nxt;
@@ -656,20 +698,37 @@ ZF_DEV void unit_rle(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, ui
         }
         const uint32_t end_abs = cur.goff + uint32_t(incl);  // end of run `lane`
         const uint32_t start_abs = end_abs - r;
-        // run values: base, then base + prefix sums of (dmin + field)
-        U delta = cur.base;
-        if (lane >= 1 && act) {
-            const uint32_t sh = uint32_t((uint64_t(lane - 1) * cur.w) & 31u);
-            U f;
+        // RLE: run values are base, then base + prefix sums of (dmin + field).
+        // DeltaStride: run j writes c_j + d_j * p at element p, with stride
+        // d_j = dmin + field, start s_j = base + prefix sums of
+        // (d_{j-1} r_{j-1} + gmin + gap field) and c_j = s_j - d_j * start_j.
+        U v, dstr = 0;
+        if constexpr (DS) {
+            dstr = act ? U(cur.dmin + field_of<U>(cur.dw0, cur.dw1, cur.dw2, uint64_t(lane) * cur.wd, cur.wd))
+                       : U(0);
+            // stride and count of the run before (lane - 1)
+            const int src = int((lane - 1) * 4);
+            const uint32_t rp = uint32_t(__builtin_amdgcn_ds_bpermute(src, int(r)));
+            U dp;
             if constexpr (BITS == 32) {
-                f = uint32_t((uint64_t(cur.w0) | (uint64_t(cur.w1) << 32)) >> sh) & mask32(cur.w);
+                dp = uint32_t(__builtin_amdgcn_ds_bpermute(src, int(dstr)));
             } else {
-                const uint64_t lo = uint64_t(cur.w0) | (uint64_t(cur.w1) << 32);
-                f = (sh ? ((lo >> sh) | (uint64_t(cur.w2) << (64 - sh))) : lo) & mask64(cur.w);
+                const uint32_t lo = uint32_t(__builtin_amdgcn_ds_bpermute(src, int(uint32_t(dstr))));
+                const uint32_t hi = uint32_t(__builtin_amdgcn_ds_bpermute(src, int(uint32_t(dstr >> 32))));
+                dp = uint64_t(lo) | (uint64_t(hi) << 32);
             }
-            delta = U(cur.dmin + f);
+            U e = cur.base;
+            if (lane >= 1)
+                e = U(dp * U(rp) + cur.gmin +
+                      field_of<U>(cur.w0, cur.w1, cur.w2, uint64_t(lane - 1) * cur.w, cur.w));
+            const U st = scan_addT<U>(act ? e : U(0));
+            v = U(st - dstr * U(start_abs));
+        } else {
+            U delta = cur.base;
+            if (lane >= 1 && act)
+                delta = U(cur.dmin + field_of<U>(cur.w0, cur.w1, cur.w2, uint64_t(lane - 1) * cur.w, cur.w));
+            v = scan_addT<U>(act ? delta : U(0));
         }
-        const U v = scan_addT<U>(act ? delta : U(0));
         // expand the part of this group inside [e0, e1), R outputs per lane
         // per window (16 bytes: one aligned store when whole)
         constexpr uint32_t R = 16 / sizeof(U), SPAN = 64 * R;
@@ -707,6 +766,19 @@ ZF_DEV void unit_rle(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, ui
                         const uint32_t lo = uint32_t(__builtin_amdgcn_ds_bpermute(src, int(uint32_t(v))));
                         const uint32_t hi = uint32_t(__builtin_amdgcn_ds_bpermute(src, int(uint32_t(v >> 32))));
                         val[i] = uint64_t(lo) | (uint64_t(hi) << 32);
+                    }
+                    if constexpr (DS) {
+                        // plus stride * element index
+                        U dd;
+                        if constexpr (BITS == 32) {
+                            dd = uint32_t(__builtin_amdgcn_ds_bpermute(src, int(dstr)));
+                        } else {
+                            const uint32_t lo = uint32_t(__builtin_amdgcn_ds_bpermute(src, int(uint32_t(dstr))));
+                            const uint32_t hi =
+                                uint32_t(__builtin_amdgcn_ds_bpermute(src, int(uint32_t(dstr >> 32))));
+                            dd = uint64_t(lo) | (uint64_t(hi) << 32);
+                        }
+                        val[i] = U(val[i] + dd * U(uint32_t(W0 + int32_t(R * lane + i))));
                     }
                 }
                 const int32_t p = W0 + int32_t(R * lane);
@@ -1138,8 +1210,14 @@ ZF_DEV void run_unit(const LaunchArgs &A, uint32_t kind, uint32_t u, uint32_t *l
     case K_DICT32: unit_fp<4, true, UNR>(A, t, ck); break;
     case K_DICT64: unit_fp<8, true, UNR>(A, t, ck); break;
     case K_DICT128: unit_fp<16, true, UNR>(A, t, ck); break;
-    case K_RLE32: unit_rle<uint32_t>(A, t, ck, lz_row); break;
-    case K_RLE64: unit_rle<uint64_t>(A, t, ck, lz_row); break;
+    case K_RLE32:
+        if (ck.codec == C_DSTRIDE_BP) unit_rle<uint32_t, true>(A, t, ck, lz_row);
+        else unit_rle<uint32_t, false>(A, t, ck, lz_row);
+        break;
+    case K_RLE64:
+        if (ck.codec == C_DSTRIDE_BP) unit_rle<uint64_t, true>(A, t, ck, lz_row);
+        else unit_rle<uint64_t, false>(A, t, ck, lz_row);
+        break;
     case K_LZ: unit_lz<16>(A, ck, lz_row); break;
     case K_ANS: unit_ans(A, ck, lz_row); break;
     }
@@ -1170,10 +1248,12 @@ __global__ __launch_bounds__(1024) void k_decode_kind(LaunchArgs A) {
         unit_fp<16, true, 8>(A, t, ck);
     } else if constexpr (KIND == K_RLE32) {
         __shared__ uint32_t rle_slots[16][256];
-        unit_rle<uint32_t>(A, t, ck, rle_slots[threadIdx.x / 64]);
+        if (ck.codec == C_DSTRIDE_BP) unit_rle<uint32_t, true>(A, t, ck, rle_slots[threadIdx.x / 64]);
+        else unit_rle<uint32_t, false>(A, t, ck, rle_slots[threadIdx.x / 64]);
     } else if constexpr (KIND == K_RLE64) {
         __shared__ uint32_t rle_slots[16][256];
-        unit_rle<uint64_t>(A, t, ck, rle_slots[threadIdx.x / 64]);
+        if (ck.codec == C_DSTRIDE_BP) unit_rle<uint64_t, true>(A, t, ck, rle_slots[threadIdx.x / 64]);
+        else unit_rle<uint64_t, false>(A, t, ck, rle_slots[threadIdx.x / 64]);
     }
 }
 

@@ -268,3 +268,17 @@ def returnflag_column(n, p_a, p_n, seed):
     out[u < p_a + p_n] = ord("N")
     out[u < p_a] = ord("A")
     return out
+
+
+def key_column(n, seed, mean_run=8, max_jump=64, dtype=np.int32, start=1):
+    """Nearly increasing primary keys: blocks of consecutive keys with
+    geometric lengths (mean `mean_run`), each block starting a uniform
+    1..max_jump past the end of the previous one."""
+    g = rng(seed)
+    r = run_lengths_geometric(n, mean_run, seed)
+    jumps = g.integers(1, max_jump + 1, size=r.size).astype(np.int64)
+    jumps[0] = 0
+    block_start = start + np.cumsum(np.concatenate([[0], r[:-1]])) + np.cumsum(jumps)
+    first = np.repeat(block_start, r)
+    within = np.arange(n, dtype=np.int64) - np.repeat(np.cumsum(r) - r, r)
+    return (first + within).astype(dtype)

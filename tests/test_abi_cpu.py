@@ -1,6 +1,7 @@
 """Host side of the product, no GPU: the library loads and exports every
 symbol zf.h declares; the product encoder writes the oracle's canonical
-streams byte for byte (FOR_BP, DICT_BP, DELTA_BP, RLE_DELTA_BP, PLAIN); its
+streams byte for byte (FOR_BP, DICT_BP, DELTA_BP, RLE_DELTA_BP, DSTRIDE_BP,
+F2I_BP, ANS, PLAIN); its
 LZ77 streams decode to the input under the oracle; host validation rejects
 corrupt columns."""
 import ctypes
@@ -110,6 +111,38 @@ def test_ans_host_validation():
     t[c["comp_off"] + 784 + 4 * 7 + 3] = 0x7F  # a word offset past the words
     with pytest.raises(zf.ZfError):
         zf.Column.from_bytes(t, pinned=False)
+
+
+def test_encoder_byte_identical_dstride():
+    """DeltaStride: nearly increasing keys, evenly spaced key blocks, random
+    values, extremes, progressions across the wrap, uneven and tiny chunks."""
+    r = g.rng(29)
+    cases = []
+    for dt in (np.int32, np.int64):
+        info = np.iinfo(dt)
+        cases += [(g.key_column(30000, 5, dtype=dt), [1, 64, 4096, 30000 - 4161]),
+                  ((np.arange(9000) // 8 * 32 + np.arange(9000) % 8 + 1).astype(dt), [9000]),
+                  (r.integers(info.min, info.max, size=5000, dtype=dt, endpoint=True), [2500, 2500]),
+                  (np.array([info.min, info.max, 0, -1, info.min, info.min, 5] * 300, dt), [2100]),
+                  ((np.arange(7000, dtype=np.int64) * 977 + int(info.max) - 3000).astype(
+                      np.uint64 if dt == np.int64 else np.int64).astype(dt), [3000, 4000])]
+    for x, ce in cases:
+        ours, ref = same_streams(x, zf.DSTRIDE_BP, ce)
+        assert ours.tobytes() == ref.tobytes(), (x.dtype, ce)
+        assert np.array_equal(zo.decode(ours), x)
+
+
+def test_dstride_host_validation():
+    x = g.key_column(5000, 6)
+    b = zo.encode(x, zo.DSTRIDE_BP).copy()
+    c = zo.chunks(b)[0]
+    for off, val in ((16 + 8, 33),            # gap width above 32
+                     (16 + 4, 20),            # payload offset not 8-aligned
+                     (16 + 32, 0)):           # second group's output offset 0
+        t = b.copy()
+        t[c["comp_off"] + off:c["comp_off"] + off + 4] = np.frombuffer(np.uint32(val).tobytes(), np.uint8)
+        with pytest.raises(zf.ZfError):
+            zf.Column.from_bytes(t, pinned=False)
 
 
 def test_encoder_byte_identical_fixed16_and_mixed():

@@ -146,6 +146,42 @@ def test_rle_families_and_tiles(gp_elems):
     check(cols, decode_image(cols, persistent=True, tiles={"GP": dict(unit=gp_elems, waves_per_block=8)}), xs)
 
 
+@pytest.mark.parametrize("gp_elems", [64, 100, 4096])
+def test_dstride_keys_random_extremes_and_tiles(gp_elems):
+    """DeltaStride: nearly increasing keys (int32, int64), evenly spaced key
+    blocks, random values (runs of two), extremes, progressions across the
+    wrap; every tile shape, per-kind and persistent launches."""
+    log("dstride", gp_elems)
+    r = g.rng(31)
+    xs, cols = [], []
+    for dt in (np.int32, np.int64):
+        info = np.iinfo(dt)
+        xs += [g.key_column(70000, 8, dtype=dt),
+               (np.arange(20000) // 8 * 32 + np.arange(20000) % 8 + 1).astype(dt),
+               r.integers(info.min, info.max, size=9000, dtype=dt, endpoint=True),
+               np.array([info.min, info.max, 0, -1, info.min, info.min, 5] * 500, dt),
+               (np.arange(30000, dtype=np.int64) * 977 + int(info.max) - 3000).astype(
+                   np.uint64 if dt == np.int64 else np.int64).astype(dt)]
+    for x in xs:
+        n = len(x)
+        ce = [1, 4095, 16384, n - 20480] if n > 20480 else [1, n // 3, n - 1 - n // 3]
+        cols.append(zf.Column.compress(x, zf.DSTRIDE_BP, chunk_elems=ce))
+    check(cols, decode_image(cols, tiles={"GP": dict(unit=gp_elems)}), xs)
+    check(cols, decode_image(cols, persistent=True, tiles={"GP": dict(unit=gp_elems, waves_per_block=8)}), xs)
+
+
+def test_dstride_oracle_streams_and_auto():
+    """Streams written by the oracle decode the same; ZF_AUTO keeps
+    DeltaStride for evenly spaced keys (its stream is the smallest)."""
+    log("dstride oracle/auto")
+    x = g.key_column(50000, 9)
+    col = zf.Column.from_bytes(zo.encode(x, zo.DSTRIDE_BP, [20000, 30000]))
+    y = (np.arange(200000) // 8 * 32 + np.arange(200000) % 8 + 1).astype(np.int32)
+    auto = zf.Column.compress(y, zf.AUTO)
+    assert set(c["codec"] for c in zo.chunks(auto.bytes())) == {zf.DSTRIDE_BP}
+    check([col, auto], decode_image([col, auto]), [x, y])
+
+
 def test_rle_and_delta_extremes():
     log("rle extremes")
     xs, cols = [], []
@@ -433,6 +469,15 @@ def test_device_detects_corrupt_streams():
     at = c["comp_off"] + roff
     b[at:at + 4] = np.frombuffer(np.uint32(1000).tobytes(), np.uint8)
     _expect_corrupt([zf.Column.from_bytes(b)])
+    # DeltaStride: a zero count; counts that do not add up to the chunk
+    x = g.key_column(5000, 2)
+    for val in (0, 1000):
+        b = zo.encode(x, zo.DSTRIDE_BP).copy()
+        c = zo.chunks(b)[0]
+        roff = int(np.frombuffer(b[c["comp_off"] + 8:c["comp_off"] + 12].tobytes(), np.uint32)[0])
+        at = c["comp_off"] + roff + 4 * 70
+        b[at:at + 4] = np.frombuffer(np.uint32(val).tobytes(), np.uint8)
+        _expect_corrupt([zf.Column.from_bytes(b)])
     # F2I: exception records out of order (the host does not read them)
     x = np.array([0.5, -0.0, np.nan, 1.5] * 3, dtype=np.float64)
     b = zo.encode(x, zo.F2I_BP).copy()
