@@ -847,6 +847,144 @@ static int dec_dstride(const uint8_t *s, uint64_t comp_len, uint32_t dtype, uint
     return ZFO_OK;
 }
 
+/* ======================================================= String-dictionary
+ * String-dictionary (Sec. 2.1; Sec. 5: the text is cut into words at spaces
+ * and periods, each distinct word is a dictionary entry, the word indices are
+ * bit-packed, and each word decodes as one group of the Group-Parallel
+ * pattern).  Tokens: every byte belongs to exactly one token; a token is a
+ * run of bytes other than ' ' and '.' followed by one ' ' or '.', or the
+ * chunk's final bytes when they end without one; a run longer than
+ * SD_MAX_TOKEN bytes is cut into pieces of SD_MAX_TOKEN (the piece that ends
+ * with the separator may be shorter).  Entries are the distinct tokens in
+ * order of first appearance.
+ * Stream:
+ *   header 32 bytes: u32 n_tokens, u32 n_entries, u32 w (code width =
+ *       bitlen(n_entries - 1)), u32 n_groups = ceil(n_tokens/64),
+ *       u32 ent_off, u32 bytes_off, u32 codes_off, u32 n_bytes (sum of the
+ *       entry lengths)
+ *   group offsets: u32[n_groups] at 32, the output byte offset of token 64g
+ *   entries: u32[n_entries] at ent_off = align16(32 + 4*n_groups), entry k =
+ *       byte offset of its bytes (bits 0-23) | length 1..64 (bits 24-31)
+ *   entry bytes at bytes_off = ent_off + 4*n_entries, n_bytes of them, then
+ *       zero bytes up to codes_off = align16(bytes_off + n_bytes + 4)
+ *   codes at codes_off: n_tokens fields of width w (entry index of token i)
+ *   comp_len = codes_off + 4*ceil(n_tokens*w/32).
+ * Decode: token i writes entry code_i's bytes at the group offset plus the
+ * lengths of the earlier tokens of its group. */
+#define SD_MAX_TOKEN 64u
+
+static int sd_is_sep(uint8_t c) { return c == ' ' || c == '.'; }
+
+/* length of the token starting at byte i of x[0..n) */
+static uint32_t sd_token_len(const uint8_t *x, uint32_t n, uint32_t i) {
+    uint32_t k = 0;
+    while (i + k < n && k < SD_MAX_TOKEN) {
+        k++;
+        if (sd_is_sep(x[i + k - 1])) break;
+    }
+    return k;
+}
+
+static uint64_t sd_hash(const uint8_t *p, uint32_t len) {
+    uint64_t h = 1469598103934665603ull;  /* FNV-1a */
+    for (uint32_t k = 0; k < len; k++) h = (h ^ p[k]) * 1099511628211ull;
+    return h;
+}
+
+static void enc_sdict(buf_t *s, const uint8_t *x, uint32_t n) {
+    /* tokens */
+    uint32_t nt = 0;
+    for (uint32_t i = 0; i < n; i += sd_token_len(x, n, i)) nt++;
+    uint32_t *tstart = (uint32_t *)malloc(sizeof(uint32_t) * (nt ? nt : 1));
+    uint32_t *tlen = (uint32_t *)malloc(sizeof(uint32_t) * (nt ? nt : 1));
+    uint32_t *code = (uint32_t *)malloc(sizeof(uint32_t) * (nt ? nt : 1));
+    uint32_t *efirst = (uint32_t *)malloc(sizeof(uint32_t) * (nt ? nt : 1)); /* token that defines entry k */
+    uint64_t cap = 16;
+    while (cap < 2 * (uint64_t)nt) cap *= 2;
+    int64_t *slot = (int64_t *)malloc(sizeof(int64_t) * cap);  /* entry index or -1 */
+    if (!tstart || !tlen || !code || !efirst || !slot) {
+        free(tstart); free(tlen); free(code); free(efirst); free(slot);
+        s->bad = 1;
+        return;
+    }
+    for (uint64_t k = 0; k < cap; k++) slot[k] = -1;
+    uint32_t ne = 0, nbytes = 0;
+    for (uint32_t i = 0, t = 0; i < n; t++) {
+        uint32_t L = sd_token_len(x, n, i);
+        tstart[t] = i;
+        tlen[t] = L;
+        /* find the token among the entries (open addressing) */
+        uint64_t h = sd_hash(x + i, L) & (cap - 1);
+        while (slot[h] >= 0) {
+            uint32_t f = efirst[slot[h]];
+            if (tlen[f] == L && memcmp(x + tstart[f], x + i, L) == 0) break;
+            h = (h + 1) & (cap - 1);
+        }
+        if (slot[h] < 0) {
+            slot[h] = ne;
+            efirst[ne] = t;
+            ne++;
+            nbytes += L;
+        }
+        code[t] = (uint32_t)slot[h];
+        i += L;
+    }
+    uint32_t w = ne > 1 ? bitlen64(ne - 1) : 0;
+    uint32_t ng = (nt + 63) / 64;
+    uint64_t ent_off = align16(32 + 4 * (uint64_t)ng);
+    uint64_t bytes_off = ent_off + 4 * (uint64_t)ne;
+    uint64_t codes_off = align16(bytes_off + nbytes + 4);
+    buf_resize(s, codes_off + 4 * packed_words(nt, w));
+    if (!s->bad) {
+        uint8_t *p = s->p;
+        put32(p + 0, nt);
+        put32(p + 4, ne);
+        put32(p + 8, w);
+        put32(p + 12, ng);
+        put32(p + 16, (uint32_t)ent_off);
+        put32(p + 20, (uint32_t)bytes_off);
+        put32(p + 24, (uint32_t)codes_off);
+        put32(p + 28, nbytes);
+        for (uint32_t g = 0; g < ng; g++) put32(p + 32 + 4 * (uint64_t)g, tstart[64 * g]);
+        uint32_t at = 0;
+        for (uint32_t k = 0; k < ne; k++) {
+            uint32_t f = efirst[k];
+            put32(p + ent_off + 4 * (uint64_t)k, at | (tlen[f] << 24));
+            memcpy(p + bytes_off + at, x + tstart[f], tlen[f]);
+            at += tlen[f];
+        }
+        for (uint32_t t = 0; t < nt; t++) pack_bits(p + codes_off, t, w, code[t]);
+        s->n = codes_off + 4 * packed_words(nt, w);
+    }
+    free(tstart); free(tlen); free(code); free(efirst); free(slot);
+}
+
+static int dec_sdict(const uint8_t *s, uint64_t comp_len, uint32_t plain_len, uint8_t *out) {
+    if (comp_len < 32) return ZFO_ECORRUPT;
+    uint32_t nt = get32(s), ne = get32(s + 4), w = get32(s + 8), ng = get32(s + 12);
+    uint32_t ent_off = get32(s + 16), bytes_off = get32(s + 20), codes_off = get32(s + 24);
+    uint32_t nbytes = get32(s + 28);
+    if (ng != (nt + 63) / 64 || ne == 0 || w > 32) return ZFO_ECORRUPT;
+    if (w != (ne > 1 ? bitlen64(ne - 1) : 0)) return ZFO_ECORRUPT;
+    if (ent_off != align16(32 + 4 * (uint64_t)ng) || bytes_off != ent_off + 4 * (uint64_t)ne ||
+        codes_off != align16((uint64_t)bytes_off + nbytes + 4) ||
+        (uint64_t)codes_off + 4 * packed_words(nt, w) != comp_len)
+        return ZFO_ECORRUPT;
+    uint64_t p = 0;
+    for (uint32_t t = 0; t < nt; t++) {
+        if (t % 64 == 0 && get32(s + 32 + 4 * (uint64_t)(t / 64)) != p) return ZFO_ECORRUPT;
+        uint64_t c = unpack_bits(s + codes_off, t, w);
+        if (c >= ne) return ZFO_ECORRUPT;
+        uint32_t e = get32(s + ent_off + 4 * c), off = e & 0xFFFFFFu, len = e >> 24;
+        if (len == 0 || len > SD_MAX_TOKEN || (uint64_t)off + len > nbytes) return ZFO_ECORRUPT;
+        if (p + len > plain_len) return ZFO_ECORRUPT;
+        memcpy(out + p, s + bytes_off + off, len);
+        p += len;
+    }
+    if (p != plain_len) return ZFO_ECORRUPT;
+    return ZFO_OK;
+}
+
 /* ================================================================= LZ77
  * LZ77 family (Sec. 2.1): repeated byte sequences become pointers to earlier
  * output.  A chunk holds at most 65536 plain bytes and decodes on its own
@@ -995,6 +1133,7 @@ static int codec_allows(uint32_t codec, uint32_t dtype) {
     case ZFO_F2I_BP: return dtype == ZFO_F64;
     case ZFO_ANS: return zfo_elem_size(dtype) != 0;
     case ZFO_DSTRIDE_BP: return dtype == ZFO_I32 || dtype == ZFO_I64;
+    case ZFO_SDICT_BP: return dtype == ZFO_BYTES;
     default: return 0;
     }
 }
@@ -1022,6 +1161,8 @@ int zfo_decode_stream(uint32_t codec, uint32_t dtype, const uint8_t *s, uint64_t
         return dec_ans(s, comp_len, (uint32_t)plain, dst);
     case ZFO_DSTRIDE_BP:
         return dec_dstride(s, comp_len, dtype, n, dst);
+    case ZFO_SDICT_BP:
+        return dec_sdict(s, comp_len, (uint32_t)plain, dst);
     case ZFO_FOR_BP:
     case ZFO_DICT_BP: {
         uint64_t *tmp = (uint64_t *)malloc(sizeof(uint64_t) * n);
@@ -1108,6 +1249,7 @@ int zfo_encode(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t code
         case ZFO_F2I_BP: enc_f2i_bp(&s, x, n); break;
         case ZFO_ANS: enc_ans(&s, x, n * es); break;
         case ZFO_DSTRIDE_BP: enc_dstride(&s, x, dtype, n); break;
+        case ZFO_SDICT_BP: enc_sdict(&s, x, n); break;
         }
         if (s.bad || s.n > 0xFFFFFFFFu) { free(s.p); b.bad = 1; break; }
         buf_resize(&b, pos + s.n);

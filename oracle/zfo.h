@@ -38,6 +38,7 @@ extern "C" {
 #define ZFO_F2I_BP 7
 #define ZFO_ANS 8
 #define ZFO_DSTRIDE_BP 9
+#define ZFO_SDICT_BP 10
 
 /* status */
 #define ZFO_OK 0
