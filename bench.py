@@ -89,6 +89,11 @@ def single(kind, n):
         c = zf.Column.compress(x, zf.ANS)
         desc = (f"ANS bytes, {n} flags 'A'/'N'/'R' with probabilities 0.25/0.5/0.25, 64 KiB chunks, "
                 f"64 interleaved coders per chunk")
+    elif kind == "sdict":
+        x = g.text_column(n, 2)
+        c = zf.Column.compress(x, zf.SDICT_BP)
+        desc = (f"SDICT_BP text, {n} bytes, Zipf(1.1) over 10,000 words, String-dictionary per 1 MiB "
+                f"chunk (tokens end at spaces and periods)")
     elif kind == "keys":
         x = g.key_column(n, 11)
         c = zf.Column.compress(x, zf.DSTRIDE_BP)
@@ -178,7 +183,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="fact", choices=["fact", "for", "rle", "lz", "f2i", "ans", "keys", "copy"])
+    ap.add_argument("--workload", default="fact", choices=["fact", "for", "rle", "lz", "f2i", "ans", "keys", "sdict", "copy"])
     ap.add_argument("--rows", type=int, default=None)
     ap.add_argument("--no-e2e", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -202,7 +207,8 @@ def main():
         cols, xs, names, desc = fact_table(args.rows or g.FACT_ROWS)
     else:
         n = args.rows or {"for": 1 << 28, "rle": 1 << 26, "lz": 1 << 30, "f2i": 1 << 26,
-                           "ans": 1 << 30, "keys": 1 << 26, "copy": 1 << 30}[args.workload]
+                           "ans": 1 << 30, "keys": 1 << 26, "sdict": 1 << 30,
+                           "copy": 1 << 30}[args.workload]
         cols, xs, names, desc = single(args.workload, n)
     plain = sum(c.plain_bytes for c in cols)
     comp = sum(c.host_pointer()[1] for c in cols)

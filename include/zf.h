@@ -106,6 +106,17 @@ typedef enum {
  *                   fields, FOR-bit-packed.  Start j >= 1 = start j-1 +
  *                   stride j-1 * count j-1 + gap j.  Header and u32 run
  *                   lengths as ZF_RLE_DELTA_BP.  I32, I64.
+ *  ZF_SDICT_BP      [GP] String-dictionary (Sec. 2.1, Sec. 5): tokens end
+ *                   after ' ' or '.' (at most 64 bytes; the chunk's last may
+ *                   end without one); distinct tokens in order of first
+ *                   appearance are the entries.  Header {u32 n_tokens,
+ *                   n_entries, w, n_groups, ent_off, bytes_off, codes_off,
+ *                   n_bytes}; u32 output offset per 64 tokens at 32; u32
+ *                   entries {offset bits 0-23, length bits 24-31} at ent_off
+ *                   = align16(32 + 4 n_groups); entry bytes at bytes_off,
+ *                   zero-padded to codes_off = align16(bytes_off + n_bytes +
+ *                   4); n_tokens entry indices of w = bitlen(n_entries - 1)
+ *                   bits at codes_off.  BYTES.
  */
 typedef enum {
     ZF_AUTO = 0,
@@ -117,7 +128,8 @@ typedef enum {
     ZF_LZ77 = 6,
     ZF_F2I_BP = 7,
     ZF_ANS = 8,
-    ZF_DSTRIDE_BP = 9
+    ZF_DSTRIDE_BP = 9,
+    ZF_SDICT_BP = 10
 } zf_codec;
 
 typedef void *zf_stream_t;              /* a hipStream_t */
@@ -184,6 +196,7 @@ typedef enum {
     ZF_KIND_ANS,     /* range ANS, one chunk per wavefront */
     ZF_KIND_RLE64,   /* RLE_DELTA_BP, DELTA_BP and DSTRIDE_BP, int64 */
     ZF_KIND_RLE32,   /* RLE_DELTA_BP, DELTA_BP and DSTRIDE_BP, int32 */
+    ZF_KIND_SDICT,   /* SDICT_BP (String-dictionary), bytes */
     ZF_KIND_DICT128,
     ZF_KIND_DICT64,
     ZF_KIND_DICT32,
@@ -197,7 +210,8 @@ typedef enum {
 /* Tile shape of one kind, the device geometry of Sec. 4 (<L,S,C>): `unit`
  * is the work of one wavefront (FP: 2048-value blocks; GP: output elements;
  * PLAIN: bytes; LZ77: output bytes per block of the copy step, 4, 8 or 16,
- * one chunk per wavefront; the persistent kernel always uses 16),
+ * one chunk per wavefront; the persistent kernel always uses 16; SDICT:
+ * output bytes, in whole groups of 64 tokens),
  * `waves_per_block`
  * the wavefronts per workgroup (S/64).  A lane always owns 16 output bytes
  * per step (C).  Zero fields take the tune cache's value, else a default. */

@@ -35,11 +35,12 @@ UNITS = {
     "PLAIN": [16384, 65536, 262144, 1048576],
     "NP": [4, 8, 16],                        # LZ77: output bytes per block
     "ANS": [0],                              # one chunk per wave, no unit knob
+    "SDICT": [1024, 4096, 16384, 65536],     # output bytes per wave (whole groups)
 }
 GROUP = {"FOR32": "FP", "FOR64": "FP", "DICT32": "FP", "DICT64": "FP", "DICT128": "FP",
          "RLE32": "GP", "RLE64": "GP", "LZ77": "NP", "PLAIN": "PLAIN", "F2I": "FP",
-         "ANS": "ANS"}
-DEFAULT = {"FP": 2, "GP": 4096, "PLAIN": 65536, "NP": 16, "ANS": 0}
+         "ANS": "ANS", "SDICT": "SDICT"}
+DEFAULT = {"FP": 2, "GP": 4096, "PLAIN": 65536, "NP": 16, "ANS": 0, "SDICT": 16384}
 
 
 def log(*a):
@@ -63,6 +64,7 @@ def workloads(scale):
         "LZ77": (g.text_column(n(1 << 30), 2), zf.LZ77),
         "F2I": (g.decimal_column(n(1 << 25), 5, 90000, 10500000), zf.F2I_BP),
         "ANS": (g.returnflag_column(n(1 << 28), 0.25, 0.5, 9), zf.ANS),
+        "SDICT": (g.text_column(n(1 << 30), 2), zf.SDICT_BP),
         "PLAIN": (np.frombuffer(g.rng(5).bytes(n(1 << 28)), np.uint8), zf.PLAIN),
     }
 

@@ -12,6 +12,8 @@
 #include <cstdlib>
 #include <thread>
 #include <type_traits>
+#include <unordered_map>
+#include <cstring>
 
 #include "features.hpp"
 #include "zf_internal.hpp"
@@ -554,6 +556,69 @@ static void enc_dstride(std::vector<uint8_t> &s, const T *x, uint32_t n) {
     for (uint32_t j = 0; j < nr; j++) wr32(p + roff + 4ull * j, len[j]);
 }
 
+// ------------------------------------------------------ String-dictionary
+// Tokens end after a space or a period (at most 64 bytes; the chunk's last
+// token may end without one); the distinct tokens, in order of first
+// appearance, are the entries; entry indices bit-packed at the smallest
+// width that holds the last index; one output offset per 64 tokens.
+static void enc_sdict(std::vector<uint8_t> &s, const uint8_t *x, uint32_t n) {
+    struct Key {
+        const uint8_t *p;
+        uint32_t len;
+        bool operator==(const Key &o) const { return len == o.len && std::memcmp(p, o.p, len) == 0; }
+    };
+    struct Hash {
+        size_t operator()(const Key &k) const {
+            uint64_t h = 0x9E3779B97F4A7C15ull ^ k.len;
+            for (uint32_t i = 0; i < k.len; i++) h = (h ^ k.p[i]) * 0x100000001B3ull;
+            return size_t(h ^ (h >> 29));
+        }
+    };
+    std::unordered_map<Key, uint32_t, Hash> index;
+    std::vector<Key> entries;
+    std::vector<uint32_t> codes, starts;
+    uint32_t nbytes = 0;
+    for (uint32_t i = 0; i < n;) {
+        uint32_t L = 0;
+        while (i + L < n && L < kSdMaxToken) {
+            const uint8_t c = x[i + L++];
+            if (c == ' ' || c == '.') break;
+        }
+        const Key k{x + i, L};
+        auto it = index.find(k);
+        uint32_t code;
+        if (it == index.end()) {
+            code = uint32_t(entries.size());
+            index.emplace(k, code);
+            entries.push_back(k);
+            nbytes += L;
+        } else {
+            code = it->second;
+        }
+        if (codes.size() % 64 == 0) starts.push_back(i);
+        codes.push_back(code);
+        i += L;
+    }
+    const uint32_t nt = uint32_t(codes.size()), ne = uint32_t(entries.size());
+    const uint32_t w = ne > 1 ? bit_width64(ne - 1) : 0, ng = uint32_t(starts.size());
+    const uint64_t eo = align_up(32 + 4ull * ng, 16), bo = eo + 4ull * ne;
+    const uint64_t co = align_up(bo + nbytes + 4, 16);
+    s.assign(co + 4 * ((uint64_t(nt) * w + 31) / 32), 0);
+    uint8_t *p = s.data();
+    const uint32_t hdr[8] = {nt, ne, w, ng, uint32_t(eo), uint32_t(bo), uint32_t(co), nbytes};
+    for (int k = 0; k < 8; k++) wr32(p + 4 * k, hdr[k]);
+    for (uint32_t g = 0; g < ng; g++) wr32(p + 32 + 4ull * g, starts[g]);
+    uint32_t at = 0;
+    for (uint32_t k = 0; k < ne; k++) {
+        wr32(p + eo + 4ull * k, at | (entries[k].len << 24));
+        std::memcpy(p + bo + at, entries[k].p, entries[k].len);
+        at += entries[k].len;
+    }
+    BitPacker bp(p + co);
+    for (uint32_t c : codes) bp.put(c, w);
+    bp.flush();
+}
+
 // ------------------------------------------------------------------ LZ77
 // Greedy LZ77 over a chunk of <= 64 KiB: hash chains of 4-byte prefixes
 // (depth 16), longest match, nearest source on ties.
@@ -706,6 +771,7 @@ static void encode_chunk(std::vector<uint8_t> &out, uint32_t codec, uint32_t dty
         if (dtype == D_I32) enc_dstride<int32_t>(out, reinterpret_cast<const int32_t *>(x), n);
         else enc_dstride<int64_t>(out, reinterpret_cast<const int64_t *>(x), n);
         return;
+    case C_SDICT_BP: enc_sdict(out, x, n); return;
     }
     fail(ZF_E_INVALID, "unknown codec %u", codec);
 }
@@ -851,7 +917,7 @@ void compress_host(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t 
         } else {
             // smallest stream among the applicable codecs
             const uint32_t cands[] = {C_FOR_BP, C_DICT_BP, C_DELTA_BP, C_RLE_DELTA_BP, C_LZ77, C_F2I_BP, C_ANS,
-                                      C_DSTRIDE_BP};
+                                      C_DSTRIDE_BP, C_SDICT_BP};
             encode_chunk(out.bytes, C_PLAIN, dtype, x, ce[i], nullptr, *sc);
             out.codec = C_PLAIN;
             std::vector<uint8_t> tmp;

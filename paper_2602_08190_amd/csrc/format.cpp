@@ -41,6 +41,7 @@ bool codec_allows(uint32_t codec, uint32_t dtype) {
     case C_DELTA_BP:
     case C_RLE_DELTA_BP:
     case C_DSTRIDE_BP: return dtype == D_I32 || dtype == D_I64;
+    case C_SDICT_BP: return dtype == D_BYTES;
     case C_DICT_BP: return dtype != D_BYTES && dtype != D_F64;
     case C_F2I_BP: return dtype == D_F64;
     case C_ANS: return true;
@@ -56,6 +57,7 @@ Kind kind_of(uint32_t codec, uint32_t dtype) {
     case C_DELTA_BP:
     case C_RLE_DELTA_BP:
     case C_DSTRIDE_BP: return dtype == D_I32 ? K_RLE32 : K_RLE64;
+    case C_SDICT_BP: return K_SDICT;
     case C_LZ77: return K_LZ;
     case C_F2I_BP: return K_F2I;
     case C_ANS: return K_ANS;
@@ -239,6 +241,30 @@ void check_stream(const ColumnView &v, const uint8_t *blob, uint32_t i) {
                            poff + 8 + 4 * (words_for(cnt - 1, wg) + words_for(cnt, wd)) <= L,
                        ZF_E_CORRUPT, "chunk %u group %u: bad record", i, g);
             ZF_REQUIRE(g == 0 ? off == 0 : (off > prev && off < n), ZF_E_CORRUPT,
+                       "chunk %u group %u: output offset out of order", i, g);
+            prev = off;
+        }
+        return;
+    }
+    case C_SDICT_BP: {
+        ZF_REQUIRE(L >= 32, ZF_E_CORRUPT, "chunk %u: short String-dictionary header", i);
+        const uint32_t nt = rd32(s), ne = rd32(s + 4), w = rd32(s + 8), ng = rd32(s + 12);
+        const uint32_t eo = rd32(s + 16), bo = rd32(s + 20), co = rd32(s + 24), nb = rd32(s + 28);
+        const uint32_t wneed = ne > 1 ? 32 - uint32_t(__builtin_clz(ne - 1)) : 0;
+        ZF_REQUIRE(ne >= 1 && nt >= 1 && w == wneed && ng == (uint64_t(nt) + 63) / 64 &&
+                       eo == align_up(32 + 4ull * ng, 16) && bo == eo + 4ull * ne &&
+                       co == align_up(uint64_t(bo) + nb + 4, 16) && co + 4 * words_for(nt, w) == L &&
+                       nb <= 0xFFFFFFu,
+                   ZF_E_CORRUPT, "chunk %u: String-dictionary header does not match its sizes", i);
+        for (uint32_t k = 0; k < ne; k++) {
+            const uint32_t e = rd32(s + eo + 4ull * k), len = e >> 24;
+            ZF_REQUIRE(len >= 1 && len <= kSdMaxToken && (e & 0xFFFFFFu) + uint64_t(len) <= nb,
+                       ZF_E_CORRUPT, "chunk %u: String-dictionary entry %u", i, k);
+        }
+        uint64_t prev = 0;
+        for (uint32_t g = 0; g < ng; g++) {
+            const uint32_t off = rd32(s + 32 + 4ull * g);
+            ZF_REQUIRE(g == 0 ? off == 0 : (off > prev && off < c.plain_len), ZF_E_CORRUPT,
                        "chunk %u group %u: output offset out of order", i, g);
             prev = off;
         }

@@ -54,6 +54,7 @@ hipError_t launch_decode(const LaunchArgs &A, uint32_t persistent_waves, const u
     launch_ans(A, wpb[K_ANS], st);
     launch_rle32(A, wpb[K_RLE32], st);
     launch_rle64(A, wpb[K_RLE64], st);
+    launch_sdict(A, wpb[K_SDICT], st);
     launch_dict128(A, wpb[K_DICT128], st);
     launch_dict64(A, wpb[K_DICT64], st);
     launch_dict32(A, wpb[K_DICT32], st);

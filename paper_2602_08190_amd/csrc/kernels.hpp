@@ -822,25 +822,146 @@ ZF_DEV uint32_t ext_pick(uint32_t ew, uint32_t k) {
 }
 
 
-// Flat batches (every match reads bytes before the batch or its own
-// literals; the product encoder keeps every batch flat) are copied without
-// any per-lane walk:
-//  * the output of the batch is cut into aligned blocks of BLK bytes, block b
-//    of a step of 64 blocks owned by lane b;
-//  * a byte's source is p + delta, with delta constant over a segment (a
-//    literal run, or one period of a match); bit 31 of the source set means
-//    "literal index".  Each sequence lane writes the delta of each of its
-//    segments at the segment's first byte, in an LDS row of BLK dwords per
-//    block (entry k of block b at row[64k + b]; zero = no segment starts
-//    here; no delta is ever zero);
+// Copies output bytes [pos, end) of a flat batch of segments (no source byte
+// at or after pos), in steps of 64 * BLK bytes:
+//  * a byte's source is p + delta, with delta constant over a segment; bit 31
+//    of the source set means "index into the second view";
+//  * scatter(w0, span, put) calls put(a, delta) for the start a of every
+//    segment of the calling lane, and may skip those outside [w0, w0 + span);
+//    put records the delta at the segment's first byte in an LDS row of BLK
+//    dwords per block (entry k of block b at row[64k + b]; zero = no segment
+//    starts here; no delta is ever zero);
 //  * each block lane carries the last delta forward over its bytes, taking
-//    the delta in force at its first byte from the blocks before it (a wave
+//    the delta in force at its first byte from the blocks before it (a
 //    ballot over the wave) or from the previous step;
 //  * each run of equal delta inside a 4-byte quarter of a block is read as
 //    one unaligned dword through two bounds-checked buffer views (the output
-//    and the literals), one of which is out of range and reads 0; a dword
+//    and the second view), one of which is out of range and reads 0; a dword
 //    that would reach past its view sends the block down a byte path; each
-//    block is written with one aligned store.
+//    block is written with one aligned store (bytes at the edges one by one).
+// plain4 / nlit4: sizes of the views less 3 (0 if below 4); mis: the output
+// pointer's misalignment modulo BLK.
+template <uint32_t BLK, class Scatter>
+ZF_DEV void copy_segments(uint32_t *row, uint8_t *out, __amdgpu_buffer_rsrc_t rs_out,
+                          __amdgpu_buffer_rsrc_t rs_lit, uint32_t plain4, uint32_t nlit4, uint32_t mis,
+                          uint32_t pos, uint32_t end, Scatter &&scatter) {
+    const uint32_t lane = lane_id();
+    const int32_t B0 = int32_t(pos) - int32_t((mis + pos) & (BLK - 1));
+    uint32_t carry = 0;  // delta in force before the step (0: none yet)
+    for (int32_t W = B0; W < int32_t(end); W += int32_t(64 * BLK)) {
+        const uint32_t w0 = uint32_t(W), span = 64 * BLK;
+#pragma unroll
+        for (uint32_t k = 0; k < BLK; k++) row[64 * k + lane] = 0;
+        wave_fence();
+        // scatter the segment starts that fall in the step
+        auto put = [&](uint32_t a, uint32_t d) {
+            const uint32_t r = a - w0;
+            if (r < span) row[64 * (r & (BLK - 1)) + r / BLK] = d;
+        };
+        scatter(w0, span, put);
+        wave_fence();
+        // gather: block lane b owns bytes [w0 + BLK b, w0 + BLK b + BLK)
+        uint32_t v[BLK];
+        uint32_t last = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < BLK; k++) {
+            v[k] = row[64 * k + lane];
+            last = v[k] ? v[k] : last;
+        }
+        uint32_t cur = last_nonzero_below(last, carry);
+        const uint32_t Bb = w0 + BLK * lane;
+        const int32_t Bi = W + int32_t(BLK * lane);
+        // a block wholly outside [pos, end) has no segment start; its
+        // reads are sent out of range of both views (no memory traffic)
+        const bool live = Bi + int32_t(BLK) > int32_t(pos) && Bi < int32_t(end);
+        if (!live) cur = 0x7FFFFFF0u - Bb;
+        // one unaligned dword read per run of equal delta inside each
+        // 4-byte quarter of the block: at the quarter's first byte and
+        // at every segment start.  Byte t of a run sits t bytes into
+        // the run's dword.  A dword that would reach past the end of
+        // its view is not read; its block takes the byte path below.
+        const uint32_t cur0 = cur;
+        uint32_t ro[BLK], rl[BLK];
+        bool slow = false;
+        // all reads first (every lane issues every read; a lane with no
+        // run start at byte k reads nothing), then the bytes
+#pragma unroll
+        for (uint32_t k = 0; k < BLK; k++) {
+            cur = v[k] ? v[k] : cur;
+            const bool start = (k & 3u) == 0 || v[k] != 0;
+            const uint32_t x = Bb + k + cur;
+            const uint32_t xl = x ^ 0x80000000u;
+            const bool in_out = start && x < plain4, in_lit = start && xl < nlit4;
+            // (a byte of a partial block outside [pos, end) may send its
+            // block down the byte path needlessly; that is rare)
+            slow = slow || (live && start && !in_out && !in_lit);
+            ro[k] = __builtin_amdgcn_raw_buffer_load_b32(rs_out, int(in_out ? x : 0x7FFFFFF0u), 0, 0);
+            rl[k] = __builtin_amdgcn_raw_buffer_load_b32(rs_lit, int(in_lit ? xl : 0x7FFFFFF0u), 0, 0);
+        }
+        uint32_t wv[BLK / 4];
+#pragma unroll
+        for (uint32_t d = 0; d < BLK / 4; d++) {
+            uint32_t word = 0, run = 0;
+#pragma unroll
+            for (uint32_t t = 0; t < 4; t++) {
+                const uint32_t k = 4 * d + t;
+                run = (t == 0 || v[k] != 0) ? (ro[k] | rl[k]) : run >> 8;
+                word |= (run & 0xFFu) << (8 * t);
+            }
+            wv[d] = word;
+        }
+        if (any(slow)) {
+            // byte by byte through the views (the chunk's last bytes,
+            // the literal array's last bytes)
+            if (slow) {
+                uint32_t c = cur0;
+#pragma unroll
+                for (uint32_t d = 0; d < BLK / 4; d++) {
+                    uint32_t word = 0;
+#pragma unroll
+                    for (uint32_t t = 0; t < 4; t++) {
+                        const uint32_t k = 4 * d + t;
+                        c = v[k] ? v[k] : c;
+                        const uint32_t x = Bb + k + c;
+                        word |= (__builtin_amdgcn_raw_buffer_load_b8(rs_out, int(x), 0, 0) |
+                                 __builtin_amdgcn_raw_buffer_load_b8(rs_lit, int(x ^ 0x80000000u), 0, 0))
+                                << (8 * t);
+                    }
+                    wv[d] = word;
+                }
+            }
+        }
+        if (Bi >= int32_t(pos) && Bi + int32_t(BLK) <= int32_t(end)) {
+            if constexpr (BLK == 16) {
+                const u32x4 vv = {wv[0], wv[1], wv[2], wv[3]};
+                *gp(reinterpret_cast<u32x4 *>(out + Bi)) = vv;
+            } else if constexpr (BLK == 8) {
+                const u32x2 vv = {wv[0], wv[1]};
+                *gp(reinterpret_cast<u32x2 *>(out + Bi)) = vv;
+            } else {
+                *gp(reinterpret_cast<uint32_t *>(out + Bi)) = wv[0];
+            }
+        } else if (Bi < int32_t(end) && Bi + int32_t(BLK) > int32_t(pos)) {
+            const uint32_t p0 = uint32_t(max(Bi, int32_t(pos)));
+            const uint32_t pe = min(uint32_t(Bi) + BLK, end);
+            for (uint32_t p = p0; p < pe; p++) {
+                const uint32_t k = p - uint32_t(Bi);
+                uint32_t wd = wv[0];
+#pragma unroll
+                for (uint32_t d = 1; d < BLK / 4; d++) wd = k >= 4 * d ? wv[d] : wd;
+                gp(out)[p] = uint8_t(wd >> (8 * (k & 3)));
+            }
+        }
+        wave_fence();
+    }
+}
+
+// Flat batches (every match reads bytes before the batch or its own
+// literals; the product encoder keeps every batch flat) are copied by
+// copy_segments without any per-lane walk: a literal run is one segment
+// whose source is in the literal view, a match one segment (or one per
+// period when it overlaps itself) whose source is earlier output.  Other
+// batches are replayed in order, one sequence at a time.
 // BLK: bytes per block (4, 8 or 16); row: this wave's 64 * BLK dwords.
 template <uint32_t BLK>
 ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, uint32_t *row) {
@@ -921,18 +1042,8 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, uint32_t *row) {
             const uint32_t dL = 0x80000000u + (LP - P);        // literal run
             uint32_t dM = q0 - D;                              // match, first period
             if (q0 >= P) dM += 0x80000000u + (LP - P);         // source in own literals
-            const int32_t B0 = int32_t(pos) - int32_t((mis + pos) & (BLK - 1));
-            uint32_t carry = 0;  // delta in force before the step (0: none yet)
-            for (int32_t W = B0; W < int32_t(end); W += int32_t(64 * BLK)) {
-                const uint32_t w0 = uint32_t(W), span = 64 * BLK;
-#pragma unroll
-                for (uint32_t k = 0; k < BLK; k++) row[64 * k + lane] = 0;
-                wave_fence();
-                // scatter this sequence's segment starts that fall in the step
-                auto put = [&](uint32_t a, uint32_t d) {
-                    const uint32_t r = a - w0;
-                    if (r < span) row[64 * (r & (BLK - 1)) + r / BLK] = d;
-                };
+            copy_segments<BLK>(row, out, rs_out, rs_lit, plain4, nlit4, mis, pos, end,
+                               [&](uint32_t w0, uint32_t span, auto &&put) {
                 if (act && ll) put(P, dL);
                 if (act && ml) {
                     if (off >= ml) {
@@ -947,101 +1058,7 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, uint32_t *row) {
                             put(a, dM - m * off);
                     }
                 }
-                wave_fence();
-                // gather: block lane b owns bytes [w0 + BLK b, w0 + BLK b + BLK)
-                uint32_t v[BLK];
-                uint32_t last = 0;
-#pragma unroll
-                for (uint32_t k = 0; k < BLK; k++) {
-                    v[k] = row[64 * k + lane];
-                    last = v[k] ? v[k] : last;
-                }
-                uint32_t cur = last_nonzero_below(last, carry);
-                const uint32_t Bb = w0 + BLK * lane;
-                const int32_t Bi = W + int32_t(BLK * lane);
-                // a block wholly outside [pos, end) has no segment start; its
-                // reads are sent out of range of both views (no memory traffic)
-                const bool live = Bi + int32_t(BLK) > int32_t(pos) && Bi < int32_t(end);
-                if (!live) cur = 0x7FFFFFF0u - Bb;
-                // one unaligned dword read per run of equal delta inside each
-                // 4-byte quarter of the block: at the quarter's first byte and
-                // at every segment start.  Byte t of a run sits t bytes into
-                // the run's dword.  A dword that would reach past the end of
-                // its view is not read; its block takes the byte path below.
-                const uint32_t cur0 = cur;
-                uint32_t ro[BLK], rl[BLK];
-                bool slow = false;
-                // all reads first (every lane issues every read; a lane with no
-                // run start at byte k reads nothing), then the bytes
-#pragma unroll
-                for (uint32_t k = 0; k < BLK; k++) {
-                    cur = v[k] ? v[k] : cur;
-                    const bool start = (k & 3u) == 0 || v[k] != 0;
-                    const uint32_t x = Bb + k + cur;
-                    const uint32_t xl = x ^ 0x80000000u;
-                    const bool in_out = start && x < plain4, in_lit = start && xl < nlit4;
-                    // (a byte of a partial block outside [pos, end) may send its
-                    // block down the byte path needlessly; that is rare)
-                    slow = slow || (live && start && !in_out && !in_lit);
-                    ro[k] = __builtin_amdgcn_raw_buffer_load_b32(rs_out, int(in_out ? x : 0x7FFFFFF0u), 0, 0);
-                    rl[k] = __builtin_amdgcn_raw_buffer_load_b32(rs_lit, int(in_lit ? xl : 0x7FFFFFF0u), 0, 0);
-                }
-                uint32_t wv[BLK / 4];
-#pragma unroll
-                for (uint32_t d = 0; d < BLK / 4; d++) {
-                    uint32_t word = 0, run = 0;
-#pragma unroll
-                    for (uint32_t t = 0; t < 4; t++) {
-                        const uint32_t k = 4 * d + t;
-                        run = (t == 0 || v[k] != 0) ? (ro[k] | rl[k]) : run >> 8;
-                        word |= (run & 0xFFu) << (8 * t);
-                    }
-                    wv[d] = word;
-                }
-                if (any(slow)) {
-                    // byte by byte through the views (the chunk's last bytes,
-                    // the literal array's last bytes)
-                    if (slow) {
-                        uint32_t c = cur0;
-#pragma unroll
-                        for (uint32_t d = 0; d < BLK / 4; d++) {
-                            uint32_t word = 0;
-#pragma unroll
-                            for (uint32_t t = 0; t < 4; t++) {
-                                const uint32_t k = 4 * d + t;
-                                c = v[k] ? v[k] : c;
-                                const uint32_t x = Bb + k + c;
-                                word |= (__builtin_amdgcn_raw_buffer_load_b8(rs_out, int(x), 0, 0) |
-                                         __builtin_amdgcn_raw_buffer_load_b8(rs_lit, int(x ^ 0x80000000u), 0, 0))
-                                        << (8 * t);
-                            }
-                            wv[d] = word;
-                        }
-                    }
-                }
-                if (Bi >= int32_t(pos) && Bi + int32_t(BLK) <= int32_t(end)) {
-                    if constexpr (BLK == 16) {
-                        const u32x4 vv = {wv[0], wv[1], wv[2], wv[3]};
-                        *gp(reinterpret_cast<u32x4 *>(out + Bi)) = vv;
-                    } else if constexpr (BLK == 8) {
-                        const u32x2 vv = {wv[0], wv[1]};
-                        *gp(reinterpret_cast<u32x2 *>(out + Bi)) = vv;
-                    } else {
-                        *gp(reinterpret_cast<uint32_t *>(out + Bi)) = wv[0];
-                    }
-                } else if (Bi < int32_t(end) && Bi + int32_t(BLK) > int32_t(pos)) {
-                    const uint32_t p0 = uint32_t(max(Bi, int32_t(pos)));
-                    const uint32_t pe = min(uint32_t(Bi) + BLK, end);
-                    for (uint32_t p = p0; p < pe; p++) {
-                        const uint32_t k = p - uint32_t(Bi);
-                        uint32_t wd = wv[0];
-#pragma unroll
-                        for (uint32_t d = 1; d < BLK / 4; d++) wd = k >= 4 * d ? wv[d] : wd;
-                        gp(out)[p] = uint8_t(wd >> (8 * (k & 3)));
-                    }
-                }
-                wave_fence();
-            }
+            });
         } else {
             // in-order replay of this batch
             for (uint32_t k = 0; k < cnt; k++) {
@@ -1064,6 +1081,64 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, uint32_t *row) {
         off = noff;
     }
     if (pos != plain || lp != nlit || ep != next) flag(A.err, ERR_CORRUPT);
+}
+
+// ======================================================= String-dictionary
+// Group-Parallel (Sec. 5: each word is a group that expands to its entry's
+// bytes).  One wave takes whole groups of 64 tokens [t.a, t.b): lane i reads
+// token i's entry index from the packed codes, then the entry (offset,
+// length); a wave scan of the lengths gives each token's output position; the
+// group's bytes are copied by copy_segments with one segment per token whose
+// source is in the entry bytes.  The host checked the header, the entries
+// and the group offsets; the wave checks the codes and each group's length.
+// row: this wave's 256 dwords.
+ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, uint32_t *row) {
+    const uint8_t *s = A.comp + ck.comp_off;
+    const uint32_t lane = lane_id(), plain = ck.n_elems;
+    uint8_t *out = A.out_tab[ck.col] + ck.out_off;
+    const uint32_t nt = first32(ld32u(s)), ne = first32(ld32u(s + 4)), w = first32(ld32u(s + 8));
+    const uint32_t ng = first32(ld32u(s + 12)), eo = first32(ld32u(s + 16));
+    const uint32_t bo = first32(ld32u(s + 20)), co = first32(ld32u(s + 24));
+    if (t.b > ng || t.a >= t.b) {
+        flag(A.err, ERR_CORRUPT);
+        return;
+    }
+    const uint32_t *ents = reinterpret_cast<const uint32_t *>(s + eo);
+    const uint32_t *codes = reinterpret_cast<const uint32_t *>(s + co);
+    const uint64_t ncw = (uint64_t(nt) * w + 31) / 32;
+    // the entry bytes run up to the codes (at least 4 bytes of padding)
+    const __amdgpu_buffer_rsrc_t rs_out = __builtin_amdgcn_make_buffer_rsrc(out, 0, int(plain), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rs_ent =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(s + bo), 0, int(co - bo), 0x00020000);
+    const uint32_t plain4 = plain >= 4 ? plain - 3 : 0, nent4 = co - bo - 3;
+    const uint32_t mis = uint32_t(reinterpret_cast<uintptr_t>(out) & 3u);
+    for (uint32_t g = t.a; g < t.b; g++) {
+        const uint32_t i = 64 * g + lane;
+        const bool act = i < nt;
+        // entry index: w bits at bit i * w (w <= 32: two words)
+        uint32_t code = 0;
+        if (act && w) {
+            const uint64_t bit = uint64_t(i) * w, k = bit >> 5;
+            const uint32_t w0 = codes[k], w1 = k + 1 < ncw ? codes[k + 1] : 0u;
+            code = uint32_t((uint64_t(w0) | (uint64_t(w1) << 32)) >> (bit & 31u)) & mask32(w);
+        }
+        const bool bad_code = act && code >= ne;
+        const uint32_t e = (act && !bad_code) ? ents[code] : 0u;
+        const uint32_t len = e >> 24, eoff = e & 0xFFFFFFu;
+        const uint32_t incl = scan_add32(len), total = rl32(incl, 63);
+        const uint32_t pos = first32(ld32u(s + 32 + 4 * g));
+        const uint32_t end = g + 1 < ng ? first32(ld32u(s + 32 + 4 * (g + 1))) : plain;
+        if (any(bad_code) || uint64_t(pos) + total != end) {
+            flag(A.err, ERR_CORRUPT);
+            return;
+        }
+        const uint32_t P = pos + incl - len;
+        const uint32_t d = 0x80000000u + (eoff - P);  // source index = p + d - 2^31
+        copy_segments<4>(row, out, rs_out, rs_ent, plain4, nent4, mis, pos, end,
+                         [&](uint32_t, uint32_t, auto &&put) {
+                             if (act) put(P, d);
+                         });
+    }
 }
 
 // ===================================================================== ANS
@@ -1219,6 +1294,7 @@ ZF_DEV void run_unit(const LaunchArgs &A, uint32_t kind, uint32_t u, uint32_t *l
         else unit_rle<uint64_t, false>(A, t, ck, lz_row);
         break;
     case K_LZ: unit_lz<16>(A, ck, lz_row); break;
+    case K_SDICT: unit_sdict(A, t, ck, lz_row); break;
     case K_ANS: unit_ans(A, ck, lz_row); break;
     }
 }
@@ -1246,6 +1322,9 @@ __global__ __launch_bounds__(1024) void k_decode_kind(LaunchArgs A) {
         unit_fp<8, true, 8>(A, t, ck);
     } else if constexpr (KIND == K_DICT128) {
         unit_fp<16, true, 8>(A, t, ck);
+    } else if constexpr (KIND == K_SDICT) {
+        __shared__ uint32_t sd_rows[16][256];
+        unit_sdict(A, t, ck, sd_rows[threadIdx.x / 64]);
     } else if constexpr (KIND == K_RLE32) {
         __shared__ uint32_t rle_slots[16][256];
         if (ck.codec == C_DSTRIDE_BP) unit_rle<uint32_t, true>(A, t, ck, rle_slots[threadIdx.x / 64]);
@@ -1273,7 +1352,7 @@ void launch_ans(const LaunchArgs &A, uint32_t waves, hipStream_t st);
 
 // Host launchers, one per kind, each defined in its kind's translation unit.
 #define ZF_KIND_LAUNCHERS(X)                                                                       \
-    X(K_RLE64, launch_rle64) X(K_RLE32, launch_rle32)                           \
+    X(K_RLE64, launch_rle64) X(K_RLE32, launch_rle32) X(K_SDICT, launch_sdict)  \
     X(K_DICT128, launch_dict128) X(K_DICT64, launch_dict64) X(K_DICT32, launch_dict32)              \
     X(K_FOR64, launch_for64) X(K_FOR32, launch_for32) X(K_F2I, launch_f2i) X(K_PLAIN, launch_plain)
 #define ZF_DECLARE_LAUNCHER(KIND, NAME) void NAME(const LaunchArgs &A, uint32_t waves, hipStream_t st);

@@ -17,6 +17,7 @@ static double rate_gbps(Kind k) {
     case K_ANS: return 500;
     case K_RLE32:
     case K_RLE64: return 2500;
+    case K_SDICT: return 2000;
     default: return 4000;
     }
 }
@@ -75,6 +76,19 @@ static void add_chunk(WorkTables &w, const zf_column &col, uint32_t ci, uint32_t
             }
             T.push_back({idx, g, e, e_end});
             e = e_end;
+        }
+        break;
+    }
+    case K_SDICT: {
+        // whole groups of 64 tokens, about `unit` output bytes per unit
+        const uint8_t *s = col.buf.p + c.comp_off;
+        const uint32_t ng = rd32(s + 12), n = c.plain_len;
+        auto gof = [&](uint32_t g) { return g < ng ? rd32(s + 32 + 4ull * g) : n; };
+        for (uint32_t g = 0; g < ng;) {
+            uint32_t gb = g + 1;
+            while (gb < ng && gof(gb) - gof(g) < unit) gb++;
+            T.push_back({idx, g, gb, 0});
+            g = gb;
         }
         break;
     }

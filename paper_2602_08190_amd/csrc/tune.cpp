@@ -76,7 +76,7 @@ struct Json {
     }
 };
 
-const char *kKindNames[K_COUNT] = {"LZ77", "ANS", "RLE64", "RLE32", "DICT128", "DICT64",
+const char *kKindNames[K_COUNT] = {"LZ77", "ANS", "RLE64", "RLE32", "SDICT", "DICT128", "DICT64",
                                    "DICT32", "FOR64", "FOR32", "F2I", "PLAIN"};
 
 std::string default_cache_path() {
@@ -95,7 +95,8 @@ const char *kind_name(uint32_t k) { return k < K_COUNT ? kKindNames[k] : "?"; }
 TileShape default_tiles() {
     TileShape t;
     for (uint32_t k = 0; k < K_COUNT; k++) {
-        t.unit[k] = (k == K_PLAIN) ? 65536u : (k == K_RLE32 || k == K_RLE64) ? 4096u : (k == K_LZ) ? 16u : 2u;
+        t.unit[k] = (k == K_PLAIN) ? 65536u : (k == K_RLE32 || k == K_RLE64) ? 4096u : (k == K_LZ) ? 16u
+                    : (k == K_SDICT) ? 16384u : 2u;
         t.wpb[k] = 4;
     }
     t.wpcu = 16;
@@ -169,6 +170,7 @@ TileShape resolve_tiles(const zf_plan_opts &o) {
     t.unit[K_RLE32] = std::max(64u, t.unit[K_RLE32]);
     t.unit[K_RLE64] = std::max(64u, t.unit[K_RLE64]);
     t.unit[K_PLAIN] = std::max(1024u, t.unit[K_PLAIN]);
+    t.unit[K_SDICT] = std::max(256u, t.unit[K_SDICT]);
     // LZ77: output bytes per block, 4, 8 or 16
     t.unit[K_LZ] = t.unit[K_LZ] <= 4 ? 4u : t.unit[K_LZ] <= 8 ? 8u : 16u;
     return t;
@@ -180,7 +182,8 @@ uint32_t scheduled_unit(uint32_t kind, uint32_t sched, uint32_t tuned) {
     case K_RLE32:
     case K_RLE64: return 1024u << (sched - 1);        // 1024 .. 8192 elements
     case K_PLAIN: return 16384u << (2 * (sched - 1)); // 16 KiB .. 1 MiB
-    case K_LZ: return tuned;
+    case K_LZ:
+    case K_SDICT: return tuned;
     default: return 1u << (sched - 1);                 // 1 .. 8 blocks
     }
 }

@@ -12,10 +12,12 @@ constexpr uint32_t kMaxCols = 256;     // columns per plan (output table size)
 // ANS: M = 2^12 model, state in [2^16, 2^32), 64 interleaved coders, stream
 // header of 16 + 512 (frequencies) + 256 (states) + 256 (word offsets) bytes.
 constexpr uint32_t kAnsM = 4096, kAnsL = 65536, kAnsLanes = 64, kAnsHdr = 1040;
+// String-dictionary: longest token
+constexpr uint32_t kSdMaxToken = 64;
 
 // Codec / dtype codes, as in zf.h.
 enum : uint8_t { C_PLAIN = 1, C_FOR_BP = 2, C_DICT_BP = 3, C_DELTA_BP = 4, C_RLE_DELTA_BP = 5, C_LZ77 = 6,
-                 C_F2I_BP = 7, C_ANS = 8, C_DSTRIDE_BP = 9 };
+                 C_F2I_BP = 7, C_ANS = 8, C_DSTRIDE_BP = 9, C_SDICT_BP = 10 };
 enum : uint8_t { D_I32 = 1, D_I64 = 2, D_BYTES = 3, D_FIXED16 = 4, D_F64 = 5 };
 
 // Kernel kinds: one device routine per (codec class, value width).  The
@@ -24,8 +26,9 @@ enum : uint8_t { D_I32 = 1, D_I64 = 2, D_BYTES = 3, D_FIXED16 = 4, D_F64 = 5 };
 enum Kind : uint32_t {
     K_LZ = 0,
     K_ANS,     // range ANS, 64 interleaved coders per chunk
-    K_RLE64,   // RLE_DELTA_BP and DELTA_BP, int64
-    K_RLE32,   // RLE_DELTA_BP and DELTA_BP, int32
+    K_RLE64,   // RLE_DELTA_BP, DELTA_BP and DSTRIDE_BP, int64
+    K_RLE32,   // RLE_DELTA_BP, DELTA_BP and DSTRIDE_BP, int32
+    K_SDICT,   // String-dictionary, bytes
     K_DICT128,
     K_DICT64,
     K_DICT32,

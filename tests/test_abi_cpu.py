@@ -1,7 +1,7 @@
 """Host side of the product, no GPU: the library loads and exports every
 symbol zf.h declares; the product encoder writes the oracle's canonical
 streams byte for byte (FOR_BP, DICT_BP, DELTA_BP, RLE_DELTA_BP, DSTRIDE_BP,
-F2I_BP, ANS, PLAIN); its
+SDICT_BP, F2I_BP, ANS, PLAIN); its
 LZ77 streams decode to the input under the oracle; host validation rejects
 corrupt columns."""
 import ctypes
@@ -141,6 +141,35 @@ def test_dstride_host_validation():
                      (16 + 32, 0)):           # second group's output offset 0
         t = b.copy()
         t[c["comp_off"] + off:c["comp_off"] + off + 4] = np.frombuffer(np.uint32(val).tobytes(), np.uint8)
+        with pytest.raises(zf.ZfError):
+            zf.Column.from_bytes(t, pinned=False)
+
+
+def test_encoder_byte_identical_sdict():
+    """String-dictionary: generated text in uneven chunks, random bytes, long
+    runs without separators, separators only, tiny chunks."""
+    r = g.rng(37)
+    text = g.text_column(400000, 5)
+    cases = [(text, [1, 100, 65536, 400000 - 65637]),
+             (np.frombuffer(r.bytes(30000), np.uint8), [30000]),
+             (np.frombuffer(b"a" * 300 + b" b. " * 50, np.uint8), [150, 350]),
+             (np.full(5000, ord("."), np.uint8), [64, 4936])]
+    for x, ce in cases:
+        ours, ref = same_streams(x, zf.SDICT_BP, ce)
+        assert ours.tobytes() == ref.tobytes()
+        assert np.array_equal(zo.decode(ours), x)
+
+
+def test_sdict_host_validation():
+    x = np.frombuffer(b"the cat. the dog ran the cat", np.uint8)
+    b = zo.encode(x, zo.SDICT_BP).copy()
+    at = zo.chunks(b)[0]["comp_off"]
+    for off, val in ((48, 0),                  # entry of length 0
+                     (48, 18 | (4 << 24)),     # entry past the entry bytes
+                     (8, 4),                   # width does not match the entry count
+                     (32, 1)):                 # first group offset not 0
+        t = b.copy()
+        t[at + off:at + off + 4] = np.frombuffer(np.uint32(val).tobytes(), np.uint8)
         with pytest.raises(zf.ZfError):
             zf.Column.from_bytes(t, pinned=False)
 

@@ -182,6 +182,27 @@ def test_dstride_oracle_streams_and_auto():
     check([col, auto], decode_image([col, auto]), [x, y])
 
 
+@pytest.mark.parametrize("sd_bytes", [256, 4096, 65536])
+def test_sdict_text_bytes_and_tiles(sd_bytes):
+    """String-dictionary: generated text (product and oracle streams), random
+    bytes, long runs, separators only, tiny and uneven chunks; every tile,
+    per-kind and persistent launches."""
+    log("sdict", sd_bytes)
+    r = g.rng(41)
+    text = g.text_column(3_000_000, 6)
+    xs = [text, text[:200001],
+          np.frombuffer(r.bytes(100000), np.uint8),
+          np.frombuffer(b"a" * 300 + b" b. " * 50 + b"z" * 65, np.uint8),
+          np.full(7000, ord(" "), np.uint8)]
+    cols = [zf.Column.compress(xs[0], zf.SDICT_BP),
+            zf.Column.from_bytes(zo.encode(xs[1], zo.SDICT_BP, [1, 64, 65536, 200001 - 65601])),
+            zf.Column.compress(xs[2], zf.SDICT_BP, chunk_elems=[33333, 66667]),
+            zf.Column.compress(xs[3], zf.SDICT_BP, chunk_elems=[1, 499, len(xs[3]) - 500]),
+            zf.Column.compress(xs[4], zf.SDICT_BP, chunk_elems=[3, 6997])]
+    check(cols, decode_image(cols, tiles={"SDICT": dict(unit=sd_bytes)}), xs)
+    check(cols, decode_image(cols, persistent=True, tiles={"SDICT": dict(unit=sd_bytes, waves_per_block=8)}), xs)
+
+
 def test_rle_and_delta_extremes():
     log("rle extremes")
     xs, cols = [], []
@@ -478,6 +499,19 @@ def test_device_detects_corrupt_streams():
         at = c["comp_off"] + roff + 4 * 70
         b[at:at + 4] = np.frombuffer(np.uint32(val).tobytes(), np.uint8)
         _expect_corrupt([zf.Column.from_bytes(b)])
+    # String-dictionary: an entry index past the entries; an entry shortened
+    # so that the groups no longer meet their offsets
+    x = np.frombuffer(b"the cat. the dog ran the cat " * 10, np.uint8)
+    b = zo.encode(x, zo.SDICT_BP).copy()
+    at = zo.chunks(b)[0]["comp_off"]
+    co = int(np.frombuffer(b[at + 24:at + 28].tobytes(), np.uint32)[0])
+    assert int(np.frombuffer(b[at + 4:at + 8].tobytes(), np.uint32)[0]) == 6
+    t = b.copy()
+    t[at + co:at + co + 4] = np.frombuffer(np.uint32(7).tobytes(), np.uint8)   # code 7 >= 6 entries
+    _expect_corrupt([zf.Column.from_bytes(t)])
+    t = b.copy()
+    t[at + 48:at + 52] = np.frombuffer(np.uint32(3 << 24).tobytes(), np.uint8)  # "the " -> "the"
+    _expect_corrupt([zf.Column.from_bytes(t)])
     # F2I: exception records out of order (the host does not read them)
     x = np.array([0.5, -0.0, np.nan, 1.5] * 3, dtype=np.float64)
     b = zo.encode(x, zo.F2I_BP).copy()
