@@ -840,8 +840,10 @@ ZF_DEV uint32_t ext_pick(uint32_t ew, uint32_t k) {
 //    that would reach past its view sends the block down a byte path; each
 //    block is written with one aligned store (bytes at the edges one by one).
 // plain4 / nlit4: sizes of the views less 3 (0 if below 4); mis: the output
-// pointer's misalignment modulo BLK.
-template <uint32_t BLK, class Scatter>
+// pointer's misalignment modulo BLK.  OUT_SRC = false: no segment reads the
+// output (only the bytes of a partial first block before pos do, and those
+// are not stored), so the output view is never read.
+template <uint32_t BLK, bool OUT_SRC = true, class Scatter>
 ZF_DEV void copy_segments(uint32_t *row, uint8_t *out, __amdgpu_buffer_rsrc_t rs_out,
                           __amdgpu_buffer_rsrc_t rs_lit, uint32_t plain4, uint32_t nlit4, uint32_t mis,
                           uint32_t pos, uint32_t end, Scatter &&scatter) {
@@ -891,11 +893,13 @@ ZF_DEV void copy_segments(uint32_t *row, uint8_t *out, __amdgpu_buffer_rsrc_t rs
             const bool start = (k & 3u) == 0 || v[k] != 0;
             const uint32_t x = Bb + k + cur;
             const uint32_t xl = x ^ 0x80000000u;
-            const bool in_out = start && x < plain4, in_lit = start && xl < nlit4;
+            const bool in_out = OUT_SRC && start && x < plain4, in_lit = start && xl < nlit4;
             // (a byte of a partial block outside [pos, end) may send its
             // block down the byte path needlessly; that is rare)
-            slow = slow || (live && start && !in_out && !in_lit);
-            ro[k] = __builtin_amdgcn_raw_buffer_load_b32(rs_out, int(in_out ? x : 0x7FFFFFF0u), 0, 0);
+            if constexpr (OUT_SRC) slow = slow || (live && start && !in_out && !in_lit);
+            else slow = slow || (live && start && (x & 0x80000000u) && !in_lit);
+            ro[k] = OUT_SRC ? __builtin_amdgcn_raw_buffer_load_b32(rs_out, int(in_out ? x : 0x7FFFFFF0u), 0, 0)
+                            : 0u;
             rl[k] = __builtin_amdgcn_raw_buffer_load_b32(rs_lit, int(in_lit ? xl : 0x7FFFFFF0u), 0, 0);
         }
         uint32_t wv[BLK / 4];
@@ -1091,7 +1095,8 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, uint32_t *row) {
 // group's bytes are copied by copy_segments with one segment per token whose
 // source is in the entry bytes.  The host checked the header, the entries
 // and the group offsets; the wave checks the codes and each group's length.
-// row: this wave's 256 dwords.
+// row: this wave's 64 * kSdBlk dwords.
+constexpr uint32_t kSdBlk = 4;
 ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, uint32_t *row) {
     const uint8_t *s = A.comp + ck.comp_off;
     const uint32_t lane = lane_id(), plain = ck.n_elems;
@@ -1111,7 +1116,7 @@ ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, 
     const __amdgpu_buffer_rsrc_t rs_ent =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(s + bo), 0, int(co - bo), 0x00020000);
     const uint32_t plain4 = plain >= 4 ? plain - 3 : 0, nent4 = co - bo - 3;
-    const uint32_t mis = uint32_t(reinterpret_cast<uintptr_t>(out) & 3u);
+    const uint32_t mis = uint32_t(reinterpret_cast<uintptr_t>(out) & (kSdBlk - 1));
     for (uint32_t g = t.a; g < t.b; g++) {
         const uint32_t i = 64 * g + lane;
         const bool act = i < nt;
@@ -1134,7 +1139,7 @@ ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, 
         }
         const uint32_t P = pos + incl - len;
         const uint32_t d = 0x80000000u + (eoff - P);  // source index = p + d - 2^31
-        copy_segments<4>(row, out, rs_out, rs_ent, plain4, nent4, mis, pos, end,
+        copy_segments<kSdBlk, false>(row, out, rs_out, rs_ent, plain4, nent4, mis, pos, end,
                          [&](uint32_t, uint32_t, auto &&put) {
                              if (act) put(P, d);
                          });
@@ -1323,7 +1328,7 @@ __global__ __launch_bounds__(1024) void k_decode_kind(LaunchArgs A) {
     } else if constexpr (KIND == K_DICT128) {
         unit_fp<16, true, 8>(A, t, ck);
     } else if constexpr (KIND == K_SDICT) {
-        __shared__ uint32_t sd_rows[16][256];
+        __shared__ uint32_t sd_rows[16][64 * kSdBlk];
         unit_sdict(A, t, ck, sd_rows[threadIdx.x / 64]);
     } else if constexpr (KIND == K_RLE32) {
         __shared__ uint32_t rle_slots[16][256];
