@@ -3,17 +3,19 @@
 Default workload: the batched 16-column fact table (45.45M rows, ~8.0 GiB
 plain): six int32 key columns (FOR_BP), three int64 cents columns (FOR_BP),
 three date-like columns with runs (RLE_DELTA_BP), three CHAR(16) flag columns
-(DICT_BP) and one comment-text column (LZ77), in uneven chunks of
-16 KiB - 4 MiB.  Synthetic, seeded data.
+(DICT_BP) and one comment-text column (String-dictionary, SDICT_BP; LZ77 with
+--text-codec lz77), in uneven chunks of 16 KiB - 4 MiB.  Synthetic, seeded
+data.
 
 One step decodes the whole table from its compressed image already in HBM
-(zf_decompress_async: one persistent kernel over every chunk).  `value` is the
-plain bytes produced per second.  Reported beside it: the PCIe end-to-end rate
-of zf_transfer_and_decompress from pinned host memory, the raw uncompressed
-PCIe copy rate, the kernel's HBM roofline, and the oracle decoding a sample on
-the host CPU.
+(zf_decompress_async: one kernel per kind, or the persistent kernel with
+--persistent 1).  `value` is the plain bytes produced per second.  Reported
+beside it: the PCIe end-to-end rate of zf_transfer_and_decompress from pinned
+host memory, the raw uncompressed PCIe copy rate, the dominant kernel's HBM
+roofline, and the oracle decoding a sample on the host CPU.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload fact|for|rle|lz|copy]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+                    [--workload fact|for|rle|lz|f2i|ans|keys|sdict|copy]
 """
 import argparse
 import json
@@ -41,11 +43,14 @@ def kernel_hash():
 
 
 # ------------------------------------------------------------- workloads
-def fact_table(rows):
+def fact_table(rows, text_codec="sdict"):
+    """The 16-column table.  The comment text is String-dictionary coded (the
+    paper's choice for comment columns, Sec. 5) on the same uneven chunks as
+    the other columns; text_codec="lz77" codes it as LZ77 in 64 KiB chunks."""
     from paper_2602_08190_amd import datagen as g
     from paper_2602_08190_amd import zf
     codec_of = {"u32": zf.FOR_BP, "cents": zf.FOR_BP, "date": zf.RLE_DELTA_BP,
-                "char16": zf.DICT_BP, "text": zf.LZ77}
+                "char16": zf.DICT_BP, "text": zf.SDICT_BP if text_codec == "sdict" else zf.LZ77}
     cols, xs, names = [], [], []
     for i, (name, kind, _) in enumerate(g.FACT_COLUMNS):
         t = time.time()
@@ -57,9 +62,10 @@ def fact_table(rows):
         cols.append(c)
         xs.append(x)
         names.append(name)
+    text = ("String-dictionary, SDICT_BP" if text_codec == "sdict" else "LZ77 in 64 KiB chunks")
     desc = (f"batched 16-column fact table, {rows} rows: 6 int32 keys (FOR_BP), 3 int64 cents "
             f"(FOR_BP), 3 run-sorted dates (RLE_DELTA_BP), 3 CHAR(16) flags (DICT_BP), 1 Zipf "
-            f"comment text (LZ77); uneven chunks 16 KiB-4 MiB")
+            f"comment text ({text}); uneven chunks 16 KiB-4 MiB")
     return cols, xs, names, desc
 
 
@@ -185,6 +191,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="fact", choices=["fact", "for", "rle", "lz", "f2i", "ans", "keys", "sdict", "copy"])
     ap.add_argument("--rows", type=int, default=None)
+    ap.add_argument("--text-codec", default="sdict", choices=["sdict", "lz77"],
+                    help="codec of the fact table's comment column")
     ap.add_argument("--no-e2e", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--persistent", type=int, default=0)
@@ -204,7 +212,7 @@ def main():
     zf.lib()
     t0 = time.time()
     if args.workload == "fact":
-        cols, xs, names, desc = fact_table(args.rows or g.FACT_ROWS)
+        cols, xs, names, desc = fact_table(args.rows or g.FACT_ROWS, args.text_codec)
     else:
         n = args.rows or {"for": 1 << 28, "rle": 1 << 26, "lz": 1 << 30, "f2i": 1 << 26,
                            "ans": 1 << 30, "keys": 1 << 26, "sdict": 1 << 30,
