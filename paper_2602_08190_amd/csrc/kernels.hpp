@@ -1238,7 +1238,7 @@ ZF_DEV void unit_ans(const LaunchArgs &A, const ChunkDesc &ck, uint32_t *lds) {
                     a0 = ld16(w + 4), a1 = ld16(w + 5), a2 = ld16(w + 6), a3 = ld16(w + 7);
                 }
             }
-            gp(out)[i] = uint8_t(b);
+            __builtin_nontemporal_store(uint8_t(b), gp(out) + i);  // never read back here
         }
     }
     bad = x != kAnsL || w != wend;
