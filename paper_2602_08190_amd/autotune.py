@@ -35,12 +35,12 @@ UNITS = {
     "PLAIN": [16384, 65536, 262144, 1048576],
     "NP": [4, 8, 16],                        # LZ77: output bytes per block
     "ANS": [0],                              # one chunk per wave, no unit knob
-    "SDICT": [1024, 4096, 16384, 65536],     # output bytes per wave (whole groups)
+    "SDICT": [1024, 2048, 4096, 8192, 16384],  # output bytes per wave (whole groups)
 }
 GROUP = {"FOR32": "FP", "FOR64": "FP", "DICT32": "FP", "DICT64": "FP", "DICT128": "FP",
          "RLE32": "GP", "RLE64": "GP", "LZ77": "NP", "PLAIN": "PLAIN", "F2I": "FP",
          "ANS": "ANS", "SDICT": "SDICT"}
-DEFAULT = {"FP": 2, "GP": 4096, "PLAIN": 65536, "NP": 16, "ANS": 0, "SDICT": 16384}
+DEFAULT = {"FP": 2, "GP": 4096, "PLAIN": 65536, "NP": 16, "ANS": 0, "SDICT": 4096}
 
 
 def log(*a):

@@ -1304,12 +1304,25 @@ ZF_DEV void run_unit(const LaunchArgs &A, uint32_t kind, uint32_t u, uint32_t *l
     }
 }
 
+// Workgroup b of n runs on XCD b mod 8 (workgroups are dealt to the eight
+// XCDs in turn).  This maps it to a work index such that each XCD takes one
+// contiguous eighth of the indices, in order: XCD x holds indices
+// [x q + min(x, r), ...) with n = 8 q + r.
+ZF_DEV uint32_t xcd_block(uint32_t b, uint32_t n) {
+    constexpr uint32_t kXcds = 8;
+    const uint32_t q = n / kXcds, r = n % kXcds, x = b % kXcds, i = b / kXcds;
+    return x * q + min(x, r) + i;
+}
+
 // One launch per kind: wave w of block b takes unit begin + b*waves + w.
 // Only the routine of KIND is instantiated here.
 template <uint32_t KIND>
 __global__ __launch_bounds__(1024) void k_decode_kind(LaunchArgs A) {
     const uint32_t waves = blockDim.x / 64;
-    const uint32_t u = A.kind_begin[KIND] + blockIdx.x * waves + first32(threadIdx.x / 64);
+    // String-dictionary: the tiles of a chunk share its dictionary, so
+    // neighbouring tiles go to the same XCD (and its L2)
+    const uint32_t blk = KIND == K_SDICT ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+    const uint32_t u = A.kind_begin[KIND] + blk * waves + first32(threadIdx.x / 64);
     if (u >= A.kind_begin[KIND + 1]) return;
     const Tile t = A.tiles[u];
     const ChunkDesc ck = A.chunks[t.chunk];

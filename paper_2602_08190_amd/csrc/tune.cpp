@@ -96,7 +96,7 @@ TileShape default_tiles() {
     TileShape t;
     for (uint32_t k = 0; k < K_COUNT; k++) {
         t.unit[k] = (k == K_PLAIN) ? 65536u : (k == K_RLE32 || k == K_RLE64) ? 4096u : (k == K_LZ) ? 16u
-                    : (k == K_SDICT) ? 16384u : 2u;
+                    : (k == K_SDICT) ? 4096u : 2u;
         t.wpb[k] = 4;
     }
     t.wpcu = 16;
