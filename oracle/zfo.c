@@ -985,6 +985,49 @@ static int dec_sdict(const uint8_t *s, uint64_t comp_len, uint32_t plain_len, ui
     return ZFO_OK;
 }
 
+/* ============================================ String-dictionary | BP | ANS
+ * A nested scheme (Sec. 5, the comment column's String-dictionary, then
+ * bit-packing, then ANS): the SDICT_BP stream whose packed entry indices
+ * (the 4*ceil(n_tokens*w/32) bytes at codes_off) are replaced by the ANS
+ * stream of those bytes.  Every header field keeps its SDICT_BP meaning;
+ * comp_len = codes_off + the ANS stream's length, or codes_off alone when
+ * there are no index bytes (w = 0). */
+static void enc_sdict_ans(buf_t *s, const uint8_t *x, uint32_t n) {
+    buf_t inner = {0};
+    enc_sdict(&inner, x, n);
+    if (inner.bad) { free(inner.p); s->bad = 1; return; }
+    uint32_t co = get32(inner.p + 24);
+    uint64_t ncb = inner.n - co;  /* index bytes */
+    buf_t a = {0};
+    if (ncb) enc_ans(&a, inner.p + co, (uint32_t)ncb);
+    buf_resize(s, co + a.n);
+    if (!s->bad && !a.bad) {
+        memcpy(s->p, inner.p, co);
+        if (a.n) memcpy(s->p + co, a.p, a.n);
+        s->n = co + a.n;
+    } else {
+        s->bad = 1;
+    }
+    free(inner.p);
+    free(a.p);
+}
+
+static int dec_sdict_ans(const uint8_t *s, uint64_t comp_len, uint32_t plain_len, uint8_t *out) {
+    if (comp_len < 32) return ZFO_ECORRUPT;
+    uint32_t nt = get32(s), w = get32(s + 8), co = get32(s + 24);
+    if (w > 32 || co > comp_len) return ZFO_ECORRUPT;
+    uint64_t ncb = 4 * packed_words(nt, w);
+    uint8_t *inner = (uint8_t *)malloc(co + ncb + 1);
+    if (!inner) return ZFO_ENOMEM;
+    memcpy(inner, s, co);
+    int rc = ZFO_OK;
+    if (ncb) rc = dec_ans(s + co, comp_len - co, (uint32_t)ncb, inner + co);
+    else if (comp_len != co) rc = ZFO_ECORRUPT;
+    if (rc == ZFO_OK) rc = dec_sdict(inner, co + ncb, plain_len, out);
+    free(inner);
+    return rc;
+}
+
 /* ================================================================= LZ77
  * LZ77 family (Sec. 2.1): repeated byte sequences become pointers to earlier
  * output.  A chunk holds at most 65536 plain bytes and decodes on its own
@@ -1133,7 +1176,8 @@ static int codec_allows(uint32_t codec, uint32_t dtype) {
     case ZFO_F2I_BP: return dtype == ZFO_F64;
     case ZFO_ANS: return zfo_elem_size(dtype) != 0;
     case ZFO_DSTRIDE_BP: return dtype == ZFO_I32 || dtype == ZFO_I64;
-    case ZFO_SDICT_BP: return dtype == ZFO_BYTES;
+    case ZFO_SDICT_BP:
+    case ZFO_SDICT_ANS: return dtype == ZFO_BYTES;
     default: return 0;
     }
 }
@@ -1163,6 +1207,8 @@ int zfo_decode_stream(uint32_t codec, uint32_t dtype, const uint8_t *s, uint64_t
         return dec_dstride(s, comp_len, dtype, n, dst);
     case ZFO_SDICT_BP:
         return dec_sdict(s, comp_len, (uint32_t)plain, dst);
+    case ZFO_SDICT_ANS:
+        return dec_sdict_ans(s, comp_len, (uint32_t)plain, dst);
     case ZFO_FOR_BP:
     case ZFO_DICT_BP: {
         uint64_t *tmp = (uint64_t *)malloc(sizeof(uint64_t) * n);
@@ -1250,6 +1296,7 @@ int zfo_encode(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t code
         case ZFO_ANS: enc_ans(&s, x, n * es); break;
         case ZFO_DSTRIDE_BP: enc_dstride(&s, x, dtype, n); break;
         case ZFO_SDICT_BP: enc_sdict(&s, x, n); break;
+        case ZFO_SDICT_ANS: enc_sdict_ans(&s, x, n); break;
         }
         if (s.bad || s.n > 0xFFFFFFFFu) { free(s.p); b.bad = 1; break; }
         buf_resize(&b, pos + s.n);

@@ -39,6 +39,7 @@ extern "C" {
 #define ZFO_ANS 8
 #define ZFO_DSTRIDE_BP 9
 #define ZFO_SDICT_BP 10
+#define ZFO_SDICT_ANS 11
 
 /* status */
 #define ZFO_OK 0

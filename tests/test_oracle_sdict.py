@@ -2,7 +2,10 @@
 streams derived by hand (tests/golden/sdict_examples.json), the properties
 that define the tokens and the entry order, brute-force round trips over
 every short string of a small alphabet, the entry count of generated text
-against a regular-expression split, and rejection of corrupt streams."""
+against a regular-expression split, and rejection of corrupt streams.  The
+nested String-dictionary | bit-packing | ANS stream is pinned to its two
+separately pinned parts: the String-dictionary stream up to its codes, then
+the ANS stream of exactly its packed index bytes."""
 import itertools
 import re
 import struct
@@ -118,3 +121,54 @@ def test_corrupt_streams_are_rejected(golden):
     assert bad(lambda s: struct.pack_into("<I", s, 32, 1)) == z.ECORRUPT           # group offset
     assert bad(lambda s: struct.pack_into("<I", s, 8, 4)) == z.ECORRUPT            # width
     assert bad(lambda s: None, n=len(x) + 1) == z.ECORRUPT                          # too few bytes
+
+
+# ----------------------------------------- String-dictionary | BP | ANS
+def test_nested_stream_is_sdict_with_ans_coded_indices():
+    """The nested stream is the String-dictionary stream up to its codes,
+    then the ANS stream (a separately pinned codec) of exactly the packed
+    index bytes; it decodes to the input."""
+    r = np.random.default_rng(8)
+    for x in (np.frombuffer(g.text_column(200000, 7).tobytes(), np.uint8),
+              np.frombuffer(b"the cat. the dog ran the cat", np.uint8),
+              np.frombuffer(r.bytes(5000), np.uint8)):
+        sd = stream_of(z.encode(x, z.SDICT_BP))
+        nested = stream_of(z.encode(x, z.SDICT_ANS))
+        co = struct.unpack_from("<I", sd, 24)[0]
+        assert nested[:co] == sd[:co]
+        codes = np.frombuffer(sd[co:], np.uint8)
+        assert nested[co:] == stream_of(z.encode(codes, z.ANS, chunk_elems=[len(codes)]))
+        rc, out = z.decode_stream(z.ANS, z.BYTES, nested[co:], len(codes))
+        assert rc == z.OK and np.array_equal(out, codes)
+        rc, out = z.decode_stream(z.SDICT_ANS, z.BYTES, nested, len(x))
+        assert rc == z.OK and np.array_equal(out, x)
+
+
+def test_nested_without_index_bytes():
+    # one distinct token: w = 0, no index bytes, no ANS stream
+    x = np.frombuffer(b"x " * 70, np.uint8)
+    s = stream_of(z.encode(x, z.SDICT_ANS))
+    assert struct.unpack_from("<I", s, 8)[0] == 0 and len(s) == struct.unpack_from("<I", s, 24)[0]
+    assert z.decode_stream(z.SDICT_ANS, z.BYTES, s, len(x))[1].tobytes() == x.tobytes()
+
+
+def test_nested_brute_force_round_trips():
+    for n in range(1, 7):
+        for t in itertools.product(b"ab .", repeat=n):
+            x = np.frombuffer(bytes(t), np.uint8)
+            assert z.decode(z.encode(x, z.SDICT_ANS)).tobytes() == bytes(t)
+
+
+def test_nested_corrupt_streams_are_rejected():
+    x = np.frombuffer(g.text_column(20000, 9).tobytes(), np.uint8)
+    good = bytearray(stream_of(z.encode(x, z.SDICT_ANS)))
+    co = struct.unpack_from("<I", good, 24)[0]
+    assert z.decode_stream(z.SDICT_ANS, z.BYTES, bytes(good), len(x))[0] == z.OK
+
+    def bad(mut):
+        s = bytearray(good)
+        mut(s)
+        return z.decode_stream(z.SDICT_ANS, z.BYTES, bytes(s), len(x))[0]
+    assert bad(lambda s: struct.pack_into("<I", s, co, 7)) == z.ECORRUPT       # ANS length field
+    assert bad(lambda s: s.__setitem__(len(s) - 1, s[-1] ^ 0x55)) == z.ECORRUPT  # a word
+    assert bad(lambda s: struct.pack_into("<I", s, 24, co + 16)) == z.ECORRUPT  # codes offset
