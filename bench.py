@@ -15,7 +15,7 @@ host memory, the raw uncompressed PCIe copy rate, the dominant kernel's HBM
 roofline, and the oracle decoding a sample on the host CPU.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--workload fact|for|rle|lz|f2i|ans|keys|sdict|copy]
+                    [--workload fact|for|rle|lz|f2i|ans|keys|sdict|sdict_ans|copy]
 """
 import argparse
 import json
@@ -100,6 +100,12 @@ def single(kind, n):
         c = zf.Column.compress(x, zf.SDICT_BP)
         desc = (f"SDICT_BP text, {n} bytes, Zipf(1.1) over 10,000 words, String-dictionary per 1 MiB "
                 f"chunk (tokens end at spaces and periods)")
+    elif kind == "sdict_ans":
+        x = g.text_column(n, 2)
+        c = zf.Column.compress(x, zf.SDICT_ANS)
+        desc = (f"SDICT_ANS text, {n} bytes, Zipf(1.1) over 10,000 words: String-dictionary | "
+                f"bit-packing | ANS per 1 MiB chunk (two launches: ANS stage into scratch, then "
+                f"String-dictionary)")
     elif kind == "keys":
         x = g.key_column(n, 11)
         c = zf.Column.compress(x, zf.DSTRIDE_BP)
@@ -189,7 +195,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="fact", choices=["fact", "for", "rle", "lz", "f2i", "ans", "keys", "sdict", "copy"])
+    ap.add_argument("--workload", default="fact", choices=["fact", "for", "rle", "lz", "f2i", "ans", "keys", "sdict",
+                                                              "sdict_ans", "copy"])
     ap.add_argument("--rows", type=int, default=None)
     ap.add_argument("--text-codec", default="sdict", choices=["sdict", "lz77"],
                     help="codec of the fact table's comment column")
@@ -215,7 +222,7 @@ def main():
         cols, xs, names, desc = fact_table(args.rows or g.FACT_ROWS, args.text_codec)
     else:
         n = args.rows or {"for": 1 << 28, "rle": 1 << 26, "lz": 1 << 30, "f2i": 1 << 26,
-                           "ans": 1 << 30, "keys": 1 << 26, "sdict": 1 << 30,
+                           "ans": 1 << 30, "keys": 1 << 26, "sdict": 1 << 30, "sdict_ans": 1 << 30,
                            "copy": 1 << 30}[args.workload]
         cols, xs, names, desc = single(args.workload, n)
     plain = sum(c.plain_bytes for c in cols)

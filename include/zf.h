@@ -117,6 +117,13 @@ typedef enum {
  *                   zero-padded to codes_off = align16(bytes_off + n_bytes +
  *                   4); n_tokens entry indices of w = bitlen(n_entries - 1)
  *                   bits at codes_off.  BYTES.
+ *  ZF_SDICT_ANS     [GP, two stages] String-dictionary | bit-packing | ANS
+ *                   (Sec. 5): the ZF_SDICT_BP stream with its packed entry
+ *                   indices (4 ceil(n_tokens w / 32) bytes) replaced by the
+ *                   ZF_ANS stream of those bytes (nothing when w = 0).  The
+ *                   indices are ANS-decoded into the plan's scratch area by
+ *                   one launch and expanded by the next, so a plan holding
+ *                   such chunks cannot use the persistent kernel.  BYTES.
  */
 typedef enum {
     ZF_AUTO = 0,
@@ -129,7 +136,8 @@ typedef enum {
     ZF_F2I_BP = 7,
     ZF_ANS = 8,
     ZF_DSTRIDE_BP = 9,
-    ZF_SDICT_BP = 10
+    ZF_SDICT_BP = 10,
+    ZF_SDICT_ANS = 11
 } zf_codec;
 
 typedef void *zf_stream_t;              /* a hipStream_t */

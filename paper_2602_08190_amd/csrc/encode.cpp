@@ -772,6 +772,18 @@ static void encode_chunk(std::vector<uint8_t> &out, uint32_t codec, uint32_t dty
         else enc_dstride<int64_t>(out, reinterpret_cast<const int64_t *>(x), n);
         return;
     case C_SDICT_BP: enc_sdict(out, x, n); return;
+    case C_SDICT_ANS: {
+        // String-dictionary, then ANS over its packed entry indices
+        enc_sdict(out, x, n);
+        const uint32_t co = rd32(out.data() + 24);
+        if (out.size() > co) {
+            std::vector<uint8_t> a;
+            enc_ans(a, out.data() + co, uint32_t(out.size() - co));
+            out.resize(co);
+            out.insert(out.end(), a.begin(), a.end());
+        }
+        return;
+    }
     }
     fail(ZF_E_INVALID, "unknown codec %u", codec);
 }
@@ -917,7 +929,7 @@ void compress_host(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t 
         } else {
             // smallest stream among the applicable codecs
             const uint32_t cands[] = {C_FOR_BP, C_DICT_BP, C_DELTA_BP, C_RLE_DELTA_BP, C_LZ77, C_F2I_BP, C_ANS,
-                                      C_DSTRIDE_BP, C_SDICT_BP};
+                                      C_DSTRIDE_BP, C_SDICT_BP, C_SDICT_ANS};
             encode_chunk(out.bytes, C_PLAIN, dtype, x, ce[i], nullptr, *sc);
             out.codec = C_PLAIN;
             std::vector<uint8_t> tmp;

@@ -41,7 +41,8 @@ bool codec_allows(uint32_t codec, uint32_t dtype) {
     case C_DELTA_BP:
     case C_RLE_DELTA_BP:
     case C_DSTRIDE_BP: return dtype == D_I32 || dtype == D_I64;
-    case C_SDICT_BP: return dtype == D_BYTES;
+    case C_SDICT_BP:
+    case C_SDICT_ANS: return dtype == D_BYTES;
     case C_DICT_BP: return dtype != D_BYTES && dtype != D_F64;
     case C_F2I_BP: return dtype == D_F64;
     case C_ANS: return true;
@@ -57,7 +58,8 @@ Kind kind_of(uint32_t codec, uint32_t dtype) {
     case C_DELTA_BP:
     case C_RLE_DELTA_BP:
     case C_DSTRIDE_BP: return dtype == D_I32 ? K_RLE32 : K_RLE64;
-    case C_SDICT_BP: return K_SDICT;
+    case C_SDICT_BP:
+    case C_SDICT_ANS: return K_SDICT;
     case C_LZ77: return K_LZ;
     case C_F2I_BP: return K_F2I;
     case C_ANS: return K_ANS;
@@ -174,6 +176,22 @@ void assemble_column(HostBuf &out, bool pinned, uint32_t dtype, uint64_t n_elems
 // ------------------------------------------------------------- validation
 static uint64_t words_for(uint64_t fields, uint32_t w) { return (fields * w + 31) / 32; }
 
+// An ANS stream of L bytes decoding to n bytes: header sizes, frequencies
+// that sum to M, word offsets in order and inside the words.
+static void check_ans(const uint8_t *s, uint64_t L, uint64_t n, uint32_t i) {
+    ZF_REQUIRE(L >= kAnsHdr && rd32(s) == n && kAnsHdr + 2ull * rd32(s + 4) == L, ZF_E_CORRUPT,
+               "chunk %u: ANS header does not match its sizes", i);
+    uint32_t sum = 0;
+    for (uint32_t t = 0; t < 256; t++) sum += rd16(s + 16 + 2 * t);
+    ZF_REQUIRE(sum == kAnsM, ZF_E_CORRUPT, "chunk %u: ANS frequencies sum to %u", i, sum);
+    uint32_t prev = 0;
+    for (uint32_t j = 0; j < kAnsLanes; j++) {
+        const uint32_t w = rd32(s + 784 + 4 * j);
+        ZF_REQUIRE(w >= prev && w <= rd32(s + 4), ZF_E_CORRUPT, "chunk %u: ANS word offsets", i);
+        prev = w;
+    }
+}
+
 void check_stream(const ColumnView &v, const uint8_t *blob, uint32_t i) {
     const ChunkInfo &c = v.chunks[i];
     const uint8_t *s = blob + c.comp_off;
@@ -246,16 +264,23 @@ void check_stream(const ColumnView &v, const uint8_t *blob, uint32_t i) {
         }
         return;
     }
-    case C_SDICT_BP: {
+    case C_SDICT_BP:
+    case C_SDICT_ANS: {
         ZF_REQUIRE(L >= 32, ZF_E_CORRUPT, "chunk %u: short String-dictionary header", i);
         const uint32_t nt = rd32(s), ne = rd32(s + 4), w = rd32(s + 8), ng = rd32(s + 12);
         const uint32_t eo = rd32(s + 16), bo = rd32(s + 20), co = rd32(s + 24), nb = rd32(s + 28);
         const uint32_t wneed = ne > 1 ? 32 - uint32_t(__builtin_clz(ne - 1)) : 0;
         ZF_REQUIRE(ne >= 1 && nt >= 1 && w == wneed && ng == (uint64_t(nt) + 63) / 64 &&
                        eo == align_up(32 + 4ull * ng, 16) && bo == eo + 4ull * ne &&
-                       co == align_up(uint64_t(bo) + nb + 4, 16) && co + 4 * words_for(nt, w) == L &&
-                       nb <= 0xFFFFFFu,
+                       co == align_up(uint64_t(bo) + nb + 4, 16) && co <= L && nb <= 0xFFFFFFu,
                    ZF_E_CORRUPT, "chunk %u: String-dictionary header does not match its sizes", i);
+        const uint64_t ncb = 4 * words_for(nt, w);  // packed entry-index bytes
+        if (c.codec == C_SDICT_BP)
+            ZF_REQUIRE(co + ncb == L, ZF_E_CORRUPT, "chunk %u: String-dictionary codes size", i);
+        else if (ncb == 0)
+            ZF_REQUIRE(co == L, ZF_E_CORRUPT, "chunk %u: String-dictionary codes size", i);
+        else
+            check_ans(s + co, L - co, ncb, i);  // the ANS stream of those bytes
         for (uint32_t k = 0; k < ne; k++) {
             const uint32_t e = rd32(s + eo + 4ull * k), len = e >> 24;
             ZF_REQUIRE(len >= 1 && len <= kSdMaxToken && (e & 0xFFFFFFu) + uint64_t(len) <= nb,
@@ -286,20 +311,7 @@ void check_stream(const ColumnView &v, const uint8_t *blob, uint32_t i) {
         }
         return;
     }
-    case C_ANS: {
-        ZF_REQUIRE(L >= kAnsHdr && rd32(s) == c.plain_len && kAnsHdr + 2ull * rd32(s + 4) == L,
-                   ZF_E_CORRUPT, "chunk %u: ANS header does not match its sizes", i);
-        uint32_t sum = 0;
-        for (uint32_t t = 0; t < 256; t++) sum += rd16(s + 16 + 2 * t);
-        ZF_REQUIRE(sum == kAnsM, ZF_E_CORRUPT, "chunk %u: ANS frequencies sum to %u", i, sum);
-        uint32_t prev = 0;
-        for (uint32_t j = 0; j < kAnsLanes; j++) {
-            const uint32_t w = rd32(s + 784 + 4 * j);
-            ZF_REQUIRE(w >= prev && w <= rd32(s + 4), ZF_E_CORRUPT, "chunk %u: ANS word offsets", i);
-            prev = w;
-        }
-        return;
-    }
+    case C_ANS: check_ans(s, L, c.plain_len, i); return;
     case C_LZ77: {
         ZF_REQUIRE(L >= 16 && c.plain_len <= kLzMaxChunk, ZF_E_CORRUPT, "chunk %u: LZ77 sizes", i);
         uint64_t ns = rd32(s), nl = rd32(s + 4), ne = rd32(s + 8), pl = rd32(s + 12);

@@ -32,10 +32,12 @@ __global__ void k_set_out_tab(uint8_t **tab, OutTable t, uint32_t n) {
 }
 
 // ============================================================ host side
-hipError_t launch_set_out_tab(uint8_t **d_tab, uint8_t *const *ptrs, uint32_t n, hipStream_t st) {
+hipError_t launch_set_out_tab(uint8_t **d_tab, uint8_t *const *ptrs, uint32_t n, uint8_t *scratch,
+                              hipStream_t st) {
     OutTable t{};
-    for (uint32_t i = 0; i < n && i < kMaxCols; i++) t.p[i] = ptrs[i];
-    hipLaunchKernelGGL(k_set_out_tab, dim3(1), dim3(kMaxCols), 0, st, d_tab, t, n);
+    for (uint32_t i = 0; i < n && i < kScratchCol; i++) t.p[i] = ptrs[i];
+    t.p[kScratchCol] = scratch;
+    hipLaunchKernelGGL(k_set_out_tab, dim3(1), dim3(kMaxCols), 0, st, d_tab, t, kMaxCols);
     return hipGetLastError();
 }
 

@@ -1109,7 +1109,10 @@ ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, 
         return;
     }
     const uint32_t *ents = reinterpret_cast<const uint32_t *>(s + eo);
-    const uint32_t *codes = reinterpret_cast<const uint32_t *>(s + co);
+    // SDICT_ANS: the indices were ANS-decoded into the scratch area by an
+    // earlier launch (the codes checks below hold for them all the same)
+    const uint32_t *codes = reinterpret_cast<const uint32_t *>(
+        ck.codec == C_SDICT_ANS ? A.out_tab[kScratchCol] + ck.aux_off : s + co);
     const uint64_t ncw = (uint64_t(nt) * w + 31) / 32;
     // the entry bytes run up to the codes (at least 4 bytes of padding)
     const __amdgpu_buffer_rsrc_t rs_out = __builtin_amdgcn_make_buffer_rsrc(out, 0, int(plain), 0x00020000);

@@ -35,6 +35,28 @@ static void add_chunk(WorkTables &w, const zf_column &col, uint32_t ci, uint32_t
     d.col = uint16_t(col_idx);
     d.codec = c.codec;
     d.dtype = uint8_t(col.view.dtype);
+    if (c.codec == C_SDICT_ANS) {
+        // first stage: ANS-decode the packed entry indices into the scratch
+        // area; the String-dictionary stage reads them from there
+        const uint8_t *s = col.buf.p + c.comp_off;
+        const uint32_t nt = rd32(s), wd = rd32(s + 8), co = rd32(s + 24);
+        const uint64_t ncb = 4 * ((uint64_t(nt) * wd + 31) / 32);
+        d.aux_off = w.scratch_bytes;
+        if (ncb) {
+            ChunkDesc a = d;
+            a.comp_off = comp_off + co;
+            a.comp_len = c.comp_len - co;
+            a.n_elems = uint32_t(ncb);
+            a.out_off = d.aux_off;
+            a.col = uint16_t(kScratchCol);
+            a.codec = C_ANS;
+            a.dtype = D_BYTES;
+            a.aux_off = 0;
+            w.tiles[K_ANS].push_back({uint32_t(w.chunks.size()), 0, 0, 0});
+            w.chunks.push_back(a);
+            w.scratch_bytes = align_up(d.aux_off + ncb, 256);
+        }
+    }
     const uint32_t idx = uint32_t(w.chunks.size());
     w.chunks.push_back(d);
     const Kind k = kind_of(c.codec, col.view.dtype);
@@ -150,8 +172,8 @@ struct DeviceGuard {
 
 void build_plan(zf_plan_t *P, const zf_column *const *cols, uint32_t n_cols, int device,
                 const zf_plan_opts &o) {
-    ZF_REQUIRE(cols && n_cols >= 1 && n_cols <= kMaxCols, ZF_E_INVALID,
-               "a plan needs 1..%u columns", kMaxCols);
+    ZF_REQUIRE(cols && n_cols >= 1 && n_cols <= kScratchCol, ZF_E_INVALID,
+               "a plan needs 1..%u columns", kScratchCol);
     for (uint32_t c = 0; c < n_cols; c++) ZF_REQUIRE(cols[c], ZF_E_INVALID, "column %u is null", c);
     ZF_REQUIRE(o.n_slots >= 1, ZF_E_INVALID, "n_slots must be >= 1");
     P->device = device;
@@ -274,6 +296,12 @@ void build_plan(zf_plan_t *P, const zf_column *const *cols, uint32_t n_cols, int
         for (auto &sp : P->d_slots) ZF_HIP(hipMalloc(&sp, slot));
     }
     if (dict_total) ZF_HIP(hipMalloc(&P->d_dict, dict_total));
+    P->scratch_bytes = image.scratch_bytes;
+    for (auto &b : P->batches) P->scratch_bytes = std::max(P->scratch_bytes, b.w.scratch_bytes);
+    ZF_REQUIRE(!(P->scratch_bytes && P->persistent_waves), ZF_E_UNSUPPORTED,
+               "String-dictionary | BP | ANS chunks decode in two ordered launches; the persistent "
+               "kernel does not order its units");
+    if (P->scratch_bytes) ZF_HIP(hipMalloc(&P->d_scratch, P->scratch_bytes));
 
     auto fill = [&](LaunchArgs &A) {
         A.out_tab = P->d_out_tab;
@@ -359,6 +387,7 @@ void release_plan(zf_plan_t *P) {
     if (p.d_dict) (void)hipFree(p.d_dict);
     if (p.d_tables) (void)hipFree(p.d_tables);
     if (p.d_out_tab) (void)hipFree(p.d_out_tab);
+    if (p.d_scratch) (void)hipFree(p.d_scratch);
     if (p.d_err) (void)hipFree(p.d_err);
     if (prev >= 0 && prev != device) (void)hipSetDevice(prev);
 }

@@ -10,7 +10,7 @@ namespace zf {
 // lz_blk: output bytes per block of the per-kind LZ77 kernel (4, 8 or 16).
 hipError_t launch_decode(const LaunchArgs &A, uint32_t persistent_waves, const uint32_t *waves_per_block,
                          uint32_t lz_blk, hipStream_t st);
-hipError_t launch_set_out_tab(uint8_t **d_tab, uint8_t *const *ptrs, uint32_t n, hipStream_t st);
+hipError_t launch_set_out_tab(uint8_t **d_tab, uint8_t *const *ptrs, uint32_t n, uint8_t *scratch, hipStream_t st);
 
 struct CopyOp {
     const uint8_t *src;  // pinned host bytes of a column
@@ -23,6 +23,7 @@ struct WorkTables {
     std::vector<ChunkDesc> chunks;
     std::vector<Tile> tiles[K_COUNT];
     uint64_t plain_bytes = 0, comp_bytes = 0;
+    uint64_t scratch_bytes = 0;  // scratch area the launch's two-stage chunks use
     double t_dec = 0;  // decode-time estimate, seconds
 };
 
@@ -61,6 +62,8 @@ struct zf_plan {
     std::vector<uint8_t *> d_slots;
     uint64_t slot_bytes = 0;
     uint8_t *d_dict = nullptr;
+    uint8_t *d_scratch = nullptr;  // shared by every launch (they run in stream order)
+    uint64_t scratch_bytes = 0;
     uint64_t dict_bytes = 0;
     std::vector<zf::CopyOp> dict_copies;
 

@@ -13,7 +13,7 @@ static void set_outputs(zf_plan_t *P, void *const *d_out, hipStream_t st) {
         ZF_REQUIRE((reinterpret_cast<uintptr_t>(d_out[c]) & 15u) == 0, ZF_E_INVALID,
                    "output %u is not 16-byte aligned", c);
     }
-    ZF_HIP(launch_set_out_tab(P->d_out_tab, reinterpret_cast<uint8_t *const *>(d_out), n, st));
+    ZF_HIP(launch_set_out_tab(P->d_out_tab, reinterpret_cast<uint8_t *const *>(d_out), n, P->d_scratch, st));
 }
 
 void decompress_async(zf_plan_t *P, const void *d_comp, uint64_t comp_bytes, void *const *d_out,

@@ -8,7 +8,10 @@ namespace zf {
 constexpr uint32_t kForBlock = 2048;   // values per FOR / bit-packing block
 constexpr uint32_t kRleGroup = 64;     // runs per RLE group record (one wave)
 constexpr uint32_t kLzMaxChunk = 65536;
-constexpr uint32_t kMaxCols = 256;     // columns per plan (output table size)
+constexpr uint32_t kMaxCols = 256;     // output table size: columns per plan + 1
+// Output-table slot of the plan's scratch area (the decoded entry indices of
+// String-dictionary | BP | ANS chunks, the first of their two decode stages)
+constexpr uint32_t kScratchCol = kMaxCols - 1;
 // ANS: M = 2^12 model, state in [2^16, 2^32), 64 interleaved coders, stream
 // header of 16 + 512 (frequencies) + 256 (states) + 256 (word offsets) bytes.
 constexpr uint32_t kAnsM = 4096, kAnsL = 65536, kAnsLanes = 64, kAnsHdr = 1040;
@@ -17,7 +20,7 @@ constexpr uint32_t kSdMaxToken = 64;
 
 // Codec / dtype codes, as in zf.h.
 enum : uint8_t { C_PLAIN = 1, C_FOR_BP = 2, C_DICT_BP = 3, C_DELTA_BP = 4, C_RLE_DELTA_BP = 5, C_LZ77 = 6,
-                 C_F2I_BP = 7, C_ANS = 8, C_DSTRIDE_BP = 9, C_SDICT_BP = 10 };
+                 C_F2I_BP = 7, C_ANS = 8, C_DSTRIDE_BP = 9, C_SDICT_BP = 10, C_SDICT_ANS = 11 };
 enum : uint8_t { D_I32 = 1, D_I64 = 2, D_BYTES = 3, D_FIXED16 = 4, D_F64 = 5 };
 
 // Kernel kinds: one device routine per (codec class, value width).  The
@@ -50,8 +53,9 @@ struct ChunkDesc {
     uint16_t col;         // column index (output table slot)
     uint8_t codec;
     uint8_t dtype;
+    uint64_t aux_off;     // SDICT_ANS: offset of the decoded entry indices in the scratch area
 };
-static_assert(sizeof(ChunkDesc) == 40, "ChunkDesc layout");
+static_assert(sizeof(ChunkDesc) == 48, "ChunkDesc layout");
 
 // One unit of work for one wavefront.
 //   FOR / DICT / F2I: a = first block, b = number of blocks

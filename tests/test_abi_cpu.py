@@ -1,7 +1,7 @@
 """Host side of the product, no GPU: the library loads and exports every
 symbol zf.h declares; the product encoder writes the oracle's canonical
 streams byte for byte (FOR_BP, DICT_BP, DELTA_BP, RLE_DELTA_BP, DSTRIDE_BP,
-SDICT_BP, F2I_BP, ANS, PLAIN); its
+SDICT_BP, SDICT_ANS, F2I_BP, ANS, PLAIN); its
 LZ77 streams decode to the input under the oracle; host validation rejects
 corrupt columns."""
 import ctypes
@@ -168,6 +168,34 @@ def test_sdict_host_validation():
                      (48, 18 | (4 << 24)),     # entry past the entry bytes
                      (8, 4),                   # width does not match the entry count
                      (32, 1)):                 # first group offset not 0
+        t = b.copy()
+        t[at + off:at + off + 4] = np.frombuffer(np.uint32(val).tobytes(), np.uint8)
+        with pytest.raises(zf.ZfError):
+            zf.Column.from_bytes(t, pinned=False)
+
+
+def test_encoder_byte_identical_sdict_ans():
+    """String-dictionary | BP | ANS: text in uneven chunks, random bytes, a
+    chunk with one distinct token (no index bytes), tiny chunks."""
+    r = g.rng(43)
+    text = g.text_column(300000, 8)
+    cases = [(text, [1, 100, 65536, 300000 - 65637]),
+             (np.frombuffer(r.bytes(20000), np.uint8), [20000]),
+             (np.frombuffer(b"x " * 500, np.uint8), [1000]),
+             (np.frombuffer(b"a b. c " * 40, np.uint8), [3, 277])]
+    for x, ce in cases:
+        ours, ref = same_streams(x, zf.SDICT_ANS, ce)
+        assert ours.tobytes() == ref.tobytes()
+        assert np.array_equal(zo.decode(ours), x)
+
+
+def test_sdict_ans_host_validation():
+    x = g.text_column(20000, 3)
+    b = zo.encode(x, zo.SDICT_ANS).copy()
+    at = zo.chunks(b)[0]["comp_off"]
+    co = int(np.frombuffer(b[at + 24:at + 28].tobytes(), np.uint32)[0])
+    for off, val in ((co, 5),                 # ANS length does not match the index bytes
+                     (co + 16, 0)):           # ANS frequencies no longer sum to 4096
         t = b.copy()
         t[at + off:at + off + 4] = np.frombuffer(np.uint32(val).tobytes(), np.uint8)
         with pytest.raises(zf.ZfError):

@@ -203,6 +203,37 @@ def test_sdict_text_bytes_and_tiles(sd_bytes):
     check(cols, decode_image(cols, persistent=True, tiles={"SDICT": dict(unit=sd_bytes, waves_per_block=8)}), xs)
 
 
+@pytest.mark.parametrize("mode", ["graphs", "no_graphs", "staged", "persistent_rejected"])
+def test_sdict_ans_two_stage_decode(mode):
+    """String-dictionary | BP | ANS: the ANS stage writes the entry indices to
+    the plan's scratch area, the String-dictionary stage reads them; mixed
+    with plain String-dictionary, LZ77 and FOR columns; staged transfers with
+    small slots run several batches through the one scratch area."""
+    log("sdict_ans", mode)
+    r = g.rng(47)
+    text = g.text_column(2_000_000, 9)
+    xs = [text, text[:150001], np.frombuffer(r.bytes(60000), np.uint8),
+          np.frombuffer(b"x " * 3000, np.uint8), g.text_column(300000, 10), g.for_bp_column(100000, 3)]
+    cols = [zf.Column.compress(xs[0], zf.SDICT_ANS, chunk_bytes=(16 << 10, 1 << 20), seed=5),
+            zf.Column.from_bytes(zo.encode(xs[1], zo.SDICT_ANS, [1, 64, 65536, 150001 - 65601])),
+            zf.Column.compress(xs[2], zf.SDICT_ANS, chunk_elems=[30000, 30000]),
+            zf.Column.compress(xs[3], zf.SDICT_ANS, chunk_elems=[6000]),
+            zf.Column.compress(xs[4], zf.SDICT_BP),
+            zf.Column.compress(xs[5], zf.FOR_BP)]
+    cols.append(zf.Column.compress(xs[4], zf.LZ77))
+    xs.append(xs[4])
+    if mode == "persistent_rejected":
+        with pytest.raises(zf.ZfError) as e:
+            zf.Plan(cols, device=0, persistent=True)
+        assert e.value.status == zf.E_UNSUPPORTED
+        return
+    if mode == "staged":
+        outs, _ = decode_staged(cols, slot_bytes=1 << 18)
+        check(cols, outs, xs)
+        return
+    check(cols, decode_image(cols, use_graphs=(mode == "graphs")), xs)
+
+
 def test_rle_and_delta_extremes():
     log("rle extremes")
     xs, cols = [], []
@@ -512,6 +543,18 @@ def test_device_detects_corrupt_streams():
     t = b.copy()
     t[at + 48:at + 52] = np.frombuffer(np.uint32(3 << 24).tobytes(), np.uint8)  # "the " -> "the"
     _expect_corrupt([zf.Column.from_bytes(t)])
+    # String-dictionary | BP | ANS: an ANS stage that decodes to indices past
+    # the entries (the host checks the ANS stream, not what it decodes to)
+    x = np.frombuffer(b"the cat. the dog ran the cat " * 10, np.uint8)
+    b = bytes(zo.encode(x, zo.SDICT_ANS))
+    c = zo.chunks(np.frombuffer(b, np.uint8))[0]
+    s = b[c["comp_off"]:c["comp_off"] + c["comp_len"]]
+    co = int(np.frombuffer(s[24:28], np.uint32)[0])
+    idx = np.full(32, 0xFF, np.uint8)                       # every index 7 >= 6 entries
+    ib = zo.encode(idx, zo.ANS)
+    ic = zo.chunks(ib)[0]
+    bad = s[:co] + bytes(ib[ic["comp_off"]:ic["comp_off"] + ic["comp_len"]])
+    _expect_corrupt([zf.Column.from_bytes(H.container(zf.BYTES, [(bad, len(x), zf.SDICT_ANS)]))])
     # F2I: exception records out of order (the host does not read them)
     x = np.array([0.5, -0.0, np.nan, 1.5] * 3, dtype=np.float64)
     b = zo.encode(x, zo.F2I_BP).copy()
