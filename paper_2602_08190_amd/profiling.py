@@ -63,7 +63,8 @@ def _per_dispatch(path, kernel_id):
 def traffic(root, out_dir, command):
     def f(w, c):
         return os.path.join(root, f"pmc_{w}_{c}", "run_counter_collection.csv")
-    workloads = sorted({d.split("_")[1] for d in os.listdir(root) if d.startswith("pmc_")})
+    workloads = sorted({d[4:].rsplit("_", 2)[0] for d in os.listdir(root)
+                        if d.startswith("pmc_") and d.endswith(("_FETCH_SIZE", "_WRITE_SIZE"))})
     copy_id = KIND_OF_ID.index("PLAIN")
     sf = (1 << 30) / _per_dispatch(f("copy", "FETCH_SIZE"), copy_id)
     sw = (1 << 30) / _per_dispatch(f("copy", "WRITE_SIZE"), copy_id)
