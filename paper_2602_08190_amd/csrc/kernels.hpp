@@ -700,28 +700,20 @@ ZF_DEV void unit_rle(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, ui
         const uint32_t start_abs = end_abs - r;
         // RLE: run values are base, then base + prefix sums of (dmin + field).
         // DeltaStride: run j writes c_j + d_j * p at element p, with stride
-        // d_j = dmin + field, start s_j = base + prefix sums of
-        // (d_{j-1} r_{j-1} + gmin + gap field) and c_j = s_j - d_j * start_j.
+        // d_j = dmin + field, start s_j = s_{j-1} + d_{j-1} r_{j-1} + gap_j
+        // (gap_j = gmin + field, s_0 = base) and c_j = s_j - d_j * start_j.
         U v, dstr = 0;
         if constexpr (DS) {
             dstr = act ? U(cur.dmin + field_of<U>(cur.dw0, cur.dw1, cur.dw2, uint64_t(lane) * cur.wd, cur.wd))
                        : U(0);
-            // stride and count of the run before (lane - 1)
-            const int src = int((lane - 1) * 4);
-            const uint32_t rp = uint32_t(__builtin_amdgcn_ds_bpermute(src, int(r)));
-            U dp;
-            if constexpr (BITS == 32) {
-                dp = uint32_t(__builtin_amdgcn_ds_bpermute(src, int(dstr)));
-            } else {
-                const uint32_t lo = uint32_t(__builtin_amdgcn_ds_bpermute(src, int(uint32_t(dstr))));
-                const uint32_t hi = uint32_t(__builtin_amdgcn_ds_bpermute(src, int(uint32_t(dstr >> 32))));
-                dp = uint64_t(lo) | (uint64_t(hi) << 32);
-            }
-            U e = cur.base;
-            if (lane >= 1)
-                e = U(dp * U(rp) + cur.gmin +
-                      field_of<U>(cur.w0, cur.w1, cur.w2, uint64_t(lane - 1) * cur.w, cur.w));
-            const U st = scan_addT<U>(act ? e : U(0));
+            // start_j = base + sum_{k<j} stride_k count_k + sum_{k<=j} gap_k:
+            // an exclusive and an inclusive wave scan, no cross-lane reads
+            const U f = act ? U(dstr * U(r)) : U(0);
+            const U gap = (act && lane >= 1)
+                              ? U(cur.gmin + field_of<U>(cur.w0, cur.w1, cur.w2, uint64_t(lane - 1) * cur.w, cur.w))
+                              : U(0);
+            const U F = scan_addT<U>(f), Gs = scan_addT<U>(gap);
+            const U st = U(cur.base + (F - f) + Gs);
             v = U(st - dstr * U(start_abs));
         } else {
             U delta = cur.base;
@@ -842,7 +834,9 @@ ZF_DEV uint32_t ext_pick(uint32_t ew, uint32_t k) {
 // plain4 / nlit4: sizes of the views less 3 (0 if below 4); mis: the output
 // pointer's misalignment modulo BLK.  OUT_SRC = false: no segment reads the
 // output (only the bytes of a partial first block before pos do, and those
-// are not stored), so the output view is never read.
+// are not stored), so the output view is never read, and the caller
+// guarantees that the dword at every segment byte lies inside the second
+// view, so no block needs the byte path.
 template <uint32_t BLK, bool OUT_SRC = true, class Scatter>
 ZF_DEV void copy_segments(uint32_t *row, uint8_t *out, __amdgpu_buffer_rsrc_t rs_out,
                           __amdgpu_buffer_rsrc_t rs_lit, uint32_t plain4, uint32_t nlit4, uint32_t mis,
@@ -897,7 +891,6 @@ ZF_DEV void copy_segments(uint32_t *row, uint8_t *out, __amdgpu_buffer_rsrc_t rs
             // (a byte of a partial block outside [pos, end) may send its
             // block down the byte path needlessly; that is rare)
             if constexpr (OUT_SRC) slow = slow || (live && start && !in_out && !in_lit);
-            else slow = slow || (live && start && (x & 0x80000000u) && !in_lit);
             ro[k] = OUT_SRC ? __builtin_amdgcn_raw_buffer_load_b32(rs_out, int(in_out ? x : 0x7FFFFFF0u), 0, 0)
                             : 0u;
             rl[k] = __builtin_amdgcn_raw_buffer_load_b32(rs_lit, int(in_lit ? xl : 0x7FFFFFF0u), 0, 0);
@@ -914,7 +907,7 @@ ZF_DEV void copy_segments(uint32_t *row, uint8_t *out, __amdgpu_buffer_rsrc_t rs
             }
             wv[d] = word;
         }
-        if (any(slow)) {
+        if (OUT_SRC && any(slow)) {
             // byte by byte through the views (the chunk's last bytes,
             // the literal array's last bytes)
             if (slow) {

@@ -58,7 +58,11 @@ def decode_staged(cols, **plan_kw):
 def check(cols, outs, ref=None):
     for i, (c, o) in enumerate(zip(cols, outs)):
         want = zo.decode(c.bytes())
-        assert np.array_equal(o, want), f"column {i}: GPU != oracle"
+        if not np.array_equal(o, want):
+            bad = np.nonzero(o != want)[0]
+            raise AssertionError(f"column {i}: GPU != oracle at {len(bad)} of {len(want)} elements, "
+                                 f"first {bad[:8].tolist()}, got {o[bad[:4]].tolist()}, "
+                                 f"want {want[bad[:4]].tolist()}")
         if ref is not None:
             assert np.array_equal(want, ref[i])
 
