@@ -2,10 +2,14 @@
 paper reports per pattern (Sec. 5.2):
 
     python -m paper_2602_08190_amd.sweeps ans [--mib 1024]
+    python -m paper_2602_08190_amd.sweeps text [--mib 1024]
 
 ANS: decode throughput of a flag column ('A', 'N', 'R') from HBM, over the
 frequency skew (the paper's L_RETURNFLAG-shaped workload made more and more
-imbalanced) and over the chunk size (parallelism against ratio)."""
+imbalanced) and over the chunk size (parallelism against ratio).
+text: the comment-text column under LZ77 (64 KiB chunks, its largest), and
+String-dictionary and String-dictionary | BP | ANS over the chunk size (the
+per-chunk dictionary against parallelism)."""
 import argparse
 import json
 import sys
@@ -65,12 +69,34 @@ def ans(mib):
     return {"workload": f"{mib} MiB flag column, decode from HBM, one kernel per launch", "rows": rows}
 
 
+def text(mib):
+    import torch
+    n = mib << 20
+    x = g.text_column(n, 2)
+    rows = []
+
+    def one(codec, name, kib):
+        col = zf.Column.compress(x, codec, chunk_bytes=(kib << 10, kib << 10))
+        ms, out = time_decode(torch, col)
+        assert np.array_equal(out[:1 << 16].cpu().numpy(), x[:1 << 16])
+        rows.append({"codec": name, "chunk_bytes": kib << 10, "ratio": round(n / col.host_pointer()[1], 3),
+                     "ms": round(ms, 4), "plain_GBps": round(n / ms / 1e6, 1)})
+        log(rows[-1])
+        col.free()
+    one(zf.LZ77, "LZ77", 64)
+    for kib in (64, 256, 1024, 4096, 16384):
+        one(zf.SDICT_BP, "SDICT_BP", kib)
+    for kib in (256, 1024, 4096):
+        one(zf.SDICT_ANS, "SDICT_ANS", kib)
+    return {"workload": f"{mib} MiB comment text (Zipf 1.1 over 10,000 words), decode from HBM", "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["ans"])
+    ap.add_argument("what", choices=["ans", "text"])
     ap.add_argument("--mib", type=int, default=1024)
     a = ap.parse_args()
-    print(json.dumps(ans(a.mib)))
+    print(json.dumps(ans(a.mib) if a.what == "ans" else text(a.mib)))
 
 
 if __name__ == "__main__":
