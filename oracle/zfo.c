@@ -988,28 +988,45 @@ static int dec_sdict(const uint8_t *s, uint64_t comp_len, uint32_t plain_len, ui
 /* ============================================ String-dictionary | BP | ANS
  * A nested scheme (Sec. 5, the comment column's String-dictionary, then
  * bit-packing, then ANS): the SDICT_BP stream whose packed entry indices
- * (the 4*ceil(n_tokens*w/32) bytes at codes_off) are replaced by the ANS
- * stream of those bytes.  Every header field keeps its SDICT_BP meaning;
- * comp_len = codes_off + the ANS stream's length, or codes_off alone when
- * there are no index bytes (w = 0). */
+ * (the ncb = 4*ceil(n_tokens*w/32) bytes at codes_off) are replaced by ANS
+ * streams of those bytes, cut into pieces of SD_ANS_PIECE bytes (the last
+ * one shorter) so that the pieces decode independently.  Every header field
+ * keeps its SDICT_BP meaning.  At codes_off: u32 n_pieces =
+ * ceil(ncb / SD_ANS_PIECE), then u32 end[n_pieces] (the end of each piece's
+ * ANS stream, counted from the first stream's start at codes_off + 4 +
+ * 4*n_pieces), then the streams, each followed by zero bytes up to a
+ * multiple of 4 (so every stream starts 4-aligned; the padding is counted in
+ * the ends).  No index bytes (w = 0): nothing at codes_off,
+ * comp_len = codes_off. */
+#define SD_ANS_PIECE 65536u
+
 static void enc_sdict_ans(buf_t *s, const uint8_t *x, uint32_t n) {
     buf_t inner = {0};
     enc_sdict(&inner, x, n);
     if (inner.bad) { free(inner.p); s->bad = 1; return; }
     uint32_t co = get32(inner.p + 24);
     uint64_t ncb = inner.n - co;  /* index bytes */
-    buf_t a = {0};
-    if (ncb) enc_ans(&a, inner.p + co, (uint32_t)ncb);
-    buf_resize(s, co + a.n);
-    if (!s->bad && !a.bad) {
-        memcpy(s->p, inner.p, co);
-        if (a.n) memcpy(s->p + co, a.p, a.n);
-        s->n = co + a.n;
-    } else {
-        s->bad = 1;
+    uint32_t np = (uint32_t)((ncb + SD_ANS_PIECE - 1) / SD_ANS_PIECE);
+    uint64_t at = co + (np ? 4 + 4 * (uint64_t)np : 0);
+    buf_resize(s, at);
+    if (!s->bad) memcpy(s->p, inner.p, co);
+    if (np && !s->bad) put32(s->p + co, np);
+    for (uint32_t k = 0; k < np && !s->bad; k++) {
+        uint64_t lo = (uint64_t)k * SD_ANS_PIECE, hi = lo + SD_ANS_PIECE < ncb ? lo + SD_ANS_PIECE : ncb;
+        buf_t a = {0};
+        enc_ans(&a, inner.p + co + lo, (uint32_t)(hi - lo));
+        if (a.bad) { s->bad = 1; free(a.p); break; }
+        uint64_t padded = (a.n + 3) & ~(uint64_t)3;
+        buf_resize(s, at + padded);
+        if (!s->bad) {
+            memcpy(s->p + at, a.p, a.n);
+            at += padded;
+            put32(s->p + co + 4 + 4 * (uint64_t)k, (uint32_t)(at - (co + 4 + 4 * (uint64_t)np)));
+        }
+        free(a.p);
     }
+    if (!s->bad) s->n = at;
     free(inner.p);
-    free(a.p);
 }
 
 static int dec_sdict_ans(const uint8_t *s, uint64_t comp_len, uint32_t plain_len, uint8_t *out) {
@@ -1017,12 +1034,26 @@ static int dec_sdict_ans(const uint8_t *s, uint64_t comp_len, uint32_t plain_len
     uint32_t nt = get32(s), w = get32(s + 8), co = get32(s + 24);
     if (w > 32 || co > comp_len) return ZFO_ECORRUPT;
     uint64_t ncb = 4 * packed_words(nt, w);
+    uint32_t np = (uint32_t)((ncb + SD_ANS_PIECE - 1) / SD_ANS_PIECE);
+    if (np == 0 && comp_len != co) return ZFO_ECORRUPT;
+    if (np && (co + 4 + 4 * (uint64_t)np > comp_len || get32(s + co) != np)) return ZFO_ECORRUPT;
     uint8_t *inner = (uint8_t *)malloc(co + ncb + 1);
     if (!inner) return ZFO_ENOMEM;
     memcpy(inner, s, co);
     int rc = ZFO_OK;
-    if (ncb) rc = dec_ans(s + co, comp_len - co, (uint32_t)ncb, inner + co);
-    else if (comp_len != co) rc = ZFO_ECORRUPT;
+    uint64_t base = co + 4 + 4 * (uint64_t)np, prev = 0;
+    for (uint32_t k = 0; k < np && rc == ZFO_OK; k++) {
+        uint64_t end = get32(s + co + 4 + 4 * (uint64_t)k);
+        uint64_t lo = (uint64_t)k * SD_ANS_PIECE, hi = lo + SD_ANS_PIECE < ncb ? lo + SD_ANS_PIECE : ncb;
+        if (end < prev + ANS_HDR || base + end > comp_len || (k + 1 == np && base + end != comp_len)) {
+            rc = ZFO_ECORRUPT;
+        } else {
+            uint64_t alen = ANS_HDR + 2 * (uint64_t)get32(s + base + prev + 4);
+            if (((alen + 3) & ~(uint64_t)3) != end - prev) rc = ZFO_ECORRUPT;
+            else rc = dec_ans(s + base + prev, alen, (uint32_t)(hi - lo), inner + co + lo);
+        }
+        prev = end;
+    }
     if (rc == ZFO_OK) rc = dec_sdict(inner, co + ncb, plain_len, out);
     free(inner);
     return rc;

@@ -773,14 +773,27 @@ static void encode_chunk(std::vector<uint8_t> &out, uint32_t codec, uint32_t dty
         return;
     case C_SDICT_BP: enc_sdict(out, x, n); return;
     case C_SDICT_ANS: {
-        // String-dictionary, then ANS over its packed entry indices
-        enc_sdict(out, x, n);
-        const uint32_t co = rd32(out.data() + 24);
-        if (out.size() > co) {
+        // String-dictionary, then ANS over its packed entry indices in
+        // independent pieces of kSdAnsPiece bytes: u32 count, u32 stream
+        // ends, streams (each zero-padded to a multiple of 4 bytes)
+        std::vector<uint8_t> sd;
+        enc_sdict(sd, x, n);
+        const uint32_t co = rd32(sd.data() + 24);
+        const uint64_t ncb = sd.size() - co;
+        const uint32_t np = uint32_t((ncb + kSdAnsPiece - 1) / kSdAnsPiece);
+        out.assign(sd.begin(), sd.begin() + co);
+        if (np) {
+            out.resize(co + 4 + 4ull * np, 0);
+            wr32(out.data() + co, np);
+            const uint64_t base = out.size();
             std::vector<uint8_t> a;
-            enc_ans(a, out.data() + co, uint32_t(out.size() - co));
-            out.resize(co);
-            out.insert(out.end(), a.begin(), a.end());
+            for (uint32_t k = 0; k < np; k++) {
+                const uint64_t lo = uint64_t(k) * kSdAnsPiece, hi = std::min<uint64_t>(lo + kSdAnsPiece, ncb);
+                enc_ans(a, sd.data() + co + lo, uint32_t(hi - lo));
+                out.insert(out.end(), a.begin(), a.end());
+                out.resize(align_up(out.size(), 4), 0);  // the next stream starts 4-aligned
+                wr32(out.data() + co + 4 + 4ull * k, uint32_t(out.size() - base));
+            }
         }
         return;
     }

@@ -279,8 +279,25 @@ void check_stream(const ColumnView &v, const uint8_t *blob, uint32_t i) {
             ZF_REQUIRE(co + ncb == L, ZF_E_CORRUPT, "chunk %u: String-dictionary codes size", i);
         else if (ncb == 0)
             ZF_REQUIRE(co == L, ZF_E_CORRUPT, "chunk %u: String-dictionary codes size", i);
-        else
-            check_ans(s + co, L - co, ncb, i);  // the ANS stream of those bytes
+        else {
+            // the ANS streams of those bytes, one per piece of kSdAnsPiece
+            const uint32_t np = uint32_t((ncb + kSdAnsPiece - 1) / kSdAnsPiece);
+            ZF_REQUIRE(co + 4 + 4ull * np <= L && rd32(s + co) == np, ZF_E_CORRUPT,
+                       "chunk %u: String-dictionary ANS piece table", i);
+            const uint64_t base = co + 4 + 4ull * np;
+            uint64_t prev = 0;
+            for (uint32_t k = 0; k < np; k++) {
+                const uint64_t end = rd32(s + co + 4 + 4ull * k);
+                const uint64_t len = std::min<uint64_t>(kSdAnsPiece, ncb - uint64_t(k) * kSdAnsPiece);
+                ZF_REQUIRE(end >= prev + kAnsHdr && base + end <= L && (k + 1 < np || base + end == L),
+                           ZF_E_CORRUPT, "chunk %u: String-dictionary ANS piece %u", i, k);
+                const uint64_t alen = kAnsHdr + 2ull * rd32(s + base + prev + 4);  // without padding
+                ZF_REQUIRE(align_up(alen, 4) == end - prev, ZF_E_CORRUPT,
+                           "chunk %u: String-dictionary ANS piece %u padding", i, k);
+                check_ans(s + base + prev, alen, len, i);
+                prev = end;
+            }
+        }
         for (uint32_t k = 0; k < ne; k++) {
             const uint32_t e = rd32(s + eo + 4ull * k), len = e >> 24;
             ZF_REQUIRE(len >= 1 && len <= kSdMaxToken && (e & 0xFFFFFFu) + uint64_t(len) <= nb,

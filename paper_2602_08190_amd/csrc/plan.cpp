@@ -43,17 +43,25 @@ static void add_chunk(WorkTables &w, const zf_column &col, uint32_t ci, uint32_t
         const uint64_t ncb = 4 * ((uint64_t(nt) * wd + 31) / 32);
         d.aux_off = w.scratch_bytes;
         if (ncb) {
-            ChunkDesc a = d;
-            a.comp_off = comp_off + co;
-            a.comp_len = c.comp_len - co;
-            a.n_elems = uint32_t(ncb);
-            a.out_off = d.aux_off;
-            a.col = uint16_t(kScratchCol);
-            a.codec = C_ANS;
-            a.dtype = D_BYTES;
-            a.aux_off = 0;
-            w.tiles[K_ANS].push_back({uint32_t(w.chunks.size()), 0, 0, 0});
-            w.chunks.push_back(a);
+            // one ANS unit per piece (the host checked the piece table)
+            const uint32_t np = rd32(s + co);
+            const uint64_t base = co + 4 + 4ull * np;
+            uint64_t prev = 0;
+            for (uint32_t k = 0; k < np; k++) {
+                const uint64_t end = rd32(s + co + 4 + 4ull * k);
+                ChunkDesc a = d;
+                a.comp_off = comp_off + base + prev;
+                a.comp_len = uint32_t(kAnsHdr + 2ull * rd32(s + base + prev + 4));  // without padding
+                a.n_elems = uint32_t(std::min<uint64_t>(kSdAnsPiece, ncb - uint64_t(k) * kSdAnsPiece));
+                a.out_off = d.aux_off + uint64_t(k) * kSdAnsPiece;
+                a.col = uint16_t(kScratchCol);
+                a.codec = C_ANS;
+                a.dtype = D_BYTES;
+                a.aux_off = 0;
+                w.tiles[K_ANS].push_back({uint32_t(w.chunks.size()), 0, 0, 0});
+                w.chunks.push_back(a);
+                prev = end;
+            }
             w.scratch_bytes = align_up(d.aux_off + ncb, 256);
         }
     }

@@ -61,6 +61,10 @@ inline void wr64(uint8_t *p, uint64_t v) { std::memcpy(p, &v, 8); }
 inline void wr16(uint8_t *p, uint16_t v) { std::memcpy(p, &v, 2); }
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
+// Bytes of packed entry indices per ANS piece of the nested
+// String-dictionary | BP | ANS scheme (each piece decodes on its own).
+constexpr uint32_t kSdAnsPiece = 65536;
+
 uint32_t elem_size(uint32_t dtype);
 bool codec_allows(uint32_t codec, uint32_t dtype);
 uint32_t crc32(const uint8_t *p, uint64_t n, uint32_t crc = 0);

@@ -194,8 +194,11 @@ def test_sdict_ans_host_validation():
     b = zo.encode(x, zo.SDICT_ANS).copy()
     at = zo.chunks(b)[0]["comp_off"]
     co = int(np.frombuffer(b[at + 24:at + 28].tobytes(), np.uint32)[0])
-    for off, val in ((co, 5),                 # ANS length does not match the index bytes
-                     (co + 16, 0)):           # ANS frequencies no longer sum to 4096
+    # at co: piece count, stream end, then the one ANS stream (header at co + 8)
+    for off, val in ((co, 5),                 # piece count does not match the index bytes
+                     (co + 8, 5),             # ANS length does not match the piece
+                     (co + 8 + 4, 1),         # word count no longer fills the padded stream
+                     (co + 8 + 16, 0)):       # ANS frequencies no longer sum to 4096
         t = b.copy()
         t[at + off:at + off + 4] = np.frombuffer(np.uint32(val).tobytes(), np.uint8)
         with pytest.raises(zf.ZfError):

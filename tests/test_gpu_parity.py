@@ -557,7 +557,9 @@ def test_device_detects_corrupt_streams():
     idx = np.full(32, 0xFF, np.uint8)                       # every index 7 >= 6 entries
     ib = zo.encode(idx, zo.ANS)
     ic = zo.chunks(ib)[0]
-    bad = s[:co] + bytes(ib[ic["comp_off"]:ic["comp_off"] + ic["comp_len"]])
+    piece = bytes(ib[ic["comp_off"]:ic["comp_off"] + ic["comp_len"]])
+    piece += bytes(-len(piece) % 4)                         # streams are stored 4-aligned
+    bad = s[:co] + np.array([1, len(piece)], np.uint32).tobytes() + piece   # one piece
     _expect_corrupt([zf.Column.from_bytes(H.container(zf.BYTES, [(bad, len(x), zf.SDICT_ANS)]))])
     # F2I: exception records out of order (the host does not read them)
     x = np.array([0.5, -0.0, np.nan, 1.5] * 3, dtype=np.float64)

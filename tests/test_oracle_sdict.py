@@ -5,7 +5,7 @@ every short string of a small alphabet, the entry count of generated text
 against a regular-expression split, and rejection of corrupt streams.  The
 nested String-dictionary | bit-packing | ANS stream is pinned to its two
 separately pinned parts: the String-dictionary stream up to its codes, then
-the ANS stream of exactly its packed index bytes."""
+the ANS streams of exactly its packed index bytes, 64 KiB per piece."""
 import itertools
 import re
 import struct
@@ -124,22 +124,40 @@ def test_corrupt_streams_are_rejected(golden):
 
 
 # ----------------------------------------- String-dictionary | BP | ANS
+PIECE = 65536
+
+
+def pieces_of(nested, co):
+    """The ANS streams of a nested stream, read from its piece table."""
+    np_ = struct.unpack_from("<I", nested, co)[0]
+    ends = struct.unpack_from(f"<{np_}I", nested, co + 4)
+    base = co + 4 + 4 * np_
+    return [nested[base + (ends[k - 1] if k else 0):base + ends[k]] for k in range(np_)], base + ends[-1]
+
+
 def test_nested_stream_is_sdict_with_ans_coded_indices():
     """The nested stream is the String-dictionary stream up to its codes,
-    then the ANS stream (a separately pinned codec) of exactly the packed
-    index bytes; it decodes to the input."""
+    then ANS streams (a separately pinned codec) of exactly the packed index
+    bytes, cut into pieces of 65536 bytes and each zero-padded to a multiple
+    of 4 bytes; it decodes to the input."""
     r = np.random.default_rng(8)
-    for x in (np.frombuffer(g.text_column(200000, 7).tobytes(), np.uint8),
+    for x in (np.frombuffer(g.text_column(2_000_000, 7).tobytes(), np.uint8),
               np.frombuffer(b"the cat. the dog ran the cat", np.uint8),
               np.frombuffer(r.bytes(5000), np.uint8)):
-        sd = stream_of(z.encode(x, z.SDICT_BP))
-        nested = stream_of(z.encode(x, z.SDICT_ANS))
+        sd = stream_of(z.encode(x, z.SDICT_BP, chunk_elems=[len(x)]))
+        nested = stream_of(z.encode(x, z.SDICT_ANS, chunk_elems=[len(x)]))
         co = struct.unpack_from("<I", sd, 24)[0]
         assert nested[:co] == sd[:co]
         codes = np.frombuffer(sd[co:], np.uint8)
-        assert nested[co:] == stream_of(z.encode(codes, z.ANS, chunk_elems=[len(codes)]))
-        rc, out = z.decode_stream(z.ANS, z.BYTES, nested[co:], len(codes))
-        assert rc == z.OK and np.array_equal(out, codes)
+        streams, end = pieces_of(nested, co)
+        assert end == len(nested) and len(streams) == (len(codes) + PIECE - 1) // PIECE
+        for k, st in enumerate(streams):
+            piece = codes[k * PIECE:(k + 1) * PIECE]
+            ans = stream_of(z.encode(piece, z.ANS, chunk_elems=[len(piece)]))
+            # each stream is stored zero-padded to a multiple of 4 bytes
+            assert len(st) == (len(ans) + 3) // 4 * 4 and st == ans + bytes(len(st) - len(ans))
+            rc, out = z.decode_stream(z.ANS, z.BYTES, ans, len(piece))
+            assert rc == z.OK and np.array_equal(out, piece)
         rc, out = z.decode_stream(z.SDICT_ANS, z.BYTES, nested, len(x))
         assert rc == z.OK and np.array_equal(out, x)
 
@@ -169,6 +187,8 @@ def test_nested_corrupt_streams_are_rejected():
         s = bytearray(good)
         mut(s)
         return z.decode_stream(z.SDICT_ANS, z.BYTES, bytes(s), len(x))[0]
-    assert bad(lambda s: struct.pack_into("<I", s, co, 7)) == z.ECORRUPT       # ANS length field
-    assert bad(lambda s: s.__setitem__(len(s) - 1, s[-1] ^ 0x55)) == z.ECORRUPT  # a word
+    assert bad(lambda s: struct.pack_into("<I", s, co, 2)) == z.ECORRUPT        # piece count
+    assert bad(lambda s: struct.pack_into("<I", s, co + 8, 7)) == z.ECORRUPT    # ANS length field
+    last = co + 8 + 1040 + 2 * struct.unpack_from("<I", good, co + 8 + 4)[0] - 1  # end of the ANS words
+    assert bad(lambda s: s.__setitem__(last, s[last] ^ 0x55)) == z.ECORRUPT  # a word
     assert bad(lambda s: struct.pack_into("<I", s, 24, co + 16)) == z.ECORRUPT  # codes offset
