@@ -226,6 +226,14 @@ def test_sdict_ans_two_stage_decode(mode):
             zf.Column.compress(xs[5], zf.FOR_BP)]
     cols.append(zf.Column.compress(xs[4], zf.LZ77))
     xs.append(xs[4])
+    # two entries ("a ", "b "), w = 1: 65536 index bytes (one full 64 KiB ANS
+    # piece), then 65540 (a second piece of 4 bytes)
+    for nt in (8 << 16, (8 << 16) + 32):
+        t = g.rng(nt).integers(0, 2, nt)
+        ab = np.empty(2 * nt, np.uint8)
+        ab[0::2], ab[1::2] = np.where(t == 0, ord("a"), ord("b")), ord(" ")
+        xs.append(ab)
+        cols.append(zf.Column.compress(ab, zf.SDICT_ANS, chunk_elems=[len(ab)]))
     if mode == "persistent_rejected":
         with pytest.raises(zf.ZfError) as e:
             zf.Plan(cols, device=0, persistent=True)

@@ -162,6 +162,29 @@ def test_nested_stream_is_sdict_with_ans_coded_indices():
         assert rc == z.OK and np.array_equal(out, x)
 
 
+def ab_tokens(nt, seed):
+    """nt tokens, each "a " or "b " at random: two entries, so w = 1 and the
+    packed indices take 4*ceil(nt/32) bytes."""
+    t = np.random.default_rng(seed).integers(0, 2, nt)
+    x = np.empty(2 * nt, np.uint8)
+    x[0::2], x[1::2] = np.where(t == 0, ord("a"), ord("b")), ord(" ")
+    return x
+
+
+def test_nested_piece_boundary():
+    # exactly one full piece of index bytes, then one 4-byte piece past it
+    for nt, pieces, last in ((8 * PIECE, 1, PIECE), (8 * PIECE + 32, 2, 4)):
+        x = ab_tokens(nt, nt)
+        sd = stream_of(z.encode(x, z.SDICT_BP, chunk_elems=[len(x)]))
+        nested = stream_of(z.encode(x, z.SDICT_ANS, chunk_elems=[len(x)]))
+        co = struct.unpack_from("<I", sd, 24)[0]
+        assert struct.unpack_from("<I", sd, 8)[0] == 1 and len(sd) - co == (nt + 31) // 32 * 4
+        streams, _ = pieces_of(nested, co)
+        assert len(streams) == pieces and struct.unpack_from("<I", streams[-1], 0)[0] == last
+        rc, out = z.decode_stream(z.SDICT_ANS, z.BYTES, nested, len(x))
+        assert rc == z.OK and np.array_equal(out, x)
+
+
 def test_nested_without_index_bytes():
     # one distinct token: w = 0, no index bytes, no ANS stream
     x = np.frombuffer(b"x " * 70, np.uint8)
