@@ -150,6 +150,13 @@ def cpu_baseline(cols, budget_s=15.0):
                       f"/ time"}
 
 
+def group_traffic(workload, group):
+    """HBM bytes per decode of one kernel group ("ANS+SDICT" sums its two
+    launches), or None if any launch has no current counter reading."""
+    parts = [read_traffic(f"{workload}/{k}") for k in group.split("+")]
+    return None if None in parts else sum(parts)
+
+
 def read_traffic(key):
     """HBM bytes per launch of one kernel from the committed counter summary
     (profiles/traffic.txt), if it was taken on the current kernel sources."""
@@ -272,6 +279,8 @@ def main():
     groups = {}
     for c, o in zip(cols, outs):
         key = zf.kind_of_column(c)
+        if zf.first_codec(c) == zf.SDICT_ANS:
+            key = "ANS+SDICT"  # two ordered launches: the ANS stage, then String-dictionary
         groups.setdefault(key, ([], []))
         groups[key][0].append(c)
         groups[key][1].append(o)
@@ -296,8 +305,9 @@ def main():
         "decode_hbm_GBps": round(hbm_gbps, 1),
         "roofline": {"bound": "hbm", "achieved": kinds[dom]["GBps"], "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(kinds[dom]["GBps"] / HBM_PEAK_GBPS, 4),
-                     "traffic": read_traffic(f"{args.workload}/{dom}"),
-                     "kernel": {"LZ77": "k_decode_lz (LZ77)", "ANS": "k_decode_ans"}.get(dom, f"k_decode_kind<{dom}>"),
+                     "traffic": group_traffic(args.workload, dom),
+                     "kernel": {"LZ77": "k_decode_lz (LZ77)", "ANS": "k_decode_ans",
+                                "ANS+SDICT": "k_decode_ans then k_decode_kind<SDICT>"}.get(dom, f"k_decode_kind<{dom}>"),
                      "algorithmic_bytes_per_launch": kinds[dom]["algorithmic_bytes"],
                      "avg_launch_ms": kinds[dom]["ms"]},
         "kernels": kinds,

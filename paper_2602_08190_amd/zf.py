@@ -317,12 +317,17 @@ class Plan:
             pass
 
 
+def first_codec(col):
+    """Codec of a column's first chunk (byte 28 of its first chunk-table
+    entry), read in place; PLAIN for a column without chunks."""
+    if col.n_chunks == 0:
+        return PLAIN
+    return ctypes.string_at(col.host_pointer()[0] + 64 + 28, 1)[0]
+
+
 def kind_of_column(col):
     """Kernel kind of a single-codec column (its first chunk's codec)."""
-    b = col.bytes()[:96]
-    if col.n_chunks == 0:
-        return "PLAIN"
-    codec = b[64 + 28]
+    codec = first_codec(col)
     dt = col.dtype
     if codec == PLAIN:
         return "PLAIN"
