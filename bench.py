@@ -213,9 +213,9 @@ def main():
     ap.add_argument("--e2e-reps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the decode path needs no exchange between GPUs, and "
-              "multi-GPU runs are not part of this build (each GPU would decode its own chunks "
-              "over its own PCIe link).", file=sys.stderr)
+        print("bench.py measures one GPU only: decoding needs no exchange between GPUs, and a "
+              "multi-GPU run is not implemented (each GPU would decode its own chunks over its "
+              "own PCIe link).", file=sys.stderr)
         sys.exit(2)
 
     import torch
