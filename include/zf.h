@@ -40,7 +40,7 @@ extern "C" {
 typedef enum {
     ZF_OK = 0,
     ZF_E_INVALID = 1,     /* bad argument (null pointer, size mismatch, bad enum) */
-    ZF_E_UNSUPPORTED = 2, /* valid request this build does not handle          */
+    ZF_E_UNSUPPORTED = 2, /* valid request this library does not handle        */
     ZF_E_CORRUPT = 3,     /* stream failed validation on the host or the device */
     ZF_E_NOMEM = 4,       /* host or device allocation failed                   */
     ZF_E_HIP = 5,         /* a HIP runtime call failed                          */
