@@ -257,6 +257,37 @@ zf_status zf_plan(const zf_column_t *const *cols, uint32_t n_cols, int32_t devic
                   const zf_plan_opts *opts /* nullable */, zf_plan_t **out);
 void zf_plan_free(zf_plan_t *plan);
 
+/*
+ * Batches of a plan in execution order (Sec. 3.3: each batch is a two-stage
+ * job, its PCIe copy then its decode, and the plan orders the batches by
+ * Johnson's rule for the two-machine flow shop).  For batch k (0-based, in
+ * execution order) zf_plan_batch_info fills:
+ *   t_h2d_ms   copy-time estimate: compressed bytes / the plan's PCIe rate
+ *              (zf_plan_opts.pcie_gbps, default 55 GB/s);
+ *   t_dec_ms   decode-time estimate: per chunk, plain bytes / the measured
+ *              rate of its kernel kind in the tune cache (plain_GBps);
+ *   comp_bytes, plain_bytes, n_chunks   the batch's chunks;
+ *   index      the batch's position in column order, before ordering.
+ * Errors: ZF_E_INVALID (null pointer, k >= zf_plan_n_batches).
+ */
+typedef struct {
+    double t_h2d_ms, t_dec_ms;
+    uint64_t comp_bytes, plain_bytes;
+    uint32_t n_chunks, index;
+} zf_batch_info;
+uint32_t zf_plan_n_batches(const zf_plan_t *plan);
+zf_status zf_plan_batch_info(const zf_plan_t *plan, uint32_t k, zf_batch_info *info);
+
+/*
+ * Johnson's rule (Sec. 3.3), the order zf_plan gives its batches: jobs with
+ * a[i] < b[i] first, by increasing a; then the others, by decreasing b; equal
+ * keys keep the lower index first.  a, b: n first- and second-stage times
+ * (host arrays, read only); order: n job indices written by the call (host
+ * array owned by the caller).  Host only, no device needed.  Errors:
+ * ZF_E_INVALID (null pointer with n > 0, a NaN time).
+ */
+zf_status zf_johnson_order(const double *a, const double *b, uint32_t n, uint32_t *order);
+
 /* Device image for zf_decompress_async: column c's serialised bytes go at
  * byte offset zf_plan_image_offset(plan, c) of a device buffer of
  * zf_plan_image_bytes(plan) bytes (offsets are 256-aligned). */

@@ -45,19 +45,34 @@ def build_gen():
     return GENLIB
 
 
-def build_zf(jobs=None):
+def _stale(obj, src):
+    """True if obj is older than its source or any header (incremental builds)."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    heads = [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".hpp")]
+    heads.append(os.path.join(INCLUDE, "zf.h"))
+    return any(os.path.getmtime(p) > t for p in [src] + heads)
+
+
+def build_zf(jobs=None, incremental=False):
+    """Compile every source (incremental=True: only objects older than their
+    source or a header) and link libzf.so."""
     jobs = jobs or max(1, min(16, os.cpu_count() or 1))
     os.makedirs(OBJ, exist_ok=True)
     cmds = []
     objs = []
     for s in HOST_SRC:
         o = os.path.join(OBJ, s + ".o")
-        cmds.append([HIPCC] + COMMON + ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-c", "-o", o,
-                                        os.path.join(CSRC, s)])
+        src = os.path.join(CSRC, s)
+        if not incremental or _stale(o, src):
+            cmds.append([HIPCC] + COMMON + ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-c", "-o", o, src])
         objs.append(o)
     for s in HIP_SRC:
         o = os.path.join(OBJ, s + ".o")
-        cmds.append([HIPCC] + COMMON + DEVICE + ["-c", "-o", o, os.path.join(CSRC, s)])
+        src = os.path.join(CSRC, s)
+        if not incremental or _stale(o, src):
+            cmds.append([HIPCC] + COMMON + DEVICE + ["-c", "-o", o, src])
         objs.append(o)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         list(ex.map(_run, cmds))
@@ -75,4 +90,8 @@ def build():
 
 
 if __name__ == "__main__":
-    print(build())
+    if "--incremental" in sys.argv:
+        build_gen()
+        print(build_zf(incremental=True))
+    else:
+        print(build())

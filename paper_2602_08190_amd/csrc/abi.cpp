@@ -104,6 +104,35 @@ uint64_t zf_plan_image_offset(const zf_plan_t *plan, uint32_t col) {
     return (plan && col < plan->image_off.size()) ? plan->image_off[col] : 0;
 }
 
+uint32_t zf_plan_n_batches(const zf_plan_t *plan) { return plan ? uint32_t(plan->batches.size()) : 0; }
+
+zf_status zf_plan_batch_info(const zf_plan_t *plan, uint32_t k, zf_batch_info *info) {
+    return guard([&] {
+        ZF_REQUIRE(plan && info, ZF_E_INVALID, "null pointer");
+        ZF_REQUIRE(k < plan->batches.size(), ZF_E_INVALID, "batch %u of %zu", k, plan->batches.size());
+        const Batch &b = plan->batches[k];
+        zf_batch_info r{};
+        r.t_h2d_ms = b.t_h2d * 1e3;
+        r.t_dec_ms = b.w.t_dec * 1e3;
+        r.comp_bytes = b.w.comp_bytes;
+        r.plain_bytes = b.w.plain_bytes;
+        r.n_chunks = 0;
+        for (const ChunkDesc &c : b.w.chunks) r.n_chunks += c.col != kScratchCol;
+        r.index = b.index;
+        *info = r;
+    });
+}
+
+zf_status zf_johnson_order(const double *a, const double *b, uint32_t n, uint32_t *order) {
+    return guard([&] {
+        ZF_REQUIRE((a && b && order) || n == 0, ZF_E_INVALID, "null pointer");
+        for (uint32_t i = 0; i < n; i++)
+            ZF_REQUIRE(a[i] == a[i] && b[i] == b[i], ZF_E_INVALID, "job %u has a NaN time", i);
+        const std::vector<uint32_t> o = johnson(std::vector<double>(a, a + n), std::vector<double>(b, b + n));
+        std::copy(o.begin(), o.end(), order);
+    });
+}
+
 zf_status zf_decompress_async(zf_plan_t *plan, const void *d_comp, uint64_t comp_bytes,
                               void *const *d_out, zf_stream_t stream) {
     return guard([&] {

@@ -10,18 +10,6 @@
 
 namespace zf {
 
-// Decode-rate estimates (GB/s of plain output) used only to order batches.
-static double rate_gbps(Kind k) {
-    switch (k) {
-    case K_LZ: return 150;
-    case K_ANS: return 500;
-    case K_RLE32:
-    case K_RLE64: return 2500;
-    case K_SDICT: return 2000;
-    default: return 4000;
-    }
-}
-
 static void add_chunk(WorkTables &w, const zf_column &col, uint32_t ci, uint32_t col_idx,
                       uint64_t comp_off, uint64_t dict_off, const TileShape &ts) {
     const ChunkInfo &c = col.view.chunks[ci];
@@ -128,12 +116,13 @@ static void add_chunk(WorkTables &w, const zf_column &col, uint32_t ci, uint32_t
     }
     w.plain_bytes += c.plain_len;
     w.comp_bytes += c.comp_len;
-    w.t_dec += double(c.plain_len) / (rate_gbps(k) * 1e9);
+    w.t_dec += double(c.plain_len) / (ts.rate_gbps[k] * 1e9);
 }
 
 // Johnson's rule (Sec. 3.3): batches whose copy is shorter than their decode
-// first, by increasing copy time; the rest by decreasing decode time.
-static std::vector<uint32_t> johnson(const std::vector<double> &a, const std::vector<double> &b) {
+// first, by increasing copy time; the rest by decreasing decode time; equal
+// keys keep the lower batch index first (stable sorts of ascending indices).
+std::vector<uint32_t> johnson(const std::vector<double> &a, const std::vector<double> &b) {
     std::vector<uint32_t> first, rest;
     for (uint32_t i = 0; i < a.size(); i++) (a[i] < b[i] ? first : rest).push_back(i);
     std::stable_sort(first.begin(), first.end(), [&](uint32_t x, uint32_t y) { return a[x] < a[y]; });
@@ -269,9 +258,11 @@ void build_plan(zf_plan_t *P, const zf_column *const *cols, uint32_t n_cols, int
     close();
     const double pcie = (o.pcie_gbps > 0 ? o.pcie_gbps : 55.0) * 1e9;
     std::vector<double> ta, tb;
-    for (auto &b : batches) {
+    for (uint32_t i = 0; i < batches.size(); i++) {
+        Batch &b = batches[i];
         uint64_t bytes = 0;
         for (auto &cp : b.copies) bytes += cp.len;
+        b.index = i;
         b.t_h2d = double(bytes) / pcie;
         ta.push_back(b.t_h2d);
         tb.push_back(b.w.t_dec);

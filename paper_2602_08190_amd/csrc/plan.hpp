@@ -28,12 +28,15 @@ struct WorkTables {
 };
 
 void release_plan(zf_plan_t *P);
+// Johnson's two-machine order of jobs with first-stage times a, second b.
+std::vector<uint32_t> johnson(const std::vector<double> &a, const std::vector<double> &b);
 
 struct Batch {
     WorkTables w;
     std::vector<CopyOp> copies;
     uint64_t slot_used = 0;
     double t_h2d = 0;
+    uint32_t index = 0;     // position in column order, before ordering
     LaunchArgs args{};      // comp base = its slot
     int slot = 0;
     hipGraphExec_t exec = nullptr;

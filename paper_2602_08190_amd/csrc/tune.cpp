@@ -98,6 +98,9 @@ TileShape default_tiles() {
         t.unit[k] = (k == K_PLAIN) ? 65536u : (k == K_RLE32 || k == K_RLE64) ? 4096u : (k == K_LZ) ? 16u
                     : (k == K_SDICT) ? 4096u : 2u;
         t.wpb[k] = 4;
+        // rates for ordering batches when the cache has no measurement
+        t.rate_gbps[k] = k == K_LZ ? 600 : k == K_ANS ? 1200 : k == K_SDICT ? 800
+                         : (k == K_RLE32 || k == K_RLE64) ? 3000 : 4000;
     }
     t.wpcu = 16;
     return t;
@@ -138,6 +141,7 @@ bool read_tune_cache(const std::string &path, TileShape &t) {
                                 if (kind < 0) continue;
                                 if (f2 == "unit" && v >= 1) t.unit[kind] = uint32_t(v);
                                 if (f2 == "waves_per_block" && v >= 1 && v <= 16) t.wpb[kind] = uint32_t(v);
+                                if (f2 == "plain_GBps" && v > 0) t.rate_gbps[kind] = v;
                             } while (j.eat(','));
                             if (!j.eat('}')) return false;
                         }

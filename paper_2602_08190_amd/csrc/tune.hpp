@@ -10,6 +10,7 @@ struct TileShape {
     uint32_t unit[K_COUNT];  // FP: blocks; GP: elements; PLAIN: bytes; LZ77: bytes per block
     uint32_t wpb[K_COUNT];   // waves per workgroup
     uint32_t wpcu;           // persistent kernel: waves per CU
+    double rate_gbps[K_COUNT];  // measured decode rate (GB/s of plain output) of the tuned tile
 };
 
 TileShape default_tiles();

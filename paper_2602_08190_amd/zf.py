@@ -66,6 +66,15 @@ class Timing(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("t_h2d_ms", ctypes.c_double), ("t_dec_ms", ctypes.c_double),
+                ("comp_bytes", ctypes.c_uint64), ("plain_bytes", ctypes.c_uint64),
+                ("n_chunks", ctypes.c_uint32), ("index", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 # every symbol zf.h declares, with (restype, argtypes)
 _vp, _u32, _u64, _i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
 SIGNATURES = {
@@ -86,6 +95,9 @@ SIGNATURES = {
     "zf_plan_free": (None, [_vp]),
     "zf_plan_image_bytes": (_u64, [_vp]),
     "zf_plan_image_offset": (_u64, [_vp, _u32]),
+    "zf_plan_n_batches": (_u32, [_vp]),
+    "zf_plan_batch_info": (_i32, [_vp, _u32, ctypes.POINTER(BatchInfo)]),
+    "zf_johnson_order": (_i32, [_vp, _vp, _u32, _vp]),
     "zf_decompress_async": (_i32, [_vp, _vp, _u64, ctypes.POINTER(_vp), _vp]),
     "zf_transfer_and_decompress": (_i32, [_vp, ctypes.POINTER(_vp), _vp,
                                           ctypes.POINTER(Timing)]),
@@ -231,6 +243,16 @@ def chunk_features(x):
     return out
 
 
+def johnson_order(a, b):
+    """The library's Johnson order of jobs with stage times a (copy), b (decode)."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    assert a.shape == b.shape and a.ndim == 1
+    order = np.zeros(a.size, np.uint32)
+    _check(lib().zf_johnson_order(a.ctypes.data, b.ctypes.data, a.size, order.ctypes.data))
+    return order.tolist()
+
+
 def _ptr(x):
     """Device pointer of a torch tensor, or an int."""
     if x is None:
@@ -286,6 +308,15 @@ class Plan:
 
     def image_offset(self, c):
         return lib().zf_plan_image_offset(self._h, c)
+
+    def batches(self):
+        """The plan's batches in execution order (zf_plan_batch_info)."""
+        out = []
+        for k in range(lib().zf_plan_n_batches(self._h)):
+            b = BatchInfo()
+            _check(lib().zf_plan_batch_info(self._h, k, ctypes.byref(b)))
+            out.append(b.as_dict())
+        return out
 
     def _outs(self, outs):
         return (ctypes.c_void_p * len(outs))(*[_ptr(t) for t in outs])
