@@ -9,10 +9,18 @@ data.
 
 One step decodes the whole table from its compressed image already in HBM
 (zf_decompress_async: one kernel per kind, or the persistent kernel with
---persistent 1).  `value` is the plain bytes produced per second.  Reported
-beside it: the PCIe end-to-end rate of zf_transfer_and_decompress from pinned
-host memory, the raw uncompressed PCIe copy rate, the dominant kernel's HBM
-roofline, and the oracle decoding a sample on the host CPU.
+--persistent 1).  The metric names two rates: the end-to-end effective rate
+of H2D + decode from pinned host memory, and the decode HBM rate.  `value` is
+the second, (compressed bytes read + plain bytes written) / step time, since
+its inputs are resident in HBM when the timed region starts; the PCIe-
+inclusive rate is reported beside it under "e2e" with the raw uncompressed
+copy it is compared with.  Also reported: plain bytes decoded per second,
+per-step median and p10/p90, each kernel kind's time inside the step (HIP
+events around its launch), the dominant kernel's HBM roofline, the whole
+output checked against the oracle (decoded chunk-parallel on the host
+cores, which also times the oracle on all cores), the oracle on one core on a
+bounded sample, the host and ROCm description and a sha256 manifest of the
+generated inputs.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
                     [--workload fact|for|rle|lz|f2i|ans|keys|sdict|sdict_ans|copy]
@@ -121,7 +129,76 @@ def single(kind, n):
 
 
 # ------------------------------------------------------------- CPU oracle
-def cpu_baseline(cols, budget_s=15.0):
+def host_threads():
+    """Host threads for the chunk-parallel oracle: the CPUs this process may
+    run on, at most 16 (one GPU's share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def host_description(threads):
+    d = {"threads_used": threads, "cpus_visible": os.cpu_count()}
+    try:
+        models, sockets = set(), set()
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                models.add(line.split(":", 1)[1].strip())
+            elif line.startswith("physical id"):
+                sockets.add(line.split(":", 1)[1].strip())
+        d["cpu_model"] = "; ".join(sorted(models))
+        d["sockets"] = len(sockets) or None
+    except OSError:
+        pass
+    try:
+        cpus = sorted(os.sched_getaffinity(0))
+        nodes = set()
+        base = "/sys/devices/system/node"
+        for nd in os.listdir(base):
+            if nd.startswith("node"):
+                lst = open(os.path.join(base, nd, "cpulist")).read().strip()
+                ids = set()
+                for part in lst.split(","):
+                    if "-" in part:
+                        a, b = part.split("-")
+                        ids.update(range(int(a), int(b) + 1))
+                    elif part:
+                        ids.add(int(part))
+                if ids & set(cpus):
+                    nodes.add(nd)
+        d["numa_nodes"] = sorted(nodes)
+    except OSError:
+        pass
+    try:
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                d["mem_total_GiB"] = round(int(line.split()[1]) / 2**20, 1)
+    except OSError:
+        pass
+    return d
+
+
+def gpu_description(torch):
+    import subprocess
+    d = {"name": torch.cuda.get_device_name(0)}
+    try:
+        d["rocm"] = open("/opt/rocm/.info/version").read().strip()
+    except OSError:
+        pass
+    d["torch"] = torch.__version__
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True, timeout=20)
+        clocks = json.loads(r.stdout)
+        card = next(iter(clocks.values()))
+        d["clocks"] = {k: v for k, v in card.items() if "clock" in k.lower()}
+    except Exception as e:  # the description is informational
+        d["clocks"] = f"unavailable ({type(e).__name__})"
+    return d
+
+
+def cpu_single_thread(cols, budget_s=12.0):
     """The oracle (single-threaded C) decoding runs of consecutive chunks from
     every column for about budget_s seconds in total."""
     import oracle.zfo as zo
@@ -143,11 +220,70 @@ def cpu_baseline(cols, budget_s=15.0):
             first = (first + k) % len(cs)
             k *= 2
     return {"value": round(total_bytes / total_s / 1e9, 4), "unit": "GB/s", "cores": 1,
-            "kind": "oracle",
             "sample": f"{nchunks} chunks in runs of consecutive chunks, about {per_col:.1f} s of "
                       f"decoding per column over all {len(cols)} columns, {total_bytes / 2**20:.0f} "
-                      f"MiB plain decoded from host memory in {total_s:.1f} s; rate = plain bytes "
-                      f"/ time"}
+                      f"MiB plain decoded from host memory in {total_s:.1f} s"}
+
+
+def oracle_full_decode(cols, threads):
+    """Every chunk of every column decoded by the oracle, chunk ranges spread
+    over `threads` host threads (the oracle itself is single-threaded).
+    Returns (outputs as flat uint8 arrays, wall seconds)."""
+    import concurrent.futures as cf
+    import oracle.zfo as zo
+    blobs = [c.bytes() for c in cols]
+    outs, jobs = [], []
+    for ci, b in enumerate(blobs):
+        info = zo.inspect(b)
+        cs = zo.chunks(b)
+        out = np.empty(info["plain_bytes"], np.uint8)
+        outs.append(out)
+        piece = max(1, info["plain_bytes"] // (threads * 4))
+        i = 0
+        while i < len(cs):
+            j, nb = i, 0
+            while j < len(cs) and (nb < piece or j == i):
+                nb += cs[j]["plain_len"]
+                j += 1
+            jobs.append((ci, i, j - i, cs[i]["plain_off"], nb))
+            i = j
+    t = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(lambda jb: zo.decode_chunks_into(blobs[jb[0]], jb[1], jb[2], outs[jb[0]], jb[3], jb[4]),
+                    jobs))
+    return outs, time.perf_counter() - t
+
+
+def compare_outputs(torch, outs, ref, threads):
+    """Whole-output check: each GPU column against the oracle's bytes.
+    Returns per-column {"ok", "first_mismatch"}."""
+    import concurrent.futures as cf
+    host = [o.view(torch.uint8).reshape(-1).cpu().numpy() for o in outs]
+
+    def one(i):
+        a, b = host[i], ref[i]
+        if a.size == b.size and np.array_equal(a, b):
+            return {"ok": True}
+        if a.size != b.size:
+            return {"ok": False, "first_mismatch": f"size {a.size} != {b.size}"}
+        bad = np.flatnonzero(a != b)
+        return {"ok": False, "first_mismatch": int(bad[0]), "mismatching_bytes": int(bad.size)}
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(one, range(len(outs))))
+
+
+def sha256_manifest(xs, names, threads):
+    import concurrent.futures as cf
+    import hashlib
+
+    def one(x):
+        return hashlib.sha256(np.ascontiguousarray(x).view(np.uint8).reshape(-1)).hexdigest()
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        return dict(zip(names, ex.map(one, xs)))
+
+
+def pct(v, q):
+    return float(np.percentile(np.asarray(v, dtype=np.float64), q))
 
 
 def group_traffic(workload, group):
@@ -176,26 +312,6 @@ def read_traffic(key):
         return None
 
 
-def time_decode(zf, torch, cols, outs, steps, warmup, **plan_kw):
-    """Average ms of zf_decompress_async over `steps` on the current stream."""
-    plan = zf.Plan(cols, device=0, **plan_kw)
-    img = zf.upload_image(plan, cols)
-    stream = torch.cuda.current_stream()
-    for _ in range(warmup):
-        plan.decompress_async(img, img.numel(), outs)
-    torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record(stream)
-    for _ in range(steps):
-        plan.decompress_async(img, img.numel(), outs)
-    b.record(stream)
-    torch.cuda.synchronize()
-    plan.sync()
-    ms = a.elapsed_time(b) / steps
-    del img
-    return ms
-
-
 # ------------------------------------------------------------------ main
 def main():
     ap = argparse.ArgumentParser()
@@ -208,9 +324,11 @@ def main():
     ap.add_argument("--text-codec", default="sdict", choices=["sdict", "lz77"],
                     help="codec of the fact table's comment column")
     ap.add_argument("--no-e2e", action="store_true")
-    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the one-core oracle sample")
+    ap.add_argument("--no-verify", action="store_true",
+                    help="skip the whole-output oracle check (and the all-core oracle timing)")
     ap.add_argument("--persistent", type=int, default=0)
-    ap.add_argument("--e2e-reps", type=int, default=3)
+    ap.add_argument("--e2e-reps", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: decoding needs no exchange between GPUs, and a "
@@ -224,6 +342,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     zf.lib()
+    threads = host_threads()
     t0 = time.time()
     if args.workload == "fact":
         cols, xs, names, desc = fact_table(args.rows or g.FACT_ROWS, args.text_codec)
@@ -236,6 +355,7 @@ def main():
     comp = sum(c.host_pointer()[1] for c in cols)
     log(f"data ready in {time.time() - t0:.1f}s: plain {plain / 2**30:.2f} GiB, compressed "
         f"{comp / 2**30:.2f} GiB (ratio {plain / comp:.2f}x)")
+    manifest = sha256_manifest(xs, names, threads)
 
     plan = zf.Plan(cols, device=0, persistent=bool(args.persistent))
     img = zf.upload_image(plan, cols)
@@ -256,73 +376,114 @@ def main():
         assert np.array_equal(got, want), "decode mismatch"
     log("sampled check against the input: ok")
 
-    # timed steps: decode of the whole table from HBM
+    # the whole output against the oracle's decode of the same bytes
+    verify, ref, cpu_all = None, None, None
+    if not args.no_verify:
+        ref, secs = oracle_full_decode(cols, threads)
+        cpu_all = {"value": round(plain / secs / 1e9, 4), "unit": "GB/s", "cores": threads,
+                   "seconds": round(secs, 2)}
+        log(f"oracle, all chunks on {threads} host threads: {secs:.2f} s ({plain / secs / 1e9:.2f} GB/s)")
+        res = compare_outputs(torch, outs, ref, threads)
+        inputs_ok = [np.array_equal(rf, np.ascontiguousarray(x).view(np.uint8).reshape(-1))
+                     for rf, x in zip(ref, xs)]
+        verify = {"image_decode_vs_oracle": "ok" if all(v["ok"] for v in res) else
+                  {n: v for n, v in zip(names, res) if not v["ok"]},
+                  "oracle_vs_input": "ok" if all(inputs_ok) else
+                  [n for n, ok in zip(names, inputs_ok) if not ok],
+                  "bytes_compared": plain}
+        log(f"whole output vs oracle: {verify['image_decode_vs_oracle']}; oracle vs input: "
+            f"{verify['oracle_vs_input']}")
+
+    # timed steps: decode of the whole table from HBM, an event per step
     for _ in range(args.warmup):
         plan.decompress_async(img, img.numel(), outs)
     torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(args.steps):
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    evs[0].record(stream)
+    for k in range(args.steps):
         plan.decompress_async(img, img.numel(), outs)
-    ev1.record(stream)
+        evs[k + 1].record(stream)
     torch.cuda.synchronize()
     plan.sync()
-    ms = ev0.elapsed_time(ev1) / args.steps
-    value = plain / (ms * 1e-3) / 1e9
+    step_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]
+    ms = evs[0].elapsed_time(evs[-1]) / args.steps
     alg_bytes = comp + plain  # every compressed byte read once, every plain byte written once
     hbm_gbps = alg_bytes / (ms * 1e-3) / 1e9
-    log(f"decode from HBM: {ms:.3f} ms/step, {value:.1f} GB/s plain, {hbm_gbps:.1f} GB/s HBM")
+    plain_gbps = plain / (ms * 1e-3) / 1e9
+    log(f"decode from HBM: {ms:.3f} ms/step (median {pct(step_ms, 50):.3f}), {hbm_gbps:.1f} GB/s HBM, "
+        f"{plain_gbps:.1f} GB/s plain")
 
-    # per-kernel breakdown: each codec's columns decoded alone (one kernel
-    # kind per plan), to find the dominant kernel and its roofline
-    kinds = {}
+    # kernel times inside the step: events before and after each kind's launch
+    prof_steps = max(5, args.steps // 2)
+    plan.profile(True)
+    per = {}
+    for _ in range(prof_steps):
+        plan.decompress_async(img, img.numel(), outs)
+        for k, v in plan.kind_ms().items():
+            per.setdefault(k, []).append(v)
+    plan.profile(False)
+    plan.sync()
     groups = {}
-    for c, o in zip(cols, outs):
+    for c in cols:
         key = zf.kind_of_column(c)
         if zf.first_codec(c) == zf.SDICT_ANS:
             key = "ANS+SDICT"  # two ordered launches: the ANS stage, then String-dictionary
-        groups.setdefault(key, ([], []))
-        groups[key][0].append(c)
-        groups[key][1].append(o)
-    for key, (gc, go) in groups.items():
-        kms = time_decode(zf, torch, gc, go, max(3, args.steps // 2), 1,
-                          persistent=bool(args.persistent))
-        kb = sum(c.host_pointer()[1] + c.plain_bytes for c in gc)
-        kinds[key] = {"ms": round(kms, 4), "algorithmic_bytes": kb,
-                      "GBps": round(kb / (kms * 1e-3) / 1e9, 1)}
-        log(f"kernel {key:8s}: {kms:.3f} ms, {kb / (kms * 1e-3) / 1e9:.1f} GB/s of algorithmic bytes")
-    dom = max(kinds, key=lambda k: kinds[k]["ms"])
+        if args.persistent:
+            key = "PERSISTENT"
+        groups[key] = groups.get(key, 0) + c.host_pointer()[1] + c.plain_bytes
+    kinds = {}
+    for key, kb in groups.items():
+        series = [sum(v) for v in zip(*[per[k] for k in key.split("+")])]
+        med = pct(series, 50)
+        kinds[key] = {"ms_median": round(med, 4), "ms_p10": round(pct(series, 10), 4),
+                      "ms_p90": round(pct(series, 90), 4), "algorithmic_bytes": kb,
+                      "GBps": round(kb / (med * 1e-3) / 1e9, 1),
+                      "frac_of_hbm_peak": round(kb / (med * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+        log(f"kernel {key:8s} in the step: {med:.3f} ms, {kinds[key]['GBps']:.1f} GB/s of algorithmic bytes")
+    dom = max(kinds, key=lambda k: kinds[k]["ms_median"])
 
     result = {
-        "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1,
+        "metric": METRIC, "value": round(hbm_gbps, 2), "unit": "GB/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.workload == "f2i" else "u32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.workload == "f2i" else "u32",
         "data": "synthetic",
         "config": {"workload": desc, "plain_bytes": plain, "comp_bytes": comp,
                    "ratio": round(plain / comp, 3),
                    "chunks": sum(c.n_chunks for c in cols),
                    "launch": "persistent" if args.persistent else "per-kind"},
-        "decode_hbm_GBps": round(hbm_gbps, 1),
+        "value_is": "decode HBM GB/s = (compressed + plain bytes) / step time, inputs in HBM",
+        "decode_plain_GBps": round(plain_gbps, 2),
+        "step_ms": {"median": round(pct(step_ms, 50), 4), "p10": round(pct(step_ms, 10), 4),
+                    "p90": round(pct(step_ms, 90), 4)},
         "roofline": {"bound": "hbm", "achieved": kinds[dom]["GBps"], "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": round(kinds[dom]["GBps"] / HBM_PEAK_GBPS, 4),
+                     "unit": "GB/s", "frac": kinds[dom]["frac_of_hbm_peak"],
                      "traffic": group_traffic(args.workload, dom),
                      "kernel": {"LZ77": "k_decode_lz (LZ77)", "ANS": "k_decode_ans",
-                                "ANS+SDICT": "k_decode_ans then k_decode_kind<SDICT>"}.get(dom, f"k_decode_kind<{dom}>"),
+                                "ANS+SDICT": "k_decode_ans then k_decode_kind<SDICT>",
+                                "PERSISTENT": "k_decode_persistent"}.get(dom, f"k_decode_kind<{dom}>"),
                      "algorithmic_bytes_per_launch": kinds[dom]["algorithmic_bytes"],
-                     "avg_launch_ms": kinds[dom]["ms"]},
+                     "avg_launch_ms": kinds[dom]["ms_median"],
+                     "timing": f"median of {prof_steps} steps, HIP events around the launch inside the step"},
         "kernels": kinds,
     }
+    if verify is not None:
+        result["verify"] = verify
 
     if not args.no_e2e:
         # PCIe end to end: pinned host -> staging slots -> decode, pipelined
         walls = []
         for rep in range(args.e2e_reps):
             plan.transfer_and_decompress(outs, timing=True)
-            t = plan.sync()
-            walls.append(t)
+            walls.append(plan.sync())
         walls.sort(key=lambda t: t["wall_ms"])
         tm = walls[len(walls) // 2]
         eff = plain / (tm["wall_ms"] * 1e-3) / 1e9
+        if ref is not None:
+            res = compare_outputs(torch, outs, ref, threads)
+            result["verify"]["staged_decode_vs_oracle"] = "ok" if all(v["ok"] for v in res) else \
+                {n: v for n, v in zip(names, res) if not v["ok"]}
+            log(f"staged output vs oracle: {result['verify']['staged_decode_vs_oracle']}")
         # raw copy of the plain bytes from pinned memory, 256 MiB pieces
         hosts = [torch.from_numpy(np.ascontiguousarray(x).view(np.uint8).reshape(-1)).pin_memory()
                  for x in xs]
@@ -338,24 +499,42 @@ def main():
             b.record(stream)
             torch.cuda.synchronize()
             raws.append(a.elapsed_time(b))
-        raw_ms = sorted(raws)[len(raws) // 2]
+        raw_ms = pct(raws, 50)
         raw = plain / (raw_ms * 1e-3) / 1e9
         del hosts
+        wall = [t["wall_ms"] for t in walls]
         result["e2e"] = {
             "effective_GBps": round(eff, 2), "raw_copy_GBps": round(raw, 2),
             "vs_raw_copy": round(eff / raw, 3), "wall_ms": round(tm["wall_ms"], 2),
+            "wall_ms_p10": round(pct(wall, 10), 2), "wall_ms_p90": round(pct(wall, 90), 2),
             "h2d_ms": round(tm["h2d_ms"], 2), "decode_ms": round(tm["decode_ms"], 2),
             "pcie_GBps_compressed": round(comp / (tm["h2d_ms"] * 1e-3) / 1e9, 2),
-            "pcie_frac_of_63": round(comp / (tm["h2d_ms"] * 1e-3) / 1e9 / PCIE_PEAK_GBPS, 3)}
+            "pcie_frac_of_63": round(comp / (tm["h2d_ms"] * 1e-3) / 1e9 / PCIE_PEAK_GBPS, 3),
+            "reps": args.e2e_reps}
         log(f"end to end: {eff:.1f} GB/s effective vs raw copy {raw:.1f} GB/s "
             f"(x{eff / raw:.2f}); wall {tm['wall_ms']:.1f} ms, h2d {tm['h2d_ms']:.1f} ms, "
             f"decode {tm['decode_ms']:.1f} ms")
 
     if not args.no_cpu:
-        log("CPU oracle baseline ...")
-        result["cpu_baseline"] = cpu_baseline(cols)
-        log(f"oracle: {result['cpu_baseline']['value']} GB/s")
+        log("CPU oracle baseline, one core ...")
+        one = cpu_single_thread(cols)
+        log(f"oracle on one core: {one['value']} GB/s")
+        if cpu_all is not None:
+            result["cpu_baseline"] = {
+                "value": cpu_all["value"], "unit": "GB/s", "cores": threads, "kind": "oracle",
+                "sample": f"every chunk of the workload ({plain / 2**30:.2f} GiB plain) decoded from host "
+                          f"memory by the single-threaded oracle, chunk ranges spread over {threads} "
+                          f"host threads, in {cpu_all['seconds']} s; rate = plain bytes / wall time",
+                "one_core": one}
+        else:
+            result["cpu_baseline"] = dict(one, kind="oracle")
+    result["host"] = host_description(threads)
+    result["gpu"] = gpu_description(torch)
+    result["inputs_sha256"] = manifest
     print(json.dumps(result), flush=True)
+    if verify is not None and any(v != "ok" for k, v in result["verify"].items() if k != "bytes_compared"):
+        log("output mismatch against the oracle")
+        sys.exit(1)
 
 
 if __name__ == "__main__":

@@ -325,6 +325,21 @@ typedef struct {
 zf_status zf_transfer_and_decompress(zf_plan_t *plan, void *const *d_out, zf_stream_t stream,
                                      zf_timing *timing);
 
+/*
+ * Kernel times inside a decode (measurement, Sec. 5.1): after
+ * zf_plan_profile(plan, 1), every zf_decompress_async of the plan records a
+ * HIP event on its stream before and after each kernel kind's launch (the
+ * persistent kernel as a whole).  zf_plan_kind_ms then fills
+ * ms[ZF_KIND_COUNT + 1] (host array owned by the caller) with the durations,
+ * in ms, of the most recent such call: entry k for kind k, entry
+ * ZF_KIND_COUNT for the persistent kernel, -1 where nothing was launched; it
+ * waits for those events.  zf_plan_profile(plan, 0) stops recording.
+ * Errors: ZF_E_INVALID (null pointer), ZF_E_STATE (no profiled decode since
+ * profiling was switched on), ZF_E_HIP.
+ */
+zf_status zf_plan_profile(zf_plan_t *plan, int32_t on);
+zf_status zf_plan_kind_ms(zf_plan_t *plan, double *ms);
+
 /* Wait for the plan's work on `stream`; read the device error word:
  * ZF_E_CORRUPT if any kernel found a corrupt stream (sticky until
  * zf_plan_clear_error). */
@@ -358,6 +373,23 @@ uint64_t zf_mlp_grad_work_bytes(uint32_t n);
 zf_status zf_mlp_grad(const float *d_params, const float *d_x, const int32_t *d_k, const float *d_t,
                       uint32_t n, float *d_grad, float *d_loss, void *d_work, uint64_t work_bytes,
                       zf_stream_t stream);
+/*
+ * zf_mlp_grad without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels and results (bit for bit) as
+ * zf_mlp_grad; the per-workgroup partial gradients go to a static device
+ * array of the library (ceil(ZF_MLP_STATIC_MAX_N / 64) x 7833 floats, about
+ * 8 MB, held on each device the call runs on until the process ends).  The
+ * call allocates nothing; it runs on the current device (the stream must
+ * belong to it).  n > ZF_MLP_STATIC_MAX_N: ZF_E_UNSUPPORTED; null pointers
+ * or n == 0: ZF_E_INVALID.  Every call on one device shares that array, so
+ * calls that overlap on one device (concurrent streams, threads) race; calls
+ * ordered on one stream do not.
+ */
+#define ZF_MLP_STATIC_MAX_N 16384
+zf_status zf_mlp_grad_noalloc(const float *d_params, const float *d_x, const int32_t *d_k,
+                              const float *d_t, uint32_t n, float *d_grad, float *d_loss,
+                              zf_stream_t stream);
 /* One Adam step (step counts from 1) on the parameters in place; d_m and
  * d_v are the moment estimates (ZF_MLP_PARAMS floats each, zero at start). */
 zf_status zf_mlp_adam(float *d_params, const float *d_grad, float *d_m, float *d_v, uint32_t step,

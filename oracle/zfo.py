@@ -168,6 +168,19 @@ def decode_chunks(blob, first, count):
     return out
 
 
+def decode_chunks_into(blob, first, count, out, byte_off, nbytes):
+    """Decode chunks [first, first + count) of a column blob (contiguous
+    np.uint8) into the bytes of numpy array `out` from byte `byte_off`;
+    nbytes = the chunks' plain bytes.  For running many chunk ranges at once
+    on host threads (the C call holds no Python lock)."""
+    assert blob.dtype == np.uint8 and blob.flags.c_contiguous and out.flags.c_contiguous
+    assert 0 <= byte_off and byte_off + nbytes <= out.nbytes
+    rc = lib().zfo_decode_chunks(ctypes.c_void_p(blob.ctypes.data), blob.size, first, count,
+                                 ctypes.c_void_p(out.ctypes.data + byte_off), nbytes)
+    if rc:
+        raise OracleError(rc, "decode_chunks")
+
+
 def decode_stream(codec, dtype, stream, n_elems, dictionary=None, dict_count=0):
     """Decode one raw codec stream (no container).  Returns (status, output)."""
     s, sp = _buf(_as_bytes(stream) if len(stream) else np.zeros(1, np.uint8))

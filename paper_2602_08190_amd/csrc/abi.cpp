@@ -17,6 +17,8 @@ void decompress_async(zf_plan_t *P, const void *d_comp, uint64_t comp_bytes, voi
 void transfer_and_decompress(zf_plan_t *P, void *const *d_out, hipStream_t st, zf_timing *timing);
 void sync_plan(zf_plan_t *P, hipStream_t st);
 void clear_error(zf_plan_t *P);
+void set_profile(zf_plan_t *P, bool on);
+void kind_ms(zf_plan_t *P, double *ms);
 }  // namespace zf
 
 using namespace zf;
@@ -153,6 +155,22 @@ zf_status zf_sync(zf_plan_t *plan, zf_stream_t stream) {
     return guard([&] {
         ZF_REQUIRE(plan, ZF_E_INVALID, "null plan");
         sync_plan(plan, static_cast<hipStream_t>(stream));
+    });
+}
+
+zf_status zf_plan_profile(zf_plan_t *plan, int32_t on) {
+    return guard([&] {
+        ZF_REQUIRE(plan, ZF_E_INVALID, "null plan");
+        set_profile(plan, on != 0);
+    });
+}
+
+zf_status zf_plan_kind_ms(zf_plan_t *plan, double *ms) {
+    return guard([&] {
+        ZF_REQUIRE(plan && ms, ZF_E_INVALID, "null pointer");
+        double t[ZF_KIND_COUNT + 1];
+        kind_ms(plan, t);
+        std::copy(t, t + ZF_KIND_COUNT + 1, ms);
     });
 }
 

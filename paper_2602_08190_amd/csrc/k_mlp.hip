@@ -14,6 +14,7 @@
 
 #include <cstdint>
 
+#include <mutex>
 #include <string>
 
 #include "zf.h"
@@ -195,6 +196,39 @@ __global__ void k_mlp_adam(float *P, const float *G, float *M, float *V, float l
     P[p] -= lr * (m * c1) / (sqrtf(v * c2) + eps);
 }
 
+// Allocation-free gradient (zf_mlp_grad_noalloc): the per-workgroup partials
+// live in this file-scope device array instead of a caller workspace.  Every
+// partial a launch reads is written by the same launch first, so nothing has
+// to be cleared between calls.  In host code `scratch` only names the symbol;
+// its device address comes from hipGetSymbolAddress, once per device.
+constexpr uint32_t kStaticBlocks = (ZF_MLP_STATIC_MAX_N + TS - 1) / TS;
+static __device__ __align__(256) float scratch[uint64_t(kStaticBlocks) * (NP + 1)];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static float *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call per device).
+static zf_status static_scratch(float **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_with(ZF_E_HIP, "hipGetDevice failed");
+    if (dev < 0 || dev >= kMaxDevices) return fail_with(ZF_E_UNSUPPORTED, "device index above 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_last_error(std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+            return ZF_E_HIP;
+        }
+        g_scratch_ptr[dev] = static_cast<float *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return ZF_OK;
+}
+
 }  // namespace zf
 
 using namespace zf;
@@ -223,6 +257,27 @@ zf_status zf_mlp_grad(const float *d_params, const float *d_x, const int32_t *d_
     const hipStream_t st = static_cast<hipStream_t>(stream);
     const uint32_t nb = (n + TS - 1) / TS;
     float *work = static_cast<float *>(d_work);
+    hipLaunchKernelGGL(k_mlp_grad, dim3(nb), dim3(256), 0, st, d_params, d_x, d_k, d_t, n, work);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((NP + 1 + 255) / 256), dim3(256), 0, st, work, nb, d_grad,
+                       d_loss);
+    return launched();
+}
+
+zf_status zf_mlp_grad_noalloc(const float *d_params, const float *d_x, const int32_t *d_k,
+                              const float *d_t, uint32_t n, float *d_grad, float *d_loss,
+                              zf_stream_t stream) {
+    if (!n || !d_params || !d_x || !d_k || !d_t || !d_grad || !d_loss)
+        return fail_with(ZF_E_INVALID, "null pointer or empty batch");
+    if (n > ZF_MLP_STATIC_MAX_N) {
+        set_last_error("zf_mlp_grad_noalloc: " + std::to_string(n) + " samples exceed the static scratch "
+                       "limit of " + std::to_string(ZF_MLP_STATIC_MAX_N) + " (use zf_mlp_grad with a workspace)");
+        return ZF_E_UNSUPPORTED;
+    }
+    float *work = nullptr;
+    const zf_status st0 = static_scratch(&work);
+    if (st0 != ZF_OK) return st0;
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const uint32_t nb = (n + TS - 1) / TS;
     hipLaunchKernelGGL(k_mlp_grad, dim3(nb), dim3(256), 0, st, d_params, d_x, d_k, d_t, n, work);
     hipLaunchKernelGGL(k_mlp_reduce, dim3((NP + 1 + 255) / 256), dim3(256), 0, st, work, nb, d_grad,
                        d_loss);

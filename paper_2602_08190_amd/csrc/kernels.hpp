@@ -1361,6 +1361,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     unit_lz<BLK>(A, A.chunks[A.tiles[u].chunk], lz_smem + (threadIdx.x / 64) * 64 * BLK);
 }
 void launch_lz(const LaunchArgs &A, uint32_t waves, uint32_t blk, hipStream_t st);
+hipError_t launch_decode(const LaunchArgs &A, uint32_t persistent_waves, const uint32_t *wpb,
+                         uint32_t lz_blk, hipStream_t st, KindEvents *ev);
 
 void launch_ans(const LaunchArgs &A, uint32_t waves, hipStream_t st);
 

@@ -380,6 +380,9 @@ void release_plan(zf_plan_t *P) {
     kill(p.ev_dec1);
     for (auto e : {p.ev_start, p.ev_end, p.ev_dict})
         if (e) (void)hipEventDestroy(e);
+    for (uint32_t k = 0; k <= K_COUNT; k++)
+        for (auto e : {p.kind_ev.e0[k], p.kind_ev.e1[k]})
+            if (e) (void)hipEventDestroy(e);
     if (p.copy_stream) (void)hipStreamDestroy(p.copy_stream);
     for (auto sp : p.d_slots)
         if (sp) (void)hipFree(sp);

@@ -9,7 +9,7 @@ namespace zf {
 
 // lz_blk: output bytes per block of the per-kind LZ77 kernel (4, 8 or 16).
 hipError_t launch_decode(const LaunchArgs &A, uint32_t persistent_waves, const uint32_t *waves_per_block,
-                         uint32_t lz_blk, hipStream_t st);
+                         uint32_t lz_blk, hipStream_t st, KindEvents *ev = nullptr);
 hipError_t launch_set_out_tab(uint8_t **d_tab, uint8_t *const *ptrs, uint32_t n, uint8_t *scratch, hipStream_t st);
 
 struct CopyOp {
@@ -79,6 +79,9 @@ struct zf_plan {
     hipEvent_t ev_start = nullptr, ev_end = nullptr, ev_dict = nullptr;
     zf_timing *pending_timing = nullptr;
     bool timing_valid = false;
+    // per-kind events of profiled image decodes (zf_plan_profile)
+    bool profile = false, kinds_recorded = false;
+    zf::KindEvents kind_ev;
 
     ~zf_plan() { zf::release_plan(this); }
 };

@@ -25,7 +25,9 @@ void decompress_async(zf_plan_t *P, const void *d_comp, uint64_t comp_bytes, voi
     LaunchArgs A = P->image_args;
     A.comp = static_cast<const uint8_t *>(d_comp);
     A.dict = static_cast<const uint8_t *>(d_comp);
-    ZF_HIP(launch_decode(A, P->persistent_waves, P->waves_per_block, P->lz_blk, st));
+    ZF_HIP(launch_decode(A, P->persistent_waves, P->waves_per_block, P->lz_blk, st,
+                         P->profile ? &P->kind_ev : nullptr));
+    if (P->profile) P->kinds_recorded = true;
     P->timing_valid = false;
 }
 
@@ -84,6 +86,29 @@ void sync_plan(zf_plan_t *P, hipStream_t st) {
     uint32_t err = 0;
     ZF_HIP(hipMemcpy(&err, P->d_err, sizeof err, hipMemcpyDeviceToHost));
     ZF_REQUIRE(err == 0, ZF_E_CORRUPT, "a kernel found a corrupt stream (error word 0x%x)", err);
+}
+
+void set_profile(zf_plan_t *P, bool on) {
+    if (on && !P->kind_ev.e0[0]) {
+        for (uint32_t k = 0; k <= K_COUNT; k++) {
+            ZF_HIP(hipEventCreate(&P->kind_ev.e0[k]));
+            ZF_HIP(hipEventCreate(&P->kind_ev.e1[k]));
+        }
+    }
+    P->profile = on;
+    P->kinds_recorded = false;
+}
+
+void kind_ms(zf_plan_t *P, double *ms) {
+    ZF_REQUIRE(P->kinds_recorded, ZF_E_STATE, "no profiled zf_decompress_async since profiling was switched on");
+    for (uint32_t k = 0; k <= K_COUNT; k++) {
+        ms[k] = -1.0;
+        if (!P->kind_ev.used[k]) continue;
+        ZF_HIP(hipEventSynchronize(P->kind_ev.e1[k]));
+        float t = 0;
+        ZF_HIP(hipEventElapsedTime(&t, P->kind_ev.e0[k], P->kind_ev.e1[k]));
+        ms[k] = t;
+    }
 }
 
 void clear_error(zf_plan_t *P) { (void)hipMemset(P->d_err, 0, sizeof(uint32_t)); }

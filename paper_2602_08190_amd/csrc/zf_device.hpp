@@ -1,6 +1,7 @@
 // Device-side work tables: written by the host planner, read by the kernels.
 // Plain structs only; the same definitions compile on both sides.
 #pragma once
+#include <hip/hip_runtime_api.h>
 #include <stdint.h>
 
 namespace zf {
@@ -81,6 +82,13 @@ struct LaunchArgs {
     uint32_t *err;                // device error word
     uint32_t *counter;            // persistent-kernel queue head (zeroed per launch)
     uint32_t kind_begin[K_COUNT + 1];
+};
+
+// Host side: events recorded around each kind's launch of a profiled decode
+// (index K_COUNT: the persistent kernel).
+struct KindEvents {
+    hipEvent_t e0[K_COUNT + 1] = {}, e1[K_COUNT + 1] = {};
+    bool used[K_COUNT + 1] = {};
 };
 
 }  // namespace zf

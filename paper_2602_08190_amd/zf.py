@@ -103,9 +103,12 @@ SIGNATURES = {
                                           ctypes.POINTER(Timing)]),
     "zf_sync": (_i32, [_vp, _vp]),
     "zf_plan_clear_error": (None, [_vp]),
+    "zf_plan_profile": (_i32, [_vp, _i32]),
+    "zf_plan_kind_ms": (_i32, [_vp, _vp]),
     "zf_mlp_forward": (_i32, [_vp, _vp, _u32, _vp, _vp]),
     "zf_mlp_grad_work_bytes": (_u64, [_u32]),
     "zf_mlp_grad": (_i32, [_vp, _vp, _vp, _vp, _u32, _vp, _vp, _vp, _u64, _vp]),
+    "zf_mlp_grad_noalloc": (_i32, [_vp, _vp, _vp, _vp, _u32, _vp, _vp, _vp]),
     "zf_mlp_adam": (_i32, [_vp, _vp, _vp, _vp, _u32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                            ctypes.c_float, _vp]),
     "zf_status_str": (ctypes.c_char_p, [_i32]),
@@ -309,6 +312,17 @@ class Plan:
     def image_offset(self, c):
         return lib().zf_plan_image_offset(self._h, c)
 
+    def profile(self, on=True):
+        """Record per-kind kernel times in zf_decompress_async (zf_plan_profile)."""
+        _check(lib().zf_plan_profile(self._h, 1 if on else 0))
+
+    def kind_ms(self):
+        """{kind name or "PERSISTENT": ms} of the most recent profiled decode."""
+        ms = np.zeros(len(KINDS) + 1, np.float64)
+        _check(lib().zf_plan_kind_ms(self._h, ms.ctypes.data))
+        names = KINDS + ["PERSISTENT"]
+        return {names[k]: float(ms[k]) for k in range(len(names)) if ms[k] >= 0}
+
     def batches(self):
         """The plan's batches in execution order (zf_plan_batch_info)."""
         out = []
@@ -424,6 +438,14 @@ def mlp_forward(params, x, y, stream=None):
 
 def mlp_grad_work_bytes(n):
     return lib().zf_mlp_grad_work_bytes(n)
+
+
+MLP_STATIC_MAX_N = 16384
+
+
+def mlp_grad_noalloc(params, x, k, t, grad, loss, stream=None):
+    _check(lib().zf_mlp_grad_noalloc(_ptr(params), _ptr(x), _ptr(k), _ptr(t), x.shape[0], _ptr(grad),
+                                     _ptr(loss), _stream(stream)))
 
 
 def mlp_grad(params, x, k, t, grad, loss, work, stream=None):
