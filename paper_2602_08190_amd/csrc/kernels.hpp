@@ -1092,12 +1092,24 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, uint32_t *row) {
 constexpr uint32_t kSdBlk = 4;
 ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, uint32_t *row) {
     const uint8_t *s = A.comp + ck.comp_off;
-    const uint32_t lane = lane_id(), plain = ck.n_elems;
+    const uint32_t lane = lane_id(), plain = ck.n_elems, clen = ck.comp_len;
     uint8_t *out = A.out_tab[ck.col] + ck.out_off;
+    if (clen < 32) {
+        flag(A.err, ERR_CORRUPT);
+        return;
+    }
     const uint32_t nt = first32(ld32u(s)), ne = first32(ld32u(s + 4)), w = first32(ld32u(s + 8));
     const uint32_t ng = first32(ld32u(s + 12)), eo = first32(ld32u(s + 16));
-    const uint32_t bo = first32(ld32u(s + 20)), co = first32(ld32u(s + 24));
-    if (t.b > ng || t.a >= t.b) {
+    const uint32_t bo = first32(ld32u(s + 20)), co = first32(ld32u(s + 24)), nb = first32(ld32u(s + 28));
+    const uint64_t ncw = (uint64_t(nt) * w + 31) / 32;
+    // every field used below is checked against the stream's size first:
+    // entries, entry bytes (with their 4 bytes of padding) and codes in
+    // order inside the chunk, so no view or load leaves it
+    const bool hdr_ok = ne >= 1 && w <= 32 && ng == (uint64_t(nt) + 63) / 64 && (eo & 3u) == 0 &&
+                        eo >= 32ull + 4ull * ng && uint64_t(eo) + 4ull * ne <= bo &&
+                        uint64_t(bo) + nb + 4 <= co && co <= clen &&
+                        (ck.codec == C_SDICT_ANS || uint64_t(co) + 4 * ncw <= clen);
+    if (!hdr_ok || t.b > ng || t.a >= t.b) {
         flag(A.err, ERR_CORRUPT);
         return;
     }
@@ -1106,7 +1118,6 @@ ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, 
     // earlier launch (the codes checks below hold for them all the same)
     const uint32_t *codes = reinterpret_cast<const uint32_t *>(
         ck.codec == C_SDICT_ANS ? A.out_tab[kScratchCol] + ck.aux_off : s + co);
-    const uint64_t ncw = (uint64_t(nt) * w + 31) / 32;
     // the entry bytes run up to the codes (at least 4 bytes of padding)
     const __amdgpu_buffer_rsrc_t rs_out = __builtin_amdgcn_make_buffer_rsrc(out, 0, int(plain), 0x00020000);
     const __amdgpu_buffer_rsrc_t rs_ent =
@@ -1126,10 +1137,12 @@ ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, 
         const bool bad_code = act && code >= ne;
         const uint32_t e = (act && !bad_code) ? ents[code] : 0u;
         const uint32_t len = e >> 24, eoff = e & 0xFFFFFFu;
+        // an entry's bytes (and the dword read at each) lie in the entry bytes
+        const bool bad_ent = act && (len == 0 || len > kSdMaxToken || uint64_t(eoff) + len > nb);
         const uint32_t incl = scan_add32(len), total = rl32(incl, 63);
         const uint32_t pos = first32(ld32u(s + 32 + 4 * g));
         const uint32_t end = g + 1 < ng ? first32(ld32u(s + 32 + 4 * (g + 1))) : plain;
-        if (any(bad_code) || uint64_t(pos) + total != end) {
+        if (any(bad_code || bad_ent) || uint64_t(pos) + total != end || end > plain) {
             flag(A.err, ERR_CORRUPT);
             return;
         }
@@ -1157,16 +1170,29 @@ ZF_DEV void unit_ans(const LaunchArgs &A, const ChunkDesc &ck, uint32_t *lds) {
                         : ck.dtype == D_FIXED16 ? 16 : 1;
     const uint32_t n = ck.n_elems * es;
     uint8_t *out = A.out_tab[ck.col] + ck.out_off;
-    // the host checked: comp_len = 1040 + 2 nw, n matches, frequencies sum to
-    // M, word offsets non-decreasing and within nw
+    // sizes, the frequency total and every coder's word range are checked
+    // here before any of them is used (the host checked them too)
+    if (ck.comp_len < kAnsHdr) {
+        flag(A.err, ERR_CORRUPT);
+        return;
+    }
     const uint32_t nw = first32(ld32u(s + 4));
+    if (first32(ld32u(s)) != n || uint64_t(kAnsHdr) + 2ull * nw > ck.comp_len) {
+        flag(A.err, ERR_CORRUPT);
+        return;
+    }
     uint8_t *sym = reinterpret_cast<uint8_t *>(lds);
     uint32_t *fc = lds + kAnsM / 4;
     // model: lane l owns bytes 4l .. 4l + 3
     const uint32_t f2 = ld32u(s + 16 + 8 * lane), f3 = ld32u(s + 20 + 8 * lane);
     const uint32_t f[4] = {f2 & 0xFFFFu, f2 >> 16, f3 & 0xFFFFu, f3 >> 16};
     const uint32_t tot = f[0] + f[1] + f[2] + f[3];
-    uint32_t c = scan_add32(tot) - tot;  // cum of byte 4l
+    const uint32_t cincl = scan_add32(tot);
+    if (rl32(cincl, 63) != kAnsM) {  // the slot walk below needs the exact total
+        flag(A.err, ERR_CORRUPT);
+        return;
+    }
+    uint32_t c = cincl - tot;  // cum of byte 4l
 #pragma unroll
     for (uint32_t k = 0; k < 4; k++) {
         fc[4 * lane + k] = f[k] | (c << 16);
@@ -1202,6 +1228,10 @@ ZF_DEV void unit_ans(const LaunchArgs &A, const ChunkDesc &ck, uint32_t *lds) {
     uint32_t x = ld32u(s + 528 + 4 * lane);
     uint32_t w = ld32u(s + 784 + 4 * lane);
     const uint32_t wend = lane + 1 < kAnsLanes ? ld32u(s + 788 + 4 * lane) : nw;
+    if (any(w > wend || wend > nw)) {
+        flag(A.err, ERR_CORRUPT);
+        return;
+    }
     // words at, at+1, at+2, at+3 through a bounds-checked view of the chunk's
     // words (0 past them): no branch, so the loads stay in flight until used.
     // A coder never consumes past its own range in a valid stream; reading a

@@ -590,3 +590,66 @@ def test_device_detects_corrupt_streams():
     p = c["comp_off"]
     b[p:p + 8] = np.frombuffer(np.int64(2).tobytes(), np.uint8)   # ref 2 + field up to 3 > 3
     _expect_corrupt([zf.Column.from_bytes(b)])
+
+
+def test_device_checks_headers_that_differ_from_the_plan():
+    """The plan is built from valid columns; the device image then holds
+    String-dictionary and ANS headers that differ from what the host
+    validated.  The kernels check every header field against the stream's
+    size before using it, report ZF_E_CORRUPT, and a clean image decodes
+    right afterwards."""
+    log("headers differ from the plan")
+    T = torch()
+    text = g.text_column(300000, 4)
+    flags = g.returnflag_column(200000, 0.25, 0.5, 11)
+    filler = g.for_bp_column(100000, 2)
+    cols = [zf.Column.compress(text, zf.SDICT_BP), zf.Column.compress(flags, zf.ANS),
+            zf.Column.compress(filler, zf.FOR_BP)]
+    plan = zf.Plan(cols, device=0)
+    img = zf.upload_image(plan, cols)
+    outs = zf.empty_outputs(cols)
+
+    def at(ci, field_off, chunk=0):
+        c = zo.chunks(cols[ci].bytes())[chunk]
+        return plan.image_offset(ci) + c["comp_off"] + field_off
+
+    def u32(off):
+        return int(np.frombuffer(img[off:off + 4].cpu().numpy().tobytes(), np.uint32)[0])
+
+    def patched(edits):
+        bad = img.clone()
+        for off, val in edits:
+            bad[off:off + 4] = T.from_numpy(np.frombuffer(np.uint32(val).tobytes(), np.uint8).copy()).cuda()
+        return bad
+
+    sd_bo, sd_co = u32(at(0, 20)), u32(at(0, 24))
+    an_nw = u32(at(1, 4))
+    an_w5, an_w6 = u32(at(1, 784 + 4 * 5)), u32(at(1, 784 + 4 * 6))
+    f_last = None
+    fr = img[at(1, 16):at(1, 16) + 512].cpu().numpy().view(np.uint16)
+    f_last = int(np.nonzero(fr)[0][-1])
+    cases = {
+        "codes offset 1 past the entry bytes (no padding)": [(at(0, 24), sd_bo + 1)],
+        "entry-byte count beyond the padding": [(at(0, 28), sd_co - sd_bo)],
+        "group count not ceil(tokens / 64)": [(at(0, 12), u32(at(0, 12)) + 1000)],
+        "no entries": [(at(0, 4), 0)],
+        "ANS word count beyond the stream": [(at(1, 4), an_nw + 100)],
+        "ANS coder word offsets out of order": [(at(1, 784 + 4 * 5), an_w6 + 1), (at(1, 784 + 4 * 6), an_w5)],
+    }
+    # a frequency total of M + 1 (last nonzero frequency raised by one)
+    fo = at(1, 16) + 2 * (f_last & ~1)
+    word = u32(fo)
+    word += 1 if f_last % 2 == 0 else 1 << 16
+    cases["ANS frequencies total M + 1"] = [(fo, word)]
+    for name, edits in cases.items():
+        log(" ", name)
+        bad = patched(edits)
+        plan.decompress_async(bad, bad.numel(), outs)
+        with pytest.raises(zf.ZfError) as e:
+            plan.sync()
+        assert e.value.status == zf.E_CORRUPT, name
+        plan.clear_error()
+    plan.decompress_async(img, img.numel(), outs)
+    plan.sync()
+    for x, o in zip([text, flags, filler], outs):
+        assert np.array_equal(o.cpu().numpy(), x)
