@@ -1000,21 +1000,20 @@ static int dec_sdict(const uint8_t *s, uint64_t comp_len, uint32_t plain_len, ui
  * comp_len = codes_off. */
 #define SD_ANS_PIECE 65536u
 
-static void enc_sdict_ans(buf_t *s, const uint8_t *x, uint32_t n) {
-    buf_t inner = {0};
-    enc_sdict(&inner, x, n);
-    if (inner.bad) { free(inner.p); s->bad = 1; return; }
-    uint32_t co = get32(inner.p + 24);
-    uint64_t ncb = inner.n - co;  /* index bytes */
+/* The ncb = inner->n - co packed index bytes at co of an inner stream
+ * replaced by the piece table and the pieces' ANS streams, as described
+ * above; the inner bytes before co are kept. */
+static void ans_pieces_encode(buf_t *s, const buf_t *inner, uint32_t co) {
+    uint64_t ncb = inner->n - co;  /* index bytes */
     uint32_t np = (uint32_t)((ncb + SD_ANS_PIECE - 1) / SD_ANS_PIECE);
     uint64_t at = co + (np ? 4 + 4 * (uint64_t)np : 0);
     buf_resize(s, at);
-    if (!s->bad) memcpy(s->p, inner.p, co);
+    if (!s->bad) memcpy(s->p, inner->p, co);
     if (np && !s->bad) put32(s->p + co, np);
     for (uint32_t k = 0; k < np && !s->bad; k++) {
         uint64_t lo = (uint64_t)k * SD_ANS_PIECE, hi = lo + SD_ANS_PIECE < ncb ? lo + SD_ANS_PIECE : ncb;
         buf_t a = {0};
-        enc_ans(&a, inner.p + co + lo, (uint32_t)(hi - lo));
+        enc_ans(&a, inner->p + co + lo, (uint32_t)(hi - lo));
         if (a.bad) { s->bad = 1; free(a.p); break; }
         uint64_t padded = (a.n + 3) & ~(uint64_t)3;
         buf_resize(s, at + padded);
@@ -1026,19 +1025,15 @@ static void enc_sdict_ans(buf_t *s, const uint8_t *x, uint32_t n) {
         free(a.p);
     }
     if (!s->bad) s->n = at;
-    free(inner.p);
 }
 
-static int dec_sdict_ans(const uint8_t *s, uint64_t comp_len, uint32_t plain_len, uint8_t *out) {
-    if (comp_len < 32) return ZFO_ECORRUPT;
-    uint32_t nt = get32(s), w = get32(s + 8), co = get32(s + 24);
-    if (w > 32 || co > comp_len) return ZFO_ECORRUPT;
-    uint64_t ncb = 4 * packed_words(nt, w);
+/* Inverse of ans_pieces_encode: inner (co + ncb bytes) = the stream's first
+ * co bytes followed by the decoded index bytes. */
+static int ans_pieces_decode(const uint8_t *s, uint64_t comp_len, uint32_t co, uint64_t ncb, uint8_t *inner) {
     uint32_t np = (uint32_t)((ncb + SD_ANS_PIECE - 1) / SD_ANS_PIECE);
+    if (co > comp_len) return ZFO_ECORRUPT;
     if (np == 0 && comp_len != co) return ZFO_ECORRUPT;
     if (np && (co + 4 + 4 * (uint64_t)np > comp_len || get32(s + co) != np)) return ZFO_ECORRUPT;
-    uint8_t *inner = (uint8_t *)malloc(co + ncb + 1);
-    if (!inner) return ZFO_ENOMEM;
     memcpy(inner, s, co);
     int rc = ZFO_OK;
     uint64_t base = co + 4 + 4 * (uint64_t)np, prev = 0;
@@ -1054,7 +1049,251 @@ static int dec_sdict_ans(const uint8_t *s, uint64_t comp_len, uint32_t plain_len
         }
         prev = end;
     }
+    return rc;
+}
+
+static void enc_sdict_ans(buf_t *s, const uint8_t *x, uint32_t n) {
+    buf_t inner = {0};
+    enc_sdict(&inner, x, n);
+    if (inner.bad) { free(inner.p); s->bad = 1; return; }
+    ans_pieces_encode(s, &inner, get32(inner.p + 24));
+    free(inner.p);
+}
+
+static int dec_sdict_ans(const uint8_t *s, uint64_t comp_len, uint32_t plain_len, uint8_t *out) {
+    if (comp_len < 32) return ZFO_ECORRUPT;
+    uint32_t nt = get32(s), w = get32(s + 8), co = get32(s + 24);
+    if (w > 32 || co > comp_len) return ZFO_ECORRUPT;
+    uint64_t ncb = 4 * packed_words(nt, w);
+    uint8_t *inner = (uint8_t *)malloc(co + ncb + 1);
+    if (!inner) return ZFO_ENOMEM;
+    int rc = ans_pieces_decode(s, comp_len, co, ncb, inner);
     if (rc == ZFO_OK) rc = dec_sdict(inner, co + ncb, plain_len, out);
+    free(inner);
+    return rc;
+}
+
+/* =============================== String-dictionary over a column dictionary
+ * The paper builds one word dictionary for a whole column (Sec. 5: the
+ * comment column's 1,878 distinct words, indices bit-packed) from the
+ * frequent byte sequences of the data (Sec. 2.1).  Here the dictionary lives
+ * in the container's dictionary area, shared by every chunk, and each chunk
+ * keeps only its bit-packed indices and group offsets, so chunks still decode
+ * on their own.  Tokens are cut as for SDICT_BP, except that a newline also
+ * ends a token: the byte column holds rows ended by '\n', a row is one value
+ * of the column, and no token spans two values.
+ * Column dictionary (dtype BYTES, at the container's dict_off, dict_count =
+ * number of entries):
+ *   u32 n_bytes, u32 0, u32 0, u32 0
+ *   u32 entry[dict_count] at 16: byte offset (bits 0-23) | length 1..64
+ *       (bits 24-31)
+ *   n_bytes entry bytes at 16 + 4*dict_count, then zero bytes up to
+ *   16 + 4*dict_count + align16(n_bytes + 4).
+ *   Entries: the distinct tokens of the column's SDICT_COL / SDICT_COL_ANS
+ *   chunks, by decreasing number of occurrences, ties by first appearance;
+ *   at most 2^24 entries and 2^24 - 1 entry bytes.
+ * Chunk stream:
+ *   header 16 bytes: u32 n_tokens, u32 w (= bitlen(dict_count - 1)),
+ *       u32 n_groups = ceil(n_tokens/64), u32 codes_off = align16(16 + 4*n_groups)
+ *   group offsets: u32[n_groups] at 16, the output byte offset of token 64g
+ *   codes at codes_off: n_tokens fields of width w (entry index of token i)
+ *   comp_len = codes_off + 4*ceil(n_tokens*w/32).
+ * SDICT_COL_ANS: the same stream with the packed codes replaced exactly as
+ * SDICT_ANS replaces them (piece table and 64 KiB ANS pieces at codes_off). */
+#define SDC_MAX_ENTRIES (1u << 24)
+#define SDC_MAX_BYTES ((1u << 24) - 1)
+
+static int sdc_is_sep(uint8_t c) { return c == ' ' || c == '.' || c == '\n'; }
+
+static uint32_t sdc_token_len(const uint8_t *x, uint32_t n, uint32_t i) {
+    uint32_t k = 0;
+    while (i + k < n && k < SD_MAX_TOKEN) {
+        k++;
+        if (sdc_is_sep(x[i + k - 1])) break;
+    }
+    return k;
+}
+
+/* Distinct tokens: open-addressing table of (position of the first
+ * occurrence in the column, length, count). */
+typedef struct {
+    uint64_t *pos;    /* first occurrence, byte offset in the column */
+    uint32_t *len, *count, *code;
+    int64_t *slot;    /* token id or -1 */
+    uint64_t cap, n;
+    const uint8_t *src;
+    int bad;
+} tdict_t;
+
+static void tdict_free(tdict_t *d) {
+    free(d->pos); free(d->len); free(d->count); free(d->code); free(d->slot);
+    memset(d, 0, sizeof *d);
+}
+
+/* id of the token src[at, at+L), added (count 0) if new; -1 on failure */
+static int64_t tdict_find(tdict_t *d, uint64_t at, uint32_t L, int add) {
+    if (add && 2 * (d->n + 1) > d->cap) {
+        uint64_t nc = d->cap ? 2 * d->cap : 1024;
+        int64_t *ns = (int64_t *)malloc(sizeof(int64_t) * nc);
+        uint64_t *np = (uint64_t *)realloc(d->pos, sizeof(uint64_t) * nc);
+        uint32_t *nl = (uint32_t *)realloc(d->len, sizeof(uint32_t) * nc);
+        uint32_t *nn = (uint32_t *)realloc(d->count, sizeof(uint32_t) * nc);
+        if (np) d->pos = np;
+        if (nl) d->len = nl;
+        if (nn) d->count = nn;
+        if (!ns || !np || !nl || !nn) { free(ns); d->bad = 1; return -1; }
+        for (uint64_t k = 0; k < nc; k++) ns[k] = -1;
+        for (uint64_t t = 0; t < d->n; t++) {
+            uint64_t h = sd_hash(d->src + d->pos[t], d->len[t]) & (nc - 1);
+            while (ns[h] >= 0) h = (h + 1) & (nc - 1);
+            ns[h] = (int64_t)t;
+        }
+        free(d->slot);
+        d->slot = ns;
+        d->cap = nc;
+    }
+    if (!d->cap) return -1;
+    uint64_t h = sd_hash(d->src + at, L) & (d->cap - 1);
+    while (d->slot[h] >= 0) {
+        uint64_t t = (uint64_t)d->slot[h];
+        if (d->len[t] == L && memcmp(d->src + d->pos[t], d->src + at, L) == 0) return (int64_t)t;
+        h = (h + 1) & (d->cap - 1);
+    }
+    if (!add) return -1;
+    d->slot[h] = (int64_t)d->n;
+    d->pos[d->n] = at;
+    d->len[d->n] = L;
+    d->count[d->n] = 0;
+    return (int64_t)d->n++;
+}
+
+static const tdict_t *g_sort_dict;
+static int tdict_order(const void *a, const void *b) {
+    uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    const tdict_t *d = g_sort_dict;
+    if (d->count[x] != d->count[y]) return d->count[x] > d->count[y] ? -1 : 1;
+    return d->pos[x] < d->pos[y] ? -1 : d->pos[x] > d->pos[y];
+}
+
+/* Build the column dictionary from the chunks coded with SDICT_COL or
+ * SDICT_COL_ANS; fills d (codes = entry index of each token id) and the
+ * dictionary area bytes.  Returns ZFO_OK, ZFO_EUNSUP (too many entries or
+ * bytes) or ZFO_ENOMEM. */
+static int tdict_build(const uint8_t *src, const uint32_t *chunk_elems, uint32_t n_chunks,
+                       const uint32_t *codecs, uint32_t codec, tdict_t *d, uint8_t **area,
+                       uint64_t *area_len, uint32_t *n_entries) {
+    memset(d, 0, sizeof *d);
+    d->src = src;
+    uint64_t off = 0;
+    for (uint32_t i = 0; i < n_chunks; i++) {
+        uint32_t c = codecs ? codecs[i] : codec, n = chunk_elems[i];
+        if (c == ZFO_SDICT_COL || c == ZFO_SDICT_COL_ANS) {
+            for (uint32_t k = 0; k < n;) {
+                uint32_t L = sdc_token_len(src + off, n, k);
+                int64_t t = tdict_find(d, off + k, L, 1);
+                if (t < 0) { tdict_free(d); return ZFO_ENOMEM; }
+                d->count[t]++;
+                k += L;
+            }
+        }
+        off += n;
+    }
+    if (d->n > SDC_MAX_ENTRIES) { tdict_free(d); return ZFO_EUNSUP; }
+    uint64_t nb = 0;
+    for (uint64_t t = 0; t < d->n; t++) nb += d->len[t];
+    if (nb > SDC_MAX_BYTES) { tdict_free(d); return ZFO_EUNSUP; }
+    uint64_t *ord = (uint64_t *)malloc(sizeof(uint64_t) * (d->n ? d->n : 1));
+    d->code = (uint32_t *)malloc(sizeof(uint32_t) * (d->n ? d->n : 1));
+    uint64_t len = 16 + 4 * d->n + align16(nb + 4);
+    uint8_t *a = (uint8_t *)calloc(len, 1);
+    if (!ord || !d->code || !a) { free(ord); free(a); tdict_free(d); return ZFO_ENOMEM; }
+    for (uint64_t t = 0; t < d->n; t++) ord[t] = t;
+    g_sort_dict = d;
+    qsort(ord, d->n, sizeof(uint64_t), tdict_order);
+    put32(a, (uint32_t)nb);
+    uint64_t at = 0;
+    for (uint64_t k = 0; k < d->n; k++) {
+        uint64_t t = ord[k];
+        d->code[t] = (uint32_t)k;
+        put32(a + 16 + 4 * k, (uint32_t)at | (d->len[t] << 24));
+        memcpy(a + 16 + 4 * d->n + at, src + d->pos[t], d->len[t]);
+        at += d->len[t];
+    }
+    free(ord);
+    *area = a;
+    *area_len = len;
+    *n_entries = (uint32_t)d->n;
+    return ZFO_OK;
+}
+
+/* chunk x = column bytes [x0, x0 + n) */
+static void enc_sdict_col(buf_t *s, tdict_t *d, uint64_t x0, uint32_t n, uint32_t ne) {
+    const uint8_t *x = d->src + x0;
+    uint32_t nt = 0;
+    for (uint32_t i = 0; i < n; i += sdc_token_len(x, n, i)) nt++;
+    uint32_t w = ne > 1 ? bitlen64(ne - 1) : 0;
+    uint32_t ng = (nt + 63) / 64;
+    uint64_t co = align16(16 + 4 * (uint64_t)ng);
+    buf_resize(s, co + 4 * packed_words(nt, w));
+    if (s->bad) return;
+    uint8_t *p = s->p;
+    put32(p, nt);
+    put32(p + 4, w);
+    put32(p + 8, ng);
+    put32(p + 12, (uint32_t)co);
+    for (uint32_t i = 0, t = 0; i < n; t++) {
+        uint32_t L = sdc_token_len(x, n, i);
+        if (t % 64 == 0) put32(p + 16 + 4 * (uint64_t)(t / 64), i);
+        int64_t id = tdict_find(d, x0 + i, L, 0);
+        if (id < 0) { s->bad = 1; return; }
+        pack_bits(p + co, t, w, d->code[id]);
+        i += L;
+    }
+    s->n = co + 4 * packed_words(nt, w);
+}
+
+static int dec_sdict_col(const uint8_t *s, uint64_t comp_len, uint32_t plain_len, const uint8_t *dict,
+                         uint32_t dict_count, uint8_t *out) {
+    if (comp_len < 16 || !dict || dict_count == 0) return ZFO_ECORRUPT;
+    uint32_t nt = get32(s), w = get32(s + 4), ng = get32(s + 8), co = get32(s + 12);
+    if (ng != (nt + 63) / 64 || w != (dict_count > 1 ? bitlen64(dict_count - 1) : 0) ||
+        co != align16(16 + 4 * (uint64_t)ng) || (uint64_t)co + 4 * packed_words(nt, w) != comp_len)
+        return ZFO_ECORRUPT;
+    uint32_t nb = get32(dict);
+    const uint8_t *ents = dict + 16, *bytes = dict + 16 + 4 * (uint64_t)dict_count;
+    uint64_t p = 0;
+    for (uint32_t t = 0; t < nt; t++) {
+        if (t % 64 == 0 && get32(s + 16 + 4 * (uint64_t)(t / 64)) != p) return ZFO_ECORRUPT;
+        uint64_t c = unpack_bits(s + co, t, w);
+        if (c >= dict_count) return ZFO_ECORRUPT;
+        uint32_t e = get32(ents + 4 * c), off = e & 0xFFFFFFu, len = e >> 24;
+        if (len == 0 || len > SD_MAX_TOKEN || (uint64_t)off + len > nb) return ZFO_ECORRUPT;
+        if (p + len > plain_len) return ZFO_ECORRUPT;
+        memcpy(out + p, bytes + off, len);
+        p += len;
+    }
+    if (p != plain_len) return ZFO_ECORRUPT;
+    return ZFO_OK;
+}
+
+static void enc_sdict_col_ans(buf_t *s, tdict_t *d, uint64_t x0, uint32_t n, uint32_t ne) {
+    buf_t inner = {0};
+    enc_sdict_col(&inner, d, x0, n, ne);
+    if (inner.bad) { free(inner.p); s->bad = 1; return; }
+    ans_pieces_encode(s, &inner, get32(inner.p + 12));
+    free(inner.p);
+}
+
+static int dec_sdict_col_ans(const uint8_t *s, uint64_t comp_len, uint32_t plain_len, const uint8_t *dict,
+                             uint32_t dict_count, uint8_t *out) {
+    if (comp_len < 16) return ZFO_ECORRUPT;
+    uint32_t nt = get32(s), w = get32(s + 4), co = get32(s + 12);
+    if (w > 32 || co > comp_len) return ZFO_ECORRUPT;
+    uint64_t ncb = 4 * packed_words(nt, w);
+    uint8_t *inner = (uint8_t *)malloc(co + ncb + 1);
+    if (!inner) return ZFO_ENOMEM;
+    int rc = ans_pieces_decode(s, comp_len, co, ncb, inner);
+    if (rc == ZFO_OK) rc = dec_sdict_col(inner, co + ncb, plain_len, dict, dict_count, out);
     free(inner);
     return rc;
 }
@@ -1208,7 +1447,9 @@ static int codec_allows(uint32_t codec, uint32_t dtype) {
     case ZFO_ANS: return zfo_elem_size(dtype) != 0;
     case ZFO_DSTRIDE_BP: return dtype == ZFO_I32 || dtype == ZFO_I64;
     case ZFO_SDICT_BP:
-    case ZFO_SDICT_ANS: return dtype == ZFO_BYTES;
+    case ZFO_SDICT_ANS:
+    case ZFO_SDICT_COL:
+    case ZFO_SDICT_COL_ANS: return dtype == ZFO_BYTES;
     default: return 0;
     }
 }
@@ -1240,6 +1481,10 @@ int zfo_decode_stream(uint32_t codec, uint32_t dtype, const uint8_t *s, uint64_t
         return dec_sdict(s, comp_len, (uint32_t)plain, dst);
     case ZFO_SDICT_ANS:
         return dec_sdict_ans(s, comp_len, (uint32_t)plain, dst);
+    case ZFO_SDICT_COL:
+        return dec_sdict_col(s, comp_len, (uint32_t)plain, dict, dict_count, dst);
+    case ZFO_SDICT_COL_ANS:
+        return dec_sdict_col_ans(s, comp_len, (uint32_t)plain, dict, dict_count, dst);
     case ZFO_FOR_BP:
     case ZFO_DICT_BP: {
         uint64_t *tmp = (uint64_t *)malloc(sizeof(uint64_t) * n);
@@ -1268,13 +1513,14 @@ int zfo_encode(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t code
     uint32_t es = zfo_elem_size(dtype);
     if (!es || !out || !out_len) return ZFO_EINVAL;
     uint64_t sum = 0;
-    int any_dict = 0;
+    int any_dict = 0, any_tdict = 0;
     for (uint32_t i = 0; i < n_chunks; i++) {
         uint32_t c = codecs ? codecs[i] : codec;
         if (chunk_elems[i] == 0 || !codec_allows(c, dtype)) return ZFO_EINVAL;
         if (c == ZFO_LZ77 && (uint64_t)chunk_elems[i] * es > LZ_MAX_CHUNK) return ZFO_EINVAL;
         if ((uint64_t)chunk_elems[i] * es > 0xFFFFFFFFu) return ZFO_EINVAL;
         any_dict |= c == ZFO_DICT_BP;
+        any_tdict |= c == ZFO_SDICT_COL || c == ZFO_SDICT_COL_ANS;
         sum += chunk_elems[i];
     }
     if (sum != n_elems) return ZFO_EINVAL;
@@ -1284,13 +1530,20 @@ int zfo_encode(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t code
 
     uint8_t *dict = NULL;
     uint32_t dict_count = 0;
+    uint64_t dl = 0;  /* dictionary area bytes */
+    tdict_t td;
+    memset(&td, 0, sizeof td);
     if (any_dict) {
         int rc = build_dict(src, n_elems, dtype, &dict, &dict_count);
+        if (rc) return rc;
+        dl = (uint64_t)dict_count * es;
+    } else if (any_tdict) {
+        int rc = tdict_build(src, chunk_elems, n_chunks, codecs, codec, &td, &dict, &dl, &dict_count);
         if (rc) return rc;
     }
     uint64_t table_end = 64 + (uint64_t)32 * n_chunks;
     uint64_t dict_off = dict_count ? align16(table_end) : 0;
-    uint64_t pos = align16(dict_count ? dict_off + (uint64_t)dict_count * es : table_end);
+    uint64_t pos = align16(dict_count ? dict_off + dl : table_end);
 
     buf_t b = {0};
     buf_resize(&b, pos);
@@ -1328,6 +1581,8 @@ int zfo_encode(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t code
         case ZFO_DSTRIDE_BP: enc_dstride(&s, x, dtype, n); break;
         case ZFO_SDICT_BP: enc_sdict(&s, x, n); break;
         case ZFO_SDICT_ANS: enc_sdict_ans(&s, x, n); break;
+        case ZFO_SDICT_COL: enc_sdict_col(&s, &td, plain_off, n, dict_count); break;
+        case ZFO_SDICT_COL_ANS: enc_sdict_col_ans(&s, &td, plain_off, n, dict_count); break;
         }
         if (s.bad || s.n > 0xFFFFFFFFu) { free(s.p); b.bad = 1; break; }
         buf_resize(&b, pos + s.n);
@@ -1346,9 +1601,10 @@ int zfo_encode(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t code
         plain_off += (uint64_t)n * es;
     }
     free(codes);
+    tdict_free(&td);
     buf_resize(&b, pos);
     if (b.bad) { free(b.p); free(dict); return ZFO_ENOMEM; }
-    if (dict_count) memcpy(b.p + dict_off, dict, (uint64_t)dict_count * es);
+    if (dict_count) memcpy(b.p + dict_off, dict, dl);
     free(dict);
 
     uint8_t *h = b.p;
@@ -1365,7 +1621,7 @@ int zfo_encode(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t code
     put64(h + 32, dict_off);
     put64(h + 40, pos);
     /* table CRC covers the chunk table followed by the dictionary */
-    uint64_t tl = (uint64_t)32 * n_chunks, dl = (uint64_t)dict_count * es;
+    uint64_t tl = (uint64_t)32 * n_chunks;
     uint8_t *tmp = (uint8_t *)malloc(tl + dl + 1);
     if (!tmp) { free(b.p); return ZFO_ENOMEM; }
     memcpy(tmp, h + 64, tl);
@@ -1398,6 +1654,13 @@ int zfo_inspect(const uint8_t *blob, uint64_t len, zfo_info *info) {
     uint64_t tl = (uint64_t)32 * in.n_chunks;
     if (64 + tl > len) return ZFO_ECORRUPT;
     uint64_t dl = (uint64_t)in.dict_count * es;
+    if (in.dict_count && in.dtype == ZFO_BYTES) {
+        /* a token dictionary: its size follows from its entry-byte count */
+        if (in.dict_off % 16 != 0 || in.dict_off < 64 + tl || in.dict_off + 16 > len) return ZFO_ECORRUPT;
+        uint32_t nb = get32(blob + in.dict_off);
+        if (nb > SDC_MAX_BYTES || in.dict_count > SDC_MAX_ENTRIES) return ZFO_ECORRUPT;
+        dl = 16 + 4 * (uint64_t)in.dict_count + align16((uint64_t)nb + 4);
+    }
     if (in.dict_count) {
         if (in.dict_off % 16 != 0 || in.dict_off < 64 + tl || in.dict_off + dl > len)
             return ZFO_ECORRUPT;
@@ -1419,7 +1682,9 @@ int zfo_inspect(const uint8_t *blob, uint64_t len, zfo_info *info) {
         if (c.comp_off % 16 != 0 || c.comp_off < 64 + tl || c.comp_off + c.comp_len > len)
             return ZFO_ECORRUPT;
         if (!codec_allows(c.codec, in.dtype)) return ZFO_ECORRUPT;
-        if (c.codec == ZFO_DICT_BP && in.dict_count == 0) return ZFO_ECORRUPT;
+        if ((c.codec == ZFO_DICT_BP || c.codec == ZFO_SDICT_COL || c.codec == ZFO_SDICT_COL_ANS) &&
+            in.dict_count == 0)
+            return ZFO_ECORRUPT;
         plain_off += c.plain_len;
         elems += c.n_elems;
     }

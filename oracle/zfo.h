@@ -40,6 +40,8 @@ extern "C" {
 #define ZFO_DSTRIDE_BP 9
 #define ZFO_SDICT_BP 10
 #define ZFO_SDICT_ANS 11
+#define ZFO_SDICT_COL 12
+#define ZFO_SDICT_COL_ANS 13
 
 /* status */
 #define ZFO_OK 0

@@ -39,7 +39,7 @@ def test_oracle_full_decode_and_compare():
     codecs = [zf.FOR_BP, zf.SDICT_BP, zf.DICT_BP]
     cols = [zf.Column.compress(x, c, chunk_bytes=(16 << 10, 256 << 10), seed=5 + i, pinned=False)
             for i, (x, c) in enumerate(zip(xs, codecs))]
-    ref, secs = bench.oracle_full_decode(cols, 3)
+    ref, secs = bench.cpu_baseline_all_cores(cols, 3)
     assert secs > 0
     for x, c, r in zip(xs, cols, ref):
         assert c.n_chunks > 3
