@@ -51,14 +51,20 @@ def kernel_hash():
 
 
 # ------------------------------------------------------------- workloads
+TEXT_CODECS = {"sdict": "SDICT_BP", "sdict_ans": "SDICT_ANS", "sdict_col": "SDICT_COL",
+               "sdict_col_ans": "SDICT_COL_ANS", "lz77": "LZ77"}
+
+
 def fact_table(rows, text_codec="sdict"):
     """The 16-column table.  The comment text is String-dictionary coded (the
     paper's choice for comment columns, Sec. 5) on the same uneven chunks as
-    the other columns; text_codec="lz77" codes it as LZ77 in 64 KiB chunks."""
+    the other columns: one dictionary per chunk (sdict), one for the column
+    (sdict_col), either nested with bit-packing and ANS (*_ans);
+    text_codec="lz77" codes it as LZ77 in 64 KiB chunks."""
     from paper_2602_08190_amd import datagen as g
     from paper_2602_08190_amd import zf
     codec_of = {"u32": zf.FOR_BP, "cents": zf.FOR_BP, "date": zf.RLE_DELTA_BP,
-                "char16": zf.DICT_BP, "text": zf.SDICT_BP if text_codec == "sdict" else zf.LZ77}
+                "char16": zf.DICT_BP, "text": getattr(zf, TEXT_CODECS[text_codec])}
     cols, xs, names = [], [], []
     for i, (name, kind, _) in enumerate(g.FACT_COLUMNS):
         t = time.time()
@@ -70,7 +76,7 @@ def fact_table(rows, text_codec="sdict"):
         cols.append(c)
         xs.append(x)
         names.append(name)
-    text = ("String-dictionary, SDICT_BP" if text_codec == "sdict" else "LZ77 in 64 KiB chunks")
+    text = ("LZ77 in 64 KiB chunks" if text_codec == "lz77" else f"String-dictionary, {TEXT_CODECS[text_codec]}")
     desc = (f"batched 16-column fact table, {rows} rows: 6 int32 keys (FOR_BP), 3 int64 cents "
             f"(FOR_BP), 3 run-sorted dates (RLE_DELTA_BP), 3 CHAR(16) flags (DICT_BP), 1 Zipf "
             f"comment text ({text}); uneven chunks 16 KiB-4 MiB")
@@ -114,6 +120,14 @@ def single(kind, n):
         desc = (f"SDICT_ANS text, {n} bytes, Zipf(1.1) over 10,000 words: String-dictionary | "
                 f"bit-packing | ANS per 1 MiB chunk (two launches: ANS stage into scratch, then "
                 f"String-dictionary)")
+    elif kind in ("sdict_col", "sdict_col_ans"):
+        x = g.text_column(n, 2)
+        codec = zf.SDICT_COL if kind == "sdict_col" else zf.SDICT_COL_ANS
+        c = zf.Column.compress(x, codec)
+        desc = (f"{zf.CODEC_NAMES[codec]} text, {n} bytes, Zipf(1.1) over 10,000 words: one String-dictionary "
+                f"for the column (tokens end at spaces, periods and row ends), 1 MiB chunks"
+                + (" (two launches: ANS stage into scratch, then String-dictionary)" if codec == zf.SDICT_COL_ANS
+                   else ""))
     elif kind == "keys":
         x = g.key_column(n, 11)
         c = zf.Column.compress(x, zf.DSTRIDE_BP)
@@ -321,9 +335,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="fact", choices=["fact", "for", "rle", "lz", "f2i", "ans", "keys", "sdict",
-                                                              "sdict_ans", "copy"])
+                                                              "sdict_ans", "sdict_col", "sdict_col_ans", "copy"])
     ap.add_argument("--rows", type=int, default=None)
-    ap.add_argument("--text-codec", default="sdict", choices=["sdict", "lz77"],
+    ap.add_argument("--text-codec", default="sdict", choices=sorted(TEXT_CODECS),
                     help="codec of the fact table's comment column")
     ap.add_argument("--no-e2e", action="store_true")
     ap.add_argument("--no-cpu", action="store_true",
@@ -351,7 +365,7 @@ def main():
     else:
         n = args.rows or {"for": 1 << 28, "rle": 1 << 26, "lz": 1 << 30, "f2i": 1 << 26,
                            "ans": 1 << 30, "keys": 1 << 26, "sdict": 1 << 30, "sdict_ans": 1 << 30,
-                           "copy": 1 << 30}[args.workload]
+                           "sdict_col": 1 << 30, "sdict_col_ans": 1 << 30, "copy": 1 << 30}[args.workload]
         cols, xs, names, desc = single(args.workload, n)
     plain = sum(c.plain_bytes for c in cols)
     comp = sum(c.host_pointer()[1] for c in cols)
@@ -429,7 +443,7 @@ def main():
     groups = {}
     for c in cols:
         key = zf.kind_of_column(c)
-        if zf.first_codec(c) == zf.SDICT_ANS:
+        if zf.first_codec(c) in (zf.SDICT_ANS, zf.SDICT_COL_ANS):
             key = "ANS+SDICT"  # two ordered launches: the ANS stage, then String-dictionary
         if args.persistent:
             key = "PERSISTENT"

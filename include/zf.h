@@ -24,7 +24,8 @@
  *     u32 plain_len, u32 comp_len, u32 n_elems, u8 codec, u8 schedule hint
  *     (0 = tuned default, 1..4 = tile granularity chosen at encode time;
  *     decoding does not depend on it), 2 zero bytes}.
- *   dictionary (dict_count > 0) at dict_off: sorted unique values.
+ *   dictionary (dict_count > 0) at dict_off: sorted unique values (dtype
+ *     BYTES: the token dictionary described at ZF_SDICT_COL).
  *   chunk streams at 16-aligned comp_off.  table_crc = CRC-32 of the chunk
  *   table followed by the dictionary.  The per-codec streams are described
  *   at zf_codec below.
@@ -124,6 +125,24 @@ typedef enum {
  *                   indices are ANS-decoded into the plan's scratch area by
  *                   one launch and expanded by the next, so a plan holding
  *                   such chunks cannot use the persistent kernel.  BYTES.
+ *  ZF_SDICT_COL     [GP] String-dictionary over one dictionary for the whole
+ *                   column (Sec. 5: one word dictionary for the comment
+ *                   column; Sec. 2.1: it holds the data's frequent byte
+ *                   sequences).  Tokens as ZF_SDICT_BP, except that '\n' (the
+ *                   end of a row value) also ends one.  The column dictionary
+ *                   sits in the container's dictionary area (dict_count =
+ *                   entries): {u32 n_bytes, 3 u32 0, u32 entries {offset bits
+ *                   0-23, length bits 24-31}, n_bytes entry bytes, zero
+ *                   padding to a multiple of 16 of at least 4 bytes}; entries
+ *                   are the distinct tokens of the column's ZF_SDICT_COL /
+ *                   ZF_SDICT_COL_ANS chunks by decreasing count, ties by first
+ *                   appearance; at most 2^24 entries and 2^24 - 1 bytes
+ *                   (ZF_E_UNSUPPORTED beyond).  Chunk: header {u32 n_tokens,
+ *                   u32 w = bitlen(dict_count - 1), u32 n_groups, u32
+ *                   codes_off = align16(16 + 4 n_groups)}, u32 output offset
+ *                   per 64 tokens at 16, packed indices at codes_off.  BYTES.
+ *  ZF_SDICT_COL_ANS [GP, two stages] ZF_SDICT_COL | bit-packing | ANS: the
+ *                   packed indices replaced as in ZF_SDICT_ANS.  BYTES.
  */
 typedef enum {
     ZF_AUTO = 0,
@@ -137,7 +156,9 @@ typedef enum {
     ZF_ANS = 8,
     ZF_DSTRIDE_BP = 9,
     ZF_SDICT_BP = 10,
-    ZF_SDICT_ANS = 11
+    ZF_SDICT_ANS = 11,
+    ZF_SDICT_COL = 12,
+    ZF_SDICT_COL_ANS = 13
 } zf_codec;
 
 typedef void *zf_stream_t;              /* a hipStream_t */

@@ -619,6 +619,178 @@ static void enc_sdict(std::vector<uint8_t> &s, const uint8_t *x, uint32_t n) {
     bp.flush();
 }
 
+// ----------------------------------- String-dictionary, column dictionary
+// One dictionary for the column's SDICT_COL / SDICT_COL_ANS chunks: tokens
+// end after a space, a period or a newline (the end of a row value), at most
+// 64 bytes; entries by decreasing count, ties by first appearance in the
+// column; in the container's dictionary area as {u32 n_bytes, 3 x u32 0,
+// u32 entry[n] (offset | length << 24), entry bytes, zero padding to a
+// multiple of 16 of at least 4 bytes}.  A chunk keeps its token count,
+// width, group offsets and the bit-packed entry indices.
+static inline uint32_t sdc_token_len(const uint8_t *x, uint32_t n, uint32_t i) {
+    uint32_t L = 0;
+    while (i + L < n && L < kSdMaxToken) {
+        const uint8_t c = x[i + L++];
+        if (c == ' ' || c == '.' || c == '\n') break;
+    }
+    return L;
+}
+
+// Open-addressing table of tokens (a pointer into the column and a length).
+struct TokenTable {
+    struct Slot {
+        const uint8_t *p = nullptr;
+        uint32_t len = 0, val = 0;  // val: count while counting, then the entry index
+        uint64_t first = 0;         // first occurrence (byte offset in the column)
+    };
+    std::vector<Slot> slots;
+    uint64_t mask = 0, count = 0;
+    static inline uint64_t hash(const uint8_t *p, uint32_t len) {
+        uint64_t h = 0x9E3779B97F4A7C15ull ^ len;
+        uint32_t i = 0;
+        for (; i + 8 <= len; i += 8) {
+            uint64_t v;
+            std::memcpy(&v, p + i, 8);
+            h = (h ^ v) * 0xBF58476D1CE4E5B9ull;
+            h ^= h >> 31;
+        }
+        uint64_t t = 0;
+        for (uint32_t k = 0; i + k < len; k++) t |= uint64_t(p[i + k]) << (8 * k);
+        h = (h ^ t) * 0x94D049BB133111EBull;
+        return h ^ (h >> 29);
+    }
+    TokenTable() { init(1024); }
+    void init(uint64_t cap) {
+        uint64_t c = 16;
+        while (c < 2 * cap) c <<= 1;
+        slots.assign(c, Slot{});
+        mask = c - 1;
+        count = 0;
+    }
+    Slot *find(const uint8_t *p, uint32_t len) {
+        uint64_t h = hash(p, len) & mask;
+        while (slots[h].p) {
+            if (slots[h].len == len && std::memcmp(slots[h].p, p, len) == 0) return &slots[h];
+            h = (h + 1) & mask;
+        }
+        return nullptr;
+    }
+    const Slot *find(const uint8_t *p, uint32_t len) const { return const_cast<TokenTable *>(this)->find(p, len); }
+    // add `cnt` occurrences of a token first seen at `first`
+    void add(const uint8_t *p, uint32_t len, uint64_t first, uint32_t cnt) {
+        if (2 * (count + 1) > mask + 1) grow();
+        uint64_t h = hash(p, len) & mask;
+        while (slots[h].p) {
+            Slot &s = slots[h];
+            if (s.len == len && std::memcmp(s.p, p, len) == 0) {
+                s.val += cnt;
+                s.first = std::min(s.first, first);
+                return;
+            }
+            h = (h + 1) & mask;
+        }
+        slots[h] = Slot{p, len, cnt, first};
+        count++;
+    }
+    void grow() {
+        std::vector<Slot> old;
+        old.swap(slots);
+        init(2 * (mask + 1));
+        for (const Slot &s : old)
+            if (s.p) add(s.p, s.len, s.first, s.val);
+    }
+};
+
+struct TokenDictionary {
+    TokenTable table;            // token -> entry index
+    std::vector<uint8_t> area;   // the dictionary area
+    uint32_t count = 0, w = 0;
+};
+
+// Count the tokens of the chunks with codec SDICT_COL / SDICT_COL_ANS (in
+// parallel), order them and lay out the dictionary area.
+static void build_token_dictionary(TokenDictionary &d, const uint8_t *src, const std::vector<uint32_t> &ce,
+                                   const std::vector<uint8_t> &cc, const std::vector<uint64_t> &first,
+                                   int threads) {
+    std::vector<uint64_t> todo;
+    for (size_t i = 0; i < ce.size(); i++)
+        if (cc[i] == C_SDICT_COL || cc[i] == C_SDICT_COL_ANS) todo.push_back(i);
+    const int nt = int(std::max<uint64_t>(1, std::min<uint64_t>(uint64_t(threads), todo.size())));
+    std::vector<TokenTable> part(nt);
+    std::atomic<uint64_t> next{0};
+    auto work = [&](int t) {
+        for (uint64_t k; (k = next.fetch_add(1)) < todo.size();) {
+            const uint64_t i = todo[k];
+            const uint8_t *x = src + first[i];
+            for (uint32_t a = 0; a < ce[i];) {
+                const uint32_t L = sdc_token_len(x, ce[i], a);
+                part[t].add(x + a, L, first[i] + a, 1);
+                a += L;
+            }
+        }
+    };
+    {
+        std::vector<std::thread> ts;
+        for (int t = 1; t < nt; t++) ts.emplace_back(work, t);
+        work(0);
+        for (auto &th : ts) th.join();
+    }
+    for (int t = 1; t < nt; t++)
+        for (const auto &s : part[t].slots)
+            if (s.p) part[0].add(s.p, s.len, s.first, s.val);
+    std::vector<const TokenTable::Slot *> ent;
+    for (const auto &s : part[0].slots)
+        if (s.p) ent.push_back(&s);
+    ZF_REQUIRE(ent.size() <= (1u << 24), ZF_E_UNSUPPORTED,
+               "%zu distinct tokens: a column dictionary holds at most 2^24", ent.size());
+    std::sort(ent.begin(), ent.end(), [](const TokenTable::Slot *a, const TokenTable::Slot *b) {
+        return a->val != b->val ? a->val > b->val : a->first < b->first;
+    });
+    uint64_t nb = 0;
+    for (auto *e : ent) nb += e->len;
+    ZF_REQUIRE(nb < (1u << 24), ZF_E_UNSUPPORTED,
+               "%llu bytes of distinct tokens: a column dictionary holds at most 2^24 - 1",
+               (unsigned long long)nb);
+    d.count = uint32_t(ent.size());
+    d.w = d.count > 1 ? bit_width64(d.count - 1) : 0;
+    d.area.assign(16 + 4ull * d.count + align_up(nb + 4, 16), 0);
+    wr32(d.area.data(), uint32_t(nb));
+    d.table.init(d.count);
+    uint32_t at = 0;
+    for (uint32_t k = 0; k < d.count; k++) {
+        const TokenTable::Slot *e = ent[k];
+        wr32(d.area.data() + 16 + 4ull * k, at | (e->len << 24));
+        std::memcpy(d.area.data() + 16 + 4ull * d.count + at, e->p, e->len);
+        at += e->len;
+        d.table.add(e->p, e->len, e->first, k);
+    }
+}
+
+static void enc_sdict_col(std::vector<uint8_t> &s, const uint8_t *x, uint32_t n, const TokenDictionary &d) {
+    std::vector<uint32_t> codes, starts;
+    codes.reserve(n / 4 + 1);
+    for (uint32_t i = 0; i < n;) {
+        const uint32_t L = sdc_token_len(x, n, i);
+        const TokenTable::Slot *e = d.table.find(x + i, L);
+        if (!e) fail(ZF_E_INVALID, "token missing from the column dictionary");
+        if (codes.size() % 64 == 0) starts.push_back(i);
+        codes.push_back(e->val);
+        i += L;
+    }
+    const uint32_t nt = uint32_t(codes.size()), ng = uint32_t(starts.size()), w = d.w;
+    const uint64_t co = align_up(16 + 4ull * ng, 16);
+    s.assign(co + 4 * ((uint64_t(nt) * w + 31) / 32), 0);
+    uint8_t *p = s.data();
+    wr32(p, nt);
+    wr32(p + 4, w);
+    wr32(p + 8, ng);
+    wr32(p + 12, uint32_t(co));
+    for (uint32_t g = 0; g < ng; g++) wr32(p + 16 + 4ull * g, starts[g]);
+    BitPacker bp(p + co);
+    for (uint32_t c : codes) bp.put(c, w);
+    bp.flush();
+}
+
 // ------------------------------------------------------------------ LZ77
 // Greedy LZ77 over a chunk of <= 64 KiB: hash chains of 4-byte prefixes
 // (depth 16), longest match, nearest source on ties.
@@ -749,8 +921,30 @@ static uint64_t splitmix(uint64_t &s) {
     return z ^ (z >> 31);
 }
 
+// The packed entry indices at co of a String-dictionary stream `sd`
+// replaced by ANS streams of them in independent pieces of kSdAnsPiece
+// bytes: u32 count, u32 stream ends, streams (each zero-padded to a multiple
+// of 4 bytes).
+static void ans_pieces(std::vector<uint8_t> &out, const std::vector<uint8_t> &sd, uint32_t co) {
+    const uint64_t ncb = sd.size() - co;
+    const uint32_t np = uint32_t((ncb + kSdAnsPiece - 1) / kSdAnsPiece);
+    out.assign(sd.begin(), sd.begin() + co);
+    if (!np) return;
+    out.resize(co + 4 + 4ull * np, 0);
+    wr32(out.data() + co, np);
+    const uint64_t base = out.size();
+    std::vector<uint8_t> a;
+    for (uint32_t k = 0; k < np; k++) {
+        const uint64_t lo = uint64_t(k) * kSdAnsPiece, hi = std::min<uint64_t>(lo + kSdAnsPiece, ncb);
+        enc_ans(a, sd.data() + co + lo, uint32_t(hi - lo));
+        out.insert(out.end(), a.begin(), a.end());
+        out.resize(align_up(out.size(), 4), 0);  // the next stream starts 4-aligned
+        wr32(out.data() + co + 4 + 4ull * k, uint32_t(out.size() - base));
+    }
+}
+
 static void encode_chunk(std::vector<uint8_t> &out, uint32_t codec, uint32_t dtype, const uint8_t *x,
-                         uint32_t n, const Dictionary *dict, LzScratch &sc) {
+                         uint32_t n, const Dictionary *dict, const TokenDictionary *tdict, LzScratch &sc) {
     const uint32_t es = elem_size(dtype);
     switch (codec) {
     case C_PLAIN: out.assign(x, x + uint64_t(n) * es); return;
@@ -773,28 +967,16 @@ static void encode_chunk(std::vector<uint8_t> &out, uint32_t codec, uint32_t dty
         return;
     case C_SDICT_BP: enc_sdict(out, x, n); return;
     case C_SDICT_ANS: {
-        // String-dictionary, then ANS over its packed entry indices in
-        // independent pieces of kSdAnsPiece bytes: u32 count, u32 stream
-        // ends, streams (each zero-padded to a multiple of 4 bytes)
         std::vector<uint8_t> sd;
         enc_sdict(sd, x, n);
-        const uint32_t co = rd32(sd.data() + 24);
-        const uint64_t ncb = sd.size() - co;
-        const uint32_t np = uint32_t((ncb + kSdAnsPiece - 1) / kSdAnsPiece);
-        out.assign(sd.begin(), sd.begin() + co);
-        if (np) {
-            out.resize(co + 4 + 4ull * np, 0);
-            wr32(out.data() + co, np);
-            const uint64_t base = out.size();
-            std::vector<uint8_t> a;
-            for (uint32_t k = 0; k < np; k++) {
-                const uint64_t lo = uint64_t(k) * kSdAnsPiece, hi = std::min<uint64_t>(lo + kSdAnsPiece, ncb);
-                enc_ans(a, sd.data() + co + lo, uint32_t(hi - lo));
-                out.insert(out.end(), a.begin(), a.end());
-                out.resize(align_up(out.size(), 4), 0);  // the next stream starts 4-aligned
-                wr32(out.data() + co + 4 + 4ull * k, uint32_t(out.size() - base));
-            }
-        }
+        ans_pieces(out, sd, rd32(sd.data() + 24));
+        return;
+    }
+    case C_SDICT_COL: enc_sdict_col(out, x, n, *tdict); return;
+    case C_SDICT_COL_ANS: {
+        std::vector<uint8_t> sd;
+        enc_sdict_col(sd, x, n, *tdict);
+        ans_pieces(out, sd, rd32(sd.data() + 12));
         return;
     }
     }
@@ -928,6 +1110,10 @@ void compress_host(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t 
     // encode
     std::vector<uint64_t> first(ce.size() + 1, 0);
     for (size_t i = 0; i < ce.size(); i++) first[i + 1] = first[i] + ce[i];
+    TokenDictionary tdict;
+    bool want_tdict = false;
+    for (auto c : cc) want_tdict |= c == C_SDICT_COL || c == C_SDICT_COL_ANS;
+    if (want_tdict) build_token_dictionary(tdict, src, ce, cc, first, threads);
     std::vector<EncodedChunk> chunks(ce.size());
     parallel_for(ce.size(), threads, [&](uint64_t i) {
         static thread_local LzScratch sc_tl;
@@ -938,19 +1124,19 @@ void compress_host(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t 
         out.sched = sched[i];
         if (cc[i] != 0) {
             out.codec = cc[i];
-            encode_chunk(out.bytes, cc[i], dtype, x, ce[i], &dict, *sc);
+            encode_chunk(out.bytes, cc[i], dtype, x, ce[i], &dict, &tdict, *sc);
         } else {
             // smallest stream among the applicable codecs
             const uint32_t cands[] = {C_FOR_BP, C_DICT_BP, C_DELTA_BP, C_RLE_DELTA_BP, C_LZ77, C_F2I_BP, C_ANS,
                                       C_DSTRIDE_BP, C_SDICT_BP, C_SDICT_ANS};
-            encode_chunk(out.bytes, C_PLAIN, dtype, x, ce[i], nullptr, *sc);
+            encode_chunk(out.bytes, C_PLAIN, dtype, x, ce[i], nullptr, nullptr, *sc);
             out.codec = C_PLAIN;
             std::vector<uint8_t> tmp;
             for (uint32_t c : cands) {
                 if (!codec_allows(c, dtype)) continue;
                 if (c == C_DICT_BP && !have_dict) continue;
                 if (c == C_LZ77 && uint64_t(ce[i]) * es > kLzMaxChunk) continue;
-                encode_chunk(tmp, c, dtype, x, ce[i], &dict, *sc);
+                encode_chunk(tmp, c, dtype, x, ce[i], &dict, nullptr, *sc);
                 if (tmp.size() < out.bytes.size()) {
                     out.bytes.swap(tmp);
                     out.codec = uint8_t(c);
@@ -961,8 +1147,12 @@ void compress_host(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t 
     });
     bool uses_dict = false;
     for (auto &c : chunks) uses_dict |= c.codec == C_DICT_BP;
-    assemble_column(col->buf, o.pinned != 0, dtype, n_elems, chunks,
-                    uses_dict ? dict.bytes.data() : nullptr, uses_dict ? dict.count : 0);
+    if (want_tdict)
+        assemble_column(col->buf, o.pinned != 0, dtype, n_elems, chunks, tdict.area.data(), tdict.count,
+                        tdict.area.size());
+    else
+        assemble_column(col->buf, o.pinned != 0, dtype, n_elems, chunks, uses_dict ? dict.bytes.data() : nullptr,
+                        uses_dict ? dict.count : 0, uses_dict ? uint64_t(dict.count) * es : 0);
     col->view = parse_column(col->buf.p, col->buf.n);
 }
 

@@ -42,7 +42,9 @@ bool codec_allows(uint32_t codec, uint32_t dtype) {
     case C_RLE_DELTA_BP:
     case C_DSTRIDE_BP: return dtype == D_I32 || dtype == D_I64;
     case C_SDICT_BP:
-    case C_SDICT_ANS: return dtype == D_BYTES;
+    case C_SDICT_ANS:
+    case C_SDICT_COL:
+    case C_SDICT_COL_ANS: return dtype == D_BYTES;
     case C_DICT_BP: return dtype != D_BYTES && dtype != D_F64;
     case C_F2I_BP: return dtype == D_F64;
     case C_ANS: return true;
@@ -59,7 +61,9 @@ Kind kind_of(uint32_t codec, uint32_t dtype) {
     case C_RLE_DELTA_BP:
     case C_DSTRIDE_BP: return dtype == D_I32 ? K_RLE32 : K_RLE64;
     case C_SDICT_BP:
-    case C_SDICT_ANS: return K_SDICT;
+    case C_SDICT_ANS:
+    case C_SDICT_COL:
+    case C_SDICT_COL_ANS: return K_SDICT;
     case C_LZ77: return K_LZ;
     case C_F2I_BP: return K_F2I;
     case C_ANS: return K_ANS;
@@ -114,12 +118,12 @@ void HostBuf::release() {
 // ---------------------------------------------------------------- layout
 void assemble_column(HostBuf &out, bool pinned, uint32_t dtype, uint64_t n_elems,
                      const std::vector<EncodedChunk> &chunks, const uint8_t *dict,
-                     uint32_t dict_count) {
+                     uint32_t dict_count, uint64_t dict_len) {
     const uint32_t es = elem_size(dtype);
     const uint64_t nc = chunks.size();
     const uint64_t table_end = 64 + 32 * nc;
     const uint64_t dict_off = dict_count ? align_up(table_end, 16) : 0;
-    uint64_t pos = align_up(dict_count ? dict_off + uint64_t(dict_count) * es : table_end, 16);
+    uint64_t pos = align_up(dict_count ? dict_off + dict_len : table_end, 16);
     std::vector<uint64_t> comp_off(nc);
     for (uint64_t i = 0; i < nc; i++) {
         comp_off[i] = pos;
@@ -130,13 +134,13 @@ void assemble_column(HostBuf &out, bool pinned, uint32_t dtype, uint64_t n_elems
     std::memset(b, 0, table_end);
     if (dict_count) {
         std::memset(b + table_end, 0, dict_off - table_end);
-        std::memcpy(b + dict_off, dict, uint64_t(dict_count) * es);
+        std::memcpy(b + dict_off, dict, dict_len);
     }
     uint64_t plain_off = 0;
     bool mixed = false;
     for (uint64_t i = 0; i < nc; i++) {
         const EncodedChunk &c = chunks[i];
-        uint64_t gap_from = i == 0 ? (dict_count ? dict_off + uint64_t(dict_count) * es : table_end)
+        uint64_t gap_from = i == 0 ? (dict_count ? dict_off + dict_len : table_end)
                                    : comp_off[i - 1] + chunks[i - 1].bytes.size();
         std::memset(b + gap_from, 0, comp_off[i] - gap_from);
         std::memcpy(b + comp_off[i], c.bytes.data(), c.bytes.size());
@@ -152,7 +156,7 @@ void assemble_column(HostBuf &out, bool pinned, uint32_t dtype, uint64_t n_elems
         mixed |= c.codec != chunks[0].codec;
     }
     uint64_t tail = nc ? comp_off[nc - 1] + chunks[nc - 1].bytes.size()
-                       : (dict_count ? dict_off + uint64_t(dict_count) * es : table_end);
+                       : (dict_count ? dict_off + dict_len : table_end);
     std::memset(b + tail, 0, pos - tail);
 
     std::memcpy(b, "ZFC1", 4);
@@ -166,7 +170,7 @@ void assemble_column(HostBuf &out, bool pinned, uint32_t dtype, uint64_t n_elems
     wr64(b + 32, dict_off);
     wr64(b + 40, pos);
     uint32_t tcrc = crc32(b + 64, 32 * nc);
-    if (dict_count) tcrc = crc32(b + dict_off, uint64_t(dict_count) * es, tcrc);
+    if (dict_count) tcrc = crc32(b + dict_off, dict_len, tcrc);
     wr32(b + 48, tcrc);
     wr32(b + 52, 0);
     wr32(b + 56, 0);
@@ -189,6 +193,32 @@ static void check_ans(const uint8_t *s, uint64_t L, uint64_t n, uint32_t i) {
         const uint32_t w = rd32(s + 784 + 4 * j);
         ZF_REQUIRE(w >= prev && w <= rd32(s + 4), ZF_E_CORRUPT, "chunk %u: ANS word offsets", i);
         prev = w;
+    }
+}
+
+// The packed entry indices of a nested String-dictionary stream: nothing
+// when there are none, else the piece table at co and one ANS stream per
+// kSdAnsPiece bytes of them, each 4-aligned.
+static void check_ans_pieces(const uint8_t *s, uint64_t L, uint64_t co, uint64_t ncb, uint32_t i) {
+    if (ncb == 0) {
+        ZF_REQUIRE(co == L, ZF_E_CORRUPT, "chunk %u: String-dictionary codes size", i);
+        return;
+    }
+    const uint32_t np = uint32_t((ncb + kSdAnsPiece - 1) / kSdAnsPiece);
+    ZF_REQUIRE(co + 4 + 4ull * np <= L && rd32(s + co) == np, ZF_E_CORRUPT,
+               "chunk %u: String-dictionary ANS piece table", i);
+    const uint64_t base = co + 4 + 4ull * np;
+    uint64_t prev = 0;
+    for (uint32_t k = 0; k < np; k++) {
+        const uint64_t end = rd32(s + co + 4 + 4ull * k);
+        const uint64_t len = std::min<uint64_t>(kSdAnsPiece, ncb - uint64_t(k) * kSdAnsPiece);
+        ZF_REQUIRE(end >= prev + kAnsHdr && base + end <= L && (k + 1 < np || base + end == L),
+                   ZF_E_CORRUPT, "chunk %u: String-dictionary ANS piece %u", i, k);
+        const uint64_t alen = kAnsHdr + 2ull * rd32(s + base + prev + 4);  // without padding
+        ZF_REQUIRE(align_up(alen, 4) == end - prev, ZF_E_CORRUPT,
+                   "chunk %u: String-dictionary ANS piece %u padding", i, k);
+        check_ans(s + base + prev, alen, len, i);
+        prev = end;
     }
 }
 
@@ -277,27 +307,8 @@ void check_stream(const ColumnView &v, const uint8_t *blob, uint32_t i) {
         const uint64_t ncb = 4 * words_for(nt, w);  // packed entry-index bytes
         if (c.codec == C_SDICT_BP)
             ZF_REQUIRE(co + ncb == L, ZF_E_CORRUPT, "chunk %u: String-dictionary codes size", i);
-        else if (ncb == 0)
-            ZF_REQUIRE(co == L, ZF_E_CORRUPT, "chunk %u: String-dictionary codes size", i);
-        else {
-            // the ANS streams of those bytes, one per piece of kSdAnsPiece
-            const uint32_t np = uint32_t((ncb + kSdAnsPiece - 1) / kSdAnsPiece);
-            ZF_REQUIRE(co + 4 + 4ull * np <= L && rd32(s + co) == np, ZF_E_CORRUPT,
-                       "chunk %u: String-dictionary ANS piece table", i);
-            const uint64_t base = co + 4 + 4ull * np;
-            uint64_t prev = 0;
-            for (uint32_t k = 0; k < np; k++) {
-                const uint64_t end = rd32(s + co + 4 + 4ull * k);
-                const uint64_t len = std::min<uint64_t>(kSdAnsPiece, ncb - uint64_t(k) * kSdAnsPiece);
-                ZF_REQUIRE(end >= prev + kAnsHdr && base + end <= L && (k + 1 < np || base + end == L),
-                           ZF_E_CORRUPT, "chunk %u: String-dictionary ANS piece %u", i, k);
-                const uint64_t alen = kAnsHdr + 2ull * rd32(s + base + prev + 4);  // without padding
-                ZF_REQUIRE(align_up(alen, 4) == end - prev, ZF_E_CORRUPT,
-                           "chunk %u: String-dictionary ANS piece %u padding", i, k);
-                check_ans(s + base + prev, alen, len, i);
-                prev = end;
-            }
-        }
+        else
+            check_ans_pieces(s, L, co, ncb, i);
         for (uint32_t k = 0; k < ne; k++) {
             const uint32_t e = rd32(s + eo + 4ull * k), len = e >> 24;
             ZF_REQUIRE(len >= 1 && len <= kSdMaxToken && (e & 0xFFFFFFu) + uint64_t(len) <= nb,
@@ -306,6 +317,29 @@ void check_stream(const ColumnView &v, const uint8_t *blob, uint32_t i) {
         uint64_t prev = 0;
         for (uint32_t g = 0; g < ng; g++) {
             const uint32_t off = rd32(s + 32 + 4ull * g);
+            ZF_REQUIRE(g == 0 ? off == 0 : (off > prev && off < c.plain_len), ZF_E_CORRUPT,
+                       "chunk %u group %u: output offset out of order", i, g);
+            prev = off;
+        }
+        return;
+    }
+    case C_SDICT_COL:
+    case C_SDICT_COL_ANS: {
+        ZF_REQUIRE(L >= 16, ZF_E_CORRUPT, "chunk %u: short String-dictionary header", i);
+        const uint32_t nt = rd32(s), w = rd32(s + 4), ng = rd32(s + 8), co = rd32(s + 12);
+        const uint32_t ne = v.dict_count;
+        const uint32_t wneed = ne > 1 ? 32 - uint32_t(__builtin_clz(ne - 1)) : 0;
+        ZF_REQUIRE(ne >= 1 && nt >= 1 && w == wneed && ng == (uint64_t(nt) + 63) / 64 &&
+                       co == align_up(16 + 4ull * ng, 16) && co <= L,
+                   ZF_E_CORRUPT, "chunk %u: String-dictionary header does not match its sizes", i);
+        const uint64_t ncb = 4 * words_for(nt, w);
+        if (c.codec == C_SDICT_COL)
+            ZF_REQUIRE(co + ncb == L, ZF_E_CORRUPT, "chunk %u: String-dictionary codes size", i);
+        else
+            check_ans_pieces(s, L, co, ncb, i);
+        uint64_t prev = 0;
+        for (uint32_t g = 0; g < ng; g++) {
+            const uint32_t off = rd32(s + 16 + 4ull * g);
             ZF_REQUIRE(g == 0 ? off == 0 : (off > prev && off < c.plain_len), ZF_E_CORRUPT,
                        "chunk %u group %u: output offset out of order", i, g);
             prev = off;
@@ -357,8 +391,18 @@ ColumnView parse_column(const uint8_t *p, uint64_t len) {
     const uint32_t es = elem_size(v.dtype);
     ZF_REQUIRE(es && v.plain_bytes == v.n_elems * es && v.total_bytes == len, ZF_E_CORRUPT,
                "header sizes inconsistent");
-    const uint64_t tl = 32ull * v.n_chunks, dl = uint64_t(v.dict_count) * es;
+    const uint64_t tl = 32ull * v.n_chunks;
+    uint64_t dl = uint64_t(v.dict_count) * es;
     ZF_REQUIRE(64 + tl <= len, ZF_E_CORRUPT, "chunk table overruns the column");
+    if (v.dict_count && v.dtype == D_BYTES) {
+        // a token dictionary: its size follows from its entry-byte count
+        ZF_REQUIRE(v.dict_off % 16 == 0 && v.dict_off >= 64 + tl && v.dict_off + 16 <= len, ZF_E_CORRUPT,
+                   "dictionary out of range");
+        const uint32_t nb = rd32(p + v.dict_off);
+        ZF_REQUIRE(nb < (1u << 24) && v.dict_count <= (1u << 24), ZF_E_CORRUPT, "token dictionary too large");
+        dl = 16 + 4ull * v.dict_count + align_up(nb + 4ull, 16);
+    }
+    v.dict_bytes = dl;
     if (v.dict_count)
         ZF_REQUIRE(v.dict_off % 16 == 0 && v.dict_off >= 64 + tl && v.dict_off + dl <= len,
                    ZF_E_CORRUPT, "dictionary out of range");
@@ -367,6 +411,17 @@ ColumnView parse_column(const uint8_t *p, uint64_t len) {
     uint32_t tcrc = crc32(p + 64, tl);
     if (v.dict_count) tcrc = crc32(p + v.dict_off, dl, tcrc);
     ZF_REQUIRE(tcrc == rd32(p + 48), ZF_E_CORRUPT, "chunk table CRC mismatch");
+    if (v.dict_count && v.dtype == D_BYTES) {
+        const uint8_t *d = p + v.dict_off;
+        const uint32_t nb = rd32(d);
+        ZF_REQUIRE(rd32(d + 4) == 0 && rd32(d + 8) == 0 && rd32(d + 12) == 0, ZF_E_CORRUPT,
+                   "token dictionary header");
+        for (uint32_t k = 0; k < v.dict_count; k++) {
+            const uint32_t e = rd32(d + 16 + 4ull * k), elen = e >> 24;
+            ZF_REQUIRE(elen >= 1 && elen <= kSdMaxToken && (e & 0xFFFFFFu) + uint64_t(elen) <= nb, ZF_E_CORRUPT,
+                       "token dictionary entry %u", k);
+        }
+    }
     v.chunks.resize(v.n_chunks);
     uint64_t plain = 0, elems = 0;
     for (uint32_t i = 0; i < v.n_chunks; i++) {
@@ -386,8 +441,9 @@ ColumnView parse_column(const uint8_t *p, uint64_t len) {
                    ZF_E_CORRUPT, "chunk %u: stream out of range", i);
         ZF_REQUIRE(codec_allows(c.codec, v.dtype), ZF_E_CORRUPT, "chunk %u: codec %u for dtype %u",
                    i, c.codec, v.dtype);
-        ZF_REQUIRE(c.codec != C_DICT_BP || v.dict_count > 0, ZF_E_CORRUPT,
-                   "chunk %u: dictionary chunk without dictionary", i);
+        ZF_REQUIRE((c.codec != C_DICT_BP && c.codec != C_SDICT_COL && c.codec != C_SDICT_COL_ANS) ||
+                       v.dict_count > 0,
+                   ZF_E_CORRUPT, "chunk %u: dictionary chunk without dictionary", i);
         plain += c.plain_len;
         elems += c.n_elems;
         check_stream(v, p, i);

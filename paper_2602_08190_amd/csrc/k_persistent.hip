@@ -7,7 +7,7 @@ namespace zf {
 // Persistent: every wave pulls units from one queue until it is empty.
 // Units are ordered by kind, the costliest kinds first.
 __global__ __launch_bounds__(256) void k_decode_persistent(LaunchArgs A) {
-    __shared__ uint32_t lz_rows[4][1280];
+    __shared__ __attribute__((aligned(16))) uint32_t lz_rows[4][kSdBufWords];
     uint32_t *mine = lz_rows[threadIdx.x / 64];
     const uint32_t n = A.kind_begin[K_COUNT];
     for (;;) {

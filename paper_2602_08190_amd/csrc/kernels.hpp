@@ -1083,47 +1083,101 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, uint32_t *row) {
 // ======================================================= String-dictionary
 // Group-Parallel (Sec. 5: each word is a group that expands to its entry's
 // bytes).  One wave takes whole groups of 64 tokens [t.a, t.b): lane i reads
-// token i's entry index from the packed codes, then the entry (offset,
-// length); a wave scan of the lengths gives each token's output position; the
-// group's bytes are copied by copy_segments with one segment per token whose
-// source is in the entry bytes.  The host checked the header, the entries
-// and the group offsets; the wave checks the codes and each group's length.
-// row: this wave's 64 * kSdBlk dwords.
-constexpr uint32_t kSdBlk = 4;
-ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, uint32_t *row) {
+// token i's entry index from the packed codes, then the entry {offset,
+// length}; a wave scan of the lengths gives each token's output position.
+// The tokens' bytes are assembled in the wave's LDS buffer, laid on the
+// output's 16-byte grid: each lane ORs the dwords its token covers (read as
+// unaligned dwords from the entry bytes and masked to the token) into the
+// zeroed buffer.  Whenever at least kSdFlushBytes of whole 16-byte blocks are
+// complete, and at the unit's end, the wave writes them out with one 16-byte
+// store per lane per block and carries the unfinished block to the buffer's
+// front.  Bytes of a block outside the unit's output range belong to the
+// neighbouring units and are left alone.
+// Entries and entry bytes are the chunk's (SDICT_BP, SDICT_ANS) or the
+// column dictionary's (SDICT_COL, SDICT_COL_ANS); the packed indices are the
+// chunk's, or were ANS-decoded into the scratch area by an earlier launch
+// (the *_ANS codecs).  Every header field is checked against the stream or
+// dictionary size before use; the wave checks every index and entry and each
+// group's length.
+// buf: this wave's kSdBufWords dwords (16-byte aligned).
+constexpr uint32_t kSdBufWords = 1280;    // 5120 bytes
+constexpr uint32_t kSdFlushBytes = 1024;  // whole blocks that trigger a write-out
+// Before a group the buffer holds < kSdFlushBytes bytes (else it would have
+// been written out); a group adds at most 64 tokens of kSdMaxToken bytes.
+static_assert(kSdFlushBytes + 64 * kSdMaxToken <= 4 * kSdBufWords, "String-dictionary buffer");
+
+ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, uint32_t *buf) {
     const uint8_t *s = A.comp + ck.comp_off;
     const uint32_t lane = lane_id(), plain = ck.n_elems, clen = ck.comp_len;
     uint8_t *out = A.out_tab[ck.col] + ck.out_off;
-    if (clen < 32) {
-        flag(A.err, ERR_CORRUPT);
-        return;
+    const bool coldict = ck.codec == C_SDICT_COL || ck.codec == C_SDICT_COL_ANS;
+    const bool staged = ck.codec == C_SDICT_ANS || ck.codec == C_SDICT_COL_ANS;
+    uint32_t nt = 0, ne = 0, w = 0, ng = 0, co = 0, nb = 0, go = 0;
+    const uint8_t *ebase = nullptr, *bbase = nullptr;  // entries, entry bytes
+    bool ok;
+    if (coldict) {
+        // header {n_tokens, w, n_groups, codes_off}; the dictionary area
+        // {n_bytes, 0, 0, 0, entries, bytes, >= 4 bytes of padding}
+        const uint8_t *D = A.dict + ck.dict_off;
+        ok = clen >= 16 && ck.dict_bytes >= 16;
+        if (ok) {
+            nt = first32(ld32u(s));
+            w = first32(ld32u(s + 4));
+            ng = first32(ld32u(s + 8));
+            co = first32(ld32u(s + 12));
+            nb = first32(ld32u(D));
+        }
+        ne = ck.dict_count;
+        go = 16;
+        ebase = D + 16;
+        bbase = D + 16 + 4ull * ne;
+        ok = ok && ne >= 1 && 16ull + 4ull * ne + nb + 4 <= ck.dict_bytes && co >= 16ull + 4ull * ng;
+    } else {
+        // header {n_tokens, n_entries, w, n_groups, ent_off, bytes_off,
+        // codes_off, n_bytes}; entries, bytes and >= 4 bytes of padding
+        // inside the chunk, in that order
+        uint32_t eo = 0, bo = 0;
+        ok = clen >= 32;
+        if (ok) {
+            nt = first32(ld32u(s));
+            ne = first32(ld32u(s + 4));
+            w = first32(ld32u(s + 8));
+            ng = first32(ld32u(s + 12));
+            eo = first32(ld32u(s + 16));
+            bo = first32(ld32u(s + 20));
+            co = first32(ld32u(s + 24));
+            nb = first32(ld32u(s + 28));
+        }
+        go = 32;
+        ebase = s + eo;
+        bbase = s + bo;
+        ok = ok && ne >= 1 && (eo & 3u) == 0 && eo >= 32ull + 4ull * ng && uint64_t(eo) + 4ull * ne <= bo &&
+             uint64_t(bo) + nb + 4 <= co;
     }
-    const uint32_t nt = first32(ld32u(s)), ne = first32(ld32u(s + 4)), w = first32(ld32u(s + 8));
-    const uint32_t ng = first32(ld32u(s + 12)), eo = first32(ld32u(s + 16));
-    const uint32_t bo = first32(ld32u(s + 20)), co = first32(ld32u(s + 24)), nb = first32(ld32u(s + 28));
     const uint64_t ncw = (uint64_t(nt) * w + 31) / 32;
-    // every field used below is checked against the stream's size first:
-    // entries, entry bytes (with their 4 bytes of padding) and codes in
-    // order inside the chunk, so no view or load leaves it
-    const bool hdr_ok = ne >= 1 && w <= 32 && ng == (uint64_t(nt) + 63) / 64 && (eo & 3u) == 0 &&
-                        eo >= 32ull + 4ull * ng && uint64_t(eo) + 4ull * ne <= bo &&
-                        uint64_t(bo) + nb + 4 <= co && co <= clen &&
-                        (ck.codec == C_SDICT_ANS || uint64_t(co) + 4 * ncw <= clen);
-    if (!hdr_ok || t.b > ng || t.a >= t.b) {
+    ok = ok && w <= 32 && ng == (uint64_t(nt) + 63) / 64 && co <= clen && (staged || uint64_t(co) + 4 * ncw <= clen);
+    if (!ok || t.b > ng || t.a >= t.b) {
         flag(A.err, ERR_CORRUPT);
         return;
     }
-    const uint32_t *ents = reinterpret_cast<const uint32_t *>(s + eo);
-    // SDICT_ANS: the indices were ANS-decoded into the scratch area by an
-    // earlier launch (the codes checks below hold for them all the same)
-    const uint32_t *codes = reinterpret_cast<const uint32_t *>(
-        ck.codec == C_SDICT_ANS ? A.out_tab[kScratchCol] + ck.aux_off : s + co);
-    // the entry bytes run up to the codes (at least 4 bytes of padding)
-    const __amdgpu_buffer_rsrc_t rs_out = __builtin_amdgcn_make_buffer_rsrc(out, 0, int(plain), 0x00020000);
+    const uint32_t *ents = reinterpret_cast<const uint32_t *>(ebase);
+    const uint32_t *codes = reinterpret_cast<const uint32_t *>(staged ? A.out_tab[kScratchCol] + ck.aux_off : s + co);
+    // the entry bytes with the 4 bytes before them (entries or header) and the
+    // 4 after (padding): every dword read below lies inside this view
     const __amdgpu_buffer_rsrc_t rs_ent =
-        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(s + bo), 0, int(co - bo), 0x00020000);
-    const uint32_t plain4 = plain >= 4 ? plain - 3 : 0, nent4 = co - bo - 3;
-    const uint32_t mis = uint32_t(reinterpret_cast<uintptr_t>(out) & (kSdBlk - 1));
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(bbase - 4), 0, int(nb + 8), 0x00020000);
+    const uint32_t ua = first32(ld32u(s + go + 4ull * t.a));
+    const uint32_t ub = t.b < ng ? first32(ld32u(s + go + 4ull * t.b)) : plain;
+    if (ua >= ub || ub > plain) {
+        flag(A.err, ERR_CORRUPT);
+        return;
+    }
+    // buffer byte k holds output byte sbase + k; out + sbase is 16-aligned
+    int64_t sbase = int64_t(ua) - int64_t((reinterpret_cast<uintptr_t>(out) + ua) & 15u);
+    const u32x4 zero4 = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (uint32_t k = 0; k < kSdBufWords / 256; k++) *reinterpret_cast<u32x4 *>(buf + 4 * (64 * k + lane)) = zero4;
+    wave_fence();
     for (uint32_t g = t.a; g < t.b; g++) {
         const uint32_t i = 64 * g + lane;
         const bool act = i < nt;
@@ -1140,18 +1194,71 @@ ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, 
         // an entry's bytes (and the dword read at each) lie in the entry bytes
         const bool bad_ent = act && (len == 0 || len > kSdMaxToken || uint64_t(eoff) + len > nb);
         const uint32_t incl = scan_add32(len), total = rl32(incl, 63);
-        const uint32_t pos = first32(ld32u(s + 32 + 4 * g));
-        const uint32_t end = g + 1 < ng ? first32(ld32u(s + 32 + 4 * (g + 1))) : plain;
-        if (any(bad_code || bad_ent) || uint64_t(pos) + total != end || end > plain) {
+        const uint32_t pos = first32(ld32u(s + go + 4ull * g));
+        const uint32_t end = g + 1 < ng ? first32(ld32u(s + go + 4ull * (g + 1))) : plain;
+        if (any(bad_code || bad_ent) || uint64_t(pos) + total != end || end > ub || pos < ua) {
             flag(A.err, ERR_CORRUPT);
             return;
         }
-        const uint32_t P = pos + incl - len;
-        const uint32_t d = 0x80000000u + (eoff - P);  // source index = p + d - 2^31
-        copy_segments<kSdBlk, false>(row, out, rs_out, rs_ent, plain4, nent4, mis, pos, end,
-                         [&](uint32_t, uint32_t, auto &&put) {
-                             if (act) put(P, d);
-                         });
+        // OR the token's bytes into the buffer, one dword at a time:
+        // dword j of the token's span starts at token byte 4j - (o & 3)
+        const uint32_t o = uint32_t(int64_t(pos + incl - len) - sbase);  // buffer byte of the token
+        const uint32_t nd = act ? ((o & 3u) + len + 3) >> 2 : 0u;
+        auto part = [&](uint32_t j, uint32_t v) {
+            const int32_t q0 = int32_t(4 * j) - int32_t(o & 3u);
+            const uint32_t lo = q0 < 0 ? uint32_t(-q0) : 0u;
+            const int32_t hi = int32_t(len) - q0;  // bytes of the token from this dword's start
+            const uint32_t m = (0xFFFFFFFFu << (8 * lo)) & (hi >= 4 ? 0xFFFFFFFFu : ((1u << (8 * hi)) - 1u));
+            __hip_atomic_fetch_or(buf + (o >> 2) + j, v & m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        };
+        auto ld = [&](uint32_t j) {
+            const int32_t q0 = int32_t(4 * j) - int32_t(o & 3u);
+            return __builtin_amdgcn_raw_buffer_load_b32(rs_ent, int(j < nd ? uint32_t(int32_t(eoff) + q0 + 4)
+                                                                             : 0x7FFFFFF0u), 0, 0);
+        };
+        // the first four dwords' loads in flight together (tokens of up
+        // to 13 bytes), then any further dwords
+        const uint32_t v0 = ld(0), v1 = ld(1), v2 = ld(2), v3 = ld(3);
+        if (0 < nd) part(0, v0);
+        if (1 < nd) part(1, v1);
+        if (2 < nd) part(2, v2);
+        if (3 < nd) part(3, v3);
+        for (uint32_t j = 4; any(j < nd); j++) {
+            const uint32_t v = ld(j);
+            if (j < nd) part(j, v);
+        }
+        // write out the whole blocks when enough are done, and everything at
+        // the unit's end
+        const uint32_t fill = uint32_t(int64_t(end) - sbase);
+        const bool last = g + 1 == t.b;
+        if (!last && fill < kSdFlushBytes) continue;
+        const uint32_t nblk = last ? (fill + 15) / 16 : fill / 16;
+        wave_fence();
+        for (uint32_t b = lane; b < nblk; b += 64) {
+            const int64_t q = sbase + 16 * int64_t(b);
+            const u32x4 v = *reinterpret_cast<const u32x4 *>(buf + 4 * b);
+            *reinterpret_cast<u32x4 *>(buf + 4 * b) = zero4;
+            if (q >= int64_t(ua) && q + 16 <= int64_t(ub)) {
+                *gp(reinterpret_cast<u32x4 *>(out + q)) = v;
+            } else {
+                for (uint32_t k = 0; k < 16; k++)
+                    if (q + k >= int64_t(ua) && q + k < int64_t(ub))
+                        gp(out)[q + k] = uint8_t(v[k >> 2] >> (8 * (k & 3u)));
+            }
+        }
+        if (last) break;
+        // carry the unfinished block (its bytes from the next group are
+        // still to come) to the front
+        wave_fence();
+        uint32_t carry = 0;
+        if (lane < 4) {
+            carry = buf[4 * nblk + lane];
+            buf[4 * nblk + lane] = 0;
+        }
+        wave_fence();
+        if (lane < 4) buf[lane] = carry;
+        wave_fence();
+        sbase += 16 * int64_t(nblk);
     }
 }
 
@@ -1347,8 +1454,7 @@ __global__ __launch_bounds__(1024) void k_decode_kind(LaunchArgs A) {
     const uint32_t waves = blockDim.x / 64;
     // String-dictionary: the tiles of a chunk share its dictionary, so
     // neighbouring tiles go to the same XCD (and its L2)
-    const uint32_t blk = KIND == K_SDICT ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
-    const uint32_t u = A.kind_begin[KIND] + blk * waves + first32(threadIdx.x / 64);
+    const uint32_t u = A.kind_begin[KIND] + blockIdx.x * waves + first32(threadIdx.x / 64);
     if (u >= A.kind_begin[KIND + 1]) return;
     const Tile t = A.tiles[u];
     const ChunkDesc ck = A.chunks[t.chunk];
@@ -1366,9 +1472,6 @@ __global__ __launch_bounds__(1024) void k_decode_kind(LaunchArgs A) {
         unit_fp<8, true, 8>(A, t, ck);
     } else if constexpr (KIND == K_DICT128) {
         unit_fp<16, true, 8>(A, t, ck);
-    } else if constexpr (KIND == K_SDICT) {
-        __shared__ uint32_t sd_rows[16][64 * kSdBlk];
-        unit_sdict(A, t, ck, sd_rows[threadIdx.x / 64]);
     } else if constexpr (KIND == K_RLE32) {
         __shared__ uint32_t rle_slots[16][256];
         if (ck.codec == C_DSTRIDE_BP) unit_rle<uint32_t, true>(A, t, ck, rle_slots[threadIdx.x / 64]);
@@ -1379,6 +1482,8 @@ __global__ __launch_bounds__(1024) void k_decode_kind(LaunchArgs A) {
         else unit_rle<uint64_t, false>(A, t, ck, rle_slots[threadIdx.x / 64]);
     }
 }
+
+void launch_sdict(const LaunchArgs &A, uint32_t waves, hipStream_t st);
 
 // LZ77: one unit (chunk) per wave; each wave's LDS row is dynamic shared
 // memory, 64 * BLK dwords.
@@ -1398,7 +1503,7 @@ void launch_ans(const LaunchArgs &A, uint32_t waves, hipStream_t st);
 
 // Host launchers, one per kind, each defined in its kind's translation unit.
 #define ZF_KIND_LAUNCHERS(X)                                                                       \
-    X(K_RLE64, launch_rle64) X(K_RLE32, launch_rle32) X(K_SDICT, launch_sdict)  \
+    X(K_RLE64, launch_rle64) X(K_RLE32, launch_rle32)                            \
     X(K_DICT128, launch_dict128) X(K_DICT64, launch_dict64) X(K_DICT32, launch_dict32)              \
     X(K_FOR64, launch_for64) X(K_FOR32, launch_for32) X(K_F2I, launch_f2i) X(K_PLAIN, launch_plain)
 #define ZF_DECLARE_LAUNCHER(KIND, NAME) void NAME(const LaunchArgs &A, uint32_t waves, hipStream_t st);

@@ -20,14 +20,16 @@ static void add_chunk(WorkTables &w, const zf_column &col, uint32_t ci, uint32_t
     d.comp_len = c.comp_len;
     d.n_elems = c.n_elems;
     d.dict_count = col.view.dict_count;
+    d.dict_bytes = col.view.dict_bytes;
     d.col = uint16_t(col_idx);
     d.codec = c.codec;
     d.dtype = uint8_t(col.view.dtype);
-    if (c.codec == C_SDICT_ANS) {
+    const bool col_dict = c.codec == C_SDICT_COL || c.codec == C_SDICT_COL_ANS;
+    if (c.codec == C_SDICT_ANS || c.codec == C_SDICT_COL_ANS) {
         // first stage: ANS-decode the packed entry indices into the scratch
         // area; the String-dictionary stage reads them from there
         const uint8_t *s = col.buf.p + c.comp_off;
-        const uint32_t nt = rd32(s), wd = rd32(s + 8), co = rd32(s + 24);
+        const uint32_t nt = rd32(s), wd = rd32(s + (col_dict ? 4 : 8)), co = rd32(s + (col_dict ? 12 : 24));
         const uint64_t ncb = 4 * ((uint64_t(nt) * wd + 31) / 32);
         d.aux_off = w.scratch_bytes;
         if (ncb) {
@@ -100,8 +102,8 @@ static void add_chunk(WorkTables &w, const zf_column &col, uint32_t ci, uint32_t
     case K_SDICT: {
         // whole groups of 64 tokens, about `unit` output bytes per unit
         const uint8_t *s = col.buf.p + c.comp_off;
-        const uint32_t ng = rd32(s + 12), n = c.plain_len;
-        auto gof = [&](uint32_t g) { return g < ng ? rd32(s + 32 + 4ull * g) : n; };
+        const uint32_t ng = rd32(s + (col_dict ? 8 : 12)), n = c.plain_len, go = col_dict ? 16 : 32;
+        auto gof = [&](uint32_t g) { return g < ng ? rd32(s + go + 4ull * g) : n; };
         for (uint32_t g = 0; g < ng;) {
             uint32_t gb = g + 1;
             while (gb < ng && gof(gb) - gof(g) < unit) gb++;
@@ -209,7 +211,7 @@ void build_plan(zf_plan_t *P, const zf_column *const *cols, uint32_t n_cols, int
     for (uint32_t c = 0; c < n_cols; c++) {
         const zf_column &col = *cols[c];
         if (!col.view.dict_count) continue;
-        const uint64_t len = uint64_t(col.view.dict_count) * elem_size(col.view.dtype);
+        const uint64_t len = col.view.dict_bytes;
         dict_at[c] = dict_total;
         P->dict_copies.push_back({col.buf.p + col.view.dict_off, dict_total, len});
         dict_total = align_up(dict_total + len, 256);

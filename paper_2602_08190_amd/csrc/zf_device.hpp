@@ -21,7 +21,8 @@ constexpr uint32_t kSdMaxToken = 64;
 
 // Codec / dtype codes, as in zf.h.
 enum : uint8_t { C_PLAIN = 1, C_FOR_BP = 2, C_DICT_BP = 3, C_DELTA_BP = 4, C_RLE_DELTA_BP = 5, C_LZ77 = 6,
-                 C_F2I_BP = 7, C_ANS = 8, C_DSTRIDE_BP = 9, C_SDICT_BP = 10, C_SDICT_ANS = 11 };
+                 C_F2I_BP = 7, C_ANS = 8, C_DSTRIDE_BP = 9, C_SDICT_BP = 10, C_SDICT_ANS = 11,
+                 C_SDICT_COL = 12, C_SDICT_COL_ANS = 13 };
 enum : uint8_t { D_I32 = 1, D_I64 = 2, D_BYTES = 3, D_FIXED16 = 4, D_F64 = 5 };
 
 // Kernel kinds: one device routine per (codec class, value width).  The
@@ -54,9 +55,10 @@ struct ChunkDesc {
     uint16_t col;         // column index (output table slot)
     uint8_t codec;
     uint8_t dtype;
-    uint64_t aux_off;     // SDICT_ANS: offset of the decoded entry indices in the scratch area
+    uint64_t aux_off;     // SDICT_ANS, SDICT_COL_ANS: offset of the decoded entry indices in the scratch area
+    uint64_t dict_bytes;  // size of the column's dictionary area
 };
-static_assert(sizeof(ChunkDesc) == 48, "ChunkDesc layout");
+static_assert(sizeof(ChunkDesc) == 56, "ChunkDesc layout");
 
 // One unit of work for one wavefront.
 //   FOR / DICT / F2I: a = first block, b = number of blocks

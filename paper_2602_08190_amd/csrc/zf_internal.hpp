@@ -94,6 +94,7 @@ struct ChunkInfo {
 struct ColumnView {
     uint32_t dtype = 0, codec = 0, n_chunks = 0, dict_count = 0;
     uint64_t n_elems = 0, plain_bytes = 0, dict_off = 0, total_bytes = 0;
+    uint64_t dict_bytes = 0;  // size of the dictionary area
     std::vector<ChunkInfo> chunks;
 };
 
@@ -102,7 +103,8 @@ ColumnView parse_column(const uint8_t *p, uint64_t len);
 // Validate the directory of chunk i's stream (host side; throws ZF_E_CORRUPT).
 void check_stream(const ColumnView &v, const uint8_t *blob, uint32_t i);
 
-// Lay out a column: header, table, dictionary, streams (16-aligned).
+// Lay out a column: header, table, dictionary (dict_len bytes), streams
+// (16-aligned).
 struct EncodedChunk {
     std::vector<uint8_t> bytes;
     uint32_t n_elems;
@@ -111,7 +113,7 @@ struct EncodedChunk {
 };
 void assemble_column(HostBuf &out, bool pinned, uint32_t dtype, uint64_t n_elems,
                      const std::vector<EncodedChunk> &chunks, const uint8_t *dict,
-                     uint32_t dict_count);
+                     uint32_t dict_count, uint64_t dict_len);
 
 }  // namespace zf
 

@@ -17,9 +17,11 @@ LIB_PATH = os.path.join(HERE, "libzf.so")
 I32, I64, BYTES, FIXED16, F64 = 1, 2, 3, 4, 5
 AUTO, PLAIN, FOR_BP, DICT_BP, DELTA_BP, RLE_DELTA_BP, LZ77, F2I_BP, ANS, DSTRIDE_BP, SDICT_BP, SDICT_ANS = \
     0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11
+SDICT_COL, SDICT_COL_ANS = 12, 13
 CODEC_NAMES = {PLAIN: "PLAIN", FOR_BP: "FOR_BP", DICT_BP: "DICT_BP", DELTA_BP: "DELTA_BP",
                RLE_DELTA_BP: "RLE_DELTA_BP", LZ77: "LZ77", F2I_BP: "F2I_BP", ANS: "ANS",
-               DSTRIDE_BP: "DSTRIDE_BP", SDICT_BP: "SDICT_BP", SDICT_ANS: "SDICT_ANS"}
+               DSTRIDE_BP: "DSTRIDE_BP", SDICT_BP: "SDICT_BP", SDICT_ANS: "SDICT_ANS",
+               SDICT_COL: "SDICT_COL", SDICT_COL_ANS: "SDICT_COL_ANS"}
 ELEM_SIZE = {I32: 4, I64: 8, BYTES: 1, FIXED16: 16, F64: 8}
 OK, E_INVALID, E_UNSUPPORTED, E_CORRUPT, E_NOMEM, E_HIP, E_TOO_SMALL, E_STATE = range(8)
 
@@ -382,7 +384,7 @@ def kind_of_column(col):
         return "F2I"
     if codec == ANS:
         return "ANS"
-    if codec in (SDICT_BP, SDICT_ANS):
+    if codec in (SDICT_BP, SDICT_ANS, SDICT_COL, SDICT_COL_ANS):
         return "SDICT"
     if codec in (DELTA_BP, RLE_DELTA_BP, DSTRIDE_BP):
         return "RLE32" if dt == I32 else "RLE64"

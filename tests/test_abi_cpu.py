@@ -205,6 +205,59 @@ def test_sdict_ans_host_validation():
             zf.Column.from_bytes(t, pinned=False)
 
 
+def test_encoder_byte_identical_sdict_col():
+    """String-dictionary over a column dictionary: the dictionary (token
+    counts over all chunks, encoded by several host threads) and every chunk
+    stream equal the oracle's, for text in uneven chunks, random bytes, long
+    runs without separators, row ends only, tiny chunks, and a column that
+    mixes SDICT_COL and SDICT_COL_ANS chunks with PLAIN ones."""
+    r = g.rng(47)
+    text = g.text_column(500000, 5)
+    cases = [(text, [1, 100, 65536, 500000 - 65637], None),
+             (np.frombuffer(r.bytes(30000), np.uint8), [30000], None),
+             (np.frombuffer(b"a" * 300 + b" b.\nb\n " * 50, np.uint8), [150, 500], None),
+             (np.full(5000, ord("\n"), np.uint8), [64, 4936], None)]
+    for codec in (zf.SDICT_COL, zf.SDICT_COL_ANS):
+        for x, ce, _ in cases:
+            ours, ref = same_streams(x, codec, ce)
+            assert ours.tobytes() == ref.tobytes(), codec
+            assert np.array_equal(zo.decode(ours), x)
+    ce = [70000, 100000, 130000, 200000]
+    cc = [zf.SDICT_COL, zf.PLAIN, zf.SDICT_COL_ANS, zf.SDICT_COL]
+    ours, ref = same_streams(text, 0, ce, cc)
+    assert ours.tobytes() == ref.tobytes()
+    assert np.array_equal(zo.decode(ours), text)
+    col = compress(text, zf.SDICT_COL, chunk_bytes=(16 << 10, 128 << 10), threads=5)
+    assert np.array_equal(zo.decode(col.bytes()), text)
+
+
+def test_sdict_col_host_validation():
+    x = np.frombuffer(b"the cat. the dog\nthe cat " * 3, np.uint8)
+    b = zo.encode(x, zo.SDICT_COL, [30, 45]).copy()
+    d = zo.inspect(b)["dict_off"]
+    at = zo.chunks(b)[0]["comp_off"]
+
+    def rejects(off, val):
+        t = b.copy()
+        t[off:off + 4] = np.frombuffer(np.uint32(val).tobytes(), np.uint8)
+        if off >= d and off < at:   # keep the table CRC right so that the entry check is what fails
+            ne, nb = int(b[28:32].view(np.uint32)[0]), int(b[d:d + 4].view(np.uint32)[0])
+            tl, dl = 32 * 2, 16 + 4 * ne + (nb + 4 + 15) // 16 * 16
+            crc = zo.crc32(bytes(t[64:64 + tl]) + bytes(t[d:d + dl]))
+            t[48:52] = np.frombuffer(np.uint32(crc).tobytes(), np.uint8)
+            t[60:64] = np.frombuffer(np.uint32(zo.crc32(bytes(t[:60]))).tobytes(), np.uint8)
+        with pytest.raises(zf.ZfError):
+            zf.Column.from_bytes(t, pinned=False)
+    rejects(d + 16, 0)                     # entry of length 0
+    rejects(d + 16 + 16, 20 | (4 << 24))   # entry past the entry bytes (21 of them)
+    rejects(d + 4, 1)                      # a nonzero reserved word
+    rejects(at + 4, 2)                     # width does not match the entry count
+    rejects(at + 16, 1)                    # first group offset not 0
+    rejects(at + 12, 48)                   # codes offset
+    ok = zf.Column.from_bytes(b, pinned=False)
+    assert np.array_equal(zo.decode(ok.bytes()), x)
+
+
 def test_encoder_byte_identical_fixed16_and_mixed():
     x = g.fixed16_column(30000, 25, 4)
     ours, ref = same_streams(x, zf.DICT_BP, [10000, 20000])

@@ -207,6 +207,58 @@ def test_sdict_text_bytes_and_tiles(sd_bytes):
     check(cols, decode_image(cols, persistent=True, tiles={"SDICT": dict(unit=sd_bytes, waves_per_block=8)}), xs)
 
 
+@pytest.mark.parametrize("sd_bytes", [256, 4096, 65536])
+def test_sdict_col_text_bytes_and_tiles(sd_bytes):
+    """String-dictionary over a column dictionary: generated text (product
+    and oracle streams), random bytes (tokens of up to 64 bytes, groups of up
+    to 4 KiB), long runs, row ends only, tiny and uneven chunks; every tile,
+    per-kind and persistent launches."""
+    log("sdict_col", sd_bytes)
+    r = g.rng(53)
+    text = g.text_column(3_000_000, 6)
+    long_tokens = np.frombuffer((b"a" * 63 + b" ") * 300 + (b"b" * 63 + b"\n") * 300, np.uint8)
+    xs = [text, text[:200001],
+          np.frombuffer(r.bytes(100000), np.uint8),
+          np.frombuffer(b"a" * 300 + b" b.\n " * 50 + b"z" * 65, np.uint8),
+          np.full(7000, ord("\n"), np.uint8),
+          long_tokens]
+    cols = [zf.Column.compress(xs[0], zf.SDICT_COL, chunk_bytes=(16 << 10, 1 << 20), seed=3),
+            zf.Column.from_bytes(zo.encode(xs[1], zo.SDICT_COL, [1, 64, 65536, 200001 - 65601])),
+            zf.Column.compress(xs[2], zf.SDICT_COL, chunk_elems=[33333, 66667]),
+            zf.Column.compress(xs[3], zf.SDICT_COL, chunk_elems=[1, 499, len(xs[3]) - 500]),
+            zf.Column.compress(xs[4], zf.SDICT_COL, chunk_elems=[3, 6997]),
+            zf.Column.compress(xs[5], zf.SDICT_COL, chunk_elems=[len(xs[5]) - 4097, 4097])]
+    check(cols, decode_image(cols, tiles={"SDICT": dict(unit=sd_bytes)}), xs)
+    check(cols, decode_image(cols, persistent=True, tiles={"SDICT": dict(unit=sd_bytes, waves_per_block=8)}), xs)
+
+
+@pytest.mark.parametrize("mode", ["graphs", "staged"])
+def test_sdict_col_ans_two_stage_decode(mode):
+    """String-dictionary over a column dictionary | BP | ANS, mixed with
+    the other String-dictionary codecs, LZ77 and FOR; the staged run copies
+    the column dictionaries once and sends the chunks through small slots."""
+    log("sdict_col_ans", mode)
+    r = g.rng(59)
+    text = g.text_column(2_000_000, 9)
+    xs = [text, text[:150001], np.frombuffer(r.bytes(60000), np.uint8),
+          np.frombuffer(b"x\n" * 3000, np.uint8), g.text_column(300000, 10), g.for_bp_column(100000, 3)]
+    cols = [zf.Column.compress(xs[0], zf.SDICT_COL_ANS, chunk_bytes=(16 << 10, 1 << 20), seed=5),
+            zf.Column.from_bytes(zo.encode(xs[1], zo.SDICT_COL_ANS, [1, 64, 65536, 150001 - 65601])),
+            zf.Column.compress(xs[2], zf.SDICT_COL_ANS, chunk_elems=[30000, 30000]),
+            zf.Column.compress(xs[3], zf.SDICT_COL_ANS, chunk_elems=[6000]),
+            zf.Column.compress(xs[4], zf.SDICT_COL),
+            zf.Column.compress(xs[5], zf.FOR_BP)]
+    cols.append(zf.Column.compress(xs[4], zf.SDICT_ANS))
+    xs.append(xs[4])
+    cols.append(zf.Column.compress(xs[4], zf.LZ77))
+    xs.append(xs[4])
+    if mode == "staged":
+        outs, _ = decode_staged(cols, slot_bytes=1 << 18)
+        check(cols, outs, xs)
+        return
+    check(cols, decode_image(cols), xs)
+
+
 @pytest.mark.parametrize("mode", ["graphs", "no_graphs", "staged", "persistent_rejected"])
 def test_sdict_ans_two_stage_decode(mode):
     """String-dictionary | BP | ANS: the ANS stage writes the entry indices to
@@ -604,7 +656,7 @@ def test_device_checks_headers_that_differ_from_the_plan():
     flags = g.returnflag_column(200000, 0.25, 0.5, 11)
     filler = g.for_bp_column(100000, 2)
     cols = [zf.Column.compress(text, zf.SDICT_BP), zf.Column.compress(flags, zf.ANS),
-            zf.Column.compress(filler, zf.FOR_BP)]
+            zf.Column.compress(filler, zf.FOR_BP), zf.Column.compress(text, zf.SDICT_COL)]
     plan = zf.Plan(cols, device=0)
     img = zf.upload_image(plan, cols)
     outs = zf.empty_outputs(cols)
@@ -641,6 +693,11 @@ def test_device_checks_headers_that_differ_from_the_plan():
     word = u32(fo)
     word += 1 if f_last % 2 == 0 else 1 << 16
     cases["ANS frequencies total M + 1"] = [(fo, word)]
+    # the column dictionary's byte count beyond its area; a codes offset
+    # inside the group offsets
+    dcol = plan.image_offset(3) + zo.inspect(cols[3].bytes())["dict_off"]
+    cases["column dictionary bytes beyond its area"] = [(dcol, u32(dcol) + 64)]
+    cases["codes offset inside the group offsets"] = [(at(3, 12), 16)]
     for name, edits in cases.items():
         log(" ", name)
         bad = patched(edits)
@@ -651,5 +708,5 @@ def test_device_checks_headers_that_differ_from_the_plan():
         plan.clear_error()
     plan.decompress_async(img, img.numel(), outs)
     plan.sync()
-    for x, o in zip([text, flags, filler], outs):
+    for x, o in zip([text, flags, filler, text], outs):
         assert np.array_equal(o.cpu().numpy(), x)
