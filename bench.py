@@ -457,6 +457,10 @@ def main():
                       "GBps": round(kb / (med * 1e-3) / 1e9, 1),
                       "frac_of_hbm_peak": round(kb / (med * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
         log(f"kernel {key:8s} in the step: {med:.3f} ms, {kinds[key]['GBps']:.1f} GB/s of algorithmic bytes")
+    for key in groups:
+        if "+" in key:   # the launches of a two-stage group, each on its own
+            for k in key.split("+"):
+                kinds[key][f"{k}_ms_median"] = round(pct(per[k], 50), 4)
     dom = max(kinds, key=lambda k: kinds[k]["ms_median"])
 
     result = {

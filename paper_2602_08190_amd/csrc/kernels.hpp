@@ -1172,93 +1172,145 @@ ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, 
         flag(A.err, ERR_CORRUPT);
         return;
     }
+    const uint32_t oa = uint32_t(reinterpret_cast<uintptr_t>(out) & 15u);
     // buffer byte k holds output byte sbase + k; out + sbase is 16-aligned
-    int64_t sbase = int64_t(ua) - int64_t((reinterpret_cast<uintptr_t>(out) + ua) & 15u);
+    int64_t sbase = int64_t(ua) - int64_t((oa + ua) & 15u);
     const u32x4 zero4 = {0u, 0u, 0u, 0u};
 #pragma unroll
     for (uint32_t k = 0; k < kSdBufWords / 256; k++) *reinterpret_cast<u32x4 *>(buf + 4 * (64 * k + lane)) = zero4;
     wave_fence();
-    for (uint32_t g = t.a; g < t.b; g++) {
+
+    // Three stages run ahead of the group being written: the packed index
+    // words of group g + 2 and the entries of group g + 1 are loaded, and
+    // group g + 1's token positions are computed and its entry bytes loaded,
+    // before group g's bytes are ORed into the buffer.
+    auto words_of = [&](uint32_t g, uint32_t &w0, uint32_t &w1) {
+        w0 = w1 = 0;
         const uint32_t i = 64 * g + lane;
-        const bool act = i < nt;
-        // entry index: w bits at bit i * w (w <= 32: two words)
-        uint32_t code = 0;
-        if (act && w) {
-            const uint64_t bit = uint64_t(i) * w, k = bit >> 5;
-            const uint32_t w0 = codes[k], w1 = k + 1 < ncw ? codes[k + 1] : 0u;
-            code = uint32_t((uint64_t(w0) | (uint64_t(w1) << 32)) >> (bit & 31u)) & mask32(w);
+        if (g < t.b && i < nt && w) {
+            const uint64_t k = (uint64_t(i) * w) >> 5;
+            w0 = codes[k];
+            w1 = k + 1 < ncw ? codes[k + 1] : 0u;
         }
-        const bool bad_code = act && code >= ne;
-        const uint32_t e = (act && !bad_code) ? ents[code] : 0u;
-        const uint32_t len = e >> 24, eoff = e & 0xFFFFFFu;
+    };
+    // entry of group g's token from its index words; bad: index past the entries
+    auto entry_of = [&](uint32_t g, uint32_t w0, uint32_t w1, bool &bad) -> uint32_t {
+        const uint32_t i = 64 * g + lane;
+        const bool act = g < t.b && i < nt;
+        const uint32_t code =
+            w ? uint32_t((uint64_t(w0) | (uint64_t(w1) << 32)) >> ((uint64_t(i) * w) & 31u)) & mask32(w) : 0u;
+        bad = act && code >= ne;
+        return (act && !bad) ? ents[code] : 0u;
+    };
+    struct Grp {
+        uint32_t len, eoff, P, end;  // token length and entry offset, token start, group end
+        uint32_t v0, v1, v2, v3;     // the first four dwords of the token's bytes
+    };
+    // positions and checks of group g from its entries, then its first loads
+    auto prepare = [&](uint32_t g, uint32_t e, bool bad_code, Grp &G) -> bool {
+        const bool act = 64 * g + lane < nt;
+        G.len = e >> 24;
+        G.eoff = e & 0xFFFFFFu;
         // an entry's bytes (and the dword read at each) lie in the entry bytes
-        const bool bad_ent = act && (len == 0 || len > kSdMaxToken || uint64_t(eoff) + len > nb);
-        const uint32_t incl = scan_add32(len), total = rl32(incl, 63);
+        const bool bad_ent = act && (G.len == 0 || G.len > kSdMaxToken || uint64_t(G.eoff) + G.len > nb);
+        const uint32_t incl = scan_add32(G.len), total = rl32(incl, 63);
         const uint32_t pos = first32(ld32u(s + go + 4ull * g));
-        const uint32_t end = g + 1 < ng ? first32(ld32u(s + go + 4ull * (g + 1))) : plain;
-        if (any(bad_code || bad_ent) || uint64_t(pos) + total != end || end > ub || pos < ua) {
-            flag(A.err, ERR_CORRUPT);
-            return;
-        }
-        // OR the token's bytes into the buffer, one dword at a time:
-        // dword j of the token's span starts at token byte 4j - (o & 3)
-        const uint32_t o = uint32_t(int64_t(pos + incl - len) - sbase);  // buffer byte of the token
-        const uint32_t nd = act ? ((o & 3u) + len + 3) >> 2 : 0u;
-        auto part = [&](uint32_t j, uint32_t v) {
-            const int32_t q0 = int32_t(4 * j) - int32_t(o & 3u);
-            const uint32_t lo = q0 < 0 ? uint32_t(-q0) : 0u;
-            const int32_t hi = int32_t(len) - q0;  // bytes of the token from this dword's start
-            const uint32_t m = (0xFFFFFFFFu << (8 * lo)) & (hi >= 4 ? 0xFFFFFFFFu : ((1u << (8 * hi)) - 1u));
-            __hip_atomic_fetch_or(buf + (o >> 2) + j, v & m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        };
+        G.end = g + 1 < ng ? first32(ld32u(s + go + 4ull * (g + 1))) : plain;
+        if (any(bad_code || bad_ent) || uint64_t(pos) + total != G.end || G.end > ub || pos < ua) return false;
+        G.P = pos + incl - G.len;
+        // token byte 4j - ((oa + P) & 3) begins buffer dword j of the token
+        const uint32_t m = (oa + G.P) & 3u, nd = act ? (m + G.len + 3) >> 2 : 0u;
         auto ld = [&](uint32_t j) {
-            const int32_t q0 = int32_t(4 * j) - int32_t(o & 3u);
-            return __builtin_amdgcn_raw_buffer_load_b32(rs_ent, int(j < nd ? uint32_t(int32_t(eoff) + q0 + 4)
-                                                                             : 0x7FFFFFF0u), 0, 0);
+            return __builtin_amdgcn_raw_buffer_load_b32(
+                rs_ent, int(j < nd ? uint32_t(int32_t(G.eoff) + int32_t(4 * j) - int32_t(m) + 4) : 0x7FFFFFF0u), 0, 0);
         };
-        // the first four dwords' loads in flight together (tokens of up
-        // to 13 bytes), then any further dwords
-        const uint32_t v0 = ld(0), v1 = ld(1), v2 = ld(2), v3 = ld(3);
-        if (0 < nd) part(0, v0);
-        if (1 < nd) part(1, v1);
-        if (2 < nd) part(2, v2);
-        if (3 < nd) part(3, v3);
-        for (uint32_t j = 4; any(j < nd); j++) {
-            const uint32_t v = ld(j);
+        G.v0 = ld(0);
+        G.v1 = ld(1);
+        G.v2 = ld(2);
+        G.v3 = ld(3);
+        return true;
+    };
+    // OR group G's token bytes into the buffer
+    auto stage = [&](const Grp &G, uint32_t g) {
+        const bool act = 64 * g + lane < nt;
+        const uint32_t o = uint32_t(int64_t(G.P) - sbase), m = o & 3u;
+        const uint32_t nd = act ? (m + G.len + 3) >> 2 : 0u;
+        auto part = [&](uint32_t j, uint32_t v) {
+            const int32_t q0 = int32_t(4 * j) - int32_t(m);
+            const uint32_t lo = q0 < 0 ? uint32_t(-q0) : 0u;
+            const int32_t hi = int32_t(G.len) - q0;  // bytes of the token from this dword's start
+            const uint32_t msk = (0xFFFFFFFFu << (8 * lo)) & (hi >= 4 ? 0xFFFFFFFFu : ((1u << (8 * hi)) - 1u));
+            __hip_atomic_fetch_or(buf + (o >> 2) + j, v & msk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        };
+        if (0 < nd) part(0, G.v0);
+        if (1 < nd) part(1, G.v1);
+        if (2 < nd) part(2, G.v2);
+        if (3 < nd) part(3, G.v3);
+        for (uint32_t j = 4; any(j < nd); j++) {  // tokens of more than 13 bytes
+            const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(
+                rs_ent, int(j < nd ? uint32_t(int32_t(G.eoff) + int32_t(4 * j) - int32_t(m) + 4) : 0x7FFFFFF0u), 0, 0);
             if (j < nd) part(j, v);
         }
+    };
+
+    Grp cur, nxt;
+    uint32_t w0, w1, e1 = 0;
+    bool bad = false, bad1 = false;
+    words_of(t.a, w0, w1);
+    const uint32_t e0 = entry_of(t.a, w0, w1, bad);
+    words_of(t.a + 1, w0, w1);
+    if (!prepare(t.a, e0, bad, cur)) {
+        flag(A.err, ERR_CORRUPT);
+        return;
+    }
+    if (t.a + 1 < t.b) e1 = entry_of(t.a + 1, w0, w1, bad1);
+    words_of(t.a + 2, w0, w1);
+    for (uint32_t g = t.a; g < t.b; g++) {
+        // run ahead: group g + 1's positions and bytes, g + 2's entries,
+        // g + 3's index words
+        if (g + 1 < t.b) {
+            if (!prepare(g + 1, e1, bad1, nxt)) {
+                flag(A.err, ERR_CORRUPT);
+                return;
+            }
+            e1 = entry_of(g + 2, w0, w1, bad1);
+            words_of(g + 3, w0, w1);
+        }
+        stage(cur, g);
         // write out the whole blocks when enough are done, and everything at
         // the unit's end
-        const uint32_t fill = uint32_t(int64_t(end) - sbase);
+        const uint32_t fill = uint32_t(int64_t(cur.end) - sbase);
         const bool last = g + 1 == t.b;
-        if (!last && fill < kSdFlushBytes) continue;
-        const uint32_t nblk = last ? (fill + 15) / 16 : fill / 16;
-        wave_fence();
-        for (uint32_t b = lane; b < nblk; b += 64) {
-            const int64_t q = sbase + 16 * int64_t(b);
-            const u32x4 v = *reinterpret_cast<const u32x4 *>(buf + 4 * b);
-            *reinterpret_cast<u32x4 *>(buf + 4 * b) = zero4;
-            if (q >= int64_t(ua) && q + 16 <= int64_t(ub)) {
-                *gp(reinterpret_cast<u32x4 *>(out + q)) = v;
-            } else {
-                for (uint32_t k = 0; k < 16; k++)
-                    if (q + k >= int64_t(ua) && q + k < int64_t(ub))
-                        gp(out)[q + k] = uint8_t(v[k >> 2] >> (8 * (k & 3u)));
+        if (last || fill >= kSdFlushBytes) {
+            const uint32_t nblk = last ? (fill + 15) / 16 : fill / 16;
+            wave_fence();
+            for (uint32_t b = lane; b < nblk; b += 64) {
+                const int64_t q = sbase + 16 * int64_t(b);
+                const u32x4 v = *reinterpret_cast<const u32x4 *>(buf + 4 * b);
+                *reinterpret_cast<u32x4 *>(buf + 4 * b) = zero4;
+                if (q >= int64_t(ua) && q + 16 <= int64_t(ub)) {
+                    *gp(reinterpret_cast<u32x4 *>(out + q)) = v;
+                } else {
+                    for (uint32_t k = 0; k < 16; k++)
+                        if (q + k >= int64_t(ua) && q + k < int64_t(ub))
+                            gp(out)[q + k] = uint8_t(v[k >> 2] >> (8 * (k & 3u)));
+                }
             }
+            if (last) break;
+            // carry the unfinished block (its bytes from the next group are
+            // still to come) to the front
+            wave_fence();
+            uint32_t carry = 0;
+            if (lane < 4) {
+                carry = buf[4 * nblk + lane];
+                buf[4 * nblk + lane] = 0;
+            }
+            wave_fence();
+            if (lane < 4) buf[lane] = carry;
+            wave_fence();
+            sbase += 16 * int64_t(nblk);
         }
-        if (last) break;
-        // carry the unfinished block (its bytes from the next group are
-        // still to come) to the front
-        wave_fence();
-        uint32_t carry = 0;
-        if (lane < 4) {
-            carry = buf[4 * nblk + lane];
-            buf[4 * nblk + lane] = 0;
-        }
-        wave_fence();
-        if (lane < 4) buf[lane] = carry;
-        wave_fence();
-        sbase += 16 * int64_t(nblk);
+        cur = nxt;
     }
 }
 
