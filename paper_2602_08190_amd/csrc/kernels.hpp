@@ -1160,14 +1160,30 @@ ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, 
         flag(A.err, ERR_CORRUPT);
         return;
     }
-    const uint32_t *ents = reinterpret_cast<const uint32_t *>(ebase);
-    const uint32_t *codes = reinterpret_cast<const uint32_t *>(staged ? A.out_tab[kScratchCol] + ck.aux_off : s + co);
+    // Index words, entries and group offsets are read through bounds-checked
+    // views (a read past a view returns 0), so no load sits behind a branch
+    // and loads stay in flight until their values are used.
+    const uint8_t *codes = staged ? A.out_tab[kScratchCol] + ck.aux_off : s + co;
+    const __amdgpu_buffer_rsrc_t rs_codes =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(codes), 0, int(4 * ncw), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rs_ents =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(ebase), 0, int(4 * ne), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rs_gofs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(s + go), 0, int(4 * ng), 0x00020000);
     // the entry bytes with the 4 bytes before them (entries or header) and the
     // 4 after (padding): every dword read below lies inside this view
     const __amdgpu_buffer_rsrc_t rs_ent =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(bbase - 4), 0, int(nb + 8), 0x00020000);
-    const uint32_t ua = first32(ld32u(s + go + 4ull * t.a));
-    const uint32_t ub = t.b < ng ? first32(ld32u(s + go + 4ull * t.b)) : plain;
+    // output offsets of groups t.a + l (l = 0..63; plain past the last
+    // group), one per lane; the planner gives a unit at most 63 groups
+    if (t.b - t.a > 63) {
+        flag(A.err, ERR_CORRUPT);
+        return;
+    }
+    const uint32_t gwin = t.a + lane < ng ? __builtin_amdgcn_raw_buffer_load_b32(rs_gofs, int(4 * (t.a + lane)), 0, 0)
+                                          : plain;
+    auto goff = [&](uint32_t g) { return rl32(gwin, g - t.a); };
+    const uint32_t ua = goff(t.a), ub = goff(t.b);
     if (ua >= ub || ub > plain) {
         flag(A.err, ERR_CORRUPT);
         return;
@@ -1185,13 +1201,11 @@ ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, 
     // group g + 1's token positions are computed and its entry bytes loaded,
     // before group g's bytes are ORed into the buffer.
     auto words_of = [&](uint32_t g, uint32_t &w0, uint32_t &w1) {
-        w0 = w1 = 0;
         const uint32_t i = 64 * g + lane;
-        if (g < t.b && i < nt && w) {
-            const uint64_t k = (uint64_t(i) * w) >> 5;
-            w0 = codes[k];
-            w1 = k + 1 < ncw ? codes[k + 1] : 0u;
-        }
+        const bool act = g < t.b && i < nt && w;
+        const uint32_t k = uint32_t((uint64_t(i) * w) >> 5);
+        w0 = __builtin_amdgcn_raw_buffer_load_b32(rs_codes, int(act ? 4 * k : 0x7FFFFFF0u), 0, 0);
+        w1 = __builtin_amdgcn_raw_buffer_load_b32(rs_codes, int(act ? 4 * k + 4 : 0x7FFFFFF0u), 0, 0);
     };
     // entry of group g's token from its index words; bad: index past the entries
     auto entry_of = [&](uint32_t g, uint32_t w0, uint32_t w1, bool &bad) -> uint32_t {
@@ -1200,7 +1214,7 @@ ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, 
         const uint32_t code =
             w ? uint32_t((uint64_t(w0) | (uint64_t(w1) << 32)) >> ((uint64_t(i) * w) & 31u)) & mask32(w) : 0u;
         bad = act && code >= ne;
-        return (act && !bad) ? ents[code] : 0u;
+        return __builtin_amdgcn_raw_buffer_load_b32(rs_ents, int((act && !bad) ? 4 * code : 0x7FFFFFF0u), 0, 0);
     };
     struct Grp {
         uint32_t len, eoff, P, end;  // token length and entry offset, token start, group end
@@ -1211,45 +1225,55 @@ ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, 
         const bool act = 64 * g + lane < nt;
         G.len = e >> 24;
         G.eoff = e & 0xFFFFFFu;
-        // an entry's bytes (and the dword read at each) lie in the entry bytes
-        const bool bad_ent = act && (G.len == 0 || G.len > kSdMaxToken || uint64_t(G.eoff) + G.len > nb);
         const uint32_t incl = scan_add32(G.len), total = rl32(incl, 63);
-        const uint32_t pos = first32(ld32u(s + go + 4ull * g));
-        G.end = g + 1 < ng ? first32(ld32u(s + go + 4ull * (g + 1))) : plain;
-        if (any(bad_code || bad_ent) || uint64_t(pos) + total != G.end || G.end > ub || pos < ua) return false;
+        const uint32_t pos = goff(g);
+        G.end = goff(g + 1);
         G.P = pos + incl - G.len;
-        // token byte 4j - ((oa + P) & 3) begins buffer dword j of the token
+        // token byte 4j - ((oa + P) & 3) begins buffer dword j of the token;
+        // the loads go out before the checks (they cannot leave the view), so
+        // that no branch stands between them and their use
         const uint32_t m = (oa + G.P) & 3u, nd = act ? (m + G.len + 3) >> 2 : 0u;
-        auto ld = [&](uint32_t j) {
-            return __builtin_amdgcn_raw_buffer_load_b32(
-                rs_ent, int(j < nd ? uint32_t(int32_t(G.eoff) + int32_t(4 * j) - int32_t(m) + 4) : 0x7FFFFFF0u), 0, 0);
-        };
-        G.v0 = ld(0);
-        G.v1 = ld(1);
-        G.v2 = ld(2);
-        G.v3 = ld(3);
-        return true;
+        const uint32_t at = G.eoff - m + 4;
+        G.v0 = __builtin_amdgcn_raw_buffer_load_b32(rs_ent, int(0 < nd ? at : 0x7FFFFFF0u), 0, 0);
+        G.v1 = __builtin_amdgcn_raw_buffer_load_b32(rs_ent, int(1 < nd ? at + 4 : 0x7FFFFFF0u), 0, 0);
+        G.v2 = __builtin_amdgcn_raw_buffer_load_b32(rs_ent, int(2 < nd ? at + 8 : 0x7FFFFFF0u), 0, 0);
+        G.v3 = __builtin_amdgcn_raw_buffer_load_b32(rs_ent, int(3 < nd ? at + 12 : 0x7FFFFFF0u), 0, 0);
+        // an entry's bytes (and the dword read at each) lie in the entry bytes;
+        // the group's tokens fill exactly its output range
+        const bool bad = bad_code || (act && (G.len == 0 || G.len > kSdMaxToken || uint64_t(G.eoff) + G.len > nb)) ||
+                         uint64_t(pos) + total != G.end || G.end > ub || pos < ua;
+        return !any(bad);
     };
-    // OR group G's token bytes into the buffer
+    // OR group G's token bytes into the buffer: dword j of the token's span
+    // holds token bytes [4j - m, 4j - m + 4) clipped to [0, len); every lane
+    // ORs (a zero where it has nothing) so that no branch splits the wave
     auto stage = [&](const Grp &G, uint32_t g) {
         const bool act = 64 * g + lane < nt;
         const uint32_t o = uint32_t(int64_t(G.P) - sbase), m = o & 3u;
         const uint32_t nd = act ? (m + G.len + 3) >> 2 : 0u;
-        auto part = [&](uint32_t j, uint32_t v) {
-            const int32_t q0 = int32_t(4 * j) - int32_t(m);
-            const uint32_t lo = q0 < 0 ? uint32_t(-q0) : 0u;
-            const int32_t hi = int32_t(G.len) - q0;  // bytes of the token from this dword's start
-            const uint32_t msk = (0xFFFFFFFFu << (8 * lo)) & (hi >= 4 ? 0xFFFFFFFFu : ((1u << (8 * hi)) - 1u));
-            __hip_atomic_fetch_or(buf + (o >> 2) + j, v & msk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const uint32_t head = 0xFFFFFFFFu << (8 * m);            // bytes from the token's start
+        const uint32_t endb = m + G.len;                         // buffer byte after the token, from o & ~3
+        auto tail = [&](uint32_t j) {                            // bytes before the token's end
+            const uint32_t r = endb - 4 * j;
+            return r >= 4 ? 0xFFFFFFFFu : ((1u << (8 * r)) - 1u);
         };
-        if (0 < nd) part(0, G.v0);
-        if (1 < nd) part(1, G.v1);
-        if (2 < nd) part(2, G.v2);
-        if (3 < nd) part(3, G.v3);
+        // a token's dwords lie inside the buffer; lanes with nothing to OR at
+        // dword j send a zero to a clamped address
+        const uint32_t d0 = o >> 2;
+        auto at = [&](uint32_t j) { return buf + min(d0 + j, kSdBufWords - 1); };
+        const uint32_t v0 = 0 < nd ? G.v0 & head & tail(0) : 0u;
+        const uint32_t v1 = 1 < nd ? G.v1 & tail(1) : 0u;
+        const uint32_t v2 = 2 < nd ? G.v2 & tail(2) : 0u;
+        const uint32_t v3 = 3 < nd ? G.v3 & tail(3) : 0u;
+        __hip_atomic_fetch_or(at(0), v0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_or(at(1), v1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_or(at(2), v2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_or(at(3), v3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         for (uint32_t j = 4; any(j < nd); j++) {  // tokens of more than 13 bytes
             const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(
-                rs_ent, int(j < nd ? uint32_t(int32_t(G.eoff) + int32_t(4 * j) - int32_t(m) + 4) : 0x7FFFFFF0u), 0, 0);
-            if (j < nd) part(j, v);
+                rs_ent, int(j < nd ? G.eoff - m + 4 * j + 4 : 0x7FFFFFF0u), 0, 0);
+            if (j < nd) __hip_atomic_fetch_or(buf + (o >> 2) + j, v & tail(j), __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     };
 
@@ -1263,7 +1287,7 @@ ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, 
         flag(A.err, ERR_CORRUPT);
         return;
     }
-    if (t.a + 1 < t.b) e1 = entry_of(t.a + 1, w0, w1, bad1);
+    e1 = entry_of(t.a + 1, w0, w1, bad1);
     words_of(t.a + 2, w0, w1);
     for (uint32_t g = t.a; g < t.b; g++) {
         // run ahead: group g + 1's positions and bytes, g + 2's entries,

@@ -106,7 +106,7 @@ static void add_chunk(WorkTables &w, const zf_column &col, uint32_t ci, uint32_t
         auto gof = [&](uint32_t g) { return g < ng ? rd32(s + go + 4ull * g) : n; };
         for (uint32_t g = 0; g < ng;) {
             uint32_t gb = g + 1;
-            while (gb < ng && gof(gb) - gof(g) < unit) gb++;
+            while (gb < ng && gof(gb) - gof(g) < unit && gb - g < 63) gb++;  // at most 63 groups per unit
             T.push_back({idx, g, gb, 0});
             g = gb;
         }

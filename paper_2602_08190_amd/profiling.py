@@ -2,6 +2,7 @@
 
     python -m paper_2602_08190_amd.profiling stats <run_kernel_stats.csv> <out.txt> "<command>"
     python -m paper_2602_08190_amd.profiling traffic <pmc_root> <out_dir> "<command>"
+    python -m paper_2602_08190_amd.profiling counters <out.txt> <kernel> "<command>" <csv> [<csv> ...]
 
 `traffic` expects <pmc_root>/pmc_<workload>_<COUNTER>/run_counter_collection.csv
 for COUNTER in FETCH_SIZE, WRITE_SIZE and workloads including `copy` (the
@@ -47,7 +48,8 @@ def stats(csv_path, out_path, command):
 def _kernel_of(kernel_id):
     """Name fragment of the per-kind decode kernel (LZ77 has its own)."""
     kind = KIND_OF_ID[kernel_id]
-    return {"LZ77": "k_decode_lz<", "ANS": "k_decode_ans"}.get(kind, f"k_decode_kind<{kernel_id}u>")
+    return {"LZ77": "k_decode_lz<", "ANS": "k_decode_ans", "SDICT": "k_decode_sdict"}.get(
+        kind, f"k_decode_kind<{kernel_id}u>")
 
 
 def _per_dispatch(path, kernel_id):
@@ -89,8 +91,32 @@ def traffic(root, out_dir, command):
         fo.write("\n".join(lines) + "\n")
 
 
+def counters(csv_paths, fragment, out_path, command):
+    """Median per-dispatch value of every counter in the given
+    run_counter_collection.csv files for kernels whose name contains
+    `fragment` (each dispatch's value summed over the agent's instances)."""
+    rows = {}
+    for path in csv_paths:
+        per = collections.defaultdict(lambda: collections.defaultdict(float))
+        for r in csv.DictReader(open(path)):
+            if fragment in r["Kernel_Name"]:
+                per[r["Counter_Name"]][r["Dispatch_Id"]] += float(r["Counter_Value"])
+        for name, d in per.items():
+            v = sorted(d.values())
+            rows[name] = (v[len(v) // 2], len(v))
+    lines = [f"# rocprofv3 --pmc counters of kernels matching '{fragment}', median per dispatch",
+             f"# command (one run per counter set): {command}", f"# kernel sources sha: {kernel_sha()}", ""]
+    for name in sorted(rows):
+        lines.append(f"{name:32s} {rows[name][0]:18.0f}   ({rows[name][1]} dispatches)")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "counters":
+        # counters <out.txt> <kernel fragment> "<command>" <csv> [<csv> ...]
+        counters(sys.argv[5:], sys.argv[3], sys.argv[2], sys.argv[4])
