@@ -1088,7 +1088,11 @@ static int dec_sdict_ans(const uint8_t *s, uint64_t comp_len, uint32_t plain_len
  *   u32 entry[dict_count] at 16: byte offset (bits 0-23) | length 1..64
  *       (bits 24-31)
  *   n_bytes entry bytes at 16 + 4*dict_count, then zero bytes up to
- *   16 + 4*dict_count + align16(n_bytes + 4).
+ *   16 + 4*dict_count + align16(n_bytes).  The first entry starts at byte 4,
+ *   each next one at align4(end of the previous + 3), and n_bytes =
+ *   align4(end of the last + 3): every entry has at least three zero bytes
+ *   before and after it (a decoder may read whole dwords around an entry).
+ *   A dictionary whose entries lack those zero bytes is corrupt.
  *   Entries: the distinct tokens of the column's SDICT_COL / SDICT_COL_ANS
  *   chunks, by decreasing number of occurrences, ties by first appearance;
  *   at most 2^24 entries and 2^24 - 1 entry bytes.
@@ -1199,25 +1203,27 @@ static int tdict_build(const uint8_t *src, const uint32_t *chunk_elems, uint32_t
         off += n;
     }
     if (d->n > SDC_MAX_ENTRIES) { tdict_free(d); return ZFO_EUNSUP; }
-    uint64_t nb = 0;
-    for (uint64_t t = 0; t < d->n; t++) nb += d->len[t];
+    /* entry bytes with the zero guards: 4 before the first, then each entry
+     * and at least 3 zero bytes, up to a multiple of 4 */
+    uint64_t nb = 4;
+    for (uint64_t t = 0; t < d->n; t++) nb = (nb + d->len[t] + 3 + 3) & ~(uint64_t)3;
     if (nb > SDC_MAX_BYTES) { tdict_free(d); return ZFO_EUNSUP; }
     uint64_t *ord = (uint64_t *)malloc(sizeof(uint64_t) * (d->n ? d->n : 1));
     d->code = (uint32_t *)malloc(sizeof(uint32_t) * (d->n ? d->n : 1));
-    uint64_t len = 16 + 4 * d->n + align16(nb + 4);
+    uint64_t len = 16 + 4 * d->n + align16(nb);
     uint8_t *a = (uint8_t *)calloc(len, 1);
     if (!ord || !d->code || !a) { free(ord); free(a); tdict_free(d); return ZFO_ENOMEM; }
     for (uint64_t t = 0; t < d->n; t++) ord[t] = t;
     g_sort_dict = d;
     qsort(ord, d->n, sizeof(uint64_t), tdict_order);
     put32(a, (uint32_t)nb);
-    uint64_t at = 0;
+    uint64_t at = 4;
     for (uint64_t k = 0; k < d->n; k++) {
         uint64_t t = ord[k];
         d->code[t] = (uint32_t)k;
         put32(a + 16 + 4 * k, (uint32_t)at | (d->len[t] << 24));
         memcpy(a + 16 + 4 * d->n + at, src + d->pos[t], d->len[t]);
-        at += d->len[t];
+        at = (at + d->len[t] + 3 + 3) & ~(uint64_t)3;
     }
     free(ord);
     *area = a;
@@ -1659,7 +1665,16 @@ int zfo_inspect(const uint8_t *blob, uint64_t len, zfo_info *info) {
         if (in.dict_off % 16 != 0 || in.dict_off < 64 + tl || in.dict_off + 16 > len) return ZFO_ECORRUPT;
         uint32_t nb = get32(blob + in.dict_off);
         if (nb > SDC_MAX_BYTES || in.dict_count > SDC_MAX_ENTRIES) return ZFO_ECORRUPT;
-        dl = 16 + 4 * (uint64_t)in.dict_count + align16((uint64_t)nb + 4);
+        dl = 16 + 4 * (uint64_t)in.dict_count + align16(nb);
+        if (in.dict_off + dl > len) return ZFO_ECORRUPT;
+        /* every entry inside the bytes with three zero bytes on each side */
+        const uint8_t *ents = blob + in.dict_off + 16, *bytes = ents + 4 * (uint64_t)in.dict_count;
+        for (uint32_t k = 0; k < in.dict_count; k++) {
+            uint32_t e = get32(ents + 4 * (uint64_t)k), off = e & 0xFFFFFFu, el = e >> 24;
+            if (el == 0 || el > SD_MAX_TOKEN || off < 3 || (uint64_t)off + el + 3 > nb) return ZFO_ECORRUPT;
+            for (uint32_t q = 1; q <= 3; q++)
+                if (bytes[off - q] != 0 || bytes[off + el + q - 1] != 0) return ZFO_ECORRUPT;
+        }
     }
     if (in.dict_count) {
         if (in.dict_off % 16 != 0 || in.dict_off < 64 + tl || in.dict_off + dl > len)

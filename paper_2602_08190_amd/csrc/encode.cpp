@@ -624,8 +624,8 @@ static void enc_sdict(std::vector<uint8_t> &s, const uint8_t *x, uint32_t n) {
 // end after a space, a period or a newline (the end of a row value), at most
 // 64 bytes; entries by decreasing count, ties by first appearance in the
 // column; in the container's dictionary area as {u32 n_bytes, 3 x u32 0,
-// u32 entry[n] (offset | length << 24), entry bytes, zero padding to a
-// multiple of 16 of at least 4 bytes}.  A chunk keeps its token count,
+// u32 entry[n] (offset | length << 24), entry bytes with at least 3 zero
+// bytes on each side of every entry, zero padding to a multiple of 16}.  A chunk keeps its token count,
 // width, group offsets and the bit-packed entry indices.
 static inline uint32_t sdc_token_len(const uint8_t *x, uint32_t n, uint32_t i) {
     uint32_t L = 0;
@@ -746,22 +746,25 @@ static void build_token_dictionary(TokenDictionary &d, const uint8_t *src, const
     std::sort(ent.begin(), ent.end(), [](const TokenTable::Slot *a, const TokenTable::Slot *b) {
         return a->val != b->val ? a->val > b->val : a->first < b->first;
     });
-    uint64_t nb = 0;
-    for (auto *e : ent) nb += e->len;
+    // entry bytes with zero guards: 4 zero bytes, then each entry followed by
+    // at least 3 zero bytes up to a multiple of 4 (a decoder may read whole
+    // dwords around an entry)
+    uint64_t nb = 4;
+    for (auto *e : ent) nb = align_up(nb + e->len + 3, 4);
     ZF_REQUIRE(nb < (1u << 24), ZF_E_UNSUPPORTED,
                "%llu bytes of distinct tokens: a column dictionary holds at most 2^24 - 1",
                (unsigned long long)nb);
     d.count = uint32_t(ent.size());
     d.w = d.count > 1 ? bit_width64(d.count - 1) : 0;
-    d.area.assign(16 + 4ull * d.count + align_up(nb + 4, 16), 0);
+    d.area.assign(16 + 4ull * d.count + align_up(nb, 16), 0);
     wr32(d.area.data(), uint32_t(nb));
     d.table.init(d.count);
-    uint32_t at = 0;
+    uint32_t at = 4;
     for (uint32_t k = 0; k < d.count; k++) {
         const TokenTable::Slot *e = ent[k];
         wr32(d.area.data() + 16 + 4ull * k, at | (e->len << 24));
         std::memcpy(d.area.data() + 16 + 4ull * d.count + at, e->p, e->len);
-        at += e->len;
+        at = uint32_t(align_up(at + e->len + 3, 4));
         d.table.add(e->p, e->len, e->first, k);
     }
 }

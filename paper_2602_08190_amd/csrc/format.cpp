@@ -400,7 +400,7 @@ ColumnView parse_column(const uint8_t *p, uint64_t len) {
                    "dictionary out of range");
         const uint32_t nb = rd32(p + v.dict_off);
         ZF_REQUIRE(nb < (1u << 24) && v.dict_count <= (1u << 24), ZF_E_CORRUPT, "token dictionary too large");
-        dl = 16 + 4ull * v.dict_count + align_up(nb + 4ull, 16);
+        dl = 16 + 4ull * v.dict_count + align_up(nb, 16);
     }
     v.dict_bytes = dl;
     if (v.dict_count)
@@ -416,10 +416,15 @@ ColumnView parse_column(const uint8_t *p, uint64_t len) {
         const uint32_t nb = rd32(d);
         ZF_REQUIRE(rd32(d + 4) == 0 && rd32(d + 8) == 0 && rd32(d + 12) == 0, ZF_E_CORRUPT,
                    "token dictionary header");
+        // every entry inside the bytes with three zero bytes on each side
+        const uint8_t *bytes = d + 16 + 4ull * v.dict_count;
         for (uint32_t k = 0; k < v.dict_count; k++) {
-            const uint32_t e = rd32(d + 16 + 4ull * k), elen = e >> 24;
-            ZF_REQUIRE(elen >= 1 && elen <= kSdMaxToken && (e & 0xFFFFFFu) + uint64_t(elen) <= nb, ZF_E_CORRUPT,
+            const uint32_t e = rd32(d + 16 + 4ull * k), elen = e >> 24, off = e & 0xFFFFFFu;
+            ZF_REQUIRE(elen >= 1 && elen <= kSdMaxToken && off >= 3 && off + uint64_t(elen) + 3 <= nb, ZF_E_CORRUPT,
                        "token dictionary entry %u", k);
+            for (uint32_t q = 1; q <= 3; q++)
+                ZF_REQUIRE(bytes[off - q] == 0 && bytes[off + elen + q - 1] == 0, ZF_E_CORRUPT,
+                           "token dictionary entry %u: no zero bytes around it", k);
         }
     }
     v.chunks.resize(v.n_chunks);

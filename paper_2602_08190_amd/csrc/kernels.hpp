@@ -1106,18 +1106,22 @@ constexpr uint32_t kSdFlushBytes = 1024;  // whole blocks that trigger a write-o
 // been written out); a group adds at most 64 tokens of kSdMaxToken bytes.
 static_assert(kSdFlushBytes + 64 * kSdMaxToken <= 4 * kSdBufWords, "String-dictionary buffer");
 
-ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, uint32_t *buf) {
+// COL: a column dictionary (SDICT_COL, SDICT_COL_ANS), whose entries have
+// at least three zero bytes on each side, so a dword read around a token
+// needs no mask; else the chunk's own dictionary (SDICT_BP, SDICT_ANS).
+template <bool COL>
+ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, uint32_t *buf) {
     const uint8_t *s = A.comp + ck.comp_off;
     const uint32_t lane = lane_id(), plain = ck.n_elems, clen = ck.comp_len;
     uint8_t *out = A.out_tab[ck.col] + ck.out_off;
-    const bool coldict = ck.codec == C_SDICT_COL || ck.codec == C_SDICT_COL_ANS;
+    constexpr bool coldict = COL;
     const bool staged = ck.codec == C_SDICT_ANS || ck.codec == C_SDICT_COL_ANS;
     uint32_t nt = 0, ne = 0, w = 0, ng = 0, co = 0, nb = 0, go = 0;
     const uint8_t *ebase = nullptr, *bbase = nullptr;  // entries, entry bytes
     bool ok;
-    if (coldict) {
+    if constexpr (coldict) {
         // header {n_tokens, w, n_groups, codes_off}; the dictionary area
-        // {n_bytes, 0, 0, 0, entries, bytes, >= 4 bytes of padding}
+        // {n_bytes, 0, 0, 0, entries, bytes (zero-guarded, ending in zeros)}
         const uint8_t *D = A.dict + ck.dict_off;
         ok = clen >= 16 && ck.dict_bytes >= 16;
         if (ok) {
@@ -1131,7 +1135,7 @@ ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, 
         go = 16;
         ebase = D + 16;
         bbase = D + 16 + 4ull * ne;
-        ok = ok && ne >= 1 && 16ull + 4ull * ne + nb + 4 <= ck.dict_bytes && co >= 16ull + 4ull * ng;
+        ok = ok && ne >= 1 && 16ull + 4ull * ne + nb <= ck.dict_bytes && co >= 16ull + 4ull * ng;
     } else {
         // header {n_tokens, n_entries, w, n_groups, ent_off, bytes_off,
         // codes_off, n_bytes}; entries, bytes and >= 4 bytes of padding
@@ -1170,10 +1174,12 @@ ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, 
         __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(ebase), 0, int(4 * ne), 0x00020000);
     const __amdgpu_buffer_rsrc_t rs_gofs =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(s + go), 0, int(4 * ng), 0x00020000);
-    // the entry bytes with the 4 bytes before them (entries or header) and the
-    // 4 after (padding): every dword read below lies inside this view
+    // the entry bytes, shifted by 4 so that the dword before a token is at a
+    // non-negative offset, with the 4 bytes before them (entries or header)
+    // and 4 after (padding, or the last guard of a column dictionary): every
+    // dword read below lies inside this view
     const __amdgpu_buffer_rsrc_t rs_ent =
-        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(bbase - 4), 0, int(nb + 8), 0x00020000);
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(bbase - 4), 0, int(nb + (COL ? 4 : 8)), 0x00020000);
     // output offsets of groups t.a + l (l = 0..63; plain past the last
     // group), one per lane; the planner gives a unit at most 63 groups
     if (t.b - t.a > 63) {
@@ -1240,9 +1246,10 @@ ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, 
         G.v3 = __builtin_amdgcn_raw_buffer_load_b32(rs_ent, int(3 < nd ? at + 12 : 0x7FFFFFF0u), 0, 0);
         // an entry's bytes (and the dword read at each) lie in the entry bytes;
         // the group's tokens fill exactly its output range
-        const bool bad = bad_code || (act && (G.len == 0 || G.len > kSdMaxToken || uint64_t(G.eoff) + G.len > nb)) ||
-                         uint64_t(pos) + total != G.end || G.end > ub || pos < ua;
-        return !any(bad);
+        // (bitwise, not short-circuit: no branch per condition)
+        const bool bad_lane = bad_code | (act & ((G.len - 1u) >= kSdMaxToken | (G.eoff + G.len > nb)));
+        const bool bad_grp = (uint64_t(pos) + total != G.end) | (G.end > ub) | (pos < ua);
+        return !(any(bad_lane) | bad_grp);
     };
     // OR group G's token bytes into the buffer: dword j of the token's span
     // holds token bytes [4j - m, 4j - m + 4) clipped to [0, len); every lane
@@ -1261,10 +1268,12 @@ ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, 
         // dword j send a zero to a clamped address
         const uint32_t d0 = o >> 2;
         auto at = [&](uint32_t j) { return buf + min(d0 + j, kSdBufWords - 1); };
-        const uint32_t v0 = 0 < nd ? G.v0 & head & tail(0) : 0u;
-        const uint32_t v1 = 1 < nd ? G.v1 & tail(1) : 0u;
-        const uint32_t v2 = 2 < nd ? G.v2 & tail(2) : 0u;
-        const uint32_t v3 = 3 < nd ? G.v3 & tail(3) : 0u;
+        // (a dword past nd was read out of range as 0; a column dictionary's
+        // guards make every byte around a token 0)
+        const uint32_t v0 = COL ? G.v0 : G.v0 & head & tail(0);
+        const uint32_t v1 = COL ? G.v1 : G.v1 & tail(1);
+        const uint32_t v2 = COL ? G.v2 : G.v2 & tail(2);
+        const uint32_t v3 = COL ? G.v3 : G.v3 & tail(3);
         __hip_atomic_fetch_or(at(0), v0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         __hip_atomic_fetch_or(at(1), v1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         __hip_atomic_fetch_or(at(2), v2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -1272,7 +1281,7 @@ ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, 
         for (uint32_t j = 4; any(j < nd); j++) {  // tokens of more than 13 bytes
             const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(
                 rs_ent, int(j < nd ? G.eoff - m + 4 * j + 4 : 0x7FFFFFF0u), 0, 0);
-            if (j < nd) __hip_atomic_fetch_or(buf + (o >> 2) + j, v & tail(j), __ATOMIC_RELAXED,
+            if (j < nd) __hip_atomic_fetch_or(buf + (o >> 2) + j, COL ? v : v & tail(j), __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     };
@@ -1336,6 +1345,11 @@ ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, 
         }
         cur = nxt;
     }
+}
+
+ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, uint32_t *buf) {
+    if (ck.codec == C_SDICT_COL || ck.codec == C_SDICT_COL_ANS) unit_sdict_t<true>(A, t, ck, buf);
+    else unit_sdict_t<false>(A, t, ck, buf);
 }
 
 // ===================================================================== ANS

@@ -242,14 +242,16 @@ def test_sdict_col_host_validation():
         t[off:off + 4] = np.frombuffer(np.uint32(val).tobytes(), np.uint8)
         if off >= d and off < at:   # keep the table CRC right so that the entry check is what fails
             ne, nb = int(b[28:32].view(np.uint32)[0]), int(b[d:d + 4].view(np.uint32)[0])
-            tl, dl = 32 * 2, 16 + 4 * ne + (nb + 4 + 15) // 16 * 16
+            tl, dl = 32 * 2, 16 + 4 * ne + (nb + 15) // 16 * 16
             crc = zo.crc32(bytes(t[64:64 + tl]) + bytes(t[d:d + dl]))
             t[48:52] = np.frombuffer(np.uint32(crc).tobytes(), np.uint8)
             t[60:64] = np.frombuffer(np.uint32(zo.crc32(bytes(t[:60]))).tobytes(), np.uint8)
         with pytest.raises(zf.ZfError):
             zf.Column.from_bytes(t, pinned=False)
     rejects(d + 16, 0)                     # entry of length 0
-    rejects(d + 16 + 16, 20 | (4 << 24))   # entry past the entry bytes (21 of them)
+    nb = int(b[d:d + 4].view(np.uint32)[0])
+    rejects(d + 16 + 16, (nb - 5) | (4 << 24))   # entry past the entry bytes' last guard
+    rejects(d + 16 + 28 + 9, 0x41414141)         # a nonzero byte in the guard after the first entry
     rejects(d + 4, 1)                      # a nonzero reserved word
     rejects(at + 4, 2)                     # width does not match the entry count
     rejects(at + 16, 1)                    # first group offset not 0

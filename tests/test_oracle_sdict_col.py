@@ -44,7 +44,7 @@ def dictionary(blob):
     words = struct.unpack_from(f"<{ne}I", b, d + 16)
     base = d + 16 + 4 * ne
     ents = [b[base + (e & 0xFFFFFF):base + (e & 0xFFFFFF) + (e >> 24)] for e in words]
-    return ents, list(words), nb, 16 + 4 * ne + (nb + 4 + 15) // 16 * 16
+    return ents, list(words), nb, 16 + 4 * ne + (nb + 15) // 16 * 16
 
 
 def parse(s, ents):
@@ -68,9 +68,16 @@ def test_hand_derived_streams(golden):
             assert list(struct.unpack_from("<4I", b, d)) == e["dict_header"]
             ents, words, nb, dlen = dictionary(blob)
             assert words == e["dict_entries"] and dlen == e["dict_len"]
-            if "dict_bytes" in e:
-                assert b[d + 16 + 4 * len(words):][:nb] == e["dict_bytes"].encode()
+            if "dict_bytes_hex" in e:
+                assert b[d + 16 + 4 * len(words):][:nb] == bytes.fromhex(e["dict_bytes_hex"])
             assert b[d + 16 + 4 * len(words) + nb:d + dlen] == bytes(dlen - 16 - 4 * len(words) - nb)
+            # the stored layout: first entry at 4, each next at align4(end + 3),
+            # n_bytes = align4(last end + 3), zeros between entries
+            at = 4
+            for wd in words:
+                assert wd & 0xFFFFFF == at
+                at = (at + (wd >> 24) + 3 + 3) // 4 * 4
+            assert nb == at
             for i, c in enumerate(ch["chunks"]):
                 s = stream_of(blob, i)
                 h = c["header"]
@@ -171,7 +178,7 @@ def test_corrupt_streams_and_dictionaries_are_rejected():
     info = z.inspect(blob)
     d = info["dict_off"]
     s = stream_of(blob)
-    dict_area = bytes(blob[d:d + 68])
+    dict_area = bytes(blob[d:d + 84])
     assert z.decode_stream(z.SDICT_COL, z.BYTES, s, len(x), dict_area, 5)[0] == z.OK
 
     def bad(mut=None, dmut=None, n=len(x), count=5):
@@ -187,7 +194,7 @@ def test_corrupt_streams_and_dictionaries_are_rejected():
     assert bad(lambda t: struct.pack_into("<I", t, 12, 48)) == z.ECORRUPT        # codes offset
     assert bad(count=4) == z.ECORRUPT                                             # width of 4 entries is 2
     assert bad(dmut=lambda dd: struct.pack_into("<I", dd, 16, 0)) == z.ECORRUPT  # entry of length 0
-    assert bad(dmut=lambda dd: struct.pack_into("<I", dd, 16 + 16, 14 | (4 << 24))) == z.ECORRUPT  # past bytes
+    assert bad(dmut=lambda dd: struct.pack_into("<I", dd, 16 + 16, 38 | (4 << 24))) == z.ECORRUPT  # past bytes
     assert bad(n=len(x) + 1) == z.ECORRUPT                                        # too few bytes
     # the container: a token dictionary's size follows its byte count
     b = bytearray(blob)
@@ -198,6 +205,18 @@ def test_corrupt_streams_and_dictionaries_are_rejected():
     b[d + 16] ^= 1            # the table CRC covers the dictionary
     with pytest.raises(z.OracleError):
         z.inspect(b)
+    # a nonzero byte next to an entry, the table CRC kept right
+    import zlib
+    for at in (d + 16 + 20 + 8, d + 16 + 20 + 11, d + 16 + 20 + 3):   # after "the ", before "cat.", before "the "
+        b = bytearray(blob)
+        b[at] = 0x41
+        ne = 5
+        tl = 32 * info["n_chunks"]
+        crc = zlib.crc32(bytes(b[64:64 + tl]) + bytes(b[d:d + 84]))
+        struct.pack_into("<I", b, 48, crc)
+        struct.pack_into("<I", b, 60, zlib.crc32(bytes(b[:60])))
+        with pytest.raises(z.OracleError):
+            z.inspect(b)
 
 
 def test_nested_stream_is_sdict_col_with_ans_coded_indices():
