@@ -134,9 +134,10 @@ typedef enum {
  *                   entries): {u32 n_bytes, 3 u32 0, u32 entries {offset bits
  *                   0-23, length bits 24-31}, n_bytes entry bytes (the first
  *                   entry at 4, each next at align4(previous end + 3),
- *                   n_bytes = align4(last end + 3): at least three zero bytes
- *                   on each side of every entry), zero padding to a multiple
- *                   of 16}; entries
+ *                   n_bytes = max(align4(last end + 3), last start + 16): at
+ *                   least three zero bytes on each side of every entry and 16
+ *                   bytes from each start within n_bytes), zero padding to a
+ *                   multiple of 16}; entries
  *                   are the distinct tokens of the column's ZF_SDICT_COL /
  *                   ZF_SDICT_COL_ANS chunks by decreasing count, ties by first
  *                   appearance; at most 2^24 entries and 2^24 - 1 bytes

@@ -1089,10 +1089,12 @@ static int dec_sdict_ans(const uint8_t *s, uint64_t comp_len, uint32_t plain_len
  *       (bits 24-31)
  *   n_bytes entry bytes at 16 + 4*dict_count, then zero bytes up to
  *   16 + 4*dict_count + align16(n_bytes).  The first entry starts at byte 4,
- *   each next one at align4(end of the previous + 3), and n_bytes =
- *   align4(end of the last + 3): every entry has at least three zero bytes
- *   before and after it (a decoder may read whole dwords around an entry).
- *   A dictionary whose entries lack those zero bytes is corrupt.
+ *   each next one at align4(end of the previous + 3), and n_bytes is the
+ *   larger of align4(end of the last + 3) and the last start + 16: every
+ *   entry has at least three zero bytes before and after it, and 16 bytes
+ *   from its start lie within n_bytes (a decoder may read whole dwords
+ *   around an entry, or 16 bytes from its start).  A dictionary whose
+ *   entries lack those zero bytes or 16 bytes is corrupt.
  *   Entries: the distinct tokens of the column's SDICT_COL / SDICT_COL_ANS
  *   chunks, by decreasing number of occurrences, ties by first appearance;
  *   at most 2^24 entries and 2^24 - 1 entry bytes.
@@ -1205,17 +1207,23 @@ static int tdict_build(const uint8_t *src, const uint32_t *chunk_elems, uint32_t
     if (d->n > SDC_MAX_ENTRIES) { tdict_free(d); return ZFO_EUNSUP; }
     /* entry bytes with the zero guards: 4 before the first, then each entry
      * and at least 3 zero bytes, up to a multiple of 4 */
-    uint64_t nb = 4;
-    for (uint64_t t = 0; t < d->n; t++) nb = (nb + d->len[t] + 3 + 3) & ~(uint64_t)3;
-    if (nb > SDC_MAX_BYTES) { tdict_free(d); return ZFO_EUNSUP; }
     uint64_t *ord = (uint64_t *)malloc(sizeof(uint64_t) * (d->n ? d->n : 1));
     d->code = (uint32_t *)malloc(sizeof(uint32_t) * (d->n ? d->n : 1));
-    uint64_t len = 16 + 4 * d->n + align16(nb);
-    uint8_t *a = (uint8_t *)calloc(len, 1);
-    if (!ord || !d->code || !a) { free(ord); free(a); tdict_free(d); return ZFO_ENOMEM; }
+    if (!ord || !d->code) { free(ord); tdict_free(d); return ZFO_ENOMEM; }
     for (uint64_t t = 0; t < d->n; t++) ord[t] = t;
     g_sort_dict = d;
     qsort(ord, d->n, sizeof(uint64_t), tdict_order);
+    /* entry starts in dictionary order: 4, then align4(end + 3) */
+    uint64_t nb = 4, last = 4;
+    for (uint64_t k = 0; k < d->n; k++) {
+        last = nb;
+        nb = (nb + d->len[ord[k]] + 3 + 3) & ~(uint64_t)3;
+    }
+    if (nb < last + 16) nb = last + 16;
+    if (nb > SDC_MAX_BYTES) { free(ord); tdict_free(d); return ZFO_EUNSUP; }
+    uint64_t len = 16 + 4 * d->n + align16(nb);
+    uint8_t *a = (uint8_t *)calloc(len, 1);
+    if (!a) { free(ord); tdict_free(d); return ZFO_ENOMEM; }
     put32(a, (uint32_t)nb);
     uint64_t at = 4;
     for (uint64_t k = 0; k < d->n; k++) {
@@ -1671,7 +1679,8 @@ int zfo_inspect(const uint8_t *blob, uint64_t len, zfo_info *info) {
         const uint8_t *ents = blob + in.dict_off + 16, *bytes = ents + 4 * (uint64_t)in.dict_count;
         for (uint32_t k = 0; k < in.dict_count; k++) {
             uint32_t e = get32(ents + 4 * (uint64_t)k), off = e & 0xFFFFFFu, el = e >> 24;
-            if (el == 0 || el > SD_MAX_TOKEN || off < 3 || (uint64_t)off + el + 3 > nb) return ZFO_ECORRUPT;
+            if (el == 0 || el > SD_MAX_TOKEN || off < 3 || (uint64_t)off + el + 3 > nb || (uint64_t)off + 16 > nb)
+                return ZFO_ECORRUPT;
             for (uint32_t q = 1; q <= 3; q++)
                 if (bytes[off - q] != 0 || bytes[off + el + q - 1] != 0) return ZFO_ECORRUPT;
         }

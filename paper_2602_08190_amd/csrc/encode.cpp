@@ -749,8 +749,12 @@ static void build_token_dictionary(TokenDictionary &d, const uint8_t *src, const
     // entry bytes with zero guards: 4 zero bytes, then each entry followed by
     // at least 3 zero bytes up to a multiple of 4 (a decoder may read whole
     // dwords around an entry)
-    uint64_t nb = 4;
-    for (auto *e : ent) nb = align_up(nb + e->len + 3, 4);
+    uint64_t nb = 4, last = 4;
+    for (auto *e : ent) {
+        last = nb;
+        nb = align_up(nb + e->len + 3, 4);
+    }
+    nb = std::max(nb, last + 16);  // 16 bytes from the last entry's start
     ZF_REQUIRE(nb < (1u << 24), ZF_E_UNSUPPORTED,
                "%llu bytes of distinct tokens: a column dictionary holds at most 2^24 - 1",
                (unsigned long long)nb);

@@ -420,8 +420,9 @@ ColumnView parse_column(const uint8_t *p, uint64_t len) {
         const uint8_t *bytes = d + 16 + 4ull * v.dict_count;
         for (uint32_t k = 0; k < v.dict_count; k++) {
             const uint32_t e = rd32(d + 16 + 4ull * k), elen = e >> 24, off = e & 0xFFFFFFu;
-            ZF_REQUIRE(elen >= 1 && elen <= kSdMaxToken && off >= 3 && off + uint64_t(elen) + 3 <= nb, ZF_E_CORRUPT,
-                       "token dictionary entry %u", k);
+            ZF_REQUIRE(elen >= 1 && elen <= kSdMaxToken && off >= 3 && off + uint64_t(elen) + 3 <= nb &&
+                           off + 16ull <= nb,
+                       ZF_E_CORRUPT, "token dictionary entry %u", k);
             for (uint32_t q = 1; q <= 3; q++)
                 ZF_REQUIRE(bytes[off - q] == 0 && bytes[off + elen + q - 1] == 0, ZF_E_CORRUPT,
                            "token dictionary entry %u: no zero bytes around it", k);

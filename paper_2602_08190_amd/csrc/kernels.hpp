@@ -1239,11 +1239,21 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
         // the loads go out before the checks (they cannot leave the view), so
         // that no branch stands between them and their use
         const uint32_t m = (oa + G.P) & 3u, nd = act ? (m + G.len + 3) >> 2 : 0u;
-        const uint32_t at = G.eoff - m + 4;
-        G.v0 = __builtin_amdgcn_raw_buffer_load_b32(rs_ent, int(0 < nd ? at : 0x7FFFFFF0u), 0, 0);
-        G.v1 = __builtin_amdgcn_raw_buffer_load_b32(rs_ent, int(1 < nd ? at + 4 : 0x7FFFFFF0u), 0, 0);
-        G.v2 = __builtin_amdgcn_raw_buffer_load_b32(rs_ent, int(2 < nd ? at + 8 : 0x7FFFFFF0u), 0, 0);
-        G.v3 = __builtin_amdgcn_raw_buffer_load_b32(rs_ent, int(3 < nd ? at + 12 : 0x7FFFFFF0u), 0, 0);
+        if constexpr (COL) {
+            // the entry's first 16 bytes, 4-aligned, in one load; the dwords
+            // are shifted into the buffer's alignment when they are ORed
+            const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(rs_ent, int(act ? G.eoff + 4 : 0x7FFFFFF0u), 0, 0);
+            G.v0 = q.x;
+            G.v1 = q.y;
+            G.v2 = q.z;
+            G.v3 = q.w;
+        } else {
+            const uint32_t at = G.eoff - m + 4;
+            G.v0 = __builtin_amdgcn_raw_buffer_load_b32(rs_ent, int(0 < nd ? at : 0x7FFFFFF0u), 0, 0);
+            G.v1 = __builtin_amdgcn_raw_buffer_load_b32(rs_ent, int(1 < nd ? at + 4 : 0x7FFFFFF0u), 0, 0);
+            G.v2 = __builtin_amdgcn_raw_buffer_load_b32(rs_ent, int(2 < nd ? at + 8 : 0x7FFFFFF0u), 0, 0);
+            G.v3 = __builtin_amdgcn_raw_buffer_load_b32(rs_ent, int(3 < nd ? at + 12 : 0x7FFFFFF0u), 0, 0);
+        }
         // an entry's bytes (and the dword read at each) lie in the entry bytes;
         // the group's tokens fill exactly its output range
         // (bitwise, not short-circuit: no branch per condition)
@@ -1268,21 +1278,42 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
         // dword j send a zero to a clamped address
         const uint32_t d0 = o >> 2;
         auto at = [&](uint32_t j) { return buf + min(d0 + j, kSdBufWords - 1); };
-        // (a dword past nd was read out of range as 0; a column dictionary's
-        // guards make every byte around a token 0)
-        const uint32_t v0 = COL ? G.v0 : G.v0 & head & tail(0);
-        const uint32_t v1 = COL ? G.v1 : G.v1 & tail(1);
-        const uint32_t v2 = COL ? G.v2 : G.v2 & tail(2);
-        const uint32_t v3 = COL ? G.v3 : G.v3 & tail(3);
+        uint32_t v0, v1, v2, v3;
+        if constexpr (COL) {
+            // buffer dword j = entry bytes [4j - m, 4j - m + 4): a funnel
+            // shift of aligned entry dwords j - 1 and j (the three bytes
+            // before an entry and after it are zero, so only dwords past
+            // the token need clearing)
+            auto sh = [&](uint32_t hi, uint32_t lo) { return m ? __builtin_amdgcn_alignbit(hi, lo, 32 - 8 * m) : hi; };
+            v0 = 0 < nd ? sh(G.v0, 0u) : 0u;
+            v1 = 1 < nd ? sh(G.v1, G.v0) : 0u;
+            v2 = 2 < nd ? sh(G.v2, G.v1) : 0u;
+            v3 = 3 < nd ? sh(G.v3, G.v2) : 0u;
+        } else {
+            // (a dword past nd was read out of range as 0)
+            v0 = G.v0 & head & tail(0);
+            v1 = G.v1 & tail(1);
+            v2 = G.v2 & tail(2);
+            v3 = G.v3 & tail(3);
+        }
         __hip_atomic_fetch_or(at(0), v0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         __hip_atomic_fetch_or(at(1), v1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         __hip_atomic_fetch_or(at(2), v2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         __hip_atomic_fetch_or(at(3), v3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        uint32_t prev = G.v3;
         for (uint32_t j = 4; any(j < nd); j++) {  // tokens of more than 13 bytes
-            const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(
-                rs_ent, int(j < nd ? G.eoff - m + 4 * j + 4 : 0x7FFFFFF0u), 0, 0);
-            if (j < nd) __hip_atomic_fetch_or(buf + (o >> 2) + j, COL ? v : v & tail(j), __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_WORKGROUP);
+            if constexpr (COL) {
+                const uint32_t e = __builtin_amdgcn_raw_buffer_load_b32(rs_ent, int(j < nd ? G.eoff + 4 * j + 4
+                                                                                         : 0x7FFFFFF0u), 0, 0);
+                const uint32_t v = m ? __builtin_amdgcn_alignbit(e, prev, 32 - 8 * m) : e;
+                prev = e;
+                if (j < nd) __hip_atomic_fetch_or(buf + d0 + j, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            } else {
+                const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(
+                    rs_ent, int(j < nd ? G.eoff - m + 4 * j + 4 : 0x7FFFFFF0u), 0, 0);
+                if (j < nd) __hip_atomic_fetch_or(buf + d0 + j, v & tail(j), __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
         }
     };
 

@@ -73,11 +73,12 @@ def test_hand_derived_streams(golden):
             assert b[d + 16 + 4 * len(words) + nb:d + dlen] == bytes(dlen - 16 - 4 * len(words) - nb)
             # the stored layout: first entry at 4, each next at align4(end + 3),
             # n_bytes = align4(last end + 3), zeros between entries
-            at = 4
+            at = last = 4
             for wd in words:
                 assert wd & 0xFFFFFF == at
+                last = at
                 at = (at + (wd >> 24) + 3 + 3) // 4 * 4
-            assert nb == at
+            assert nb == max(at, last + 16)
             for i, c in enumerate(ch["chunks"]):
                 s = stream_of(blob, i)
                 h = c["header"]
@@ -179,6 +180,7 @@ def test_corrupt_streams_and_dictionaries_are_rejected():
     d = info["dict_off"]
     s = stream_of(blob)
     dict_area = bytes(blob[d:d + 84])
+    assert len(dictionary(blob)[0]) == 5 and dictionary(blob)[3] == 84
     assert z.decode_stream(z.SDICT_COL, z.BYTES, s, len(x), dict_area, 5)[0] == z.OK
 
     def bad(mut=None, dmut=None, n=len(x), count=5):
@@ -194,7 +196,7 @@ def test_corrupt_streams_and_dictionaries_are_rejected():
     assert bad(lambda t: struct.pack_into("<I", t, 12, 48)) == z.ECORRUPT        # codes offset
     assert bad(count=4) == z.ECORRUPT                                             # width of 4 entries is 2
     assert bad(dmut=lambda dd: struct.pack_into("<I", dd, 16, 0)) == z.ECORRUPT  # entry of length 0
-    assert bad(dmut=lambda dd: struct.pack_into("<I", dd, 16 + 16, 38 | (4 << 24))) == z.ECORRUPT  # past bytes
+    assert bad(dmut=lambda dd: struct.pack_into("<I", dd, 16 + 16, 46 | (4 << 24))) == z.ECORRUPT  # past bytes
     assert bad(n=len(x) + 1) == z.ECORRUPT                                        # too few bytes
     # the container: a token dictionary's size follows its byte count
     b = bytearray(blob)
@@ -212,7 +214,7 @@ def test_corrupt_streams_and_dictionaries_are_rejected():
         b[at] = 0x41
         ne = 5
         tl = 32 * info["n_chunks"]
-        crc = zlib.crc32(bytes(b[64:64 + tl]) + bytes(b[d:d + 84]))
+        crc = zlib.crc32(bytes(b[64:64 + tl]) + bytes(b[d:d + 84]))  # the dictionary area is 84 bytes
         struct.pack_into("<I", b, 48, crc)
         struct.pack_into("<I", b, 60, zlib.crc32(bytes(b[:60])))
         with pytest.raises(z.OracleError):
