@@ -3,9 +3,10 @@
 Default workload: the batched 16-column fact table (45.45M rows, ~8.0 GiB
 plain): six int32 key columns (FOR_BP), three int64 cents columns (FOR_BP),
 three date-like columns with runs (RLE_DELTA_BP), three CHAR(16) flag columns
-(DICT_BP) and one comment-text column (String-dictionary, SDICT_BP; LZ77 with
---text-codec lz77), in uneven chunks of 16 KiB - 4 MiB.  Synthetic, seeded
-data.
+(DICT_BP) and one comment-text column (String-dictionary over one dictionary
+for the column, bit-packing and ANS: SDICT_COL_ANS; --text-codec picks another
+String-dictionary variant or LZ77), in uneven chunks of 16 KiB - 4 MiB.
+Synthetic, seeded data.
 
 One step decodes the whole table from its compressed image already in HBM
 (zf_decompress_async: one kernel per kind, or the persistent kernel with
@@ -55,16 +56,17 @@ TEXT_CODECS = {"sdict": "SDICT_BP", "sdict_ans": "SDICT_ANS", "sdict_col": "SDIC
                "sdict_col_ans": "SDICT_COL_ANS", "lz77": "LZ77"}
 
 
-def fact_table(rows, text_codec="sdict"):
+def fact_table(rows, text_codec="sdict_col_ans"):
     """The 16-column table.  The comment text is String-dictionary coded (the
     paper's choice for comment columns, Sec. 5) on the same uneven chunks as
-    the other columns: one dictionary per chunk (sdict), one for the column
-    (sdict_col), either nested with bit-packing and ANS (*_ans);
+    the other columns: one dictionary for the column, nested with bit-packing
+    and ANS (sdict_col_ans, the paper's comment-column scheme; the default),
+    or not (sdict_col), or one dictionary per chunk (sdict, sdict_ans);
     text_codec="lz77" codes it as LZ77 in 64 KiB chunks."""
     from paper_2602_08190_amd import datagen as g
     from paper_2602_08190_amd import zf
-    codec_of = {"u32": zf.FOR_BP, "cents": zf.FOR_BP, "date": zf.RLE_DELTA_BP,
-                "char16": zf.DICT_BP, "text": getattr(zf, TEXT_CODECS[text_codec])}
+    codec_of = {k: getattr(zf, v) for k, v in g.FACT_CODECS.items()}
+    codec_of["text"] = getattr(zf, TEXT_CODECS[text_codec])
     cols, xs, names = [], [], []
     for i, (name, kind, _) in enumerate(g.FACT_COLUMNS):
         t = time.time()
@@ -337,7 +339,7 @@ def main():
     ap.add_argument("--workload", default="fact", choices=["fact", "for", "rle", "lz", "f2i", "ans", "keys", "sdict",
                                                               "sdict_ans", "sdict_col", "sdict_col_ans", "copy"])
     ap.add_argument("--rows", type=int, default=None)
-    ap.add_argument("--text-codec", default="sdict", choices=sorted(TEXT_CODECS),
+    ap.add_argument("--text-codec", default="sdict_col_ans", choices=sorted(TEXT_CODECS),
                     help="codec of the fact table's comment column")
     ap.add_argument("--no-e2e", action="store_true")
     ap.add_argument("--no-cpu", action="store_true",

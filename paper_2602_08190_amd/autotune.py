@@ -10,9 +10,19 @@ Two searches run on the same measurements:
     ten probes).
 Ties within 1% of the fastest go to the smaller workgroup.  The result is
 the tile cache libzf reads (``tune_gfx950.json`` next to
-libzf.so, or ``$ZF_TUNE_CACHE``).
+libzf.so, or ``$ZF_TUNE_CACHE``); the kinds tuned in a run replace their
+entries, the others are kept.
+
+Two kinds of measurement:
+  * --workload columns (default): one representative column per kind,
+    decoded alone;
+  * --workload fact: the batched fact table; each kind's time is taken inside
+    the whole table's decode (events around its launch), with the other kinds
+    at their cached tiles, so a tile is chosen for the kind's neighbours and
+    uneven chunks as well.
 
     python -m paper_2602_08190_amd.autotune [--out PATH] [--scale 1.0]
+                                            [--workload columns|fact] [--kinds K ...]
 """
 import argparse
 import json
@@ -35,7 +45,7 @@ UNITS = {
     "PLAIN": [16384, 65536, 262144, 1048576],
     "NP": [4, 8, 16],                        # LZ77: output bytes per block
     "ANS": [0],                              # one chunk per wave, no unit knob
-    "SDICT": [1024, 2048, 4096, 8192, 16384],  # output bytes per wave (whole groups)
+    "SDICT": [1024, 2048, 4096, 8192, 16384, 32768],  # output bytes per wave (whole groups, <= 63)
 }
 GROUP = {"FOR32": "FP", "FOR64": "FP", "DICT32": "FP", "DICT64": "FP", "DICT128": "FP",
          "RLE32": "GP", "RLE64": "GP", "LZ77": "NP", "PLAIN": "PLAIN", "F2I": "FP",
@@ -64,7 +74,7 @@ def workloads(scale):
         "LZ77": (g.text_column(n(1 << 30), 2), zf.LZ77),
         "F2I": (g.decimal_column(n(1 << 25), 5, 90000, 10500000), zf.F2I_BP),
         "ANS": (g.returnflag_column(n(1 << 28), 0.25, 0.5, 9), zf.ANS),
-        "SDICT": (g.text_column(n(1 << 30), 2), zf.SDICT_BP),
+        "SDICT": (g.text_column(n(1 << 30), 2), zf.SDICT_COL),
         "PLAIN": (np.frombuffer(g.rng(5).bytes(n(1 << 28)), np.uint8), zf.PLAIN),
     }
 
@@ -127,48 +137,94 @@ def coordinate_search(measure, units, wpbs, start):
     return (units[ui], wpbs[wi]), best, len(seen)
 
 
+def choose(grid):
+    """The brute-force winner of a {(unit, wpb): ms} grid: the smallest
+    workgroup among the shapes within 1% of the fastest (whole workgroups
+    retire together, so smaller ones refill a CU sooner when unit times vary,
+    as they do on bigger inputs than the probe), then the faster."""
+    fastest = min(grid.values())
+    return min((k for k, v in grid.items() if v <= fastest * 1.01), key=lambda k: (k[1], grid[k]))
+
+
+def report(kind, grid, plain, t0):
+    grp = GROUP[kind]
+    units = UNITS[grp]
+    bu, bw = choose(grid)
+    (cu, cw), ct, probes = coordinate_search(lambda u, w: grid[(u, w)], units, WPB, (DEFAULT[grp], 4))
+    dflt = grid[(DEFAULT[grp], 4)]
+    log(f"{kind:8s} best unit={bu} wpb={bw} {grid[(bu, bw)]:.3f} ms "
+        f"({plain / grid[(bu, bw)] / 1e6:.0f} GB/s; default {dflt:.3f} ms; coordinate search "
+        f"{probes} probes -> {ct:.3f} ms) in {time.time() - t0:.1f}s")
+    return {
+        "unit": bu, "waves_per_block": bw,
+        "ms": round(grid[(bu, bw)], 4), "plain_GBps": round(plain / grid[(bu, bw)] / 1e6, 1),
+        "default_ms": round(dflt, 4),
+        "brute_force_candidates": len(grid),
+        "coordinate_search": {"unit": cu, "waves_per_block": cw, "ms": round(ct, 4), "probes": probes},
+        "grid_ms": {f"{u}x{w}": round(v, 4) for (u, w), v in sorted(grid.items())},
+    }
+
+
 def tune(scale=1.0, kinds=None):
     import torch
     assert torch.cuda.is_available(), "the autotuner measures on the GPU"
     zf.lib()
-    out = {"arch": "gfx950", "cus": torch.cuda.get_device_properties(0).multi_processor_count,
-           "method": "brute force over the grid; coordinate search reported beside it",
-           "kinds": {}}
+    res = {}
     for kind, (x, codec) in workloads(scale).items():
         if kinds and kind not in kinds:
             continue
-        grp = GROUP[kind]
-        units = UNITS[grp]
+        units = UNITS[GROUP[kind]]
         col = zf.Column.compress(x, codec)
         timer = Timer(torch, col)
-        plain = col.plain_bytes
         grid = {}
         t0 = time.time()
         for u in units:
             for w in WPB:
                 grid[(u, w)] = timer(kind, u, w)
-        # ties (within 1% of the fastest) go to the smallest workgroup: whole
-        # workgroups retire together, so smaller ones refill a CU sooner when
-        # unit times vary, as they do on bigger inputs than the probe
-        fastest = min(grid.values())
-        (bu, bw) = min((k for k, v in grid.items() if v <= fastest * 1.01), key=lambda k: (k[1], grid[k]))
-        (cu, cw), ct, probes = coordinate_search(lambda u, w: grid[(u, w)], units, WPB,
-                                                 (DEFAULT[grp], 4))
-        dflt = grid[(DEFAULT[grp], 4)]
-        out["kinds"][kind] = {
-            "unit": bu, "waves_per_block": bw,
-            "ms": round(grid[(bu, bw)], 4), "plain_GBps": round(plain / grid[(bu, bw)] / 1e6, 1),
-            "default_ms": round(dflt, 4),
-            "brute_force_candidates": len(grid),
-            "coordinate_search": {"unit": cu, "waves_per_block": cw, "ms": round(ct, 4),
-                                  "probes": probes},
-            "grid_ms": {f"{u}x{w}": round(v, 4) for (u, w), v in sorted(grid.items())},
-        }
-        log(f"{kind:8s} best unit={bu} wpb={bw} {grid[(bu, bw)]:.3f} ms "
-            f"({plain / grid[(bu, bw)] / 1e6:.0f} GB/s; default {dflt:.3f} ms; coordinate search "
-            f"{probes} probes -> {ct:.3f} ms) in {time.time() - t0:.1f}s")
+        res[kind] = report(kind, grid, col.plain_bytes, t0)
+        res[kind]["measured"] = "column decoded alone"
         col.free()
-    return out
+    return res
+
+
+def tune_fact(scale=1.0, kinds=None, reps=3):
+    """Each kind's tile chosen on its in-step time in the fact table's decode."""
+    import torch
+    assert torch.cuda.is_available(), "the autotuner measures on the GPU"
+    zf.lib()
+    rows = max(1 << 16, int(g.FACT_ROWS * scale))
+    cols = []
+    for i, (name, kind, _) in enumerate(g.FACT_COLUMNS):
+        x = g.fact_column(i, rows)
+        cols.append(zf.Column.compress(x, getattr(zf, g.FACT_CODECS[kind]), chunk_bytes=(16 << 10, 4 << 20),
+                                       seed=3000 + i))
+        log(f"column {i} {name} ready")
+    present = sorted({zf.kind_of_column(c) for c in cols} |
+                     ({"ANS"} if any(zf.first_codec(c) in (zf.SDICT_ANS, zf.SDICT_COL_ANS) for c in cols) else set()))
+    img = zf.upload_image(zf.Plan(cols, device=0), cols)
+    outs = zf.empty_outputs(cols)
+    plain = {k: sum(c.plain_bytes for c in cols if zf.kind_of_column(c) == k) for k in present}
+    plain["ANS"] = plain.get("ANS") or plain.get("SDICT", 0)   # the stage feeds the String-dictionary text
+    res = {}
+    for kind in present:
+        if kinds and kind not in kinds:
+            continue
+        units = UNITS[GROUP[kind]]
+        grid = {}
+        t0 = time.time()
+        for u in units:
+            for w in WPB:
+                plan = zf.Plan(cols, device=0, tiles={kind: {"unit": u, "waves_per_block": w}})
+                plan.profile(True)
+                ts = []
+                for _ in range(reps + 1):
+                    plan.decompress_async(img, img.numel(), outs)
+                    ts.append(plan.kind_ms()[kind])
+                plan.sync()
+                grid[(u, w)] = sorted(ts[1:])[len(ts[1:]) // 2]
+        res[kind] = report(kind, grid, plain[kind], t0)
+        res[kind]["measured"] = "inside the fact table's decode (%d rows)" % rows
+    return res
 
 
 def main():
@@ -176,11 +232,18 @@ def main():
     ap.add_argument("--out", default=DEFAULT_OUT)
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--kinds", nargs="*")
+    ap.add_argument("--workload", default="columns", choices=["columns", "fact"])
     a = ap.parse_args()
-    res = tune(a.scale, a.kinds)
+    res = tune_fact(a.scale, a.kinds) if a.workload == "fact" else tune(a.scale, a.kinds)
+    out = {"arch": "gfx950", "method": "brute force over the grid; coordinate search reported beside it",
+           "kinds": {}}
+    if os.path.exists(a.out):
+        with open(a.out) as f:
+            out = json.load(f)
+    out["kinds"].update(res)
     with open(a.out, "w") as f:
-        json.dump(res, f, indent=1)
-    log("wrote", a.out)
+        json.dump(out, f, indent=1)
+    log("wrote", a.out, "kinds", sorted(res))
 
 
 if __name__ == "__main__":

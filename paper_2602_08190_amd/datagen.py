@@ -228,6 +228,11 @@ FACT_COLUMNS = [
     ("comment", "text", {}),
 ]
 FACT_ROWS = 45_450_000
+# codec of each kind of fact-table column (names of zf codecs): the text
+# column takes the comment column's scheme, String-dictionary | bit-packing |
+# ANS over one dictionary for the column
+FACT_CODECS = {"u32": "FOR_BP", "cents": "FOR_BP", "date": "RLE_DELTA_BP", "char16": "DICT_BP",
+               "text": "SDICT_COL_ANS"}
 
 
 def fact_column(i, rows=FACT_ROWS, seed=3):
