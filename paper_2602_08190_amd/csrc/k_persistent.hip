@@ -7,7 +7,7 @@ namespace zf {
 // Persistent: every wave pulls units from one queue until it is empty.
 // Units are ordered by kind, the costliest kinds first.
 __global__ __launch_bounds__(256) void k_decode_persistent(LaunchArgs A) {
-    __shared__ __attribute__((aligned(16))) uint32_t lz_rows[4][kSdBufWords];
+    __shared__ __attribute__((aligned(16))) uint32_t lz_rows[4][kAnsLdsWords > kSdBufWords ? kAnsLdsWords : kSdBufWords];
     uint32_t *mine = lz_rows[threadIdx.x / 64];
     const uint32_t n = A.kind_begin[K_COUNT];
     for (;;) {

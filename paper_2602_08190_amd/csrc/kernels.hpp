@@ -1390,7 +1390,7 @@ ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, 
 // holds the model: slot -> byte (4096 bytes) and byte -> {f, cum} (256 dwords).
 // A coder's next four 16-bit words are loaded ahead of their use, so the loop
 // waits on memory only when a coder drains words faster than that.
-// lds: this wave's 1280 dwords.
+// lds: this wave's kAnsLdsWords dwords (the last 256: output staging).
 ZF_DEV void unit_ans(const LaunchArgs &A, const ChunkDesc &ck, uint32_t *lds) {
     const uint8_t *s = A.comp + ck.comp_off;
     const uint32_t lane = lane_id();
@@ -1460,38 +1460,71 @@ ZF_DEV void unit_ans(const LaunchArgs &A, const ChunkDesc &ck, uint32_t *lds) {
         flag(A.err, ERR_CORRUPT);
         return;
     }
-    // words at, at+1, at+2, at+3 through a bounds-checked view of the chunk's
-    // words (0 past them): no branch, so the loads stay in flight until used.
-    // A coder never consumes past its own range in a valid stream; reading a
+    // The coder's next words sit in buf (2 to 4 of them before each step,
+    // low word first); when a step leaves one, the next aligned dword of the
+    // stream (two words), loaded one refill ahead, is appended.  Loads go
+    // through a bounds-checked view of the words (0 past them), so no branch
+    // guards them; the aligned dword holding an odd count's last word reads
+    // past the view, so that word comes from one separate 16-bit load.  A coder
+    // never consumes past its own range in a valid stream; reading a
     // neighbour's words ahead is harmless (the end check catches overruns).
     const __amdgpu_buffer_rsrc_t rw =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(s + kAnsHdr), 0, int(2 * nw), 0x00020000);
-    auto ld16 = [&](uint32_t at) { return uint32_t(__builtin_amdgcn_raw_buffer_load_b16(rw, int(2 * at), 0, 0)); };
-    // the words ahead stay in four registers, combined only when taken into
-    // buf, so nothing waits for them before then
-    uint32_t a0 = ld16(w), a1 = ld16(w + 1), a2 = ld16(w + 2), a3 = ld16(w + 3);
-    uint64_t buf = uint64_t(a0 | (a1 << 16)) | (uint64_t(a2 | (a3 << 16)) << 32);
-    a0 = ld16(w + 4), a1 = ld16(w + 5), a2 = ld16(w + 6), a3 = ld16(w + 7);
-    uint32_t nbuf = 4;   // words left in buf
+    const uint32_t kl = (nw & 1u) ? nw >> 1 : 0xFFFFFFFFu;
+    const uint32_t lastw =
+        (nw & 1u) ? uint32_t(__builtin_amdgcn_raw_buffer_load_b16(rw, int(2 * (nw - 1)), 0, 0)) : 0u;
+    auto ldd = [&](uint32_t k) {
+        const uint32_t d = __builtin_amdgcn_raw_buffer_load_b32(rw, int(4 * k), 0, 0);
+        return k == kl ? d | lastw : d;
+    };
+    uint64_t buf = uint32_t(__builtin_amdgcn_raw_buffer_load_b16(rw, int((w & 1u) ? 2 * w : 0x7FFFFFF0u), 0, 0));
+    uint32_t nbuf = w & 1u, k = (w + 1) >> 1;
+    buf |= uint64_t(ldd(k)) << (16 * nbuf);
+    nbuf += 2;
+    uint32_t pre = ldd(k + 1);
+    k += 2;
+    auto step = [&](uint32_t &b) {
+        const uint32_t slot = x & (kAnsM - 1);
+        b = sym[slot];
+        const uint32_t e = fc[b];
+        x = (e & 0xFFFFu) * (x >> 12) + slot - (e >> 16);
+        const bool need = x < kAnsL;  // one word at most: x >= 1 * 2^4 before the shift
+        x = need ? (x << 16) | uint32_t(buf & 0xFFFFu) : x;
+        buf = need ? buf >> 16 : buf;
+        w += need;
+        nbuf -= need;
+        if (nbuf == 1) {
+            buf |= uint64_t(pre) << 16;
+            nbuf = 3;
+            pre = ldd(k);
+            k++;
+        }
+    };
     bool bad = false;
     const uint32_t steps = (n + kAnsLanes - 1) / kAnsLanes;
-    for (uint32_t t = 0; t < steps; t++) {
+    uint32_t t = 0;
+    if ((reinterpret_cast<uintptr_t>(out) & 15u) == 0) {
+        // 16 steps at a time: each lane's 16 bytes (one per step, 64 apart)
+        // gathered in LDS, then written back as 16 contiguous bytes per lane
+        uint8_t *stg = reinterpret_cast<uint8_t *>(lds + kAnsLdsWords - 256);
+        for (; t + 16 <= n / kAnsLanes; t += 16) {
+#pragma unroll
+            for (uint32_t j = 0; j < 16; j++) {
+                uint32_t b;
+                step(b);
+                stg[64 * j + lane] = uint8_t(b);
+            }
+            wave_fence();
+            const u32x4 v = *reinterpret_cast<const u32x4 *>(stg + 16 * lane);
+            __builtin_nontemporal_store(v, gp(reinterpret_cast<u32x4 *>(out + uint64_t(t) * kAnsLanes + 16 * lane)));
+            wave_fence();
+        }
+    }
+    for (; t < steps; t++) {
         const uint32_t i = t * kAnsLanes + lane;
         if (i < n) {
-            const uint32_t slot = x & (kAnsM - 1);
-            const uint32_t b = sym[slot];
-            const uint32_t e = fc[b];
-            x = (e & 0xFFFFu) * (x >> 12) + slot - (e >> 16);
-            if (x < kAnsL) {  // one word at most: x >= 1 * 2^4 before the shift
-                x = (x << 16) | uint32_t(buf & 0xFFFFu);
-                buf >>= 16;
-                w++;
-                if (--nbuf == 0) {
-                    buf = uint64_t(a0 | (a1 << 16)) | (uint64_t(a2 | (a3 << 16)) << 32);
-                    nbuf = 4;
-                    a0 = ld16(w + 4), a1 = ld16(w + 5), a2 = ld16(w + 6), a3 = ld16(w + 7);
-                }
-            }
+            uint32_t b;
+            step(b);
             __builtin_nontemporal_store(uint8_t(b), gp(out) + i);  // never read back here
         }
     }
@@ -1531,8 +1564,9 @@ ZF_DEV void unit_plain(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck) 
 // ============================================================== dispatch
 // UNR: FP lane-steps of loads kept in flight; 0 = runtime-width FP path.
 template <uint32_t UNR>
-// lz_row: this wave's LDS scratch (1280 dwords): the LZ77 row, the ANS model
-// or the RLE window slots.
+// lz_row: this wave's LDS scratch (max(kAnsLdsWords, kSdBufWords) dwords):
+// the LZ77 row, the ANS model and staging, the String-dictionary buffer or
+// the RLE window slots.
 ZF_DEV void run_unit(const LaunchArgs &A, uint32_t kind, uint32_t u, uint32_t *lz_row) {
     const Tile t = A.tiles[u];
     const ChunkDesc ck = A.chunks[t.chunk];
