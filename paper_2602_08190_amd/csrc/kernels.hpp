@@ -1460,44 +1460,33 @@ ZF_DEV void unit_ans(const LaunchArgs &A, const ChunkDesc &ck, uint32_t *lds) {
         flag(A.err, ERR_CORRUPT);
         return;
     }
-    // The coder's next words sit in buf (2 to 4 of them before each step,
-    // low word first); when a step leaves one, the next aligned dword of the
-    // stream (two words), loaded one refill ahead, is appended.  Loads go
-    // through a bounds-checked view of the words (0 past them), so no branch
-    // guards them; the aligned dword holding an odd count's last word reads
-    // past the view, so that word comes from one separate 16-bit load.  A coder
-    // never consumes past its own range in a valid stream; reading a
+    // words at, at+1, at+2, at+3 through a bounds-checked view of the chunk's
+    // words (0 past them): no branch, so the loads stay in flight until used.
+    // A coder never consumes past its own range in a valid stream; reading a
     // neighbour's words ahead is harmless (the end check catches overruns).
     const __amdgpu_buffer_rsrc_t rw =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(s + kAnsHdr), 0, int(2 * nw), 0x00020000);
-    const uint32_t kl = (nw & 1u) ? nw >> 1 : 0xFFFFFFFFu;
-    const uint32_t lastw =
-        (nw & 1u) ? uint32_t(__builtin_amdgcn_raw_buffer_load_b16(rw, int(2 * (nw - 1)), 0, 0)) : 0u;
-    auto ldd = [&](uint32_t k) {
-        const uint32_t d = __builtin_amdgcn_raw_buffer_load_b32(rw, int(4 * k), 0, 0);
-        return k == kl ? d | lastw : d;
-    };
-    uint64_t buf = uint32_t(__builtin_amdgcn_raw_buffer_load_b16(rw, int((w & 1u) ? 2 * w : 0x7FFFFFF0u), 0, 0));
-    uint32_t nbuf = w & 1u, k = (w + 1) >> 1;
-    buf |= uint64_t(ldd(k)) << (16 * nbuf);
-    nbuf += 2;
-    uint32_t pre = ldd(k + 1);
-    k += 2;
+    auto ld16 = [&](uint32_t at) { return uint32_t(__builtin_amdgcn_raw_buffer_load_b16(rw, int(2 * at), 0, 0)); };
+    // the words ahead stay in four registers, combined only when taken into
+    // buf, so nothing waits for them before then
+    uint32_t a0 = ld16(w), a1 = ld16(w + 1), a2 = ld16(w + 2), a3 = ld16(w + 3);
+    uint64_t buf = uint64_t(a0 | (a1 << 16)) | (uint64_t(a2 | (a3 << 16)) << 32);
+    a0 = ld16(w + 4), a1 = ld16(w + 5), a2 = ld16(w + 6), a3 = ld16(w + 7);
+    uint32_t nbuf = 4;   // words left in buf
     auto step = [&](uint32_t &b) {
         const uint32_t slot = x & (kAnsM - 1);
         b = sym[slot];
         const uint32_t e = fc[b];
         x = (e & 0xFFFFu) * (x >> 12) + slot - (e >> 16);
-        const bool need = x < kAnsL;  // one word at most: x >= 1 * 2^4 before the shift
-        x = need ? (x << 16) | uint32_t(buf & 0xFFFFu) : x;
-        buf = need ? buf >> 16 : buf;
-        w += need;
-        nbuf -= need;
-        if (nbuf == 1) {
-            buf |= uint64_t(pre) << 16;
-            nbuf = 3;
-            pre = ldd(k);
-            k++;
+        if (x < kAnsL) {  // one word at most: x >= 1 * 2^4 before the shift
+            x = (x << 16) | uint32_t(buf & 0xFFFFu);
+            buf >>= 16;
+            w++;
+            if (--nbuf == 0) {
+                buf = uint64_t(a0 | (a1 << 16)) | (uint64_t(a2 | (a3 << 16)) << 32);
+                nbuf = 4;
+                a0 = ld16(w + 4), a1 = ld16(w + 5), a2 = ld16(w + 6), a3 = ld16(w + 7);
+            }
         }
     };
     bool bad = false;
