@@ -13,10 +13,16 @@
 //    RLE + delta + BP.  A wave takes one group of 64 runs: lane l loads run
 //    l, an exclusive wave scan of the counts gives each run's output offset
 //    (the paper's presum, fused), an inclusive wave scan of the unpacked
-//    deltas gives the run values.  Output is written in 64-wide windows; the
-//    runs that start inside a window are walked with uniform readlanes, so the
-//    work per window is proportional to its run count and long runs cost no
-//    more than short ones.  Units are balanced by output count on the host.
+//    deltas gives the run values.  Output is written in windows of 64 lanes x
+//    16 bytes: every run starting in a window marks its start in an LDS slot,
+//    a wave max-scan carries the latest run over the window and each lane
+//    fetches its run's value with a cross-lane permute, so a window costs the
+//    same whatever its run count.  Units are balanced by output count on the
+//    host.
+//  String dictionary (Sec. 5.3) is a Group-Parallel expansion too: a wave
+//    takes groups of 64 tokens, scans their lengths for output offsets and
+//    gathers each token's bytes into a per-wave LDS staging buffer that is
+//    written back in aligned 16-byte stores.
 //  Non-Parallel (Sec. 4 "Scheduling Non-Parallel towards SIMT"): LZ77, one
 //    chunk per wavefront.  Lane i holds sequence i of a batch of 64; wave
 //    scans give every sequence's output and literal positions at once.  When
@@ -1257,7 +1263,7 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
         // an entry's bytes (and the dword read at each) lie in the entry bytes;
         // the group's tokens fill exactly its output range
         // (bitwise, not short-circuit: no branch per condition)
-        const bool bad_lane = bad_code | (act & ((G.len - 1u) >= kSdMaxToken | (G.eoff + G.len > nb)));
+        const bool bad_lane = bad_code | (act & (((G.len - 1u) >= kSdMaxToken) | (G.eoff + G.len > nb)));
         const bool bad_grp = (uint64_t(pos) + total != G.end) | (G.end > ub) | (pos < ua);
         return !(any(bad_lane) | bad_grp);
     };
