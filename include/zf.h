@@ -181,9 +181,16 @@ typedef struct {
     const char *mlp_weights;      /* cost model for ZF_AUTO (NULL: $ZF_MLP_WEIGHTS;
                                      without one, ZF_AUTO keeps the smallest
                                      stream of the applicable codecs)         */
+    int32_t fallback_device;      /* ZF_AUTO with a cost model: HIP device on
+                                     which near-ties are timed; -1 (default):
+                                     the network's choice stands              */
+    float fallback_margin;        /* near-tie: the two lowest predicted log
+                                     times differ by less than this (default
+                                     0.05, about 5%); <= 0 turns timing off   */
 } zf_encode_opts;
 
-/* Defaults: chunks of 1 MiB plain (LZ77: 64 KiB), all cores, pinned. */
+/* Defaults: chunks of 1 MiB plain (LZ77: 64 KiB), all cores, pinned, no
+ * near-tie timing (fallback_device -1, fallback_margin 0.05). */
 void zf_encode_opts_default(zf_encode_opts *opts);
 
 /*
@@ -198,7 +205,12 @@ void zf_encode_opts_default(zf_encode_opts *opts);
  * ZF_AUTO with a cost model: each chunk's statistics (zf_chunk_features) go
  * through the network and the chunk takes the applicable (codec, schedule)
  * with the lowest predicted transfer + decode time; the schedule is stored in
- * the chunk table (LZ77 chunks are split at the chosen chunk size).
+ * the chunk table (LZ77 chunks are split at the chosen chunk size).  With
+ * fallback_device >= 0, a chunk whose two best predictions are within
+ * fallback_margin is encoded both ways on its own, each candidate's
+ * zf_transfer_and_decompress time is measured on that device (median of three
+ * after one untimed run) and the faster is kept (Sec. 3.3: measured search
+ * behind the learned choice); errors of that device come back as ZF_E_HIP.
  */
 zf_status zf_compress_host(const void *src, uint64_t n_elems, zf_dtype dtype, zf_codec codec,
                            const zf_encode_opts *opts /* nullable */, zf_column_t **out);

@@ -222,24 +222,27 @@ static int dec_for_bp_u64(const uint8_t *s, uint64_t comp_len, uint32_t n, uint3
  *   while sum f > M: the byte with the largest f (ties: the smallest byte)
  *       loses one;
  *   cum_s = sum of f_t for t < s.
- * Coder (state x in [L, L * 2^16), L = 2^16), over its bytes in reverse
- * order, starting from x = L:
- *   while x >= 2^20 * f_s: emit the low 16 bits of x; x = x >> 16
- *   x = floor(x / f_s) * M + (x mod f_s) + cum_s.
- * Decode, in forward order from the final state: slot = x mod M, s = the byte
- * with cum_s <= slot < cum_s + f_s, x = f_s * floor(x / M) + slot - cum_s,
- * then while x < L: x = x * 2^16 + the coder's next 16-bit word.  A valid
- * coder ends with x = L and every word read.
+ * Coder (state x in [L, L * 2^16), L = 2^16), one step per byte:
+ *   encode byte s: while x >= 2^20 * f_s: emit the low 16 bits of x;
+ *       x = x >> 16; then x = floor(x / f_s) * M + (x mod f_s) + cum_s;
+ *   decode: slot = x mod M, s = the byte with cum_s <= slot < cum_s + f_s,
+ *       x = f_s * floor(x / M) + slot - cum_s, then while x < L:
+ *       x = x * 2^16 + the next 16-bit word.
+ * The 64 coders share one word stream.  Decoding takes the bytes in order
+ * i = 0, 1, ..., n-1, byte i by coder i mod 64, and each renormalisation
+ * reads the next word of the stream; encoding takes the bytes in the reverse
+ * order (i = n-1 down to 0), every coder starting from x = L, and the stream
+ * is its emitted words reversed.  A valid stream leaves every coder at x = L
+ * with every word read.
  * Stream of a chunk of n bytes:
- *   u32 n, u32 nw (total 16-bit words), u32 0, u32 0;
- *   u16 f[256]; u32 state[64] (final states); u32 wofs[64] (coder j reads
- *   words [wofs[j], wofs[j+1]), wofs[64] = nw); u16 words[nw] at byte 1040,
- *   each coder's words in the order the decoder reads them (the reverse of
- *   emission).  comp_len = 1040 + 2*nw. */
+ *   u32 n, u32 nw (16-bit words), u32 0, u32 0; u16 f[256];
+ *   u32 state[64] (coder j's state after encoding, where decoding starts);
+ *   u16 words[nw] at byte 784, in the order the decoder reads them.
+ *   comp_len = 784 + 2*nw. */
 #define ANS_M 4096u
 #define ANS_L 65536u
 #define ANS_LANES 64u
-#define ANS_HDR 1040u
+#define ANS_HDR 784u
 
 static void ans_model(const uint8_t *x, uint32_t n, uint32_t f[256]) {
     uint64_t c[256] = {0};
@@ -274,47 +277,31 @@ static void enc_ans(buf_t *s, const uint8_t *x, uint32_t n) {
     ans_model(x, n, f);
     cum[0] = 0;
     for (int t = 1; t < 256; t++) cum[t] = cum[t - 1] + f[t - 1];
-    /* coder j's emitted words, in emission order, at em[j * stride ...]; a
-     * byte emits at most one word (after one shift x < 2^16 <= 2^20 * f) */
-    uint64_t stride = (uint64_t)n / ANS_LANES + 2;
-    uint16_t *em = (uint16_t *)malloc(sizeof(uint16_t) * stride * ANS_LANES);
-    uint64_t *cnt = (uint64_t *)calloc(ANS_LANES, sizeof(uint64_t));
-    uint32_t state[ANS_LANES];
-    if (!em || !cnt) { s->bad = 1; free(em); free(cnt); return; }
-    for (uint32_t j = 0; j < ANS_LANES; j++) {
-        uint64_t x_st = ANS_L;
-        if (j < n) {
-            uint32_t last = j + ((n - 1 - j) / ANS_LANES) * ANS_LANES;
-            for (int64_t i = last; i >= (int64_t)j; i -= ANS_LANES) {
-                uint32_t sy = x[i];
-                uint64_t xmax = ((uint64_t)(ANS_L >> 12) << 16) * f[sy];
-                while (x_st >= xmax) {
-                    em[j * stride + cnt[j]++] = (uint16_t)(x_st & 0xFFFFu);
-                    x_st >>= 16;
-                }
-                x_st = (x_st / f[sy]) * ANS_M + (x_st % f[sy]) + cum[sy];
-            }
+    /* emitted words in emission order; a byte emits at most one word (after
+     * one shift x < 2^16 <= 2^20 * f) */
+    uint16_t *em = (uint16_t *)malloc(sizeof(uint16_t) * ((uint64_t)n + 1));
+    uint64_t state[ANS_LANES], nw = 0;
+    if (!em) { s->bad = 1; return; }
+    for (uint32_t j = 0; j < ANS_LANES; j++) state[j] = ANS_L;
+    for (int64_t i = (int64_t)n - 1; i >= 0; i--) {
+        uint64_t *xs = &state[i % ANS_LANES];
+        uint32_t sy = x[i];
+        uint64_t xmax = ((uint64_t)(ANS_L >> 12) << 16) * f[sy];
+        while (*xs >= xmax) {
+            em[nw++] = (uint16_t)(*xs & 0xFFFFu);
+            *xs >>= 16;
         }
-        state[j] = (uint32_t)x_st;
+        *xs = (*xs / f[sy]) * ANS_M + (*xs % f[sy]) + cum[sy];
     }
-    uint64_t nw = 0;
-    for (uint32_t j = 0; j < ANS_LANES; j++) nw += cnt[j];
     buf_resize(s, ANS_HDR + 2 * nw);
     if (!s->bad) {
         put32(s->p, n);
         put32(s->p + 4, (uint32_t)nw);
         for (int t = 0; t < 256; t++) put16(s->p + 16 + 2 * t, f[t]);
-        uint64_t at = 0;
-        for (uint32_t j = 0; j < ANS_LANES; j++) {
-            put32(s->p + 528 + 4 * j, state[j]);
-            put32(s->p + 784 + 4 * j, (uint32_t)at);
-            for (uint64_t k = 0; k < cnt[j]; k++) /* reverse of emission */
-                put16(s->p + ANS_HDR + 2 * (at + k), em[j * stride + cnt[j] - 1 - k]);
-            at += cnt[j];
-        }
+        for (uint32_t j = 0; j < ANS_LANES; j++) put32(s->p + 528 + 4 * j, (uint32_t)state[j]);
+        for (uint64_t k = 0; k < nw; k++) put16(s->p + ANS_HDR + 2 * k, em[nw - 1 - k]);
     }
     free(em);
-    free(cnt);
 }
 
 static int dec_ans(const uint8_t *s, uint64_t comp_len, uint32_t n, uint8_t *out) {
@@ -328,24 +315,22 @@ static int dec_ans(const uint8_t *s, uint64_t comp_len, uint32_t n, uint8_t *out
         sum += f[t];
     }
     if (sum != ANS_M) return ZFO_ECORRUPT;
-    for (uint32_t j = 0; j < ANS_LANES; j++) {
-        uint64_t x_st = get32(s + 528 + 4 * j);
-        uint64_t w = get32(s + 784 + 4 * j);
-        uint64_t wend = j + 1 < ANS_LANES ? get32(s + 784 + 4 * (j + 1)) : nw;
-        if (w > wend || wend > nw) return ZFO_ECORRUPT;
-        for (uint64_t i = j; i < n; i += ANS_LANES) {
-            uint32_t slot = (uint32_t)(x_st % ANS_M), sy = 0;
-            while (!(cum[sy] <= slot && slot < cum[sy] + f[sy])) sy++;
-            x_st = f[sy] * (x_st / ANS_M) + slot - cum[sy];
-            while (x_st < ANS_L) {
-                if (w >= wend) return ZFO_ECORRUPT;
-                x_st = (x_st << 16) | get16(s + ANS_HDR + 2 * w++);
-            }
-            out[i] = (uint8_t)sy;
+    uint64_t state[ANS_LANES], w = 0;
+    for (uint32_t j = 0; j < ANS_LANES; j++) state[j] = get32(s + 528 + 4 * j);
+    for (uint64_t i = 0; i < n; i++) {
+        uint64_t *xs = &state[i % ANS_LANES];
+        uint32_t slot = (uint32_t)(*xs % ANS_M), sy = 0;
+        while (!(cum[sy] <= slot && slot < cum[sy] + f[sy])) sy++;
+        *xs = f[sy] * (*xs / ANS_M) + slot - cum[sy];
+        while (*xs < ANS_L) {
+            if (w >= nw) return ZFO_ECORRUPT;
+            *xs = (*xs << 16) | get16(s + ANS_HDR + 2 * w++);
         }
-        if (x_st != ANS_L || w != wend) return ZFO_ECORRUPT;
+        out[i] = (uint8_t)sy;
     }
-    return ZFO_OK;
+    for (uint32_t j = 0; j < ANS_LANES; j++)
+        if (state[j] != ANS_L) return ZFO_ECORRUPT;
+    return w == nw ? ZFO_OK : ZFO_ECORRUPT;
 }
 
 /* ============================================================= Float2Int
@@ -845,6 +830,235 @@ static int dec_dstride(const uint8_t *s, uint64_t comp_len, uint32_t dtype, uint
     }
     if (produced != n) return ZFO_ECORRUPT;
     return ZFO_OK;
+}
+
+/* =============================== DeltaStride | [Delta | RLE | [BP, BP], BP]
+ * The order-key tree of the paper's table of applied schemes (Sec. 5): a
+ * DeltaStride stage with two outputs, the first nested as Delta | RLE with
+ * both of RLE's outputs bit-packed, the second bit-packed.
+ * DeltaStride stage: the chunk's stride d is the most frequent difference
+ * x[i+1] - x[i] (mod 2^bits; ties to the smaller one read as unsigned; 0 for a
+ * chunk of one value); runs are maximal from the left, a run extending while
+ * the next difference equals d.  Its outputs are the run starts S[0..R) and
+ * the run counts C[0..R); run k writes S[k] + d*t, t = 0 .. C[k]-1.
+ * Delta: D[0] = S[0], D[k] = S[k] - S[k-1] (mod 2^bits), so S is the running
+ * sum of D.  RLE of D: maximal runs, values V[0..Q) and lengths L[0..Q).
+ * Bit-packing of V, L and C: per group of 64 (one wavefront), the group's
+ * smallest value (V read as signed) is the reference and each field holds
+ * value - reference at the width of the largest such difference.
+ * Every 64 consecutive runs of either level form a group whose record holds
+ * its output offset (and, for D's runs, the running sum before it), so
+ * groups decode independently.
+ * Stream:
+ *   header 32 bytes: u32 R, u32 ngB = ceil(R/64), u32 Q, u32 ngA = ceil(Q/64),
+ *       i64 d, u32 b_off = 32 + 32*ngA, u32 0
+ *   D's run groups, 32 bytes each at 32 + 32*g:
+ *       u32 out_off (index in S of the group's first element), u32 poff
+ *       (byte offset of the group's payload, 4-aligned), u32 widths (bits
+ *       0-7: V width wv, bits 8-15: L width wl), u32 lmin,
+ *       i64 base (S[out_off - 1]; 0 for the first group), i64 vmin
+ *   the runs' groups, 16 bytes each at b_off + 16*g:
+ *       u32 out_off (element index of the group's first run), u32 poff,
+ *       u32 wc (C width), u32 cmin
+ *   payloads from b_off + 16*ngB on, first D's groups then the runs' groups,
+ *   each group's starting at the word after the previous one's:
+ *       D group: cnt V fields (V_j - vmin), then from the next u32 word cnt L
+ *           fields (L_j - lmin);
+ *       runs group: cnt C fields (C_j - cmin).
+ *   comp_len = end of the last payload.
+ * Decode: S from D's groups (S[k] = S[k-1] + V_j over the L_j positions of
+ * run j, starting from the group's base), then the output from the runs'
+ * groups. */
+typedef struct {
+    uint32_t n;
+    uint64_t *v; /* values */
+    uint32_t *c; /* counts */
+} runs_t;
+
+static void runs_free(runs_t *r) { free(r->v); free(r->c); }
+
+/* group g of a value array: reference (smallest, read as signed) and width */
+static void group_for(const uint64_t *v, uint32_t cnt, uint32_t bits, uint64_t *ref, uint32_t *w) {
+    uint64_t mask = mask_bits(bits);
+    int64_t lo = 0;
+    for (uint32_t j = 0; j < cnt; j++)
+        if (j == 0 || as_signed(v[j], bits) < lo) lo = as_signed(v[j], bits);
+    uint64_t fmax = 0;
+    for (uint32_t j = 0; j < cnt; j++) {
+        uint64_t f = (v[j] - (uint64_t)lo) & mask;
+        if (f > fmax) fmax = f;
+    }
+    *ref = (uint64_t)lo;
+    *w = bitlen64(fmax);
+}
+
+static void group_for32(const uint32_t *c, uint32_t cnt, uint32_t *ref, uint32_t *w) {
+    uint32_t lo = c[0], hi = c[0];
+    for (uint32_t j = 1; j < cnt; j++) {
+        if (c[j] < lo) lo = c[j];
+        if (c[j] > hi) hi = c[j];
+    }
+    *ref = lo;
+    *w = bitlen64(hi - lo);
+}
+
+static int cmp_u64(const void *a, const void *b) {
+    uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return x < y ? -1 : x > y;
+}
+
+static void enc_dstree(buf_t *s, const uint8_t *x, uint32_t dtype, uint32_t n) {
+    uint32_t bits = int_bits(dtype);
+    uint64_t mask = mask_bits(bits);
+    /* the stride: the most frequent difference, ties to the smaller */
+    uint64_t d = 0;
+    if (n > 1) {
+        uint64_t *df = (uint64_t *)malloc(sizeof(uint64_t) * (n - 1));
+        if (!df) { s->bad = 1; return; }
+        for (uint32_t i = 0; i + 1 < n; i++)
+            df[i] = ((uint64_t)load_int(x, dtype, i + 1) - (uint64_t)load_int(x, dtype, i)) & mask;
+        qsort(df, n - 1, sizeof(uint64_t), cmp_u64);
+        uint32_t best = 0;
+        for (uint32_t i = 0; i < n - 1;) {
+            uint32_t k = i;
+            while (k < n - 1 && df[k] == df[i]) k++;
+            if (k - i > best) { best = k - i; d = df[i]; }
+            i = k;
+        }
+        free(df);
+    }
+    /* DeltaStride runs */
+    runs_t st = {0, (uint64_t *)malloc(sizeof(uint64_t) * n), (uint32_t *)malloc(sizeof(uint32_t) * n)};
+    runs_t dr = {0, (uint64_t *)malloc(sizeof(uint64_t) * n), (uint32_t *)malloc(sizeof(uint32_t) * n)};
+    if (!st.v || !st.c || !dr.v || !dr.c) { runs_free(&st); runs_free(&dr); s->bad = 1; return; }
+    for (uint32_t i = 0; i < n;) {
+        uint32_t r = 1;
+        while (i + r < n && ((((uint64_t)load_int(x, dtype, i + r)) -
+                              (uint64_t)load_int(x, dtype, i + r - 1)) & mask) == d)
+            r++;
+        st.v[st.n] = (uint64_t)load_int(x, dtype, i) & mask;
+        st.c[st.n] = r;
+        st.n++;
+        i += r;
+    }
+    /* Delta of the starts, then RLE */
+    for (uint32_t k = 0; k < st.n; k++) {
+        uint64_t dk = k == 0 ? st.v[0] : (st.v[k] - st.v[k - 1]) & mask;
+        if (dr.n > 0 && dr.v[dr.n - 1] == dk) dr.c[dr.n - 1]++;
+        else { dr.v[dr.n] = dk; dr.c[dr.n] = 1; dr.n++; }
+    }
+    uint32_t R = st.n, Q = dr.n, ngA = (Q + 63) / 64, ngB = (R + 63) / 64;
+    uint64_t b_off = 32 + (uint64_t)32 * ngA, pos = b_off + (uint64_t)16 * ngB;
+    buf_resize(s, pos);
+    uint32_t at = 0; /* index in S */
+    for (uint32_t g = 0; g < ngA && !s->bad; g++) {
+        uint32_t j0 = 64 * g, cnt = Q - j0 < 64 ? Q - j0 : 64;
+        uint64_t vmin;
+        uint32_t wv, lmin, wl;
+        group_for(dr.v + j0, cnt, bits, &vmin, &wv);
+        group_for32(dr.c + j0, cnt, &lmin, &wl);
+        uint64_t vw = packed_words(cnt, wv), lw = packed_words(cnt, wl);
+        buf_resize(s, pos + 4 * (vw + lw));
+        if (s->bad) break;
+        uint8_t *rec = s->p + 32 + (uint64_t)32 * g;
+        put32(rec, at);
+        put32(rec + 4, (uint32_t)pos);
+        put32(rec + 8, wv | (wl << 8));
+        put32(rec + 12, lmin);
+        put64(rec + 16, at == 0 ? 0 : (uint64_t)as_signed(st.v[at - 1], bits));
+        put64(rec + 24, vmin);
+        for (uint32_t j = 0; j < cnt; j++) {
+            pack_bits(s->p + pos, j, wv, (dr.v[j0 + j] - vmin) & mask);
+            pack_bits(s->p + pos + 4 * vw, j, wl, dr.c[j0 + j] - lmin);
+            at += dr.c[j0 + j];
+        }
+        pos += 4 * (vw + lw);
+    }
+    uint32_t out = 0;
+    for (uint32_t g = 0; g < ngB && !s->bad; g++) {
+        uint32_t j0 = 64 * g, cnt = R - j0 < 64 ? R - j0 : 64;
+        uint32_t cmin, wc;
+        group_for32(st.c + j0, cnt, &cmin, &wc);
+        uint64_t cw = packed_words(cnt, wc);
+        buf_resize(s, pos + 4 * cw);
+        if (s->bad) break;
+        uint8_t *rec = s->p + b_off + (uint64_t)16 * g;
+        put32(rec, out);
+        put32(rec + 4, (uint32_t)pos);
+        put32(rec + 8, wc);
+        put32(rec + 12, cmin);
+        for (uint32_t j = 0; j < cnt; j++) {
+            pack_bits(s->p + pos, j, wc, st.c[j0 + j] - cmin);
+            out += st.c[j0 + j];
+        }
+        pos += 4 * cw;
+    }
+    if (!s->bad) {
+        put32(s->p, R);
+        put32(s->p + 4, ngB);
+        put32(s->p + 8, Q);
+        put32(s->p + 12, ngA);
+        put64(s->p + 16, (uint64_t)as_signed(d, bits));
+        put32(s->p + 24, (uint32_t)b_off);
+        put32(s->p + 28, 0);
+        s->n = pos;
+    }
+    runs_free(&st);
+    runs_free(&dr);
+}
+
+static int dec_dstree(const uint8_t *s, uint64_t comp_len, uint32_t dtype, uint32_t n, uint8_t *dst) {
+    uint32_t bits = int_bits(dtype);
+    uint64_t mask = mask_bits(bits);
+    if (comp_len < 32) return ZFO_ECORRUPT;
+    uint32_t R = get32(s), ngB = get32(s + 4), Q = get32(s + 8), ngA = get32(s + 12);
+    uint64_t d = get64(s + 16) & mask, b_off = get32(s + 24);
+    if (R == 0 || R > n || Q == 0 || Q > R || ngB != (R + 63) / 64 || ngA != (Q + 63) / 64) return ZFO_ECORRUPT;
+    if (b_off != 32 + (uint64_t)32 * ngA || get32(s + 28) != 0) return ZFO_ECORRUPT;
+    if (b_off + (uint64_t)16 * ngB > comp_len) return ZFO_ECORRUPT;
+    uint64_t *S = (uint64_t *)malloc(sizeof(uint64_t) * R);
+    if (!S) return ZFO_ENOMEM;
+    int rc = ZFO_OK;
+    /* S from D's run groups */
+    uint64_t k = 0;
+    for (uint32_t g = 0; g < ngA && rc == ZFO_OK; g++) {
+        const uint8_t *rec = s + 32 + (uint64_t)32 * g;
+        uint32_t out_off = get32(rec), poff = get32(rec + 4), widths = get32(rec + 8), lmin = get32(rec + 12);
+        uint32_t wv = widths & 0xFFu, wl = (widths >> 8) & 0xFFu;
+        uint64_t v = get64(rec + 16) & mask, vmin = get64(rec + 24);
+        uint32_t cnt = Q - 64 * g < 64 ? Q - 64 * g : 64;
+        uint64_t vw = packed_words(cnt, wv), lw = packed_words(cnt, wl);
+        if (wv > bits || wl > 32 || (widths >> 16) || poff % 4 || out_off != k ||
+            (uint64_t)poff + 4 * (vw + lw) > comp_len) { rc = ZFO_ECORRUPT; break; }
+        for (uint32_t j = 0; j < cnt; j++) {
+            uint64_t vj = (vmin + unpack_bits(s + poff, j, wv)) & mask;
+            uint64_t lj = (uint64_t)lmin + unpack_bits(s + poff + 4 * vw, j, wl);
+            if (lj == 0 || lj > 0xFFFFFFFFu || k + lj > R) { rc = ZFO_ECORRUPT; break; }
+            for (uint64_t t = 0; t < lj; t++) {
+                v = (v + vj) & mask;
+                S[k++] = v;
+            }
+        }
+    }
+    if (rc == ZFO_OK && k != R) rc = ZFO_ECORRUPT;
+    /* the output from the runs' groups */
+    uint64_t p = 0;
+    for (uint32_t g = 0; g < ngB && rc == ZFO_OK; g++) {
+        const uint8_t *rec = s + b_off + (uint64_t)16 * g;
+        uint32_t out_off = get32(rec), poff = get32(rec + 4), wc = get32(rec + 8), cmin = get32(rec + 12);
+        uint32_t cnt = R - 64 * g < 64 ? R - 64 * g : 64;
+        uint64_t cw = packed_words(cnt, wc);
+        if (wc > 32 || poff % 4 || out_off != p || (uint64_t)poff + 4 * cw > comp_len) { rc = ZFO_ECORRUPT; break; }
+        for (uint32_t j = 0; j < cnt; j++) {
+            uint64_t cj = (uint64_t)cmin + unpack_bits(s + poff, j, wc);
+            if (cj == 0 || cj > 0xFFFFFFFFu || p + cj > n) { rc = ZFO_ECORRUPT; break; }
+            for (uint64_t t = 0; t < cj; t++) store_int(dst, dtype, p + t, (S[64 * g + j] + d * t) & mask);
+            p += cj;
+        }
+    }
+    if (rc == ZFO_OK && p != n) rc = ZFO_ECORRUPT;
+    free(S);
+    return rc;
 }
 
 /* ======================================================= String-dictionary
@@ -1459,7 +1673,8 @@ static int codec_allows(uint32_t codec, uint32_t dtype) {
     case ZFO_LZ77: return zfo_elem_size(dtype) != 0;
     case ZFO_F2I_BP: return dtype == ZFO_F64;
     case ZFO_ANS: return zfo_elem_size(dtype) != 0;
-    case ZFO_DSTRIDE_BP: return dtype == ZFO_I32 || dtype == ZFO_I64;
+    case ZFO_DSTRIDE_BP:
+    case ZFO_DSTREE: return dtype == ZFO_I32 || dtype == ZFO_I64;
     case ZFO_SDICT_BP:
     case ZFO_SDICT_ANS:
     case ZFO_SDICT_COL:
@@ -1491,6 +1706,8 @@ int zfo_decode_stream(uint32_t codec, uint32_t dtype, const uint8_t *s, uint64_t
         return dec_ans(s, comp_len, (uint32_t)plain, dst);
     case ZFO_DSTRIDE_BP:
         return dec_dstride(s, comp_len, dtype, n, dst);
+    case ZFO_DSTREE:
+        return dec_dstree(s, comp_len, dtype, n, dst);
     case ZFO_SDICT_BP:
         return dec_sdict(s, comp_len, (uint32_t)plain, dst);
     case ZFO_SDICT_ANS:
@@ -1593,6 +1810,7 @@ int zfo_encode(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t code
         case ZFO_F2I_BP: enc_f2i_bp(&s, x, n); break;
         case ZFO_ANS: enc_ans(&s, x, n * es); break;
         case ZFO_DSTRIDE_BP: enc_dstride(&s, x, dtype, n); break;
+        case ZFO_DSTREE: enc_dstree(&s, x, dtype, n); break;
         case ZFO_SDICT_BP: enc_sdict(&s, x, n); break;
         case ZFO_SDICT_ANS: enc_sdict_ans(&s, x, n); break;
         case ZFO_SDICT_COL: enc_sdict_col(&s, &td, plain_off, n, dict_count); break;

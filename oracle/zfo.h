@@ -42,6 +42,7 @@ extern "C" {
 #define ZFO_SDICT_ANS 11
 #define ZFO_SDICT_COL 12
 #define ZFO_SDICT_COL_ANS 13
+#define ZFO_DSTREE 14
 
 /* status */
 #define ZFO_OK 0

@@ -12,6 +12,7 @@ I32, I64, BYTES, FIXED16, F64 = 1, 2, 3, 4, 5
 PLAIN, FOR_BP, DICT_BP, DELTA_BP, RLE_DELTA_BP, LZ77, F2I_BP, ANS, DSTRIDE_BP, SDICT_BP, SDICT_ANS = \
     1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11
 SDICT_COL, SDICT_COL_ANS = 12, 13
+DSTREE = 14
 OK, EINVAL, EUNSUP, ECORRUPT, ENOMEM = 0, 1, 2, 3, 4
 ELEM_SIZE = {I32: 4, I64: 8, BYTES: 1, FIXED16: 16, F64: 8}
 

@@ -18,7 +18,8 @@ GENLIB = os.path.join(HERE, "libzfgen.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-HOST_SRC = ["abi.cpp", "format.cpp", "encode.cpp", "plan.cpp", "run.cpp", "tune.cpp", "features.cpp"]
+HOST_SRC = ["abi.cpp", "format.cpp", "encode.cpp", "plan.cpp", "run.cpp", "tune.cpp", "features.cpp",
+            "choose.cpp"]
 HIP_SRC = ["k_persistent.hip", "k_for32.hip", "k_dict32.hip", "k_for64.hip", "k_dict64.hip",
            "k_fp128.hip", "k_f2i.hip", "k_gp.hip", "k_np.hip", "k_ans.hip", "k_mlp.hip"]
 

@@ -9,7 +9,7 @@
 namespace zf {
 const std::string &last_error();
 void compress_host(const void *src, uint64_t n_elems, uint32_t dtype, uint32_t codec,
-                   const zf_encode_opts &o, zf_column_t *col);
+                   const zf_encode_opts &o, zf_column_t *col, const uint8_t *forced_sched);
 void build_plan(zf_plan_t *P, const zf_column *const *cols, uint32_t n_cols, int device,
                 const zf_plan_opts &o);
 void decompress_async(zf_plan_t *P, const void *d_comp, uint64_t comp_bytes, void *const *d_out,
@@ -29,6 +29,8 @@ void zf_encode_opts_default(zf_encode_opts *o) {
     if (!o) return;
     std::memset(o, 0, sizeof *o);
     o->pinned = 1;
+    o->fallback_device = -1;
+    o->fallback_margin = 0.05f;
 }
 
 void zf_plan_opts_default(zf_plan_opts *o) {
@@ -50,7 +52,7 @@ zf_status zf_compress_host(const void *src, uint64_t n_elems, zf_dtype dtype, zf
         zf_encode_opts_default(&o);
         if (opts) o = *opts;
         auto col = std::make_unique<zf_column>();
-        compress_host(src, n_elems, uint32_t(dtype), uint32_t(codec), o, col.get());
+        compress_host(src, n_elems, uint32_t(dtype), uint32_t(codec), o, col.get(), nullptr);
         *out = col.release();
     });
 }

@@ -235,27 +235,23 @@ static void enc_ans(std::vector<uint8_t> &s, const uint8_t *x, uint32_t n) {
         cum[b] = c;
         c += f[b];
     }
-    std::vector<std::vector<uint16_t>> words(kAnsLanes);
-    uint32_t state[kAnsLanes];
-    for (uint32_t j = 0; j < kAnsLanes; j++) {
-        uint64_t st = kAnsL;
-        if (j < n) {
-            const uint32_t cnt = (n - 1 - j) / kAnsLanes + 1;
-            words[j].reserve(cnt);
-            for (uint32_t k = cnt; k-- > 0;) {
-                const uint32_t b = x[j + uint64_t(k) * kAnsLanes];
-                const uint64_t lim = (uint64_t(kAnsL >> 12) << 16) * f[b];
-                while (st >= lim) {
-                    words[j].push_back(uint16_t(st));
-                    st >>= 16;
-                }
-                st = (st / f[b]) * kAnsM + st % f[b] + cum[b];
-            }
+    // bytes from last to first, byte i into coder i mod 64; the words come
+    // out in the reverse of the order the decoder takes them
+    uint64_t st[kAnsLanes];
+    for (uint32_t j = 0; j < kAnsLanes; j++) st[j] = kAnsL;
+    std::vector<uint16_t> emitted;
+    emitted.reserve(n / 4 + 16);
+    for (uint32_t i = n; i-- > 0;) {
+        uint64_t &x_ = st[i % kAnsLanes];
+        const uint32_t b = x[i];
+        const uint64_t lim = (uint64_t(kAnsL >> 12) << 16) * f[b];
+        while (x_ >= lim) {
+            emitted.push_back(uint16_t(x_));
+            x_ >>= 16;
         }
-        state[j] = uint32_t(st);
+        x_ = (x_ / f[b]) * kAnsM + x_ % f[b] + cum[b];
     }
-    uint64_t nw = 0;
-    for (auto &w : words) nw += w.size();
+    const uint64_t nw = emitted.size();
     s.assign(kAnsHdr + 2 * nw, 0);
     uint8_t *p = s.data();
     wr32(p, n);
@@ -264,16 +260,12 @@ static void enc_ans(std::vector<uint8_t> &s, const uint8_t *x, uint32_t n) {
         p[16 + 2 * b] = uint8_t(f[b]);
         p[17 + 2 * b] = uint8_t(f[b] >> 8);
     }
-    uint64_t at = 0;
-    for (uint32_t j = 0; j < kAnsLanes; j++) {
-        wr32(p + 528 + 4 * j, state[j]);
-        wr32(p + 784 + 4 * j, uint32_t(at));
-        for (size_t k = words[j].size(); k-- > 0;) {
-            const uint16_t w = words[j][k];
-            p[kAnsHdr + 2 * at] = uint8_t(w);
-            p[kAnsHdr + 2 * at + 1] = uint8_t(w >> 8);
-            at++;
-        }
+    for (uint32_t j = 0; j < kAnsLanes; j++) wr32(p + 528 + 4 * j, uint32_t(st[j]));
+    uint8_t *wp = p + kAnsHdr;
+    for (uint64_t k = 0; k < nw; k++) {
+        const uint16_t w = emitted[nw - 1 - k];
+        wp[2 * k] = uint8_t(w);
+        wp[2 * k + 1] = uint8_t(w >> 8);
     }
 }
 
@@ -990,8 +982,13 @@ static void encode_chunk(std::vector<uint8_t> &out, uint32_t codec, uint32_t dty
     fail(ZF_E_INVALID, "unknown codec %u", codec);
 }
 
+double time_choice(const uint8_t *x, uint32_t n, uint32_t dtype, uint32_t codec, uint32_t sched, int device,
+                   int threads);
+
+// forced_sched (internal, nullable): the schedule stored for each chunk of an
+// explicit chunking
 void compress_host(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t codec,
-                   const zf_encode_opts &o, zf_column_t *col) {
+                   const zf_encode_opts &o, zf_column_t *col, const uint8_t *forced_sched) {
     const uint8_t *src = static_cast<const uint8_t *>(srcv);
     const uint32_t es = elem_size(dtype);
     ZF_REQUIRE(es, ZF_E_INVALID, "unknown dtype %u", dtype);
@@ -1060,6 +1057,8 @@ void compress_host(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t 
 
     // ZF_AUTO with a cost model: predicted (codec, schedule) per chunk
     std::vector<uint8_t> sched(ce.size(), 0);
+    if (forced_sched)
+        for (size_t i = 0; i < ce.size(); i++) sched[i] = forced_sched[i];
     if (any_auto) {
         CostModel model;
         std::string wpath = o.mlp_weights ? o.mlp_weights : "";
@@ -1071,19 +1070,41 @@ void compress_host(const void *srcv, uint64_t n_elems, uint32_t dtype, uint32_t 
             ZF_REQUIRE(model.load(wpath), ZF_E_INVALID, "cannot read cost model %s", wpath.c_str());
             std::vector<uint64_t> at(ce.size() + 1, 0);
             for (size_t i = 0; i < ce.size(); i++) at[i + 1] = at[i] + ce[i];
-            std::vector<int> pick(ce.size(), -1);
+            std::vector<int> pick(ce.size(), -1), runner(ce.size(), -1);
+            std::vector<float> gap(ce.size(), 0.f);
             parallel_for(ce.size(), threads, [&](uint64_t i) {
                 if (cc[i] != 0) return;
                 float x[kFeatures], y[kChoices];
                 chunk_features(src + at[i] * es, ce[i], dtype, x);
                 model.predict(x, y);
-                int best = -1;
-                for (int c = 0; c < kChoices; c++)
-                    if (choice_allowed(uint32_t(c), dtype, uint64_t(ce[i]) * es, have_dict) &&
-                        (best < 0 || y[c] < y[best]))
+                int best = -1, second = -1;
+                for (int c = 0; c < kChoices; c++) {
+                    if (!choice_allowed(uint32_t(c), dtype, uint64_t(ce[i]) * es, have_dict)) continue;
+                    if (best < 0 || y[c] < y[best]) {
+                        second = best;
                         best = c;
+                    } else if (second < 0 || y[c] < y[second]) {
+                        second = c;
+                    }
+                }
                 pick[i] = best;
+                runner[i] = second;
+                gap[i] = second >= 0 ? y[second] - y[best] : 0.f;
             });
+            // near-ties (the two lowest predicted log times closer than the
+            // margin): both candidates are timed on the device, the faster kept
+            if (o.fallback_device >= 0 && o.fallback_margin > 0) {
+                for (size_t i = 0; i < ce.size(); i++) {
+                    if (pick[i] < 0 || runner[i] < 0 || !(gap[i] < o.fallback_margin)) continue;
+                    const uint8_t *x = src + at[i] * es;
+                    const int a = pick[i], b = runner[i];
+                    const double ta = time_choice(x, ce[i], dtype, kChoiceCodec[a / 4], uint32_t(a % 4 + 1),
+                                                  o.fallback_device, threads);
+                    const double tb = time_choice(x, ce[i], dtype, kChoiceCodec[b / 4], uint32_t(b % 4 + 1),
+                                                  o.fallback_device, threads);
+                    if (tb < ta) pick[i] = b;
+                }
+            }
             std::vector<uint32_t> ce2;
             std::vector<uint8_t> cc2, sc2;
             for (size_t i = 0; i < ce.size(); i++) {

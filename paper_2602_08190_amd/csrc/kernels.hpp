@@ -1394,8 +1394,13 @@ ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, 
 // j + 64, j + 128, ... (Sec. 3.1 sees ANS as one serial state chain per chunk;
 // the 64 interleaved chains of a chunk advance in lockstep).  Per wave the LDS
 // holds the model: slot -> byte (4096 bytes) and byte -> {f, cum} (256 dwords).
-// A coder's next four 16-bit words are loaded ahead of their use, so the loop
-// waits on memory only when a coder drains words faster than that.
+// The coders share one stream of 16-bit words, read in byte order: at each
+// step the lanes whose state fell below L take the next words in lane order
+// (a ballot and a count of the set bits below each lane).  The wave keeps a
+// window of 128 words in registers (lane l: words base + l and base + 64 + l,
+// packed in one dword) and reads a lane's word with one cross-lane permute;
+// the 64 words after the window are loaded one slide ahead, so the stream is
+// read once, in coalesced 128-byte loads.
 // lds: this wave's kAnsLdsWords dwords (the last 256: output staging).
 ZF_DEV void unit_ans(const LaunchArgs &A, const ChunkDesc &ck, uint32_t *lds) {
     const uint8_t *s = A.comp + ck.comp_off;
@@ -1458,41 +1463,37 @@ ZF_DEV void unit_ans(const LaunchArgs &A, const ChunkDesc &ck, uint32_t *lds) {
         }
     }
     wave_fence();
-    // this coder's state and words
+    // this coder's state; the shared words through a bounds-checked view of
+    // the stream (0 past its end, which only a corrupt stream reaches)
     uint32_t x = ld32u(s + 528 + 4 * lane);
-    uint32_t w = ld32u(s + 784 + 4 * lane);
-    const uint32_t wend = lane + 1 < kAnsLanes ? ld32u(s + 788 + 4 * lane) : nw;
-    if (any(w > wend || wend > nw)) {
-        flag(A.err, ERR_CORRUPT);
-        return;
-    }
-    // words at, at+1, at+2, at+3 through a bounds-checked view of the chunk's
-    // words (0 past them): no branch, so the loads stay in flight until used.
-    // A coder never consumes past its own range in a valid stream; reading a
-    // neighbour's words ahead is harmless (the end check catches overruns).
     const __amdgpu_buffer_rsrc_t rw =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(s + kAnsHdr), 0, int(2 * nw), 0x00020000);
     auto ld16 = [&](uint32_t at) { return uint32_t(__builtin_amdgcn_raw_buffer_load_b16(rw, int(2 * at), 0, 0)); };
-    // the words ahead stay in four registers, combined only when taken into
-    // buf, so nothing waits for them before then
-    uint32_t a0 = ld16(w), a1 = ld16(w + 1), a2 = ld16(w + 2), a3 = ld16(w + 3);
-    uint64_t buf = uint64_t(a0 | (a1 << 16)) | (uint64_t(a2 | (a3 << 16)) << 32);
-    a0 = ld16(w + 4), a1 = ld16(w + 5), a2 = ld16(w + 6), a3 = ld16(w + 7);
-    uint32_t nbuf = 4;   // words left in buf
-    auto step = [&](uint32_t &b) {
+    // window: words [base, base + 128) in win (lane l: base + l low, base + 64
+    // + l high); ahead: word base + 128 + l.  pos - base < 64 at every step's
+    // start, so a step's at most 64 words lie inside the window.
+    uint32_t pos = 0, base = 0;
+    uint32_t win = ld16(lane) | (ld16(64 + lane) << 16);
+    uint32_t ahead = ld16(128 + lane);
+    auto step = [&](uint32_t &b, bool act) {
         const uint32_t slot = x & (kAnsM - 1);
         b = sym[slot];
         const uint32_t e = fc[b];
-        x = (e & 0xFFFFu) * (x >> 12) + slot - (e >> 16);
-        if (x < kAnsL) {  // one word at most: x >= 1 * 2^4 before the shift
-            x = (x << 16) | uint32_t(buf & 0xFFFFu);
-            buf >>= 16;
-            w++;
-            if (--nbuf == 0) {
-                buf = uint64_t(a0 | (a1 << 16)) | (uint64_t(a2 | (a3 << 16)) << 32);
-                nbuf = 4;
-                a0 = ld16(w + 4), a1 = ld16(w + 5), a2 = ld16(w + 6), a3 = ld16(w + 7);
-            }
+        const uint32_t xn = (e & 0xFFFFu) * (x >> 12) + slot - (e >> 16);
+        x = act ? xn : x;
+        const bool need = act && x < kAnsL;  // one word at most: x >= 1 * 2^4 before the shift
+        const uint64_t m = __ballot(need);
+        const uint32_t rank = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+        const uint32_t j = pos - base + rank;  // < 128
+        const uint32_t pair = uint32_t(__builtin_amdgcn_ds_bpermute(int((j & 63u) << 2), int(win)));
+        // (x << 16) | (the low or high half of pair) in one byte permute
+        const uint32_t sel = 0x05040100u + ((j >> 6) & 1u) * 0x0202u;
+        x = need ? __builtin_amdgcn_perm(x, pair, sel) : x;
+        pos += uint32_t(__popcll(m));
+        if (pos - base >= 64) {  // slide by 64 words
+            base += 64;
+            win = (win >> 16) | (ahead << 16);
+            ahead = ld16(base + 128 + lane);
         }
     };
     bool bad = false;
@@ -1504,10 +1505,10 @@ ZF_DEV void unit_ans(const LaunchArgs &A, const ChunkDesc &ck, uint32_t *lds) {
         uint8_t *stg = reinterpret_cast<uint8_t *>(lds + kAnsLdsWords - 256);
         for (; t + 16 <= n / kAnsLanes; t += 16) {
 #pragma unroll
-            for (uint32_t j = 0; j < 16; j++) {
+            for (uint32_t jj = 0; jj < 16; jj++) {
                 uint32_t b;
-                step(b);
-                stg[64 * j + lane] = uint8_t(b);
+                step(b, true);
+                stg[64 * jj + lane] = uint8_t(b);
             }
             wave_fence();
             const u32x4 v = *reinterpret_cast<const u32x4 *>(stg + 16 * lane);
@@ -1517,13 +1518,11 @@ ZF_DEV void unit_ans(const LaunchArgs &A, const ChunkDesc &ck, uint32_t *lds) {
     }
     for (; t < steps; t++) {
         const uint32_t i = t * kAnsLanes + lane;
-        if (i < n) {
-            uint32_t b;
-            step(b);
-            __builtin_nontemporal_store(uint8_t(b), gp(out) + i);  // never read back here
-        }
+        uint32_t b;
+        step(b, i < n);
+        if (i < n) __builtin_nontemporal_store(uint8_t(b), gp(out) + i);  // never read back here
     }
-    bad = x != kAnsL || w != wend;
+    bad = x != kAnsL || pos != nw;
     if (any(bad)) flag(A.err, ERR_CORRUPT);
 }
 

@@ -15,7 +15,7 @@ constexpr uint32_t kMaxCols = 256;     // output table size: columns per plan + 
 constexpr uint32_t kScratchCol = kMaxCols - 1;
 // ANS: M = 2^12 model, state in [2^16, 2^32), 64 interleaved coders, stream
 // header of 16 + 512 (frequencies) + 256 (states) + 256 (word offsets) bytes.
-constexpr uint32_t kAnsM = 4096, kAnsL = 65536, kAnsLanes = 64, kAnsHdr = 1040;
+constexpr uint32_t kAnsM = 4096, kAnsL = 65536, kAnsLanes = 64, kAnsHdr = 784;
 // ANS: LDS per wave, the model (1280 dwords) and 1 KiB of output staging
 constexpr uint32_t kAnsLdsWords = 1536;
 // String-dictionary: longest token

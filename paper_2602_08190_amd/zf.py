@@ -37,7 +37,8 @@ class EncodeOpts(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("n_threads", ctypes.c_int32),
                 ("pinned", ctypes.c_int32), ("chunk_elems", ctypes.c_void_p),
                 ("n_chunk_elems", ctypes.c_uint32), ("chunk_codecs", ctypes.c_void_p),
-                ("mlp_weights", ctypes.c_char_p)]
+                ("mlp_weights", ctypes.c_char_p), ("fallback_device", ctypes.c_int32),
+                ("fallback_margin", ctypes.c_float)]
 
 
 # kernel kinds (zf_kind), in enum order
@@ -164,7 +165,7 @@ class Column:
 
     @classmethod
     def compress(cls, x, codec, chunk_elems=None, chunk_codecs=None, chunk_bytes=None, seed=0,
-                 threads=0, pinned=True, mlp_weights=None):
+                 threads=0, pinned=True, mlp_weights=None, fallback_device=None, fallback_margin=None):
         x = np.ascontiguousarray(x)
         o = EncodeOpts()
         lib().zf_encode_opts_default(ctypes.byref(o))
@@ -175,6 +176,10 @@ class Column:
         if mlp_weights is not None:
             keep.append(mlp_weights.encode())
             o.mlp_weights = keep[-1]
+        if fallback_device is not None:
+            o.fallback_device = fallback_device
+        if fallback_margin is not None:
+            o.fallback_margin = fallback_margin
         if chunk_bytes is not None:
             o.chunk_bytes_min, o.chunk_bytes_max = chunk_bytes
         if chunk_elems is not None:
@@ -370,6 +375,15 @@ def first_codec(col):
     if col.n_chunks == 0:
         return PLAIN
     return ctypes.string_at(col.host_pointer()[0] + 64 + 28, 1)[0]
+
+
+def chunk_table(col):
+    """(n_elems, codec, schedule) of every chunk, read in place from the
+    column's 32-byte chunk-table entries (bytes 24..27, 28 and 29)."""
+    n = col.n_chunks
+    raw = ctypes.string_at(col.host_pointer()[0] + 64, 32 * n)
+    return [(int.from_bytes(raw[32 * i + 24:32 * i + 28], "little"), raw[32 * i + 28], raw[32 * i + 29])
+            for i in range(n)]
 
 
 def kind_of_column(col):

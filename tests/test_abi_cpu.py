@@ -108,7 +108,7 @@ def test_ans_host_validation():
     with pytest.raises(zf.ZfError):
         zf.Column.from_bytes(t, pinned=False)
     t = b.copy()
-    t[c["comp_off"] + 784 + 4 * 7 + 3] = 0x7F  # a word offset past the words
+    t[c["comp_off"] + 4] ^= 1  # a word count that does not match the stream's size
     with pytest.raises(zf.ZfError):
         zf.Column.from_bytes(t, pinned=False)
 

@@ -1,0 +1,79 @@
+"""Regret of the committed cost model against exhaustive measured search
+(Sec. 3.3: the learned choice stands in for measuring every (codec,
+schedule); the target is a total time within 5% of the best).
+
+The exhaustive table is measured here, on this GPU, for held-out chunks (the
+columns the committed network never saw in training: (id // 5) % 5 == 4, two
+of each family, one 8 MiB chunk each): every applicable (codec, schedule)
+timed by zf_transfer_and_decompress, median of three.  Two choosers are priced
+against it: the network's argmin, and the product encoder (ZF_AUTO with the
+committed weights and near-tie timing on this device), whose choice is read
+back from the column's chunk table."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2602_08190_amd import learn as Lr
+from paper_2602_08190_amd import zf
+
+from conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+HERE = os.path.dirname(os.path.abspath(Lr.__file__))
+WEIGHTS = os.path.join(HERE, "cost_model_gfx950.bin")
+HELD_OUT = [20, 21, 22, 23, 24, 45, 46, 47, 48, 49]
+
+
+def read_weights(path):
+    raw = open(path, "rb").read()
+    assert raw[:8] == b"ZFMLP1\0\0"
+    v = np.frombuffer(raw[8:], "<f4")
+    return v[:32].copy(), v[32:64].copy(), v[64:].copy()
+
+
+def test_regret_against_measured_exhaustive_search(tmp_path):
+    assert all((c // 5) % 5 == 4 for c in HELD_OUT)
+    out = str(tmp_path / "held_out.npz")
+    Lr.collect(HELD_OUT, out, chunk_bytes=Lr.CHUNK_BYTES, chunks_per_col=1)
+    d = Lr.load([out])
+    T = d["T"]
+    assert T.shape == (len(HELD_OUT), 24) and np.all(np.isfinite(T).sum(axis=1) >= 8)
+    best = np.nanmin(T, axis=1)
+
+    mean, scale, params = read_weights(WEIGHTS)
+    Y = Lr.predict(mean, scale, params, d["X"])
+    ev = Lr.evaluate(d, np.ones(len(T), bool), Y)
+    print("network", {k: ev[k] for k in ("regret_mlp", "regret_mlp_fallback", "fallback_rate",
+                                          "regret_smallest_stream_tuned", "exact_best_rate")})
+    assert ev["regret_mlp"] <= 0.05
+
+    # the product: ZF_AUTO with the weights, near-ties timed on device 0
+    chosen, n_timed = [], 0
+    for row, i in enumerate(HELD_OUT):
+        x = Lr.chunk_data(i, 0, Lr.column_params(i), Lr.CHUNK_BYTES)
+        col = zf.Column.compress(x, zf.AUTO, chunk_elems=[len(x)], mlp_weights=WEIGHTS,
+                                 fallback_device=0, fallback_margin=0.05)
+        table = zf.chunk_table(col)
+        codec, sched = table[0][1], table[0][2]
+        assert all(c == codec and s == sched for _, c, s in table)  # LZ77 splits keep one choice
+        assert 1 <= sched <= 4
+        k = Lr.CODECS.index(codec) * 4 + sched - 1
+        assert np.isfinite(T[row, k])
+        chosen.append(T[row, k])
+        # what was decoded is what was encoded
+        plan = zf.Plan([col], device=0)
+        outs = zf.empty_outputs([col])
+        plan.transfer_and_decompress(outs)
+        plan.sync()
+        assert np.array_equal(outs[0].cpu().numpy(), x)
+        plan.free()
+        col.free()
+        ys = np.where(np.isfinite(T[row]), Y[row], np.inf)
+        o = np.argsort(ys)
+        n_timed += int(ys[o[1]] - ys[o[0]] < 0.05)
+    regret = float(np.sum(chosen) / np.sum(best) - 1.0)
+    print(f"product ZF_AUTO + near-tie timing: regret {regret:.4f} over {len(T)} chunks "
+          f"({n_timed} near-ties timed)")
+    assert regret <= 0.05

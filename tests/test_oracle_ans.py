@@ -1,5 +1,6 @@
-"""ANS (range ANS, 64 interleaved coders) in the oracle, pinned to things
-other than itself: hand-computed streams (one with renormalisation), the
+"""ANS (range ANS, 64 interleaved coders sharing one word stream) in the
+oracle, pinned to things other than itself: hand-computed streams (two with
+renormalisation, one of them interleaving two coders' words), the
 hand-derived frequency quantisation, brute-force round trips of every short
 string over a small alphabet, the coding cost against the model's entropy,
 and rejection of corrupt streams."""
@@ -11,7 +12,7 @@ import numpy as np
 
 import oracle.zfo as z
 
-HDR = 1040
+HDR = 784
 
 
 def stream_of(blob, i=0):
@@ -19,15 +20,14 @@ def stream_of(blob, i=0):
     return bytes(blob[c["comp_off"]:c["comp_off"] + c["comp_len"]])
 
 
-def expected_stream(n, freq, states, wofs, words):
+def expected_stream(n, freq, states, words):
     def per_lane(d):
         return [d.get(str(j), d.get("rest")) for j in range(64)]
     f = [0] * 256
     for k, v in freq.items():
         f[int(k)] = v
     return (struct.pack("<IIII", n, len(words), 0, 0) + struct.pack("<256H", *f) +
-            struct.pack("<64I", *per_lane(states)) + struct.pack("<64I", *per_lane(wofs)) +
-            struct.pack(f"<{len(words)}H", *words))
+            struct.pack("<64I", *per_lane(states)) + struct.pack(f"<{len(words)}H", *words))
 
 
 def freqs_of(stream):
@@ -40,8 +40,10 @@ def test_golden_streams(golden):
     x0 = np.frombuffer(ex[0]["text"].encode(), np.uint8)
     x1 = np.full(256, ord("a"), np.uint8)
     x1[[0, 64, 128, 192]] = [ord("W"), ord("X"), ord("Y"), ord("Z")]
-    for e, x in ((ex[0], x0), (ex[1], x1)):
-        want = expected_stream(len(x), e["freq"], e["states"], e["wofs"], e["words"])
+    x2 = np.full(256, ord("a"), np.uint8)
+    x2[[0, 64, 128, 192, 65, 193]] = [ord(c) for c in "PQRSTU"]
+    for e, x in ((ex[0], x0), (ex[1], x1), (ex[2], x2)):
+        want = expected_stream(len(x), e["freq"], e["states"], e["words"])
         got = stream_of(z.encode(x, z.ANS))
         assert got == want, e["name"]
         rc, out = z.decode_stream(z.ANS, z.BYTES, want, len(x))
@@ -92,7 +94,8 @@ def test_corrupt_streams_rejected():
     bad = []
     t = bytearray(s); t[16 + 2 * ord("A")] ^= 1; bad.append(t)          # frequencies not summing to M
     t = bytearray(s); t[528] ^= 0x40; bad.append(t)                     # a final state
-    t = bytearray(s); t[784 + 4 * 5] += 1; bad.append(t)                # a coder's word range
+    t = bytearray(s); t[4] += 1; bad.append(t)                          # the word count
+    t = bytearray(s[:-2]); t[4:8] = struct.pack("<I", len(t) // 2 - HDR // 2); bad.append(t)  # a word short
     t = bytearray(s); t[HDR] ^= 0xFF; t[HDR + 1] ^= 0xFF; bad.append(t)  # a word
     for t in bad:
         assert z.decode_stream(z.ANS, z.BYTES, bytes(t), n)[0] == z.ECORRUPT

@@ -212,6 +212,6 @@ def test_nested_corrupt_streams_are_rejected():
         return z.decode_stream(z.SDICT_ANS, z.BYTES, bytes(s), len(x))[0]
     assert bad(lambda s: struct.pack_into("<I", s, co, 2)) == z.ECORRUPT        # piece count
     assert bad(lambda s: struct.pack_into("<I", s, co + 8, 7)) == z.ECORRUPT    # ANS length field
-    last = co + 8 + 1040 + 2 * struct.unpack_from("<I", good, co + 8 + 4)[0] - 1  # end of the ANS words
+    last = co + 8 + 784 + 2 * struct.unpack_from("<I", good, co + 8 + 4)[0] - 1  # end of the ANS words
     assert bad(lambda s: s.__setitem__(last, s[last] ^ 0x55)) == z.ECORRUPT  # a word
     assert bad(lambda s: struct.pack_into("<I", s, 24, co + 16)) == z.ECORRUPT  # codes offset
