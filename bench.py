@@ -135,6 +135,12 @@ def single(kind, n):
         c = zf.Column.compress(x, zf.DSTRIDE_BP)
         desc = (f"DSTRIDE_BP int32, {n} nearly increasing keys (blocks of consecutive keys, "
                 f"geometric(8) lengths, jumps uniform 1..64), 1 MiB chunks")
+    elif kind == "orderkey":
+        x = g.orderkey_column(n, 12)
+        c = zf.Column.compress(x, zf.DSTREE)
+        desc = (f"DSTREE int32, {n} sparse order keys (the first 8 of every 32, 1% deleted): DeltaStride | "
+                f"[Delta | RLE | [BP, BP], BP], 1 MiB chunks (two launches: the run starts into scratch, "
+                f"then the output)")
     elif kind == "copy":
         x = np.frombuffer(np.random.default_rng(0).bytes(n), np.uint8)
         c = zf.Column.compress(x, zf.PLAIN, chunk_bytes=(4 << 20, 4 << 20))
@@ -336,7 +342,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="fact", choices=["fact", "for", "rle", "lz", "f2i", "ans", "keys", "sdict",
+    ap.add_argument("--workload", default="fact", choices=["fact", "for", "rle", "lz", "f2i", "ans", "keys", "orderkey", "sdict",
                                                               "sdict_ans", "sdict_col", "sdict_col_ans", "copy"])
     ap.add_argument("--rows", type=int, default=None)
     ap.add_argument("--text-codec", default="sdict_col_ans", choices=sorted(TEXT_CODECS),
@@ -366,7 +372,7 @@ def main():
         cols, xs, names, desc = fact_table(args.rows or g.FACT_ROWS, args.text_codec)
     else:
         n = args.rows or {"for": 1 << 28, "rle": 1 << 26, "lz": 1 << 30, "f2i": 1 << 26,
-                           "ans": 1 << 30, "keys": 1 << 26, "sdict": 1 << 30, "sdict_ans": 1 << 30,
+                           "ans": 1 << 30, "keys": 1 << 26, "orderkey": 1 << 26, "sdict": 1 << 30, "sdict_ans": 1 << 30,
                            "sdict_col": 1 << 30, "sdict_col_ans": 1 << 30, "copy": 1 << 30}[args.workload]
         cols, xs, names, desc = single(args.workload, n)
     plain = sum(c.plain_bytes for c in cols)
@@ -447,6 +453,8 @@ def main():
         key = zf.kind_of_column(c)
         if zf.first_codec(c) in (zf.SDICT_ANS, zf.SDICT_COL_ANS):
             key = "ANS+SDICT"  # two ordered launches: the ANS stage, then String-dictionary
+        if zf.first_codec(c) == zf.DSTREE:
+            key = ("RLE32" if c.dtype == zf.I32 else "RLE64") + "+TREE"  # the run starts, then the output
         if args.persistent:
             key = "PERSISTENT"
         groups[key] = groups.get(key, 0) + c.host_pointer()[1] + c.plain_bytes
@@ -483,7 +491,9 @@ def main():
                      "unit": "GB/s", "frac": kinds[dom]["frac_of_hbm_peak"],
                      "traffic": group_traffic(args.workload, dom),
                      "kernel": {"LZ77": "k_decode_lz (LZ77)", "ANS": "k_decode_ans",
-                                "ANS+SDICT": "k_decode_ans then k_decode_kind<SDICT>",
+                                "ANS+SDICT": "k_decode_ans then k_decode_sdict",
+                                "RLE32+TREE": "k_decode_kind<RLE32> then k_decode_kind<TREE>",
+                                "RLE64+TREE": "k_decode_kind<RLE64> then k_decode_kind<TREE>",
                                 "PERSISTENT": "k_decode_persistent"}.get(dom, f"k_decode_kind<{dom}>"),
                      "algorithmic_bytes_per_launch": kinds[dom]["algorithmic_bytes"],
                      "avg_launch_ms": kinds[dom]["ms_median"],

@@ -95,8 +95,9 @@ typedef enum {
  *                   the byte counts), byte i coded by coder i mod 64, state
  *                   in [2^16, 2^32), 16-bit renormalisation.  Header {u32 n,
  *                   u32 nw, u32 0, u32 0}, u16 f[256], u32 final state[64],
- *                   u32 word offset[64], then nw u16 words, each coder's in
- *                   decode order.  Any dtype (decoded as bytes).
+ *                   then nw u16 words shared by the coders, in the order
+ *                   the decoder reads them (byte order: each renormalisation
+ *                   takes the next word).  Any dtype (decoded as bytes).
  *  ZF_DSTRIDE_BP    [GP] DeltaStride (Sec. 5): runs that are arithmetic
  *                   progressions (start, stride, count), maximal from the
  *                   left; groups of 64 runs, each with a 32-byte record
@@ -107,6 +108,21 @@ typedef enum {
  *                   fields, FOR-bit-packed.  Start j >= 1 = start j-1 +
  *                   stride j-1 * count j-1 + gap j.  Header and u32 run
  *                   lengths as ZF_RLE_DELTA_BP.  I32, I64.
+ *  ZF_DSTREE        [GP, two stages] DeltaStride | [Delta | RLE | [BP, BP],
+ *                   BP], the order-key scheme of Sec. 5: stride d = the
+ *                   chunk's most frequent neighbour difference (ties to the
+ *                   smaller, unsigned); maximal runs of step d give starts S
+ *                   and counts C; D = S[0], S[1] - S[0], ... is run-length
+ *                   coded into values V and lengths L; V, L, C bit-packed per
+ *                   group of 64 against the group minimum.  Header {u32 R,
+ *                   u32 ngB, u32 Q, u32 ngA, i64 d, u32 b_off = 32 + 32 ngA,
+ *                   u32 0}; D groups {u32 out_off, u32 poff, u32 widths (V
+ *                   bits 0-7, L bits 8-15), u32 lmin, i64 base, i64 vmin} at
+ *                   32; run groups {u32 out_off, u32 poff, u32 wc, u32 cmin}
+ *                   at b_off; payloads after them (V fields, then L fields
+ *                   from the next word; C fields).  The starts are decoded
+ *                   into the plan's scratch area by one launch and expanded
+ *                   by the next (no persistent kernel).  I32, I64.
  *  ZF_SDICT_BP      [GP] String-dictionary (Sec. 2.1, Sec. 5): tokens end
  *                   after ' ' or '.' (at most 64 bytes; the chunk's last may
  *                   end without one); distinct tokens in order of first
@@ -162,7 +178,8 @@ typedef enum {
     ZF_SDICT_BP = 10,
     ZF_SDICT_ANS = 11,
     ZF_SDICT_COL = 12,
-    ZF_SDICT_COL_ANS = 13
+    ZF_SDICT_COL_ANS = 13,
+    ZF_DSTREE = 14
 } zf_codec;
 
 typedef void *zf_stream_t;              /* a hipStream_t */
@@ -249,6 +266,7 @@ typedef enum {
     ZF_KIND_FOR32,
     ZF_KIND_F2I,     /* Float2Int + bit-packing, float64 */
     ZF_KIND_PLAIN,
+    ZF_KIND_TREE,    /* DSTREE output stage (its run starts decode in RLE32/RLE64) */
     ZF_KIND_COUNT
 } zf_kind;
 

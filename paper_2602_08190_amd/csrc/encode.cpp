@@ -548,6 +548,127 @@ static void enc_dstride(std::vector<uint8_t> &s, const T *x, uint32_t n) {
     for (uint32_t j = 0; j < nr; j++) wr32(p + roff + 4ull * j, len[j]);
 }
 
+// ------------------------------------ DeltaStride | [Delta | RLE | [BP, BP], BP]
+// The chunk's stride d is its most frequent neighbour difference (ties to the
+// smaller as unsigned); maximal runs of step d give the starts S and counts
+// C; D = S[0], S[1] - S[0], ... is run-length coded into V (values) and L
+// (lengths).  V, L and C are bit-packed per group of 64 against the group's
+// smallest value; each group record holds its output offset (D's groups also
+// the start before them), so both levels decode group-parallel.
+template <class T>
+static void enc_dstree(std::vector<uint8_t> &s, const T *x, uint32_t n) {
+    using U = std::make_unsigned_t<T>;
+    U d = 0;
+    if (n > 1) {
+        std::vector<U> df(n - 1);
+        for (uint32_t i = 0; i + 1 < n; i++) df[i] = U(U(x[i + 1]) - U(x[i]));
+        std::sort(df.begin(), df.end());
+        uint32_t best = 0;
+        for (uint32_t i = 0; i < n - 1;) {
+            uint32_t k = i;
+            while (k < n - 1 && df[k] == df[i]) k++;
+            if (k - i > best) {
+                best = k - i;
+                d = df[i];
+            }
+            i = k;
+        }
+    }
+    std::vector<U> S, V;
+    std::vector<uint32_t> C, L;
+    for (uint32_t i = 0; i < n;) {
+        uint32_t r = 1;
+        while (i + r < n && U(U(x[i + r]) - U(x[i + r - 1])) == d) r++;
+        S.push_back(U(x[i]));
+        C.push_back(r);
+        i += r;
+    }
+    for (size_t k = 0; k < S.size(); k++) {
+        const U dk = k == 0 ? S[0] : U(S[k] - S[k - 1]);
+        if (!V.empty() && V.back() == dk) L.back()++;
+        else {
+            V.push_back(dk);
+            L.push_back(1);
+        }
+    }
+    const uint32_t R = uint32_t(S.size()), Q = uint32_t(V.size());
+    const uint32_t ngA = (Q + 63) / 64, ngB = (R + 63) / 64;
+    const uint64_t b_off = 32 + 32ull * ngA;
+    auto words = [](uint32_t cnt, uint32_t w) { return (uint64_t(cnt) * w + 31) / 32; };
+    struct GA { uint32_t wv, wl, lmin; T vmin; };
+    struct GB { uint32_t wc, cmin; };
+    std::vector<GA> ga(ngA);
+    std::vector<GB> gb(ngB);
+    uint64_t pos = b_off + 16ull * ngB;
+    for (uint32_t g = 0; g < ngA; g++) {
+        const uint32_t j0 = 64 * g, cnt = std::min(64u, Q - j0);
+        T vmin = T(V[j0]);
+        uint32_t lmin = L[j0], lmax = L[j0];
+        for (uint32_t j = 1; j < cnt; j++) {
+            vmin = std::min(vmin, T(V[j0 + j]));
+            lmin = std::min(lmin, L[j0 + j]);
+            lmax = std::max(lmax, L[j0 + j]);
+        }
+        U fmax = 0;
+        for (uint32_t j = 0; j < cnt; j++) fmax = std::max(fmax, U(V[j0 + j] - U(vmin)));
+        ga[g] = {bit_width64(uint64_t(fmax)), bit_width64(lmax - lmin), lmin, vmin};
+        pos += 4 * (words(cnt, ga[g].wv) + words(cnt, ga[g].wl));
+    }
+    for (uint32_t g = 0; g < ngB; g++) {
+        const uint32_t j0 = 64 * g, cnt = std::min(64u, R - j0);
+        uint32_t lo = C[j0], hi = C[j0];
+        for (uint32_t j = 1; j < cnt; j++) {
+            lo = std::min(lo, C[j0 + j]);
+            hi = std::max(hi, C[j0 + j]);
+        }
+        gb[g] = {bit_width64(hi - lo), lo};
+        pos += 4 * words(cnt, gb[g].wc);
+    }
+    s.assign(pos, 0);
+    uint8_t *p = s.data();
+    wr32(p, R);
+    wr32(p + 4, ngB);
+    wr32(p + 8, Q);
+    wr32(p + 12, ngA);
+    wr64(p + 16, uint64_t(int64_t(T(d))));
+    wr32(p + 24, uint32_t(b_off));
+    pos = b_off + 16ull * ngB;
+    uint32_t at = 0;
+    for (uint32_t g = 0; g < ngA; g++) {
+        const uint32_t j0 = 64 * g, cnt = std::min(64u, Q - j0);
+        const GA &q = ga[g];
+        uint8_t *rec = p + 32 + 32ull * g;
+        wr32(rec, at);
+        wr32(rec + 4, uint32_t(pos));
+        wr32(rec + 8, q.wv | (q.wl << 8));
+        wr32(rec + 12, q.lmin);
+        wr64(rec + 16, at == 0 ? 0 : uint64_t(int64_t(T(S[at - 1]))));
+        wr64(rec + 24, uint64_t(int64_t(q.vmin)));
+        BitPacker bv(p + pos);
+        for (uint32_t j = 0; j < cnt; j++) bv.put(uint64_t(U(V[j0 + j] - U(q.vmin))), q.wv);
+        bv.flush();
+        BitPacker bl(p + pos + 4 * words(cnt, q.wv));
+        for (uint32_t j = 0; j < cnt; j++) bl.put(L[j0 + j] - q.lmin, q.wl);
+        bl.flush();
+        pos += 4 * (words(cnt, q.wv) + words(cnt, q.wl));
+        for (uint32_t j = 0; j < cnt; j++) at += L[j0 + j];
+    }
+    uint32_t out = 0;
+    for (uint32_t g = 0; g < ngB; g++) {
+        const uint32_t j0 = 64 * g, cnt = std::min(64u, R - j0);
+        uint8_t *rec = p + b_off + 16ull * g;
+        wr32(rec, out);
+        wr32(rec + 4, uint32_t(pos));
+        wr32(rec + 8, gb[g].wc);
+        wr32(rec + 12, gb[g].cmin);
+        BitPacker bc(p + pos);
+        for (uint32_t j = 0; j < cnt; j++) bc.put(C[j0 + j] - gb[g].cmin, gb[g].wc);
+        bc.flush();
+        pos += 4 * words(cnt, gb[g].wc);
+        for (uint32_t j = 0; j < cnt; j++) out += C[j0 + j];
+    }
+}
+
 // ------------------------------------------------------ String-dictionary
 // Tokens end after a space or a period (at most 64 bytes; the chunk's last
 // token may end without one); the distinct tokens, in order of first
@@ -963,6 +1084,10 @@ static void encode_chunk(std::vector<uint8_t> &out, uint32_t codec, uint32_t dty
     case C_DSTRIDE_BP:
         if (dtype == D_I32) enc_dstride<int32_t>(out, reinterpret_cast<const int32_t *>(x), n);
         else enc_dstride<int64_t>(out, reinterpret_cast<const int64_t *>(x), n);
+        return;
+    case C_DSTREE:
+        if (dtype == D_I32) enc_dstree<int32_t>(out, reinterpret_cast<const int32_t *>(x), n);
+        else enc_dstree<int64_t>(out, reinterpret_cast<const int64_t *>(x), n);
         return;
     case C_SDICT_BP: enc_sdict(out, x, n); return;
     case C_SDICT_ANS: {

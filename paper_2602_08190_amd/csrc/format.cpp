@@ -40,7 +40,8 @@ bool codec_allows(uint32_t codec, uint32_t dtype) {
     case C_FOR_BP:
     case C_DELTA_BP:
     case C_RLE_DELTA_BP:
-    case C_DSTRIDE_BP: return dtype == D_I32 || dtype == D_I64;
+    case C_DSTRIDE_BP:
+    case C_DSTREE: return dtype == D_I32 || dtype == D_I64;
     case C_SDICT_BP:
     case C_SDICT_ANS:
     case C_SDICT_COL:
@@ -67,6 +68,7 @@ Kind kind_of(uint32_t codec, uint32_t dtype) {
     case C_LZ77: return K_LZ;
     case C_F2I_BP: return K_F2I;
     case C_ANS: return K_ANS;
+    case C_DSTREE: return K_TREE;
     }
     fail(ZF_E_CORRUPT, "unknown codec %u", codec);
 }
@@ -285,6 +287,41 @@ void check_stream(const ColumnView &v, const uint8_t *blob, uint32_t i) {
                        ZF_E_CORRUPT, "chunk %u group %u: bad record", i, g);
             ZF_REQUIRE(g == 0 ? off == 0 : (off > prev && off < n), ZF_E_CORRUPT,
                        "chunk %u group %u: output offset out of order", i, g);
+            prev = off;
+        }
+        return;
+    }
+    case C_DSTREE: {
+        // header, both levels' group records (widths, payloads in range,
+        // output offsets from 0 and increasing); the run lengths and counts
+        // are checked by the kernels as they expand them
+        const uint32_t bits = v.dtype == D_I32 ? 32 : 64;
+        ZF_REQUIRE(L >= 32, ZF_E_CORRUPT, "chunk %u: short DeltaStride tree header", i);
+        const uint32_t R = rd32(s), ngB = rd32(s + 4), Q = rd32(s + 8), ngA = rd32(s + 12), b_off = rd32(s + 24);
+        ZF_REQUIRE(R >= 1 && R <= n && Q >= 1 && Q <= R && ngB == (uint64_t(R) + 63) / 64 &&
+                       ngA == (uint64_t(Q) + 63) / 64 && b_off == 32 + 32ull * ngA && rd32(s + 28) == 0 &&
+                       b_off + 16ull * ngB <= L,
+                   ZF_E_CORRUPT, "chunk %u: DeltaStride tree header does not match its sizes", i);
+        uint64_t prev = 0;
+        for (uint32_t g = 0; g < ngA; g++) {
+            const uint8_t *r = s + 32 + 32ull * g;
+            const uint32_t off = rd32(r), poff = rd32(r + 4), widths = rd32(r + 8);
+            const uint32_t wv = widths & 0xFFu, wl = (widths >> 8) & 0xFFu, cnt = std::min(64u, Q - 64 * g);
+            ZF_REQUIRE(wv <= bits && wl <= 32 && (widths >> 16) == 0 && poff % 4 == 0 &&
+                           poff + 4 * (words_for(cnt, wv) + words_for(cnt, wl)) <= L,
+                       ZF_E_CORRUPT, "chunk %u start group %u: bad record", i, g);
+            ZF_REQUIRE(g == 0 ? off == 0 : (off > prev && off < R), ZF_E_CORRUPT,
+                       "chunk %u start group %u: output offset out of order", i, g);
+            prev = off;
+        }
+        prev = 0;
+        for (uint32_t g = 0; g < ngB; g++) {
+            const uint8_t *r = s + b_off + 16ull * g;
+            const uint32_t off = rd32(r), poff = rd32(r + 4), wc = rd32(r + 8), cnt = std::min(64u, R - 64 * g);
+            ZF_REQUIRE(wc <= 32 && poff % 4 == 0 && poff + 4 * words_for(cnt, wc) <= L, ZF_E_CORRUPT,
+                       "chunk %u run group %u: bad record", i, g);
+            ZF_REQUIRE(g == 0 ? off == 0 : (off > prev && off < n), ZF_E_CORRUPT,
+                       "chunk %u run group %u: output offset out of order", i, g);
             prev = off;
         }
         return;

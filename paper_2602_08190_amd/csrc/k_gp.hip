@@ -1,9 +1,11 @@
-// Group-Parallel decodes: RLE + delta, DeltaStride, String-dictionary.
+// Group-Parallel decodes: RLE + delta, DeltaStride (and its order-key tree),
+// String-dictionary.
 #include "kernels.hpp"
 
 namespace zf {
 ZF_DEFINE_LAUNCHER(K_RLE32, launch_rle32)
 ZF_DEFINE_LAUNCHER(K_RLE64, launch_rle64)
+ZF_DEFINE_LAUNCHER(K_TREE, launch_tree)
 // String-dictionary: tiles mapped XCD-aware (the tiles of a chunk share its
 // dictionary, so neighbouring tiles go to the same XCD and its L2); each
 // wave's staging buffer is dynamic shared memory, kSdBufWords dwords.

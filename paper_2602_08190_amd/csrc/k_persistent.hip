@@ -65,8 +65,10 @@ hipError_t launch_decode(const LaunchArgs &A, uint32_t persistent_waves, const u
         return mark(K_COUNT, true);
     }
     // launch order: the slow serial kinds first
-    static const uint32_t order[K_COUNT] = {K_LZ, K_ANS, K_RLE32, K_RLE64, K_SDICT, K_DICT128,
-                                            K_DICT64, K_DICT32, K_FOR64, K_FOR32, K_F2I, K_PLAIN};
+    // (TREE after the RLE kinds, which write its chunks' run starts; SDICT
+    // after ANS, which writes its chunks' entry indices)
+    static const uint32_t order[K_COUNT] = {K_LZ,     K_ANS,    K_RLE32, K_RLE64, K_TREE, K_SDICT, K_DICT128,
+                                            K_DICT64, K_DICT32, K_FOR64, K_FOR32, K_F2I,  K_PLAIN};
     for (uint32_t i = 0; i < K_COUNT; i++) {
         const uint32_t k = order[i];
         if (A.kind_begin[k + 1] == A.kind_begin[k]) continue;
@@ -76,6 +78,7 @@ hipError_t launch_decode(const LaunchArgs &A, uint32_t persistent_waves, const u
         case K_ANS: launch_ans(A, wpb[K_ANS], st); break;
         case K_RLE32: launch_rle32(A, wpb[K_RLE32], st); break;
         case K_RLE64: launch_rle64(A, wpb[K_RLE64], st); break;
+        case K_TREE: launch_tree(A, wpb[K_TREE], st); break;
         case K_SDICT: launch_sdict(A, wpb[K_SDICT], st); break;
         case K_DICT128: launch_dict128(A, wpb[K_DICT128], st); break;
         case K_DICT64: launch_dict64(A, wpb[K_DICT64], st); break;

@@ -605,6 +605,84 @@ ZF_DEV U field_of(uint32_t w0, uint32_t w1, uint32_t w2, uint64_t bit, uint32_t 
     }
 }
 
+// Expansion of one group of up to 64 runs into out[a, bnd): lane j holds run
+// j (act), its output range [start_abs, end_abs) and its value: v for RLE
+// (DS = false), v + dstr * p at element p for progressions (DS = true).
+// Output goes by windows of 64 lanes x 16 bytes: each run starting in the
+// window writes its index into an LDS slot at its start, a wave scan carries
+// the latest index over the window, and each lane takes its values with
+// cross-lane permutes — no per-run loop.  slot: this wave's 256 dwords.
+template <class U, bool DS>
+ZF_DEV void expand_runs(U *out, uint32_t a, uint32_t bnd, bool act, uint32_t start_abs, uint32_t end_abs, U v,
+                        U dstr, uint32_t *slot) {
+    constexpr uint32_t BITS = sizeof(U) * 8;
+    const uint32_t lane = lane_id();
+    // R outputs per lane per window (16 bytes: one aligned store when whole)
+    constexpr uint32_t R = 16 / sizeof(U), SPAN = 64 * R;
+    if (a < bnd) {
+        // window grid aligned so that out + W0 + R * lane is 16-byte aligned
+        // (signed: the first window may start before element 0)
+        const int32_t mis = int32_t((reinterpret_cast<uintptr_t>(out + a) & 15u) / sizeof(U));
+        const int32_t ia = int32_t(a), ib = int32_t(bnd);
+        // 1 + index of the run holding a (a run index, plus one, marks a start)
+        uint32_t carry = 1 + uint32_t(__popcll(__ballot(act && end_abs <= a)));
+        for (int32_t W0 = ia - mis; W0 < ib; W0 += int32_t(SPAN)) {
+#pragma unroll
+            for (uint32_t i = 0; i < R; i++) slot[64 * i + lane] = 0;
+            wave_fence();
+            // element W0 + R l + i has slot 64 i + l
+            const uint32_t rel = start_abs - uint32_t(W0);
+            if (act && rel < SPAN && start_abs >= a) slot[64 * (rel % R) + rel / R] = lane + 1;
+            wave_fence();
+            uint32_t m[R], last = 0;
+#pragma unroll
+            for (uint32_t i = 0; i < R; i++) {
+                m[i] = slot[64 * i + lane];
+                last = m[i] ? m[i] : last;
+            }
+            uint32_t cur1 = last_nonzero_below(last, carry);
+            U val[R];
+#pragma unroll
+            for (uint32_t i = 0; i < R; i++) {
+                cur1 = m[i] ? m[i] : cur1;
+                const int src = int((cur1 - 1) * 4);
+                if constexpr (BITS == 32) {
+                    val[i] = uint32_t(__builtin_amdgcn_ds_bpermute(src, int(v)));
+                } else {
+                    const uint32_t lo = uint32_t(__builtin_amdgcn_ds_bpermute(src, int(uint32_t(v))));
+                    const uint32_t hi = uint32_t(__builtin_amdgcn_ds_bpermute(src, int(uint32_t(v >> 32))));
+                    val[i] = uint64_t(lo) | (uint64_t(hi) << 32);
+                }
+                if constexpr (DS) {
+                    // plus stride * element index
+                    U dd;
+                    if constexpr (BITS == 32) {
+                        dd = uint32_t(__builtin_amdgcn_ds_bpermute(src, int(dstr)));
+                    } else {
+                        const uint32_t lo = uint32_t(__builtin_amdgcn_ds_bpermute(src, int(uint32_t(dstr))));
+                        const uint32_t hi =
+                            uint32_t(__builtin_amdgcn_ds_bpermute(src, int(uint32_t(dstr >> 32))));
+                        dd = uint64_t(lo) | (uint64_t(hi) << 32);
+                    }
+                    val[i] = U(val[i] + dd * U(uint32_t(W0 + int32_t(R * lane + i))));
+                }
+            }
+            const int32_t p = W0 + int32_t(R * lane);
+            if (p >= ia && p + int32_t(R) <= ib) {
+                u32x4 q;
+                if constexpr (BITS == 32) q = u32x4{val[0], val[1], val[2], val[3]};
+                else q = u32x4{uint32_t(val[0]), uint32_t(val[0] >> 32), uint32_t(val[1]), uint32_t(val[1] >> 32)};
+                __builtin_nontemporal_store(q, gp(reinterpret_cast<u32x4 *>(out + p)));
+            } else {
+#pragma unroll
+                for (int32_t i = 0; i < int32_t(R); i++)
+                    if (p + i >= ia && p + i < ib) out[p + i] = val[i];
+            }
+            wave_fence();
+        }
+    }
+}
+
 // Group-Parallel decode of RLE_DELTA_BP / DELTA_BP (DS = false) and
 // DSTRIDE_BP (DS = true) chunks: one wave expands the groups that meet its
 // tile's element range [t.b, t.c), starting with group t.a.
@@ -727,74 +805,140 @@ ZF_DEV void unit_rle(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, ui
                 delta = U(cur.dmin + field_of<U>(cur.w0, cur.w1, cur.w2, uint64_t(lane - 1) * cur.w, cur.w));
             v = scan_addT<U>(act ? delta : U(0));
         }
-        // expand the part of this group inside [e0, e1), R outputs per lane
-        // per window (16 bytes: one aligned store when whole)
-        constexpr uint32_t R = 16 / sizeof(U), SPAN = 64 * R;
-        const uint32_t a = max(e0, cur.goff), bnd = min(e1, cur.next_off);
-        if (a < bnd) {
-            // window grid aligned so that out + W0 + R * lane is 16-byte aligned
-            // (signed: the first window may start before element 0)
-            const int32_t mis = int32_t((reinterpret_cast<uintptr_t>(out + a) & 15u) / sizeof(U));
-            const int32_t ia = int32_t(a), ib = int32_t(bnd);
-            // 1 + index of the run holding a (a run index, plus one, marks a start)
-            uint32_t carry = 1 + uint32_t(__popcll(__ballot(act && end_abs <= a)));
-            for (int32_t W0 = ia - mis; W0 < ib; W0 += int32_t(SPAN)) {
-#pragma unroll
-                for (uint32_t i = 0; i < R; i++) slot[64 * i + lane] = 0;
-                wave_fence();
-                // element W0 + R l + i has slot 64 i + l
-                const uint32_t rel = start_abs - uint32_t(W0);
-                if (act && rel < SPAN && start_abs >= a) slot[64 * (rel % R) + rel / R] = lane + 1;
-                wave_fence();
-                uint32_t m[R], last = 0;
-#pragma unroll
-                for (uint32_t i = 0; i < R; i++) {
-                    m[i] = slot[64 * i + lane];
-                    last = m[i] ? m[i] : last;
-                }
-                uint32_t cur1 = last_nonzero_below(last, carry);
-                U val[R];
-#pragma unroll
-                for (uint32_t i = 0; i < R; i++) {
-                    cur1 = m[i] ? m[i] : cur1;
-                    const int src = int((cur1 - 1) * 4);
-                    if constexpr (BITS == 32) {
-                        val[i] = uint32_t(__builtin_amdgcn_ds_bpermute(src, int(v)));
-                    } else {
-                        const uint32_t lo = uint32_t(__builtin_amdgcn_ds_bpermute(src, int(uint32_t(v))));
-                        const uint32_t hi = uint32_t(__builtin_amdgcn_ds_bpermute(src, int(uint32_t(v >> 32))));
-                        val[i] = uint64_t(lo) | (uint64_t(hi) << 32);
-                    }
-                    if constexpr (DS) {
-                        // plus stride * element index
-                        U dd;
-                        if constexpr (BITS == 32) {
-                            dd = uint32_t(__builtin_amdgcn_ds_bpermute(src, int(dstr)));
-                        } else {
-                            const uint32_t lo = uint32_t(__builtin_amdgcn_ds_bpermute(src, int(uint32_t(dstr))));
-                            const uint32_t hi =
-                                uint32_t(__builtin_amdgcn_ds_bpermute(src, int(uint32_t(dstr >> 32))));
-                            dd = uint64_t(lo) | (uint64_t(hi) << 32);
-                        }
-                        val[i] = U(val[i] + dd * U(uint32_t(W0 + int32_t(R * lane + i))));
-                    }
-                }
-                const int32_t p = W0 + int32_t(R * lane);
-                if (p >= ia && p + int32_t(R) <= ib) {
-                    u32x4 q;
-                    if constexpr (BITS == 32) q = u32x4{val[0], val[1], val[2], val[3]};
-                    else q = u32x4{uint32_t(val[0]), uint32_t(val[0] >> 32), uint32_t(val[1]), uint32_t(val[1] >> 32)};
-                    __builtin_nontemporal_store(q, gp(reinterpret_cast<u32x4 *>(out + p)));
-                } else {
-#pragma unroll
-                    for (int32_t i = 0; i < int32_t(R); i++)
-                        if (p + i >= ia && p + i < ib) out[p + i] = val[i];
-                }
-                wave_fence();
-            }
-        }
+        expand_runs<U, DS>(out, max(e0, cur.goff), min(e1, cur.next_off), act, start_abs, end_abs, v, dstr, slot);
         if (!more) return;
         cur = nxt;
+    }
+}
+
+// ============================= DeltaStride | [Delta | RLE | [BP, BP], BP]
+// Two Group-Parallel stages (Sec. 5's order-key scheme).  The first expands
+// the runs of D (values V, lengths L, both bit-packed per group) into the run
+// starts S, written to the scratch area: S is the running sum of D, so run j
+// of D is the progression P_j + V_j (p - a_j + 1) over its positions p, P_j
+// the sum before it (the group's base plus an exclusive wave scan of V L).
+// The second expands the DeltaStride runs (start S_k from the scratch area,
+// count C_k bit-packed per group, the chunk's stride d) into the output.
+
+// Field j (width w <= 32) of packed words at p, from two bounds-checked loads.
+ZF_DEV uint32_t field32_at(const uint8_t *p, uint64_t nwords, uint32_t j, uint32_t w) {
+    const uint64_t bit = uint64_t(j) * w, k = bit >> 5;
+    const uint32_t *words = reinterpret_cast<const uint32_t *>(p);
+    const uint32_t w0 = k < nwords ? words[k] : 0u, w1 = k + 1 < nwords ? words[k + 1] : 0u;
+    return field_of<uint32_t>(w0, w1, 0u, bit, w);
+}
+template <class U>
+ZF_DEV U fieldU_at(const uint8_t *p, uint64_t nwords, uint32_t j, uint32_t w) {
+    const uint64_t bit = uint64_t(j) * w, k = bit >> 5;
+    const uint32_t *words = reinterpret_cast<const uint32_t *>(p);
+    const uint32_t w0 = k < nwords ? words[k] : 0u, w1 = k + 1 < nwords ? words[k + 1] : 0u;
+    uint32_t w2 = 0;
+    if constexpr (sizeof(U) == 8) w2 = k + 2 < nwords ? words[k + 2] : 0u;
+    return field_of<U>(w0, w1, w2, bit, w);
+}
+
+// First stage: S[t.b, t.c) of a chunk (ck.n_elems = R starts, written at
+// out_tab[kScratchCol] + ck.out_off), starting with D's group t.a.
+template <class U>
+ZF_DEV void unit_tree_starts(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, uint32_t *slot) {
+    constexpr uint32_t BITS = sizeof(U) * 8;
+    const uint8_t *s = A.comp + ck.comp_off;
+    const uint32_t R = ck.n_elems, clen = ck.comp_len, lane = lane_id();
+    U *out = reinterpret_cast<U *>(A.out_tab[kScratchCol] + ck.out_off);
+    if (clen < 32) {
+        flag(A.err, ERR_CORRUPT);
+        return;
+    }
+    const uint32_t Q = ld32u(s + 8), ngA = ld32u(s + 12);
+    const uint32_t e0 = t.b, e1 = t.c;
+    if (ld32u(s) != R || Q == 0 || Q > R || ngA != (uint64_t(Q) + 63) / 64 || 32ull + 32ull * ngA > clen ||
+        e1 > R || e0 >= e1 || t.a >= ngA) {
+        flag(A.err, ERR_CORRUPT);
+        return;
+    }
+    for (uint32_t g = t.a;; g++) {
+        const uint8_t *rec = s + 32 + 32ull * g;
+        const uint32_t goff = ld32u(rec), poff = ld32u(rec + 4), widths = ld32u(rec + 8), lmin = ld32u(rec + 12);
+        const U base = U(ld64u(rec + 16)), vmin = U(ld64u(rec + 24));
+        const uint32_t next_off = g + 1 < ngA ? ld32u(rec + 32) : R;
+        const uint32_t cnt = min(64u, Q - 64 * g), wv = widths & 0xFFu, wl = (widths >> 8) & 0xFFu;
+        const uint64_t vw = (uint64_t(cnt) * min(wv, 64u) + 31) / 32, lw = (uint64_t(cnt) * min(wl, 64u) + 31) / 32;
+        if (wv > BITS || wl > 32 || (widths >> 16) != 0 || (poff & 3u) != 0 || poff + 4 * (vw + lw) > clen ||
+            next_off > R || (g == t.a && goff > e0)) {
+            flag(A.err, ERR_CORRUPT);
+            return;
+        }
+        const bool act = lane < cnt;
+        const U vj = act ? U(vmin + fieldU_at<U>(s + poff, vw, lane, wv)) : U(0);
+        const uint32_t r = act ? lmin + field32_at(s + poff + 4 * vw, lw, lane, wl) : 0u;
+        const uint64_t incl = scan_add64(r);
+        const uint64_t total = rl64(incl, cnt - 1);
+        if (any(act && r == 0) || uint64_t(goff) + total != next_off) {
+            flag(A.err, ERR_CORRUPT);
+            return;
+        }
+        const uint32_t end_abs = goff + uint32_t(incl), start_abs = end_abs - r;
+        // run j: value P_j + V_j at its first position, then + V_j per position
+        const U f = act ? U(vj * U(r)) : U(0);
+        const U F = scan_addT<U>(f);
+        const U first = U(base + (F - f) + vj);
+        const U c = U(first - vj * U(start_abs));
+        expand_runs<U, true>(out, max(e0, goff), min(e1, next_off), act, start_abs, end_abs, c, vj, slot);
+        if (next_off >= e1) return;
+        if (g + 1 >= ngA) {
+            flag(A.err, ERR_CORRUPT);
+            return;
+        }
+    }
+}
+
+// Second stage: output elements [t.b, t.c) of a chunk, starting with run
+// group t.a; the starts S are in the scratch area at ck.aux_off.
+template <class U>
+ZF_DEV void unit_tree(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, uint32_t *slot) {
+    const uint8_t *s = A.comp + ck.comp_off;
+    const uint32_t n = ck.n_elems, clen = ck.comp_len, lane = lane_id();
+    U *out = reinterpret_cast<U *>(A.out_tab[ck.col] + ck.out_off);
+    const U *S = reinterpret_cast<const U *>(A.out_tab[kScratchCol] + ck.aux_off);
+    if (clen < 32) {
+        flag(A.err, ERR_CORRUPT);
+        return;
+    }
+    const uint32_t R = ld32u(s), ngB = ld32u(s + 4), ngA = ld32u(s + 12), b_off = ld32u(s + 24);
+    const U d = U(ld64u(s + 16));
+    const uint32_t e0 = t.b, e1 = t.c;
+    if (R == 0 || R > n || ngB != (uint64_t(R) + 63) / 64 || b_off != 32ull + 32ull * ngA ||
+        uint64_t(b_off) + 16ull * ngB > clen || e1 > n || e0 >= e1 || t.a >= ngB) {
+        flag(A.err, ERR_CORRUPT);
+        return;
+    }
+    for (uint32_t g = t.a;; g++) {
+        const uint8_t *rec = s + b_off + 16ull * g;
+        const uint32_t goff = ld32u(rec), poff = ld32u(rec + 4), wc = ld32u(rec + 8), cmin = ld32u(rec + 12);
+        const uint32_t next_off = g + 1 < ngB ? ld32u(rec + 16) : n;
+        const uint32_t cnt = min(64u, R - 64 * g);
+        const uint64_t cw = (uint64_t(cnt) * min(wc, 64u) + 31) / 32;
+        if (wc > 32 || (poff & 3u) != 0 || poff + 4 * cw > clen || next_off > n || (g == t.a && goff > e0)) {
+            flag(A.err, ERR_CORRUPT);
+            return;
+        }
+        const bool act = lane < cnt;
+        const uint32_t r = act ? cmin + field32_at(s + poff, cw, lane, wc) : 0u;
+        const U st = act ? S[64ull * g + lane] : U(0);
+        const uint64_t incl = scan_add64(r);
+        const uint64_t total = rl64(incl, cnt - 1);
+        if (any(act && r == 0) || uint64_t(goff) + total != next_off) {
+            flag(A.err, ERR_CORRUPT);
+            return;
+        }
+        const uint32_t end_abs = goff + uint32_t(incl), start_abs = end_abs - r;
+        const U c = U(st - d * U(start_abs));
+        expand_runs<U, true>(out, max(e0, goff), min(e1, next_off), act, start_abs, end_abs, c, d, slot);
+        if (next_off >= e1) return;
+        if (g + 1 >= ngB) {
+            flag(A.err, ERR_CORRUPT);
+            return;
+        }
     }
 }
 
@@ -1574,11 +1718,17 @@ ZF_DEV void run_unit(const LaunchArgs &A, uint32_t kind, uint32_t u, uint32_t *l
     case K_DICT128: unit_fp<16, true, UNR>(A, t, ck); break;
     case K_RLE32:
         if (ck.codec == C_DSTRIDE_BP) unit_rle<uint32_t, true>(A, t, ck, lz_row);
+        else if (ck.codec == C_DSTREE_STARTS) unit_tree_starts<uint32_t>(A, t, ck, lz_row);
         else unit_rle<uint32_t, false>(A, t, ck, lz_row);
         break;
     case K_RLE64:
         if (ck.codec == C_DSTRIDE_BP) unit_rle<uint64_t, true>(A, t, ck, lz_row);
+        else if (ck.codec == C_DSTREE_STARTS) unit_tree_starts<uint64_t>(A, t, ck, lz_row);
         else unit_rle<uint64_t, false>(A, t, ck, lz_row);
+        break;
+    case K_TREE:
+        if (ck.dtype == D_I32) unit_tree<uint32_t>(A, t, ck, lz_row);
+        else unit_tree<uint64_t>(A, t, ck, lz_row);
         break;
     case K_LZ: unit_lz<16>(A, ck, lz_row); break;
     case K_SDICT: unit_sdict(A, t, ck, lz_row); break;
@@ -1624,11 +1774,17 @@ __global__ __launch_bounds__(1024) void k_decode_kind(LaunchArgs A) {
     } else if constexpr (KIND == K_RLE32) {
         __shared__ uint32_t rle_slots[16][256];
         if (ck.codec == C_DSTRIDE_BP) unit_rle<uint32_t, true>(A, t, ck, rle_slots[threadIdx.x / 64]);
+        else if (ck.codec == C_DSTREE_STARTS) unit_tree_starts<uint32_t>(A, t, ck, rle_slots[threadIdx.x / 64]);
         else unit_rle<uint32_t, false>(A, t, ck, rle_slots[threadIdx.x / 64]);
     } else if constexpr (KIND == K_RLE64) {
         __shared__ uint32_t rle_slots[16][256];
         if (ck.codec == C_DSTRIDE_BP) unit_rle<uint64_t, true>(A, t, ck, rle_slots[threadIdx.x / 64]);
+        else if (ck.codec == C_DSTREE_STARTS) unit_tree_starts<uint64_t>(A, t, ck, rle_slots[threadIdx.x / 64]);
         else unit_rle<uint64_t, false>(A, t, ck, rle_slots[threadIdx.x / 64]);
+    } else if constexpr (KIND == K_TREE) {
+        __shared__ uint32_t rle_slots[16][256];
+        if (ck.dtype == D_I32) unit_tree<uint32_t>(A, t, ck, rle_slots[threadIdx.x / 64]);
+        else unit_tree<uint64_t>(A, t, ck, rle_slots[threadIdx.x / 64]);
     }
 }
 
@@ -1652,7 +1808,7 @@ void launch_ans(const LaunchArgs &A, uint32_t waves, hipStream_t st);
 
 // Host launchers, one per kind, each defined in its kind's translation unit.
 #define ZF_KIND_LAUNCHERS(X)                                                                       \
-    X(K_RLE64, launch_rle64) X(K_RLE32, launch_rle32)                            \
+    X(K_RLE64, launch_rle64) X(K_RLE32, launch_rle32) X(K_TREE, launch_tree)                       \
     X(K_DICT128, launch_dict128) X(K_DICT64, launch_dict64) X(K_DICT32, launch_dict32)              \
     X(K_FOR64, launch_for64) X(K_FOR32, launch_for32) X(K_F2I, launch_f2i) X(K_PLAIN, launch_plain)
 #define ZF_DECLARE_LAUNCHER(KIND, NAME) void NAME(const LaunchArgs &A, uint32_t waves, hipStream_t st);

@@ -10,6 +10,30 @@
 
 namespace zf {
 
+// Output-balanced Group-Parallel units over n elements whose ng groups start
+// at gof(g): about `unit` outputs each, cut at a group boundary when one is
+// near, so a unit rarely rescans a group.  Tile {chunk, first group, first
+// element, end element}.
+template <class GroupOffset>
+static void gp_tiles(std::vector<Tile> &T, uint32_t idx, uint32_t ng, uint32_t n, uint32_t unit,
+                     GroupOffset gof) {
+    uint32_t e = 0, g = 0;
+    while (e < n) {
+        while (g + 1 < ng && gof(g + 1) <= e) g++;
+        const uint64_t target = uint64_t(e) + unit;
+        uint32_t e_end;
+        if (target >= n) {
+            e_end = n;
+        } else {
+            uint32_t gb = g + 1;
+            while (gb < ng && gof(gb) < target) gb++;
+            e_end = (gb < ng && gof(gb) <= target + unit) ? gof(gb) : uint32_t(target);
+        }
+        T.push_back({idx, g, e, e_end});
+        e = e_end;
+    }
+}
+
 static void add_chunk(WorkTables &w, const zf_column &col, uint32_t ci, uint32_t col_idx,
                       uint64_t comp_off, uint64_t dict_off, const TileShape &ts) {
     const ChunkInfo &c = col.view.chunks[ci];
@@ -55,6 +79,25 @@ static void add_chunk(WorkTables &w, const zf_column &col, uint32_t ci, uint32_t
             w.scratch_bytes = align_up(d.aux_off + ncb, 256);
         }
     }
+    if (c.codec == C_DSTREE) {
+        // first stage: the run starts S (R values) into the scratch area, as
+        // units of the RLE kind of the column's width; the second stage
+        // (kind TREE, launched after the RLE kinds) reads them there
+        const uint8_t *s = col.buf.p + c.comp_off;
+        const uint32_t R = rd32(s), ngA = rd32(s + 12);
+        const uint32_t es = col.view.dtype == D_I32 ? 4 : 8;
+        const Kind ks = col.view.dtype == D_I32 ? K_RLE32 : K_RLE64;
+        d.aux_off = w.scratch_bytes;
+        ChunkDesc a = d;
+        a.out_off = d.aux_off;
+        a.n_elems = R;
+        a.col = uint16_t(kScratchCol);
+        a.codec = C_DSTREE_STARTS;
+        const uint32_t aidx = uint32_t(w.chunks.size());
+        w.chunks.push_back(a);
+        gp_tiles(w.tiles[ks], aidx, ngA, R, ts.unit[ks], [&](uint32_t g) { return rd32(s + 32 + 32ull * g); });
+        w.scratch_bytes = align_up(d.aux_off + uint64_t(R) * es, 256);
+    }
     const uint32_t idx = uint32_t(w.chunks.size());
     w.chunks.push_back(d);
     const Kind k = kind_of(c.codec, col.view.dtype);
@@ -77,26 +120,14 @@ static void add_chunk(WorkTables &w, const zf_column &col, uint32_t ci, uint32_t
     }
     case K_RLE32:
     case K_RLE64: {
-        // Output-balanced units: about gp_elems outputs each, cut at a group
-        // boundary when one is near, so a unit rarely rescans a group.
         const uint8_t *s = col.buf.p + c.comp_off;
-        const uint32_t ng = rd32(s + 4), n = c.n_elems;
-        auto gof = [&](uint32_t g) { return rd32(s + 16 + 32ull * g); };
-        uint32_t e = 0, g = 0;
-        while (e < n) {
-            while (g + 1 < ng && gof(g + 1) <= e) g++;
-            const uint64_t target = uint64_t(e) + unit;
-            uint32_t e_end;
-            if (target >= n) {
-                e_end = n;
-            } else {
-                uint32_t gb = g + 1;
-                while (gb < ng && gof(gb) < target) gb++;
-                e_end = (gb < ng && gof(gb) <= target + unit) ? gof(gb) : uint32_t(target);
-            }
-            T.push_back({idx, g, e, e_end});
-            e = e_end;
-        }
+        gp_tiles(T, idx, rd32(s + 4), c.n_elems, unit, [&](uint32_t g) { return rd32(s + 16 + 32ull * g); });
+        break;
+    }
+    case K_TREE: {
+        const uint8_t *s = col.buf.p + c.comp_off;
+        const uint32_t b_off = rd32(s + 24);
+        gp_tiles(T, idx, rd32(s + 4), c.n_elems, unit, [&](uint32_t g) { return rd32(s + b_off + 16ull * g); });
         break;
     }
     case K_SDICT: {
@@ -300,8 +331,8 @@ void build_plan(zf_plan_t *P, const zf_column *const *cols, uint32_t n_cols, int
     P->scratch_bytes = image.scratch_bytes;
     for (auto &b : P->batches) P->scratch_bytes = std::max(P->scratch_bytes, b.w.scratch_bytes);
     ZF_REQUIRE(!(P->scratch_bytes && P->persistent_waves), ZF_E_UNSUPPORTED,
-               "String-dictionary | BP | ANS chunks decode in two ordered launches; the persistent "
-               "kernel does not order its units");
+               "two-stage chunks (String-dictionary | BP | ANS, the DeltaStride tree) decode in two "
+               "ordered launches; the persistent kernel does not order its units");
     if (P->scratch_bytes) ZF_HIP(hipMalloc(&P->d_scratch, P->scratch_bytes));
 
     auto fill = [&](LaunchArgs &A) {

@@ -55,7 +55,7 @@ struct zf_plan {
     // launch configuration
     uint32_t persistent_waves = 0;  // 0: per-kind launches
     uint32_t lz_blk = 16;         // LZ77 bytes per block
-    uint32_t waves_per_block[zf::K_COUNT] = {4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4};
+    uint32_t waves_per_block[zf::K_COUNT] = {4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4};
     uint32_t cu_count = 0;
 
     // device memory

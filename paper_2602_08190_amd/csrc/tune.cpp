@@ -77,7 +77,7 @@ struct Json {
 };
 
 const char *kKindNames[K_COUNT] = {"LZ77", "ANS", "RLE64", "RLE32", "SDICT", "DICT128", "DICT64",
-                                   "DICT32", "FOR64", "FOR32", "F2I", "PLAIN"};
+                                   "DICT32", "FOR64", "FOR32", "F2I", "PLAIN", "TREE"};
 
 std::string default_cache_path() {
     Dl_info info;
@@ -95,12 +95,12 @@ const char *kind_name(uint32_t k) { return k < K_COUNT ? kKindNames[k] : "?"; }
 TileShape default_tiles() {
     TileShape t;
     for (uint32_t k = 0; k < K_COUNT; k++) {
-        t.unit[k] = (k == K_PLAIN) ? 65536u : (k == K_RLE32 || k == K_RLE64) ? 4096u : (k == K_LZ) ? 16u
-                    : (k == K_SDICT) ? 4096u : 2u;
+        t.unit[k] = (k == K_PLAIN) ? 65536u : (k == K_RLE32 || k == K_RLE64 || k == K_TREE) ? 4096u
+                    : (k == K_LZ) ? 16u : (k == K_SDICT) ? 4096u : 2u;
         t.wpb[k] = 4;
         // rates for ordering batches when the cache has no measurement
         t.rate_gbps[k] = k == K_LZ ? 600 : k == K_ANS ? 1200 : k == K_SDICT ? 800
-                         : (k == K_RLE32 || k == K_RLE64) ? 3000 : 4000;
+                         : (k == K_RLE32 || k == K_RLE64 || k == K_TREE) ? 3000 : 4000;
     }
     t.wpcu = 16;
     return t;
@@ -173,6 +173,7 @@ TileShape resolve_tiles(const zf_plan_opts &o) {
     // sane floors: GP units cover at least one window, PLAIN units one vector
     t.unit[K_RLE32] = std::max(64u, t.unit[K_RLE32]);
     t.unit[K_RLE64] = std::max(64u, t.unit[K_RLE64]);
+    t.unit[K_TREE] = std::max(64u, t.unit[K_TREE]);
     t.unit[K_PLAIN] = std::max(1024u, t.unit[K_PLAIN]);
     t.unit[K_SDICT] = std::max(256u, t.unit[K_SDICT]);
     // LZ77: output bytes per block, 4, 8 or 16
@@ -184,7 +185,8 @@ uint32_t scheduled_unit(uint32_t kind, uint32_t sched, uint32_t tuned) {
     if (sched == 0 || sched > 4) return tuned;
     switch (kind) {
     case K_RLE32:
-    case K_RLE64: return 1024u << (sched - 1);        // 1024 .. 8192 elements
+    case K_RLE64:
+    case K_TREE: return 1024u << (sched - 1);         // 1024 .. 8192 elements
     case K_PLAIN: return 16384u << (2 * (sched - 1)); // 16 KiB .. 1 MiB
     case K_LZ:
     case K_SDICT: return tuned;

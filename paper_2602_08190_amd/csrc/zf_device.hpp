@@ -24,7 +24,9 @@ constexpr uint32_t kSdMaxToken = 64;
 // Codec / dtype codes, as in zf.h.
 enum : uint8_t { C_PLAIN = 1, C_FOR_BP = 2, C_DICT_BP = 3, C_DELTA_BP = 4, C_RLE_DELTA_BP = 5, C_LZ77 = 6,
                  C_F2I_BP = 7, C_ANS = 8, C_DSTRIDE_BP = 9, C_SDICT_BP = 10, C_SDICT_ANS = 11,
-                 C_SDICT_COL = 12, C_SDICT_COL_ANS = 13 };
+                 C_SDICT_COL = 12, C_SDICT_COL_ANS = 13, C_DSTREE = 14,
+                 // internal: the first decode stage of a C_DSTREE chunk (its run starts)
+                 C_DSTREE_STARTS = 200 };
 enum : uint8_t { D_I32 = 1, D_I64 = 2, D_BYTES = 3, D_FIXED16 = 4, D_F64 = 5 };
 
 // Kernel kinds: one device routine per (codec class, value width).  The
@@ -33,8 +35,8 @@ enum : uint8_t { D_I32 = 1, D_I64 = 2, D_BYTES = 3, D_FIXED16 = 4, D_F64 = 5 };
 enum Kind : uint32_t {
     K_LZ = 0,
     K_ANS,     // range ANS, 64 interleaved coders per chunk
-    K_RLE64,   // RLE_DELTA_BP, DELTA_BP and DSTRIDE_BP, int64
-    K_RLE32,   // RLE_DELTA_BP, DELTA_BP and DSTRIDE_BP, int32
+    K_RLE64,   // RLE_DELTA_BP, DELTA_BP, DSTRIDE_BP and the DSTREE starts, int64
+    K_RLE32,   // RLE_DELTA_BP, DELTA_BP, DSTRIDE_BP and the DSTREE starts, int32
     K_SDICT,   // String-dictionary, bytes
     K_DICT128,
     K_DICT64,
@@ -43,6 +45,7 @@ enum Kind : uint32_t {
     K_FOR32,
     K_F2I,     // Float2Int + bit-packing, float64
     K_PLAIN,
+    K_TREE,    // DSTREE second stage (after the RLE kinds wrote its run starts)
     K_COUNT
 };
 

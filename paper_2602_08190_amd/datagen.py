@@ -275,6 +275,25 @@ def returnflag_column(n, p_a, p_n, seed):
     return out
 
 
+def orderkey_column(n, seed, drop=0.01, block=8, spacing=32, dtype=np.int32, start=1):
+    """Sparse order keys: the first `block` keys of every `spacing` (the key
+    layout of the TPC-H orders table), each key then removed with
+    probability `drop` (deleted orders), so some blocks are shorter and some
+    gaps wider; n keys are returned."""
+    g = rng(seed)
+    m = int(n / (1.0 - drop)) + block + 64
+    i = np.arange(m, dtype=np.int64)
+    keys = start + spacing * (i // block) + i % block
+    keep = g.random(m) >= drop
+    out = keys[keep][:n]
+    while out.size < n:  # rare: more drops than expected
+        m *= 2
+        i = np.arange(m, dtype=np.int64)
+        keys = start + spacing * (i // block) + i % block
+        out = keys[g.random(m) >= drop][:n]
+    return out.astype(dtype)
+
+
 def key_column(n, seed, mean_run=8, max_jump=64, dtype=np.int32, start=1):
     """Nearly increasing primary keys: blocks of consecutive keys with
     geometric lengths (mean `mean_run`), each block starting a uniform

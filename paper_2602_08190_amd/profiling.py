@@ -17,7 +17,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 KIND_OF_ID = ["LZ77", "ANS", "RLE64", "RLE32", "SDICT", "DICT128", "DICT64", "DICT32", "FOR64", "FOR32", "F2I",
-              "PLAIN"]
+              "PLAIN", "TREE"]
 
 
 def kernel_sha():

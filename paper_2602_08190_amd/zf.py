@@ -17,11 +17,11 @@ LIB_PATH = os.path.join(HERE, "libzf.so")
 I32, I64, BYTES, FIXED16, F64 = 1, 2, 3, 4, 5
 AUTO, PLAIN, FOR_BP, DICT_BP, DELTA_BP, RLE_DELTA_BP, LZ77, F2I_BP, ANS, DSTRIDE_BP, SDICT_BP, SDICT_ANS = \
     0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11
-SDICT_COL, SDICT_COL_ANS = 12, 13
+SDICT_COL, SDICT_COL_ANS, DSTREE = 12, 13, 14
 CODEC_NAMES = {PLAIN: "PLAIN", FOR_BP: "FOR_BP", DICT_BP: "DICT_BP", DELTA_BP: "DELTA_BP",
                RLE_DELTA_BP: "RLE_DELTA_BP", LZ77: "LZ77", F2I_BP: "F2I_BP", ANS: "ANS",
                DSTRIDE_BP: "DSTRIDE_BP", SDICT_BP: "SDICT_BP", SDICT_ANS: "SDICT_ANS",
-               SDICT_COL: "SDICT_COL", SDICT_COL_ANS: "SDICT_COL_ANS"}
+               SDICT_COL: "SDICT_COL", SDICT_COL_ANS: "SDICT_COL_ANS", DSTREE: "DSTREE"}
 ELEM_SIZE = {I32: 4, I64: 8, BYTES: 1, FIXED16: 16, F64: 8}
 OK, E_INVALID, E_UNSUPPORTED, E_CORRUPT, E_NOMEM, E_HIP, E_TOO_SMALL, E_STATE = range(8)
 
@@ -43,8 +43,9 @@ class EncodeOpts(ctypes.Structure):
 
 # kernel kinds (zf_kind), in enum order
 KINDS = ["LZ77", "ANS", "RLE64", "RLE32", "SDICT", "DICT128", "DICT64", "DICT32", "FOR64", "FOR32", "F2I",
-         "PLAIN"]
-KIND_GROUPS = {"FP": ["FOR32", "FOR64", "DICT32", "DICT64", "DICT128", "F2I"], "GP": ["RLE32", "RLE64", "SDICT"],
+         "PLAIN", "TREE"]
+KIND_GROUPS = {"FP": ["FOR32", "FOR64", "DICT32", "DICT64", "DICT128", "F2I"],
+               "GP": ["RLE32", "RLE64", "SDICT", "TREE"],
                "NP": ["LZ77", "ANS"]}
 
 
@@ -400,6 +401,8 @@ def kind_of_column(col):
         return "ANS"
     if codec in (SDICT_BP, SDICT_ANS, SDICT_COL, SDICT_COL_ANS):
         return "SDICT"
+    if codec == DSTREE:
+        return "TREE"
     if codec in (DELTA_BP, RLE_DELTA_BP, DSTRIDE_BP):
         return "RLE32" if dt == I32 else "RLE64"
     if codec == DICT_BP:

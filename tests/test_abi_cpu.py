@@ -145,6 +145,51 @@ def test_dstride_host_validation():
             zf.Column.from_bytes(t, pinned=False)
 
 
+def test_encoder_byte_identical_dstree():
+    """DeltaStride | [Delta | RLE | [BP, BP], BP]: sparse order keys with and
+    without deletions, nearly increasing keys, random values, extremes, a
+    descending progression, a progression across the wrap, uneven and tiny
+    chunks."""
+    r = g.rng(31)
+    cases = []
+    for dt in (np.int32, np.int64):
+        info = np.iinfo(dt)
+        cases += [(g.orderkey_column(30000, 1, dtype=dt), [1, 64, 4096, 30000 - 4161]),
+                  (g.orderkey_column(20000, 2, drop=0.0, dtype=dt), [20000]),
+                  (g.key_column(9000, 5, dtype=dt), [4500, 4500]),
+                  (r.integers(info.min, info.max, size=5000, dtype=dt, endpoint=True), [2500, 2500]),
+                  (np.array([info.min, info.max, 0, -1, info.min, info.min, 5] * 300, dt), [2100]),
+                  (np.arange(3000, dtype=dt)[::-1] * 3, [3000]),
+                  ((np.arange(7000, dtype=np.int64) * 977 + int(info.max) - 3000).astype(
+                      np.uint64 if dt == np.int64 else np.int64).astype(dt), [3000, 4000])]
+    for x, ce in cases:
+        ours, ref = same_streams(x, zf.DSTREE, ce)
+        assert ours.tobytes() == ref.tobytes(), (x.dtype, ce)
+        assert np.array_equal(zo.decode(ours), x)
+
+
+def test_dstree_host_validation():
+    x = g.orderkey_column(20000, 3, drop=0.05)
+    b = zo.encode(x, zo.DSTREE).copy()
+    c = zo.chunks(b)[0]
+    s = c["comp_off"]
+    b_off = int(np.frombuffer(b[s + 24:s + 28].tobytes(), np.uint32)[0])
+    ngA = int(np.frombuffer(b[s + 12:s + 16].tobytes(), np.uint32)[0])
+    assert ngA >= 2
+    for off, val in ((0, 0),                  # no runs
+                     (12, ngA + 1),           # start groups not ceil(Q / 64)
+                     (24, b_off + 16),        # run records offset
+                     (32 + 8, 33),            # V width above 32
+                     (32 + 4, 2),             # payload offset not 4-aligned
+                     (32 + 32, 0),            # second start group's output offset 0
+                     (b_off + 8, 33),         # C width above 32
+                     (b_off + 16, 0)):        # second run group's output offset 0
+        t = b.copy()
+        t[s + off:s + off + 4] = np.frombuffer(np.uint32(val).tobytes(), np.uint8)
+        with pytest.raises(zf.ZfError):
+            zf.Column.from_bytes(t, pinned=False)
+
+
 def test_encoder_byte_identical_sdict():
     """String-dictionary: generated text in uneven chunks, random bytes, long
     runs without separators, separators only, tiny chunks."""

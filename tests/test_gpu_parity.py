@@ -186,6 +186,55 @@ def test_dstride_oracle_streams_and_auto():
     check([col, auto], decode_image([col, auto]), [x, y])
 
 
+def dstree_columns():
+    r = g.rng(53)
+    xs = [g.orderkey_column(300000, 1), g.orderkey_column(100000, 2, drop=0.0, dtype=np.int64),
+          g.orderkey_column(70000, 3, drop=0.2), g.key_column(50000, 4, dtype=np.int64),
+          r.integers(-2**31, 2**31, size=9000).astype(np.int32),
+          np.array([-2**63, 2**63 - 1, 0, -1, -2**63, -2**63, 5] * 500, np.int64),
+          (np.arange(40000, dtype=np.int32)[::-1] * 3).copy(),
+          (np.arange(30000, dtype=np.uint64) * np.uint64(977) + np.uint64(2**63 - 3000)).astype(np.int64),
+          np.array([7], np.int32)]
+    cols = []
+    for x in xs:
+        n = len(x)
+        ce = [1, 4095, 16384, n - 20480] if n > 20480 else ([n] if n < 3 else [1, n // 3, n - 1 - n // 3])
+        cols.append(zf.Column.compress(x, zf.DSTREE, chunk_elems=ce))
+    # an oracle-written stream, and columns sharing the RLE kernels
+    cols.append(zf.Column.from_bytes(zo.encode(xs[0], zo.DSTREE, [100000, 200000])))
+    xs.append(xs[0])
+    y = g.sorted_runs_column(100000, 8, 3)
+    cols += [zf.Column.compress(y, zf.RLE_DELTA_BP), zf.Column.compress(xs[3], zf.DSTRIDE_BP)]
+    xs += [y, xs[3]]
+    return cols, xs
+
+
+@pytest.mark.parametrize("mode", ["graphs", "plain", "staged", "tiles256", "persistent_rejected"])
+def test_dstree_two_stage_decode(mode):
+    """DeltaStride | [Delta | RLE | [BP, BP], BP]: the run starts are expanded
+    into the scratch area by the RLE kinds' launch, the output by the TREE
+    launch after it; sparse order keys with and without deletions, nearly
+    increasing keys, random values, extremes, descending keys, a progression
+    across the wrap, a one-value chunk; beside RLE and DeltaStride columns;
+    staged transfers with small slots run several batches through the one
+    scratch area."""
+    log("dstree", mode)
+    cols, xs = dstree_columns()
+    if mode == "persistent_rejected":
+        with pytest.raises(zf.ZfError) as e:
+            zf.Plan(cols, device=0, persistent=True)
+        assert e.value.status == zf.E_UNSUPPORTED
+        return
+    if mode == "staged":
+        outs, _ = decode_staged(cols, slot_bytes=1 << 18)
+        check(cols, outs, xs)
+        return
+    if mode == "tiles256":
+        check(cols, decode_image(cols, tiles={"GP": dict(unit=256, waves_per_block=8)}), xs)
+        return
+    check(cols, decode_image(cols, use_graphs=(mode == "graphs")), xs)
+
+
 @pytest.mark.parametrize("sd_bytes", [256, 4096, 65536])
 def test_sdict_text_bytes_and_tiles(sd_bytes):
     """String-dictionary: generated text (product and oracle streams), random
@@ -635,6 +684,18 @@ def test_device_detects_corrupt_streams():
     c = zo.chunks(b)[0]
     b[c["comp_off"] + 784 + 10] ^= 0x5A
     _expect_corrupt([zf.Column.from_bytes(b)])
+    # DeltaStride tree: start lengths or run counts that no longer add up to
+    # the next group's offset (the host checks the records, not the sums)
+    x = g.orderkey_column(30000, 6, drop=0.05)
+    base = zo.encode(x, zo.DSTREE).copy()
+    c = zo.chunks(base)[0]
+    b_off = int(np.frombuffer(base[c["comp_off"] + 24:c["comp_off"] + 28].tobytes(), np.uint32)[0])
+    for off in (32 + 12, b_off + 12):  # lmin of the first start group, cmin of the first run group
+        b = base.copy()
+        p = c["comp_off"] + off
+        b[p:p + 4] = np.frombuffer(np.uint32(int(np.frombuffer(b[p:p + 4].tobytes(), np.uint32)[0]) + 1).tobytes(),
+                                   np.uint8)
+        _expect_corrupt([zf.Column.from_bytes(b)])
     # DICT: a code beyond the dictionary
     y = g.fixed16_column(4096, 4, 1)
     b = zo.encode(y, zo.DICT_BP).copy()
