@@ -204,17 +204,25 @@ def host_description(threads):
 
 def gpu_description(torch):
     import subprocess
-    d = {"name": torch.cuda.get_device_name(0)}
+    props = torch.cuda.get_device_properties(0)
+    d = {"name": torch.cuda.get_device_name(0) or getattr(props, "gcnArchName", ""),
+         "arch": getattr(props, "gcnArchName", ""), "compute_units": props.multi_processor_count}
     try:
         d["rocm"] = open("/opt/rocm/.info/version").read().strip()
     except OSError:
         pass
     d["torch"] = torch.__version__
     try:
+        # the tool may print notices around its JSON; the text form is the fallback
         r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True, timeout=20)
-        clocks = json.loads(r.stdout)
-        card = next(iter(clocks.values()))
-        d["clocks"] = {k: v for k, v in card.items() if "clock" in k.lower()}
+        out = r.stdout
+        try:
+            clocks = json.loads(out[out.index("{"):out.rindex("}") + 1])
+            card = next(iter(clocks.values()))
+            d["clocks"] = {k: v for k, v in card.items() if "clock" in k.lower()}
+        except ValueError:
+            r = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True, timeout=20)
+            d["clocks"] = [ln.strip() for ln in r.stdout.splitlines() if "clk" in ln.lower()][:8]
     except Exception as e:  # the description is informational
         d["clocks"] = f"unavailable ({type(e).__name__})"
     return d
@@ -352,6 +360,10 @@ def main():
                     help="skip the CPU baseline (the oracle on all host threads, whose outputs the whole "
                          "GPU output is compared with, and on one core)")
     ap.add_argument("--persistent", type=int, default=0)
+    ap.add_argument("--waves-per-cu", type=int, default=0,
+                    help="persistent kernel: waves in flight per CU (0: the tune cache's)")
+    ap.add_argument("--untuned", action="store_true",
+                    help="plan with the built-in default tile of every kind instead of the tune cache")
     ap.add_argument("--e2e-reps", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -381,7 +393,8 @@ def main():
         f"{comp / 2**30:.2f} GiB (ratio {plain / comp:.2f}x)")
     manifest = sha256_manifest(xs, names, threads)
 
-    plan = zf.Plan(cols, device=0, persistent=bool(args.persistent))
+    plan = zf.Plan(cols, device=0, persistent=bool(args.persistent), waves_per_cu=args.waves_per_cu,
+                   **({"tune_cache": os.devnull} if args.untuned else {}))
     img = zf.upload_image(plan, cols)
     outs = zf.empty_outputs(cols)
     stream = torch.cuda.current_stream()
@@ -473,6 +486,29 @@ def main():
                 kinds[key][f"{k}_ms_median"] = round(pct(per[k], 50), 4)
     dom = max(kinds, key=lambda k: kinds[k]["ms_median"])
 
+    # the same decode with the persistent kernel (same image, same outputs)
+    pers = None
+    if not args.persistent:
+        plan_p = zf.Plan(cols, device=0, persistent=True, waves_per_cu=args.waves_per_cu,
+                         **({"tune_cache": os.devnull} if args.untuned else {}))
+        assert all(plan_p.image_offset(i) == plan.image_offset(i) for i in range(len(cols)))
+        for _ in range(max(1, args.warmup)):
+            plan_p.decompress_async(img, img.numel(), outs)
+        torch.cuda.synchronize()
+        pe = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        pe[0].record(stream)
+        for k in range(args.steps):
+            plan_p.decompress_async(img, img.numel(), outs)
+            pe[k + 1].record(stream)
+        torch.cuda.synchronize()
+        plan_p.sync()
+        pms = [pe[k].elapsed_time(pe[k + 1]) for k in range(args.steps)]
+        pers = {"ms_per_step": round(pe[0].elapsed_time(pe[-1]) / args.steps, 4),
+                "ms_median": round(pct(pms, 50), 4),
+                "vs_per_kind": round((pe[0].elapsed_time(pe[-1]) / args.steps) / ms, 3)}
+        plan_p.free()
+        log(f"persistent kernel: {pers['ms_per_step']:.3f} ms/step ({pers['vs_per_kind']:.2f}x the per-kind step)")
+
     result = {
         "metric": METRIC, "value": round(hbm_gbps, 2), "unit": "GB/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
@@ -482,7 +518,8 @@ def main():
         "config": {"workload": desc, "plain_bytes": plain, "comp_bytes": comp,
                    "ratio": round(plain / comp, 3),
                    "chunks": sum(c.n_chunks for c in cols),
-                   "launch": "persistent" if args.persistent else "per-kind"},
+                   "launch": "persistent" if args.persistent else "per-kind",
+                   "tiles": "built-in defaults" if args.untuned else "tune cache"},
         "value_is": "decode HBM GB/s = (compressed + plain bytes) / step time, inputs in HBM",
         "decode_plain_GBps": round(plain_gbps, 2),
         "step_ms": {"median": round(pct(step_ms, 50), 4), "p10": round(pct(step_ms, 10), 4),
@@ -500,6 +537,8 @@ def main():
                      "timing": f"median of {prof_steps} steps, HIP events around the launch inside the step"},
         "kernels": kinds,
     }
+    if pers is not None:
+        result["persistent_launch"] = pers
     if verify is not None:
         result["verify"] = verify
 

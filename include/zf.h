@@ -122,7 +122,7 @@ typedef enum {
  *                   at b_off; payloads after them (V fields, then L fields
  *                   from the next word; C fields).  The starts are decoded
  *                   into the plan's scratch area by one launch and expanded
- *                   by the next (no persistent kernel).  I32, I64.
+ *                   by the next.  I32, I64.
  *  ZF_SDICT_BP      [GP] String-dictionary (Sec. 2.1, Sec. 5): tokens end
  *                   after ' ' or '.' (at most 64 bytes; the chunk's last may
  *                   end without one); distinct tokens in order of first
@@ -139,8 +139,9 @@ typedef enum {
  *                   indices (4 ceil(n_tokens w / 32) bytes) replaced by the
  *                   ZF_ANS stream of those bytes (nothing when w = 0).  The
  *                   indices are ANS-decoded into the plan's scratch area by
- *                   one launch and expanded by the next, so a plan holding
- *                   such chunks cannot use the persistent kernel.  BYTES.
+ *                   one launch and expanded by the next (with the persistent
+ *                   kernel: one persistent launch for the kinds up to RLE,
+ *                   then one for the rest).  BYTES.
  *  ZF_SDICT_COL     [GP] String-dictionary over one dictionary for the whole
  *                   column (Sec. 5: one word dictionary for the comment
  *                   column; Sec. 2.1: it holds the data's frequent byte
@@ -273,7 +274,7 @@ typedef enum {
 /* Tile shape of one kind, the device geometry of Sec. 4 (<L,S,C>): `unit`
  * is the work of one wavefront (FP: 2048-value blocks; GP: output elements;
  * PLAIN: bytes; LZ77: output bytes per block of the copy step, 4, 8 or 16,
- * one chunk per wavefront; the persistent kernel always uses 16; SDICT:
+ * one chunk per wavefront; the persistent kernel always uses 4; SDICT:
  * output bytes, in whole groups of 64 tokens),
  * `waves_per_block`
  * the wavefronts per workgroup (S/64).  A lane always owns 16 output bytes
@@ -287,7 +288,9 @@ typedef struct {
     uint64_t slot_bytes;     /* staging slot size for transfers (default 256 MiB) */
     int32_t n_slots;         /* staging slots, >= 1 (default 2: double buffering)   */
     int32_t use_graphs;      /* 1: one hipGraph per batch (default); 0: plain launches */
-    int32_t persistent;      /* 1: one persistent multi-codec kernel per batch;
+    int32_t persistent;      /* 1: a persistent multi-codec kernel per batch (two
+                                ordered launches when two-stage chunks are present),
+                                its waves pulling units from one queue per XCD;
                                 0: one launch per kernel kind (default)             */
     int32_t order;           /* 0: Johnson order (default); 1: column order          */
     double pcie_gbps;        /* transfer-time estimate for ordering (0: 55)          */

@@ -4,24 +4,45 @@
 
 namespace zf {
 
-// Persistent: every wave pulls units from one queue until it is empty.
-// Units are ordered by kind, the costliest kinds first.
-__global__ __launch_bounds__(256) void k_decode_persistent(LaunchArgs A) {
+// Persistent: waves pull units of [ub, ue) from eight queues, one per XCD,
+// until all are empty.  Units are ordered by kind, the costliest kinds first;
+// the range is dealt to the queues in blocks of kPersistBlock consecutive
+// units, round robin, so every XCD works through the kinds in that order and
+// neighbouring tiles of a chunk stay on one XCD (and its L2).  A workgroup
+// starts on the queue of its own XCD (workgroups are dealt to the XCDs in
+// turn) and moves on to the others' when it is empty.  ctr: the eight
+// counters, 32 dwords apart.
+constexpr uint32_t kPersistBlock = 16;
+// Its register budget is the union of every kind's routine (about 140 VGPRs
+// unconstrained, 2 to 3 waves per SIMD); it is held to 128 (4 waves per SIMD,
+// a few spills), the fastest of 2, 4 and 6 waves per SIMD on the fact table.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_decode_persistent(
+    LaunchArgs A, uint32_t ub, uint32_t ue, uint32_t *ctr) {
     __shared__ __attribute__((aligned(16))) uint32_t lz_rows[4][kAnsLdsWords > kSdBufWords ? kAnsLdsWords : kSdBufWords];
     uint32_t *mine = lz_rows[threadIdx.x / 64];
-    const uint32_t n = A.kind_begin[K_COUNT];
-    for (;;) {
-        uint32_t u = 0;
-        if (lane_id() == 0) u = atomicAdd(A.counter, 1u);
-        u = first32(u);
-        if (u >= n) return;
-        uint32_t kind = 0;
-        while (kind + 1 < K_COUNT && u >= A.kind_begin[kind + 1]) kind++;
-        run_unit<0>(A, kind, u, mine);
+    const uint32_t n = ue - ub, nblk = (n + kPersistBlock - 1) / kPersistBlock;
+    const uint32_t x0 = blockIdx.x % 8;
+    for (uint32_t k = 0; k < 8; k++) {
+        const uint32_t x = (x0 + k) % 8;
+        // queue x holds blocks x, x + 8, x + 16, ... of the range
+        const uint32_t qlen = x < nblk ? ((nblk - x + 7) / 8) * kPersistBlock : 0u;
+        for (;;) {
+            uint32_t i = 0;
+            if (lane_id() == 0) i = atomicAdd(ctr + 32 * x, 1u);
+            i = first32(i);
+            if (i >= qlen) break;
+            const uint32_t u = ub + ((i / kPersistBlock) * 8 + x) * kPersistBlock + i % kPersistBlock;
+            if (u >= ue) continue;  // the last block's tail
+            uint32_t kind = 0;
+            while (kind + 1 < K_COUNT && u >= A.kind_begin[kind + 1]) kind++;
+            run_unit<0>(A, kind, u, mine);
+        }
     }
 }
 
-__global__ void k_zero_counter(uint32_t *c) { *c = 0; }
+__global__ void k_zero_counters(uint32_t *c) {
+    if (threadIdx.x < 16) c[32 * threadIdx.x] = 0;
+}
 
 struct OutTable {
     uint8_t *p[kMaxCols];
@@ -57,10 +78,18 @@ hipError_t launch_decode(const LaunchArgs &A, uint32_t persistent_waves, const u
     };
     hipError_t e = hipSuccess;
     if (persistent_waves) {
+        // two-stage chunks: the kinds up to RLE (LZ77, ANS, RLE) write the
+        // scratch area that String-dictionary and TREE units read, so they
+        // get a launch of their own first; otherwise one launch takes all
         if ((e = mark(K_COUNT, false)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, st, A.counter);
-        const uint32_t blocks = (persistent_waves + 3) / 4;
-        hipLaunchKernelGGL(k_decode_persistent, dim3(blocks), dim3(256), 0, st, A);
+        hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, st, A.counter);
+        const uint32_t blocks = (persistent_waves + 3) / 4, all = A.kind_begin[K_COUNT];
+        const uint32_t cut = A.two_stage ? A.kind_begin[K_SDICT] : all;
+        if (cut > 0)
+            hipLaunchKernelGGL(k_decode_persistent, dim3(blocks), dim3(256), 0, st, A, 0u, cut, A.counter);
+        if (all > cut)
+            hipLaunchKernelGGL(k_decode_persistent, dim3(blocks), dim3(256), 0, st, A, cut, all,
+                               A.counter + 8 * 32);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         return mark(K_COUNT, true);
     }

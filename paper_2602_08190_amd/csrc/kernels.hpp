@@ -53,6 +53,16 @@ ZF_DEV T rlT(T v, uint32_t lane) {
     else return T(rl32(uint32_t(v), lane));
 }
 ZF_DEV uint32_t first32(uint32_t v) { return uint32_t(__builtin_amdgcn_readfirstlane(int(v))); }
+// A pointer that every lane holds the same value of, moved to scalar
+// registers: a buffer resource built from a pointer the compiler cannot
+// prove uniform (one read from memory) is otherwise wrapped in a loop over
+// the distinct values, around every load through it.
+template <class T>
+ZF_DEV T *uniform_ptr(T *p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint64_t u = (uint64_t(first32(uint32_t(v >> 32))) << 32) | first32(uint32_t(v));
+    return reinterpret_cast<T *>(u);
+}
 
 // Inclusive prefix sums across the 64 lanes (wrapping), with DPP lane moves:
 // row_shr 1, 2, 4, 8 inside each row of 16 lanes, then row_bcast 15 and 31
@@ -1317,7 +1327,7 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
     // Index words, entries and group offsets are read through bounds-checked
     // views (a read past a view returns 0), so no load sits behind a branch
     // and loads stay in flight until their values are used.
-    const uint8_t *codes = staged ? A.out_tab[kScratchCol] + ck.aux_off : s + co;
+    const uint8_t *codes = uniform_ptr(staged ? A.out_tab[kScratchCol] + ck.aux_off : s + co);
     const __amdgpu_buffer_rsrc_t rs_codes =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(codes), 0, int(4 * ncw), 0x00020000);
     const __amdgpu_buffer_rsrc_t rs_ents =
@@ -1730,7 +1740,7 @@ ZF_DEV void run_unit(const LaunchArgs &A, uint32_t kind, uint32_t u, uint32_t *l
         if (ck.dtype == D_I32) unit_tree<uint32_t>(A, t, ck, lz_row);
         else unit_tree<uint64_t>(A, t, ck, lz_row);
         break;
-    case K_LZ: unit_lz<16>(A, ck, lz_row); break;
+    case K_LZ: unit_lz<4>(A, ck, lz_row); break;
     case K_SDICT: unit_sdict(A, t, ck, lz_row); break;
     case K_ANS: unit_ans(A, ck, lz_row); break;
     }

@@ -186,6 +186,7 @@ static void flatten(const WorkTables &w, std::vector<uint8_t> &host, uint64_t of
         u += uint32_t(w.tiles[k].size());
     }
     A.kind_begin[K_COUNT] = u;
+    A.two_stage = w.scratch_bytes > 0;
 }
 
 struct DeviceGuard {
@@ -311,8 +312,10 @@ void build_plan(zf_plan_t *P, const zf_column *const *cols, uint32_t n_cols, int
     std::vector<uint8_t> host(tb_total, 0);
     ZF_HIP(hipMalloc(&P->d_tables, std::max<uint64_t>(tb_total, 256)));
     ZF_HIP(hipMalloc(&P->d_out_tab, sizeof(uint8_t *) * kMaxCols));
-    ZF_HIP(hipMalloc(&P->d_err, 256));
-    ZF_HIP(hipMemset(P->d_err, 0, 256));
+    // error word, then the persistent queue heads from byte 256 (2 x 8 of
+    // them, 128 bytes apart)
+    ZF_HIP(hipMalloc(&P->d_err, 256 + 16 * 128));
+    ZF_HIP(hipMemset(P->d_err, 0, 256 + 16 * 128));
     uint64_t off = 0;
     flatten(image, host, off, P->d_tables, P->image_args);
     off += table_bytes(image);
@@ -330,15 +333,12 @@ void build_plan(zf_plan_t *P, const zf_column *const *cols, uint32_t n_cols, int
     if (dict_total) ZF_HIP(hipMalloc(&P->d_dict, dict_total));
     P->scratch_bytes = image.scratch_bytes;
     for (auto &b : P->batches) P->scratch_bytes = std::max(P->scratch_bytes, b.w.scratch_bytes);
-    ZF_REQUIRE(!(P->scratch_bytes && P->persistent_waves), ZF_E_UNSUPPORTED,
-               "two-stage chunks (String-dictionary | BP | ANS, the DeltaStride tree) decode in two "
-               "ordered launches; the persistent kernel does not order its units");
     if (P->scratch_bytes) ZF_HIP(hipMalloc(&P->d_scratch, P->scratch_bytes));
 
     auto fill = [&](LaunchArgs &A) {
         A.out_tab = P->d_out_tab;
         A.err = P->d_err;
-        A.counter = P->d_err + 1;
+        A.counter = P->d_err + 64;
     };
     fill(P->image_args);
     for (uint32_t k = 0; k < P->batches.size(); k++) {

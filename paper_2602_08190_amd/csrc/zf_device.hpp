@@ -87,8 +87,9 @@ struct LaunchArgs {
     const ChunkDesc *chunks;
     const Tile *tiles;            // tiles grouped by kind
     uint32_t *err;                // device error word
-    uint32_t *counter;            // persistent-kernel queue head (zeroed per launch)
+    uint32_t *counter;            // persistent-kernel queue heads: 2 launches x 8 XCDs, 32 dwords apart
     uint32_t kind_begin[K_COUNT + 1];
+    uint32_t two_stage;           // some units read the scratch area that earlier kinds write
 };
 
 // Host side: events recorded around each kind's launch of a profiled decode

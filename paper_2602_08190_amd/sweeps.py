@@ -9,7 +9,8 @@ frequency skew (the paper's L_RETURNFLAG-shaped workload made more and more
 imbalanced) and over the chunk size (parallelism against ratio).
 text: the comment-text column under LZ77 (64 KiB chunks, its largest), and
 String-dictionary and String-dictionary | BP | ANS over the chunk size (the
-per-chunk dictionary against parallelism)."""
+per-chunk dictionary against parallelism), and both over one column
+dictionary."""
 import argparse
 import json
 import sys
@@ -88,6 +89,10 @@ def text(mib):
         one(zf.SDICT_BP, "SDICT_BP", kib)
     for kib in (256, 1024, 4096):
         one(zf.SDICT_ANS, "SDICT_ANS", kib)
+    for kib in (64, 1024, 4096):
+        one(zf.SDICT_COL, "SDICT_COL", kib)
+    for kib in (64, 1024, 4096):
+        one(zf.SDICT_COL_ANS, "SDICT_COL_ANS", kib)
     return {"workload": f"{mib} MiB comment text (Zipf 1.1 over 10,000 words), decode from HBM", "rows": rows}
 
 

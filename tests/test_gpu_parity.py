@@ -209,21 +209,19 @@ def dstree_columns():
     return cols, xs
 
 
-@pytest.mark.parametrize("mode", ["graphs", "plain", "staged", "tiles256", "persistent_rejected"])
+@pytest.mark.parametrize("mode", ["graphs", "plain", "staged", "tiles256", "persistent"])
 def test_dstree_two_stage_decode(mode):
     """DeltaStride | [Delta | RLE | [BP, BP], BP]: the run starts are expanded
     into the scratch area by the RLE kinds' launch, the output by the TREE
     launch after it; sparse order keys with and without deletions, nearly
     increasing keys, random values, extremes, descending keys, a progression
     across the wrap, a one-value chunk; beside RLE and DeltaStride columns;
-    staged transfers with small slots run several batches through the one
+    per-kind and persistent launches; staged transfers with small slots run several batches through the one
     scratch area."""
     log("dstree", mode)
     cols, xs = dstree_columns()
-    if mode == "persistent_rejected":
-        with pytest.raises(zf.ZfError) as e:
-            zf.Plan(cols, device=0, persistent=True)
-        assert e.value.status == zf.E_UNSUPPORTED
+    if mode == "persistent":  # two ordered persistent launches
+        check(cols, decode_image(cols, persistent=True), xs)
         return
     if mode == "staged":
         outs, _ = decode_staged(cols, slot_bytes=1 << 18)
@@ -308,7 +306,7 @@ def test_sdict_col_ans_two_stage_decode(mode):
     check(cols, decode_image(cols), xs)
 
 
-@pytest.mark.parametrize("mode", ["graphs", "no_graphs", "staged", "persistent_rejected"])
+@pytest.mark.parametrize("mode", ["graphs", "no_graphs", "staged", "persistent"])
 def test_sdict_ans_two_stage_decode(mode):
     """String-dictionary | BP | ANS: the ANS stage writes the entry indices to
     the plan's scratch area, the String-dictionary stage reads them; mixed
@@ -335,10 +333,8 @@ def test_sdict_ans_two_stage_decode(mode):
         ab[0::2], ab[1::2] = np.where(t == 0, ord("a"), ord("b")), ord(" ")
         xs.append(ab)
         cols.append(zf.Column.compress(ab, zf.SDICT_ANS, chunk_elems=[len(ab)]))
-    if mode == "persistent_rejected":
-        with pytest.raises(zf.ZfError) as e:
-            zf.Plan(cols, device=0, persistent=True)
-        assert e.value.status == zf.E_UNSUPPORTED
+    if mode == "persistent":  # two ordered persistent launches
+        check(cols, decode_image(cols, persistent=True), xs)
         return
     if mode == "staged":
         outs, _ = decode_staged(cols, slot_bytes=1 << 18)
