@@ -3,6 +3,7 @@
     python -m paper_2602_08190_amd.profiling stats <run_kernel_stats.csv> <out.txt> "<command>"
     python -m paper_2602_08190_amd.profiling traffic <pmc_root> <out_dir> "<command>"
     python -m paper_2602_08190_amd.profiling counters <out.txt> <kernel> "<command>" <csv> [<csv> ...]
+    python -m paper_2602_08190_amd.profiling copies <stats.csv> <trace.csv> <out.txt> "<command>"
 
 `traffic` expects <pmc_root>/pmc_<workload>_<COUNTER>/run_counter_collection.csv
 for COUNTER in FETCH_SIZE, WRITE_SIZE and workloads including `copy` (the
@@ -91,23 +92,57 @@ def traffic(root, out_dir, command):
         fo.write("\n".join(lines) + "\n")
 
 
-def counters(csv_paths, fragment, out_path, command):
+def counters(csv_paths, fragments, out_path, command):
     """Median per-dispatch value of every counter in the given
-    run_counter_collection.csv files for kernels whose name contains
-    `fragment` (each dispatch's value summed over the agent's instances)."""
-    rows = {}
-    for path in csv_paths:
-        per = collections.defaultdict(lambda: collections.defaultdict(float))
-        for r in csv.DictReader(open(path)):
-            if fragment in r["Kernel_Name"]:
-                per[r["Counter_Name"]][r["Dispatch_Id"]] += float(r["Counter_Value"])
-        for name, d in per.items():
-            v = sorted(d.values())
-            rows[name] = (v[len(v) // 2], len(v))
-    lines = [f"# rocprofv3 --pmc counters of kernels matching '{fragment}', median per dispatch",
-             f"# command (one run per counter set): {command}", f"# kernel sources sha: {kernel_sha()}", ""]
-    for name in sorted(rows):
-        lines.append(f"{name:32s} {rows[name][0]:18.0f}   ({rows[name][1]} dispatches)")
+    run_counter_collection.csv files for the kernels whose names contain each
+    of the comma-separated `fragments` (each dispatch's value summed over the
+    agent's instances), one section per kernel."""
+    lines = [f"# rocprofv3 --pmc counters, median per dispatch, of kernels matching {fragments}",
+             f"# command (one run per counter set): {command}", f"# kernel sources sha: {kernel_sha()}"]
+    for fragment in fragments.split(","):
+        rows = {}
+        for path in csv_paths:
+            per = collections.defaultdict(lambda: collections.defaultdict(float))
+            for r in csv.DictReader(open(path)):
+                if fragment in r["Kernel_Name"]:
+                    per[r["Counter_Name"]][r["Dispatch_Id"]] += float(r["Counter_Value"])
+            for name, d in per.items():
+                v = sorted(d.values())
+                rows[name] = (v[len(v) // 2], len(v))
+        lines += ["", f"## {fragment}"]
+        for name in sorted(rows):
+            lines.append(f"{name:32s} {rows[name][0]:18.0f}   ({rows[name][1]} dispatches)")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def copies(stats_csv, trace_csv, out_path, command, piece_bytes=256 << 20):
+    """Host-to-device copy summary: calls and durations per direction, and
+    the link rate from the raw-copy leg's fixed-size pieces (the copies whose
+    byte count is piece_bytes, or, when the trace has no sizes, the longest
+    copies, which are those pieces)."""
+    rows = list(csv.DictReader(open(stats_csv)))
+    lines = [f"# rocprofv3 --memory-copy-trace --stats summary ({os.path.basename(stats_csv)}, "
+             f"{os.path.basename(trace_csv)})", f"# command: {command}", "",
+             f"{'direction':32s} {'calls':>6s} {'avg_us':>10s} {'total_ms':>10s}"]
+    for r in rows:
+        lines.append(f"{r['Name']:32s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.1f} "
+                     f"{float(r['TotalDurationNs']) / 1e6:10.2f}")
+    tr = [r for r in csv.DictReader(open(trace_csv)) if "HOST_TO_DEVICE" in r.get("Direction", r.get("Kind", ""))
+          or "HOST_TO_DEVICE" in " ".join(r.values())]
+    size_key = next((k for k in ("Size", "Bytes", "Copy_Bytes") if tr and k in tr[0]), None)
+    dur = lambda r: (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9  # noqa: E731
+    if size_key:
+        pieces = [r for r in tr if int(r[size_key]) == piece_bytes]
+    else:
+        d = sorted(dur(r) for r in tr)
+        cut = d[-1] * 0.85 if d else 0
+        pieces = [r for r in tr if dur(r) >= cut]
+    if pieces:
+        t = sum(dur(r) for r in pieces) / len(pieces)
+        lines += ["", f"raw-copy pieces of {piece_bytes >> 20} MiB: {len(pieces)} copies, average {t * 1e3:.3f} ms "
+                  f"-> {piece_bytes / t / 1e9:.1f} GB/s host to device "
+                  f"({'by byte count' if size_key else 'the longest copies'})"]
     with open(out_path, "w") as f:
         f.write("\n".join(lines) + "\n")
 
@@ -117,6 +152,9 @@ if __name__ == "__main__":
         stats(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "copies":
+        # copies <run_memory_copy_stats.csv> <run_memory_copy_trace.csv> <out.txt> "<command>"
+        copies(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
     elif sys.argv[1] == "counters":
         # counters <out.txt> <kernel fragment> "<command>" <csv> [<csv> ...]
         counters(sys.argv[5:], sys.argv[3], sys.argv[2], sys.argv[4])
