@@ -346,6 +346,27 @@ zf_status zf_plan_batch_info(const zf_plan_t *plan, uint32_t k, zf_batch_info *i
  */
 zf_status zf_johnson_order(const double *a, const double *b, uint32_t n, uint32_t *order);
 
+/*
+ * The work units the planner cuts one chunk into, each decoded by one
+ * wavefront (the device geometry of Sec. 4).  units[i] = {kind (a zf_kind),
+ * a, b, c}: FP kinds (FOR, DICT, F2I): first 2048-value block, block count,
+ * 0; RLE32, RLE64, TREE: first group, first element, end element; SDICT:
+ * first group of 64 tokens, end group, 0; PLAIN: first byte, end byte, 0;
+ * LZ77 and ANS: 0, 0, 0 (the whole stream).  A two-stage chunk lists its
+ * first-stage units first (ANS pieces of SDICT_ANS / SDICT_COL_ANS, the run
+ * starts of DSTREE in RLE32 / RLE64), then the units of its output stage.
+ * Tiles come from opts (nullable: the tune cache, as zf_plan takes them)
+ * and the chunk's schedule hint.  units: caller-owned host array of cap
+ * entries; with units NULL and cap 0 only *n_units is set.  Host only, no
+ * device needed.  Errors: ZF_E_INVALID (null column or n_units, chunk out
+ * of range), ZF_E_TOO_SMALL (cap below the unit count).
+ */
+typedef struct {
+    uint32_t kind, a, b, c;
+} zf_unit;
+zf_status zf_chunk_units(const zf_column_t *col, uint32_t chunk, const zf_plan_opts *opts,
+                         zf_unit *units, uint32_t cap, uint32_t *n_units);
+
 /* Device image for zf_decompress_async: column c's serialised bytes go at
  * byte offset zf_plan_image_offset(plan, c) of a device buffer of
  * zf_plan_image_bytes(plan) bytes (offsets are 256-aligned). */

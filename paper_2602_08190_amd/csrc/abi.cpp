@@ -137,6 +137,25 @@ zf_status zf_johnson_order(const double *a, const double *b, uint32_t n, uint32_
     });
 }
 
+zf_status zf_chunk_units(const zf_column_t *col, uint32_t chunk, const zf_plan_opts *opts, zf_unit *units,
+                         uint32_t cap, uint32_t *n_units) {
+    return guard([&] {
+        ZF_REQUIRE(col && n_units, ZF_E_INVALID, "null pointer");
+        zf_plan_opts o;
+        if (opts)
+            o = *opts;
+        else
+            zf_plan_opts_default(&o);
+        const std::vector<zf_unit> u = chunk_units(*col, chunk, o);
+        if (units || cap) {
+            ZF_REQUIRE(units, ZF_E_INVALID, "null units with cap %u", cap);
+            ZF_REQUIRE(cap >= u.size(), ZF_E_TOO_SMALL, "%zu units, room for %u", u.size(), cap);
+            std::copy(u.begin(), u.end(), units);
+        }
+        *n_units = uint32_t(u.size());
+    });
+}
+
 zf_status zf_decompress_async(zf_plan_t *plan, const void *d_comp, uint64_t comp_bytes,
                               void *const *d_out, zf_stream_t stream) {
     return guard([&] {

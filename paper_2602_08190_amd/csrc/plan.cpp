@@ -164,6 +164,16 @@ std::vector<uint32_t> johnson(const std::vector<double> &a, const std::vector<do
     return first;
 }
 
+std::vector<zf_unit> chunk_units(const zf_column &col, uint32_t ci, const zf_plan_opts &o) {
+    ZF_REQUIRE(ci < col.view.n_chunks, ZF_E_INVALID, "chunk %u of %u", ci, col.view.n_chunks);
+    WorkTables w;
+    add_chunk(w, col, ci, 0, 0, 0, resolve_tiles(o));
+    std::vector<zf_unit> u;
+    for (uint32_t k = 0; k < K_COUNT; k++)
+        for (const Tile &t : w.tiles[k]) u.push_back({k, t.a, t.b, t.c});
+    return u;
+}
+
 // Size in bytes of a launch's flattened tables.
 static uint64_t table_bytes(const WorkTables &w) {
     uint64_t n = align_up(w.chunks.size() * sizeof(ChunkDesc), 256);

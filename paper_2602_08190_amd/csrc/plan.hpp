@@ -30,6 +30,8 @@ struct WorkTables {
 void release_plan(zf_plan_t *P);
 // Johnson's two-machine order of jobs with first-stage times a, second b.
 std::vector<uint32_t> johnson(const std::vector<double> &a, const std::vector<double> &b);
+// The units add_chunk cuts chunk ci of col into, in kind order (host only).
+std::vector<zf_unit> chunk_units(const zf_column &col, uint32_t ci, const zf_plan_opts &o);
 
 struct Batch {
     WorkTables w;

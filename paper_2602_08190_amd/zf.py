@@ -70,6 +70,11 @@ class Timing(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Unit(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("a", ctypes.c_uint32), ("b", ctypes.c_uint32),
+                ("c", ctypes.c_uint32)]
+
+
 class BatchInfo(ctypes.Structure):
     _fields_ = [("t_h2d_ms", ctypes.c_double), ("t_dec_ms", ctypes.c_double),
                 ("comp_bytes", ctypes.c_uint64), ("plain_bytes", ctypes.c_uint64),
@@ -102,6 +107,7 @@ SIGNATURES = {
     "zf_plan_n_batches": (_u32, [_vp]),
     "zf_plan_batch_info": (_i32, [_vp, _u32, ctypes.POINTER(BatchInfo)]),
     "zf_johnson_order": (_i32, [_vp, _vp, _u32, _vp]),
+    "zf_chunk_units": (_i32, [_vp, _u32, ctypes.POINTER(PlanOpts), _vp, _u32, ctypes.POINTER(_u32)]),
     "zf_decompress_async": (_i32, [_vp, _vp, _u64, ctypes.POINTER(_vp), _vp]),
     "zf_transfer_and_decompress": (_i32, [_vp, ctypes.POINTER(_vp), _vp,
                                           ctypes.POINTER(Timing)]),
@@ -282,6 +288,30 @@ def _stream(s):
     return s.cuda_stream
 
 
+def _set_tiles(o, tiles):
+    """tiles: {kind or group name: {"unit": u, "waves_per_block": w}} into PlanOpts o."""
+    for name, shape in (tiles or {}).items():
+        for kind in KIND_GROUPS.get(name, [name]):
+            t = o.tiles[KINDS.index(kind)]
+            t.unit = shape.get("unit", 0)
+            t.waves_per_block = shape.get("waves_per_block", 0)
+
+
+def chunk_units(col, chunk, tiles=None, tune_cache=None):
+    """[(kind name, a, b, c)] of the wavefront units the planner cuts chunk
+    `chunk` of `col` into (zf_chunk_units; host only)."""
+    o = PlanOpts()
+    lib().zf_plan_opts_default(ctypes.byref(o))
+    _set_tiles(o, tiles)
+    keep = tune_cache.encode() if tune_cache else None
+    o.tune_cache = keep
+    n = ctypes.c_uint32()
+    _check(lib().zf_chunk_units(col.handle, chunk, ctypes.byref(o), None, 0, ctypes.byref(n)))
+    arr = (Unit * max(n.value, 1))()
+    _check(lib().zf_chunk_units(col.handle, chunk, ctypes.byref(o), arr, n.value, ctypes.byref(n)))
+    return [(KINDS[u.kind], u.a, u.b, u.c) for u in arr[:n.value]]
+
+
 class Plan:
     """Work tables, batches and device workspace for decoding `cols`."""
 
@@ -299,11 +329,7 @@ class Plan:
         o.persistent = 1 if persistent else 0
         o.order = order
         o.pcie_gbps = pcie_gbps
-        for name, shape in (tiles or {}).items():
-            for kind in KIND_GROUPS.get(name, [name]):
-                t = o.tiles[KINDS.index(kind)]
-                t.unit = shape.get("unit", 0)
-                t.waves_per_block = shape.get("waves_per_block", 0)
+        _set_tiles(o, tiles)
         o.waves_per_cu = waves_per_cu
         self._tune = tune_cache.encode() if tune_cache else None
         o.tune_cache = self._tune
