@@ -18,7 +18,7 @@ constexpr uint32_t kPersistBlock = 16;
 // a few spills), the fastest of 2, 4 and 6 waves per SIMD on the fact table.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_decode_persistent(
     LaunchArgs A, uint32_t ub, uint32_t ue, uint32_t *ctr) {
-    __shared__ __attribute__((aligned(16))) uint32_t lz_rows[4][kAnsLdsWords > kSdBufWords ? kAnsLdsWords : kSdBufWords];
+    __shared__ __attribute__((aligned(16))) uint32_t lz_rows[4][kAnsLdsWords > kSdBufAlloc ? kAnsLdsWords : kSdBufAlloc];
     uint32_t *mine = lz_rows[threadIdx.x / 64];
     const uint32_t n = ue - ub, nblk = (n + kPersistBlock - 1) / kPersistBlock;
     const uint32_t x0 = blockIdx.x % 8;

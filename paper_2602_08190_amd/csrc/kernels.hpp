@@ -128,6 +128,10 @@ ZF_DEV bool any(bool p) { return __ballot(p) != 0; }
 // Orders this wave's global memory accesses for the compiler.  Lanes of one
 // wavefront share one in-order path to the L1, so a load issued after a
 // store of the same wave observes it; the fence only stops reordering.
+// Cache policy of a buffer store that bypasses the caches' normal
+// retention (the nt bit of the instruction).
+constexpr int kNonTemporal = 2;
+
 ZF_DEV void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
 
 ZF_DEV void flag(uint32_t *err, uint32_t bits) {
@@ -1248,10 +1252,11 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, uint32_t *row) {
 // The tokens' bytes are assembled in the wave's LDS buffer, laid on the
 // output's 16-byte grid: each lane ORs the dwords its token covers (read as
 // unaligned dwords from the entry bytes and masked to the token) into the
-// zeroed buffer.  Whenever at least kSdFlushBytes of whole 16-byte blocks are
-// complete, and at the unit's end, the wave writes them out with one 16-byte
-// store per lane per block and carries the unfinished block to the buffer's
-// front.  Bytes of a block outside the unit's output range belong to the
+// zeroed buffer, which starts on the output's 128-byte grid.  After each
+// group the wave writes out the whole 128-byte lines done (one 16-byte store
+// per lane and block, one store instruction per group) and carries the
+// unfinished line to the buffer's front; at the unit's end it writes out the
+// rest.  Bytes of a block outside the unit's output range belong to the
 // neighbouring units and are left alone.
 // Entries and entry bytes are the chunk's (SDICT_BP, SDICT_ANS) or the
 // column dictionary's (SDICT_COL, SDICT_COL_ANS); the packed indices are the
@@ -1259,17 +1264,24 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, uint32_t *row) {
 // (the *_ANS codecs).  Every header field is checked against the stream or
 // dictionary size before use; the wave checks every index and entry and each
 // group's length.
-// buf: this wave's kSdBufWords dwords (16-byte aligned).
-constexpr uint32_t kSdBufWords = 1280;    // 5120 bytes
-constexpr uint32_t kSdFlushBytes = 1024;  // whole blocks that trigger a write-out
-// Before a group the buffer holds < kSdFlushBytes bytes (else it would have
-// been written out); a group adds at most 64 tokens of kSdMaxToken bytes.
-static_assert(kSdFlushBytes + 64 * kSdMaxToken <= 4 * kSdBufWords, "String-dictionary buffer");
+// buf: this wave's kSdBufAlloc dwords (16-byte aligned): kSdBufWords of
+// buffer and 4 that only ever receive ORs of zero.
+constexpr uint32_t kSdBufAlloc = 1280;    // 5120 bytes: 32 one-wave workgroups fill a CU's LDS
+constexpr uint32_t kSdBufWords = kSdBufAlloc - 4;
+// Before a group the buffer holds < 128 bytes (the whole lines are written
+// out after each group); a group adds at most 64 tokens of kSdMaxToken bytes,
+// so every token position of a checked group lies in the buffer, and the
+// four dwords from a position's dword end at most 3 dwords past it.
+static_assert(128 + 64 * kSdMaxToken <= 4 * kSdBufWords, "String-dictionary buffer");
+static_assert(kSdBufAlloc % 256 == 0, "String-dictionary buffers: 16-byte aligned, zeroed in 64 lanes x 16 bytes");
 
 // COL: a column dictionary (SDICT_COL, SDICT_COL_ANS), whose entries have
 // at least three zero bytes on each side, so a dword read around a token
 // needs no mask; else the chunk's own dictionary (SDICT_BP, SDICT_ANS).
-template <bool COL>
+// PAIR: two groups per loop iteration (the per-kind kernel); one group per
+// iteration keeps the persistent kernel, which holds every kind's routine,
+// within its register budget.
+template <bool COL, bool PAIR>
 ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, uint32_t *buf) {
     const uint8_t *s = A.comp + ck.comp_off;
     const uint32_t lane = lane_id(), plain = ck.n_elems, clen = ck.comp_len;
@@ -1348,47 +1360,66 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
     }
     const uint32_t gwin = t.a + lane < ng ? __builtin_amdgcn_raw_buffer_load_b32(rs_gofs, int(4 * (t.a + lane)), 0, 0)
                                           : plain;
-    auto goff = [&](uint32_t g) { return rl32(gwin, g - t.a); };
+    auto goff = [&](uint32_t g) { return rl32(gwin, min(g - t.a, 63u)); };  // (past t.b: unused)
     const uint32_t ua = goff(t.a), ub = goff(t.b);
     if (ua >= ub || ub > plain) {
         flag(A.err, ERR_CORRUPT);
         return;
     }
-    const uint32_t oa = uint32_t(reinterpret_cast<uintptr_t>(out) & 15u);
-    // buffer byte k holds output byte sbase + k; out + sbase is 16-aligned
-    int64_t sbase = int64_t(ua) - int64_t((oa + ua) & 15u);
+    const uint32_t oa = uint32_t(reinterpret_cast<uintptr_t>(out) & 127u);
+    // buffer byte k holds output byte sbase + k; out + sbase lies on the
+    // output's 128-byte grid
+    int64_t sbase = int64_t(ua) - int64_t((oa + ua) & 127u);
+    // the chunk's output (stores past it are dropped)
+    const __amdgpu_buffer_rsrc_t rs_out =
+        __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(out), 0, int(plain), 0x00020000);
     const u32x4 zero4 = {0u, 0u, 0u, 0u};
 #pragma unroll
-    for (uint32_t k = 0; k < kSdBufWords / 256; k++) *reinterpret_cast<u32x4 *>(buf + 4 * (64 * k + lane)) = zero4;
+    for (uint32_t k = 0; k < kSdBufAlloc / 256; k++) *reinterpret_cast<u32x4 *>(buf + 4 * (64 * k + lane)) = zero4;
     wave_fence();
 
     // Three stages run ahead of the group being written: the packed index
     // words of group g + 2 and the entries of group g + 1 are loaded, and
     // group g + 1's token positions are computed and its entry bytes loaded,
     // before group g's bytes are ORed into the buffer.
-    auto words_of = [&](uint32_t g, uint32_t &w0, uint32_t &w1) {
-        const uint32_t i = 64 * g + lane;
-        const bool act = g < t.b && i < nt && w;
-        const uint32_t k = uint32_t((uint64_t(i) * w) >> 5);
-        w0 = __builtin_amdgcn_raw_buffer_load_b32(rs_codes, int(act ? 4 * k : 0x7FFFFFF0u), 0, 0);
-        w1 = __builtin_amdgcn_raw_buffer_load_b32(rs_codes, int(act ? 4 * k + 4 : 0x7FFFFFF0u), 0, 0);
+    // group g's packed indices: 64 tokens of w bits start on a dword, so the
+    // group's bits are the 2w dwords from dword 2wg; lane l loads dword
+    // 2wg + l (one coalesced load)
+    auto words_of = [&](uint32_t g) -> uint32_t {
+        const bool act = g < t.b && lane < 2 * w;
+        return __builtin_amdgcn_raw_buffer_load_b32(rs_codes, int(act ? 4 * (2 * w * g + lane) : 0x7FFFFFF0u), 0,
+                                                    0);
     };
-    // entry of group g's token from its index words; bad: index past the entries
-    auto entry_of = [&](uint32_t g, uint32_t w0, uint32_t w1, bool &bad) -> uint32_t {
+    // entry of group g's token from the group's index dwords (win): the
+    // token's w bits start at bit lane * w of them; bad: index past the
+    // entries.  (The second dword is read from lane k + 1 < 2w whenever the
+    // token reaches into it; lane 63's token at w = 32 lies in dword 63.)
+    auto entry_of = [&](uint32_t g, uint32_t win, bool &bad) -> uint32_t {
         const uint32_t i = 64 * g + lane;
         const bool act = g < t.b && i < nt;
-        const uint32_t code =
-            w ? uint32_t((uint64_t(w0) | (uint64_t(w1) << 32)) >> ((uint64_t(i) * w) & 31u)) & mask32(w) : 0u;
+        const uint32_t bit = lane * w, k = bit >> 5;
+        const uint32_t w0 = uint32_t(__builtin_amdgcn_ds_bpermute(int(4 * k), int(win)));
+        const uint32_t w1 = uint32_t(__builtin_amdgcn_ds_bpermute(int(4 * k + 4), int(win)));
+        const uint32_t code = w ? uint32_t((uint64_t(w0) | (uint64_t(w1) << 32)) >> (bit & 31u)) & mask32(w) : 0u;
         bad = act && code >= ne;
         return __builtin_amdgcn_raw_buffer_load_b32(rs_ents, int((act && !bad) ? 4 * code : 0x7FFFFFF0u), 0, 0);
     };
     struct Grp {
         uint32_t len, eoff, P, end;  // token length and entry offset, token start, group end
         uint32_t v0, v1, v2, v3;     // the first four dwords of the token's bytes
+        bool live;                   // a checked group of the unit, to be staged
     };
-    // positions and checks of group g from its entries, then its first loads
-    auto prepare = [&](uint32_t g, uint32_t e, bool bad_code, Grp &G) -> bool {
-        const bool act = 64 * g + lane < nt;
+    // A corrupt group ends the wave's work: it and every later group are not
+    // staged (the loop still runs to the unit's end, so that no exit from
+    // its middle keeps loads in flight across the loop's back edge).
+    bool dead = false;
+    // positions and checks of group g from its entries, then its first loads;
+    // a group past the unit (g >= t.b, whose entries read as zero), a corrupt
+    // group and the groups after it are not live: they take the previous
+    // group's end (prev_end) as their position and end.  Returns false for a
+    // corrupt group of the unit.
+    auto prepare = [&](uint32_t g, uint32_t e, bool bad_code, Grp &G, uint32_t prev_end) -> bool {
+        const bool act = g < t.b && 64 * g + lane < nt;
         G.len = e >> 24;
         G.eoff = e & 0xFFFFFFu;
         const uint32_t incl = scan_add32(G.len), total = rl32(incl, 63);
@@ -1419,13 +1450,17 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
         // (bitwise, not short-circuit: no branch per condition)
         const bool bad_lane = bad_code | (act & (((G.len - 1u) >= kSdMaxToken) | (G.eoff + G.len > nb)));
         const bool bad_grp = (uint64_t(pos) + total != G.end) | (G.end > ub) | (pos < ua);
-        return !(any(bad_lane) | bad_grp);
+        const bool ok = !((any(bad_lane) | bad_grp) & (g < t.b));
+        G.live = ok & !dead & (g < t.b);
+        G.P = G.live ? G.P : prev_end;
+        G.end = G.live ? G.end : prev_end;
+        return ok;
     };
     // OR group G's token bytes into the buffer: dword j of the token's span
     // holds token bytes [4j - m, 4j - m + 4) clipped to [0, len); every lane
     // ORs (a zero where it has nothing) so that no branch splits the wave
     auto stage = [&](const Grp &G, uint32_t g) {
-        const bool act = 64 * g + lane < nt;
+        const bool act = G.live && 64 * g + lane < nt;
         const uint32_t o = uint32_t(int64_t(G.P) - sbase), m = o & 3u;
         const uint32_t nd = act ? (m + G.len + 3) >> 2 : 0u;
         const uint32_t head = 0xFFFFFFFFu << (8 * m);            // bytes from the token's start
@@ -1434,88 +1469,105 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
             const uint32_t r = endb - 4 * j;
             return r >= 4 ? 0xFFFFFFFFu : ((1u << (8 * r)) - 1u);
         };
-        // a token's dwords lie inside the buffer; lanes with nothing to OR at
-        // dword j send a zero to a clamped address
+        // a checked group's positions lie inside the buffer (o < 4 kSdBufWords),
+        // so dwords d0 .. d0 + 3 lie inside the allocation; lanes with nothing
+        // to OR at dword j OR a zero
         const uint32_t d0 = o >> 2;
-        auto at = [&](uint32_t j) { return buf + min(d0 + j, kSdBufWords - 1); };
+        uint32_t *at = buf + d0;
         uint32_t v0, v1, v2, v3;
         if constexpr (COL) {
-            // buffer dword j = entry bytes [4j - m, 4j - m + 4): a funnel
-            // shift of aligned entry dwords j - 1 and j (the three bytes
-            // before an entry and after it are zero, so only dwords past
-            // the token need clearing)
-            auto sh = [&](uint32_t hi, uint32_t lo) { return m ? __builtin_amdgcn_alignbit(hi, lo, 32 - 8 * m) : hi; };
-            v0 = 0 < nd ? sh(G.v0, 0u) : 0u;
-            v1 = 1 < nd ? sh(G.v1, G.v0) : 0u;
-            v2 = 2 < nd ? sh(G.v2, G.v1) : 0u;
-            v3 = 3 < nd ? sh(G.v3, G.v2) : 0u;
+            // buffer dword j = entry bytes [4j - m, 4j - m + 4): bytes 4 - m ..
+            // 7 - m of the aligned entry dwords j - 1 (low) and j (high), one
+            // byte permute each (the three bytes before an entry and after it
+            // are zero, so only dwords past the token need clearing)
+            const uint32_t sel = 0x07060504u - 0x01010101u * m;
+            v0 = 0 < nd ? __builtin_amdgcn_perm(G.v0, 0u, sel) : 0u;
+            v1 = 1 < nd ? __builtin_amdgcn_perm(G.v1, G.v0, sel) : 0u;
+            v2 = 2 < nd ? __builtin_amdgcn_perm(G.v2, G.v1, sel) : 0u;
+            v3 = 3 < nd ? __builtin_amdgcn_perm(G.v3, G.v2, sel) : 0u;
+            __hip_atomic_fetch_or(at, v0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_or(at + 1, v1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_or(at + 2, v2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_or(at + 3, v3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            uint32_t prev = G.v3;
+            for (uint32_t j = 4; any(j < nd); j++) {  // tokens of more than 13 bytes
+                const uint32_t e = __builtin_amdgcn_raw_buffer_load_b32(rs_ent, int(j < nd ? G.eoff + 4 * j + 4
+                                                                                         : 0x7FFFFFF0u), 0, 0);
+                const uint32_t v = __builtin_amdgcn_perm(e, prev, sel);
+                prev = e;
+                if (j < nd) __hip_atomic_fetch_or(at + j, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
         } else {
             // (a dword past nd was read out of range as 0)
             v0 = G.v0 & head & tail(0);
             v1 = G.v1 & tail(1);
             v2 = G.v2 & tail(2);
             v3 = G.v3 & tail(3);
-        }
-        __hip_atomic_fetch_or(at(0), v0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        __hip_atomic_fetch_or(at(1), v1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        __hip_atomic_fetch_or(at(2), v2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        __hip_atomic_fetch_or(at(3), v3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        uint32_t prev = G.v3;
-        for (uint32_t j = 4; any(j < nd); j++) {  // tokens of more than 13 bytes
-            if constexpr (COL) {
-                const uint32_t e = __builtin_amdgcn_raw_buffer_load_b32(rs_ent, int(j < nd ? G.eoff + 4 * j + 4
-                                                                                         : 0x7FFFFFF0u), 0, 0);
-                const uint32_t v = m ? __builtin_amdgcn_alignbit(e, prev, 32 - 8 * m) : e;
-                prev = e;
-                if (j < nd) __hip_atomic_fetch_or(buf + d0 + j, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            } else {
+            __hip_atomic_fetch_or(at, v0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_or(at + 1, v1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_or(at + 2, v2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_or(at + 3, v3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            for (uint32_t j = 4; any(j < nd); j++) {  // tokens of more than 13 bytes
                 const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(
                     rs_ent, int(j < nd ? G.eoff - m + 4 * j + 4 : 0x7FFFFFF0u), 0, 0);
-                if (j < nd) __hip_atomic_fetch_or(buf + d0 + j, v & tail(j), __ATOMIC_RELAXED,
+                if (j < nd) __hip_atomic_fetch_or(at + j, v & tail(j), __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
             }
         }
     };
 
-    Grp cur, nxt;
-    uint32_t w0, w1, e1 = 0;
-    bool bad = false, bad1 = false;
-    words_of(t.a, w0, w1);
-    const uint32_t e0 = entry_of(t.a, w0, w1, bad);
-    words_of(t.a + 1, w0, w1);
-    if (!prepare(t.a, e0, bad, cur)) {
-        flag(A.err, ERR_CORRUPT);
-        return;
-    }
-    e1 = entry_of(t.a + 1, w0, w1, bad1);
-    words_of(t.a + 2, w0, w1);
-    for (uint32_t g = t.a; g < t.b; g++) {
-        // run ahead: group g + 1's positions and bytes, g + 2's entries,
-        // g + 3's index words
-        if (g + 1 < t.b) {
-            if (!prepare(g + 1, e1, bad1, nxt)) {
-                flag(A.err, ERR_CORRUPT);
-                return;
-            }
-            e1 = entry_of(g + 2, w0, w1, bad1);
-            words_of(g + 3, w0, w1);
-        }
+    struct Entry {
+        uint32_t e;
+        bool bad;
+    };
+    // OR group g (cur, whose bytes were loaded one group earlier) into the
+    // buffer, and write out the whole blocks when enough are done and
+    // everything at the unit's end (a group past the unit writes nothing).
+    auto finish = [&](uint32_t g, const Grp &cur) {
         stage(cur, g);
-        // write out the whole blocks when enough are done, and everything at
-        // the unit's end
         const uint32_t fill = uint32_t(int64_t(cur.end) - sbase);
         const bool last = g + 1 == t.b;
-        if (last || fill >= kSdFlushBytes) {
-            const uint32_t nblk = last ? (fill + 15) / 16 : fill / 16;
-            wave_fence();
-            for (uint32_t b = lane; b < nblk; b += 64) {
+        // every group (a group past the unit too) issues exactly one store
+        // instruction: the whole 128-byte lines ready, at most eight (lane l
+        // writes block l); a variable number of stores between a load and
+        // its use would make the compiler's wait for that load also wait for
+        // every store and later load
+        const uint32_t nl = g < t.b ? min(fill >> 7, 8u) : 0u;
+        wave_fence();
+        {
+            // (read and written back by every lane, without a branch, so
+            // that the store stays one instruction)
+            const bool mine = lane < 8 * nl;
+            const u32x4 v = *reinterpret_cast<const u32x4 *>(buf + 4 * lane);
+            *reinterpret_cast<u32x4 *>(buf + 4 * lane) = mine ? zero4 : v;
+            const int64_t q = sbase + 16 * int64_t(lane);
+            const bool whole = mine && q >= int64_t(ua) && q + 16 <= int64_t(ub);
+            // nontemporal: the output is not read back here, and keeping it
+            // out of the L2's way leaves that to the dictionary (0.85 against
+            // 0.56 ms per GiB)
+            // (the offset passed through an empty asm statement: the store
+            // is not duplicated into branches on whether the lane writes)
+            uint32_t off = whole ? uint32_t(q) : 0x7FFFFFF0u;
+            asm volatile("" : "+v"(off));
+            __builtin_amdgcn_raw_buffer_store_b128(v, rs_out, int(off), 0, kNonTemporal);
+            // the block shared with the unit before (at this unit's start):
+            // its bytes from ua on
+            const bool part = mine && !whole && q + 16 > int64_t(ua) && q < int64_t(ub);
+            if (any(part) && part)
+                for (uint32_t k = 0; k < 16; k++)
+                    if (q + k >= int64_t(ua) && q + k < int64_t(ub))
+                        gp(out)[q + k] = uint8_t(v[k >> 2] >> (8 * (k & 3u)));
+        }
+        uint32_t done = nl;  // lines written
+        if (g < t.b && (last || fill >= 9 * 128)) {
+            // the unit's end (everything, the last block cut at ub), or a
+            // group of more than a kilobyte: the rest of the whole lines
+            const uint32_t nb = last ? (fill + 15) >> 4 : (fill >> 7) << 3;
+            for (uint32_t b = 8 * nl + lane; b < nb; b += 64) {
                 const int64_t q = sbase + 16 * int64_t(b);
                 const u32x4 v = *reinterpret_cast<const u32x4 *>(buf + 4 * b);
                 *reinterpret_cast<u32x4 *>(buf + 4 * b) = zero4;
                 if (q >= int64_t(ua) && q + 16 <= int64_t(ub)) {
-                    // nontemporal: the output is not read back here, and
-                    // keeping it out of the L2's way leaves that to the
-                    // dictionary (0.85 against 0.56 ms per GiB)
                     __builtin_nontemporal_store(v, gp(reinterpret_cast<u32x4 *>(out + q)));
                 } else {
                     for (uint32_t k = 0; k < 16; k++)
@@ -1523,27 +1575,100 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
                             gp(out)[q + k] = uint8_t(v[k >> 2] >> (8 * (k & 3u)));
                 }
             }
-            if (last) break;
-            // carry the unfinished block (its bytes from the next group are
-            // still to come) to the front
+            done = fill >> 7;
+        }
+        if (!last && done) {
+            // carry the unfinished line (fewer than 128 bytes; its bytes from
+            // the next group are still to come) to the front
             wave_fence();
-            uint32_t carry = 0;
-            if (lane < 4) {
-                carry = buf[4 * nblk + lane];
-                buf[4 * nblk + lane] = 0;
+            u32x4 c = zero4;
+            if (lane < 8) {
+                c = *reinterpret_cast<const u32x4 *>(buf + 4 * (8 * done + lane));
+                *reinterpret_cast<u32x4 *>(buf + 4 * (8 * done + lane)) = zero4;
             }
             wave_fence();
-            if (lane < 4) buf[lane] = carry;
+            if (lane < 8) *reinterpret_cast<u32x4 *>(buf + 4 * lane) = c;
             wave_fence();
-            sbase += 16 * int64_t(nblk);
+            sbase += 128 * int64_t(done);
         }
-        cur = nxt;
+    };
+    // One group.  Run ahead: take group g + 2's entries from its index
+    // dwords (wc, loaded two groups earlier) and load them (into en), take
+    // group g + 1's positions from its entries (ec, loaded one group earlier)
+    // and load its bytes (into nxt), load group g + 4's index dwords (into
+    // wc); then finish group g.  The index dwords come from the chunk or the
+    // scratch area, often from HBM, hence the longer run ahead; entries and
+    // entry bytes are the dictionary's and stay in the caches.  A wave's
+    // loads complete in issue order, so the index dwords go last: waiting
+    // for the entries and bytes needed one group later does not wait for
+    // them.
+    auto step = [&](uint32_t g, uint32_t &wc, Entry &en, const Entry &ec, const Grp &cur, Grp &nxt) {
+        en.e = entry_of(g + 2, wc, en.bad);
+        dead |= !prepare(g + 1, ec.e, ec.bad, nxt, cur.end);
+        wc = words_of(g + 4);
+        finish(g, cur);
+    };
+    Grp ga, gb;
+    Entry ea, eb;
+    if constexpr (PAIR) {
+        // the loads in the order that leaves, at the loop's first waits, as
+        // many later loads as the loop itself does (the index dwords of
+        // groups t.a + 2 and t.a + 3 around the entries and bytes)
+        const uint32_t w0 = words_of(t.a), w1 = words_of(t.a + 1);
+        uint32_t wa = words_of(t.a + 2);
+        ea.e = entry_of(t.a, w0, ea.bad);
+        eb.e = entry_of(t.a + 1, w1, eb.bad);
+        asm volatile("" ::: "memory");  // (keeps the entry loads before the ones below)
+        if (!prepare(t.a, ea.e, ea.bad, ga, ua)) {
+            flag(A.err, ERR_CORRUPT);
+            return;
+        }
+        uint32_t wb = words_of(t.a + 3);
+        {
+            // a store that writes nothing, in the place of a group's store
+            uint32_t off = 0x7FFFFFF0u;
+            asm volatile("" : "+v"(off));
+            __builtin_amdgcn_raw_buffer_store_b128(zero4, rs_out, int(off), 0, kNonTemporal);
+        }
+        // two groups per iteration, the run-ahead state alternating between
+        // the a and b copies, so that no copy waits for the loads in flight
+        // into the next group's state; an odd unit ends with a group past it
+        for (uint32_t g = t.a;; g += 2) {
+            step(g, wa, ea, eb, ga, gb);
+            step(g + 1, wb, eb, ea, gb, ga);
+            if (g + 2 >= t.b) break;
+        }
+        if (dead) flag(A.err, ERR_CORRUPT);
+    } else {
+        // one copy of each run-ahead value, the index dwords one group ahead
+        // of their use; a corrupt group ends the unit at once
+        uint32_t wa = words_of(t.a);
+        ea.e = entry_of(t.a, wa, ea.bad);
+        wa = words_of(t.a + 1);
+        eb.e = entry_of(t.a + 1, wa, eb.bad);
+        wa = words_of(t.a + 2);
+        if (!prepare(t.a, ea.e, ea.bad, ga, ua)) {
+            flag(A.err, ERR_CORRUPT);
+            return;
+        }
+        for (uint32_t g = t.a;; g++) {
+            if (!prepare(g + 1, eb.e, eb.bad, gb, ga.end)) {
+                flag(A.err, ERR_CORRUPT);
+                return;
+            }
+            eb.e = entry_of(g + 2, wa, eb.bad);
+            wa = words_of(g + 3);
+            finish(g, ga);
+            if (g + 1 >= t.b) break;
+            ga = gb;
+        }
     }
 }
 
+template <bool PAIR>
 ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, uint32_t *buf) {
-    if (ck.codec == C_SDICT_COL || ck.codec == C_SDICT_COL_ANS) unit_sdict_t<true>(A, t, ck, buf);
-    else unit_sdict_t<false>(A, t, ck, buf);
+    if (ck.codec == C_SDICT_COL || ck.codec == C_SDICT_COL_ANS) unit_sdict_t<true, PAIR>(A, t, ck, buf);
+    else unit_sdict_t<false, PAIR>(A, t, ck, buf);
 }
 
 // ===================================================================== ANS
@@ -1715,7 +1840,7 @@ ZF_DEV void unit_plain(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck) 
 // ============================================================== dispatch
 // UNR: FP lane-steps of loads kept in flight; 0 = runtime-width FP path.
 template <uint32_t UNR>
-// lz_row: this wave's LDS scratch (max(kAnsLdsWords, kSdBufWords) dwords):
+// lz_row: this wave's LDS scratch (max(kAnsLdsWords, kSdBufAlloc) dwords):
 // the LZ77 row, the ANS model and staging, the String-dictionary buffer or
 // the RLE window slots.
 ZF_DEV void run_unit(const LaunchArgs &A, uint32_t kind, uint32_t u, uint32_t *lz_row) {
@@ -1744,7 +1869,7 @@ ZF_DEV void run_unit(const LaunchArgs &A, uint32_t kind, uint32_t u, uint32_t *l
         else unit_tree<uint64_t>(A, t, ck, lz_row);
         break;
     case K_LZ: unit_lz<4>(A, ck, lz_row); break;
-    case K_SDICT: unit_sdict(A, t, ck, lz_row); break;
+    case K_SDICT: unit_sdict<false>(A, t, ck, lz_row); break;
     case K_ANS: unit_ans(A, ck, lz_row); break;
     }
 }
