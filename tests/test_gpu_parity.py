@@ -652,6 +652,22 @@ def test_device_detects_corrupt_streams():
     t = b.copy()
     t[at + 48:at + 52] = np.frombuffer(np.uint32(3 << 24).tobytes(), np.uint8)  # "the " -> "the"
     _expect_corrupt([zf.Column.from_bytes(t)])
+    # String-dictionary, per chunk and over a column dictionary: an index
+    # past the entries in a group after the first (the wave stops staging
+    # there and runs on to the unit's end), at an even and an odd group
+    x = np.frombuffer(b"the cat. the dog ran the cat " * 200, np.uint8)
+    for codec, w_at, co_at, ne_of in ((zo.SDICT_BP, 8, 24, lambda b, at: int(b[at + 4:at + 8].view(np.uint32)[0])),
+                                      (zo.SDICT_COL, 4, 12, lambda b, at: zo.inspect(b)["dict_count"])):
+        b = zo.encode(x, codec).copy()
+        at = zo.chunks(b)[0]["comp_off"]
+        w = int(b[at + w_at:at + w_at + 4].view(np.uint32)[0])
+        co = int(b[at + co_at:at + co_at + 4].view(np.uint32)[0])
+        assert (1 << w) - 1 >= ne_of(b, at) and int(b[at:at + 4].view(np.uint32)[0]) > 64 * 8
+        for tok in (64 * 5 + 7, 64 * 6 + 40):
+            t = b.copy()
+            k = at + co + 4 * ((tok * w) // 32)
+            t[k:k + 4] = 0xFF                                 # every index in that dword past the entries
+            _expect_corrupt([zf.Column.from_bytes(t)])
     # String-dictionary | BP | ANS: an ANS stage that decodes to indices past
     # the entries (the host checks the ANS stream, not what it decodes to)
     x = np.frombuffer(b"the cat. the dog ran the cat " * 10, np.uint8)
