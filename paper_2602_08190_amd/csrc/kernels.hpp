@@ -1344,6 +1344,10 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
         __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(codes), 0, int(4 * ncw), 0x00020000);
     const __amdgpu_buffer_rsrc_t rs_ents =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(ebase), 0, int(4 * ne), 0x00020000);
+    // COL: the plan's 16-byte records of the column dictionary's entries
+    const __amdgpu_buffer_rsrc_t rs_fat = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint8_t *>(COL ? uniform_ptr(A.fat + ck.fat_off) : ebase), 0, COL ? int(kFatBytes * ne) : 0,
+        0x00020000);
     const __amdgpu_buffer_rsrc_t rs_gofs =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(s + go), 0, int(4 * ng), 0x00020000);
     // the entry bytes, shifted by 4 so that the dword before a token is at a
@@ -1394,19 +1398,33 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
     // token's w bits start at bit lane * w of them; bad: index past the
     // entries.  (The second dword is read from lane k + 1 < 2w whenever the
     // token reaches into it; lane 63's token at w = 32 lies in dword 63.)
-    auto entry_of = [&](uint32_t g, uint32_t win, bool &bad) -> uint32_t {
+    // (COL: the entry's 16-byte record from the plan's copy of the column
+    // dictionary, one load for a token of up to 15 bytes and its length)
+    struct Entry {
+        u32x4 f;        // COL: the record; else f.x = the entry {offset, length}
+        uint32_t code;  // the entry index
+        bool bad;
+    };
+    auto entry_of = [&](uint32_t g, uint32_t win) -> Entry {
         const uint32_t i = 64 * g + lane;
         const bool act = g < t.b && i < nt;
         const uint32_t bit = lane * w, k = bit >> 5;
         const uint32_t w0 = uint32_t(__builtin_amdgcn_ds_bpermute(int(4 * k), int(win)));
         const uint32_t w1 = uint32_t(__builtin_amdgcn_ds_bpermute(int(4 * k + 4), int(win)));
-        const uint32_t code = w ? uint32_t((uint64_t(w0) | (uint64_t(w1) << 32)) >> (bit & 31u)) & mask32(w) : 0u;
-        bad = act && code >= ne;
-        return __builtin_amdgcn_raw_buffer_load_b32(rs_ents, int((act && !bad) ? 4 * code : 0x7FFFFFF0u), 0, 0);
+        Entry en;
+        en.code = w ? uint32_t((uint64_t(w0) | (uint64_t(w1) << 32)) >> (bit & 31u)) & mask32(w) : 0u;
+        en.bad = act && en.code >= ne;
+        const bool use = act && !en.bad;
+        if constexpr (COL) {
+            en.f = __builtin_amdgcn_raw_buffer_load_b128(rs_fat, int(use ? kFatBytes * en.code : 0x7FFFFFF0u), 0, 0);
+        } else {
+            en.f.x = __builtin_amdgcn_raw_buffer_load_b32(rs_ents, int(use ? 4 * en.code : 0x7FFFFFF0u), 0, 0);
+        }
+        return en;
     };
     struct Grp {
-        uint32_t len, eoff, P, end;  // token length and entry offset, token start, group end
-        uint32_t v0, v1, v2, v3;     // the first four dwords of the token's bytes
+        uint32_t len, eoff, P, end;  // token length and entry offset (COL: the entry index), token start, group end
+        uint32_t v0, v1, v2, v3;     // the first four dwords of the token's bytes (COL: of its record)
         bool live;                   // a checked group of the unit, to be staged
     };
     // A corrupt group ends the wave's work: it and every later group are not
@@ -1418,10 +1436,16 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
     // group and the groups after it are not live: they take the previous
     // group's end (prev_end) as their position and end.  Returns false for a
     // corrupt group of the unit.
-    auto prepare = [&](uint32_t g, uint32_t e, bool bad_code, Grp &G, uint32_t prev_end) -> bool {
+    auto prepare = [&](uint32_t g, const Entry &en, Grp &G, uint32_t prev_end) -> bool {
         const bool act = g < t.b && 64 * g + lane < nt;
-        G.len = e >> 24;
-        G.eoff = e & 0xFFFFFFu;
+        const bool bad_code = en.bad;
+        if constexpr (COL) {
+            G.len = en.f.w >> 24;
+            G.eoff = en.code;
+        } else {
+            G.len = en.f.x >> 24;
+            G.eoff = en.f.x & 0xFFFFFFu;
+        }
         const uint32_t incl = scan_add32(G.len), total = rl32(incl, 63);
         const uint32_t pos = goff(g);
         G.end = goff(g + 1);
@@ -1431,13 +1455,13 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
         // that no branch stands between them and their use
         const uint32_t m = (oa + G.P) & 3u, nd = act ? (m + G.len + 3) >> 2 : 0u;
         if constexpr (COL) {
-            // the entry's first 16 bytes, 4-aligned, in one load; the dwords
-            // are shifted into the buffer's alignment when they are ORed
-            const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(rs_ent, int(act ? G.eoff + 4 : 0x7FFFFFF0u), 0, 0);
-            G.v0 = q.x;
-            G.v1 = q.y;
-            G.v2 = q.z;
-            G.v3 = q.w;
+            // the record's token bytes (its last byte, the length, cleared);
+            // the dwords are shifted into the buffer's alignment when they
+            // are ORed
+            G.v0 = en.f.x;
+            G.v1 = en.f.y;
+            G.v2 = en.f.z;
+            G.v3 = en.f.w & 0x00FFFFFFu;
         } else {
             const uint32_t at = G.eoff - m + 4;
             G.v0 = __builtin_amdgcn_raw_buffer_load_b32(rs_ent, int(0 < nd ? at : 0x7FFFFFF0u), 0, 0);
@@ -1448,7 +1472,8 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
         // an entry's bytes (and the dword read at each) lie in the entry bytes;
         // the group's tokens fill exactly its output range
         // (bitwise, not short-circuit: no branch per condition)
-        const bool bad_lane = bad_code | (act & (((G.len - 1u) >= kSdMaxToken) | (G.eoff + G.len > nb)));
+        const bool bad_lane =
+            bad_code | (act & (((G.len - 1u) >= kSdMaxToken) | (!COL && G.eoff + G.len > nb)));
         const bool bad_grp = (uint64_t(pos) + total != G.end) | (G.end > ub) | (pos < ua);
         const bool ok = !((any(bad_lane) | bad_grp) & (g < t.b));
         G.live = ok & !dead & (g < t.b);
@@ -1476,10 +1501,10 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
         uint32_t *at = buf + d0;
         uint32_t v0, v1, v2, v3;
         if constexpr (COL) {
-            // buffer dword j = entry bytes [4j - m, 4j - m + 4): bytes 4 - m ..
-            // 7 - m of the aligned entry dwords j - 1 (low) and j (high), one
-            // byte permute each (the three bytes before an entry and after it
-            // are zero, so only dwords past the token need clearing)
+            // buffer dword j = token bytes [4j - m, 4j - m + 4): bytes 4 - m ..
+            // 7 - m of the record's dwords j - 1 (low) and j (high), one byte
+            // permute each (the record is zero past the token, so only
+            // dwords past the token need clearing)
             const uint32_t sel = 0x07060504u - 0x01010101u * m;
             v0 = 0 < nd ? __builtin_amdgcn_perm(G.v0, 0u, sel) : 0u;
             v1 = 1 < nd ? __builtin_amdgcn_perm(G.v1, G.v0, sel) : 0u;
@@ -1489,13 +1514,30 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
             __hip_atomic_fetch_or(at + 1, v1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             __hip_atomic_fetch_or(at + 2, v2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             __hip_atomic_fetch_or(at + 3, v3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            uint32_t prev = G.v3;
-            for (uint32_t j = 4; any(j < nd); j++) {  // tokens of more than 13 bytes
-                const uint32_t e = __builtin_amdgcn_raw_buffer_load_b32(rs_ent, int(j < nd ? G.eoff + 4 * j + 4
-                                                                                         : 0x7FFFFFF0u), 0, 0);
-                const uint32_t v = __builtin_amdgcn_perm(e, prev, sel);
-                prev = e;
-                if (j < nd) __hip_atomic_fetch_or(at + j, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            // a token of 14 or 15 bytes reaching a fifth dword: the record's rest
+            const bool longer = act && G.len > kFatInline;
+            const bool fifth = act && !longer && nd > 4;
+            if (any(fifth))
+                __hip_atomic_fetch_or(at + 4, fifth ? __builtin_amdgcn_perm(0u, G.v3, sel) : 0u, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+            // a token of more than 15 bytes: dword 3 on from the dictionary's
+            // entry bytes (the record's dword 2 is the entry's dword 2), after
+            // checking the entry against the record and the entry bytes
+            if (any(longer)) {
+                const uint32_t e = __builtin_amdgcn_raw_buffer_load_b32(rs_ents, int(longer ? 4 * G.eoff : 0x7FFFFFF0u),
+                                                                        0, 0);
+                const uint32_t off = e & 0xFFFFFFu;
+                const bool bad = longer && ((e >> 24) != G.len || off + G.len > nb);
+                if (any(bad)) flag(A.err, ERR_CORRUPT);
+                const bool go = longer && !bad;
+                uint32_t prev = G.v2;
+                for (uint32_t j = 3; any(go && j < nd); j++) {
+                    const uint32_t cur = __builtin_amdgcn_raw_buffer_load_b32(
+                        rs_ent, int(go && j < nd ? off + 4 * j + 4 : 0x7FFFFFF0u), 0, 0);
+                    const uint32_t v = __builtin_amdgcn_perm(cur, prev, sel);
+                    prev = cur;
+                    if (go && j < nd) __hip_atomic_fetch_or(at + j, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
             }
         } else {
             // (a dword past nd was read out of range as 0)
@@ -1516,10 +1558,6 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
         }
     };
 
-    struct Entry {
-        uint32_t e;
-        bool bad;
-    };
     // OR group g (cur, whose bytes were loaded one group earlier) into the
     // buffer, and write out the whole blocks when enough are done and
     // everything at the unit's end (a group past the unit writes nothing).
@@ -1603,8 +1641,8 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
     // for the entries and bytes needed one group later does not wait for
     // them.
     auto step = [&](uint32_t g, uint32_t &wc, Entry &en, const Entry &ec, const Grp &cur, Grp &nxt) {
-        en.e = entry_of(g + 2, wc, en.bad);
-        dead |= !prepare(g + 1, ec.e, ec.bad, nxt, cur.end);
+        en = entry_of(g + 2, wc);
+        dead |= !prepare(g + 1, ec, nxt, cur.end);
         wc = words_of(g + 4);
         finish(g, cur);
     };
@@ -1616,10 +1654,10 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
         // groups t.a + 2 and t.a + 3 around the entries and bytes)
         const uint32_t w0 = words_of(t.a), w1 = words_of(t.a + 1);
         uint32_t wa = words_of(t.a + 2);
-        ea.e = entry_of(t.a, w0, ea.bad);
-        eb.e = entry_of(t.a + 1, w1, eb.bad);
+        ea = entry_of(t.a, w0);
+        eb = entry_of(t.a + 1, w1);
         asm volatile("" ::: "memory");  // (keeps the entry loads before the ones below)
-        if (!prepare(t.a, ea.e, ea.bad, ga, ua)) {
+        if (!prepare(t.a, ea, ga, ua)) {
             flag(A.err, ERR_CORRUPT);
             return;
         }
@@ -1643,20 +1681,20 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
         // one copy of each run-ahead value, the index dwords one group ahead
         // of their use; a corrupt group ends the unit at once
         uint32_t wa = words_of(t.a);
-        ea.e = entry_of(t.a, wa, ea.bad);
+        ea = entry_of(t.a, wa);
         wa = words_of(t.a + 1);
-        eb.e = entry_of(t.a + 1, wa, eb.bad);
+        eb = entry_of(t.a + 1, wa);
         wa = words_of(t.a + 2);
-        if (!prepare(t.a, ea.e, ea.bad, ga, ua)) {
+        if (!prepare(t.a, ea, ga, ua)) {
             flag(A.err, ERR_CORRUPT);
             return;
         }
         for (uint32_t g = t.a;; g++) {
-            if (!prepare(g + 1, eb.e, eb.bad, gb, ga.end)) {
+            if (!prepare(g + 1, eb, gb, ga.end)) {
                 flag(A.err, ERR_CORRUPT);
                 return;
             }
-            eb.e = entry_of(g + 2, wa, eb.bad);
+            eb = entry_of(g + 2, wa);
             wa = words_of(g + 3);
             finish(g, ga);
             if (g + 1 >= t.b) break;

@@ -34,8 +34,26 @@ static void gp_tiles(std::vector<Tile> &T, uint32_t idx, uint32_t ng, uint32_t n
     }
 }
 
+// The 16-byte entry records of a column token dictionary (host validated:
+// every entry of 1..64 bytes lies inside the entry bytes): an entry's first
+// 15 bytes, zero past its length, then its length, so that one aligned
+// 16-byte read gives a token of up to 15 bytes and its length.
+static void fat_records(const zf_column &col, std::vector<uint8_t> &out) {
+    const uint8_t *d = col.buf.p + col.view.dict_off;
+    const uint32_t ne = col.view.dict_count;
+    const uint8_t *bytes = d + 16 + 4ull * ne;
+    const size_t at = out.size();
+    out.resize(at + uint64_t(kFatBytes) * ne, 0);
+    for (uint32_t k = 0; k < ne; k++) {
+        const uint32_t e = rd32(d + 16 + 4ull * k), len = e >> 24, off = e & 0xFFFFFFu;
+        uint8_t *r = out.data() + at + uint64_t(kFatBytes) * k;
+        std::memcpy(r, bytes + off, std::min(len, kFatInline));
+        r[kFatInline] = uint8_t(len);
+    }
+}
+
 static void add_chunk(WorkTables &w, const zf_column &col, uint32_t ci, uint32_t col_idx,
-                      uint64_t comp_off, uint64_t dict_off, const TileShape &ts) {
+                      uint64_t comp_off, uint64_t dict_off, const TileShape &ts, uint64_t fat_off = 0) {
     const ChunkInfo &c = col.view.chunks[ci];
     ChunkDesc d{};
     d.comp_off = comp_off;
@@ -49,6 +67,7 @@ static void add_chunk(WorkTables &w, const zf_column &col, uint32_t ci, uint32_t
     d.codec = c.codec;
     d.dtype = uint8_t(col.view.dtype);
     const bool col_dict = c.codec == C_SDICT_COL || c.codec == C_SDICT_COL_ANS;
+    d.fat_off = col_dict ? fat_off : 0;
     if (c.codec == C_SDICT_ANS || c.codec == C_SDICT_COL_ANS) {
         // first stage: ANS-decode the packed entry indices into the scratch
         // area; the String-dictionary stage reads them from there
@@ -231,6 +250,15 @@ void build_plan(zf_plan_t *P, const zf_column *const *cols, uint32_t n_cols, int
     P->lz_blk = ts.unit[K_LZ];
     P->persistent_waves = o.persistent ? P->cu_count * ts.wpcu : 0;
 
+    // ---- the entry records of every column token dictionary
+    std::vector<uint8_t> fat;
+    std::vector<uint64_t> fat_at(n_cols, 0);
+    for (uint32_t c = 0; c < n_cols; c++)
+        if (cols[c]->view.dtype == D_BYTES && cols[c]->view.dict_count) {
+            fat_at[c] = fat.size();
+            fat_records(*cols[c], fat);
+        }
+
     // ---- image layout and its tables
     WorkTables image;
     P->image_off.resize(n_cols);
@@ -244,7 +272,7 @@ void build_plan(zf_plan_t *P, const zf_column *const *cols, uint32_t n_cols, int
         const zf_column &col = *cols[c];
         for (uint32_t i = 0; i < col.view.n_chunks; i++)
             add_chunk(image, col, i, c, P->image_off[c] + col.view.chunks[i].comp_off,
-                      P->image_off[c] + col.view.dict_off, ts);
+                      P->image_off[c] + col.view.dict_off, ts, fat_at[c]);
     }
 
     // ---- staged mode: dictionaries, then batches of whole chunks
@@ -296,7 +324,7 @@ void build_plan(zf_plan_t *P, const zf_column *const *cols, uint32_t n_cols, int
             cur.copies.back().len = ch.comp_off + ch.comp_len - range_src;
             cur.slot_used = dst + ch.comp_len;
             range_next_chunk = i + 1;
-            add_chunk(cur.w, col, i, c, dst, dict_at[c], ts);
+            add_chunk(cur.w, col, i, c, dst, dict_at[c], ts, fat_at[c]);
         }
     }
     close();
@@ -341,6 +369,10 @@ void build_plan(zf_plan_t *P, const zf_column *const *cols, uint32_t n_cols, int
         for (auto &sp : P->d_slots) ZF_HIP(hipMalloc(&sp, slot));
     }
     if (dict_total) ZF_HIP(hipMalloc(&P->d_dict, dict_total));
+    if (!fat.empty()) {
+        ZF_HIP(hipMalloc(&P->d_fat, fat.size()));
+        ZF_HIP(hipMemcpy(P->d_fat, fat.data(), fat.size(), hipMemcpyHostToDevice));
+    }
     P->scratch_bytes = image.scratch_bytes;
     for (auto &b : P->batches) P->scratch_bytes = std::max(P->scratch_bytes, b.w.scratch_bytes);
     if (P->scratch_bytes) ZF_HIP(hipMalloc(&P->d_scratch, P->scratch_bytes));
@@ -349,6 +381,7 @@ void build_plan(zf_plan_t *P, const zf_column *const *cols, uint32_t n_cols, int
         A.out_tab = P->d_out_tab;
         A.err = P->d_err;
         A.counter = P->d_err + 64;
+        A.fat = P->d_fat;
     };
     fill(P->image_args);
     for (uint32_t k = 0; k < P->batches.size(); k++) {
@@ -433,6 +466,7 @@ void release_plan(zf_plan_t *P) {
     if (p.d_tables) (void)hipFree(p.d_tables);
     if (p.d_out_tab) (void)hipFree(p.d_out_tab);
     if (p.d_scratch) (void)hipFree(p.d_scratch);
+    if (p.d_fat) (void)hipFree(p.d_fat);
     if (p.d_err) (void)hipFree(p.d_err);
     if (prev >= 0 && prev != device) (void)hipSetDevice(prev);
 }

@@ -68,6 +68,7 @@ struct zf_plan {
     uint64_t slot_bytes = 0;
     uint8_t *d_dict = nullptr;
     uint8_t *d_scratch = nullptr;  // shared by every launch (they run in stream order)
+    uint8_t *d_fat = nullptr;      // 16-byte entry records of the column token dictionaries
     uint64_t scratch_bytes = 0;
     uint64_t dict_bytes = 0;
     std::vector<zf::CopyOp> dict_copies;

@@ -62,8 +62,14 @@ struct ChunkDesc {
     uint8_t dtype;
     uint64_t aux_off;     // SDICT_ANS, SDICT_COL_ANS: offset of the decoded entry indices in the scratch area
     uint64_t dict_bytes;  // size of the column's dictionary area
+    uint64_t fat_off;     // SDICT_COL, SDICT_COL_ANS: offset of the column's entry table in LaunchArgs::fat
 };
-static_assert(sizeof(ChunkDesc) == 56, "ChunkDesc layout");
+static_assert(sizeof(ChunkDesc) == 64, "ChunkDesc layout");
+
+// The plan's copy of a column token dictionary, one 16-byte record per
+// entry: the entry's first 15 bytes (zero past its length), then its length.
+constexpr uint32_t kFatBytes = 16;
+constexpr uint32_t kFatInline = 15;
 
 // One unit of work for one wavefront.
 //   FOR / DICT / F2I: a = first block, b = number of blocks
@@ -88,6 +94,7 @@ struct LaunchArgs {
     const Tile *tiles;            // tiles grouped by kind
     uint32_t *err;                // device error word
     uint32_t *counter;            // persistent-kernel queue heads: 2 launches x 8 XCDs, 32 dwords apart
+    const uint8_t *fat;           // the plan's 16-byte entry records of the column token dictionaries
     uint32_t kind_begin[K_COUNT + 1];
     uint32_t two_stage;           // some units read the scratch area that earlier kinds write
 };

@@ -279,6 +279,28 @@ def test_sdict_col_text_bytes_and_tiles(sd_bytes):
     check(cols, decode_image(cols, persistent=True, tiles={"SDICT": dict(unit=sd_bytes, waves_per_block=8)}), xs)
 
 
+@pytest.mark.parametrize("codec", ["SDICT_COL", "SDICT_COL_ANS"])
+def test_sdict_col_every_token_length(codec):
+    """Tokens of every length from 1 to 64 bytes at every output alignment,
+    over a column dictionary: the kernel reads a token of up to 15 bytes
+    from the plan's 16-byte entry records (the 14- and 15-byte ones reaching
+    a fifth output dword at some alignments) and the longer ones from the
+    dictionary's entry bytes; per-kind and persistent launches."""
+    log("sdict_col lengths", codec)
+    r = g.rng(67)
+    words = [bytes(r.integers(ord("a"), ord("z") + 1, size=n).astype(np.uint8)) for n in range(1, 64)]
+    parts = []
+    for i in r.integers(0, len(words) + 1, size=30000):
+        parts.append(b" " if i == len(words) else words[i] + b" ")   # tokens end at spaces: 1..64 bytes
+    x = np.frombuffer(b"".join(parts), np.uint8)
+    c = getattr(zf, codec)
+    cols = [zf.Column.compress(x, c, chunk_elems=[len(x) // 3, len(x) - len(x) // 3]),
+            zf.Column.compress(x[7:], c)]
+    xs = [x, x[7:]]
+    check(cols, decode_image(cols, tiles={"SDICT": dict(unit=4096)}), xs)
+    check(cols, decode_image(cols, persistent=True), xs)
+
+
 @pytest.mark.parametrize("mode", ["graphs", "staged"])
 def test_sdict_col_ans_two_stage_decode(mode):
     """String-dictionary over a column dictionary | BP | ANS, mixed with
