@@ -305,7 +305,8 @@ ZF_DEV uint64_t yfield64(const Win &v, uint32_t sh) {
 // any is used, so each wave keeps UNR x 1 KiB of output's loads in flight.
 // F2I: the 64-bit values are Float2Int integers, written as the float64
 // (double)int64(value) / div.
-template <int ES, bool DICT, uint32_t UNR, uint32_t W, bool F2I = false>
+// LDS: the dictionary was copied into this wave's LDS (dict points there).
+template <int ES, bool DICT, uint32_t UNR, uint32_t W, bool F2I = false, bool LDS = false>
 ZF_DEV void fp_block(const uint32_t *words, uint64_t nwords, uint64_t ref, uint32_t nv,
                      uint8_t *ob, bool vec, const uint8_t *dict, uint32_t dict_count, bool &bad,
                      double div = 1.0) {
@@ -332,7 +333,13 @@ ZF_DEV void fp_block(const uint32_t *words, uint64_t nwords, uint64_t ref, uint3
                 uint32_t v[4];
 #pragma unroll
                 for (uint32_t i = 0; i < 4; i++) {
-                    if constexpr (DICT) {
+                    if constexpr (DICT && LDS) {
+                        const uint32_t code = uint32_t(ref) + f[i];
+                        const bool in = v0 + i < nv, ok = code < dict_count;
+                        bad |= in && !ok;
+                        const uint32_t x = *reinterpret_cast<const uint32_t *>(dict + 4 * (ok ? code : 0u));
+                        v[i] = (in && ok) ? x : 0u;
+                    } else if constexpr (DICT) {
                         const uint32_t code = uint32_t(ref) + f[i];
                         const bool in = v0 + i < nv, ok = code < dict_count;
                         bad |= in && !ok;
@@ -357,7 +364,12 @@ ZF_DEV void fp_block(const uint32_t *words, uint64_t nwords, uint64_t ref, uint3
                         const uint32_t code = uint32_t(ref) + f[i];
                         const bool in = v0 + i < nv, ok = code < dict_count;
                         bad |= in && !ok;
-                        v[i] = (in && ok) ? *reinterpret_cast<const ZF_GLOBAL uint64_t *>(gd + 8ull * code) : 0ull;
+                        if constexpr (LDS) {
+                            const uint64_t x = *reinterpret_cast<const uint64_t *>(dict + 8 * (ok ? code : 0u));
+                            v[i] = (in && ok) ? x : 0ull;
+                        } else {
+                            v[i] = (in && ok) ? *reinterpret_cast<const ZF_GLOBAL uint64_t *>(gd + 8ull * code) : 0ull;
+                        }
                     }
                 } else {
                     v[0] = ref + yfield64<W, 0>(wv[u], sh);
@@ -383,7 +395,12 @@ ZF_DEV void fp_block(const uint32_t *words, uint64_t nwords, uint64_t ref, uint3
                 const bool ok = code < dict_count;
                 bad |= !ok;
                 u32x4 e = {0, 0, 0, 0};
-                if (ok) e = *reinterpret_cast<const ZF_GLOBAL u32x4 *>(gd + 16ull * code);
+                if constexpr (LDS) {
+                    const u32x4 x = *reinterpret_cast<const u32x4 *>(dict + 16 * (ok ? code : 0u));
+                    e = ok ? x : e;
+                } else if (ok) {
+                    e = *reinterpret_cast<const ZF_GLOBAL u32x4 *>(gd + 16ull * code);
+                }
                 if (vec) {
                     st16_nt(ob + 16ull * v0, e.x, e.y, e.z, e.w);
                 } else {
@@ -472,24 +489,29 @@ ZF_DEV void fp_block_rt(uint32_t w, const uint32_t *words, uint64_t nwords, uint
 }
 
 // Uniform dispatch on the block's width to its specialised decoder.
-template <int ES, bool DICT, uint32_t UNR, uint32_t W, uint32_t WMAX, bool F2I = false>
+template <int ES, bool DICT, uint32_t UNR, uint32_t W, uint32_t WMAX, bool F2I = false, bool LDS = false>
 ZF_DEV void fp_dispatch(uint32_t w, const uint32_t *words, uint64_t nwords, uint64_t ref, uint32_t nv,
                         uint8_t *ob, bool vec, const uint8_t *dict, uint32_t dict_count, bool &bad,
                         double div = 1.0) {
     if constexpr (W <= WMAX) {
         if (w == W)
-            fp_block<ES, DICT, UNR, W, F2I>(words, nwords, ref, nv, ob, vec, dict, dict_count, bad, div);
+            fp_block<ES, DICT, UNR, W, F2I, LDS>(words, nwords, ref, nv, ob, vec, dict, dict_count, bad, div);
         else
-            fp_dispatch<ES, DICT, UNR, W + 1, WMAX, F2I>(w, words, nwords, ref, nv, ob, vec, dict, dict_count,
-                                                       bad, div);
+            fp_dispatch<ES, DICT, UNR, W + 1, WMAX, F2I, LDS>(w, words, nwords, ref, nv, ob, vec, dict, dict_count,
+                                                            bad, div);
     }
 }
 
 // One wave decodes blocks [t.a, t.a + t.b) of a FOR_BP or DICT_BP chunk.
 // ES = output bytes per value; DICT = dictionary lookup fused after unpack.
 // MAXUNR = 0 selects the runtime-width variant.
+// A dictionary of up to kDictLds bytes is copied into the wave's LDS (lds,
+// when given) and gathered from there: gathers from global memory would
+// share the wave's in-order memory counter with its stores.
+constexpr uint32_t kDictLds = 4096;
+
 template <int ES, bool DICT, uint32_t MAXUNR>
-ZF_DEV void unit_fp(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck) {
+ZF_DEV void unit_fp(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, uint8_t *lds = nullptr) {
     constexpr uint32_t VPL = 16 / ES;                     // values per lane per step
     constexpr uint32_t STEPS = kForBlock / (64 * VPL);    // lane-steps per block
     constexpr uint32_t UNR = STEPS < MAXUNR ? STEPS : (MAXUNR ? MAXUNR : 1);
@@ -504,6 +526,20 @@ ZF_DEV void unit_fp(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck) {
         return;
     }
     bool bad = false;
+    bool in_lds = false;
+    if constexpr (DICT && MAXUNR > 0) {
+        if (lds && uint64_t(ck.dict_count) * ES <= kDictLds) {
+            // 16 bytes per lane, through a view of the dictionary (a read past
+            // it gives zeros)
+            const uint32_t nbytes = ck.dict_count * ES;
+            const __amdgpu_buffer_rsrc_t rs =
+                __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(uniform_ptr(dict)), 0, int(nbytes), 0x00020000);
+            for (uint32_t k = lane_id(); 16 * k < nbytes; k += 64)
+                *reinterpret_cast<u32x4 *>(lds + 16 * k) = __builtin_amdgcn_raw_buffer_load_b128(rs, int(16 * k), 0, 0);
+            wave_fence();
+            in_lds = true;
+        }
+    }
     for (uint32_t b = t.a; b < t.a + t.b; b++) {
         const uint8_t *d = s + 16ull * b;
         const uint64_t ref = ld64u(d);
@@ -520,6 +556,9 @@ ZF_DEV void unit_fp(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck) {
         const bool vec = (reinterpret_cast<uintptr_t>(ob) & 15u) == 0;
         if constexpr (MAXUNR == 0)
             fp_block_rt<ES, DICT>(first32(w), words, nwords, ref, nv, ob, vec, dict, ck.dict_count, bad);
+        else if (DICT && in_lds)
+            fp_dispatch<ES, DICT, UNR, 0, BITS, false, true>(first32(w), words, nwords, ref, nv, ob, vec, lds,
+                                                             ck.dict_count, bad);
         else
             fp_dispatch<ES, DICT, UNR, 0, BITS>(first32(w), words, nwords, ref, nv, ob, vec, dict,
                                                 ck.dict_count, bad);
@@ -1941,12 +1980,13 @@ __global__ __launch_bounds__(1024) void k_decode_kind(LaunchArgs A) {
         unit_fp<8, false, 8>(A, t, ck);
     } else if constexpr (KIND == K_F2I) {
         unit_f2i<8>(A, t, ck);
-    } else if constexpr (KIND == K_DICT32) {
-        unit_fp<4, true, 8>(A, t, ck);
-    } else if constexpr (KIND == K_DICT64) {
-        unit_fp<8, true, 8>(A, t, ck);
-    } else if constexpr (KIND == K_DICT128) {
-        unit_fp<16, true, 8>(A, t, ck);
+    } else if constexpr (KIND == K_DICT32 || KIND == K_DICT64 || KIND == K_DICT128) {
+        // each wave's dictionary copy, kDictLds bytes of dynamic shared memory
+        extern __shared__ __attribute__((aligned(16))) uint8_t dict_lds[];
+        uint8_t *lds = dict_lds + (threadIdx.x / 64) * kDictLds;
+        if constexpr (KIND == K_DICT32) unit_fp<4, true, 8>(A, t, ck, lds);
+        else if constexpr (KIND == K_DICT64) unit_fp<8, true, 8>(A, t, ck, lds);
+        else unit_fp<16, true, 8>(A, t, ck, lds);
     } else if constexpr (KIND == K_RLE32) {
         __shared__ uint32_t rle_slots[16][256];
         if (ck.codec == C_DSTRIDE_BP) unit_rle<uint32_t, true>(A, t, ck, rle_slots[threadIdx.x / 64]);
@@ -1994,8 +2034,8 @@ ZF_KIND_LAUNCHERS(ZF_DECLARE_LAUNCHER)
     void NAME(const LaunchArgs &A, uint32_t waves, hipStream_t st) {                               \
         const uint32_t n = A.kind_begin[KIND + 1] - A.kind_begin[KIND];                            \
         if (!n) return;                                                                            \
-        hipLaunchKernelGGL(k_decode_kind<KIND>, dim3((n + waves - 1) / waves), dim3(64 * waves), 0, \
-                           st, A);                                                                 \
+        const uint32_t lds = (KIND == K_DICT32 || KIND == K_DICT64 || KIND == K_DICT128) ? waves * kDictLds : 0; \
+        hipLaunchKernelGGL(k_decode_kind<KIND>, dim3((n + waves - 1) / waves), dim3(64 * waves), lds, st, A); \
     }
 
 }  // namespace zf
