@@ -203,7 +203,7 @@ def host_description(threads):
 
 
 def gpu_description(torch):
-    import subprocess
+    import glob
     props = torch.cuda.get_device_properties(0)
     d = {"name": torch.cuda.get_device_name(0) or getattr(props, "gcnArchName", ""),
          "arch": getattr(props, "gcnArchName", ""), "compute_units": props.multi_processor_count}
@@ -212,19 +212,19 @@ def gpu_description(torch):
     except OSError:
         pass
     d["torch"] = torch.__version__
-    try:
-        # the tool may print notices around its JSON; the text form is the fallback
-        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True, timeout=20)
-        out = r.stdout
-        try:
-            clocks = json.loads(out[out.index("{"):out.rindex("}") + 1])
-            card = next(iter(clocks.values()))
-            d["clocks"] = {k: v for k, v in card.items() if "clock" in k.lower()}
-        except ValueError:
-            r = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True, timeout=20)
-            d["clocks"] = [ln.strip() for ln in r.stdout.splitlines() if "clk" in ln.lower()][:8]
-    except Exception as e:  # the description is informational
-        d["clocks"] = f"unavailable ({type(e).__name__})"
+    # the current engine and memory clock levels from the driver's sysfs
+    # tables (the level in use is marked with '*'; no helper program is run)
+    clocks = {}
+    for dev in sorted(glob.glob("/sys/class/drm/card*/device")):
+        for name in ("pp_dpm_sclk", "pp_dpm_mclk"):
+            try:
+                lines = open(f"{dev}/{name}").read().splitlines()
+            except OSError:
+                continue
+            cur = [ln.split(":", 1)[1].strip(" *") for ln in lines if ln.rstrip().endswith("*")]
+            if cur:
+                clocks[f"{dev.split('/')[-2]} {name[7:]}"] = cur[0]
+    d["clocks"] = clocks or "unavailable (no readable clock table)"
     return d
 
 

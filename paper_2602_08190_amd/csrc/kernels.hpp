@@ -1307,11 +1307,13 @@ ZF_DEV void unit_lz(const LaunchArgs &A, const ChunkDesc &ck, uint32_t *row) {
 // buffer and 4 that only ever receive ORs of zero.
 constexpr uint32_t kSdBufAlloc = 1280;    // 5120 bytes: 32 one-wave workgroups fill a CU's LDS
 constexpr uint32_t kSdBufWords = kSdBufAlloc - 4;
-// Before a group the buffer holds < 128 bytes (the whole lines are written
-// out after each group); a group adds at most 64 tokens of kSdMaxToken bytes,
-// so every token position of a checked group lies in the buffer, and the
-// four dwords from a position's dword end at most 3 dwords past it.
-static_assert(128 + 64 * kSdMaxToken <= 4 * kSdBufWords, "String-dictionary buffer");
+// Before a group the buffer holds at most kSdHold bytes (the whole lines are
+// written out after each pair of groups, or sooner); a group adds at most 64
+// tokens of kSdMaxToken bytes, so every token position of a checked group
+// lies in the buffer, and the four dwords from a position's dword end at
+// most 3 dwords past it.
+constexpr uint32_t kSdHold = 1008;
+static_assert(kSdHold + 64 * kSdMaxToken <= 4 * kSdBufWords, "String-dictionary buffer");
 static_assert(kSdBufAlloc % 256 == 0, "String-dictionary buffers: 16-byte aligned, zeroed in 64 lanes x 16 bytes");
 
 // COL: a column dictionary (SDICT_COL, SDICT_COL_ANS), whose entries have
@@ -1600,18 +1602,21 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
     // OR group g (cur, whose bytes were loaded one group earlier) into the
     // buffer, and write out the whole blocks when enough are done and
     // everything at the unit's end (a group past the unit writes nothing).
-    auto finish = [&](uint32_t g, const Grp &cur) {
+    // slot (a constant at each call): this group issues the store of its
+    // pair of groups (every group, in the one-group loop)
+    auto finish = [&](uint32_t g, const Grp &cur, bool slot) {
         stage(cur, g);
         const uint32_t fill = uint32_t(int64_t(cur.end) - sbase);
         const bool last = g + 1 == t.b;
-        // every group (a group past the unit too) issues exactly one store
-        // instruction: the whole 128-byte lines ready, at most eight (lane l
-        // writes block l); a variable number of stores between a load and
-        // its use would make the compiler's wait for that load also wait for
-        // every store and later load
-        const uint32_t nl = g < t.b ? min(fill >> 7, 8u) : 0u;
+        // every store slot (a group past the unit too) issues exactly one
+        // store instruction: the whole 128-byte lines ready, at most eight
+        // (lane l writes block l); a variable number of stores between a load
+        // and its use would make the compiler's wait for that load also wait
+        // for every store and later load.  One slot per pair of groups halves
+        // the address work of the stores (each writes about twice as much).
+        const uint32_t nl = slot && g < t.b ? min(fill >> 7, 8u) : 0u;
         wave_fence();
-        {
+        if (slot) {
             // (read and written back by every lane, without a branch, so
             // that the store stays one instruction)
             const bool mine = lane < 8 * nl;
@@ -1636,9 +1641,11 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
                         gp(out)[q + k] = uint8_t(v[k >> 2] >> (8 * (k & 3u)));
         }
         uint32_t done = nl;  // lines written
-        if (g < t.b && (last || fill >= 9 * 128)) {
-            // the unit's end (everything, the last block cut at ub), or a
-            // group of more than a kilobyte: the rest of the whole lines
+        // the buffer holds at most kSdHold bytes before a group
+        if (g < t.b && (last || fill >= 128 * nl + (slot ? 128 : kSdHold + 1))) {
+            // the unit's end (everything, the last block cut at ub), or more
+            // than the buffer may keep before the next group: the rest of
+            // the whole lines
             const uint32_t nb = last ? (fill + 15) >> 4 : (fill >> 7) << 3;
             for (uint32_t b = 8 * nl + lane; b < nb; b += 64) {
                 const int64_t q = sbase + 16 * int64_t(b);
@@ -1679,11 +1686,11 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
     // loads complete in issue order, so the index dwords go last: waiting
     // for the entries and bytes needed one group later does not wait for
     // them.
-    auto step = [&](uint32_t g, uint32_t &wc, Entry &en, const Entry &ec, const Grp &cur, Grp &nxt) {
+    auto step = [&](uint32_t g, uint32_t &wc, Entry &en, const Entry &ec, const Grp &cur, Grp &nxt, bool slot) {
         en = entry_of(g + 2, wc);
         dead |= !prepare(g + 1, ec, nxt, cur.end);
         wc = words_of(g + 4);
-        finish(g, cur);
+        finish(g, cur, slot);
     };
     Grp ga, gb;
     Entry ea, eb;
@@ -1711,8 +1718,8 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
         // the a and b copies, so that no copy waits for the loads in flight
         // into the next group's state; an odd unit ends with a group past it
         for (uint32_t g = t.a;; g += 2) {
-            step(g, wa, ea, eb, ga, gb);
-            step(g + 1, wb, eb, ea, gb, ga);
+            step(g, wa, ea, eb, ga, gb, false);
+            step(g + 1, wb, eb, ea, gb, ga, true);
             if (g + 2 >= t.b) break;
         }
         if (dead) flag(A.err, ERR_CORRUPT);
@@ -1735,7 +1742,7 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
             }
             eb = entry_of(g + 2, wa);
             wa = words_of(g + 3);
-            finish(g, ga);
+            finish(g, ga, true);
             if (g + 1 >= t.b) break;
             ga = gb;
         }

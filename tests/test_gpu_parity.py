@@ -113,12 +113,22 @@ def test_for_bp_unaligned_chunks():
 
 @pytest.mark.parametrize("mode", MODES)
 def test_dict_bp_all_widths(mode):
+    """Dictionaries of every value width, small ones (up to 4 KiB, gathered
+    from the wave's LDS copy; 256 CHAR(16) values fill it exactly) and large
+    ones (gathered from global memory)."""
     log("dict", mode)
     r = g.rng(2)
+
+    def distinct(k, dt, lo, hi):
+        return np.unique(r.integers(lo, hi, size=4 * k, dtype=np.int64))[:k].astype(dt)
     xs = [g.fixed16_column(50001, 25, 3),
           g.fixed16_column(3333, 3000, 4),
           r.choice(r.integers(-2**31, 2**31, size=200, dtype=np.int64).astype(np.int32), size=40000),
-          r.choice(r.integers(-2**62, 2**62, size=70000, dtype=np.int64), size=70001)]
+          r.choice(r.integers(-2**62, 2**62, size=70000, dtype=np.int64), size=70001),
+          g.fixed16_column(20000, 256, 5), g.fixed16_column(20000, 257, 6),
+          r.choice(distinct(512, np.int64, -2**62, 2**62), size=30000),
+          r.choice(distinct(1024, np.int32, -2**31, 2**31), size=30000),
+          r.choice(distinct(5000, np.int32, -2**31, 2**31), size=30000)]
     cols = [zf.Column.compress(x, zf.DICT_BP, chunk_elems=[len(x) // 3, len(x) - len(x) // 3]) for x in xs]
     check(cols, decode_image(cols, **mode), xs)
 
