@@ -307,9 +307,14 @@ void zf_plan_opts_default(zf_plan_opts *opts);
  * from the tune cache (Sec. 4, device geometry scheduling), batches of chunks
  * no larger than one staging slot, the batch order by Johnson's rule on
  * (transfer, decode) estimates (Sec. 3.3), and the device workspace (tables,
- * staging slots, error word, graphs).  The columns must outlive the plan and
- * must not change.  Errors: ZF_E_INVALID, ZF_E_CORRUPT (host validation of
- * every stream header), ZF_E_NOMEM, ZF_E_HIP.
+ * staging slots, error word, graphs, and a 16-byte record per entry of every
+ * column token dictionary: the entry's first 15 bytes, zero past its length,
+ * then its length, which the String-dictionary kernel reads instead of the
+ * image's entry for tokens of up to 15 bytes).  The columns must outlive the
+ * plan and must not change, and a device image given to
+ * zf_decompress_async must hold these same columns.  Errors: ZF_E_INVALID,
+ * ZF_E_CORRUPT (host validation of every stream header), ZF_E_NOMEM,
+ * ZF_E_HIP.
  */
 zf_status zf_plan(const zf_column_t *const *cols, uint32_t n_cols, int32_t device,
                   const zf_plan_opts *opts /* nullable */, zf_plan_t **out);
