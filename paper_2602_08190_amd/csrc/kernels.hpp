@@ -1851,10 +1851,14 @@ ZF_DEV void unit_ans(const LaunchArgs &A, const ChunkDesc &ck, uint32_t *lds) {
         const uint64_t m = __ballot(need);
         const uint32_t rank = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
         const uint32_t j = pos - base + rank;  // < 128
-        const uint32_t pair = uint32_t(__builtin_amdgcn_ds_bpermute(int((j & 63u) << 2), int(win)));
+        // (the permute reads lane (address / 4) mod 64)
+        const uint32_t pair = uint32_t(__builtin_amdgcn_ds_bpermute(int(j << 2), int(win)));
         // (x << 16) | (the low or high half of pair) in one byte permute
-        const uint32_t sel = 0x05040100u + ((j >> 6) & 1u) * 0x0202u;
-        x = need ? __builtin_amdgcn_perm(x, pair, sel) : x;
+        const uint32_t sel = 0x05040100u + ((j >> 5) & 2u) * 0x0101u;
+        // (computed by every lane and selected: a branch around it costs more)
+        uint32_t xp = __builtin_amdgcn_perm(x, pair, sel);
+        asm volatile("" : "+v"(xp));
+        x = need ? xp : x;
         pos += uint32_t(__popcll(m));
         if (pos - base >= 64) {  // slide by 64 words
             base += 64;
