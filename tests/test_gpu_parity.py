@@ -286,6 +286,9 @@ def test_sdict_col_text_bytes_and_tiles(sd_bytes):
             zf.Column.compress(xs[4], zf.SDICT_COL, chunk_elems=[3, 6997]),
             zf.Column.compress(xs[5], zf.SDICT_COL, chunk_elems=[len(xs[5]) - 4097, 4097])]
     check(cols, decode_image(cols, tiles={"SDICT": dict(unit=sd_bytes)}), xs)
+    # workgroups of several waves (some spanning two columns)
+    for wpb in (2, 8, 12):
+        check(cols, decode_image(cols, tiles={"SDICT": dict(unit=sd_bytes, waves_per_block=wpb)}), xs)
     check(cols, decode_image(cols, persistent=True, tiles={"SDICT": dict(unit=sd_bytes, waves_per_block=8)}), xs)
 
 
@@ -308,6 +311,7 @@ def test_sdict_col_every_token_length(codec):
             zf.Column.compress(x[7:], c)]
     xs = [x, x[7:]]
     check(cols, decode_image(cols, tiles={"SDICT": dict(unit=4096)}), xs)
+    check(cols, decode_image(cols, tiles={"SDICT": dict(unit=4096, waves_per_block=4)}), xs)
     check(cols, decode_image(cols, persistent=True), xs)
 
 
