@@ -528,7 +528,8 @@ def main():
                      "unit": "GB/s", "frac": kinds[dom]["frac_of_hbm_peak"],
                      "traffic": group_traffic(args.workload, dom),
                      "kernel": {"LZ77": "k_decode_lz (LZ77)", "ANS": "k_decode_ans",
-                                "ANS+SDICT": "k_decode_ans then k_decode_sdict",
+                                "ANS+SDICT": "k_decode_ans then the String-dictionary kernel (k_decode_sdict_hot<16u> "
+                                             "at 16 waves per workgroup, else k_decode_sdict)",
                                 "RLE32+TREE": "k_decode_kind<RLE32> then k_decode_kind<TREE>",
                                 "RLE64+TREE": "k_decode_kind<RLE64> then k_decode_kind<TREE>",
                                 "PERSISTENT": "k_decode_persistent"}.get(dom, f"k_decode_kind<{dom}>"),

@@ -277,8 +277,11 @@ typedef enum {
  * one chunk per wavefront; the persistent kernel always uses 4; SDICT:
  * output bytes, in whole groups of 64 tokens),
  * `waves_per_block`
- * the wavefronts per workgroup (S/64).  A lane always owns 16 output bytes
- * per step (C).  Zero fields take the tune cache's value, else a default. */
+ * the wavefronts per workgroup (S/64; SDICT: at most 12, or 14 and 16, which
+ * run two workgroups per compute unit over contiguous ranges of units, each
+ * sharing an LDS copy of the hottest records of a column dictionary and
+ * staging through 2 KiB buffers).  A lane always owns 16 output bytes per
+ * step (C).  Zero fields take the tune cache's value, else a default. */
 typedef struct {
     uint32_t unit;
     uint32_t waves_per_block;

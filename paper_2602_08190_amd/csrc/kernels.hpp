@@ -1322,8 +1322,17 @@ static_assert(kSdBufAlloc % 256 == 0, "String-dictionary buffers: 16-byte aligne
 // PAIR: two groups per loop iteration (the per-kind kernel); one group per
 // iteration keeps the persistent kernel, which holds every kind's routine,
 // within its register budget.
-template <bool COL, bool PAIR>
-ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, uint32_t *buf) {
+// BUFW: the buffer's dwords (kSdBufAlloc, or fewer: a group that does not
+// fit then bypasses it).  HOT (COL only): hot[1 + r] holds record r of the
+// column dictionary for r < hot_n, in LDS, and hot[0] is zero; those records
+// are read there.
+template <bool COL, bool PAIR, uint32_t BUFW = kSdBufAlloc, bool HOT = false>
+ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, uint32_t *buf,
+                         const u32x4 *hot = nullptr, uint32_t hot_n = 0) {
+    static_assert(BUFW % 256 == 0 && 4 * (BUFW - 4) >= kSdHold + 1024, "String-dictionary buffer");
+    constexpr uint32_t kWords = BUFW - 4;
+    // may a checked group not fit behind the bytes the buffer holds?
+    constexpr bool kSmall = kSdHold + 64 * kSdMaxToken > 4 * kWords;
     const uint8_t *s = A.comp + ck.comp_off;
     const uint32_t lane = lane_id(), plain = ck.n_elems, clen = ck.comp_len;
     uint8_t *out = A.out_tab[ck.col] + ck.out_off;
@@ -1420,8 +1429,12 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
         __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(out), 0, int(plain), 0x00020000);
     const u32x4 zero4 = {0u, 0u, 0u, 0u};
 #pragma unroll
-    for (uint32_t k = 0; k < kSdBufAlloc / 256; k++) *reinterpret_cast<u32x4 *>(buf + 4 * (64 * k + lane)) = zero4;
+    for (uint32_t k = 0; k < BUFW / 256; k++) *reinterpret_cast<u32x4 *>(buf + 4 * (64 * k + lane)) = zero4;
     wave_fence();
+    // output bytes below lo are written already (the unit before this one
+    // writes those of its last line; a group that bypassed the buffer wrote
+    // its own)
+    int64_t lo = ua;
 
     // Three stages run ahead of the group being written: the packed index
     // words of group g + 2 and the entries of group g + 1 are loaded, and
@@ -1443,6 +1456,7 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
     // dictionary, one load for a token of up to 15 bytes and its length)
     struct Entry {
         u32x4 f;        // COL: the record; else f.x = the entry {offset, length}
+        u32x4 h;        // HOT: the record from LDS (zero when f holds it)
         uint32_t code;  // the entry index
         bool bad;
     };
@@ -1457,7 +1471,12 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
         en.bad = act && en.code >= ne;
         const bool use = act && !en.bad;
         if constexpr (COL) {
-            en.f = __builtin_amdgcn_raw_buffer_load_b128(rs_fat, int(use ? kFatBytes * en.code : 0x7FFFFFF0u), 0, 0);
+            // (HOT: a record in the LDS copy is read there, and the global
+            // read returns zero; the two are ORed where they are used)
+            const bool h = HOT && use && en.code < hot_n;
+            en.f = __builtin_amdgcn_raw_buffer_load_b128(rs_fat, int(use && !h ? kFatBytes * en.code : 0x7FFFFFF0u),
+                                                         0, 0);
+            if constexpr (HOT) en.h = hot[h ? en.code + 1 : 0u];
         } else {
             en.f.x = __builtin_amdgcn_raw_buffer_load_b32(rs_ents, int(use ? 4 * en.code : 0x7FFFFFF0u), 0, 0);
         }
@@ -1480,8 +1499,10 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
     auto prepare = [&](uint32_t g, const Entry &en, Grp &G, uint32_t prev_end) -> bool {
         const bool act = g < t.b && 64 * g + lane < nt;
         const bool bad_code = en.bad;
+        u32x4 f = en.f;
+        if constexpr (HOT) f |= en.h;
         if constexpr (COL) {
-            G.len = en.f.w >> 24;
+            G.len = f.w >> 24;
             G.eoff = en.code;
         } else {
             G.len = en.f.x >> 24;
@@ -1499,10 +1520,10 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
             // the record's token bytes (its last byte, the length, cleared);
             // the dwords are shifted into the buffer's alignment when they
             // are ORed
-            G.v0 = en.f.x;
-            G.v1 = en.f.y;
-            G.v2 = en.f.z;
-            G.v3 = en.f.w & 0x00FFFFFFu;
+            G.v0 = f.x;
+            G.v1 = f.y;
+            G.v2 = f.z;
+            G.v3 = f.w & 0x00FFFFFFu;
         } else {
             const uint32_t at = G.eoff - m + 4;
             G.v0 = __builtin_amdgcn_raw_buffer_load_b32(rs_ent, int(0 < nd ? at : 0x7FFFFFF0u), 0, 0);
@@ -1535,7 +1556,7 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
             const uint32_t r = endb - 4 * j;
             return r >= 4 ? 0xFFFFFFFFu : ((1u << (8 * r)) - 1u);
         };
-        // a checked group's positions lie inside the buffer (o < 4 kSdBufWords),
+        // a staged group's positions lie inside the buffer (o < 4 kWords),
         // so dwords d0 .. d0 + 3 lie inside the allocation; lanes with nothing
         // to OR at dword j OR a zero
         const uint32_t d0 = o >> 2;
@@ -1604,7 +1625,52 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
     // everything at the unit's end (a group past the unit writes nothing).
     // slot (a constant at each call): this group issues the store of its
     // pair of groups (every group, in the one-group loop)
+    // A checked group that does not fit behind the bytes the buffer holds
+    // (a small buffer only): the buffer's bytes before it are written out,
+    // then its tokens byte by byte from the entry bytes, and the buffer
+    // starts again empty at the group's end.
+    auto spill = [&](uint32_t g, const Grp &cur) {
+        const int64_t p0 = goff(g);
+        wave_fence();
+        const uint32_t nbk = uint32_t(p0 - sbase + 15) >> 4;  // blocks holding bytes below p0
+        for (uint32_t b = lane; b < nbk; b += 64) {
+            const int64_t q = sbase + 16 * int64_t(b);
+            const u32x4 v = *reinterpret_cast<const u32x4 *>(buf + 4 * b);
+            if (q >= lo && q + 16 <= p0) {
+                __builtin_nontemporal_store(v, gp(reinterpret_cast<u32x4 *>(out + q)));
+            } else {
+                for (uint32_t k = 0; k < 16; k++)
+                    if (q + k >= lo && q + k < p0) gp(out)[q + k] = uint8_t(v[k >> 2] >> (8 * (k & 3u)));
+            }
+        }
+        const bool act = cur.live && 64 * g + lane < nt;
+        uint32_t off = cur.eoff;  // the token's first byte in the entry bytes
+        bool go = act;
+        if constexpr (COL) {
+            const uint32_t e = __builtin_amdgcn_raw_buffer_load_b32(rs_ents, int(act ? 4 * cur.eoff : 0x7FFFFFF0u), 0, 0);
+            off = e & 0xFFFFFFu;
+            const bool bad = act && ((e >> 24) != cur.len || off + cur.len > nb);
+            if (any(bad)) flag(A.err, ERR_CORRUPT);
+            go = act && !bad;
+        }
+        for (uint32_t k = 0; any(go && k < cur.len); k++) {
+            const uint8_t c = __builtin_amdgcn_raw_buffer_load_b8(rs_ent, int(go && k < cur.len ? off + 4 + k : 0x7FFFFFF0u),
+                                                                  0, 0);
+            if (go && k < cur.len) gp(out)[cur.P + k] = c;
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < BUFW / 256; k++) *reinterpret_cast<u32x4 *>(buf + 4 * (64 * k + lane)) = zero4;
+        wave_fence();
+        lo = cur.end;
+        sbase = int64_t(cur.end) - int64_t((oa + cur.end) & 127u);
+    };
     auto finish = [&](uint32_t g, const Grp &cur, bool slot) {
+        if constexpr (kSmall) {
+            if (int64_t(cur.end) - sbase > int64_t(4 * kWords)) {
+                spill(g, cur);
+                return;
+            }
+        }
         stage(cur, g);
         const uint32_t fill = uint32_t(int64_t(cur.end) - sbase);
         const bool last = g + 1 == t.b;
@@ -1623,7 +1689,7 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
             const u32x4 v = *reinterpret_cast<const u32x4 *>(buf + 4 * lane);
             *reinterpret_cast<u32x4 *>(buf + 4 * lane) = mine ? zero4 : v;
             const int64_t q = sbase + 16 * int64_t(lane);
-            const bool whole = mine && q >= int64_t(ua) && q + 16 <= int64_t(ub);
+            const bool whole = mine && q >= lo && q + 16 <= int64_t(ub);
             // nontemporal: the output is not read back here, and keeping it
             // out of the L2's way leaves that to the dictionary (0.85 against
             // 0.56 ms per GiB)
@@ -1632,12 +1698,12 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
             uint32_t off = whole ? uint32_t(q) : 0x7FFFFFF0u;
             asm volatile("" : "+v"(off));
             __builtin_amdgcn_raw_buffer_store_b128(v, rs_out, int(off), 0, kNonTemporal);
-            // the block shared with the unit before (at this unit's start):
-            // its bytes from ua on
-            const bool part = mine && !whole && q + 16 > int64_t(ua) && q < int64_t(ub);
+            // a block partly written already (shared with the unit before,
+            // or with a group that bypassed the buffer): its bytes from lo on
+            const bool part = mine && !whole && q + 16 > lo && q < int64_t(ub);
             if (any(part) && part)
                 for (uint32_t k = 0; k < 16; k++)
-                    if (q + k >= int64_t(ua) && q + k < int64_t(ub))
+                    if (q + k >= lo && q + k < int64_t(ub))
                         gp(out)[q + k] = uint8_t(v[k >> 2] >> (8 * (k & 3u)));
         }
         uint32_t done = nl;  // lines written
@@ -1651,11 +1717,11 @@ ZF_DEV void unit_sdict_t(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck
                 const int64_t q = sbase + 16 * int64_t(b);
                 const u32x4 v = *reinterpret_cast<const u32x4 *>(buf + 4 * b);
                 *reinterpret_cast<u32x4 *>(buf + 4 * b) = zero4;
-                if (q >= int64_t(ua) && q + 16 <= int64_t(ub)) {
+                if (q >= lo && q + 16 <= int64_t(ub)) {
                     __builtin_nontemporal_store(v, gp(reinterpret_cast<u32x4 *>(out + q)));
                 } else {
                     for (uint32_t k = 0; k < 16; k++)
-                        if (q + k >= int64_t(ua) && q + k < int64_t(ub))
+                        if (q + k >= lo && q + k < int64_t(ub))
                             gp(out)[q + k] = uint8_t(v[k >> 2] >> (8 * (k & 3u)));
                 }
             }
@@ -1753,6 +1819,17 @@ template <bool PAIR>
 ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, uint32_t *buf) {
     if (ck.codec == C_SDICT_COL || ck.codec == C_SDICT_COL_ANS) unit_sdict_t<true, PAIR>(A, t, ck, buf);
     else unit_sdict_t<false, PAIR>(A, t, ck, buf);
+}
+// The same with a buffer of kSdSmallBuf dwords and the workgroup's LDS copy
+// of a column dictionary's hottest records (hot_n of them; 0 when the unit's
+// dictionary is another one).
+constexpr uint32_t kSdSmallBuf = 512;
+ZF_DEV void unit_sdict_hot(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, uint32_t *buf, const u32x4 *hot,
+                           uint32_t hot_n) {
+    if (ck.codec == C_SDICT_COL || ck.codec == C_SDICT_COL_ANS)
+        unit_sdict_t<true, true, kSdSmallBuf, true>(A, t, ck, buf, hot, hot_n);
+    else
+        unit_sdict_t<false, true, kSdSmallBuf>(A, t, ck, buf);
 }
 
 // ===================================================================== ANS

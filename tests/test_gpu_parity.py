@@ -261,6 +261,7 @@ def test_sdict_text_bytes_and_tiles(sd_bytes):
             zf.Column.compress(xs[3], zf.SDICT_BP, chunk_elems=[1, 499, len(xs[3]) - 500]),
             zf.Column.compress(xs[4], zf.SDICT_BP, chunk_elems=[3, 6997])]
     check(cols, decode_image(cols, tiles={"SDICT": dict(unit=sd_bytes)}), xs)
+    check(cols, decode_image(cols, tiles={"SDICT": dict(unit=sd_bytes, waves_per_block=16)}), xs)
     check(cols, decode_image(cols, persistent=True, tiles={"SDICT": dict(unit=sd_bytes, waves_per_block=8)}), xs)
 
 
@@ -286,8 +287,10 @@ def test_sdict_col_text_bytes_and_tiles(sd_bytes):
             zf.Column.compress(xs[4], zf.SDICT_COL, chunk_elems=[3, 6997]),
             zf.Column.compress(xs[5], zf.SDICT_COL, chunk_elems=[len(xs[5]) - 4097, 4097])]
     check(cols, decode_image(cols, tiles={"SDICT": dict(unit=sd_bytes)}), xs)
-    # workgroups of several waves (some spanning two columns)
-    for wpb in (2, 8, 12):
+    # workgroups of several waves (some spanning two columns); 14 and 16
+    # waves share an LDS copy of the hottest records of one column dictionary
+    # and stage through small buffers that a large group bypasses
+    for wpb in (2, 8, 12, 14, 16):
         check(cols, decode_image(cols, tiles={"SDICT": dict(unit=sd_bytes, waves_per_block=wpb)}), xs)
     check(cols, decode_image(cols, persistent=True, tiles={"SDICT": dict(unit=sd_bytes, waves_per_block=8)}), xs)
 
@@ -312,6 +315,8 @@ def test_sdict_col_every_token_length(codec):
     xs = [x, x[7:]]
     check(cols, decode_image(cols, tiles={"SDICT": dict(unit=4096)}), xs)
     check(cols, decode_image(cols, tiles={"SDICT": dict(unit=4096, waves_per_block=4)}), xs)
+    for wpb in (14, 16):
+        check(cols, decode_image(cols, tiles={"SDICT": dict(unit=4096, waves_per_block=wpb)}), xs)
     check(cols, decode_image(cols, persistent=True), xs)
 
 
