@@ -278,9 +278,10 @@ typedef enum {
  * output bytes, in whole groups of 64 tokens),
  * `waves_per_block`
  * the wavefronts per workgroup (S/64; SDICT: at most 12, or 14 and 16, which
- * run two workgroups per compute unit over contiguous ranges of units, each
- * sharing an LDS copy of the hottest records of a column dictionary and
- * staging through 2 KiB buffers).  A lane always owns 16 output bytes per
+ * run the units over column dictionaries as two workgroups per compute unit
+ * over contiguous ranges of units, each sharing an LDS copy of the hottest
+ * records of a column dictionary and staging through 2 KiB buffers, and
+ * the other units in a second launch of 4-wave workgroups).  A lane always owns 16 output bytes per
  * step (C).  Zero fields take the tune cache's value, else a default. */
 typedef struct {
     uint32_t unit;

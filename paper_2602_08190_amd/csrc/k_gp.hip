@@ -9,17 +9,21 @@ ZF_DEFINE_LAUNCHER(K_TREE, launch_tree)
 // String-dictionary: tiles mapped XCD-aware (the tiles of a chunk share its
 // dictionary, so neighbouring tiles go to the same XCD and its L2); each
 // wave's staging buffer is dynamic shared memory, kSdBufAlloc dwords.
-__global__ __launch_bounds__(1024) void k_decode_sdict(LaunchArgs A) {
+// skip_col: the tiles over a column dictionary are another launch's.
+__global__ __launch_bounds__(1024) void k_decode_sdict(LaunchArgs A, uint32_t skip_col) {
     const uint32_t waves = blockDim.x / 64;
     const uint32_t u = A.kind_begin[K_SDICT] + xcd_block(blockIdx.x, gridDim.x) * waves + first32(threadIdx.x / 64);
     if (u >= A.kind_begin[K_SDICT + 1]) return;
     extern __shared__ uint32_t sd_smem[];
     const Tile t = A.tiles[u];
-    unit_sdict<true>(A, t, A.chunks[t.chunk], sd_smem + (threadIdx.x / 64) * kSdBufAlloc);
+    const ChunkDesc &ck = A.chunks[t.chunk];
+    if (skip_col && (ck.codec == C_SDICT_COL || ck.codec == C_SDICT_COL_ANS)) return;
+    unit_sdict<true>(A, t, ck, sd_smem + (threadIdx.x / 64) * kSdBufAlloc);
 }
-// 14 or 16 waves: two workgroups per compute unit, each taking a contiguous
-// range of the kind's tiles (its waves take every W-th), with staging
-// buffers of kSdSmallBuf dwords.  A workgroup first copies the hottest
+// 14 or 16 waves: the tiles over a column dictionary go to two workgroups
+// per compute unit, each taking a contiguous range of the kind's tiles (its
+// waves take every W-th, skipping the others), with staging buffers of
+// kSdSmallBuf dwords; the other tiles go to a launch of k_decode_sdict.  A workgroup first copies the hottest
 // records of its first tile's column dictionary (the entries are ordered by
 // decreasing count, so records 0, 1, ...) into the rest of its half of the
 // LDS, after a zero row; its tiles over that dictionary read those records
@@ -49,7 +53,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(W / 2, W /
     for (uint32_t u = lo + w; u < hi; u += W) {
         const Tile t = A.tiles[u];
         const ChunkDesc &ck = A.chunks[t.chunk];
-        unit_sdict_hot(A, t, ck, buf, sd_hot, col0 && ck.fat_off == c0.fat_off ? hn : 0u);
+        if (ck.codec == C_SDICT_COL || ck.codec == C_SDICT_COL_ANS)
+            unit_sdict_hot(A, t, ck, buf, sd_hot, col0 && ck.fat_off == c0.fat_off ? hn : 0u);
     }
 }
 template <uint32_t W>
@@ -66,10 +71,18 @@ static void launch_sdict_hot(const LaunchArgs &A, uint32_t n, hipStream_t st) {
 void launch_sdict(const LaunchArgs &A, uint32_t waves, hipStream_t st) {
     const uint32_t n = A.kind_begin[K_SDICT + 1] - A.kind_begin[K_SDICT];
     if (!n) return;
-    if (waves >= 16) return launch_sdict_hot<16>(A, n, st);
-    if (waves >= 14) return launch_sdict_hot<14>(A, n, st);
+    uint32_t skip_col = 0;
+    if (waves >= 14) {
+        if (A.sdict_codecs & 1u) {
+            if (waves >= 16) launch_sdict_hot<16>(A, n, st);
+            else launch_sdict_hot<14>(A, n, st);
+            skip_col = 1;
+        }
+        if (!(A.sdict_codecs & 2u)) return;
+        waves = 4;  // the other tiles
+    }
     waves = waves > 12 ? 12u : waves;  // 12 staging buffers: 60.2 KiB of LDS per workgroup
     hipLaunchKernelGGL(k_decode_sdict, dim3((n + waves - 1) / waves), dim3(64 * waves),
-                       waves * kSdBufAlloc * sizeof(uint32_t), st, A);
+                       waves * kSdBufAlloc * sizeof(uint32_t), st, A, skip_col);
 }
 }  // namespace zf

@@ -1820,16 +1820,13 @@ ZF_DEV void unit_sdict(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, 
     if (ck.codec == C_SDICT_COL || ck.codec == C_SDICT_COL_ANS) unit_sdict_t<true, PAIR>(A, t, ck, buf);
     else unit_sdict_t<false, PAIR>(A, t, ck, buf);
 }
-// The same with a buffer of kSdSmallBuf dwords and the workgroup's LDS copy
-// of a column dictionary's hottest records (hot_n of them; 0 when the unit's
-// dictionary is another one).
+// A unit over a column dictionary with a buffer of kSdSmallBuf dwords and
+// the workgroup's LDS copy of the dictionary's hottest records (hot_n of
+// them; 0 when the copy is of another dictionary).
 constexpr uint32_t kSdSmallBuf = 512;
 ZF_DEV void unit_sdict_hot(const LaunchArgs &A, const Tile &t, const ChunkDesc &ck, uint32_t *buf, const u32x4 *hot,
                            uint32_t hot_n) {
-    if (ck.codec == C_SDICT_COL || ck.codec == C_SDICT_COL_ANS)
-        unit_sdict_t<true, true, kSdSmallBuf, true>(A, t, ck, buf, hot, hot_n);
-    else
-        unit_sdict_t<false, true, kSdSmallBuf>(A, t, ck, buf);
+    unit_sdict_t<true, true, kSdSmallBuf, true>(A, t, ck, buf, hot, hot_n);
 }
 
 // ===================================================================== ANS

@@ -216,6 +216,11 @@ static void flatten(const WorkTables &w, std::vector<uint8_t> &host, uint64_t of
     }
     A.kind_begin[K_COUNT] = u;
     A.two_stage = w.scratch_bytes > 0;
+    A.sdict_codecs = 0;
+    for (const Tile &t : w.tiles[K_SDICT]) {
+        const uint32_t c = w.chunks[t.chunk].codec;
+        A.sdict_codecs |= c == C_SDICT_COL || c == C_SDICT_COL_ANS ? 1u : 2u;
+    }
 }
 
 struct DeviceGuard {

@@ -97,6 +97,7 @@ struct LaunchArgs {
     const uint8_t *fat;           // the plan's 16-byte entry records of the column token dictionaries
     uint32_t kind_begin[K_COUNT + 1];
     uint32_t two_stage;           // some units read the scratch area that earlier kinds write
+    uint32_t sdict_codecs;        // String-dictionary tiles: bit 0 some over a column dictionary, bit 1 some not
 };
 
 // Host side: events recorded around each kind's launch of a profiled decode
