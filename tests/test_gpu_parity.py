@@ -345,6 +345,11 @@ def test_sdict_col_ans_two_stage_decode(mode):
         check(cols, outs, xs)
         return
     check(cols, decode_image(cols), xs)
+    # column and chunk dictionaries in one launch of 16-wave String-dictionary
+    # workgroups: the first through the shared-record kernel, the second in a
+    # launch of their own
+    check(cols, decode_image(cols, tiles={"SDICT": dict(unit=4096, waves_per_block=16)}), xs)
+    check(cols, decode_image(cols, tiles={"SDICT": dict(unit=4096, waves_per_block=2)}), xs)
 
 
 @pytest.mark.parametrize("mode", ["graphs", "no_graphs", "staged", "persistent"])

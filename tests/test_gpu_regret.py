@@ -5,7 +5,8 @@ schedule); the target is a total time within 5% of the best).
 The exhaustive table is measured here, on this GPU, for held-out chunks (the
 columns the committed network never saw in training: (id // 5) % 5 == 4, two
 of each family, one 8 MiB chunk each): every applicable (codec, schedule)
-timed by zf_transfer_and_decompress, median of three.  Two choosers are priced
+timed by zf_transfer_and_decompress, median of three, measured twice (the
+faster median kept).  Two choosers are priced
 against it: the network's argmin, and the product encoder (ZF_AUTO with the
 committed weights and near-tie timing on this device), whose choice is read
 back from the column's chunk table."""
@@ -35,9 +36,15 @@ def read_weights(path):
 
 def test_regret_against_measured_exhaustive_search(tmp_path):
     assert all((c // 5) % 5 == 4 for c in HELD_OUT)
-    out = str(tmp_path / "held_out.npz")
-    Lr.collect(HELD_OUT, out, chunk_bytes=Lr.CHUNK_BYTES, chunks_per_col=1)
-    d = Lr.load([out])
+    # the table measured twice and the faster of the two medians kept, so
+    # that a transient on the PCIe link or the GPU does not decide a choice
+    outs = [str(tmp_path / f"held_out_{k}.npz") for k in range(2)]
+    for out in outs:
+        Lr.collect(HELD_OUT, out, chunk_bytes=Lr.CHUNK_BYTES, chunks_per_col=1)
+    d = Lr.load([outs[0]])
+    d2 = Lr.load([outs[1]])
+    assert np.array_equal(d["X"], d2["X"]) and np.array_equal(np.isfinite(d["T"]), np.isfinite(d2["T"]))
+    d["T"] = np.fmin(d["T"], d2["T"])
     T = d["T"]
     assert T.shape == (len(HELD_OUT), 24) and np.all(np.isfinite(T).sum(axis=1) >= 8)
     best = np.nanmin(T, axis=1)
